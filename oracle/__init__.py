@@ -1,0 +1,210 @@
+"""Plain FP64 CPU oracle for the Cartesian traceless FMM (arXiv 1811.06332).
+
+TEST INFRASTRUCTURE ONLY.  The product library never imports, links or calls
+anything in this package; only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` do.  It shares no code with the GPU path.
+
+This module is argument marshalling (numpy <-> ctypes) around
+``ctfmm_oracle.c``; every operator is computed there, in full symmetric
+storage, from the paper's equations (see the header of that file).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ctfmm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no intrinsics, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-Wall",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        i32, i64, d = C.c_int, C.c_int64, C.c_double
+        L.oracle_nfull.argtypes = [i32]; L.oracle_nfull.restype = i32
+        L.oracle_full_index.argtypes = [i32, i32, i32]; L.oracle_full_index.restype = i32
+        L.oracle_detracer_T.argtypes = [i32, _dp, _dp]
+        L.oracle_detracer_D.argtypes = [i32, _dp, _dp]
+        L.oracle_dtensor.argtypes = [i32, _dp, _dp]
+        L.oracle_p2m.argtypes = [i32, _dp, i64, _dp, _dp, _dp]
+        L.oracle_m2m.argtypes = [i32, _dp, _dp, _dp]
+        L.oracle_m2l.argtypes = [i32, _dp, _dp, _dp]
+        L.oracle_m2l_with_D.argtypes = [i32, _dp, _dp, _dp]
+        L.oracle_l2l.argtypes = [i32, _dp, _dp, _dp]
+        L.oracle_l2p.argtypes = [i32, _dp, _dp, _dp, _dp]
+        L.oracle_direct.argtypes = [i64, _dp, _dp, i64, C.c_void_p, _dp, _dp, i32]
+        L.oracle_fmm_uniform.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p,
+                                         _dp, _dp, C.c_void_p, C.c_void_p, i32]
+        L.oracle_fmm_uniform.restype = i32
+        L.oracle_max_threads.restype = i32
+        _lib_handle = L
+    return _lib_handle
+
+
+def _vec(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None:
+        assert a.size == n
+    return a
+
+
+# ---------------------------------------------------------------- indexing
+
+def nfull(p: int) -> int:
+    """C(p+3,3): components of a full symmetric polytensor of ranks 0..p."""
+    return _lib().oracle_nfull(p)
+
+
+def full_index(a: int, b: int, c: int) -> int:
+    """Slot of multi-index (a,b,c) in the oracle's full storage."""
+    return _lib().oracle_full_index(a, b, c)
+
+
+def multi_indices(p: int):
+    """All multi-indices of rank <= p, in the oracle's storage order."""
+    out = [None] * nfull(p)
+    for n in range(p + 1):
+        for a in range(n + 1):
+            for b in range(n - a + 1):
+                out[full_index(a, b, n - a - b)] = (a, b, n - a - b)
+    return out
+
+
+# ---------------------------------------------------------------- operators
+
+def detracer_T(p, A):
+    A = _vec(A, nfull(p)); out = np.zeros_like(A)
+    _lib().oracle_detracer_T(p, A, out)
+    return out
+
+
+def detracer_D(p, A):
+    A = _vec(A, nfull(p)); out = np.zeros_like(A)
+    _lib().oracle_detracer_D(p, A, out)
+    return out
+
+
+def dtensor(p, r):
+    out = np.zeros(nfull(p))
+    _lib().oracle_dtensor(p, _vec(r, 3), out)
+    return out
+
+
+def p2m(p, z, xyz, q):
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
+    M = np.zeros(nfull(p))
+    _lib().oracle_p2m(p, _vec(z, 3), xyz.shape[0], np.ascontiguousarray(xyz.ravel()), q, M)
+    return M
+
+
+def m2m(p, d, M):
+    out = np.zeros(nfull(p))
+    _lib().oracle_m2m(p, _vec(d, 3), _vec(M, nfull(p)), out)
+    return out
+
+
+def m2l(p, r, M):
+    out = np.zeros(nfull(p))
+    _lib().oracle_m2l(p, _vec(r, 3), _vec(M, nfull(p)), out)
+    return out
+
+
+def m2l_with_D(p, M, D):
+    out = np.zeros(nfull(p))
+    _lib().oracle_m2l_with_D(p, _vec(M, nfull(p)), _vec(D, nfull(p)), out)
+    return out
+
+
+def l2l(p, d, L):
+    out = np.zeros(nfull(p))
+    _lib().oracle_l2l(p, _vec(d, 3), _vec(L, nfull(p)), out)
+    return out
+
+
+def l2p(p, rb, L):
+    phi = np.zeros(1); grad = np.zeros(3)
+    _lib().oracle_l2p(p, _vec(rb, 3), _vec(L, nfull(p)), phi, grad)
+    return phi[0], grad
+
+
+def direct(xyz, q, targets=None, nthreads=0):
+    """O(N^2) potential and gradient at `targets` (particle indices; all if None)."""
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
+    n = xyz.shape[0]
+    if targets is None:
+        nt, tp, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt, tp = keep.size, keep.ctypes.data
+    phi = np.zeros(nt); grad = np.zeros(3 * nt)
+    _lib().oracle_direct(n, np.ascontiguousarray(xyz.ravel()), q, nt, tp, phi, grad, nthreads)
+    del keep
+    return phi, grad.reshape(-1, 3)
+
+
+def fmm_uniform(xyz, q, p, depth, lo=(0.0, 0.0, 0.0), side=1.0, targets=None,
+                dump=False, nthreads=0):
+    """Full FMM on a uniform octree (see oracle_fmm_uniform in ctfmm_oracle.c).
+
+    Returns (phi, grad) at `targets` (all particles, input order, if None);
+    with dump=True also (M, L): lists over levels 0..depth of arrays
+    [8**l, nfull(p)] (cells row-major, x fastest), full storage.
+    """
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
+    n = xyz.shape[0]
+    if targets is None:
+        nt, tp, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt, tp = keep.size, keep.ctypes.data
+    phi = np.zeros(nt); grad = np.zeros(3 * nt)
+    nf = nfull(p)
+    Md = Ld = None
+    if dump:
+        tot = sum(8 ** l for l in range(depth + 1)) * nf
+        Md = np.zeros(tot); Ld = np.zeros(tot)
+    rc = _lib().oracle_fmm_uniform(n, np.ascontiguousarray(xyz.ravel()), q, p, depth,
+                                   _vec(lo, 3), float(side), nt, tp, phi, grad,
+                                   None if Md is None else Md.ctypes.data,
+                                   None if Ld is None else Ld.ctypes.data, nthreads)
+    del keep
+    if rc != 0:
+        raise RuntimeError(f"oracle_fmm_uniform failed with code {rc}")
+    grad = grad.reshape(-1, 3)
+    if not dump:
+        return phi, grad
+    Ms, Ls, off = [], [], 0
+    for l in range(depth + 1):
+        c = 8 ** l * nf
+        Ms.append(Md[off:off + c].reshape(8 ** l, nf))
+        Ls.append(Ld[off:off + c].reshape(8 ** l, nf))
+        off += c
+    return phi, grad, Ms, Ls
+
+
+def max_threads() -> int:
+    return _lib().oracle_max_threads()

@@ -1,0 +1,667 @@
+/*
+ * ctfmm_oracle.c -- plain, slow FP64 CPU reference for the Cartesian
+ * traceless fast multipole method of Coles & Bieri, "An Optimizing Symbolic
+ * Algebra Approach for Generating Fast Multipole Method Operators"
+ * (arXiv 1811.06332).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may use it.  It shares no code, header, table or
+ * generator with the GPU path.
+ *
+ * Every tensor here is kept in FULL symmetric storage: all C(p+3,3)
+ * multi-index components (nx,ny,nz), |n| <= p, are computed and stored,
+ * dependent (trace-determined) components included.  No trace relation and
+ * no reduced basis is used; the operators are the equations written out:
+ *
+ *   detracer T, D = T/(2n-1)!!          Appendix A, Eq. (Detracer)
+ *   traceless gradient D_k(r)           Appendix A, Eq. (traceless grad),
+ *                                       compact form Eq. (Detracer3)
+ *   P2M  M'_n = sum_a q_a (-r_a)^n, M = D[M']        Sec. 2.1, Eq. (P2M)
+ *   M2M  M'_n = sum_{k<=n} n!/(k!(n-k)!) (-d)^(n-k) M_k, then D
+ *                                       Sec. 2.1, Eq. (M2M), (M2M part 2)
+ *   M2L  L_n += sum_{|m|<=p-|n|} M_m D_{n+m}(r) / m!  Sec. 2.1, Eq. (M2L)
+ *   L2L  L_n  = sum_{|k|<=p-|n|} d^k/k! L_{n+k}       Sec. 2.1, Eq. (L2L)
+ *   L2P  grad^n Phi(x_b) ~ shifted L_n                 Sec. 2.1, Eq. (L2P)
+ *   P2P  Phi_b = sum_a q_a/|x_b-x_a|                   Appendix B, Eq. (PhiAB)
+ *
+ * Readings taken where the text is ambiguous (all multi-index factorials
+ * are componentwise, n! = nx! ny! nz!):
+ *   - P2M's "-r_a^n" is (-r_a)^n, so a positive charge has a positive
+ *     monopole and a positive potential (Sec. 2.1 says the potential is
+ *     positive).
+ *   - The M2M sum "|k| <= n" runs over k <= n componentwise (indices with
+ *     negative components vanish, Appendix D).
+ *   - M2L truncates at total degree |n|+|m| <= p.
+ *   - Self pairs are excluded and coincident pairs contribute nothing.
+ *
+ * The tree is a uniform octree over a cube (the configurations name
+ * octrees; the paper's binary median tree is not used), expansion centres
+ * at geometric cell centres (Appendix C).  Interaction lists are the
+ * ws=1 ("non-adjacent") rule: at each level l >= 2, a cell B receives M2L
+ * from every same-level cell A whose parent is adjacent to or equal to
+ * B's parent while A itself is not adjacent to or equal to B.  Adjacent
+ * leaves (and the leaf itself) form the near field (Appendix C).
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC (no intrinsics, no fast-math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PMAX 16
+
+/* ---------------------------------------------------------------- indices */
+
+static int g_ready = 0;
+static int g_nfull[OR_PMAX + 2];               /* C(p+3,3): components with rank <= p */
+static int g_idx[OR_PMAX + 1][OR_PMAX + 1][OR_PMAX + 1];
+static int g_ix[1000], g_iy[1000], g_iz[1000]; /* inverse map, C(19,3)=969 */
+/* n! for 0 <= n <= 3*OR_PMAX+1, tabulated once (exact in FP64 below 23!) */
+static double g_fact[3 * OR_PMAX + 2];
+static double fact(int n) { return g_fact[n]; }
+/* f_{n,m} of the detracer, tabulated once per (component of n, m) */
+static double g_f[969][OR_PMAX / 2 + 1][OR_PMAX / 2 + 1][OR_PMAX / 2 + 1];
+static double f_nm_eval(int n1, int n2, int n3, int m1, int m2, int m3);
+
+static void init_tables(void)
+{
+    if (g_ready) return;
+    g_fact[0] = 1.0;
+    for (int i = 1; i <= 3 * OR_PMAX + 1; ++i) g_fact[i] = g_fact[i - 1] * (double)i;
+    int c = 0;
+    for (int n = 0; n <= OR_PMAX; ++n) {
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                int z = n - a - b;
+                g_idx[a][b][z] = c;
+                g_ix[c] = a; g_iy[c] = b; g_iz[c] = z;
+                ++c;
+            }
+        g_nfull[n] = c;
+    }
+    for (int e = 0; e < c; ++e)
+        for (int m1 = 0; 2 * m1 <= g_ix[e]; ++m1)
+            for (int m2 = 0; 2 * m2 <= g_iy[e]; ++m2)
+                for (int m3 = 0; 2 * m3 <= g_iz[e]; ++m3)
+                    g_f[e][m1][m2][m3] = f_nm_eval(g_ix[e], g_iy[e], g_iz[e], m1, m2, m3);
+    g_ready = 1;
+}
+
+/* number of full components of ranks 0..p (C(p+3,3)) */
+int oracle_nfull(int p) { init_tables(); return (p < 0 || p > OR_PMAX) ? 0 : g_nfull[p]; }
+
+/* linear position of (a,b,c) in full storage (rank-major, a then b descending) */
+int oracle_full_index(int a, int b, int c)
+{
+    init_tables();
+    if (a < 0 || b < 0 || c < 0 || a + b + c > OR_PMAX) return -1;
+    return g_idx[a][b][c];
+}
+
+/* double factorial, with (-1)!! = 1 */
+static double dfact(int n) { double f = 1.0; for (int i = n; i > 1; i -= 2) f *= i; return f; }
+
+static double mfact(int a, int b, int c) { return fact(a) * fact(b) * fact(c); }
+
+static double ipow(double x, int e) { double r = 1.0; for (int i = 0; i < e; ++i) r *= x; return r; }
+
+/* ---------------------------------------------------------------- detracer */
+
+/*
+ * f_{n,m} = (-1)^m (2n-2m-1)!! n! / (2^m m! (n-2m)!)   (Appendix A)
+ * with n = (n1,n2,n3), m = (m1,m2,m3), n = |n|, m = |m|, bold factorials.
+ */
+static double f_nm_eval(int n1, int n2, int n3, int m1, int m2, int m3)
+{
+    int n = n1 + n2 + n3, m = m1 + m2 + m3;
+    double s = (m & 1) ? -1.0 : 1.0;
+    return s * dfact(2 * n - 2 * m - 1) * mfact(n1, n2, n3)
+           / (ipow(2.0, m) * mfact(m1, m2, m3) * mfact(n1 - 2 * m1, n2 - 2 * m2, n3 - 2 * m3));
+}
+
+static double f_nm(int n1, int n2, int n3, int m1, int m2, int m3)
+{
+    return g_f[g_idx[n1][n2][n3]][m1][m2][m3];
+}
+
+/*
+ * T[A^(n)]_n = sum_{m <= floor(n/2)} f_{n,m} sum_{|k|=m} (m!/k!) A_{n-2m+2k}
+ * (Appendix A, Eq. Detracer), applied to the rank-|n| part of A.
+ */
+static double detracer_T_component(const double *A, int n1, int n2, int n3)
+{
+    double t = 0.0;
+    for (int m1 = 0; 2 * m1 <= n1; ++m1)
+        for (int m2 = 0; 2 * m2 <= n2; ++m2)
+            for (int m3 = 0; 2 * m3 <= n3; ++m3) {
+                int m = m1 + m2 + m3;
+                double inner = 0.0;
+                for (int k1 = 0; k1 <= m; ++k1)
+                    for (int k2 = 0; k2 <= m - k1; ++k2) {
+                        int k3 = m - k1 - k2;
+                        inner += fact(m) / mfact(k1, k2, k3)
+                                 * A[g_idx[n1 - 2 * m1 + 2 * k1][n2 - 2 * m2 + 2 * k2][n3 - 2 * m3 + 2 * k3]];
+                    }
+                t += f_nm(n1, n2, n3, m1, m2, m3) * inner;
+            }
+    return t;
+}
+
+/* out = T[A] rank by rank (full storage, ranks 0..p) */
+void oracle_detracer_T(int p, const double *A, double *out)
+{
+    init_tables();
+    for (int c = 0; c < g_nfull[p]; ++c)
+        out[c] = detracer_T_component(A, g_ix[c], g_iy[c], g_iz[c]);
+}
+
+/* out = D[A] = T[A]/(2n-1)!! rank by rank (Appendix A) */
+void oracle_detracer_D(int p, const double *A, double *out)
+{
+    init_tables();
+    for (int c = 0; c < g_nfull[p]; ++c) {
+        int n = g_ix[c] + g_iy[c] + g_iz[c];
+        out[c] = detracer_T_component(A, g_ix[c], g_iy[c], g_iz[c]) / dfact(2 * n - 1);
+    }
+}
+
+/* ------------------------------------------------------ traceless gradient */
+
+/*
+ * D_k(r) = grad^k (1/|r|) = (-1)^k |r|^{-2k-1} T[r^k]_k   (Eq. traceless grad)
+ * T[r^k]_k = sum_{m <= floor(k/2)} f_{k,m} |r|^{2m} r^{k-2m}  (Eq. Detracer3)
+ */
+void oracle_dtensor(int p, const double r[3], double *D)
+{
+    init_tables();
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rn = sqrt(r2);
+    for (int c = 0; c < g_nfull[p]; ++c) {
+        int k1 = g_ix[c], k2 = g_iy[c], k3 = g_iz[c], k = k1 + k2 + k3;
+        double t = 0.0;
+        for (int m1 = 0; 2 * m1 <= k1; ++m1)
+            for (int m2 = 0; 2 * m2 <= k2; ++m2)
+                for (int m3 = 0; 2 * m3 <= k3; ++m3) {
+                    int m = m1 + m2 + m3;
+                    t += f_nm(k1, k2, k3, m1, m2, m3) * ipow(r2, m)
+                         * ipow(r[0], k1 - 2 * m1) * ipow(r[1], k2 - 2 * m2) * ipow(r[2], k3 - 2 * m3);
+                }
+        double sgn = (k & 1) ? -1.0 : 1.0;
+        D[c] = sgn * t / ipow(rn, 2 * k + 1);
+    }
+}
+
+/* --------------------------------------------------------------- operators */
+
+/* P2M (Eq. P2M): M = sum_a q_a D[(-r_a)^n], r_a = x_a - z.  M is ADDED to. */
+void oracle_p2m(int p, const double z[3], int64_t n, const double *xyz, const double *q, double *M)
+{
+    init_tables();
+    int nf = g_nfull[p];
+    double *Mp = (double *)calloc((size_t)nf, sizeof(double));
+    double *Mt = (double *)malloc((size_t)nf * sizeof(double));
+    for (int64_t a = 0; a < n; ++a) {
+        double rx = -(xyz[3 * a + 0] - z[0]);
+        double ry = -(xyz[3 * a + 1] - z[1]);
+        double rz = -(xyz[3 * a + 2] - z[2]);
+        for (int c = 0; c < nf; ++c)
+            Mp[c] += q[a] * ipow(rx, g_ix[c]) * ipow(ry, g_iy[c]) * ipow(rz, g_iz[c]);
+    }
+    oracle_detracer_D(p, Mp, Mt);
+    for (int c = 0; c < nf; ++c) M[c] += Mt[c];
+    free(Mp);
+    free(Mt);
+}
+
+/*
+ * M2M (Eq. M2M, M2M part 2): move the expansion from centre z to z' = z - d,
+ * i.e. d = z_child - z_parent.  M'_n = sum_{k<=n} n!/(k!(n-k)!) (-d)^(n-k) M_k,
+ * then Mout += D[M'].
+ */
+void oracle_m2m(int p, const double d[3], const double *Min, double *Mout)
+{
+    init_tables();
+    int nf = g_nfull[p];
+    double *Mp = (double *)calloc((size_t)nf, sizeof(double));
+    double *Mt = (double *)malloc((size_t)nf * sizeof(double));
+    for (int c = 0; c < nf; ++c) {
+        int n1 = g_ix[c], n2 = g_iy[c], n3 = g_iz[c];
+        double s = 0.0;
+        for (int k1 = 0; k1 <= n1; ++k1)
+            for (int k2 = 0; k2 <= n2; ++k2)
+                for (int k3 = 0; k3 <= n3; ++k3) {
+                    double w = mfact(n1, n2, n3) / (mfact(k1, k2, k3) * mfact(n1 - k1, n2 - k2, n3 - k3));
+                    s += w * ipow(-d[0], n1 - k1) * ipow(-d[1], n2 - k2) * ipow(-d[2], n3 - k3)
+                         * Min[g_idx[k1][k2][k3]];
+                }
+        Mp[c] = s;
+    }
+    oracle_detracer_D(p, Mp, Mt);
+    for (int c = 0; c < nf; ++c) Mout[c] += Mt[c];
+    free(Mp);
+    free(Mt);
+}
+
+/* M2L with a given derivative tensor D (full storage to rank p):
+ * L_n += sum_{|m| <= p-|n|} M_m D_{n+m} / m!   (Eq. M2L) */
+void oracle_m2l_with_D(int p, const double *M, const double *D, double *L)
+{
+    init_tables();
+    for (int c = 0; c < g_nfull[p]; ++c) {
+        int n1 = g_ix[c], n2 = g_iy[c], n3 = g_iz[c], n = n1 + n2 + n3;
+        double s = 0.0;
+        for (int e = 0; e < g_nfull[p - n]; ++e) {
+            int m1 = g_ix[e], m2 = g_iy[e], m3 = g_iz[e];
+            s += M[e] * D[g_idx[n1 + m1][n2 + m2][n3 + m3]] / mfact(m1, m2, m3);
+        }
+        L[c] += s;
+    }
+}
+
+/* M2L (Eq. M2L) for r = z_B - z_A; L is ADDED to. */
+void oracle_m2l(int p, const double r[3], const double *M, double *L)
+{
+    init_tables();
+    double *D = (double *)malloc((size_t)g_nfull[p] * sizeof(double));
+    oracle_dtensor(p, r, D);
+    oracle_m2l_with_D(p, M, D, L);
+    free(D);
+}
+
+/* L2L (Eq. L2L): L at z' = z + d from L at z; Lout is ADDED to. */
+void oracle_l2l(int p, const double d[3], const double *Lin, double *Lout)
+{
+    init_tables();
+    for (int c = 0; c < g_nfull[p]; ++c) {
+        int n1 = g_ix[c], n2 = g_iy[c], n3 = g_iz[c], n = n1 + n2 + n3;
+        double s = 0.0;
+        for (int e = 0; e < g_nfull[p - n]; ++e) {
+            int k1 = g_ix[e], k2 = g_iy[e], k3 = g_iz[e];
+            s += ipow(d[0], k1) * ipow(d[1], k2) * ipow(d[2], k3) / mfact(k1, k2, k3)
+                 * Lin[g_idx[n1 + k1][n2 + k2][n3 + k3]];
+        }
+        Lout[c] += s;
+    }
+}
+
+/*
+ * L2P (Eq. L2P): shift L to the particle offset rb = x_b - z_B and read the
+ * rank-0 (potential) and rank-1 (gradient) components:
+ *   Phi = sum_{|n|<=p} rb^n/n! L_n,  dPhi/dx_i = sum_{|n|<=p-1} rb^n/n! L_{n+e_i}.
+ * Results are ADDED to phi[0] and grad[0..2].
+ */
+void oracle_l2p(int p, const double rb[3], const double *L, double *phi, double *grad)
+{
+    init_tables();
+    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int c = 0; c < g_nfull[p]; ++c) {
+        int n1 = g_ix[c], n2 = g_iy[c], n3 = g_iz[c], n = n1 + n2 + n3;
+        double w = ipow(rb[0], n1) * ipow(rb[1], n2) * ipow(rb[2], n3) / mfact(n1, n2, n3);
+        f += w * L[c];
+        if (n <= p - 1) {
+            gx += w * L[g_idx[n1 + 1][n2][n3]];
+            gy += w * L[g_idx[n1][n2 + 1][n3]];
+            gz += w * L[g_idx[n1][n2][n3 + 1]];
+        }
+    }
+    phi[0] += f;
+    grad[0] += gx;
+    grad[1] += gy;
+    grad[2] += gz;
+}
+
+/* one source on one target: q/|x_b-x_a| and its gradient w.r.t. x_b */
+static void pair_kernel(const double *xb, const double *xa, double qa, double *phi, double *grad)
+{
+    double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) return; /* coincident pair: contributes nothing */
+    double r = sqrt(r2);
+    double ir = 1.0 / r;
+    phi[0] += qa * ir;
+    double ir3 = qa * ir * ir * ir;
+    grad[0] -= ir3 * dx;
+    grad[1] -= ir3 * dy;
+    grad[2] -= ir3 * dz;
+}
+
+/*
+ * Direct O(N^2) sum (Eq. PhiAB) at the targets tgt[0..nt) (particle
+ * indices; NULL = all particles).  Self pairs are skipped.
+ * phi[nt], grad[3*nt] are overwritten.
+ */
+void oracle_direct(int64_t n, const double *xyz, const double *q, int64_t nt, const int64_t *tgt,
+                   double *phi, double *grad, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    if (!tgt) nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t b = tgt ? tgt[t] : t;
+        double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int64_t a = 0; a < n; ++a) {
+            if (a == b) continue;
+            pair_kernel(&xyz[3 * b], &xyz[3 * a], q[a], &f, g);
+        }
+        phi[t] = f;
+        grad[3 * t + 0] = g[0];
+        grad[3 * t + 1] = g[1];
+        grad[3 * t + 2] = g[2];
+    }
+}
+
+/* ------------------------------------------------------------ uniform tree */
+
+typedef struct {
+    int p, depth, nf;
+    double lo[3], side;
+    int64_t n;
+    const double *xyz, *q;
+    int64_t *leaf_of;   /* [n] linear leaf index (row-major, x fastest) */
+    int64_t *start;     /* [nleaves+1] offsets into order */
+    int64_t *order;     /* [n] particle indices grouped by leaf, input order within a leaf */
+    double **M, **L;    /* per level l: (8^l) * nf, NULL for unused levels */
+} otree;
+
+static inline int64_t ncell1(int l) { return (int64_t)1 << l; }
+static inline int64_t cell_id(int l, int64_t i, int64_t j, int64_t k) { return i + ncell1(l) * (j + ncell1(l) * k); }
+
+static void cell_center(const otree *T, int l, int64_t i, int64_t j, int64_t k, double z[3])
+{
+    double h = T->side / (double)ncell1(l);
+    z[0] = T->lo[0] + ((double)i + 0.5) * h;
+    z[1] = T->lo[1] + ((double)j + 0.5) * h;
+    z[2] = T->lo[2] + ((double)k + 0.5) * h;
+}
+
+/* leaf coordinate: floor((x - lo)/side * 2^d), clamped to [0, 2^d-1] */
+static int64_t leaf_coord(double x, double lo, double side, int d)
+{
+    double s = floor((x - lo) / side * (double)ncell1(d));
+    int64_t i = (int64_t)s;
+    if (s < 0.0) i = 0;
+    if (i > ncell1(d) - 1) i = ncell1(d) - 1;
+    return i;
+}
+
+static int build_tree(otree *T)
+{
+    int d = T->depth;
+    int64_t nl = ncell1(3 * d);
+    T->leaf_of = (int64_t *)malloc((size_t)(T->n > 0 ? T->n : 1) * sizeof(int64_t));
+    T->start = (int64_t *)calloc((size_t)nl + 1, sizeof(int64_t));
+    T->order = (int64_t *)malloc((size_t)(T->n > 0 ? T->n : 1) * sizeof(int64_t));
+    if (!T->leaf_of || !T->start || !T->order) return -1;
+    for (int64_t a = 0; a < T->n; ++a) {
+        int64_t i = leaf_coord(T->xyz[3 * a + 0], T->lo[0], T->side, d);
+        int64_t j = leaf_coord(T->xyz[3 * a + 1], T->lo[1], T->side, d);
+        int64_t k = leaf_coord(T->xyz[3 * a + 2], T->lo[2], T->side, d);
+        T->leaf_of[a] = cell_id(d, i, j, k);
+        T->start[T->leaf_of[a] + 1]++;
+    }
+    for (int64_t c = 0; c < nl; ++c) T->start[c + 1] += T->start[c];
+    int64_t *fill = (int64_t *)malloc((size_t)nl * sizeof(int64_t));
+    if (!fill) return -1;
+    memcpy(fill, T->start, (size_t)nl * sizeof(int64_t));
+    for (int64_t a = 0; a < T->n; ++a) T->order[fill[T->leaf_of[a]]++] = a;
+    free(fill);
+    return 0;
+}
+
+static void free_tree(otree *T)
+{
+    free(T->leaf_of);
+    free(T->start);
+    free(T->order);
+    if (T->M) for (int l = 0; l <= T->depth; ++l) free(T->M[l]);
+    if (T->L) for (int l = 0; l <= T->depth; ++l) free(T->L[l]);
+    free(T->M);
+    free(T->L);
+}
+
+/* upward pass: P2M at every leaf, then M2M from level depth to level 2 */
+static int upward(otree *T)
+{
+    int d = T->depth, nf = T->nf, p = T->p;
+    T->M = (double **)calloc((size_t)d + 1, sizeof(double *));
+    if (!T->M) return -1;
+    for (int l = 2; l <= d; ++l) {
+        T->M[l] = (double *)calloc((size_t)ncell1(3 * l) * nf, sizeof(double));
+        if (!T->M[l]) return -1;
+    }
+    int64_t nside = ncell1(d);
+#pragma omp parallel
+    {
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t c = 0; c < ncell1(3 * d); ++c) {
+            int64_t b = T->start[c], e = T->start[c + 1];
+            if (e == b) continue;
+            int64_t i = c % nside, j = (c / nside) % nside, k = c / (nside * nside);
+            double z[3];
+            cell_center(T, d, i, j, k, z);
+            double *px = (double *)malloc((size_t)(e - b) * 3 * sizeof(double));
+            double *pq = (double *)malloc((size_t)(e - b) * sizeof(double));
+            for (int64_t s = b; s < e; ++s) {
+                int64_t a = T->order[s];
+                px[3 * (s - b) + 0] = T->xyz[3 * a + 0];
+                px[3 * (s - b) + 1] = T->xyz[3 * a + 1];
+                px[3 * (s - b) + 2] = T->xyz[3 * a + 2];
+                pq[s - b] = T->q[a];
+            }
+            oracle_p2m(p, z, e - b, px, pq, &T->M[d][(size_t)c * nf]);
+            free(px);
+            free(pq);
+        }
+    }
+    for (int l = d; l >= 3; --l) {
+        int64_t ns = ncell1(l - 1);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t c = 0; c < ncell1(3 * (l - 1)); ++c) {
+            int64_t I = c % ns, J = (c / ns) % ns, K = c / (ns * ns);
+            double zp[3];
+            cell_center(T, l - 1, I, J, K, zp);
+            for (int o = 0; o < 8; ++o) {
+                int64_t i = 2 * I + (o & 1), j = 2 * J + ((o >> 1) & 1), k = 2 * K + ((o >> 2) & 1);
+                double zc[3], dd[3];
+                cell_center(T, l, i, j, k, zc);
+                dd[0] = zc[0] - zp[0]; dd[1] = zc[1] - zp[1]; dd[2] = zc[2] - zp[2];
+                oracle_m2m(p, dd, &T->M[l][(size_t)cell_id(l, i, j, k) * nf], &T->M[l - 1][(size_t)c * nf]);
+            }
+        }
+    }
+    return 0;
+}
+
+static inline int64_t iabs64(int64_t x) { return x < 0 ? -x : x; }
+static inline int64_t imax3(int64_t a, int64_t b, int64_t c) { int64_t m = a > b ? a : b; return m > c ? m : c; }
+
+/* M2L into cell (i,j,k) at level l from its ws=1 interaction list */
+static void m2l_cell(otree *T, int l, int64_t i, int64_t j, int64_t k, double *Lc)
+{
+    int nf = T->nf, p = T->p;
+    int64_t ns = ncell1(l);
+    int64_t I = i >> 1, J = j >> 1, K = k >> 1;
+    double zb[3];
+    cell_center(T, l, i, j, k, zb);
+    for (int64_t a = 2 * (I - 1); a <= 2 * (I + 1) + 1; ++a)
+        for (int64_t b = 2 * (J - 1); b <= 2 * (J + 1) + 1; ++b)
+            for (int64_t c = 2 * (K - 1); c <= 2 * (K + 1) + 1; ++c) {
+                if (a < 0 || b < 0 || c < 0 || a >= ns || b >= ns || c >= ns) continue;
+                if (imax3(iabs64(a - i), iabs64(b - j), iabs64(c - k)) <= 1) continue;
+                double za[3], r[3];
+                cell_center(T, l, a, b, c, za);
+                r[0] = zb[0] - za[0]; r[1] = zb[1] - za[1]; r[2] = zb[2] - za[2];
+                oracle_m2l(p, r, &T->M[l][(size_t)cell_id(l, a, b, c) * nf], Lc);
+            }
+}
+
+/*
+ * Downward pass for the cells in `need` (per level, a 0/1 mask of the cells
+ * whose L is needed).  L of a needed cell = M2L from its interaction list
+ * + L2L from its parent (levels >= 3).
+ */
+static int downward(otree *T, unsigned char **need)
+{
+    int d = T->depth, nf = T->nf, p = T->p;
+    T->L = (double **)calloc((size_t)d + 1, sizeof(double *));
+    if (!T->L) return -1;
+    for (int l = 2; l <= d; ++l) {
+        T->L[l] = (double *)calloc((size_t)ncell1(3 * l) * nf, sizeof(double));
+        if (!T->L[l]) return -1;
+    }
+    for (int l = 2; l <= d; ++l) {
+        int64_t ns = ncell1(l);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t c = 0; c < ncell1(3 * l); ++c) {
+            if (need && !need[l][c]) continue;
+            int64_t i = c % ns, j = (c / ns) % ns, k = c / (ns * ns);
+            double *Lc = &T->L[l][(size_t)c * nf];
+            if (l >= 3) {
+                double zc[3], zp[3], dd[3];
+                cell_center(T, l, i, j, k, zc);
+                cell_center(T, l - 1, i >> 1, j >> 1, k >> 1, zp);
+                dd[0] = zc[0] - zp[0]; dd[1] = zc[1] - zp[1]; dd[2] = zc[2] - zp[2];
+                oracle_l2l(p, dd, &T->L[l - 1][(size_t)cell_id(l - 1, i >> 1, j >> 1, k >> 1) * nf], Lc);
+            }
+            m2l_cell(T, l, i, j, k, Lc);
+        }
+    }
+    return 0;
+}
+
+/* far field (L2P) + near field (P2P over adjacent-or-equal leaves) for particle b */
+static void evaluate_particle(const otree *T, int64_t b, double *phi, double *grad)
+{
+    int d = T->depth;
+    int64_t ns = ncell1(d);
+    int64_t c = T->leaf_of[b];
+    int64_t i = c % ns, j = (c / ns) % ns, k = c / (ns * ns);
+    double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+    if (d >= 2) {
+        double z[3], rb[3];
+        cell_center(T, d, i, j, k, z);
+        rb[0] = T->xyz[3 * b + 0] - z[0];
+        rb[1] = T->xyz[3 * b + 1] - z[1];
+        rb[2] = T->xyz[3 * b + 2] - z[2];
+        oracle_l2p(T->p, rb, &T->L[d][(size_t)c * T->nf], &f, g);
+    }
+    for (int64_t a1 = i - 1; a1 <= i + 1; ++a1)
+        for (int64_t b1 = j - 1; b1 <= j + 1; ++b1)
+            for (int64_t c1 = k - 1; c1 <= k + 1; ++c1) {
+                if (a1 < 0 || b1 < 0 || c1 < 0 || a1 >= ns || b1 >= ns || c1 >= ns) continue;
+                int64_t src = cell_id(d, a1, b1, c1);
+                for (int64_t s = T->start[src]; s < T->start[src + 1]; ++s) {
+                    int64_t a = T->order[s];
+                    if (a == b) continue;
+                    pair_kernel(&T->xyz[3 * b], &T->xyz[3 * a], T->q[a], &f, g);
+                }
+            }
+    phi[0] = f;
+    grad[0] = g[0];
+    grad[1] = g[1];
+    grad[2] = g[2];
+}
+
+/*
+ * Full FMM on a uniform octree of the given depth over the cube
+ * [lo, lo+side)^3.  Targets: tgt[0..nt) particle indices, or all particles
+ * (in input order) when tgt is NULL.  Only cells on the paths of the target
+ * leaves get a downward pass, so a sample of targets costs the upward pass
+ * plus work proportional to the sample.
+ *
+ * M_dump/L_dump (optional, may be NULL): full-storage expansions of every
+ * cell of levels 0..depth, cells row-major (x fastest) within a level,
+ * levels concatenated; levels below 2 (and unneeded cells) are zero.
+ *
+ * Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
+ */
+int oracle_fmm_uniform(int64_t n, const double *xyz, const double *q, int p, int depth,
+                       const double lo[3], double side, int64_t nt, const int64_t *tgt,
+                       double *phi, double *grad, double *M_dump, double *L_dump, int nthreads)
+{
+    init_tables();
+    if (p < 0 || p > OR_PMAX || depth < 0 || depth > 9 || n < 0 || side <= 0.0) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    otree T;
+    memset(&T, 0, sizeof(T));
+    T.p = p; T.depth = depth; T.nf = g_nfull[p];
+    T.lo[0] = lo[0]; T.lo[1] = lo[1]; T.lo[2] = lo[2]; T.side = side;
+    T.n = n; T.xyz = xyz; T.q = q;
+    int rc = 0;
+    unsigned char **need = NULL;
+    if (build_tree(&T)) { rc = -2; goto done; }
+    if (depth >= 2) {
+        if (upward(&T)) { rc = -2; goto done; }
+        if (tgt) {
+            need = (unsigned char **)calloc((size_t)depth + 1, sizeof(unsigned char *));
+            if (!need) { rc = -2; goto done; }
+            for (int l = 0; l <= depth; ++l) {
+                need[l] = (unsigned char *)calloc((size_t)ncell1(3 * l), 1);
+                if (!need[l]) { rc = -2; goto done; }
+            }
+            int64_t ns = ncell1(depth);
+            for (int64_t t = 0; t < nt; ++t) {
+                int64_t c = T.leaf_of[tgt[t]];
+                int64_t i = c % ns, j = (c / ns) % ns, k = c / (ns * ns);
+                for (int l = depth; l >= 0; --l) {
+                    need[l][cell_id(l, i, j, k)] = 1;
+                    i >>= 1; j >>= 1; k >>= 1;
+                }
+            }
+        }
+        if (downward(&T, need)) { rc = -2; goto done; }
+    }
+    {
+        int64_t cnt = tgt ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t t = 0; t < cnt; ++t) {
+            int64_t b = tgt ? tgt[t] : t;
+            evaluate_particle(&T, b, &phi[t], &grad[3 * t]);
+        }
+    }
+    if (M_dump || L_dump) {
+        size_t off = 0;
+        for (int l = 0; l <= depth; ++l) {
+            size_t cnt = (size_t)ncell1(3 * l) * T.nf;
+            if (M_dump) {
+                if (l >= 2 && T.M) memcpy(M_dump + off, T.M[l], cnt * sizeof(double));
+                else memset(M_dump + off, 0, cnt * sizeof(double));
+            }
+            if (L_dump) {
+                if (l >= 2 && T.L) memcpy(L_dump + off, T.L[l], cnt * sizeof(double));
+                else memset(L_dump + off, 0, cnt * sizeof(double));
+            }
+            off += cnt;
+        }
+    }
+done:
+    if (need) {
+        for (int l = 0; l <= depth; ++l) free(need[l]);
+        free(need);
+    }
+    free_tree(&T);
+    return rc;
+}
+
+/* threads the OpenMP runtime will use for the next parallel region */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,419 @@
+"""Pins for the FP64 oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own formulas.
+
+Each ``pin_*`` function takes an oracle module (``oracle`` or a mutant built
+from a patched copy of its source) and raises AssertionError when the oracle
+disagrees.  ``tests/test_oracle_pins.py`` runs them on the real oracle;
+``tests/test_oracle_mutants.py`` plants plausible mistakes in copies of the
+oracle and checks that at least one pin fails for each.
+"""
+from __future__ import annotations
+
+import functools
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line)
+    return rows
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64); b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+# --------------------------------------------------------------- helpers
+
+def _trace_residual(o, p, A):
+    """max over ranks n >= 2 and k (|k| = n-2) of |A_{k+2x}+A_{k+2y}+A_{k+2z}|,
+    relative to max |A| of that rank (Appendix A: one-fold trace)."""
+    mi = o.multi_indices(p)
+    pos = {m: i for i, m in enumerate(mi)}
+    worst = 0.0
+    for n in range(2, p + 1):
+        scale = max(abs(A[pos[m]]) for m in mi if sum(m) == n) or 1.0
+        for k in mi:
+            if sum(k) != n - 2:
+                continue
+            a, b, c = k
+            t = A[pos[(a + 2, b, c)]] + A[pos[(a, b + 2, c)]] + A[pos[(a, b, c + 2)]]
+            worst = max(worst, abs(t) / scale)
+    return worst
+
+
+def _contract(o, p, n, A, B):
+    """n-fold contraction of the rank-n parts: sum_{|k|=n} n!/k! A_k B_k."""
+    s = 0.0
+    for i, k in enumerate(o.multi_indices(p)):
+        if sum(k) == n:
+            s += math.factorial(n) / (math.factorial(k[0]) * math.factorial(k[1]) * math.factorial(k[2])) * A[i] * B[i]
+    return s
+
+
+def _outer_powers(o, p, r):
+    """the full polytensor r^n (all ranks <= p): component n is rx^a ry^b rz^c."""
+    return np.array([r[0] ** a * r[1] ** b * r[2] ** c for (a, b, c) in o.multi_indices(p)])
+
+
+@functools.lru_cache(maxsize=None)
+def _sympy_grad_table(maxrank):
+    import sympy as sp
+    x, y, z = sp.symbols("x y z", real=True)
+    f = 1 / sp.sqrt(x * x + y * y + z * z)
+    table = {}
+    for n in range(maxrank + 1):
+        for a in range(n + 1):
+            for b in range(n - a + 1):
+                c = n - a - b
+                e = f
+                if a: e = sp.diff(e, x, a)
+                if b: e = sp.diff(e, y, b)
+                if c: e = sp.diff(e, z, c)
+                table[(a, b, c)] = sp.lambdify((x, y, z), e, "math")
+    return table
+
+
+# --------------------------------------------------------------- pins
+
+def pin_storage_table(o):
+    """Appendix table of element counts: full storage C(p+3,3) and the
+    (p+1)^2 independent traceless components (those with n_z <= 1)."""
+    for row in _read_golden("storage_table.txt"):
+        p, full_p, full_tot, tl_p, tl_tot, _ = (int(v) for v in row.split())
+        assert o.nfull(p) == full_tot, (p, o.nfull(p), full_tot)
+        mi = o.multi_indices(p)
+        assert len(set(mi)) == full_tot
+        assert sum(1 for m in mi if sum(m) == p) == full_p
+        assert sum(1 for m in mi if m[2] <= 1) == tl_tot
+        assert sum(1 for m in mi if m[2] <= 1 and sum(m) == p) == tl_p
+
+
+def pin_dtensor_sympy(o):
+    """D_k(r) = grad^k (1/r) (Eq. traceless grad) against SymPy's symbolic
+    derivatives, every component of rank <= 5 plus all of rank 7."""
+    table = _sympy_grad_table(7)
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        r = rng.uniform(-2.0, 2.0, 3)
+        r[0] += 2.5
+        D = o.dtensor(7, r)
+        for i, m in enumerate(o.multi_indices(7)):
+            if sum(m) <= 5 or sum(m) == 7:
+                ref = table[m](*r)
+                scale = math.factorial(sum(m)) / np.linalg.norm(r) ** (sum(m) + 1)
+                assert abs(D[i] - ref) <= 1e-12 * scale, (m, D[i], ref)
+
+
+def pin_dtensor_excerpt(o):
+    """Rank-2 diagonal of the traceless gradient as printed in the M2L
+    optimisation example (Sec. 2.2)."""
+    import sympy as sp
+    x, y, z, h, u = sp.symbols("x y z h u")
+    rng = np.random.default_rng(12)
+    for _ in range(4):
+        r = rng.uniform(-1.5, 1.5, 3)
+        hv = float(r @ r); uv = hv ** -0.5
+        D = o.dtensor(2, r)
+        for row in _read_golden("dtensor_rank2_excerpt.txt"):
+            lhs, rhs = row.split("=")
+            idx = tuple(int(v) for v in lhs.split())
+            val = float(sp.sympify(rhs).subs({x: r[0], y: r[1], z: r[2], h: hv, u: uv}))
+            assert abs(D[o.full_index(*idx)] - val) <= 1e-13 * abs(uv ** 3) * 3, (idx, val)
+
+
+def pin_detracer_invariants(o):
+    """Appendix A: D[A] is traceless, D D = D, T T = (2n-1)!! T, and the
+    detracer exchange theorem A.n.T[B] = T[A].n.B, on random symmetric A, B."""
+    p = 6
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal(o.nfull(p))
+    B = rng.standard_normal(o.nfull(p))
+    DA = o.detracer_D(p, A)
+    assert _trace_residual(o, p, DA) < 1e-13
+    assert rel(o.detracer_D(p, DA), DA) < 1e-13
+    TA = o.detracer_T(p, A)
+    TTA = o.detracer_T(p, TA)
+    mi = o.multi_indices(p)
+    dfact = [1.0] * (2 * p + 2)
+    for n in range(p + 1):
+        f = 1.0
+        for i in range(2 * n - 1, 1, -2):
+            f *= i
+        dfact[n] = f
+    for i, m in enumerate(mi):
+        n = sum(m)
+        assert abs(TTA[i] - dfact[n] * TA[i]) <= 1e-11 * max(1.0, abs(dfact[n] * TA[i]))
+    TB = o.detracer_T(p, B)
+    for n in range(p + 1):
+        l = _contract(o, p, n, A, TB)
+        r = _contract(o, p, n, TA, B)
+        assert abs(l - r) <= 1e-11 * max(1.0, abs(l)), (n, l, r)
+    # a traceless input is a fixed point of D
+    assert rel(o.detracer_D(p, o.detracer_D(p, B)), o.detracer_D(p, B)) < 1e-13
+
+
+def pin_detracer_vs_gradient(o):
+    """Eq. traceless grad relates the general detracer (Eq. Detracer) applied
+    to the polytensor r^n and the derivatives of 1/r:
+    T[r^n]_n = (-1)^n r^(2n+1) grad^n r^-1, with the derivatives from SymPy."""
+    p = 6
+    table = _sympy_grad_table(p)
+    r = np.array([0.7, -1.1, 0.4])
+    T = o.detracer_T(p, _outer_powers(o, p, r))
+    rn = np.linalg.norm(r)
+    for i, m in enumerate(o.multi_indices(p)):
+        n = sum(m)
+        ref = (-1) ** n * rn ** (2 * n + 1) * table[m](*r)
+        assert abs(T[i] - ref) <= 1e-11 * max(1.0, abs(ref)), (m, T[i], ref)
+
+
+def pin_m2l_listing(o):
+    """The printed symbolic L_x of M2L at p = 3 (Sec. 2.2): exactly the listed
+    terms with weights 1/m!, nothing else."""
+    p = 3
+    terms = {}
+    for row in _read_golden("m2l_Lx_p3.txt"):
+        v = row.split()
+        m = tuple(int(t) for t in v[0:3]); k = tuple(int(t) for t in v[3:6])
+        terms[m] = (k, float(v[6]))
+    mi = o.multi_indices(p)
+    lx = o.full_index(1, 0, 0)
+    rng = np.random.default_rng(14)
+    D = rng.standard_normal(o.nfull(p))
+    for j, m in enumerate(mi):
+        M = np.zeros(o.nfull(p)); M[j] = 1.0
+        L = o.m2l_with_D(p, M, D)
+        if m in terms:
+            k, w = terms[m]
+            assert abs(L[lx] - w * D[o.full_index(*k)]) < 1e-15, (m, L[lx])
+        else:
+            assert L[lx] == 0.0, m
+
+
+def pin_single_particle_at_centre(o):
+    """A charge at the expansion centre has M = q delta_{n,0}; its M2L is then
+    L_n = q grad^n(1/r) exactly (SymPy derivatives)."""
+    p = 6
+    q = 1.7
+    z = np.array([0.3, 0.2, 0.9])
+    M = o.p2m(p, z, z[None, :], np.array([q]))
+    e0 = np.zeros(o.nfull(p)); e0[0] = q
+    assert rel(M, e0) < 1e-15
+    r = np.array([2.1, -0.4, 1.3])
+    L = o.m2l(p, r, M)
+    table = _sympy_grad_table(p)
+    for i, m in enumerate(o.multi_indices(p)):
+        ref = q * table[m](*r)
+        assert abs(L[i] - ref) <= 1e-12 * max(1e-3, abs(ref)), (m, L[i], ref)
+
+
+def _cluster_case(o, p):
+    rng = np.random.default_rng(15)
+    src = rng.random((20, 3)) * 0.5
+    zA = np.array([0.25, 0.25, 0.25])
+    q = rng.uniform(0.5, 1.5, 20)
+    zB = np.array([1.25, 0.25, 0.25])
+    xb = zB + np.array([0.05, -0.1, 0.12])
+    M = o.p2m(p, zA, src, q)
+    L = o.m2l(p, zB - zA, M)
+    f, g = o.l2p(p, xb - zB, L)
+    d = xb - src
+    r = np.linalg.norm(d, axis=1)
+    fe = float((q / r).sum())
+    ge = -(q[:, None] * d / r[:, None] ** 3).sum(0)
+    return abs(f - fe) / fe, rel(g, ge)
+
+
+def pin_far_field_vs_direct(o):
+    """P2M -> M2L -> L2P reproduces the brute-force sum over 20 sources, with
+    the error falling as p grows (truncation of Eq. phi expansion)."""
+    prev = None
+    errs = []
+    for p in (2, 4, 6, 8, 10):
+        eP, eF = _cluster_case(o, p)
+        errs.append((p, eP, eF))
+        if prev is not None:
+            assert eF < prev, errs
+        prev = eF
+    assert errs[0][2] < 0.2 and errs[-1][2] < 5e-4 and errs[-1][1] < 1e-5, errs
+
+
+def pin_m2m_exact(o):
+    """M2M(P2M at z) equals P2M at the shifted centre z' (the paper's own
+    self-check, Sec. 2.2): the shift is exact."""
+    p = 8
+    rng = np.random.default_rng(16)
+    x = rng.random((15, 3)) * 0.5
+    q = rng.uniform(-1, 1, 15)
+    z = np.array([0.25, 0.25, 0.25])
+    zp = np.array([0.5, 0.5, 0.5])
+    M = o.p2m(p, z, x, q)
+    Ms = o.m2m(p, z - zp, M)
+    Mref = o.p2m(p, zp, x, q)
+    assert rel(Ms, Mref) < 1e-13, rel(Ms, Mref)
+
+
+def pin_l2l_exact(o):
+    """L2L is a Taylor shift of the degree-p local polynomial, so evaluating
+    after the shift equals evaluating before it (Eq. L2L, Eq. L2P)."""
+    p = 7
+    rng = np.random.default_rng(17)
+    L = rng.standard_normal(o.nfull(p))
+    d = np.array([0.1, -0.2, 0.15])
+    Ls = o.l2l(p, d, L)
+    for _ in range(3):
+        x = rng.uniform(-0.3, 0.3, 3)
+        f0, g0 = o.l2p(p, x, L)
+        f1, g1 = o.l2p(p, x - d, Ls)
+        assert abs(f0 - f1) <= 1e-12 * max(1.0, abs(f0))
+        assert rel(g1, g0) < 1e-12
+
+
+def pin_traceless_outputs(o):
+    """P2M, M2M, M2L and L2L outputs are totally traceless (Appendix B)."""
+    p = 7
+    rng = np.random.default_rng(18)
+    x = rng.random((12, 3)) * 0.4
+    q = rng.uniform(0.5, 1.5, 12)
+    M = o.p2m(p, np.array([0.2, 0.2, 0.2]), x, q)
+    assert _trace_residual(o, p, M) < 1e-13
+    M2 = o.m2m(p, np.array([-0.2, -0.2, -0.2]), M)
+    assert _trace_residual(o, p, M2) < 1e-13
+    L = o.m2l(p, np.array([1.5, 0.5, -0.5]), M2)
+    assert _trace_residual(o, p, L) < 1e-12
+    L2 = o.l2l(p, np.array([0.1, 0.05, -0.1]), L)
+    assert _trace_residual(o, p, L2) < 1e-12
+
+
+def pin_laplace(o):
+    """The local expansion's potential is harmonic: central differences of
+    the L2P gradient give a Laplacian that is tiny next to its diagonal terms."""
+    p = 8
+    rng = np.random.default_rng(19)
+    x = rng.random((10, 3)) * 0.5
+    q = rng.uniform(0.5, 1.5, 10)
+    M = o.p2m(p, np.array([0.25, 0.25, 0.25]), x, q)
+    L = o.m2l(p, np.array([1.2, 0.3, 0.6]), M)
+    h = 1e-4
+    pt = np.array([0.05, -0.08, 0.1])
+    lap = 0.0; diag = 0.0
+    for i in range(3):
+        e = np.zeros(3); e[i] = h
+        gp = o.l2p(p, pt + e, L)[1][i]
+        gm = o.l2p(p, pt - e, L)[1][i]
+        d2 = (gp - gm) / (2 * h)
+        lap += d2; diag += abs(d2)
+    assert abs(lap) < 1e-6 * diag, (lap, diag)
+
+
+def pin_direct_two_body(o):
+    """Eq. PhiAB for two charges, with self pairs excluded and coincident
+    pairs contributing nothing."""
+    xyz = np.array([[0.0, 0.0, 0.0], [0.3, 0.4, 0.0], [0.3, 0.4, 0.0]])
+    q = np.array([2.0, 3.0, 5.0])
+    phi, grad = o.direct(xyz, q)
+    d = 0.5
+    assert abs(phi[0] - (3.0 + 5.0) / d) < 1e-14
+    assert abs(phi[1] - 2.0 / d) < 1e-14 and abs(phi[2] - 2.0 / d) < 1e-14
+    g1 = -2.0 * np.array([0.3, 0.4, 0.0]) / d ** 3
+    assert rel(grad[1], g1) < 1e-14
+    g0 = -(8.0) * np.array([-0.3, -0.4, 0.0]) / d ** 3
+    assert rel(grad[0], g0) < 1e-14
+
+
+def pin_fmm_shallow_is_direct(o):
+    """With depth <= 1 every leaf is adjacent to every other, so the FMM is
+    the near field alone and equals the direct sum."""
+    rng = np.random.default_rng(20)
+    xyz = rng.random((300, 3)); q = rng.uniform(-1, 1, 300)
+    pd, gd = o.direct(xyz, q)
+    for depth in (0, 1):
+        pf, gf = o.fmm_uniform(xyz, q, 4, depth)
+        assert rel(pf, pd) < 1e-13 and rel(gf, gd) < 1e-13
+
+
+def pin_fmm_vs_direct_decay(o):
+    """Full FMM (uniform octree, ws=1) against the O(N^2) sum: the relative
+    errors fall monotonically with p and are at the truncation level."""
+    from paper_1811_06332_amd.workloads import uniform_cube
+    xyz, q = uniform_cube(1024, 21)
+    pd, gd = o.direct(xyz, q)
+    prev = None
+    errs = []
+    for p in (2, 4, 6, 8):
+        pf, gf = o.fmm_uniform(xyz, q, p, 3)
+        eP, eF = rel(pf, pd), rel(gf, gd)
+        errs.append((p, eP, eF))
+        if prev is not None:
+            assert eF < prev[1] and eP < prev[0], errs
+        prev = (eP, eF)
+    assert errs[0][2] < 3e-2 and errs[-1][2] < 1e-3, errs
+
+
+def pin_fmm_sampled(o):
+    """Evaluating a sample of targets gives exactly the full run's values."""
+    from paper_1811_06332_amd.workloads import uniform_cube
+    xyz, q = uniform_cube(2000, 22)
+    pf, gf = o.fmm_uniform(xyz, q, 5, 3)
+    idx = np.array([3, 17, 999, 1500, 1999])
+    ps, gs = o.fmm_uniform(xyz, q, 5, 3, targets=idx)
+    assert np.array_equal(ps, pf[idx]) and np.array_equal(gs, gf[idx])
+
+
+def pin_m2m_then_m2l(o):
+    """M2L from a parent expansion obtained by M2M agrees with M2L from the
+    child expansion up to truncation, with the gap shrinking as p grows."""
+    rng = np.random.default_rng(23)
+    x = rng.random((16, 3)) * 0.25 + 0.25  # inside the child [0.25,0.5)^3
+    q = rng.uniform(0.5, 1.5, 16)
+    zc = np.array([0.375, 0.375, 0.375]); zp = np.array([0.5, 0.5, 0.5])
+    zB = np.array([2.5, 0.5, 0.5])
+    prev = None
+    for p in (4, 8, 12):
+        Mc = o.p2m(p, zc, x, q)
+        Mp = o.m2m(p, zc - zp, Mc)
+        L1 = o.m2l(p, zB - zc, Mc)
+        L2 = o.m2l(p, zB - zp, Mp)
+        f1, g1 = o.l2p(p, np.zeros(3), L1)
+        f2, g2 = o.l2p(p, np.zeros(3), L2)
+        e = rel(g2, g1)
+        if prev is not None:
+            assert e < prev, (p, e, prev)
+        prev = e
+    assert prev < 1e-6
+
+
+def pin_fmm_expansion_centres(o):
+    """Expansions sit at the geometric cell centres (Appendix C): a charge
+    placed at the centre of its leaf gives that leaf M = q delta_{n,0}, and
+    its parent's M equals a P2M about the parent's geometric centre."""
+    depth, p = 3, 4
+    h = 1.0 / 2 ** depth
+    leaves = [(1, 2, 3), (6, 5, 0)]
+    xyz = np.array([[(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h] for (i, j, k) in leaves])
+    q = np.array([1.5, -0.75])
+    _, _, Ms, _ = o.fmm_uniform(xyz, q, p, depth, dump=True)
+    n1 = 2 ** depth
+    for (i, j, k), x, qq in zip(leaves, xyz, q):
+        M = Ms[depth][i + n1 * (j + n1 * k)]
+        ref = np.zeros(o.nfull(p)); ref[o.full_index(0, 0, 0)] = qq
+        assert rel(M, ref) < 1e-14, (i, j, k)
+        I, J, K = i // 2, j // 2, k // 2
+        zp = np.array([(I + 0.5) * 2 * h, (J + 0.5) * 2 * h, (K + 0.5) * 2 * h])
+        Mp = Ms[depth - 1][I + (n1 // 2) * (J + (n1 // 2) * K)]
+        assert rel(Mp, o.p2m(p, zp, x[None, :], np.array([qq]))) < 1e-13
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
