@@ -1,0 +1,166 @@
+/*
+ * ctfmm.h -- C ABI of libctfmm: the Cartesian traceless fast multipole
+ * method (Coles & Bieri, "An Optimizing Symbolic Algebra Approach for
+ * Generating Fast Multipole Method Operators", arXiv 1811.06332) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Problem (Appendix B, Eq. PhiAB; Sec. 2.1, Eq. L2P): given N particles with
+ * positions x_a and weights q_a, compute for every particle b
+ *     Phi(x_b)      = sum_{a != b} q_a / |x_b - x_a|
+ *     grad Phi(x_b) = -sum_{a != b} q_a (x_b - x_a) / |x_b - x_a|^3
+ * approximated by the FMM operators P2M, M2M, M2L, L2L, L2P (Sec. 2.1) with
+ * a direct near field (Appendix C).  The potential is positive for positive
+ * weights (Sec. 2.1); gravitational users negate Phi and grad Phi.  Free
+ * space: no periodic images.  A pair at exactly zero distance contributes
+ * nothing.  Accuracy is set by the expansion order p and the
+ * well-separation rule (Appendix C): here a cell interacts through M2L with
+ * the same-level cells that are not adjacent to it but whose parents are
+ * adjacent to its parent (ws = 1); adjacent leaves are summed directly.
+ *
+ * Conventions for every function:
+ *   - Pointers named "dev" are device (HIP) memory, "host" host memory.
+ *   - The caller owns every buffer it passes; the library never frees them.
+ *   - Work is asynchronous on the stream given to ctfmm_create; results are
+ *     valid after ctfmm_sync or any later stream-ordered operation.
+ *   - Every function returns a ctfmm_status; no exception crosses the ABI
+ *     and nothing aborts.  ctfmm_last_error gives a message for the last
+ *     failure on a context.
+ *   - A context is not thread-safe: use one context per host thread/stream.
+ */
+#ifndef CTFMM_H
+#define CTFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTFMM_ABI_VERSION 1
+/* largest expansion order compiled in */
+#define CTFMM_P_MAX 10
+/* deepest uniform octree (2^(3*depth) leaves) */
+#define CTFMM_DEPTH_MAX 9
+
+typedef struct ctfmm_ctx ctfmm_ctx;
+
+typedef enum ctfmm_status {
+    CTFMM_OK = 0,
+    CTFMM_EINVAL = 1,       /* bad argument: null pointer, n < 0, p or depth out of range,
+                               non-finite coordinate (reported by ctfmm_sync) */
+    CTFMM_ENOMEM = 2,       /* device allocation failed (or the allocator returned NULL) */
+    CTFMM_EDEVICE = 3,      /* a HIP runtime call failed */
+    CTFMM_EUNSUPPORTED = 4  /* valid request this build does not implement */
+} ctfmm_status;
+
+typedef enum ctfmm_tree {
+    CTFMM_TREE_UNIFORM = 0  /* uniform octree of the given depth over a cube */
+} ctfmm_tree;
+
+/* Arithmetic of the M2L translation.  Everything else (P2M, M2M, L2L, L2P,
+ * P2P, the derivative tensors) is always FP64. */
+typedef enum ctfmm_precision {
+    CTFMM_PREC_FP64 = 0,        /* FP64 matrix cores, FP64 accumulation */
+    CTFMM_PREC_FP32 = 1,        /* FP32 matrix cores, FP32 accumulation */
+    CTFMM_PREC_BF16X3 = 2       /* operands split into three BF16 pieces, the six
+                                   leading piece products on BF16 matrix cores,
+                                   FP32 accumulation */
+} ctfmm_precision;
+
+typedef struct ctfmm_params {
+    int32_t order_p;    /* expansion order p, 0..CTFMM_P_MAX */
+    int32_t tree;       /* ctfmm_tree */
+    int32_t depth;      /* leaf level of the uniform octree, 0..CTFMM_DEPTH_MAX */
+    int32_t ws;         /* well-separation in cells; only 1 is supported */
+    int32_t precision;  /* ctfmm_precision */
+    int32_t reserved0;
+    double root_lo[3];  /* lower corner of the root cube */
+    double root_side;   /* side of the root cube; particles outside are clamped
+                           into the boundary leaves */
+} ctfmm_params;
+
+typedef struct ctfmm_stats_t {
+    /* accumulated over evaluate calls since the last ctfmm_reset_stats,
+       measured with HIP events on the context stream when timing is on */
+    double ms_total;        /* whole evaluate calls */
+    double ms_tree;         /* keys, sort, leaf ranges */
+    double ms_p2m;
+    double ms_m2m;
+    double ms_m2l;          /* all M2L launches */
+    double ms_l2l;
+    double ms_near;         /* L2P + P2P */
+    int64_t evaluations;
+    int64_t m2l_launches;
+    int64_t m2l_pairs;      /* cell pairs translated by M2L, summed over calls */
+    int64_t p2p_leaf_pairs; /* leaf pairs of the near field, summed over calls */
+} ctfmm_stats_t;
+
+/* ABI version (CTFMM_ABI_VERSION). */
+int ctfmm_version(void);
+
+/* Fill *prm with defaults: p = 4, uniform tree, depth 3, ws = 1, FP64,
+ * root cube [0,1)^3.  Returns CTFMM_EINVAL if prm is NULL. */
+ctfmm_status ctfmm_default_params(ctfmm_params* prm);
+
+/* Create a context on the current HIP device, bound to hip_stream (a
+ * hipStream_t; NULL = the null stream).  Builds the per-offset M2L operator
+ * matrices for the requested p and precision.  *out receives the context
+ * (owned by the library; release with ctfmm_destroy).
+ * Errors: EINVAL (null prm/out, p, depth or ws out of range, root_side <= 0
+ * or not finite), EUNSUPPORTED (tree or precision unknown), ENOMEM, EDEVICE. */
+ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx** out);
+
+/* Route every device workspace allocation through alloc/free (called with
+ * the user pointer and the context stream).  Call before the first
+ * evaluate; buffers already held are released first.  NULL alloc restores
+ * hipMalloc/hipFree.  An alloc returning NULL makes the call that needed
+ * memory fail with ENOMEM. */
+typedef void* (*ctfmm_alloc_fn)(size_t bytes, void* user, void* hip_stream);
+typedef void (*ctfmm_free_fn)(void* ptr, void* user, void* hip_stream);
+ctfmm_status ctfmm_set_allocator(ctfmm_ctx* ctx, ctfmm_alloc_fn alloc, ctfmm_free_fn free_fn, void* user);
+
+/* Potential and gradient of n particles.
+ *   xyz  dev, n*3 doubles, row-major (x0,y0,z0,x1,...)
+ *   q    dev, n doubles
+ *   phi  dev, n doubles, may be NULL (not written)
+ *   grad dev, n*3 doubles row-major, may be NULL
+ * Outputs are in input order.  n = 0 is a no-op.  n must be < 2^31.
+ * The workspace grows to fit n and is kept for later calls. */
+ctfmm_status ctfmm_evaluate(ctfmm_ctx* ctx, int64_t n, const double* xyz, const double* q,
+                            double* phi, double* grad);
+
+/* Copy the expansions of one level of the last evaluate to host memory:
+ * which = 0 for the multipoles M, 1 for the local expansions L.  The
+ * values are the physical (unscaled) traceless components M_n, L_n with
+ * n_z in {0,1} ((p+1)^2 per cell, ordered by rank, then n_z, then n_x
+ * descending); cells row-major with x fastest (index ix + 2^l (iy + 2^l iz)).
+ * host_out must hold 8^level * (p+1)^2 doubles (cap, in doubles).
+ * Synchronises the stream.  Errors: EINVAL (level outside 2..depth, cap too
+ * small, no evaluate yet), EDEVICE. */
+ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* ctx, int32_t level, int32_t which, double* host_out,
+                                   size_t cap);
+
+/* Turn per-phase HIP-event timing on (1) or off (0; default). */
+ctfmm_status ctfmm_set_timing(ctfmm_ctx* ctx, int32_t on);
+
+/* Accumulated statistics (synchronises the stream when timing is on). */
+ctfmm_status ctfmm_stats(ctfmm_ctx* ctx, ctfmm_stats_t* out);
+ctfmm_status ctfmm_reset_stats(ctfmm_ctx* ctx);
+
+/* Wait for the context stream; reports device-side argument errors (a
+ * non-finite coordinate gives EINVAL) and HIP errors (EDEVICE). */
+ctfmm_status ctfmm_sync(ctfmm_ctx* ctx);
+
+/* Message of the last failure on ctx ("" if none); ctx may be NULL for
+ * failures of ctfmm_create.  Valid until the next call on ctx. */
+const char* ctfmm_last_error(const ctfmm_ctx* ctx);
+
+/* Release the context and every buffer it allocated.  NULL is a no-op. */
+void ctfmm_destroy(ctfmm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTFMM_H */

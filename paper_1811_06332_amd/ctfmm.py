@@ -1,0 +1,197 @@
+"""Python binding of libctfmm (argument marshalling only).
+
+Every function here forwards to the C ABI of ``include/ctfmm.h`` under the
+same name; all arithmetic runs in the library's HIP kernels.  PyTorch
+provides device memory and the stream.  There is no fallback: if the built
+library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libctfmm.so")
+
+CTFMM_OK, CTFMM_EINVAL, CTFMM_ENOMEM, CTFMM_EDEVICE, CTFMM_EUNSUPPORTED = 0, 1, 2, 3, 4
+CTFMM_TREE_UNIFORM = 0
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+CTFMM_P_MAX = 10
+CTFMM_DEPTH_MAX = 9
+
+EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
+            "ctfmm_evaluate", "ctfmm_copy_expansions", "ctfmm_set_timing", "ctfmm_stats",
+            "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
+
+
+class CtfmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ctfmm status {status}: {msg}")
+        self.status = status
+
+
+class ctfmm_params(C.Structure):
+    _fields_ = [("order_p", C.c_int32), ("tree", C.c_int32), ("depth", C.c_int32), ("ws", C.c_int32),
+                ("precision", C.c_int32), ("reserved0", C.c_int32), ("root_lo", C.c_double * 3),
+                ("root_side", C.c_double)]
+
+
+class ctfmm_stats_t(C.Structure):
+    _fields_ = [("ms_total", C.c_double), ("ms_tree", C.c_double), ("ms_p2m", C.c_double),
+                ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
+                ("ms_near", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
+                ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libctfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_1811_06332_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ctfmm_version.restype = C.c_int
+        L.ctfmm_default_params.argtypes = [C.POINTER(ctfmm_params)]
+        L.ctfmm_create.argtypes = [C.POINTER(ctfmm_params), vp, C.POINTER(vp)]
+        L.ctfmm_set_allocator.argtypes = [vp, vp, vp, vp]
+        L.ctfmm_evaluate.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
+        L.ctfmm_set_timing.argtypes = [vp, i32]
+        L.ctfmm_stats.argtypes = [vp, C.POINTER(ctfmm_stats_t)]
+        L.ctfmm_reset_stats.argtypes = [vp]
+        L.ctfmm_sync.argtypes = [vp]
+        L.ctfmm_last_error.argtypes = [vp]
+        L.ctfmm_last_error.restype = C.c_char_p
+        L.ctfmm_destroy.argtypes = [vp]
+        L.ctfmm_destroy.restype = None
+        for name in EXPORTED:
+            if name not in ("ctfmm_version", "ctfmm_last_error", "ctfmm_destroy"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != CTFMM_OK:
+        msg = load().ctfmm_last_error(ctx)
+        raise CtfmmError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- C names
+
+def ctfmm_version() -> int:
+    return load().ctfmm_version()
+
+
+def ctfmm_default_params() -> ctfmm_params:
+    prm = ctfmm_params()
+    _check(load().ctfmm_default_params(C.byref(prm)))
+    return prm
+
+
+def ctfmm_create(prm: ctfmm_params, stream: int | None = None):
+    """Returns the context handle (an int).  `stream` is a hipStream_t as an
+    int (torch.cuda.Stream.cuda_stream); None = torch's current stream."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    h = C.c_void_p()
+    _check(load().ctfmm_create(C.byref(prm), C.c_void_p(stream), C.byref(h)))
+    return h.value
+
+
+def ctfmm_evaluate(ctx, xyz, q, phi=None, grad=None):
+    """xyz: cuda float64 [n,3] contiguous; q: cuda float64 [n]; phi [n] and
+    grad [n,3] cuda float64 outputs (either may be None)."""
+    n = int(q.shape[0])
+    for t, shape in ((xyz, (n, 3)), (q, (n,)), (phi, (n,)), (grad, (n, 3))):
+        if t is None:
+            continue
+        if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError("tensors must be contiguous cuda float64 of shapes [n,3], [n], [n], [n,3]")
+    _check(load().ctfmm_evaluate(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)), C.c_void_p(ctx))
+
+
+def ctfmm_copy_expansions(ctx, level: int, which: int, out) -> None:
+    """out: host numpy float64 array with 8**level * (p+1)**2 elements."""
+    _check(load().ctfmm_copy_expansions(C.c_void_p(ctx), level, which, C.c_void_p(out.ctypes.data), out.size),
+           C.c_void_p(ctx))
+
+
+def ctfmm_set_timing(ctx, on: bool) -> None:
+    _check(load().ctfmm_set_timing(C.c_void_p(ctx), 1 if on else 0), C.c_void_p(ctx))
+
+
+def ctfmm_stats(ctx) -> dict:
+    st = ctfmm_stats_t()
+    _check(load().ctfmm_stats(C.c_void_p(ctx), C.byref(st)), C.c_void_p(ctx))
+    return {name: getattr(st, name) for name, _ in ctfmm_stats_t._fields_}
+
+
+def ctfmm_reset_stats(ctx) -> None:
+    _check(load().ctfmm_reset_stats(C.c_void_p(ctx)), C.c_void_p(ctx))
+
+
+def ctfmm_sync(ctx) -> None:
+    _check(load().ctfmm_sync(C.c_void_p(ctx)), C.c_void_p(ctx))
+
+
+def ctfmm_last_error(ctx=None) -> str:
+    m = load().ctfmm_last_error(None if ctx is None else C.c_void_p(ctx))
+    return m.decode() if m else ""
+
+
+def ctfmm_destroy(ctx) -> None:
+    load().ctfmm_destroy(C.c_void_p(ctx))
+
+
+# ---------------------------------------------------------------- convenience
+
+class FMM:
+    """A context bound to torch's current stream on the current device."""
+
+    def __init__(self, p: int, depth: int, precision: str = "fp64", root_lo=(0.0, 0.0, 0.0),
+                 root_side: float = 1.0, stream: int | None = None):
+        prm = ctfmm_default_params()
+        prm.order_p, prm.depth, prm.precision = p, depth, PRECISIONS[precision]
+        prm.root_lo[0], prm.root_lo[1], prm.root_lo[2] = root_lo
+        prm.root_side = root_side
+        self.p, self.depth = p, depth
+        self.ctx = ctfmm_create(prm, stream)
+
+    def evaluate(self, xyz, q, phi=None, grad=None, sync=False):
+        import torch
+        n = int(q.shape[0])
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float64, device=q.device)
+        if grad is None:
+            grad = torch.empty((n, 3), dtype=torch.float64, device=q.device)
+        ctfmm_evaluate(self.ctx, xyz, q, phi, grad)
+        if sync:
+            ctfmm_sync(self.ctx)
+        return phi, grad
+
+    def expansions(self, level: int, which: str):
+        import numpy as np
+        out = np.zeros((8 ** level, (self.p + 1) ** 2))
+        ctfmm_copy_expansions(self.ctx, level, {"M": 0, "L": 1}[which], out)
+        return out
+
+    def close(self):
+        if self.ctx:
+            ctfmm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

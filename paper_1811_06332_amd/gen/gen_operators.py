@@ -1,0 +1,422 @@
+"""Operator generator for the GPU path (build time only).
+
+Builds the Cartesian traceless FMM operators of Coles & Bieri (arXiv
+1811.06332, Sec. 2 and Appendices A-B) in exact rational arithmetic, reduces
+them to the independent traceless components, and emits HIP source:
+
+  * the independent basis: the (p+1)^2 components with n_z in {0,1} of each
+    traceless polytensor (Appendix B: dependent elements follow from the
+    trace, e.g. A_zz = -A_xx - A_yy);
+  * the expansion of every full component into independent ones;
+  * P2M per particle in the compact form of Eq. (Detracer3):
+    D[u^n]_n = sum_m f_{n,m}/(2n-1)!! |u|^{2m} u^{n-2m}, u = -(x - z)/h;
+  * M2M (Eq. M2M) and L2L (Eq. L2L) for the eight octant shifts of an
+    octree, in scaled variables M~_n = M_n / h^|n|, L~_n = L_n h^(|n|+1);
+    with those scalings the shift is a constant rational matrix per octant;
+  * the M2L contraction (Eq. M2L) reduced to independent components:
+    L~_n = sum_j K_v[n,j] M~_j with K_v[n,j] = sum_i c[n,j,i] D_i(v),
+    D_i the independent components of the traceless gradient at v;
+  * straight-line, common-subexpression-eliminated code for the traceless
+    gradient D_k(r) = (-1)^k r^{-2k-1} T[r^k]_k (Eq. traceless grad with
+    Eq. Detracer3), optimised as the paper's second stage does: constants
+    factored, CSE over all components of the operator together and iterated
+    until it stops improving, powers expanded into products, rationals
+    turned into floating-point literals.
+
+Usage: python gen_operators.py OUTDIR   (writes ctfmm_gen.h)
+"""
+from __future__ import annotations
+
+import os
+import sys
+from fractions import Fraction
+from math import comb, factorial
+
+PMAX = 10
+
+
+# ------------------------------------------------------------------ indices
+
+def ind_list(p=PMAX):
+    """independent components, ordered by rank, then n_z, then n_x descending"""
+    out = []
+    for n in range(p + 1):
+        for a in range(n, -1, -1):
+            out.append((a, n - a, 0))
+        for a in range(n - 1, -1, -1):
+            out.append((a, n - 1 - a, 1))
+    return out
+
+
+def full_list(p=PMAX):
+    out = []
+    for n in range(p + 1):
+        for a in range(n, -1, -1):
+            for b in range(n - a, -1, -1):
+                out.append((a, b, n - a - b))
+    return out
+
+
+IND = ind_list()
+FULL = full_list()
+IND_POS = {m: i for i, m in enumerate(IND)}
+FULL_POS = {m: i for i, m in enumerate(FULL)}
+
+
+def rank(m):
+    return m[0] + m[1] + m[2]
+
+
+def mfact(m):
+    return factorial(m[0]) * factorial(m[1]) * factorial(m[2])
+
+
+def dfact(n):
+    f = 1
+    for i in range(n, 1, -2):
+        f *= i
+    return f
+
+
+def expand(m):
+    """full component m of a traceless tensor as {independent slot: int coef}.
+    With c = 2s + t: A_{a,b,c} = (-1)^s sum_i C(s,i) A_{a+2i, b+2(s-i), t}."""
+    a, b, c = m
+    s, t = divmod(c, 2)
+    out = {}
+    for i in range(s + 1):
+        key = IND_POS[(a + 2 * i, b + 2 * (s - i), t)]
+        out[key] = out.get(key, 0) + (-1) ** s * comb(s, i)
+    return out
+
+
+def f_nm(n, m):
+    """f_{n,m} = (-1)^|m| (2|n|-2|m|-1)!! n! / (2^|m| m! (n-2m)!)  (Appendix A)"""
+    N, M = rank(n), rank(m)
+    return Fraction((-1) ** M * dfact(2 * N - 2 * M - 1) * mfact(n),
+                    2 ** M * mfact(m) * mfact((n[0] - 2 * m[0], n[1] - 2 * m[1], n[2] - 2 * m[2])))
+
+
+def detracer_rows():
+    """D[A]_n for independent n as {full slot: Fraction} (Eq. Detracer / (2n-1)!!)."""
+    rows = []
+    for n in IND:
+        N = rank(n)
+        row = {}
+        for m1 in range(n[0] // 2 + 1):
+            for m2 in range(n[1] // 2 + 1):
+                for m3 in range(n[2] // 2 + 1):
+                    m = (m1, m2, m3)
+                    M = rank(m)
+                    fv = f_nm(n, m)
+                    for k1 in range(M + 1):
+                        for k2 in range(M - k1 + 1):
+                            k = (k1, k2, M - k1 - k2)
+                            idx = (n[0] - 2 * m1 + 2 * k[0], n[1] - 2 * m2 + 2 * k[1], n[2] - 2 * m3 + 2 * k[2])
+                            w = fv * Fraction(factorial(M), mfact(k)) / dfact(2 * N - 1)
+                            key = FULL_POS[idx]
+                            row[key] = row.get(key, 0) + w
+        rows.append({k: v for k, v in row.items() if v != 0})
+    return rows
+
+
+def p2m_terms():
+    """per independent n: [(coef, ex, ey, ez, e_r2)] with
+    D[u^n]_n = sum coef * ux^ex uy^ey uz^ez |u|^(2 e_r2)  (Eq. Detracer3)."""
+    out = []
+    for n in IND:
+        N = rank(n)
+        terms = []
+        for m1 in range(n[0] // 2 + 1):
+            for m2 in range(n[1] // 2 + 1):
+                for m3 in range(n[2] // 2 + 1):
+                    m = (m1, m2, m3)
+                    c = f_nm(n, m) / dfact(2 * N - 1)
+                    terms.append((c, n[0] - 2 * m1, n[1] - 2 * m2, n[2] - 2 * m3, rank(m)))
+        out.append(terms)
+    return out
+
+
+def m2m_matrix(octant):
+    """A_o[n][j]: parent M~_n = sum_o sum_j A_o[n][j] child_o M~_j.
+    Child centre minus parent centre = (sigma/4) h_parent, sigma_d = 2 o_d - 1.
+    M'_n/h_P^|n| = sum_{k<=n} C(n,k) (-sigma/4)^(n-k) 2^-|k| M~_k (full k),
+    then the detracer (Eq. M2M, M2M part 2)."""
+    sig = [2 * ((octant >> d) & 1) - 1 for d in range(3)]
+    D = DET
+    # shift: full n <- full k
+    A = [dict() for _ in IND]
+    for ni, n in enumerate(IND):
+        for f, w in D[ni].items():
+            nn = FULL[f]  # component of M' needed by the detracer
+            for k1 in range(nn[0] + 1):
+                for k2 in range(nn[1] + 1):
+                    for k3 in range(nn[2] + 1):
+                        k = (k1, k2, k3)
+                        coef = Fraction(comb(nn[0], k1) * comb(nn[1], k2) * comb(nn[2], k3))
+                        for d in range(3):
+                            coef *= Fraction(-sig[d], 4) ** (nn[d] - k[d])
+                        coef *= Fraction(1, 2 ** rank(k))
+                        for j, e in expand(k).items():
+                            A[ni][j] = A[ni].get(j, 0) + w * coef * e
+    return [{j: v for j, v in row.items() if v != 0} for row in A]
+
+
+def l2l_matrix(octant):
+    """B_o[n][j]: child L~_n = sum_j B_o[n][j] parent L~_j (only rank(j) <= p
+    is kept at order p).  delta = (sigma/4) h_P:
+    L~c_n = 2^-(|n|+1) sum_k (sigma/4)^k / k! L~P_{n+k}  (Eq. L2L)."""
+    sig = [2 * ((octant >> d) & 1) - 1 for d in range(3)]
+    B = []
+    for n in IND:
+        row = {}
+        N = rank(n)
+        for K in range(PMAX - N + 1):
+            for k1 in range(K + 1):
+                for k2 in range(K - k1 + 1):
+                    k = (k1, k2, K - k1 - k2)
+                    coef = Fraction(1, mfact(k) * 2 ** (N + 1))
+                    for d in range(3):
+                        coef *= Fraction(sig[d], 4) ** k[d]
+                    for j, e in expand((n[0] + k[0], n[1] + k[1], n[2] + k[2])).items():
+                        row[j] = row.get(j, 0) + coef * e
+        B.append({j: v for j, v in row.items() if v != 0})
+    return B
+
+
+def m2l_contraction():
+    """c[(n, j)] = {i: coef} with K_v[n][j] = sum_i coef * D_i(v):
+    sum over full m with |m| = |j| of E[m][j] E[n+m][i] / m!  (Eq. M2L)."""
+    out = {}
+    for ni, n in enumerate(IND):
+        for ji, jm in enumerate(IND):
+            if rank(n) + rank(jm) > PMAX:
+                continue
+            J = rank(jm)
+            acc = {}
+            for m1 in range(J + 1):
+                for m2 in range(J - m1 + 1):
+                    m = (m1, m2, J - m1 - m2)
+                    e = expand(m).get(ji, 0)
+                    if e == 0:
+                        continue
+                    for i, e2 in expand((n[0] + m[0], n[1] + m[1], n[2] + m[2])).items():
+                        acc[i] = acc.get(i, 0) + Fraction(e * e2, mfact(m))
+            acc = {i: v for i, v in acc.items() if v != 0}
+            out[(ni, ji)] = acc
+    return out
+
+
+DET = None
+
+
+# ---------------------------------------------------------- straight-line D
+
+def dtensor_code(p):
+    """CSE'd straight-line FP64 code for the independent components of the
+    traceless gradient of 1/r up to rank p.  Returns (code lines, flops opt,
+    flops noopt)."""
+    import sympy as sp
+    x, y, z, u = sp.symbols("x y z u", real=True)  # u = 1/|r|
+    h = x * x + y * y + z * z
+    exprs = []
+    for n in IND:
+        N = rank(n)
+        if N > p:
+            break
+        t = 0
+        for m1 in range(n[0] // 2 + 1):
+            for m2 in range(n[1] // 2 + 1):
+                for m3 in range(n[2] // 2 + 1):
+                    m = (m1, m2, m3)
+                    fv = f_nm(n, m)
+                    t += sp.Rational(fv.numerator, fv.denominator) * h ** rank(m) * \
+                        x ** (n[0] - 2 * m1) * y ** (n[1] - 2 * m2) * z ** (n[2] - 2 * m3)
+        exprs.append(sp.expand((-1) ** N * u ** (2 * N + 1) * t))
+    noopt = sum(_count_ops(e) for e in exprs)
+    # stage 2: CSE over all components together, iterated until no gain
+    repl, red = sp.cse(exprs, symbols=sp.numbered_symbols("t"), optimizations="basic")
+    best = _count_ops_cse(repl, red)
+    for _ in range(6):
+        allx = [e for _, e in repl] + list(red)
+        repl2, red2 = sp.cse(allx, symbols=sp.numbered_symbols("s"), optimizations="basic")
+        if not repl2:
+            break
+        # substitute back into a flat assignment list
+        nrep = len(repl)
+        tmp = [(s, v) for s, v in repl2]
+        new_repl = tmp + [(repl[i][0], red2[i]) for i in range(nrep)]
+        new_red = red2[nrep:]
+        cost = _count_ops_cse(new_repl, new_red)
+        if cost >= best:
+            break
+        repl, red, best = _toposort(new_repl), new_red, cost
+    lines = []
+    for s, v in repl:
+        lines.append(f"const double {s} = {_c(v)};")
+    for i, e in enumerate(red):
+        lines.append(f"D[{i}] = {_c(e)};")
+    return lines, best, noopt
+
+
+def _toposort(assigns):
+    """order (symbol, expr) assignments so every symbol is defined before use"""
+    defined = {sym for sym, _ in assigns}
+    deps = {sym: {f for f in expr.free_symbols if f in defined} for sym, expr in assigns}
+    expr_of = dict(assigns)
+    out, done = [], set()
+
+    def visit(sym):
+        stack = [(sym, iter(sorted(deps[sym], key=str)))]
+        while stack:
+            cur, it = stack[-1]
+            nxt = next((d for d in it if d not in done), None)
+            if nxt is None:
+                stack.pop()
+                if cur not in done:
+                    done.add(cur)
+                    out.append((cur, expr_of[cur]))
+            else:
+                stack.append((nxt, iter(sorted(deps[nxt], key=str))))
+    for sym, _ in assigns:
+        if sym not in done:
+            visit(sym)
+    return out
+
+
+def _count_ops(e):
+    import sympy as sp
+    return int(sp.count_ops(e, visual=False))
+
+
+def _count_ops_cse(repl, red):
+    return sum(_count_ops(v) for _, v in repl) + sum(_count_ops(e) for e in red)
+
+
+def _c(e):
+    """C expression: powers expanded into products, rationals as FP64 literals."""
+    import sympy as sp
+
+    def rec(e):
+        if e.is_Symbol:
+            return str(e)
+        if e.is_Integer:
+            return f"{float(int(e))!r}"
+        if e.is_Rational:
+            return f"({float(e)!r})"
+        if e.is_Add:
+            return "(" + " + ".join(rec(a) for a in e.args) + ")"
+        if e.is_Mul:
+            return "(" + " * ".join(rec(a) for a in e.args) + ")"
+        if e.is_Pow:
+            b, ex = e.args
+            if ex.is_Integer and int(ex) > 0:
+                s = rec(b)
+                return "(" + " * ".join([s] * int(ex)) + ")"
+            if ex.is_Integer and int(ex) < 0:
+                s = rec(b)
+                return "(1.0 / (" + " * ".join([s] * (-int(ex))) + "))"
+        raise ValueError(f"unexpected term {e!r}")
+    return rec(sp.sympify(e))
+
+
+# ------------------------------------------------------------------ emit
+
+def _hexf(v):
+    return float(v).hex() if v != 0 else "0.0"
+
+
+def emit(outdir):
+    global DET
+    DET = detracer_rows()
+    os.makedirs(outdir, exist_ok=True)
+    L = []
+    w = L.append
+    w("// Generated by paper_1811_06332_amd/gen/gen_operators.py -- do not edit.")
+    w("// Cartesian traceless FMM operators (Coles & Bieri, arXiv 1811.06332),")
+    w("// reduced to the independent traceless components in exact rational")
+    w("// arithmetic; rationals are rounded once to FP64.")
+    w("#pragma once")
+    w(f"#define GEN_PMAX {PMAX}")
+    w(f"#define GEN_NIND {len(IND)}")
+    w(f"#define GEN_NFULL {len(FULL)}")
+    w("")
+    w("// independent slot -> (nx, ny, nz); ordered by rank, then nz, then nx descending")
+    w("static const signed char GEN_IND[GEN_NIND][3] = {" + ",".join("{%d,%d,%d}" % m for m in IND) + "};")
+    w("// full slot -> (nx, ny, nz); ordered by rank, nx descending, ny descending")
+    w("static const signed char GEN_FULL[GEN_NFULL][3] = {" + ",".join("{%d,%d,%d}" % m for m in FULL) + "};")
+    # expansion table
+    starts, slots, coefs = [0], [], []
+    for m in FULL:
+        e = expand(m)
+        for j in sorted(e):
+            slots.append(j); coefs.append(e[j])
+        starts.append(len(slots))
+    w("// full component f of a traceless polytensor = sum_{t in [EXP_START[f], EXP_START[f+1])} EXP_COEF[t] * ind[EXP_SLOT[t]]")
+    w(f"static const short GEN_EXP_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
+    w(f"static const unsigned char GEN_EXP_SLOT[{len(slots)}] = {{" + ",".join(map(str, slots)) + "};")
+    w(f"static const int GEN_EXP_COEF[{len(coefs)}] = {{" + ",".join(map(str, coefs)) + "};")
+    # P2M terms
+    pt = p2m_terms()
+    starts, cs, ex = [0], [], []
+    for terms in pt:
+        for (c, a, b, d, e2) in terms:
+            cs.append(_hexf(c)); ex.append("{%d,%d,%d,%d}" % (a, b, d, e2))
+        starts.append(len(cs))
+    w("// P2M: M~_n += q * sum_t P2M_COEF[t] * ux^e0 uy^e1 uz^e2 (|u|^2)^e3, u = (z - x)/h  (Eq. Detracer3)")
+    w(f"static const short GEN_P2M_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
+    w(f"static const double GEN_P2M_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
+    w(f"static const signed char GEN_P2M_EXP[{len(ex)}][4] = {{" + ",".join(ex) + "};")
+    # M2M / L2L octant matrices, dense [8][NIND][NIND]
+    for name, fn, doc in (("M2M", m2m_matrix, "parent M~_n += sum_j GEN_M2M[o][n][j] * child_o M~_j (exact: rank(j) <= rank(n))"),
+                          ("L2L", l2l_matrix, "child_o L~_n += sum_j GEN_L2L[o][n][j] * parent L~_j (order p keeps rank(j) <= p)")):
+        w(f"// {doc}")
+        rows = []
+        for o in range(8):
+            Mx = fn(o)
+            for n in range(len(IND)):
+                rows.append(",".join(_hexf(Mx[n].get(j, 0)) for j in range(len(IND))))
+        w(f"static const double GEN_{name}[8][GEN_NIND][GEN_NIND] = {{" + ",\n".join(rows) + "};")
+    # M2L contraction
+    c = m2l_contraction()
+    keys = sorted(c)
+    starts, ii, cc = [], [], []
+    w("// M2L: K_v[n][j] = sum_{t in [C_START[n][j], C_START[n][j]+C_COUNT[n][j])} C_COEF[t] * D_{C_SLOT[t]}(v)  (Eq. M2L)")
+    cstart = [[0] * len(IND) for _ in IND]
+    ccount = [[0] * len(IND) for _ in IND]
+    for (n, j) in keys:
+        cstart[n][j] = len(ii); ccount[n][j] = len(c[(n, j)])
+        for i in sorted(c[(n, j)]):
+            ii.append(i); cc.append(_hexf(c[(n, j)][i]))
+    w("static const int GEN_C_START[GEN_NIND][GEN_NIND] = {" + ",".join("{" + ",".join(map(str, r)) + "}" for r in cstart) + "};")
+    w("static const unsigned char GEN_C_COUNT[GEN_NIND][GEN_NIND] = {" + ",".join("{" + ",".join(map(str, r)) + "}" for r in ccount) + "};")
+    w(f"static const unsigned char GEN_C_SLOT[{len(ii)}] = {{" + ",".join(map(str, ii)) + "};")
+    w(f"static const double GEN_C_COEF[{len(cc)}] = {{" + ",".join(cc) + "};")
+    # inverse factorials of full components (L2P)
+    w("// 1/n! for full slots (L2P weights)")
+    w("static const double GEN_INV_MFACT[GEN_NFULL] = {" + ",".join(_hexf(Fraction(1, mfact(m))) for m in FULL) + "};")
+    # straight-line D code per p
+    stats = []
+    for p in range(PMAX + 1):
+        lines, opt, noopt = dtensor_code(p)
+        stats.append((p, opt, noopt))
+        w(f"// traceless gradient of 1/r, independent components of ranks <= {p}; "
+          f"{opt} operations after CSE ({noopt} before)")
+        w(f"__host__ __device__ static inline void gen_dtensor_p{p}(double x, double y, double z, double* __restrict__ D) {{")
+        w("  const double u = 1.0 / sqrt(x * x + y * y + z * z);")
+        for ln in lines:
+            w("  " + ln)
+        w("}")
+    w("template <int P> __host__ __device__ inline void gen_dtensor(double x, double y, double z, double* D);")
+    for p in range(PMAX + 1):
+        w(f"template <> __host__ __device__ inline void gen_dtensor<{p}>(double x, double y, double z, double* D) {{ gen_dtensor_p{p}(x, y, z, D); }}")
+    with open(os.path.join(outdir, "ctfmm_gen.h"), "w") as fh:
+        fh.write("\n".join(L) + "\n")
+    with open(os.path.join(outdir, "dtensor_opcounts.txt"), "w") as fh:
+        fh.write("# p  ops_after_cse  ops_before (sympy count_ops; +,-,*,/ and sqrt count 1)\n")
+        for p, o, n in stats:
+            fh.write(f"{p} {o} {n}\n")
+
+
+if __name__ == "__main__":
+    emit(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "csrc", "generated"))

@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every symbol include/ctfmm.h declares;
+argument checks that return before any device call (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1811_06332_amd import ctfmm as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ctfmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctfmm_[a-z_]+)\s*\(", src)) - {"ctfmm_alloc_fn", "ctfmm_free_fn"})
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.load()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(F.EXPORTED)
+
+
+def test_version_and_defaults():
+    assert F.ctfmm_version() == 1
+    prm = F.ctfmm_default_params()
+    assert (prm.order_p, prm.depth, prm.ws, prm.precision, prm.root_side) == (4, 3, 1, 0, 1.0)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("order_p", 11, F.CTFMM_EINVAL), ("order_p", -1, F.CTFMM_EINVAL), ("depth", 10, F.CTFMM_EINVAL),
+    ("ws", 2, F.CTFMM_EINVAL), ("root_side", 0.0, F.CTFMM_EINVAL), ("root_side", float("nan"), F.CTFMM_EINVAL),
+    ("tree", 7, F.CTFMM_EUNSUPPORTED),
+])
+def test_create_rejects_bad_params(field, value, status):
+    lib = F.load()
+    prm = F.ctfmm_default_params()
+    setattr(prm, field, value)
+    h = C.c_void_p()
+    assert lib.ctfmm_create(C.byref(prm), None, C.byref(h)) == status
+    assert h.value is None
+    assert F.ctfmm_last_error()
+
+
+def test_null_arguments():
+    lib = F.load()
+    assert lib.ctfmm_create(None, None, None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_evaluate(None, 1, None, None, None, None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_sync(None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_default_params(None) == F.CTFMM_EINVAL
+    lib.ctfmm_destroy(None)
