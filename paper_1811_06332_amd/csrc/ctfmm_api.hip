@@ -4,6 +4,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -35,6 +36,8 @@ struct ctfmm_ctx {
     DevTables T{};
     double* Dv = nullptr;  // [NOFF][NIND] derivative tensors of the offsets
     double* Kt = nullptr;  // [NOFF][nc][nc] K_v transposed
+    double* Kpk = nullptr;       // K_v as FP64 MFMA fragments
+    int16_t* offlist = nullptr;  // [8][189] offset slots of each target octant
 
     // workspace, grown on demand
     int64_t cap_n = -1;
@@ -43,6 +46,7 @@ struct ctfmm_ctx {
     int32_t* idx = nullptr;
     int32_t* idx_sorted = nullptr;
     double4* P = nullptr;
+    double4* F = nullptr;  // far field per sorted particle (phi, grad)
     int32_t* start = nullptr;
     void* sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
@@ -163,6 +167,31 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     HIPCHK(c, hipGetLastError());
     launch_build_k(c->stream, p, c->Dv, c->T, c->Kt);
     HIPCHK(c, hipGetLastError());
+    // FP64 MFMA fragments of every K_v
+    int max_lds = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    if (m2l64_lds(p) > (size_t)max_lds)
+        return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
+    c->Kpk = (double*)dev_alloc(c, m2l64_packed_doubles(p) * sizeof(double));
+    if (!c->Kpk) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+    launch_pack_k64(c->stream, p, c->Kt, c->Kpk);
+    HIPCHK(c, hipGetLastError());
+    // offsets v of the ws=1 list for a target in octant o: v_d in [-2-o_d, 3-o_d], max|v_d| >= 2
+    std::vector<int16_t> off(8 * 189);
+    for (int o = 0; o < 8; ++o) {
+        int k = 0;
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+        for (int vz = -2 - oz; vz <= 3 - oz; ++vz)
+            for (int vy = -2 - oy; vy <= 3 - oy; ++vy)
+                for (int vx = -2 - ox; vx <= 3 - ox; ++vx) {
+                    if (std::abs(vx) <= 1 && std::abs(vy) <= 1 && std::abs(vz) <= 1) continue;
+                    off[o * 189 + k++] = (int16_t)((vx + 3) + 7 * (vy + 3) + 49 * (vz + 3));
+                }
+        if (k != 189) return fail(c, CTFMM_EDEVICE, "offset list construction");
+    }
+    c->offlist = (int16_t*)dev_alloc(c, off.size() * sizeof(int16_t));
+    if (!c->offlist) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+    HIPCHK(c, hipMemcpyAsync(c->offlist, off.data(), off.size() * sizeof(int16_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CTFMM_OK;
 }
@@ -171,7 +200,8 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     if (n <= c->cap_n) return CTFMM_OK;
     // release the previous particle workspace (tables and operators are kept)
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<void*> keep = {c->tab_blob, (void*)c->Dv, (void*)c->Kt, (void*)c->err_flag};
+    std::vector<void*> keep = {c->tab_blob, (void*)c->Dv, (void*)c->Kt, (void*)c->Kpk, (void*)c->offlist,
+                               (void*)c->err_flag};
     std::vector<void*> rest;
     for (void* p : c->owned) {
         bool k = false;
@@ -195,6 +225,7 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     c->idx = (int32_t*)dev_alloc(c, nn * 4);
     c->idx_sorted = (int32_t*)dev_alloc(c, nn * 4);
     c->P = (double4*)dev_alloc(c, nn * sizeof(double4));
+    c->F = (double4*)dev_alloc(c, nn * sizeof(double4));
     c->start = (int32_t*)dev_alloc(c, (nleaves + 1) * 4);
     size_t cells = 0;
     for (int l = 0; l <= d; ++l) {
@@ -208,7 +239,7 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, c->sort_tmp_bytes, c->keys, c->keys_sorted, c->idx,
                                              c->idx_sorted, (int)nn, 0, d > 0 ? 3 * d : 1, c->stream);
     c->sort_tmp = dev_alloc(c, c->sort_tmp_bytes);
-    if (!c->keys || !c->keys_sorted || !c->idx || !c->idx_sorted || !c->P || !c->start || !c->M || !c->L ||
+    if (!c->keys || !c->keys_sorted || !c->idx || !c->idx_sorted || !c->P || !c->F || !c->start || !c->M || !c->L ||
         !c->sort_tmp)
         return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
     c->cap_n = n;
@@ -367,19 +398,20 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
         rec(c, 3);
         for (int l = 2; l <= d; ++l) {
             rec(c, evi);
-            launch_m2l_fp64(st, p, l, Ml(l), Ll(l), c->Kt);
+            HIPCHK(c, launch_m2l_mfma64(st, p, l, Ml(l), Ll(l), c->Kpk, c->offlist));
             rec(c, evi + 1);
             if (l >= 3) launch_l2l(st, p, l - 1, Ll(l - 1), Ll(l), c->T);
             rec(c, evi + 2);
             evi += 3;
         }
         rec(c, 4);
-        launch_l2p_p2p(st, p, box, c->start, c->P, c->idx_sorted, Ll(d), c->T, phi, grad);
+        launch_l2p(st, p, box, c->start, c->P, Ll(d), c->T, c->F);
+        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, c->F, phi, grad);
     } else {
         rec(c, 2);
         rec(c, 3);
         rec(c, 4);
-        launch_p2p_only(st, box, c->start, c->P, c->idx_sorted, phi, grad);
+        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, nullptr, phi, grad);
     }
     HIPCHK(c, hipGetLastError());
     const int ev_end = NPHASE_EV - 1;

@@ -69,10 +69,10 @@ void launch_offset_dtensors(hipStream_t s, int p, double* Dv);
 void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, double* Kt);
 void launch_m2l_fp64(hipStream_t s, int p, int level, const double* M, double* L, const double* Kt);
 void launch_l2l(hipStream_t s, int p, int parent_level, const double* Lparent, double* Lchild, const DevTables& T);
-void launch_l2p_p2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const int32_t* idx,
-                    const double* L, const DevTables& T, double* phi, double* grad);
-void launch_p2p_only(hipStream_t s, Box box, const int32_t* start, const double4* P, const int32_t* idx,
-                     double* phi, double* grad);
+void launch_l2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const double* L,
+                const DevTables& T, double4* F);
+void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32_t* start, const double4* P,
+                const int32_t* idx, const double4* F, double* phi, double* grad);
 size_t m2l64_packed_doubles(int p);
 size_t m2l64_lds(int p);
 void launch_pack_k64(hipStream_t s, int p, const double* Kt, double* Kpk);

@@ -293,109 +293,122 @@ __device__ inline void pair_add(double xb, double yb, double zb, double4 src, do
     gz -= ir3 * dz;
 }
 
-// One workgroup per leaf.  FAR: the leaf's local expansion is expanded to
-// full components (divided by n!) in LDS and evaluated at each particle
-// (Eq. L2P: the rank-0 and rank-1 components of L shifted to x_b).  The
-// near field sums the particles of the 27 adjacent-or-equal leaves.
-template <int P, bool FAR>
-__global__ __launch_bounds__(64) void k_near_far(Box box, const int32_t* __restrict__ start,
-                                                 const double4* __restrict__ Pt, const int32_t* __restrict__ idx,
-                                                 const double* __restrict__ L, DevTables T, double* __restrict__ phi,
-                                                 double* __restrict__ grad) {
+// L2P (Eq. L2P): one workgroup per leaf.  The leaf's local expansion is
+// expanded to full components divided by n! in LDS, together with the
+// coefficient arrays of its three first derivatives; each particle then
+// evaluates the four degree-p polynomials at r = (x - z)/h by nested Horner
+// steps in x, y and z.  Results (far field, sorted order) go to F[s].
+template <int P>
+__global__ __launch_bounds__(64) void k_l2p(Box box, const int32_t* __restrict__ start, const double4* __restrict__ Pt,
+                                            const double* __restrict__ L, DevTables T, double4* __restrict__ F) {
     constexpr int NC = (P + 1) * (P + 1);
     constexpr int NF = (P + 1) * (P + 2) * (P + 3) / 6;
     const uint32_t c = blockIdx.x;
-    const int d = box.depth;
-    const int n1 = 1 << d;
-    const double h = box.side / (double)n1;
-    const int ix = compact3(c), iy = compact3(c >> 1), iz = compact3(c >> 2);
-    const double zx = box.lo[0] + ((double)ix + 0.5) * h;
-    const double zy = box.lo[1] + ((double)iy + 0.5) * h;
-    const double zz = box.lo[2] + ((double)iz + 0.5) * h;
-    __shared__ double Lw[FAR ? NF : 1];
     const int b0 = start[c], e0 = start[c + 1];
     if (b0 == e0) return;  // uniform across the workgroup
-    if (FAR) {
-        const double* Lc = L + (size_t)c * NC;
-        for (int f = threadIdx.x; f < NF; f += 64) {
-            double v = 0.0;
-            for (int t = T.exp_start[f]; t < T.exp_start[f + 1]; ++t) v += (double)T.exp_coef[t] * Lc[T.exp_slot[t]];
-            Lw[f] = v * T.inv_mfact[f];
-        }
-        __syncthreads();
+    const int d = box.depth;
+    const double h = box.side / (double)(1 << d);
+    const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
+    const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
+    const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
+    __shared__ double W[4][NF];  // potential, d/dx, d/dy, d/dz coefficients
+    const double* Lc = L + (size_t)c * NC;
+    for (int f = threadIdx.x; f < NF; f += 64) {
+        double v = 0.0;
+        for (int t = T.exp_start[f]; t < T.exp_start[f + 1]; ++t) v += (double)T.exp_coef[t] * Lc[T.exp_slot[t]];
+        W[0][f] = v * T.inv_mfact[f];
     }
+    __syncthreads();
+    for (int f = threadIdx.x; f < NF; f += 64) {
+        const int a = T.full[3 * f], b = T.full[3 * f + 1], cc = T.full[3 * f + 2];
+        const bool inner = a + b + cc < P;
+        W[1][f] = inner ? (double)(a + 1) * W[0][full_slot(a + 1, b, cc)] : 0.0;
+        W[2][f] = inner ? (double)(b + 1) * W[0][full_slot(a, b + 1, cc)] : 0.0;
+        W[3][f] = inner ? (double)(cc + 1) * W[0][full_slot(a, b, cc + 1)] : 0.0;
+    }
+    __syncthreads();
     for (int s = b0 + threadIdx.x; s < e0; s += 64) {
         const double4 pt = Pt[s];
-        double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-        if (FAR) {
-            const double rx = (pt.x - zx) / h, ry = (pt.y - zy) / h, rz = (pt.z - zz) / h;
-            double px[P + 1], py[P + 1], pz[P + 1];
-            px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-            for (int k = 1; k <= P; ++k) {
-                px[k] = px[k - 1] * rx;
-                py[k] = py[k - 1] * ry;
-                pz[k] = pz[k - 1] * rz;
-            }
-#pragma unroll
-            for (int n = 0; n <= P; ++n) {
-#pragma unroll
-                for (int a = n; a >= 0; --a) {
-#pragma unroll
-                    for (int b = n - a; b >= 0; --b) {
-                        const int cc = n - a - b;
-                        const double m = px[a] * py[b] * pz[cc];
-                        f += m * Lw[full_slot(a, b, cc)];
-                        if (n < P) {
-                            gx += m * (double)(a + 1) * Lw[full_slot(a + 1, b, cc)];
-                            gy += m * (double)(b + 1) * Lw[full_slot(a, b + 1, cc)];
-                            gz += m * (double)(cc + 1) * Lw[full_slot(a, b, cc + 1)];
-                        }
-                    }
+        const double rx = (pt.x - zx) / h, ry = (pt.y - zy) / h, rz = (pt.z - zz) / h;
+        double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
+        for (int cz = P; cz >= 0; --cz) {
+            double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
+            for (int by = P - cz; by >= 0; --by) {
+                double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+                for (int ax = P - by - cz; ax >= 0; --ax) {
+                    const int sl = full_slot(ax, by, cz);
+                    x0 = x0 * rx + W[0][sl];
+                    x1 = x1 * rx + W[1][sl];
+                    x2 = x2 * rx + W[2][sl];
+                    x3 = x3 * rx + W[3][sl];
                 }
+                y0 = y0 * ry + x0;
+                y1 = y1 * ry + x1;
+                y2 = y2 * ry + x2;
+                y3 = y3 * ry + x3;
             }
-            f /= h;
-            const double ih2 = 1.0 / (h * h);
-            gx *= ih2;
-            gy *= ih2;
-            gz *= ih2;
+            f0 = f0 * rz + y0;
+            f1 = f1 * rz + y1;
+            f2 = f2 * rz + y2;
+            f3 = f3 * rz + y3;
         }
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int cz = iz + dz;
-            if (cz < 0 || cz >= n1) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int cy = iy + dy;
-                if (cy < 0 || cy >= n1) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int cx = ix + dx;
-                    if (cx < 0 || cx >= n1) continue;
-                    const uint32_t cn = morton3(cx, cy, cz);
-                    const int sb = start[cn], se = start[cn + 1];
-                    for (int s2 = sb; s2 < se; ++s2) {
-                        if (s2 == s) continue;
-                        pair_add(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
-                    }
-                }
-            }
-        }
-        const size_t o = (size_t)idx[s];
-        if (phi) phi[o] = f;
-        if (grad) {
-            grad[3 * o] = gx;
-            grad[3 * o + 1] = gy;
-            grad[3 * o + 2] = gz;
-        }
+        const double ih2 = 1.0 / (h * h);
+        F[s] = make_double4(f0 / h, f1 * ih2, f2 * ih2, f3 * ih2);
     }
 }
 
-void launch_l2p_p2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const int32_t* idx,
-                    const double* L, const DevTables& T, double* phi, double* grad) {
+// P2P: one thread per (sorted) target particle; sources are the particles
+// of the 27 adjacent-or-equal leaves (Appendix C near field), self excluded.
+// Adds the far field F[s] (if given) and writes the outputs in input order.
+__global__ __launch_bounds__(256) void k_p2p(int n, Box box, const uint32_t* __restrict__ keys,
+                                             const int32_t* __restrict__ start, const double4* __restrict__ Pt,
+                                             const int32_t* __restrict__ idx, const double4* __restrict__ F,
+                                             double* __restrict__ phi, double* __restrict__ grad) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int n1 = 1 << box.depth;
+    const uint32_t key = keys[s];
+    const int ix = compact3(key), iy = compact3(key >> 1), iz = compact3(key >> 2);
+    const double4 pt = Pt[s];
+    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    if (F) {
+        const double4 fv = F[s];
+        f = fv.x; gx = fv.y; gy = fv.z; gz = fv.w;
+    }
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int cz = iz + dz;
+        if (cz < 0 || cz >= n1) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int cy = iy + dy;
+            if (cy < 0 || cy >= n1) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cx = ix + dx;
+                if (cx < 0 || cx >= n1) continue;
+                const uint32_t cn = morton3(cx, cy, cz);
+                const int sb = start[cn], se = start[cn + 1];
+                for (int s2 = sb; s2 < se; ++s2) {
+                    if (s2 == s) continue;
+                    pair_add(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
+                }
+            }
+        }
+    }
+    const size_t o = (size_t)idx[s];
+    if (phi) phi[o] = f;
+    if (grad) {
+        grad[3 * o] = gx;
+        grad[3 * o + 1] = gy;
+        grad[3 * o + 2] = gz;
+    }
+}
+
+void launch_l2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const double* L,
+                const DevTables& T, double4* F) {
     const long long nleaves = 1ll << (3 * box.depth);
     switch (p) {
-#define CASE(PP)                                                                                                  \
-    case PP:                                                                                                      \
-        hipLaunchKernelGGL((k_near_far<PP, true>), dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, idx, L, \
-                           T, phi, grad);                                                                         \
+#define CASE(PP)                                                                                              \
+    case PP:                                                                                                  \
+        hipLaunchKernelGGL(k_l2p<PP>, dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, L, T, F); \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
@@ -403,12 +416,10 @@ void launch_l2p_p2p(hipStream_t s, int p, Box box, const int32_t* start, const d
     }
 }
 
-void launch_p2p_only(hipStream_t s, Box box, const int32_t* start, const double4* P, const int32_t* idx, double* phi,
-                     double* grad) {
-    const long long nleaves = 1ll << (3 * box.depth);
-    DevTables T{};
-    hipLaunchKernelGGL((k_near_far<0, false>), dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, idx, nullptr,
-                       T, phi, grad);
+void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32_t* start, const double4* P,
+                const int32_t* idx, const double4* F, double* phi, double* grad) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_p2p, dim3(cdiv(n, 256)), dim3(256), 0, s, n, box, keys, start, P, idx, F, phi, grad);
 }
 
 // ------------------------------------------------------------------ debug copy-out
@@ -447,6 +458,8 @@ void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side
 // Per offset, K_v (only its non-zero 16x4 blocks: rows of rank a need
 // columns of rank <= p - a) and the 64 source multipoles are staged in LDS
 // in MFMA fragment order; wave w owns targets 16w..16w+15 and all row tiles.
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -517,9 +530,9 @@ __global__ __launch_bounds__(256) void k_m2l_mfma64(int level, const double* __r
         tgtrow[tid] = par < nparents ? (int)(par * 8 + o) : -1;
     }
 
-    double4 acc[R][2];
+    v4d acc[R][2];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4d{0.0, 0.0, 0.0, 0.0};
 
     for (int iv = 0; iv < 189; ++iv) {
         const int vs = offlist[o * 189 + iv];
@@ -535,7 +548,8 @@ __global__ __launch_bounds__(256) void k_m2l_mfma64(int level, const double* __r
             }
             srcrow[tid] = row;
         }
-        const double* Kv = Kpk + (size_t)vs * NCH * 64;
+        // v is source - target; the operator is built for r = target - source = -v
+        const double* Kv = Kpk + (size_t)(NOFF - 1 - vs) * NCH * 64;
         for (int i = tid; i < NCH * 64; i += 256) Ks[i] = Kv[i];
         __syncthreads();
         for (int e = tid; e < 4 * NB * 64; e += 256) {
@@ -560,19 +574,18 @@ __global__ __launch_bounds__(256) void k_m2l_mfma64(int level, const double* __r
             }
         }
     }
-    // lane holds rows 16r + 4*(lane/16) + j (j = 0..3) of target lane%16 of this wave
+    // FP64 16x16 accumulator: element j of lane holds row 16r + lane/16 + 4j of target lane%16
     const int t = tgtrow[w * 16 + (lane & 15)];
     if (t >= 0) {
         double* Lt = L + (size_t)t * NC;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double4 s = make_double4(acc[r][0].x + acc[r][1].x, acc[r][0].y + acc[r][1].y,
-                                           acc[r][0].z + acc[r][1].z, acc[r][0].w + acc[r][1].w);
-            const int row0 = 16 * r + 4 * (lane >> 4);
+            const v4d s = acc[r][0] + acc[r][1];
+            const int row0 = 16 * r + (lane >> 4);
             if (row0 + 0 < NC) Lt[row0 + 0] = s.x;
-            if (row0 + 1 < NC) Lt[row0 + 1] = s.y;
-            if (row0 + 2 < NC) Lt[row0 + 2] = s.z;
-            if (row0 + 3 < NC) Lt[row0 + 3] = s.w;
+            if (row0 + 4 < NC) Lt[row0 + 4] = s.y;
+            if (row0 + 8 < NC) Lt[row0 + 8] = s.z;
+            if (row0 + 12 < NC) Lt[row0 + 12] = s.w;
         }
     }
 }
