@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -125,6 +127,13 @@ def main():
     Q = torch.from_numpy(q).to(dev)
     del xyz, q
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {a.numel() * 8} bytes done", file=sys.stderr, flush=True)
+        del a, b
     print(f"[bench] N={args.n} p={args.p} depth={args.depth} precision={args.precision}", file=sys.stderr, flush=True)
 
     chosen, phi_c, grad_c = run_leg(F, torch, X, Q, args.p, args.depth, args.precision, args.steps, args.warmup)

@@ -90,6 +90,7 @@ typedef struct ctfmm_stats_t {
     double ms_m2l;          /* all M2L launches */
     double ms_l2l;
     double ms_near;         /* L2P + P2P */
+    double ms_convert;      /* FP32 copies of the multipoles for the FP32/BF16 M2L modes */
     int64_t evaluations;
     int64_t m2l_launches;
     int64_t m2l_pairs;      /* cell pairs translated by M2L, summed over calls */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -36,8 +37,10 @@ struct ctfmm_ctx {
     DevTables T{};
     double* Dv = nullptr;  // [NOFF][NIND] derivative tensors of the offsets
     double* Kt = nullptr;  // [NOFF][nc][nc] K_v transposed
-    double* Kpk = nullptr;       // K_v as FP64 MFMA fragments
-    int16_t* offlist = nullptr;  // [8][189] offset slots of each target octant
+    unsigned char* Kpk = nullptr;  // K_v as MFMA A-fragments of the M2L precision
+    int16_t* offlist = nullptr;    // [8][189] offset slots of each target octant
+    unsigned char* zero_row = nullptr;  // a zero source row (out-of-domain sources)
+    float* M32 = nullptr;          // FP32 copy of one level's multipoles (FP32/BF16 modes)
 
     // workspace, grown on demand
     int64_t cap_n = -1;
@@ -167,14 +170,18 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     HIPCHK(c, hipGetLastError());
     launch_build_k(c->stream, p, c->Dv, c->T, c->Kt);
     HIPCHK(c, hipGetLastError());
-    // FP64 MFMA fragments of every K_v
+    // MFMA fragments of every K_v in the M2L precision
+    const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    if (m2l64_lds(p) > (size_t)max_lds)
+    if (m2l_lds_bytes(p, prec) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
-    c->Kpk = (double*)dev_alloc(c, m2l64_packed_doubles(p) * sizeof(double));
-    if (!c->Kpk) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
-    launch_pack_k64(c->stream, p, c->Kt, c->Kpk);
+    c->Kpk = (unsigned char*)dev_alloc(c, m2l_packed_bytes(p, prec));
+    const size_t zbytes = std::max((size_t)ldm_of(p) * 8, (size_t)s32_of(p) * 4);
+    c->zero_row = (unsigned char*)dev_alloc(c, zbytes);
+    if (!c->Kpk || !c->zero_row) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+    HIPCHK(c, hipMemsetAsync(c->zero_row, 0, zbytes, c->stream));
+    launch_pack_k(c->stream, p, prec, c->Kt, c->Kpk);
     HIPCHK(c, hipGetLastError());
     // offsets v of the ws=1 list for a target in octant o: v_d in [-2-o_d, 3-o_d], max|v_d| >= 2
     std::vector<int16_t> off(8 * 189);
@@ -201,7 +208,7 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     // release the previous particle workspace (tables and operators are kept)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<void*> keep = {c->tab_blob, (void*)c->Dv, (void*)c->Kt, (void*)c->Kpk, (void*)c->offlist,
-                               (void*)c->err_flag};
+                               (void*)c->zero_row, (void*)c->err_flag};
     std::vector<void*> rest;
     for (void* p : c->owned) {
         bool k = false;
@@ -233,8 +240,13 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
         cells += (size_t)1 << (3 * l);
     }
     c->lvl_off[d + 1] = cells;
-    c->M = (double*)dev_alloc(c, cells * nc * sizeof(double));
-    c->L = (double*)dev_alloc(c, cells * nc * sizeof(double));
+    c->M = (double*)dev_alloc(c, cells * (size_t)ldm_of(p) * sizeof(double));
+    c->L = (double*)dev_alloc(c, cells * (size_t)ldm_of(p) * sizeof(double));
+    c->M32 = nullptr;
+    if (c->prm.precision != CTFMM_PREC_FP64 && d >= 2) {
+        c->M32 = (float*)dev_alloc(c, nleaves * (size_t)s32_of(p) * sizeof(float));
+        if (!c->M32) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
+    }
     c->sort_tmp_bytes = 0;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, c->sort_tmp_bytes, c->keys, c->keys_sorted, c->idx,
                                              c->idx_sorted, (int)nn, 0, d > 0 ? 3 * d : 1, c->stream);
@@ -313,8 +325,9 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
         g_create_err = "only the uniform octree is implemented";
         return CTFMM_EUNSUPPORTED;
     }
-    if (prm->precision != CTFMM_PREC_FP64) {
-        g_create_err = "precision mode not implemented";
+    if (prm->precision != CTFMM_PREC_FP64 && prm->precision != CTFMM_PREC_FP32 &&
+        prm->precision != CTFMM_PREC_BF16X3) {
+        g_create_err = "unknown precision mode";
         return CTFMM_EUNSUPPORTED;
     }
     ctfmm_ctx* c = new (std::nothrow) ctfmm_ctx();
@@ -388,8 +401,9 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
     launch_leaf_start(st, nleaves, c->keys_sorted, ni, c->start);
     HIPCHK(c, hipGetLastError());
     rec(c, 1);
-    auto Ml = [&](int l) { return c->M + c->lvl_off[l] * nc; };
-    auto Ll = [&](int l) { return c->L + c->lvl_off[l] * nc; };
+    const size_t ldm = (size_t)ldm_of(p);
+    auto Ml = [&](int l) { return c->M + c->lvl_off[l] * ldm; };
+    auto Ll = [&](int l) { return c->L + c->lvl_off[l] * ldm; };
     int evi = 5;
     if (d >= 2) {
         launch_p2m(st, p, box, c->start, c->P, c->T, Ml(d));
@@ -398,11 +412,17 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
         rec(c, 3);
         for (int l = 2; l <= d; ++l) {
             rec(c, evi);
-            HIPCHK(c, launch_m2l_mfma64(st, p, l, Ml(l), Ll(l), c->Kpk, c->offlist));
+            const void* msrc = Ml(l);
+            if (c->prm.precision != CTFMM_PREC_FP64) {
+                launch_to_f32(st, p, 1ll << (3 * l), Ml(l), c->M32);
+                msrc = c->M32;
+            }
             rec(c, evi + 1);
-            if (l >= 3) launch_l2l(st, p, l - 1, Ll(l - 1), Ll(l), c->T);
+            HIPCHK(c, launch_m2l(st, p, c->prm.precision, l, msrc, Ll(l), c->Kpk, c->offlist, c->zero_row));
             rec(c, evi + 2);
-            evi += 3;
+            if (l >= 3) launch_l2l(st, p, l - 1, Ll(l - 1), Ll(l), c->T);
+            rec(c, evi + 3);
+            evi += 4;
         }
         rec(c, 4);
         launch_l2p(st, p, box, c->start, c->P, Ll(d), c->T, c->F);
@@ -432,9 +452,10 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
         c->st.ms_near += elapsed(c, 4, ev_end);
         int e = 5;
         for (int l = 2; l <= d; ++l) {
-            c->st.ms_m2l += elapsed(c, e, e + 1);
-            c->st.ms_l2l += elapsed(c, e + 1, e + 2);
-            e += 3;
+            c->st.ms_convert += elapsed(c, e, e + 1);
+            c->st.ms_m2l += elapsed(c, e + 1, e + 2);
+            c->st.ms_l2l += elapsed(c, e + 2, e + 3);
+            e += 4;
         }
     }
     return CTFMM_OK;
@@ -451,7 +472,7 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* c, int32_t level, int32_t which, d
     if (cap < cnt) return fail(c, CTFMM_EINVAL, "host buffer too small");
     double* tmp = nullptr;
     HIPCHK(c, hipMalloc(&tmp, cnt * sizeof(double)));
-    const double* X = (which == 0 ? c->M : c->L) + c->lvl_off[level] * nc;
+    const double* X = (which == 0 ? c->M : c->L) + c->lvl_off[level] * (size_t)ldm_of(p);
     launch_unscale_copy(c->stream, p, level, which, c->prm.root_side, X, tmp);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipMemcpyAsync(host_out, tmp, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);

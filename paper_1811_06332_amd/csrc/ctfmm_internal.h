@@ -31,6 +31,9 @@ struct DevTables {
     const double* c_coef;
 };
 
+// row stride of the expansion buffers: (p+1)^2 rounded up to a multiple of 4
+__host__ __device__ constexpr int ldm_of(int p) { return ((p + 1) * (p + 1) + 3) & ~3; }
+
 // Morton interleave of 10-bit coordinates (x in bit 0 of each triple).
 __host__ __device__ inline uint32_t spread3(uint32_t v) {
     v &= 0x3ffu;
@@ -67,17 +70,21 @@ void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const doubl
 void launch_m2m(hipStream_t s, int p, int parent_level, const double* Mchild, double* Mparent, const DevTables& T);
 void launch_offset_dtensors(hipStream_t s, int p, double* Dv);
 void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, double* Kt);
-void launch_m2l_fp64(hipStream_t s, int p, int level, const double* M, double* L, const double* Kt);
 void launch_l2l(hipStream_t s, int p, int parent_level, const double* Lparent, double* Lchild, const DevTables& T);
 void launch_l2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const double* L,
                 const DevTables& T, double4* F);
 void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32_t* start, const double4* P,
                 const int32_t* idx, const double4* F, double* phi, double* grad);
-size_t m2l64_packed_doubles(int p);
-size_t m2l64_lds(int p);
-void launch_pack_k64(hipStream_t s, int p, const double* Kt, double* Kpk);
-hipError_t launch_m2l_mfma64(hipStream_t s, int p, int level, const double* M, double* L, const double* Kpk,
-                             const int16_t* offlist);
+// M2L operand precision (ctfmm_precision values)
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+size_t m2l_packed_bytes(int p, int prec);
+size_t m2l_lds_bytes(int p, int prec);
+void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk);
+void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32);
+hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L,
+                      const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row);
+// row stride of the FP32 multipole copy: (p+1)^2 rounded up to a multiple of 32
+__host__ __device__ constexpr int s32_of(int p) { return (((p + 1) * (p + 1) + 31) / 32) * 32; }
 void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side, const double* X, double* out);
 
 }  // namespace ctfmm

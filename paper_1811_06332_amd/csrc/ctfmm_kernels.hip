@@ -2,9 +2,9 @@
 // operator matrices, M2L, L2L, L2P and the P2P near field.
 //
 // Expansions are stored in scaled form on a Morton-ordered uniform octree:
-// level l holds 8^l cells, cell m at M[(m * nc) + k] with nc = (p+1)^2
+// level l holds 8^l cells, cell m at M[(m * ldm) + k] with nc = (p+1)^2
 // independent traceless components k (ordered by rank, then n_z, then n_x
-// descending).  With h the cell side, M~_k = M_k / h^|k| and
+// descending) and rows padded to ldm = nc rounded up to a multiple of 4.  With h the cell side, M~_k = M_k / h^|k| and
 // L~_k = L_k h^(|k|+1); then the M2L operator of an integer offset v is the
 // same at every level (grad^n r^-1 is homogeneous of degree -n-1) and the
 // M2M/L2L shifts are constant per octant.
@@ -119,9 +119,9 @@ __global__ __launch_bounds__(64) void k_p2m(int p, Box box, const int32_t* __res
         acc1 += pt.w * v1;
         __syncthreads();
     }
-    double* Mc = M + (size_t)c * nc;
-    if (s0 < nc) Mc[s0] = acc0;
-    if (s1 < nc) Mc[s1] = acc1;
+    double* Mc = M + (size_t)c * ldm_of(p);
+    if (s0 < ldm_of(p)) Mc[s0] = s0 < nc ? acc0 : 0.0;  // padding is kept zero
+    if (s1 < ldm_of(p)) Mc[s1] = s1 < nc ? acc1 : 0.0;
 }
 
 void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M) {
@@ -137,8 +137,9 @@ __global__ __launch_bounds__(128) void k_m2m(int p, const double* __restrict__ M
     const uint32_t P = blockIdx.x;
     const int nc = (p + 1) * (p + 1);
     __shared__ double ch[8 * NIND];
-    const double* src = Mc + (size_t)8 * P * nc;
-    for (int t = threadIdx.x; t < 8 * nc; t += 128) ch[(t / nc) * NIND + (t % nc)] = src[t];
+    const int ldm = ldm_of(p);
+    const double* src = Mc + (size_t)8 * P * ldm;
+    for (int t = threadIdx.x; t < 8 * nc; t += 128) ch[(t / nc) * NIND + (t % nc)] = src[(t / nc) * ldm + (t % nc)];
     __syncthreads();
     const int n = threadIdx.x;
     if (n < nc) {
@@ -147,7 +148,9 @@ __global__ __launch_bounds__(128) void k_m2m(int p, const double* __restrict__ M
             const double* A = m2m_t + (size_t)o * NIND * NIND;
             for (int j = 0; j < nc; ++j) acc += A[(size_t)j * NIND + n] * ch[o * NIND + j];
         }
-        Mp[(size_t)P * nc + n] = acc;
+        Mp[(size_t)P * ldm + n] = acc;
+    } else if (n < ldm) {
+        Mp[(size_t)P * ldm + n] = 0.0;  // padding is kept zero
     }
 }
 
@@ -207,47 +210,6 @@ void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, 
     hipLaunchKernelGGL(k_build_k, dim3(cdiv(tot, 256)), dim3(256), 0, s, p, Dv, T, Kt);
 }
 
-// ------------------------------------------------------------------ M2L (FP64)
-
-// One target cell per workgroup: L~_T = sum over the ws=1 interaction list
-// (children of the parent's neighbours that are not adjacent to T) of
-// K_{T-S} M~_S.
-__global__ __launch_bounds__(128) void k_m2l_fp64(int p, int level, const double* __restrict__ M,
-                                                  double* __restrict__ L, const double* __restrict__ Kt) {
-    const uint32_t T = blockIdx.x;
-    const int nc = (p + 1) * (p + 1);
-    const int n1 = 1 << level;
-    const int ix = compact3(T), iy = compact3(T >> 1), iz = compact3(T >> 2);
-    const int I = ix >> 1, J = iy >> 1, K = iz >> 1;
-    __shared__ double Ms[NIND];
-    const int n = threadIdx.x;
-    double acc = 0.0;
-    for (int c = 2 * K - 2; c <= 2 * K + 3; ++c) {
-        if (c < 0 || c >= n1) continue;
-        for (int b = 2 * J - 2; b <= 2 * J + 3; ++b) {
-            if (b < 0 || b >= n1) continue;
-            for (int a = 2 * I - 2; a <= 2 * I + 3; ++a) {
-                if (a < 0 || a >= n1) continue;
-                if (abs(a - ix) <= 1 && abs(b - iy) <= 1 && abs(c - iz) <= 1) continue;
-                const uint32_t S = morton3(a, b, c);
-                __syncthreads();
-                if (n < nc) Ms[n] = M[(size_t)S * nc + n];
-                __syncthreads();
-                const int vs = (ix - a + 3) + 7 * (iy - b + 3) + 49 * (iz - c + 3);
-                const double* Kv = Kt + (size_t)vs * nc * nc;
-                if (n < nc)
-                    for (int j = 0; j < nc; ++j) acc += Kv[(size_t)j * nc + n] * Ms[j];
-            }
-        }
-    }
-    if (n < nc) L[(size_t)T * nc + n] = acc;
-}
-
-void launch_m2l_fp64(hipStream_t s, int p, int level, const double* M, double* L, const double* Kt) {
-    const long long ncell = 1ll << (3 * level);
-    hipLaunchKernelGGL(k_m2l_fp64, dim3((unsigned)ncell), dim3(128), 0, s, p, level, M, L, Kt);
-}
-
 // ------------------------------------------------------------------ L2L
 
 // child L~_o += B_o L~_parent (Eq. L2L in scaled form)
@@ -256,14 +218,15 @@ __global__ __launch_bounds__(256) void k_l2l(int p, const double* __restrict__ L
     const uint32_t P = blockIdx.x;
     const int nc = (p + 1) * (p + 1);
     __shared__ double lp[NIND];
-    for (int t = threadIdx.x; t < nc; t += 256) lp[t] = Lp[(size_t)P * nc + t];
+    const int ldm = ldm_of(p);
+    for (int t = threadIdx.x; t < nc; t += 256) lp[t] = Lp[(size_t)P * ldm + t];
     __syncthreads();
     for (int t = threadIdx.x; t < 8 * nc; t += 256) {
         const int o = t / nc, n = t % nc;
         const double* B = l2l_t + (size_t)o * NIND * NIND;
         double acc = 0.0;
         for (int j = 0; j < nc; ++j) acc += B[(size_t)j * NIND + n] * lp[j];
-        Lc[((size_t)8 * P + o) * nc + n] += acc;
+        Lc[((size_t)8 * P + o) * ldm + n] += acc;
     }
 }
 
@@ -312,7 +275,7 @@ __global__ __launch_bounds__(64) void k_l2p(Box box, const int32_t* __restrict__
     const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
     const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
     __shared__ double W[4][NF];  // potential, d/dx, d/dy, d/dz coefficients
-    const double* Lc = L + (size_t)c * NC;
+    const double* Lc = L + (size_t)c * ldm_of(P);
     for (int f = threadIdx.x; f < NF; f += 64) {
         double v = 0.0;
         for (int t = T.exp_start[f]; t < T.exp_start[f + 1]; ++t) v += (double)T.exp_coef[t] * Lc[T.exp_slot[t]];
@@ -435,7 +398,7 @@ __global__ void k_unscale_copy(int p, int level, int which, double h, const doub
     const long long cell = gid / nc;
     const uint32_t ix = (uint32_t)(cell % n1), iy = (uint32_t)((cell / n1) % n1), iz = (uint32_t)(cell / (n1 * n1));
     const uint32_t m = morton3(ix, iy, iz);
-    double v = X[(size_t)m * nc + k];
+    double v = X[(size_t)m * ldm_of(p) + k];
     const int r = rank_of(k);
     double hp = 1.0;
     for (int t = 0; t < r; ++t) hp *= h;
@@ -454,12 +417,24 @@ void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side
 // Work unit: one target octant o and a block of up to 64 Morton-consecutive
 // parent cells (a 4x4x4 cube of parents).  Its targets (parent*8 + o) share
 // the same 189 offsets v of the ws=1 list, so for each v the whole tile is
-// one small GEMM  L~[:, tile] += K_v[:, :] * M~[:, tile + v].
-// Per offset, K_v (only its non-zero 16x4 blocks: rows of rank a need
-// columns of rank <= p - a) and the 64 source multipoles are staged in LDS
-// in MFMA fragment order; wave w owns targets 16w..16w+15 and all row tiles.
+// one small GEMM  L~[:, tile] += K_v * M~[:, tile + v].  K_v is stored as
+// MFMA A-fragments of its non-zero blocks only (rows of rank a need columns
+// of rank <= p - a).  Per offset, K_v and the 64 source rows are copied into
+// LDS with direct global->LDS loads (no VGPR round trip), double-buffered so
+// the copies for offset v+1 overlap the matrix-core work of offset v.  Wave
+// w owns targets 16w..16w+15 and every row tile.
+//
+// Precisions (operand type -> accumulator):
+//   F64    : FP64 16x16x4 MFMA, FP64 accumulation
+//   F32    : operands rounded to FP32, FP32 16x16x4 MFMA, FP32 accumulation
+//   BF16X3 : operands split x = x0 + x1 + x2 into BF16 pieces (24 significant
+//            bits), the six products with piece-index sum <= 2 on BF16
+//            16x16x32 MFMA, FP32 accumulation
+// The local expansions are written back in FP64.
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -469,30 +444,48 @@ __host__ __device__ constexpr int rank_ce(int k) {
     return r;
 }
 
+constexpr int LDS_LIMIT = 163840;
+
 }  // namespace
 
-template <int P>
-struct Shape64 {
+template <int P, int PREC>
+struct Tile {
     static constexpr int NC = (P + 1) * (P + 1);
-    static constexpr int R = (NC + 15) / 16;  // 16-row tiles
-    // 4-column chunks needed by row tile r (its first row has the lowest rank)
+    static constexpr int LDM = (NC + 3) & ~3;                 // FP64 expansion row stride
+    static constexpr int S32 = ((NC + 31) / 32) * 32;          // FP32 copy row stride
+    static constexpr int KW = PREC == PREC_BF16X3 ? 32 : 4;    // k extent of one MFMA
+    static constexpr int R = (NC + 15) / 16;                   // 16-row tiles
     static constexpr int nch(int r) {
         const int m = P - rank_ce(16 * r) + 1;
-        return (m * m + 3) / 4;
+        return (m * m + KW - 1) / KW;
     }
     static constexpr int cb(int r) {
         int s = 0;
         for (int i = 0; i < r; ++i) s += nch(i);
         return s;
     }
-    static constexpr int NCH = cb(R);  // packed chunks of one K_v
-    static constexpr int NB = nch(0);  // chunks of one source multipole
+    static constexpr int NCH = cb(R);
+    static constexpr int NB = nch(0);
+    // bytes of one packed A-fragment chunk (64 lanes)
+    static constexpr int CHB = PREC == PREC_F64 ? 512 : PREC == PREC_F32 ? 256 : 3 * 64 * 16;
+    static constexpr int KBYTES = NCH * CHB;
+    // one source row in LDS: FP64 rows of LDM doubles, or FP32 rows of S32 floats
+    static constexpr int BROW = PREC == PREC_F64 ? LDM * 8 : S32 * 4;
+    static constexpr int BBYTES = 64 * BROW;
+    static constexpr int KBUF = (2 * KBYTES + 2 * BBYTES + 1024 <= LDS_LIMIT) ? 2 : 1;
+    static constexpr int LDS = KBUF * KBYTES + 2 * BBYTES;
 };
 
-// pack K_v into fragments: Kpk[v][chunk][lane], lane -> (row 16r + lane%16, col 4c + lane/16)
-template <int P>
-__global__ void k_pack_k64(const double* __restrict__ Kt, double* __restrict__ Kpk) {
-    using S = Shape64<P>;
+__device__ inline uint16_t bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// K_v as MFMA A-fragments: Kpk[v slot][chunk][...], lane -> (row 16r + lane%16, k 16-lane group)
+template <int P, int PREC>
+__global__ void k_pack_k(const double* __restrict__ Kt, unsigned char* __restrict__ Kpk) {
+    using S = Tile<P, PREC>;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (long long)NOFF * S::NCH * 64) return;
     const int lane = (int)(gid % 64);
@@ -501,23 +494,60 @@ __global__ void k_pack_k64(const double* __restrict__ Kt, double* __restrict__ K
     int r = 0;
     while (r + 1 < S::R && S::cb(r + 1) <= ch) ++r;
     const int c = ch - S::cb(r);
-    const int row = 16 * r + (lane % 16), col = 4 * c + lane / 16;
-    double val = 0.0;
-    if (row < S::NC && col < S::NC) val = Kt[((size_t)v * S::NC + col) * S::NC + row];
-    Kpk[gid] = val;
+    const int row = 16 * r + (lane % 16);
+    auto kval = [&](int col) -> double {
+        return (row < S::NC && col < S::NC) ? Kt[((size_t)v * S::NC + col) * S::NC + row] : 0.0;
+    };
+    unsigned char* dst = Kpk + ((size_t)v * S::NCH + ch) * S::CHB;
+    if (PREC == PREC_F64) {
+        reinterpret_cast<double*>(dst)[lane] = kval(4 * c + lane / 16);
+    } else if (PREC == PREC_F32) {
+        reinterpret_cast<float*>(dst)[lane] = (float)kval(4 * c + lane / 16);
+    } else {
+        // [piece][lane][8 bf16]
+        for (int e = 0; e < 8; ++e) {
+            const double x = kval(32 * c + 8 * (lane / 16) + e);
+            const uint16_t h0 = bf16_rne((float)x);
+            const double r1 = x - (double)bf16_to_f(h0);
+            const uint16_t h1 = bf16_rne((float)r1);
+            const double r2 = r1 - (double)bf16_to_f(h1);
+            const uint16_t h2 = bf16_rne((float)r2);
+            uint16_t* d16 = reinterpret_cast<uint16_t*>(dst);
+            d16[(0 * 64 + lane) * 8 + e] = h0;
+            d16[(1 * 64 + lane) * 8 + e] = h1;
+            d16[(2 * 64 + lane) * 8 + e] = h2;
+        }
+    }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_m2l_mfma64(int level, const double* __restrict__ M, double* __restrict__ L,
-                                                    const double* __restrict__ Kpk,
-                                                    const int16_t* __restrict__ offlist) {
-    using S = Shape64<P>;
-    constexpr int NC = S::NC, R = S::R, NCH = S::NCH, NB = S::NB;
-    extern __shared__ double lds[];
-    double* Ks = lds;                 // [NCH][64]
-    double* Bs = lds + NCH * 64;      // [4][NB][64]
-    __shared__ int srcrow[64];
-    __shared__ int tgtrow[64];
+// FP32 copy of one level's multipoles, rows of S32 floats, zero padded
+__global__ void k_to_f32(long long ncell, int nc, int ldm, int s32, const double* __restrict__ M,
+                         float* __restrict__ M32) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= ncell * s32) return;
+    const long long cell = gid / s32;
+    const int k = (int)(gid % s32);
+    M32[gid] = k < nc ? (float)M[cell * ldm + k] : 0.0f;
+}
+
+__device__ inline void lds_copy16(const void* g, void* lds) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+template <int P, int PREC>
+__global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restrict__ Msrc, double* __restrict__ L,
+                                                  const unsigned char* __restrict__ Kpk,
+                                                  const int16_t* __restrict__ offlist,
+                                                  const unsigned char* __restrict__ zero_row) {
+    using S = Tile<P, PREC>;
+    constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB;
+    constexpr int KU = S::KBYTES / 16;        // 16-byte units of one K_v
+    constexpr int RU = S::BROW / 16;          // 16-byte units of one source row
+    constexpr int BU = 64 * RU;               // units of the 64 source rows
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    unsigned char* Kb = lds;                              // [KBUF][KBYTES]
+    unsigned char* Bb = lds + S::KBUF * S::KBYTES;        // [2][64 rows][BROW]
+    __shared__ int tco[64];                               // packed target coords, -1 = none
 
     const int o = blockIdx.x & 7;
     const int pb = blockIdx.x >> 3;
@@ -527,130 +557,250 @@ __global__ __launch_bounds__(256) void k_m2l_mfma64(int level, const double* __r
     const long long nparents = 1ll << (3 * (level - 1));
     if (tid < 64) {
         const long long par = (long long)pb * 64 + tid;
-        tgtrow[tid] = par < nparents ? (int)(par * 8 + o) : -1;
+        int packed = -1;
+        if (par < nparents) {
+            const uint32_t t = (uint32_t)(par * 8 + o);
+            packed = (int)(compact3(t) | (compact3(t >> 1) << 10) | (compact3(t >> 2) << 20));
+        }
+        tco[tid] = packed;
     }
+    __syncthreads();
 
-    v4d acc[R][2];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4d{0.0, 0.0, 0.0, 0.0};
-
-    for (int iv = 0; iv < 189; ++iv) {
+    auto stage_k = [&](int iv, int buf) {
+        const int vs = offlist[o * 189 + iv];
+        // v is source - target; the operator is built for r = target - source = -v
+        const unsigned char* src = Kpk + (size_t)(NOFF - 1 - vs) * S::KBYTES;
+        unsigned char* dst = Kb + buf * S::KBYTES;
+        for (int i = w; i * 64 < KU; i += 4) {
+            const int u = i * 64 + lane;
+            if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
+        }
+    };
+    auto stage_b = [&](int iv, int buf) {
         const int vs = offlist[o * 189 + iv];
         const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
-        __syncthreads();  // previous offset's fragments are consumed; tgtrow visible
-        if (tid < 64) {
-            const int t = tgtrow[tid];
-            int row = -1;
-            if (t >= 0) {
-                const int sx = (int)compact3((uint32_t)t) + vx, sy = (int)compact3((uint32_t)t >> 1) + vy,
-                          sz = (int)compact3((uint32_t)t >> 2) + vz;
-                if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1) row = (int)morton3(sx, sy, sz);
-            }
-            srcrow[tid] = row;
-        }
-        // v is source - target; the operator is built for r = target - source = -v
-        const double* Kv = Kpk + (size_t)(NOFF - 1 - vs) * NCH * 64;
-        for (int i = tid; i < NCH * 64; i += 256) Ks[i] = Kv[i];
-        __syncthreads();
-        for (int e = tid; e < 4 * NB * 64; e += 256) {
-            const int ln = e & 63;
-            const int c = (e >> 6) % NB;
-            const int ww = e / (64 * NB);
-            const int row = srcrow[ww * 16 + (ln & 15)];
-            const int k = 4 * c + (ln >> 4);
-            Bs[e] = (row >= 0 && k < NC) ? M[(size_t)row * NC + k] : 0.0;
-        }
-        __syncthreads();
-        const double* Bw = Bs + w * NB * 64;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const double b = Bw[c * 64 + lane];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (c < S::nch(r)) {
-                    const double a = Ks[(S::cb(r) + c) * 64 + lane];
-                    acc[r][c & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r][c & 1], 0, 0, 0);
+        unsigned char* dst = Bb + buf * S::BBYTES;
+        for (int i = w; i * 64 < BU; i += 4) {
+            const int u = i * 64 + lane;
+            if (u < BU) {
+                const int slot = u / RU, ru = u % RU;
+                const int tc = tco[slot];
+                const unsigned char* g = zero_row + ru * 16;
+                if (tc >= 0) {
+                    const int sx = (tc & 1023) + vx, sy = ((tc >> 10) & 1023) + vy, sz = (tc >> 20) + vz;
+                    if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1)
+                        g = reinterpret_cast<const unsigned char*>(Msrc) + (size_t)morton3(sx, sy, sz) * S::BROW +
+                            ru * 16;
                 }
+                lds_copy16(g, dst + i * 1024);
+            }
+        }
+    };
+
+    // accumulators
+    v4d acc64[PREC == PREC_F64 ? R : 1][2];
+    v4f acc32[PREC == PREC_F32 ? R : 1][2];
+    v4f accb[PREC == PREC_BF16X3 ? R : 1][6];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (PREC == PREC_F64) acc64[r][0] = acc64[r][1] = v4d{0.0, 0.0, 0.0, 0.0};
+        if (PREC == PREC_F32) acc32[r][0] = acc32[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (PREC == PREC_BF16X3)
+            for (int k = 0; k < 6; ++k) accb[r][k] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+    stage_k(0, 0);
+    stage_b(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int trow = w * 16 + (lane & 15);  // this lane's target slot in B fragments
+    const int kq = lane >> 4;
+    for (int iv = 0; iv < 189; ++iv) {
+        const int kb = S::KBUF == 2 ? (iv & 1) : 0;
+        const int bb = iv & 1;
+        if (iv + 1 < 189) {
+            if (S::KBUF == 2) stage_k(iv + 1, kb ^ 1);
+            stage_b(iv + 1, bb ^ 1);
+        }
+        const unsigned char* Kc = Kb + kb * S::KBYTES;
+        const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROW;
+        if (PREC == PREC_F64) {
+            const double* Bd = reinterpret_cast<const double*>(Bc);
+            const double* Kd = reinterpret_cast<const double*>(Kc);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const double b = Bd[4 * c + kq];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (c < S::nch(r)) {
+                        const double a = Kd[(S::cb(r) + c) * 64 + lane];
+                        acc64[r][c & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[r][c & 1], 0, 0, 0);
+                    }
+            }
+        } else if (PREC == PREC_F32) {
+            const float* Bf = reinterpret_cast<const float*>(Bc);
+            const float* Kf = reinterpret_cast<const float*>(Kc);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const float b = Bf[4 * c + kq];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (c < S::nch(r)) {
+                        const float a = Kf[(S::cb(r) + c) * 64 + lane];
+                        acc32[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc32[r][c & 1], 0, 0, 0);
+                    }
+            }
+        } else {
+            const float* Bf = reinterpret_cast<const float*>(Bc);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                // this lane's 8 consecutive k of its target, split into three BF16 pieces
+                const v4f x0 = *reinterpret_cast<const v4f*>(Bf + 32 * c + 8 * kq);
+                const v4f x1 = *reinterpret_cast<const v4f*>(Bf + 32 * c + 8 * kq + 4);
+                bf16x8 b0, b1, b2;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float x = e < 4 ? x0[e] : x1[e - 4];
+                    const uint16_t h0 = bf16_rne(x);
+                    const float r1 = x - bf16_to_f(h0);
+                    const uint16_t h1 = bf16_rne(r1);
+                    const float r2 = r1 - bf16_to_f(h1);
+                    const uint16_t h2 = bf16_rne(r2);
+                    b0[e] = __builtin_bit_cast(__bf16, h0);
+                    b1[e] = __builtin_bit_cast(__bf16, h1);
+                    b2[e] = __builtin_bit_cast(__bf16, h2);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (c < S::nch(r)) {
+                        const bf16x8* A = reinterpret_cast<const bf16x8*>(Kc + (S::cb(r) + c) * S::CHB);
+                        const bf16x8 a0 = A[lane], a1 = A[64 + lane], a2 = A[128 + lane];
+                        accb[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, accb[r][0], 0, 0, 0);
+                        accb[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, accb[r][1], 0, 0, 0);
+                        accb[r][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, accb[r][2], 0, 0, 0);
+                        accb[r][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2, accb[r][3], 0, 0, 0);
+                        accb[r][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, accb[r][4], 0, 0, 0);
+                        accb[r][5] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0, accb[r][5], 0, 0, 0);
+                    }
+            }
+        }
+        if (iv + 1 < 189) {
+            if (S::KBUF == 1) {
+                __syncthreads();  // every wave is done with this offset's K_v
+                stage_k(iv + 1, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+    }
+    const long long par = (long long)pb * 64 + w * 16 + (lane & 15);
+    if (par >= nparents) return;
+    double* Lt = L + (size_t)(par * 8 + o) * LDM;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (PREC == PREC_F64) {
+            // FP64 16x16 accumulator: element j holds row 16r + lane/16 + 4j
+            const v4d sacc = acc64[r][0] + acc64[r][1];
+            const int row0 = 16 * r + (lane >> 4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (row0 + 4 * j < NC) Lt[row0 + 4 * j] = sacc[j];
+        } else {
+            // FP32 16x16 accumulator: element j holds row 16r + 4*(lane/16) + j
+            const int row0 = 16 * r + 4 * (lane >> 4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double v;
+                if (PREC == PREC_F32) {
+                    v = (double)acc32[r][0][j] + (double)acc32[r][1][j];
+                } else {
+                    v = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) v += (double)accb[r][k][j];
+                }
+                if (row0 + j < NC) Lt[row0 + j] = v;
             }
         }
     }
-    // FP64 16x16 accumulator: element j of lane holds row 16r + lane/16 + 4j of target lane%16
-    const int t = tgtrow[w * 16 + (lane & 15)];
-    if (t >= 0) {
-        double* Lt = L + (size_t)t * NC;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const v4d s = acc[r][0] + acc[r][1];
-            const int row0 = 16 * r + (lane >> 4);
-            if (row0 + 0 < NC) Lt[row0 + 0] = s.x;
-            if (row0 + 4 < NC) Lt[row0 + 4] = s.y;
-            if (row0 + 8 < NC) Lt[row0 + 8] = s.z;
-            if (row0 + 12 < NC) Lt[row0 + 12] = s.w;
-        }
-    }
 }
 
-template <int P>
-size_t m2l64_lds_bytes() {
-    using S = Shape64<P>;
-    return (size_t)(S::NCH * 64 + 4 * S::NB * 64) * sizeof(double);
-}
-
-template <int P>
-void pack_k64_impl(hipStream_t s, const double* Kt, double* Kpk) {
-    using S = Shape64<P>;
-    const long long tot = (long long)NOFF * S::NCH * 64;
-    hipLaunchKernelGGL(k_pack_k64<P>, dim3(cdiv(tot, 256)), dim3(256), 0, s, Kt, Kpk);
-}
-
-template <int P>
-hipError_t m2l64_impl(hipStream_t s, int level, const double* M, double* L, const double* Kpk, const int16_t* offlist) {
-    const size_t lds = m2l64_lds_bytes<P>();
+template <int P, int PREC>
+hipError_t m2l_tile_impl(hipStream_t s, int level, const void* Msrc, double* L, const unsigned char* Kpk,
+                         const int16_t* offlist, const unsigned char* zero_row) {
+    using S = Tile<P, PREC>;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_mfma64<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const long long nparents = 1ll << (3 * (level - 1));
     const long long nblk = (nparents + 63) / 64;
-    hipLaunchKernelGGL(k_m2l_mfma64<P>, dim3((unsigned)(8 * nblk)), dim3(256), lds, s, level, M, L, Kpk, offlist);
+    hipLaunchKernelGGL((k_m2l_tile<P, PREC>), dim3((unsigned)(8 * nblk)), dim3(256), S::LDS, s, level, Msrc, L,
+                       Kpk, offlist, zero_row);
     return hipGetLastError();
 }
 
-size_t m2l64_packed_doubles(int p) {
+template <int P, int PREC>
+void pack_k_impl(hipStream_t s, const double* Kt, unsigned char* Kpk) {
+    using S = Tile<P, PREC>;
+    const long long tot = (long long)NOFF * S::NCH * 64;
+    hipLaunchKernelGGL((k_pack_k<P, PREC>), dim3(cdiv(tot, 256)), dim3(256), 0, s, Kt, Kpk);
+}
+
+#define CTFMM_P_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+
+template <int PREC>
+static size_t tile_query(int p, int what) {
     switch (p) {
-#define CASE(PP) case PP: return (size_t)NOFF * Shape64<PP>::NCH * 64;
-        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#define CASE(PP) \
+    case PP: return what == 0 ? (size_t)NOFF * Tile<PP, PREC>::KBYTES : what == 1 ? (size_t)Tile<PP, PREC>::LDS : 0;
+        CTFMM_P_CASES(CASE)
 #undef CASE
         default: return 0;
     }
 }
 
-size_t m2l64_lds(int p) {
-    switch (p) {
-#define CASE(PP) case PP: return m2l64_lds_bytes<PP>();
-        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
-#undef CASE
-        default: return 0;
-    }
+size_t m2l_packed_bytes(int p, int prec) {
+    return prec == PREC_F64 ? tile_query<PREC_F64>(p, 0) : prec == PREC_F32 ? tile_query<PREC_F32>(p, 0)
+                                                                            : tile_query<PREC_BF16X3>(p, 0);
 }
 
-void launch_pack_k64(hipStream_t s, int p, const double* Kt, double* Kpk) {
+size_t m2l_lds_bytes(int p, int prec) {
+    return prec == PREC_F64 ? tile_query<PREC_F64>(p, 1) : prec == PREC_F32 ? tile_query<PREC_F32>(p, 1)
+                                                                            : tile_query<PREC_BF16X3>(p, 1);
+}
+
+void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk) {
     switch (p) {
-#define CASE(PP) case PP: pack_k64_impl<PP>(s, Kt, Kpk); break;
-        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#define CASE(PP)                                                             \
+    case PP:                                                                 \
+        if (prec == PREC_F64) pack_k_impl<PP, PREC_F64>(s, Kt, Kpk);        \
+        else if (prec == PREC_F32) pack_k_impl<PP, PREC_F32>(s, Kt, Kpk);   \
+        else pack_k_impl<PP, PREC_BF16X3>(s, Kt, Kpk);                      \
+        break;
+        CTFMM_P_CASES(CASE)
 #undef CASE
         default: break;
     }
 }
 
-hipError_t launch_m2l_mfma64(hipStream_t s, int p, int level, const double* M, double* L, const double* Kpk,
-                             const int16_t* offlist) {
+void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32) {
+    const int nc = (p + 1) * (p + 1);
+    const int s32 = ((nc + 31) / 32) * 32;
+    hipLaunchKernelGGL(k_to_f32, dim3(cdiv(ncell * s32, 256)), dim3(256), 0, s, ncell, nc, ldm_of(p), s32, M, M32);
+}
+
+hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L, const unsigned char* Kpk,
+                      const int16_t* offlist, const unsigned char* zero_row) {
     switch (p) {
-#define CASE(PP) case PP: return m2l64_impl<PP>(s, level, M, L, Kpk, offlist);
-        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#define CASE(PP)                                                                                           \
+    case PP:                                                                                               \
+        if (prec == PREC_F64) return m2l_tile_impl<PP, PREC_F64>(s, level, Msrc, L, Kpk, offlist, zero_row); \
+        if (prec == PREC_F32) return m2l_tile_impl<PP, PREC_F32>(s, level, Msrc, L, Kpk, offlist, zero_row); \
+        return m2l_tile_impl<PP, PREC_BF16X3>(s, level, Msrc, L, Kpk, offlist, zero_row);
+        CTFMM_P_CASES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
     }

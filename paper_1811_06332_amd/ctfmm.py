@@ -39,7 +39,7 @@ class ctfmm_params(C.Structure):
 class ctfmm_stats_t(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_tree", C.c_double), ("ms_p2m", C.c_double),
                 ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
-                ("ms_near", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
+                ("ms_near", C.c_double), ("ms_convert", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
                 ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64)]
 
 
