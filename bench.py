@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particles/s full FMM + M2L GFLOP/s at rel. force err 1e-6 (chosen vs plain FP64)"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
-DEFAULT_PRECISION = "fp64"
+DEFAULT_PRECISION = "fp32"
 
 
 def s_of_p(p: int) -> int:
@@ -72,6 +72,20 @@ def run_leg(F, torch, X, Q, p, depth, precision, steps, warmup):
         "m2l_avg_launch_ms": st["ms_m2l"] / st["m2l_launches"] if st["m2l_launches"] else None,
     }
     return leg, phi, grad
+
+
+def m2l_traffic(precision: str):
+    """HBM bytes per M2L launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, or None when it does not describe the kernel source built now."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", f"m2l_{precision}_uniform16M_p10_traffic.json")
+    src = os.path.join(ROOT, "paper_1811_06332_amd", "csrc", "ctfmm_kernels.hip")
+    if not os.path.exists(rec_path):
+        return None
+    rec = json.load(open(rec_path))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(p: int, depth_full: int):
@@ -151,8 +165,9 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     flops_launch = chosen["m2l_pairs_per_step"] * 2 * s_of_p(args.p) / max(1, chosen["m2l_launches_per_step"])
     achieved = flops_launch / (chosen["m2l_avg_launch_ms"] * 1e-3) / 1e12 if chosen["m2l_avg_launch_ms"] else None
+    traffic = m2l_traffic(args.precision) if (args.n, args.p, args.depth) == (1 << 24, 10, 7) else None
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak if achieved else None, "traffic": None,
+                "frac": achieved / peak if achieved else None, "traffic": traffic,
                 "kernel": "M2L (all levels; algorithmic 2*S(p) flops per cell pair)",
                 "flops_per_launch": flops_launch, "avg_launch_ms": chosen["m2l_avg_launch_ms"]}
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.p, args.depth)

@@ -136,6 +136,9 @@ ctfmm_status upload_tables(ctfmm_ctx* c) {
     const size_t o_cn = put(blob, &GEN_C_COUNT[0][0], (size_t)NIND * NIND);
     const size_t o_csl = put(blob, GEN_C_SLOT, sizeof(GEN_C_SLOT));
     const size_t o_cc = put(blob, GEN_C_COEF, sizeof(GEN_C_COEF) / sizeof(GEN_C_COEF[0]));
+    const size_t o_ds = put(blob, GEN_DET_START, sizeof(GEN_DET_START) / sizeof(GEN_DET_START[0]));
+    const size_t o_df = put(blob, GEN_DET_FULL, sizeof(GEN_DET_FULL) / sizeof(GEN_DET_FULL[0]));
+    const size_t o_dc = put(blob, GEN_DET_COEF, sizeof(GEN_DET_COEF) / sizeof(GEN_DET_COEF[0]));
     void* d = dev_alloc(c, blob.size());
     if (!d) return fail(c, CTFMM_ENOMEM, "table allocation failed");
     HIPCHK(c, hipMemcpyAsync(d, blob.data(), blob.size(), hipMemcpyHostToDevice, c->stream));
@@ -157,6 +160,9 @@ ctfmm_status upload_tables(ctfmm_ctx* c) {
     c->T.c_count = (const uint8_t*)(b + o_cn);
     c->T.c_slot = (const uint8_t*)(b + o_csl);
     c->T.c_coef = (const double*)(b + o_cc);
+    c->T.det_start = (const int16_t*)(b + o_ds);
+    c->T.det_full = (const int16_t*)(b + o_df);
+    c->T.det_coef = (const double*)(b + o_dc);
     return CTFMM_OK;
 }
 
@@ -195,6 +201,26 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
                     off[o * 189 + k++] = (int16_t)((vx + 3) + 7 * (vy + 3) + 49 * (vz + 3));
                 }
         if (k != 189) return fail(c, CTFMM_EDEVICE, "offset list construction");
+    }
+    if (prec == CTFMM_PREC_FP32) {
+        // source-octant-major order for the halo kernel: entries (q << 5 | u), then the K slot of r = -v
+        std::vector<int16_t> hl(2 * 8 * 189);
+        for (int o = 0; o < 8; ++o) {
+            int k = 0;
+            for (int q = 0; q < 8; ++q)
+                for (int u = 0; u < 27; ++u) {
+                    const int vx = 2 * (u % 3 - 1) + (q & 1) - (o & 1);
+                    const int vy = 2 * ((u / 3) % 3 - 1) + ((q >> 1) & 1) - ((o >> 1) & 1);
+                    const int vz = 2 * (u / 9 - 1) + ((q >> 2) & 1) - ((o >> 2) & 1);
+                    if (std::abs(vx) <= 1 && std::abs(vy) <= 1 && std::abs(vz) <= 1) continue;
+                    if (k >= 189) return fail(c, CTFMM_EDEVICE, "halo offset list construction");
+                    hl[o * 189 + k] = (int16_t)((q << 5) | u);
+                    hl[8 * 189 + o * 189 + k] = (int16_t)((NOFF - 1) - ((vx + 3) + 7 * (vy + 3) + 49 * (vz + 3)));
+                    ++k;
+                }
+            if (k != 189) return fail(c, CTFMM_EDEVICE, "halo offset list construction");
+        }
+        off = hl;
     }
     c->offlist = (int16_t*)dev_alloc(c, off.size() * sizeof(int16_t));
     if (!c->offlist) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
@@ -425,7 +451,7 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
             evi += 4;
         }
         rec(c, 4);
-        launch_l2p(st, p, box, c->start, c->P, Ll(d), c->T, c->F);
+        launch_l2p(st, p, ni, box, c->keys_sorted, c->P, Ll(d), c->F);
         launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, c->F, phi, grad);
     } else {
         rec(c, 2);

@@ -29,6 +29,9 @@ struct DevTables {
     const uint8_t* c_count;   // [NIND n][NIND j]
     const uint8_t* c_slot;
     const double* c_coef;
+    const int16_t* det_start;  // [NIND+1] detracer rows: independent n <- full f
+    const int16_t* det_full;
+    const double* det_coef;
 };
 
 // row stride of the expansion buffers: (p+1)^2 rounded up to a multiple of 4
@@ -71,8 +74,8 @@ void launch_m2m(hipStream_t s, int p, int parent_level, const double* Mchild, do
 void launch_offset_dtensors(hipStream_t s, int p, double* Dv);
 void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, double* Kt);
 void launch_l2l(hipStream_t s, int p, int parent_level, const double* Lparent, double* Lchild, const DevTables& T);
-void launch_l2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const double* L,
-                const DevTables& T, double4* F);
+void launch_l2p(hipStream_t s, int p, int n, Box box, const uint32_t* keys, const double4* P, const double* L,
+                double4* F);
 void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32_t* start, const double4* P,
                 const int32_t* idx, const double4* F, double* phi, double* grad);
 // M2L operand precision (ctfmm_precision values)

@@ -16,6 +16,13 @@ namespace ctfmm {
 
 static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// rank of independent slot k (rank n occupies slots n^2 .. (n+1)^2 - 1)
+__device__ inline int rank_of(int k) {
+    int r = 0;
+    while ((r + 1) * (r + 1) <= k) ++r;
+    return r;
+}
+
 // ------------------------------------------------------------------ tree
 
 // leaf coordinate floor((x - lo)/side * 2^d), clamped to [0, 2^d - 1]
@@ -76,52 +83,70 @@ void launch_leaf_start(hipStream_t s, int nleaves, const uint32_t* keys, int n, 
 
 // ------------------------------------------------------------------ P2M
 
-// One wavefront per leaf.  For each particle, the power table of
-// u = (z - x)/h and |u|^2 is built in LDS; each lane then sums the compact
-// detracer terms (Eq. Detracer3) of its independent slot(s).
+// One wavefront per leaf, two phases.  (1) Full monomial moments
+// S_f = sum_a q_a u_a^f, u = (z - x)/h, |f| <= p, with the power tables of up
+// to 64 particles at a time in LDS and lanes over f.  (2) The detracer:
+// M~_n = sum_f DET[n][f] S_f for the independent n (Eq. P2M with Eq. Detracer).
 __global__ __launch_bounds__(64) void k_p2m(int p, Box box, const int32_t* __restrict__ start,
                                             const double4* __restrict__ P, DevTables T, double* __restrict__ M) {
     const uint32_t c = blockIdx.x;
     const int lane = threadIdx.x;
     const int nc = (p + 1) * (p + 1);
+    const int nf = (p + 1) * (p + 2) * (p + 3) / 6;
+    const int ldm = ldm_of(p);
     const int d = box.depth;
     const double h = box.side / (double)(1 << d);
     const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
     const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
     const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
-    __shared__ double pw[4][PMAX + 1];
-    double acc0 = 0.0, acc1 = 0.0;
+    __shared__ double pw[64][3][PMAX + 1];
+    __shared__ double qs[64];
+    __shared__ double S[NFULL];
+    constexpr int FPL = (NFULL + 63) / 64;  // full components per lane
+    double acc[FPL];
+    int fa[FPL], fb[FPL], fc[FPL];
+#pragma unroll
+    for (int k = 0; k < FPL; ++k) {
+        acc[k] = 0.0;
+        const int f = lane + 64 * k;
+        fa[k] = f < nf ? T.full[3 * f] : 0;
+        fb[k] = f < nf ? T.full[3 * f + 1] : 0;
+        fc[k] = f < nf ? T.full[3 * f + 2] : 0;
+    }
     const int b = start[c], e = start[c + 1];
-    const int s0 = lane, s1 = lane + 64;
-    const int t0b = s0 < nc ? T.p2m_start[s0] : 0, t0e = s0 < nc ? T.p2m_start[s0 + 1] : 0;
-    const int t1b = s1 < nc ? T.p2m_start[s1] : 0, t1e = s1 < nc ? T.p2m_start[s1 + 1] : 0;
-    for (int s = b; s < e; ++s) {
-        const double4 pt = P[s];
-        const double ux = (zx - pt.x) / h, uy = (zy - pt.y) / h, uz = (zz - pt.z) / h;
-        if (lane < 4 * (p + 1)) {
-            const int dim = lane / (p + 1), ex = lane % (p + 1);
-            const double base = dim == 0 ? ux : dim == 1 ? uy : dim == 2 ? uz : (ux * ux + uy * uy + uz * uz);
-            double v = 1.0;
-            for (int t = 0; t < ex; ++t) v *= base;
-            pw[dim][ex] = v;
+    for (int s0 = b; s0 < e; s0 += 64) {
+        const int cnt = min(64, e - s0);
+        if (lane < cnt) {
+            const double4 pt = P[s0 + lane];
+            const double u[3] = {(zx - pt.x) / h, (zy - pt.y) / h, (zz - pt.z) / h};
+            for (int dim = 0; dim < 3; ++dim) {
+                double v = 1.0;
+                for (int k = 0; k <= p; ++k) {
+                    pw[lane][dim][k] = v;
+                    v *= u[dim];
+                }
+            }
+            qs[lane] = pt.w;
         }
         __syncthreads();
-        double v0 = 0.0, v1 = 0.0;
-        for (int t = t0b; t < t0e; ++t) {
-            const int8_t* ex = T.p2m_exp + 4 * t;
-            v0 += T.p2m_coef[t] * pw[0][ex[0]] * pw[1][ex[1]] * pw[2][ex[2]] * pw[3][ex[3]];
+        for (int i = 0; i < cnt; ++i) {
+            const double q = qs[i];
+#pragma unroll
+            for (int k = 0; k < FPL; ++k) acc[k] += q * pw[i][0][fa[k]] * pw[i][1][fb[k]] * pw[i][2][fc[k]];
         }
-        for (int t = t1b; t < t1e; ++t) {
-            const int8_t* ex = T.p2m_exp + 4 * t;
-            v1 += T.p2m_coef[t] * pw[0][ex[0]] * pw[1][ex[1]] * pw[2][ex[2]] * pw[3][ex[3]];
-        }
-        acc0 += pt.w * v0;
-        acc1 += pt.w * v1;
         __syncthreads();
     }
-    double* Mc = M + (size_t)c * ldm_of(p);
-    if (s0 < ldm_of(p)) Mc[s0] = s0 < nc ? acc0 : 0.0;  // padding is kept zero
-    if (s1 < ldm_of(p)) Mc[s1] = s1 < nc ? acc1 : 0.0;
+#pragma unroll
+    for (int k = 0; k < FPL; ++k)
+        if (lane + 64 * k < nf) S[lane + 64 * k] = acc[k];
+    __syncthreads();
+    double* Mc = M + (size_t)c * ldm;
+    for (int n = lane; n < ldm; n += 64) {
+        double v = 0.0;
+        if (n < nc)
+            for (int t = T.det_start[n]; t < T.det_start[n + 1]; ++t) v += T.det_coef[t] * S[T.det_full[t]];
+        Mc[n] = v;  // padding is kept zero
+    }
 }
 
 void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M) {
@@ -131,32 +156,48 @@ void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const doubl
 
 // ------------------------------------------------------------------ M2M
 
-// parent M~ = sum over the 8 children o of A_o M~_child (Eq. M2M in scaled form)
-__global__ __launch_bounds__(128) void k_m2m(int p, const double* __restrict__ Mc, double* __restrict__ Mp,
-                                             const double* __restrict__ m2m_t) {
-    const uint32_t P = blockIdx.x;
+constexpr int SHIFT_NP = 8;  // parents per workgroup in M2M/L2L
+
+// parent M~ = sum over the 8 children o of A_o M~_child (Eq. M2M in scaled
+// form).  A_o[n][j] vanishes for rank(j) > rank(n) (the shift is exact and
+// rank-lowering), so row n only reads the first (rank(n)+1)^2 columns.  Each
+// matrix element is loaded once per SHIFT_NP parents.
+__global__ __launch_bounds__(128) void k_m2m(int p, long long nparents, const double* __restrict__ Mc,
+                                             double* __restrict__ Mp, const double* __restrict__ m2m_t) {
+    const long long P0 = (long long)blockIdx.x * SHIFT_NP;
     const int nc = (p + 1) * (p + 1);
-    __shared__ double ch[8 * NIND];
     const int ldm = ldm_of(p);
-    const double* src = Mc + (size_t)8 * P * ldm;
-    for (int t = threadIdx.x; t < 8 * nc; t += 128) ch[(t / nc) * NIND + (t % nc)] = src[(t / nc) * ldm + (t % nc)];
+    __shared__ double ch[SHIFT_NP][8][NIND];
+    const int np = (int)min((long long)SHIFT_NP, nparents - P0);
+    for (int t = threadIdx.x; t < np * 8 * nc; t += 128) {
+        const int pp = t / (8 * nc), r = t % (8 * nc), o = r / nc, j = r % nc;
+        ch[pp][o][j] = Mc[((size_t)(P0 + pp) * 8 + o) * ldm + j];
+    }
     __syncthreads();
-    const int n = threadIdx.x;
-    if (n < nc) {
-        double acc = 0.0;
-        for (int o = 0; o < 8; ++o) {
-            const double* A = m2m_t + (size_t)o * NIND * NIND;
-            for (int j = 0; j < nc; ++j) acc += A[(size_t)j * NIND + n] * ch[o * NIND + j];
+    for (int n = threadIdx.x; n < ldm; n += 128) {
+        double acc[SHIFT_NP];
+#pragma unroll
+        for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] = 0.0;
+        if (n < nc) {
+            const int r = rank_of(n);
+            const int jmax = (r + 1) * (r + 1);
+            for (int o = 0; o < 8; ++o) {
+                const double* A = m2m_t + (size_t)o * NIND * NIND;
+                for (int j = 0; j < jmax; ++j) {
+                    const double a = A[(size_t)j * NIND + n];
+#pragma unroll
+                    for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += a * ch[pp][o][j];
+                }
+            }
         }
-        Mp[(size_t)P * ldm + n] = acc;
-    } else if (n < ldm) {
-        Mp[(size_t)P * ldm + n] = 0.0;  // padding is kept zero
+        for (int pp = 0; pp < np; ++pp) Mp[(size_t)(P0 + pp) * ldm + n] = acc[pp];  // padding stays zero
     }
 }
 
 void launch_m2m(hipStream_t s, int p, int parent_level, const double* Mchild, double* Mparent, const DevTables& T) {
     const long long np = 1ll << (3 * parent_level);
-    hipLaunchKernelGGL(k_m2m, dim3((unsigned)np), dim3(128), 0, s, p, Mchild, Mparent, T.m2m_t);
+    hipLaunchKernelGGL(k_m2m, dim3((unsigned)((np + SHIFT_NP - 1) / SHIFT_NP)), dim3(128), 0, s, p, np, Mchild,
+                       Mparent, T.m2m_t);
 }
 
 // ------------------------------------------------------------------ M2L operators
@@ -179,12 +220,6 @@ void launch_offset_dtensors(hipStream_t s, int p, double* Dv) {
 #undef CASE
         default: break;
     }
-}
-
-__device__ inline int rank_of(int k) {
-    int r = 0;
-    while ((r + 1) * (r + 1) <= k) ++r;
-    return r;
 }
 
 // Kt[v][j][n] = K_v[n][j] = sum_i c[n,j,i] D_i(v)   (Eq. M2L, independent components)
@@ -212,27 +247,38 @@ void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, 
 
 // ------------------------------------------------------------------ L2L
 
-// child L~_o += B_o L~_parent (Eq. L2L in scaled form)
-__global__ __launch_bounds__(256) void k_l2l(int p, const double* __restrict__ Lp, double* __restrict__ Lc,
-                                             const double* __restrict__ l2l_t) {
-    const uint32_t P = blockIdx.x;
+// child L~_o += B_o L~_parent (Eq. L2L in scaled form).  B_o[n][j] vanishes
+// for rank(j) < rank(n), so row n reads columns from rank(n)^2 on.  Each
+// matrix element is loaded once per SHIFT_NP parents.
+__global__ __launch_bounds__(256) void k_l2l(int p, long long nparents, const double* __restrict__ Lp,
+                                             double* __restrict__ Lc, const double* __restrict__ l2l_t) {
+    const long long P0 = (long long)blockIdx.x * SHIFT_NP;
     const int nc = (p + 1) * (p + 1);
-    __shared__ double lp[NIND];
     const int ldm = ldm_of(p);
-    for (int t = threadIdx.x; t < nc; t += 256) lp[t] = Lp[(size_t)P * ldm + t];
+    __shared__ double lp[SHIFT_NP][NIND];
+    const int np = (int)min((long long)SHIFT_NP, nparents - P0);
+    for (int t = threadIdx.x; t < np * nc; t += 256) lp[t / nc][t % nc] = Lp[(size_t)(P0 + t / nc) * ldm + t % nc];
     __syncthreads();
     for (int t = threadIdx.x; t < 8 * nc; t += 256) {
         const int o = t / nc, n = t % nc;
         const double* B = l2l_t + (size_t)o * NIND * NIND;
-        double acc = 0.0;
-        for (int j = 0; j < nc; ++j) acc += B[(size_t)j * NIND + n] * lp[j];
-        Lc[((size_t)8 * P + o) * ldm + n] += acc;
+        double acc[SHIFT_NP];
+#pragma unroll
+        for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] = 0.0;
+        const int r = rank_of(n);
+        for (int j = r * r; j < nc; ++j) {
+            const double bcoef = B[(size_t)j * NIND + n];
+#pragma unroll
+            for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += bcoef * lp[pp][j];
+        }
+        for (int pp = 0; pp < np; ++pp) Lc[((size_t)(P0 + pp) * 8 + o) * ldm + n] += acc[pp];
     }
 }
 
 void launch_l2l(hipStream_t s, int p, int parent_level, const double* Lparent, double* Lchild, const DevTables& T) {
     const long long np = 1ll << (3 * parent_level);
-    hipLaunchKernelGGL(k_l2l, dim3((unsigned)np), dim3(256), 0, s, p, Lparent, Lchild, T.l2l_t);
+    hipLaunchKernelGGL(k_l2l, dim3((unsigned)((np + SHIFT_NP - 1) / SHIFT_NP)), dim3(256), 0, s, p, np, Lparent,
+                       Lchild, T.l2l_t);
 }
 
 // ------------------------------------------------------------------ L2P + P2P
@@ -243,12 +289,21 @@ __host__ __device__ constexpr int full_slot(int a, int b, int c) {
     return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
 }
 
+// 1/sqrt(r2) in FP64: the hardware reciprocal square root refined by two
+// Newton steps y <- y (3 - r2 y^2)/2 (quadratic convergence to FP64 rounding)
+__device__ inline double rsqrt64(double r2) {
+    double y = __builtin_amdgcn_rsq(r2);
+    y = y * (1.5 - 0.5 * r2 * y * y);
+    y = y * (1.5 - 0.5 * r2 * y * y);
+    return y;
+}
+
 __device__ inline void pair_add(double xb, double yb, double zb, double4 src, double& f, double& gx, double& gy,
                                 double& gz) {
     const double dx = xb - src.x, dy = yb - src.y, dz = zb - src.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 == 0.0) return;
-    const double ir = 1.0 / sqrt(r2);
+    if (r2 == 0.0) return;  // coincident pair: contributes nothing
+    const double ir = rsqrt64(r2);
     f += src.w * ir;
     const double ir3 = src.w * ir * ir * ir;
     gx -= ir3 * dx;
@@ -256,78 +311,43 @@ __device__ inline void pair_add(double xb, double yb, double zb, double4 src, do
     gz -= ir3 * dz;
 }
 
-// L2P (Eq. L2P): one workgroup per leaf.  The leaf's local expansion is
-// expanded to full components divided by n! in LDS, together with the
-// coefficient arrays of its three first derivatives; each particle then
-// evaluates the four degree-p polynomials at r = (x - z)/h by nested Horner
-// steps in x, y and z.  Results (far field, sorted order) go to F[s].
-template <int P>
-__global__ __launch_bounds__(64) void k_l2p(Box box, const int32_t* __restrict__ start, const double4* __restrict__ Pt,
-                                            const double* __restrict__ L, DevTables T, double4* __restrict__ F) {
-    constexpr int NC = (P + 1) * (P + 1);
-    constexpr int NF = (P + 1) * (P + 2) * (P + 3) / 6;
-    const uint32_t c = blockIdx.x;
-    const int b0 = start[c], e0 = start[c + 1];
-    if (b0 == e0) return;  // uniform across the workgroup
-    const int d = box.depth;
-    const double h = box.side / (double)(1 << d);
-    const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
-    const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
-    const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
-    __shared__ double W[4][NF];  // potential, d/dx, d/dy, d/dz coefficients
-    const double* Lc = L + (size_t)c * ldm_of(P);
-    for (int f = threadIdx.x; f < NF; f += 64) {
-        double v = 0.0;
-        for (int t = T.exp_start[f]; t < T.exp_start[f + 1]; ++t) v += (double)T.exp_coef[t] * Lc[T.exp_slot[t]];
-        W[0][f] = v * T.inv_mfact[f];
-    }
-    __syncthreads();
-    for (int f = threadIdx.x; f < NF; f += 64) {
-        const int a = T.full[3 * f], b = T.full[3 * f + 1], cc = T.full[3 * f + 2];
-        const bool inner = a + b + cc < P;
-        W[1][f] = inner ? (double)(a + 1) * W[0][full_slot(a + 1, b, cc)] : 0.0;
-        W[2][f] = inner ? (double)(b + 1) * W[0][full_slot(a, b + 1, cc)] : 0.0;
-        W[3][f] = inner ? (double)(cc + 1) * W[0][full_slot(a, b, cc + 1)] : 0.0;
-    }
-    __syncthreads();
-    for (int s = b0 + threadIdx.x; s < e0; s += 64) {
-        const double4 pt = Pt[s];
-        const double rx = (pt.x - zx) / h, ry = (pt.y - zy) / h, rz = (pt.z - zz) / h;
-        double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
-        for (int cz = P; cz >= 0; --cz) {
-            double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
-            for (int by = P - cz; by >= 0; --by) {
-                double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
-                for (int ax = P - by - cz; ax >= 0; --ax) {
-                    const int sl = full_slot(ax, by, cz);
-                    x0 = x0 * rx + W[0][sl];
-                    x1 = x1 * rx + W[1][sl];
-                    x2 = x2 * rx + W[2][sl];
-                    x3 = x3 * rx + W[3][sl];
-                }
-                y0 = y0 * ry + x0;
-                y1 = y1 * ry + x1;
-                y2 = y2 * ry + x2;
-                y3 = y3 * ry + x3;
-            }
-            f0 = f0 * rz + y0;
-            f1 = f1 * rz + y1;
-            f2 = f2 * rz + y2;
-            f3 = f3 * rz + y3;
-        }
-        const double ih2 = 1.0 / (h * h);
-        F[s] = make_double4(f0 / h, f1 * ih2, f2 * ih2, f3 * ih2);
-    }
+// hardware dispatches workgroups round-robin over the 8 XCDs (each with its
+// own L2); give every XCD a contiguous range of the work instead
+__device__ inline long long xcd_remap(long long b, long long nb) {
+    if (nb % 8) return b;
+    return (b % 8) * (nb / 8) + b / 8;
 }
 
-// P2P: one thread per (sorted) target particle; sources are the particles
-// of the 27 adjacent-or-equal leaves (Appendix C near field), self excluded.
-// Adds the far field F[s] (if given) and writes the outputs in input order.
+// L2P: one thread per (sorted) particle; the generated straight-line L2P
+// (Eq. L2P: potential and gradient of the degree-p local polynomial at
+// r = (x - z)/h) from its leaf's independent coefficients.  F[s] = far field.
+template <int P>
+__global__ __launch_bounds__(256) void k_l2p(int n, Box box, const uint32_t* __restrict__ keys,
+                                             const double4* __restrict__ Pt, const double* __restrict__ L,
+                                             double4* __restrict__ F) {
+    const long long s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int n1 = 1 << box.depth;
+    const double h = box.side / (double)n1;
+    const uint32_t key = keys[s];
+    const double4 pt = Pt[s];
+    const double zx = box.lo[0] + ((double)compact3(key) + 0.5) * h;
+    const double zy = box.lo[1] + ((double)compact3(key >> 1) + 0.5) * h;
+    const double zz = box.lo[2] + ((double)compact3(key >> 2) + 0.5) * h;
+    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    gen_l2p<P>((pt.x - zx) / h, (pt.y - zy) / h, (pt.z - zz) / h, L + (size_t)key * ldm_of(P), f, gx, gy, gz);
+    const double ih2 = 1.0 / (h * h);
+    F[s] = make_double4(f / h, gx * ih2, gy * ih2, gz * ih2);
+}
+
+// P2P: one thread per (sorted) target; sources are the particles of the 27
+// adjacent-or-equal leaves, self excluded (Appendix C near field).  Adds the
+// far field F[s] if given and writes the outputs in input order.
 __global__ __launch_bounds__(256) void k_p2p(int n, Box box, const uint32_t* __restrict__ keys,
                                              const int32_t* __restrict__ start, const double4* __restrict__ Pt,
                                              const int32_t* __restrict__ idx, const double4* __restrict__ F,
                                              double* __restrict__ phi, double* __restrict__ grad) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int n1 = 1 << box.depth;
     const uint32_t key = keys[s];
@@ -365,14 +385,12 @@ __global__ __launch_bounds__(256) void k_p2p(int n, Box box, const uint32_t* __r
     }
 }
 
-void launch_l2p(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const double* L,
-                const DevTables& T, double4* F) {
-    const long long nleaves = 1ll << (3 * box.depth);
+void launch_l2p(hipStream_t s, int p, int n, Box box, const uint32_t* keys, const double4* P, const double* L,
+                double4* F) {
+    if (n <= 0) return;
+    const dim3 grid(cdiv(n, 256)), blk(256);
     switch (p) {
-#define CASE(PP)                                                                                              \
-    case PP:                                                                                                  \
-        hipLaunchKernelGGL(k_l2p<PP>, dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, L, T, F); \
-        break;
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_l2p<PP>, grid, blk, 0, s, n, box, keys, P, L, F); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;
@@ -543,14 +561,16 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
     constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB;
     constexpr int KU = S::KBYTES / 16;        // 16-byte units of one K_v
     constexpr int RU = S::BROW / 16;          // 16-byte units of one source row
-    constexpr int BU = 64 * RU;               // units of the 64 source rows
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     unsigned char* Kb = lds;                              // [KBUF][KBYTES]
     unsigned char* Bb = lds + S::KBUF * S::KBYTES;        // [2][64 rows][BROW]
     __shared__ int tco[64];                               // packed target coords, -1 = none
 
-    const int o = blockIdx.x & 7;
-    const int pb = blockIdx.x >> 3;
+    // work item = 8 * parent block + target octant; each XCD takes a contiguous
+    // range, so the 8 octants of a block and neighbouring blocks share its L2
+    const long long work = xcd_remap(blockIdx.x, gridDim.x);
+    const int o = (int)(work & 7);
+    const long long pb = work >> 3;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int n1 = 1 << level;
@@ -576,23 +596,35 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
             if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
         }
     };
-    auto stage_b = [&](int iv, int buf) {
+    // source rows of offset iv: lane = target slot (each wave computes all 64),
+    // then every copy instruction moves whole rows whose address is read with
+    // readlane (wave-uniform), so the per-lane work is one add
+    auto src_rows = [&](int iv) -> int {
         const int vs = offlist[o * 189 + iv];
         const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
+        const int tc = tco[lane];
+        int row = -1;
+        if (tc >= 0) {
+            const int sx = (tc & 1023) + vx, sy = ((tc >> 10) & 1023) + vy, sz = (tc >> 20) + vz;
+            if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1) row = (int)morton3(sx, sy, sz);
+        }
+        return row;
+    };
+    auto stage_b = [&](int iv, int buf) {
+        const int myrow = src_rows(iv);
         unsigned char* dst = Bb + buf * S::BBYTES;
-        for (int i = w; i * 64 < BU; i += 4) {
-            const int u = i * 64 + lane;
-            if (u < BU) {
-                const int slot = u / RU, ru = u % RU;
-                const int tc = tco[slot];
-                const unsigned char* g = zero_row + ru * 16;
-                if (tc >= 0) {
-                    const int sx = (tc & 1023) + vx, sy = ((tc >> 10) & 1023) + vy, sz = (tc >> 20) + vz;
-                    if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1)
-                        g = reinterpret_cast<const unsigned char*>(Msrc) + (size_t)morton3(sx, sy, sz) * S::BROW +
-                            ru * 16;
-                }
-                lds_copy16(g, dst + i * 1024);
+        const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
+        // RPI rows per copy instruction (RU units each); RPI = 1 unless RU divides 64
+        constexpr int RPI = (RU <= 64 && 64 % RU == 0) ? 64 / RU : 1;
+        constexpr int NI = 64 / RPI;
+        for (int i = w; i < NI; i += 4) {
+            int row;
+            if (RPI == 1) row = __builtin_amdgcn_readlane(myrow, i);
+            else row = __shfl(myrow, i * RPI + lane / RU);
+            if (lane < RPI * RU) {
+                const int ul = lane % RU;
+                const unsigned char* g = row >= 0 ? Mb + (size_t)row * S::BROW + ul * 16 : zero_row + ul * 16;
+                lds_copy16(g, dst + (size_t)i * RPI * S::BROW);
             }
         }
     };
@@ -724,6 +756,172 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
     }
 }
 
+// ------------------------------------------------------------------ FP32 halo M2L
+//
+// Same work unit (target octant o, 4x4x4 parent block), reorganised around
+// the sources: for each source octant q the 6x6x6 halo of octant-q cells
+// around the block (parents base-1 .. base+4) is staged in LDS once, and the
+// 27 parent offsets u (v = 2u + q - o, the adjacent ones skipped) are all
+// served from it; only K_v streams per offset, double-buffered in LDS.  189
+// offsets cost 8 halo stagings instead of 189 source stagings.
+template <int P>
+struct Halo32 {
+    using T = Tile<P, PREC_F32>;
+    static constexpr int U = T::S32 / 4;           // 16-byte units per row
+    // rows padded by 16 bytes so consecutive rows start on other banks (a
+    // rotation of the units within each row, conflict-free, measured slower:
+    // its per-read address arithmetic costs more than the 2-way conflicts)
+    static constexpr int HROWB = T::S32 * 4 + 16;
+    static constexpr int HBYTES = 216 * HROWB;
+    static constexpr int NKB = 2;  // a third buffer (prefetch distance 2) measured slower
+    static constexpr int LDS = HBYTES + NKB * T::KBYTES;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __restrict__ M32, double* __restrict__ L,
+                                                    const unsigned char* __restrict__ Kpk,
+                                                    const int16_t* __restrict__ hlist,
+                                                    const unsigned char* __restrict__ zero_row) {
+    using S = Tile<P, PREC_F32>;
+    using H = Halo32<P>;
+    constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB, U = H::U, NKB = H::NKB, KD = NKB - 1;
+    constexpr int KU = S::KBYTES / 16;
+    constexpr int KI = (KU + 63) / 64;             // copy instructions per K_v (over the 4 waves)
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    unsigned char* Hb = lds;                       // [216][S32] floats, units rotated
+    unsigned char* Kb = lds + H::HBYTES;           // [NKB][KBYTES]
+
+    const long long work = xcd_remap(blockIdx.x, gridDim.x);
+    const int o = (int)(work & 7);
+    const long long pb = work >> 3;
+    // 4 waves: wave w owns target tile w and every row tile
+    constexpr int NW = 4;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int tt = w;
+    const int np1 = 1 << (level - 1);              // parents per dimension
+    const long long nparents = (long long)np1 * np1 * np1;
+    const uint32_t base_m = (uint32_t)(pb * 64);
+    const int bx = (int)compact3(base_m), by = (int)compact3(base_m >> 1), bz = (int)compact3(base_m >> 2);
+    const int tloc = tt * 16 + (lane & 15);        // this lane's target slot in the block
+    const int tx = (int)compact3((uint32_t)tloc), ty = (int)compact3((uint32_t)tloc >> 1),
+              tz = (int)compact3((uint32_t)tloc >> 2);
+    const int kq = lane >> 4;
+    // hlist[o][i] = (q << 5 | u) of the i-th offset, hlist[8*189 + o*189 + i] = K slot of r = -v
+    const int16_t* qu_list = hlist + o * 189;
+    const int16_t* ks_list = hlist + 8 * 189 + o * 189;
+
+    auto stage_k = [&](int vslot, int buf) {
+        const unsigned char* src = Kpk + (size_t)vslot * S::KBYTES;
+        unsigned char* dst = Kb + buf * S::KBYTES;
+        for (int i = w; i < KI; i += NW) {
+            const int u = i * 64 + lane;
+            if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
+        }
+    };
+    auto stage_halo = [&](int q) {
+        int myrow[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = lane + 64 * k;
+            int row = -1;
+            if (r < 216) {
+                const int px = bx - 1 + r % 6, py = by - 1 + (r / 6) % 6, pz = bz - 1 + r / 36;
+                if (px >= 0 && py >= 0 && pz >= 0 && px < np1 && py < np1 && pz < np1)
+                    row = (int)morton3(2 * px + (q & 1), 2 * py + ((q >> 1) & 1), 2 * pz + ((q >> 2) & 1));
+            }
+            myrow[k] = row;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            for (int i = w; i < 64 && 64 * k + i < 216; i += NW) {
+                const int h = 64 * k + i;
+                const int row = __builtin_amdgcn_readlane(myrow[k], i);
+                if (lane < U) {
+                    const unsigned char* g = row >= 0 ? reinterpret_cast<const unsigned char*>(M32) +
+                                                            (size_t)row * S::S32 * 4 + lane * 16
+                                                      : zero_row + lane * 16;
+                    lds_copy16(g, Hb + (size_t)h * H::HROWB);
+                }
+            }
+        }
+    };
+
+    v4f acc[R][2];
+    v4f acc0[4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc0[k] = v4f{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int j = 0; j < KD; ++j) stage_k(ks_list[j], j);
+    int qcur = -1;
+    for (int iv = 0; iv < 189; ++iv) {
+        const int qu = qu_list[iv];
+        const int q = qu >> 5, u = qu & 31;
+        if (q != qcur) {
+            __syncthreads();  // every wave is done with the previous halo
+            stage_halo(q);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            qcur = q;
+        }
+        // buffer (iv+KD) % NKB was last read at offset iv-1 (followed by a barrier)
+        if (iv + KD < 189) stage_k(ks_list[iv + KD], (iv + KD) % NKB);
+        const float* Kf = reinterpret_cast<const float*>(Kb + (iv % NKB) * S::KBYTES);
+        const int ux = u % 3 - 1, uy = (u / 3) % 3 - 1, uz = u / 9 - 1;
+        const int h = (tx + 1 + ux) + 6 * (ty + 1 + uy) + 36 * (tz + 1 + uz);
+        const float* Bf = reinterpret_cast<const float*>(Hb + (size_t)h * H::HROWB);
+        // row tile 0 (the longest: all columns) runs on four accumulator chains
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const float b = Bf[4 * c + kq];
+            acc0[c & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kf[c * 64 + lane], b, acc0[c & 3], 0, 0, 0);
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                if (c < S::nch(r)) {
+                    const float a = Kf[(S::cb(r) + c) * 64 + lane];
+                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r][c & 1], 0, 0, 0);
+                }
+        }
+        // K of offset iv+1 must have landed; K of iv+KD (just issued) may stay in flight
+        __builtin_amdgcn_s_waitcnt(0);  // K of offset iv+1 has landed
+        __syncthreads();
+    }
+    const long long par = pb * 64 + tloc;
+    if (par >= nparents) return;
+    double* Lt = L + (size_t)(par * 8 + o) * LDM;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        // FP32 16x16 accumulator: element j holds row 16r + 4*(lane/16) + j
+        const int row0 = 16 * r + 4 * (lane >> 4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double v = r == 0 ? ((double)acc0[0][j] + (double)acc0[1][j]) + ((double)acc0[2][j] + (double)acc0[3][j])
+                                    : (double)acc[r][0][j] + (double)acc[r][1][j];
+            if (row0 + j < NC) Lt[row0 + j] = v;
+        }
+    }
+}
+
+template <int P>
+hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L, const unsigned char* Kpk,
+                           const int16_t* hlist, const unsigned char* zero_row) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_halo32<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           Halo32<P>::LDS);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const long long nparents = 1ll << (3 * (level - 1));
+    const long long nblk = (nparents + 63) / 64;
+    hipLaunchKernelGGL(k_m2l_halo32<P>, dim3((unsigned)(8 * nblk)), dim3(256), Halo32<P>::LDS, s, level, M32, L, Kpk,
+                       hlist, zero_row);
+    return hipGetLastError();
+}
+
 template <int P, int PREC>
 hipError_t m2l_tile_impl(hipStream_t s, int level, const void* Msrc, double* L, const unsigned char* Kpk,
                          const int16_t* offlist, const unsigned char* zero_row) {
@@ -768,8 +966,15 @@ size_t m2l_packed_bytes(int p, int prec) {
 }
 
 size_t m2l_lds_bytes(int p, int prec) {
-    return prec == PREC_F64 ? tile_query<PREC_F64>(p, 1) : prec == PREC_F32 ? tile_query<PREC_F32>(p, 1)
-                                                                            : tile_query<PREC_BF16X3>(p, 1);
+    if (prec == PREC_F32) {
+        switch (p) {
+#define CASE(PP) case PP: return (size_t)Halo32<PP>::LDS;
+            CTFMM_P_CASES(CASE)
+#undef CASE
+            default: return 0;
+        }
+    }
+    return prec == PREC_F64 ? tile_query<PREC_F64>(p, 1) : tile_query<PREC_BF16X3>(p, 1);
 }
 
 void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk) {
@@ -798,7 +1003,7 @@ hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msr
 #define CASE(PP)                                                                                           \
     case PP:                                                                                               \
         if (prec == PREC_F64) return m2l_tile_impl<PP, PREC_F64>(s, level, Msrc, L, Kpk, offlist, zero_row); \
-        if (prec == PREC_F32) return m2l_tile_impl<PP, PREC_F32>(s, level, Msrc, L, Kpk, offlist, zero_row); \
+        if (prec == PREC_F32) return m2l_halo32_impl<PP>(s, level, (const float*)Msrc, L, Kpk, offlist, zero_row); \
         return m2l_tile_impl<PP, PREC_BF16X3>(s, level, Msrc, L, Kpk, offlist, zero_row);
         CTFMM_P_CASES(CASE)
 #undef CASE

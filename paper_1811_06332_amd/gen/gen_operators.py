@@ -320,6 +320,54 @@ def _c(e):
     return rec(sp.sympify(e))
 
 
+# ---------------------------------------------------------- straight-line L2P
+
+def l2p_code(p):
+    """Straight-line L2P (Eq. L2P) for order p: with r = (x - z)/h and the
+    independent scaled local coefficients Lt[j],
+        f  = sum_{|n|<=p}   r^n/n! L_n,        g_i = sum_{|n|<=p-1} r^n/n! L_{n+e_i},
+    where each full component L_n is expanded into independent ones.  The
+    monomials are built incrementally (z outer, y middle, x inner), so every
+    product is computed once; coefficients are exact rationals rounded once."""
+    lines = []
+    for v in "xyz":
+        lines.append(f"double {v}0 = 1.0;")
+        for k in range(1, p + 1):
+            lines.append(f"const double {v}{k} = {v}{k - 1} * {v};")
+    acc = {"f": [], "gx": [], "gy": [], "gz": []}
+
+    def combo(m, mult):
+        e = expand(m)
+        terms = []
+        for j, cj in sorted(e.items()):
+            c = Fraction(cj * mult, mfact(m) if False else 1)
+            terms.append((j, c))
+        return terms
+
+    nterms = 0
+    out = []
+    for c in range(p + 1):
+        for b in range(p + 1 - c):
+            out.append(f"{{ const double* Lg = gen_launder(L); const double yz = y{b} * z{c};")
+            for a in range(p + 1 - b - c):
+                n = (a, b, c)
+                inv = Fraction(1, mfact(n))
+                out.append(f"  {{ const double m = x{a} * yz;")
+                # potential coefficient: L_n / n!
+                t = [(j, inv * cj) for j, cj in sorted(expand(n).items())]
+                out.append("    f += m * (" + " + ".join(f"({float(cf)!r}) * LD({j})" for j, cf in t) + ");")
+                nterms += len(t)
+                if a + b + c < p:
+                    for nm, e in (("gx", (1, 0, 0)), ("gy", (0, 1, 0)), ("gz", (0, 0, 1))):
+                        n2 = (a + e[0], b + e[1], c + e[2])
+                        t = [(j, inv * cj) for j, cj in sorted(expand(n2).items())]
+                        out.append(f"    {nm} += m * (" + " + ".join(f"({float(cf)!r}) * LD({j})" for j, cf in t) + ");")
+                        nterms += len(t)
+                out.append("  }")
+            out.append("__builtin_amdgcn_sched_barrier(0); }")
+    return lines + out, nterms
+
+
 # ------------------------------------------------------------------ emit
 
 def _hexf(v):
@@ -392,6 +440,17 @@ def emit(outdir):
     w("static const unsigned char GEN_C_COUNT[GEN_NIND][GEN_NIND] = {" + ",".join("{" + ",".join(map(str, r)) + "}" for r in ccount) + "};")
     w(f"static const unsigned char GEN_C_SLOT[{len(ii)}] = {{" + ",".join(map(str, ii)) + "};")
     w(f"static const double GEN_C_COEF[{len(cc)}] = {{" + ",".join(cc) + "};")
+    # detracer rows: independent n <- full f (P2M from monomial moments)
+    starts, fs, cs = [0], [], []
+    for row in DET:
+        for f in sorted(row):
+            fs.append(f); cs.append(_hexf(row[f]))
+        starts.append(len(fs))
+    w("// P2M: M~_n = sum_{t in [DET_START[n], DET_START[n+1])} DET_COEF[t] * S_{DET_FULL[t]},")
+    w("// S_f = sum_a q_a u_a^f the full monomial moments (Eq. P2M, Eq. Detracer / (2n-1)!!)")
+    w(f"static const short GEN_DET_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
+    w(f"static const short GEN_DET_FULL[{len(fs)}] = {{" + ",".join(map(str, fs)) + "};")
+    w(f"static const double GEN_DET_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
     # inverse factorials of full components (L2P)
     w("// 1/n! for full slots (L2P weights)")
     w("static const double GEN_INV_MFACT[GEN_NFULL] = {" + ",".join(_hexf(Fraction(1, mfact(m))) for m in FULL) + "};")
@@ -407,6 +466,29 @@ def emit(outdir):
         for ln in lines:
             w("  " + ln)
         w("}")
+    w("// Each (y, z) group of the generated L2P reads the coefficients through a")
+    w("// laundered copy of the pointer, so the compiler reloads them per group")
+    w("// (L1 hits) instead of keeping every coefficient live across the function.")
+    w("__device__ __forceinline__ const double* gen_launder(const double* p) {")
+    w("  unsigned long long a = (unsigned long long)p;")
+    w('  __asm__ volatile("" : "+v"(a));')
+    w("  return (const double*)a;")
+    w("}")
+    w("#define LD(j) (Lg[(j)])")
+    for p in range(PMAX + 1):
+        lines, nt = l2p_code(p)
+        w(f"// L2P at order {p}: potential and gradient polynomials in r = (x - z)/h, {nt} coefficient terms")
+        w(f"__device__ static inline void gen_l2p_p{p}(double x, double y, double z, const double* __restrict__ L,")
+        w("                                          double& f, double& gx, double& gy, double& gz) {")
+        for ln in lines:
+            w("  " + ln)
+        w("}")
+    w("#undef LD")
+    w("template <int P> __device__ inline void gen_l2p(double x, double y, double z, const double* L, double& f,")
+    w("                                            double& gx, double& gy, double& gz);")
+    for p in range(PMAX + 1):
+        w(f"template <> __device__ inline void gen_l2p<{p}>(double x, double y, double z, const double* L, double& f, "
+          f"double& gx, double& gy, double& gz) {{ gen_l2p_p{p}(x, y, z, L, f, gx, gy, gz); }}")
     w("template <int P> __host__ __device__ inline void gen_dtensor(double x, double y, double z, double* D);")
     for p in range(PMAX + 1):
         w(f"template <> __host__ __device__ inline void gen_dtensor<{p}>(double x, double y, double z, double* D) {{ gen_dtensor_p{p}(x, y, z, D); }}")
