@@ -61,6 +61,10 @@ def _lib():
                                          _dp, _dp, C.c_void_p, C.c_void_p, i32]
         L.oracle_fmm_uniform.restype = i32
         L.oracle_max_threads.restype = i32
+        L.oracle_fmm_adaptive.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
+                                          C.c_void_p, C.c_void_p, i32]
+        L.oracle_fmm_adaptive.restype = i32
+        L.oracle_auto_root.argtypes = [i64, _dp, _dp, C.c_void_p]
         _lib_handle = L
     return _lib_handle
 
@@ -204,6 +208,43 @@ def fmm_uniform(xyz, q, p, depth, lo=(0.0, 0.0, 0.0), side=1.0, targets=None,
         Ls.append(Ld[off:off + c].reshape(8 ** l, nf))
         off += c
     return phi, grad, Ms, Ls
+
+
+def auto_root(xyz):
+    """The automatic root cube of the adaptive tree: (lo[3], side)."""
+    xyz = _vec(xyz).reshape(-1, 3)
+    lo = np.zeros(3); side = np.zeros(1)
+    _lib().oracle_auto_root(xyz.shape[0], np.ascontiguousarray(xyz.ravel()), lo, side.ctypes.data)
+    return lo, float(side[0])
+
+
+def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=0, stats=False):
+    """Full FMM on the adaptive octree (see oracle_fmm_adaptive).  lo/side
+    None/0 selects the automatic root cube.  With stats=True also returns a
+    dict of tree and list sizes and the root box."""
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
+    n = xyz.shape[0]
+    if targets is None:
+        nt, tp, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt, tp = keep.size, keep.ctypes.data
+    phi = np.zeros(nt); grad = np.zeros(3 * nt)
+    st = np.zeros(8, dtype=np.int64); root = np.zeros(4)
+    lo_arr = _vec(lo if lo is not None else (0.0, 0.0, 0.0), 3)
+    rc = _lib().oracle_fmm_adaptive(n, np.ascontiguousarray(xyz.ravel()), q, p, leaf_max, lo_arr,
+                                    float(side) if lo is not None else 0.0, nt, tp, phi, grad,
+                                    st.ctypes.data, root.ctypes.data, nthreads)
+    del keep
+    if rc != 0:
+        raise RuntimeError(f"oracle_fmm_adaptive failed with code {rc}")
+    grad = grad.reshape(-1, 3)
+    if not stats:
+        return phi, grad
+    names = ["nodes", "leaves", "max_level", "V", "U", "W", "X"]
+    info = {k: int(v) for k, v in zip(names, st[:7])}
+    info["root_lo"] = root[:3].copy(); info["root_side"] = float(root[3])
+    return phi, grad, info
 
 
 def max_threads() -> int:

@@ -665,3 +665,420 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* ========================================================== adaptive octree */
+/*
+ * Adaptive octree over a cube (Appendix C recommends splitting geometrically
+ * at the cell centre for inhomogeneous distributions): a node holding more
+ * than leaf_max particles is split into its non-empty octants, down to level
+ * OA_DMAX.  Interactions follow the classic adaptive FMM lists, every one
+ * evaluated with the paper's operators:
+ *   V(B): children of the same-level neighbours of parent(B) that are not
+ *         adjacent to B                          -> M2L (Eq. M2L)
+ *   U(B), B a leaf: leaves adjacent to B (B too) -> P2P (Eq. PhiAB)
+ *   W(B), B a leaf: descendants of B's same-level neighbours that are not
+ *         adjacent to B while their parent is    -> multipole evaluated at
+ *         B's particles: M2L to the particle, then its rank-0/1 components
+ *   X(B): the leaves C with B in W(C)            -> local expansion of C's
+ *         particles about B: M2L of a single-charge multipole
+ * "Adjacent" means the closed cubes touch or overlap.  Expansion centres are
+ * the geometric cell centres.
+ */
+#define OA_DMAX 21
+
+typedef struct {
+    int level;
+    uint64_t pre;      /* Morton prefix of the node at its level */
+    int64_t b, e;      /* sorted particle range */
+    int parent;
+    int child[8];      /* node index or -1 */
+    int leaf;
+    int64_t ix, iy, iz; /* integer coordinates at its level */
+} oanode;
+
+typedef struct {
+    int *v;
+    int n, cap;
+} ivec;
+
+static void ivec_push(ivec *a, int x)
+{
+    if (a->n == a->cap) {
+        a->cap = a->cap ? 2 * a->cap : 8;
+        a->v = (int *)realloc(a->v, (size_t)a->cap * sizeof(int));
+    }
+    a->v[a->n++] = x;
+}
+
+static uint64_t oa_spread(uint64_t v)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < OA_DMAX; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+    return r;
+}
+
+typedef struct {
+    int p, leaf_max;
+    double lo[3], side;
+    int64_t n;
+    const double *xyz, *q;
+    int64_t *order;    /* particles sorted by key (ties by index) */
+    uint64_t *key;     /* key of sorted position */
+    oanode *nd;
+    int nn, ncap;
+    int maxlev;
+    int *lev_start;    /* nodes grouped per level: indices lev_list[lev_start[l] .. lev_start[l+1]) */
+    int *lev_list;
+    int64_t *leaf_of;  /* particle -> leaf node */
+    ivec *U, *V, *W, *X;
+    double **M, **L;   /* per node, full storage */
+    int nf;
+} oatree;
+
+static const oatree *g_sort_tree;
+static int cmp_key(const void *a, const void *b)
+{
+    const int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
+    uint64_t ka = g_sort_tree->key[ia], kb = g_sort_tree->key[ib];
+    if (ka != kb) return ka < kb ? -1 : 1;
+    return ia < ib ? -1 : (ia > ib);
+}
+
+static int oa_new_node(oatree *T, int level, uint64_t pre, int64_t b, int64_t e, int parent)
+{
+    if (T->nn == T->ncap) {
+        T->ncap = T->ncap ? 2 * T->ncap : 1024;
+        T->nd = (oanode *)realloc(T->nd, (size_t)T->ncap * sizeof(oanode));
+    }
+    oanode *x = &T->nd[T->nn];
+    x->level = level; x->pre = pre; x->b = b; x->e = e; x->parent = parent; x->leaf = 1;
+    for (int o = 0; o < 8; ++o) x->child[o] = -1;
+    int64_t ix = 0, iy = 0, iz = 0;
+    for (int l = 0; l < level; ++l) {
+        ix |= (int64_t)((pre >> (3 * l)) & 1) << l;
+        iy |= (int64_t)((pre >> (3 * l + 1)) & 1) << l;
+        iz |= (int64_t)((pre >> (3 * l + 2)) & 1) << l;
+    }
+    x->ix = ix; x->iy = iy; x->iz = iz;
+    if (level > T->maxlev) T->maxlev = level;
+    return T->nn++;
+}
+
+static void oa_split(oatree *T, int node)
+{
+    oanode nd = T->nd[node];
+    if (nd.e - nd.b <= T->leaf_max || nd.level >= OA_DMAX) return;
+    T->nd[node].leaf = 0;
+    int sh = 3 * (OA_DMAX - nd.level - 1);
+    int64_t s = nd.b;
+    for (int o = 0; o < 8; ++o) {
+        uint64_t cpre = nd.pre * 8 + (uint64_t)o;
+        int64_t e = s;
+        while (e < nd.e && (T->key[e] >> sh) == cpre) ++e;
+        if (e > s) {
+            int c = oa_new_node(T, nd.level + 1, cpre, s, e, node);
+            T->nd[node].child[o] = c;
+            oa_split(T, c);
+        }
+        s = e;
+    }
+}
+
+/* closed cubes of nodes A and B touch or overlap */
+static int oa_adjacent(const oanode *A, const oanode *B)
+{
+    int sa = OA_DMAX - A->level, sb = OA_DMAX - B->level;
+    int64_t ca[3] = {A->ix, A->iy, A->iz}, cb[3] = {B->ix, B->iy, B->iz};
+    for (int d = 0; d < 3; ++d) {
+        int64_t alo = ca[d] << sa, ahi = (ca[d] + 1) << sa;
+        int64_t blo = cb[d] << sb, bhi = (cb[d] + 1) << sb;
+        if (alo > bhi || blo > ahi) return 0;
+    }
+    return 1;
+}
+
+/* node at (level, ix, iy, iz) or -1 */
+static int oa_find(const oatree *T, int level, int64_t ix, int64_t iy, int64_t iz)
+{
+    int64_t n1 = (int64_t)1 << level;
+    if (ix < 0 || iy < 0 || iz < 0 || ix >= n1 || iy >= n1 || iz >= n1) return -1;
+    int cur = 0;
+    for (int l = 1; l <= level; ++l) {
+        int sh = level - l;
+        int o = (int)(((ix >> sh) & 1) | (((iy >> sh) & 1) << 1) | (((iz >> sh) & 1) << 2));
+        cur = T->nd[cur].child[o];
+        if (cur < 0) return -1;
+    }
+    return cur;
+}
+
+static void oa_collect_U(const oatree *T, int node, int B, ivec *out)
+{
+    if (!oa_adjacent(&T->nd[node], &T->nd[B])) return;
+    if (T->nd[node].leaf) { ivec_push(out, node); return; }
+    for (int o = 0; o < 8; ++o)
+        if (T->nd[node].child[o] >= 0) oa_collect_U(T, T->nd[node].child[o], B, out);
+}
+
+static void oa_collect_W(const oatree *T, int node, int B, ivec *out)
+{
+    /* node is a descendant of a neighbour of B whose parent is adjacent to B */
+    for (int o = 0; o < 8; ++o) {
+        int c = T->nd[node].child[o];
+        if (c < 0) continue;
+        if (!oa_adjacent(&T->nd[c], &T->nd[B])) ivec_push(out, c);
+        else if (!T->nd[c].leaf) oa_collect_W(T, c, B, out);
+    }
+}
+
+static void oa_build_lists(oatree *T)
+{
+    int nn = T->nn > 0 ? T->nn : 1;
+    T->U = (ivec *)calloc((size_t)nn, sizeof(ivec));
+    T->V = (ivec *)calloc((size_t)nn, sizeof(ivec));
+    T->W = (ivec *)calloc((size_t)nn, sizeof(ivec));
+    T->X = (ivec *)calloc((size_t)nn, sizeof(ivec));
+    nn = T->nn;
+    for (int B = 0; B < nn; ++B) {
+        const oanode *b = &T->nd[B];
+        if (b->level >= 1) {
+            const oanode *P = &T->nd[b->parent];
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int Q = oa_find(T, P->level, P->ix + dx, P->iy + dy, P->iz + dz);
+                        if (Q < 0) continue;
+                        for (int o = 0; o < 8; ++o) {
+                            int C = T->nd[Q].child[o];
+                            if (C >= 0 && !oa_adjacent(&T->nd[C], b)) ivec_push(&T->V[B], C);
+                        }
+                    }
+        }
+        if (b->leaf) {
+            oa_collect_U(T, 0, B, &T->U[B]);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        int C = oa_find(T, b->level, b->ix + dx, b->iy + dy, b->iz + dz);
+                        if (C >= 0 && !T->nd[C].leaf) oa_collect_W(T, C, B, &T->W[B]);
+                    }
+        }
+    }
+    for (int B = 0; B < nn; ++B)
+        for (int i = 0; i < T->W[B].n; ++i) ivec_push(&T->X[T->W[B].v[i]], B);
+}
+
+static void oa_center(const oatree *T, const oanode *x, double z[3])
+{
+    double h = T->side / (double)((int64_t)1 << x->level);
+    z[0] = T->lo[0] + ((double)x->ix + 0.5) * h;
+    z[1] = T->lo[1] + ((double)x->iy + 0.5) * h;
+    z[2] = T->lo[2] + ((double)x->iz + 0.5) * h;
+}
+
+/* automatic root cube: centred on the bounding box, side = largest extent * (1 + 2^-20) */
+void oracle_auto_root(int64_t n, const double *xyz, double lo[3], double *side)
+{
+    double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    for (int64_t a = 0; a < n; ++a)
+        for (int d = 0; d < 3; ++d) {
+            double v = xyz[3 * a + d];
+            if (a == 0 || v < mn[d]) mn[d] = v;
+            if (a == 0 || v > mx[d]) mx[d] = v;
+        }
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (mx[d] - mn[d] > s) s = mx[d] - mn[d];
+    if (!(s > 0.0)) s = 1.0;
+    s = s * (1.0 + 1.0 / 1048576.0);
+    for (int d = 0; d < 3; ++d) lo[d] = (mn[d] + mx[d]) * 0.5 - s * 0.5;
+    *side = s;
+}
+
+static void oa_free(oatree *T)
+{
+    free(T->order); free(T->key); free(T->leaf_of);
+    if (T->U) for (int i = 0; i < T->nn; ++i) { free(T->U[i].v); free(T->V[i].v); free(T->W[i].v); free(T->X[i].v); }
+    free(T->U); free(T->V); free(T->W); free(T->X);
+    if (T->M) for (int i = 0; i < T->nn; ++i) free(T->M[i]);
+    if (T->L) for (int i = 0; i < T->nn; ++i) free(T->L[i]);
+    free(T->M); free(T->L); free(T->nd);
+}
+
+/*
+ * Full FMM on the adaptive octree.  side <= 0 selects the automatic root
+ * cube.  Targets as in oracle_fmm_uniform (all particles when tgt is NULL).
+ * stats (optional, 8 int64): nodes, leaves, max level, |V|, |U| (leaf pairs),
+ * |W|, |X| totals, and the root box is written to root_out[4] (lo, side) if
+ * given.  Returns 0, -1 (arguments) or -2 (allocation).
+ */
+int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
+                        const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
+                        double *phi, double *grad, int64_t *stats, double *root_out, int nthreads)
+{
+    init_tables();
+    if (p < 0 || p > OR_PMAX || n < 1 || leaf_max < 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    oatree T;
+    memset(&T, 0, sizeof(T));
+    T.p = p; T.leaf_max = leaf_max; T.n = n; T.xyz = xyz; T.q = q; T.nf = g_nfull[p];
+    if (side_in > 0.0) {
+        T.lo[0] = lo_in[0]; T.lo[1] = lo_in[1]; T.lo[2] = lo_in[2]; T.side = side_in;
+    } else {
+        oracle_auto_root(n, xyz, T.lo, &T.side);
+    }
+    if (root_out) { root_out[0] = T.lo[0]; root_out[1] = T.lo[1]; root_out[2] = T.lo[2]; root_out[3] = T.side; }
+    T.order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    T.key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint64_t *pkey = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    T.leaf_of = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!T.order || !T.key || !pkey || !T.leaf_of) { free(pkey); oa_free(&T); return -2; }
+    for (int64_t a = 0; a < n; ++a) {
+        uint64_t c[3];
+        for (int d = 0; d < 3; ++d) {
+            double s = floor((xyz[3 * a + d] - T.lo[d]) / T.side * (double)((int64_t)1 << OA_DMAX));
+            int64_t i = (int64_t)s;
+            if (s < 0.0) i = 0;
+            if (i > ((int64_t)1 << OA_DMAX) - 1) i = ((int64_t)1 << OA_DMAX) - 1;
+            c[d] = (uint64_t)i;
+        }
+        pkey[a] = oa_spread(c[0]) | (oa_spread(c[1]) << 1) | (oa_spread(c[2]) << 2);
+        T.order[a] = a;
+    }
+    memcpy(T.key, pkey, (size_t)n * sizeof(uint64_t));
+    g_sort_tree = &T;
+    qsort(T.order, (size_t)n, sizeof(int64_t), cmp_key);
+    for (int64_t s = 0; s < n; ++s) T.key[s] = pkey[T.order[s]];
+    free(pkey);
+    oa_new_node(&T, 0, 0, 0, n, -1);
+    oa_split(&T, 0);
+    for (int i = 0; i < T.nn; ++i)
+        if (T.nd[i].leaf)
+            for (int64_t s = T.nd[i].b; s < T.nd[i].e; ++s) T.leaf_of[T.order[s]] = i;
+    oa_build_lists(&T);
+    int nf = T.nf;
+    T.M = (double **)calloc((size_t)T.nn, sizeof(double *));
+    T.L = (double **)calloc((size_t)T.nn, sizeof(double *));
+    for (int i = 0; i < T.nn; ++i) {
+        T.M[i] = (double *)calloc((size_t)nf, sizeof(double));
+        T.L[i] = (double *)calloc((size_t)nf, sizeof(double));
+    }
+    /* upward: P2M at leaves, then M2M from the deepest level up */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < T.nn; ++i) {
+        if (!T.nd[i].leaf) continue;
+        double z[3];
+        oa_center(&T, &T.nd[i], z);
+        int64_t cnt = T.nd[i].e - T.nd[i].b;
+        double *px = (double *)malloc((size_t)cnt * 3 * sizeof(double));
+        double *pq = (double *)malloc((size_t)cnt * sizeof(double));
+        for (int64_t s = T.nd[i].b; s < T.nd[i].e; ++s) {
+            int64_t a = T.order[s];
+            for (int d = 0; d < 3; ++d) px[3 * (s - T.nd[i].b) + d] = xyz[3 * a + d];
+            pq[s - T.nd[i].b] = q[a];
+        }
+        oracle_p2m(p, z, cnt, px, pq, T.M[i]);
+        free(px);
+        free(pq);
+    }
+    for (int l = T.maxlev; l >= 1; --l) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int i = 0; i < T.nn; ++i) {
+            if (T.nd[i].level != l - 1 || T.nd[i].leaf) continue;
+            double zp[3];
+            oa_center(&T, &T.nd[i], zp);
+            for (int o = 0; o < 8; ++o) {
+                int c = T.nd[i].child[o];
+                if (c < 0) continue;
+                double zc[3], dd[3];
+                oa_center(&T, &T.nd[c], zc);
+                dd[0] = zc[0] - zp[0]; dd[1] = zc[1] - zp[1]; dd[2] = zc[2] - zp[2];
+                oracle_m2m(p, dd, T.M[c], T.M[i]);
+            }
+        }
+    }
+    /* downward: per level, L2L from the parent, M2L from V, local expansions of X */
+    for (int l = 1; l <= T.maxlev; ++l) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int i = 0; i < T.nn; ++i) {
+            if (T.nd[i].level != l) continue;
+            double zb[3];
+            oa_center(&T, &T.nd[i], zb);
+            int par = T.nd[i].parent;
+            if (par >= 0 && T.nd[par].level >= 1) {
+                double zp[3], dd[3];
+                oa_center(&T, &T.nd[par], zp);
+                dd[0] = zb[0] - zp[0]; dd[1] = zb[1] - zp[1]; dd[2] = zb[2] - zp[2];
+                oracle_l2l(p, dd, T.L[par], T.L[i]);
+            }
+            for (int k = 0; k < T.V[i].n; ++k) {
+                int C = T.V[i].v[k];
+                double za[3], r[3];
+                oa_center(&T, &T.nd[C], za);
+                r[0] = zb[0] - za[0]; r[1] = zb[1] - za[1]; r[2] = zb[2] - za[2];
+                oracle_m2l(p, r, T.M[C], T.L[i]);
+            }
+            for (int k = 0; k < T.X[i].n; ++k) {
+                int C = T.X[i].v[k];
+                for (int64_t s = T.nd[C].b; s < T.nd[C].e; ++s) {
+                    int64_t a = T.order[s];
+                    double Mq[1000], r[3], xa[3] = {xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2]};
+                    memset(Mq, 0, (size_t)nf * sizeof(double));
+                    oracle_p2m(p, xa, 1, xa, &q[a], Mq);
+                    r[0] = zb[0] - xa[0]; r[1] = zb[1] - xa[1]; r[2] = zb[2] - xa[2];
+                    oracle_m2l(p, r, Mq, T.L[i]);
+                }
+            }
+        }
+    }
+    /* evaluation: L2P + W (M2L to the particle) + U (direct) */
+    int64_t cnt = tgt ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t b = tgt ? tgt[t] : t;
+        int B = (int)T.leaf_of[b];
+        const double *xb = &xyz[3 * b];
+        double f = 0.0, g[3] = {0.0, 0.0, 0.0}, z[3], rb[3];
+        oa_center(&T, &T.nd[B], z);
+        rb[0] = xb[0] - z[0]; rb[1] = xb[1] - z[1]; rb[2] = xb[2] - z[2];
+        oracle_l2p(p, rb, T.L[B], &f, g);
+        double *Lp = (double *)malloc((size_t)nf * sizeof(double));
+        for (int k = 0; k < T.W[B].n; ++k) {
+            int C = T.W[B].v[k];
+            double za[3], r[3], zero[3] = {0.0, 0.0, 0.0};
+            oa_center(&T, &T.nd[C], za);
+            r[0] = xb[0] - za[0]; r[1] = xb[1] - za[1]; r[2] = xb[2] - za[2];
+            memset(Lp, 0, (size_t)nf * sizeof(double));
+            oracle_m2l(p, r, T.M[C], Lp);
+            oracle_l2p(p, zero, Lp, &f, g);
+        }
+        free(Lp);
+        for (int k = 0; k < T.U[B].n; ++k) {
+            int C = T.U[B].v[k];
+            for (int64_t s = T.nd[C].b; s < T.nd[C].e; ++s) {
+                int64_t a = T.order[s];
+                if (a == b) continue;
+                pair_kernel(xb, &xyz[3 * a], q[a], &f, g);
+            }
+        }
+        phi[t] = f;
+        grad[3 * t + 0] = g[0];
+        grad[3 * t + 1] = g[1];
+        grad[3 * t + 2] = g[2];
+    }
+    if (stats) {
+        int64_t st[8] = {T.nn, 0, T.maxlev, 0, 0, 0, 0, 0};
+        for (int i = 0; i < T.nn; ++i) {
+            st[1] += T.nd[i].leaf;
+            st[3] += T.V[i].n; st[4] += T.U[i].n; st[5] += T.W[i].n; st[6] += T.X[i].n;
+        }
+        memcpy(stats, st, sizeof(st));
+    }
+    oa_free(&T);
+    return 0;
+}

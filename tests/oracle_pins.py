@@ -416,4 +416,70 @@ def pin_fmm_expansion_centres(o):
         assert rel(Mp, o.p2m(p, zp, x[None, :], np.array([qq]))) < 1e-13
 
 
+def _lattice_cube(depth, per_leaf, seed):
+    """per_leaf random particles inside every leaf of a uniform depth-`depth` grid"""
+    rng = np.random.default_rng(seed)
+    n1 = 2 ** depth
+    cells = np.array([(i, j, k) for k in range(n1) for j in range(n1) for i in range(n1)], float)
+    xyz = ((cells[:, None, :] + rng.random((len(cells), per_leaf, 3))) / n1).reshape(-1, 3)
+    return xyz, rng.uniform(-1, 1, len(xyz))
+
+
+def pin_adaptive_equals_uniform_when_tree_is_uniform(o):
+    """With exactly leaf_max particles in every depth-3 cell the adaptive tree
+    is the uniform depth-3 octree: its V/U lists are the ws=1 lists (counts
+    checked by brute force over cell pairs), W and X are empty, and the
+    result equals the uniform FMM."""
+    xyz, q = _lattice_cube(3, 8, 31)
+    pa, ga, info = o.fmm_adaptive(xyz, q, 5, 8, lo=(0.0, 0.0, 0.0), side=1.0, stats=True)
+    pu, gu = o.fmm_uniform(xyz, q, 5, 3)
+    assert rel(pa, pu) < 1e-13 and rel(ga, gu) < 1e-13
+    cnt_v = 0
+    for l in (2, 3):
+        n1 = 2 ** l
+        cells = [(i, j, k) for i in range(n1) for j in range(n1) for k in range(n1)]
+        for a in cells:
+            for b in cells:
+                par_adj = max(abs(a[d] // 2 - b[d] // 2) for d in range(3)) <= 1
+                adj = max(abs(a[d] - b[d]) for d in range(3)) <= 1
+                cnt_v += par_adj and not adj
+    n1 = 8
+    cnt_u = sum(1 for a in range(n1 ** 3) for b in range(n1 ** 3)
+                if max(abs((a >> 0) % 8 - (b >> 0) % 8), abs((a // 8) % 8 - (b // 8) % 8), abs(a // 64 - b // 64)) <= 1)
+    assert info["V"] == cnt_v and info["U"] == cnt_u and info["W"] == 0 and info["X"] == 0, info
+    assert info["leaves"] == 512 and info["max_level"] == 3
+
+
+def pin_adaptive_vs_direct_decay(o):
+    """Adaptive FMM (U, V, W, X lists) on a Plummer sphere against the O(N^2)
+    sum: the W and X lists are exercised and the errors fall with p."""
+    from paper_1811_06332_amd.workloads import plummer
+    xyz, q = plummer(2500, 41)
+    pd, gd = o.direct(xyz, q)
+    prev = None
+    errs = []
+    for p in (2, 4, 6, 8):
+        pa, ga, info = o.fmm_adaptive(xyz, q, p, 24, stats=True)
+        eP, eF = rel(pa, pd), rel(ga, gd)
+        errs.append((p, eP, eF))
+        if prev is not None:
+            assert eF < prev[1] and eP < prev[0], errs
+        prev = (eP, eF)
+    assert info["W"] > 0 and info["X"] > 0 and info["max_level"] >= 5, info
+    assert errs[0][2] < 0.1 and errs[-1][2] < 1e-3, errs
+
+
+def pin_adaptive_two_density(o):
+    """A dense small cluster beside a sparse background (leaves at very
+    different levels, large W and X lists): the adaptive FMM stays at the
+    truncation level against the direct sum."""
+    rng = np.random.default_rng(43)
+    xyz = np.vstack([rng.random((600, 3)), 0.41 + 0.03 * rng.random((900, 3))])
+    q = rng.uniform(0.5, 1.5, len(xyz))
+    pd, gd = o.direct(xyz, q)
+    pa, ga, info = o.fmm_adaptive(xyz, q, 8, 12, stats=True)
+    assert info["W"] > 0 and info["X"] > 0
+    assert rel(pa, pd) < 1e-4 and rel(ga, gd) < 2e-3, (rel(pa, pd), rel(ga, gd), info)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

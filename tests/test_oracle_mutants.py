@@ -60,6 +60,14 @@ MUTANTS = [
      "for (int64_t a = 2 * (I - 1); a <= 2 * (I + 1); ++a)", None),
     ("near_field_misses_neighbours", "for (int64_t a1 = i - 1; a1 <= i + 1; ++a1)",
      "for (int64_t a1 = i; a1 <= i + 1; ++a1)", None),
+    ("adaptive_w_list_dropped", "oracle_l2p(p, zero, Lp, &f, g);", "(void)zero;", None),
+    ("adaptive_x_list_dropped", "oracle_m2l(p, r, Mq, T.L[i]);", "(void)Mq;", None),
+    ("adaptive_adjacency_strict", "if (alo > bhi || blo > ahi) return 0;", "if (alo >= bhi || blo >= ahi) return 0;", None),
+    ("adaptive_v_includes_adjacent", "if (C >= 0 && !oa_adjacent(&T->nd[C], b)) ivec_push(&T->V[B], C);",
+     "if (C >= 0) ivec_push(&T->V[B], C);", None),
+    ("adaptive_l2l_dropped", "oracle_l2l(p, dd, T.L[par], T.L[i]);", "(void)dd;", None),
+    ("adaptive_split_threshold", "if (nd.e - nd.b <= T->leaf_max || nd.level >= OA_DMAX) return;",
+     "if (nd.e - nd.b < T->leaf_max / 2 || nd.level >= OA_DMAX) return;", None),
 ]
 
 
