@@ -37,11 +37,13 @@
 extern "C" {
 #endif
 
-#define CTFMM_ABI_VERSION 1
+#define CTFMM_ABI_VERSION 2
 /* largest expansion order compiled in */
 #define CTFMM_P_MAX 10
 /* deepest uniform octree (2^(3*depth) leaves) */
 #define CTFMM_DEPTH_MAX 9
+/* deepest level of the adaptive octree (63-bit Morton keys) */
+#define CTFMM_ADAPTIVE_LEVEL_MAX 21
 
 typedef struct ctfmm_ctx ctfmm_ctx;
 
@@ -55,7 +57,19 @@ typedef enum ctfmm_status {
 } ctfmm_status;
 
 typedef enum ctfmm_tree {
-    CTFMM_TREE_UNIFORM = 0  /* uniform octree of the given depth over a cube */
+    CTFMM_TREE_UNIFORM = 0,  /* uniform octree of the given depth over a cube */
+    CTFMM_TREE_ADAPTIVE = 1  /* a node holding more than leaf_max particles is split
+                                into its non-empty octants, down to level
+                                CTFMM_ADAPTIVE_LEVEL_MAX (Appendix C: geometric
+                                splits at the cell centre).  Interactions follow
+                                the adaptive lists: V (same-level cells that are
+                                not adjacent but whose parents are) by M2L;
+                                U (adjacent leaves) by direct summation; W (finer
+                                cells not adjacent to a leaf while their parent
+                                is) by evaluating their multipole expansion at
+                                the leaf's particles; X (the converse of W) by
+                                forming the local expansion directly from the
+                                coarse leaf's particles. */
 } ctfmm_tree;
 
 /* Arithmetic of the M2L translation.  Everything else (P2M, M2M, L2L, L2P,
@@ -71,37 +85,57 @@ typedef enum ctfmm_precision {
 typedef struct ctfmm_params {
     int32_t order_p;    /* expansion order p, 0..CTFMM_P_MAX */
     int32_t tree;       /* ctfmm_tree */
-    int32_t depth;      /* leaf level of the uniform octree, 0..CTFMM_DEPTH_MAX */
+    int32_t depth;      /* leaf level of the uniform octree, 0..CTFMM_DEPTH_MAX
+                           (ignored by the adaptive tree) */
     int32_t ws;         /* well-separation in cells; only 1 is supported */
     int32_t precision;  /* ctfmm_precision */
-    int32_t reserved0;
+    int32_t leaf_max;   /* adaptive tree: most particles in a leaf (>= 1) */
     double root_lo[3];  /* lower corner of the root cube */
     double root_side;   /* side of the root cube; particles outside are clamped
-                           into the boundary leaves */
+                           into the boundary cells.  Adaptive tree only:
+                           root_side <= 0 selects the automatic cube, centred on
+                           the particles' bounding box with side = largest
+                           extent * (1 + 2^-20) (1 if all particles coincide) */
 } ctfmm_params;
 
 typedef struct ctfmm_stats_t {
     /* accumulated over evaluate calls since the last ctfmm_reset_stats,
        measured with HIP events on the context stream when timing is on */
     double ms_total;        /* whole evaluate calls */
-    double ms_tree;         /* keys, sort, leaf ranges */
+    double ms_tree;         /* keys, sort, leaf ranges (adaptive: also the tree, its lists
+                               and the M2L tables) */
     double ms_p2m;
     double ms_m2m;
     double ms_m2l;          /* all M2L launches */
     double ms_l2l;
-    double ms_near;         /* L2P + P2P */
-    double ms_convert;      /* FP32 copies of the multipoles for the FP32/BF16 M2L modes */
+    double ms_near;         /* L2P + P2P (adaptive: also the W-list multipole evaluations) */
+    double ms_convert;      /* FP32 copies of the multipoles for the FP32/BF16 M2L modes
+                               (adaptive tree: also the weighted multipoles of the W list) */
+    double ms_p2l;          /* adaptive tree: local expansions formed from X-list particles */
     int64_t evaluations;
     int64_t m2l_launches;
     int64_t m2l_pairs;      /* cell pairs translated by M2L, summed over calls */
     int64_t p2p_leaf_pairs; /* leaf pairs of the near field, summed over calls */
 } ctfmm_stats_t;
 
+/* Shape of the tree and interaction lists built by the last evaluate. */
+typedef struct ctfmm_tree_stats_t {
+    int64_t nodes;      /* tree nodes, root included */
+    int64_t leaves;
+    int64_t max_level;
+    int64_t v_pairs;    /* M2L (target, source) cell pairs */
+    int64_t u_pairs;    /* near-field (target leaf, source leaf) pairs, self included */
+    int64_t w_pairs;    /* (target leaf, source cell) multipole evaluations */
+    int64_t x_pairs;    /* (target cell, source leaf) direct local expansions */
+    double root_lo[3];
+    double root_side;
+} ctfmm_tree_stats_t;
+
 /* ABI version (CTFMM_ABI_VERSION). */
 int ctfmm_version(void);
 
 /* Fill *prm with defaults: p = 4, uniform tree, depth 3, ws = 1, FP64,
- * root cube [0,1)^3.  Returns CTFMM_EINVAL if prm is NULL. */
+ * leaf_max 64, root cube [0,1)^3.  Returns CTFMM_EINVAL if prm is NULL. */
 ctfmm_status ctfmm_default_params(ctfmm_params* prm);
 
 /* Create a context on the current HIP device, bound to hip_stream (a
@@ -121,7 +155,10 @@ typedef void* (*ctfmm_alloc_fn)(size_t bytes, void* user, void* hip_stream);
 typedef void (*ctfmm_free_fn)(void* ptr, void* user, void* hip_stream);
 ctfmm_status ctfmm_set_allocator(ctfmm_ctx* ctx, ctfmm_alloc_fn alloc, ctfmm_free_fn free_fn, void* user);
 
-/* Potential and gradient of n particles.
+/* Potential and gradient of n particles.  With the adaptive tree the call
+ * builds the tree and its lists on the device and waits for the stream a
+ * few times while doing so (the sizes of each level decide the next
+ * launches); the numeric passes that follow are asynchronous.
  *   xyz  dev, n*3 doubles, row-major (x0,y0,z0,x1,...)
  *   q    dev, n doubles
  *   phi  dev, n doubles, may be NULL (not written)
@@ -138,9 +175,13 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* ctx, int64_t n, const double* xyz, const 
  * descending); cells row-major with x fastest (index ix + 2^l (iy + 2^l iz)).
  * host_out must hold 8^level * (p+1)^2 doubles (cap, in doubles).
  * Synchronises the stream.  Errors: EINVAL (level outside 2..depth, cap too
- * small, no evaluate yet), EDEVICE. */
+ * small, no evaluate yet), EUNSUPPORTED (adaptive tree), EDEVICE. */
 ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* ctx, int32_t level, int32_t which, double* host_out,
                                    size_t cap);
+
+/* Tree and list sizes of the last evaluate (synchronises the stream).
+ * Errors: EINVAL (null argument, no evaluate yet), EDEVICE. */
+ctfmm_status ctfmm_tree_stats(ctfmm_ctx* ctx, ctfmm_tree_stats_t* out);
 
 /* Turn per-phase HIP-event timing on (1) or off (0; default). */
 ctfmm_status ctfmm_set_timing(ctfmm_ctx* ctx, int32_t on);

@@ -962,8 +962,9 @@ int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, in
             for (int64_t s = T.nd[i].b; s < T.nd[i].e; ++s) T.leaf_of[T.order[s]] = i;
     oa_build_lists(&T);
     int nf = T.nf;
-    T.M = (double **)calloc((size_t)T.nn, sizeof(double *));
-    T.L = (double **)calloc((size_t)T.nn, sizeof(double *));
+    size_t nnodes = T.nn > 0 ? (size_t)T.nn : 1;
+    T.M = (double **)calloc(nnodes, sizeof(double *));
+    T.L = (double **)calloc(nnodes, sizeof(double *));
     for (int i = 0; i < T.nn; ++i) {
         T.M[i] = (double *)calloc((size_t)nf, sizeof(double));
         T.L[i] = (double *)calloc((size_t)nf, sizeof(double));
@@ -1002,11 +1003,20 @@ int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, in
             }
         }
     }
-    /* downward: per level, L2L from the parent, M2L from V, local expansions of X */
+    /* downward: per level, L2L from the parent, M2L from V, local expansions of X.
+       With explicit targets only the paths from the root to their leaves are needed. */
+    char *need = (char *)calloc(nnodes, 1);
+    if (!need) { oa_free(&T); return -2; }
+    if (tgt) {
+        for (int64_t t = 0; t < nt; ++t)
+            for (int i = (int)T.leaf_of[tgt[t]]; i >= 0 && !need[i]; i = T.nd[i].parent) need[i] = 1;
+    } else {
+        memset(need, 1, (size_t)T.nn);
+    }
     for (int l = 1; l <= T.maxlev; ++l) {
 #pragma omp parallel for schedule(dynamic, 16)
         for (int i = 0; i < T.nn; ++i) {
-            if (T.nd[i].level != l) continue;
+            if (T.nd[i].level != l || !need[i]) continue;
             double zb[3];
             oa_center(&T, &T.nd[i], zb);
             int par = T.nd[i].parent;
@@ -1036,6 +1046,7 @@ int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, in
             }
         }
     }
+    free(need);
     /* evaluation: L2P + W (M2L to the particle) + U (direct) */
     int64_t cnt = tgt ? nt : n;
 #pragma omp parallel for schedule(dynamic, 64)

@@ -19,7 +19,7 @@ using namespace ctfmm;
 
 namespace {
 
-constexpr int NPHASE_EV = 8 + 4 * (CTFMM_DEPTH_MAX + 1);
+constexpr int NPHASE_EV = 8 + 4 * (AMAX + 1);
 
 }  // namespace
 
@@ -59,6 +59,58 @@ struct ctfmm_ctx {
     int* err_flag = nullptr;
     bool have_result = false;
 
+    int16_t* alist = nullptr;      // [8][189] (q << 5 | u) per target octant, then [8][189] operator slots
+
+    // adaptive tree workspace (every buffer grows on demand)
+    ABox abox{};
+    uint64_t* k64 = nullptr;
+    uint64_t* k64s = nullptr;
+    size_t k64_cap = 0, k64s_cap = 0;
+    int32_t* a_idx = nullptr;
+    int32_t* a_idxs = nullptr;
+    int32_t* leaf_of = nullptr;
+    size_t a_idx_cap = 0, a_idxs_cap = 0, leaf_of_cap = 0;
+    double4* a_P = nullptr;
+    double4* a_F = nullptr;  // far field per sorted particle
+    size_t a_P_cap = 0, a_F_cap = 0;
+    double* bbox = nullptr;  // [NBB][6] partial bounds, then lo[3], side
+    ATree tr{};
+    size_t ncap = 0;
+    int nn = 0;
+    int32_t* sflag = nullptr;
+    int32_t* sincl = nullptr;
+    int32_t* scstart = nullptr;
+    size_t sflag_cap = 0, sincl_cap = 0, scstart_cap = 0;
+    unsigned char* tmp = nullptr;
+    size_t tmp_cap = 0;
+    int32_t* lcnt = nullptr;  // [3][nn+1] U, W, X counts
+    int32_t* loff = nullptr;  // [3][nn+1] exclusive scans
+    size_t lcnt_cap = 0, loff_cap = 0;
+    int32_t* ulist = nullptr;
+    int32_t* wlist = nullptr;
+    int32_t* xlist = nullptr;
+    size_t ulist_cap = 0, wlist_cap = 0, xlist_cap = 0;
+    uint32_t* lok = nullptr;
+    uint32_t* loks = nullptr;
+    int32_t* lov = nullptr;
+    int32_t* lovs = nullptr;
+    size_t lok_cap = 0, loks_cap = 0, lov_cap = 0, lovs_cap = 0;
+    int32_t* bse = nullptr;  // [2][256] (level, octant) bucket bounds
+    int4* tiles = nullptr;
+    int32_t* tgt_tab = nullptr;
+    int32_t* src_tab = nullptr;
+    int32_t* vcount = nullptr;
+    size_t tiles_cap = 0, tgt_cap = 0, src_cap = 0, vcount_cap = 0;
+    int32_t* vsum = nullptr;
+    double* aM = nullptr;
+    double* aL = nullptr;
+    double* aMh = nullptr;
+    float* aM32 = nullptr;
+    size_t aM_cap = 0, aL_cap = 0, aMh_cap = 0, aM32_cap = 0;
+    std::vector<int> lev_first, lev_count, tile_first, tile_count;
+    std::vector<int4> tiles_host;
+    int64_t tot_u = 0, tot_w = 0, tot_x = 0, v_pairs = -1;
+
     // timing
     bool timing = false;
     hipEvent_t ev[NPHASE_EV] = {};
@@ -93,6 +145,68 @@ void* dev_alloc(ctfmm_ctx* c, size_t bytes) {
     }
     if (p) c->owned.push_back(p);
     return p;
+}
+
+void dev_release(ctfmm_ctx* c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->owned.begin(), c->owned.end(), p);
+    if (it != c->owned.end()) c->owned.erase(it);
+    if (c->ufree) {
+        c->ufree(p, c->uuser, (void*)c->stream);  // stream-ordered
+    } else {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(p);
+    }
+}
+
+// grow a device array to at least `need` elements (by 1.5x or more); `keep`
+// copies the old contents
+template <class T>
+bool grow(ctfmm_ctx* c, T*& ptr, size_t& cap, size_t need, bool keep) {
+    if (ptr && need <= cap) return true;
+    const size_t ncap = std::max<size_t>(std::max<size_t>(need, 1), cap + cap / 2);
+    T* np = (T*)dev_alloc(c, ncap * sizeof(T));
+    if (!np) return false;
+    if (keep && ptr && cap) {
+        if (hipMemcpyAsync(np, ptr, cap * sizeof(T), hipMemcpyDeviceToDevice, c->stream) != hipSuccess) return false;
+    }
+    dev_release(c, ptr);
+    ptr = np;
+    cap = ncap;
+    return true;
+}
+
+void reset_adaptive(ctfmm_ctx* c) {
+    // pointers only: the buffers themselves are released with the rest
+    c->k64 = c->k64s = nullptr;
+    c->k64_cap = c->k64s_cap = 0;
+    c->a_idx = c->a_idxs = c->leaf_of = nullptr;
+    c->a_idx_cap = c->a_idxs_cap = c->leaf_of_cap = 0;
+    c->a_P = c->a_F = nullptr;
+    c->a_P_cap = c->a_F_cap = 0;
+    c->bbox = nullptr;
+    c->tr = ATree{};
+    c->ncap = 0;
+    c->nn = 0;
+    c->sflag = c->sincl = c->scstart = nullptr;
+    c->sflag_cap = c->sincl_cap = c->scstart_cap = 0;
+    c->tmp = nullptr;
+    c->tmp_cap = 0;
+    c->lcnt = c->loff = nullptr;
+    c->lcnt_cap = c->loff_cap = 0;
+    c->ulist = c->wlist = c->xlist = nullptr;
+    c->ulist_cap = c->wlist_cap = c->xlist_cap = 0;
+    c->lok = c->loks = nullptr;
+    c->lov = c->lovs = nullptr;
+    c->lok_cap = c->loks_cap = c->lov_cap = c->lovs_cap = 0;
+    c->bse = nullptr;
+    c->tiles = nullptr;
+    c->tgt_tab = c->src_tab = c->vcount = nullptr;
+    c->tiles_cap = c->tgt_cap = c->src_cap = c->vcount_cap = 0;
+    c->vsum = nullptr;
+    c->aM = c->aL = c->aMh = nullptr;
+    c->aM32 = nullptr;
+    c->aM_cap = c->aL_cap = c->aMh_cap = c->aM32_cap = 0;
 }
 
 void dev_free_all(ctfmm_ctx* c) {
@@ -180,7 +294,7 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    if (m2l_lds_bytes(p, prec) > (size_t)max_lds)
+    if (m2l_lds_bytes(p, prec) > (size_t)max_lds || m2l_tile_lds_bytes(p, prec) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
     c->Kpk = (unsigned char*)dev_alloc(c, m2l_packed_bytes(p, prec));
     const size_t zbytes = std::max((size_t)ldm_of(p) * 8, (size_t)s32_of(p) * 4);
@@ -202,8 +316,9 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
                 }
         if (k != 189) return fail(c, CTFMM_EDEVICE, "offset list construction");
     }
-    if (prec == CTFMM_PREC_FP32) {
-        // source-octant-major order for the halo kernel: entries (q << 5 | u), then the K slot of r = -v
+    {
+        // source-octant-major order (the halo kernel, the adaptive tiles): entries (q << 5 | u), then the
+        // operator slot of r = -v
         std::vector<int16_t> hl(2 * 8 * 189);
         for (int o = 0; o < 8; ++o) {
             int k = 0;
@@ -220,7 +335,11 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
                 }
             if (k != 189) return fail(c, CTFMM_EDEVICE, "halo offset list construction");
         }
-        off = hl;
+        c->alist = (int16_t*)dev_alloc(c, hl.size() * sizeof(int16_t));
+        if (!c->alist) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+        HIPCHK(c, hipMemcpyAsync(c->alist, hl.data(), hl.size() * sizeof(int16_t), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (prec == CTFMM_PREC_FP32 && c->prm.tree == CTFMM_TREE_UNIFORM) off = hl;
     }
     c->offlist = (int16_t*)dev_alloc(c, off.size() * sizeof(int16_t));
     if (!c->offlist) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
@@ -234,7 +353,7 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     // release the previous particle workspace (tables and operators are kept)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<void*> keep = {c->tab_blob, (void*)c->Dv, (void*)c->Kt, (void*)c->Kpk, (void*)c->offlist,
-                               (void*)c->zero_row, (void*)c->err_flag};
+                               (void*)c->alist, (void*)c->zero_row, (void*)c->err_flag};
     std::vector<void*> rest;
     for (void* p : c->owned) {
         bool k = false;
@@ -316,6 +435,286 @@ int64_t near_pairs(int d) {
     return a * a * a;
 }
 
+// ------------------------------------------------------------------ adaptive tree
+
+constexpr int NBB = 1024;  // blocks of the bounding-box reduction
+
+bool grow_nodes(ctfmm_ctx* c, size_t need) {
+    if (c->tr.key && need <= c->ncap) return true;
+    const size_t ncap = std::max<size_t>(std::max<size_t>(need, 1024), c->ncap + c->ncap / 2);
+    const size_t old = c->ncap;
+    size_t k;
+    k = old; if (!grow(c, c->tr.key, k, ncap, true)) return false;
+    k = old; if (!grow(c, c->tr.pb, k, ncap, true)) return false;
+    k = old; if (!grow(c, c->tr.pe, k, ncap, true)) return false;
+    k = old; if (!grow(c, c->tr.par, k, ncap, true)) return false;
+    k = old; if (!grow(c, c->tr.info, k, ncap, true)) return false;
+    k = 8 * old; if (!grow(c, c->tr.child, k, 8 * ncap, true)) return false;
+    k = 27 * old; if (!grow(c, c->tr.nb, k, 27 * ncap, true)) return false;
+    c->ncap = ncap;
+    return true;
+}
+
+// run a hipcub algorithm with the shared temporary buffer
+template <class F>
+ctfmm_status cub_run(ctfmm_ctx* c, F f) {
+    size_t bytes = 0;
+    HIPCHK(c, f(nullptr, bytes));
+    if (!grow(c, c->tmp, c->tmp_cap, bytes, false)) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
+    bytes = c->tmp_cap;
+    HIPCHK(c, f((void*)c->tmp, bytes));
+    return CTFMM_OK;
+}
+
+#define ACHK(expr)                                                                     \
+    do {                                                                               \
+        if (!(expr)) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");      \
+    } while (0)
+#define SCHK(expr)                          \
+    do {                                    \
+        ctfmm_status s_ = (expr);           \
+        if (s_ != CTFMM_OK) return s_;      \
+    } while (0)
+
+// keys, sort, the tree level by level, neighbour tables, U/W/X lists and the
+// M2L tile tables.  Waits for the stream once per tree level and a few
+// times more (sizes decide the next launches).
+ctfmm_status build_adaptive(ctfmm_ctx* c, int n, const double* xyz, const double* q) {
+    hipStream_t st = c->stream;
+    const size_t nn_ = (size_t)n;
+    ACHK(grow(c, c->k64, c->k64_cap, nn_, false));
+    ACHK(grow(c, c->k64s, c->k64s_cap, nn_, false));
+    ACHK(grow(c, c->a_idx, c->a_idx_cap, nn_, false));
+    ACHK(grow(c, c->a_idxs, c->a_idxs_cap, nn_, false));
+    ACHK(grow(c, c->leaf_of, c->leaf_of_cap, nn_, false));
+    ACHK(grow(c, c->a_P, c->a_P_cap, nn_, false));
+    ACHK(grow(c, c->a_F, c->a_F_cap, nn_, false));
+    if (!c->bbox) {
+        size_t cap = 0;
+        ACHK(grow(c, c->bbox, cap, 6 * NBB + 4, false));
+    }
+    if (!c->bse) {
+        size_t cap = 0;
+        ACHK(grow(c, c->bse, cap, 512, false));
+    }
+    if (!c->vsum) {
+        size_t cap = 0;
+        ACHK(grow(c, c->vsum, cap, 1, false));
+    }
+    // root cube
+    if (c->prm.root_side > 0.0) {
+        c->abox = ABox{{c->prm.root_lo[0], c->prm.root_lo[1], c->prm.root_lo[2]}, c->prm.root_side};
+    } else {
+        const int nparts = std::min(NBB, std::max(1, (n + 255) / 256));
+        launch_bbox(st, n, xyz, c->bbox, nparts, c->bbox + 6 * NBB);
+        double hb[4];
+        HIPCHK(c, hipMemcpyAsync(hb, c->bbox + 6 * NBB, sizeof(hb), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (!std::isfinite(hb[0]) || !std::isfinite(hb[1]) || !std::isfinite(hb[2]) || !std::isfinite(hb[3]))
+            return fail(c, CTFMM_EINVAL, "non-finite particle coordinate");
+        c->abox = ABox{{hb[0], hb[1], hb[2]}, hb[3]};
+    }
+    launch_keys64(st, n, xyz, c->abox, c->k64, c->a_idx, c->err_flag);
+    SCHK(cub_run(c, [&](void* t, size_t& b) {
+        return hipcub::DeviceRadixSort::SortPairs(t, b, c->k64, c->k64s, c->a_idx, c->a_idxs, n, 0, 3 * AMAX, st);
+    }));
+    launch_gather(st, n, c->a_idxs, xyz, q, c->a_P);
+    HIPCHK(c, hipGetLastError());
+
+    // tree, level by level
+    ACHK(grow_nodes(c, 1));
+    launch_root(st, n, c->tr);
+    c->lev_first.assign(1, 0);
+    c->lev_count.assign(1, 1);
+    int first = 0, count = 1, total = 1;
+    for (int l = 0;; ++l) {
+        const size_t m = 8 * (size_t)count;
+        ACHK(grow(c, c->sflag, c->sflag_cap, m, false));
+        ACHK(grow(c, c->sincl, c->sincl_cap, m, false));
+        ACHK(grow(c, c->scstart, c->scstart_cap, m, false));
+        launch_split(st, l, first, count, c->prm.leaf_max, c->k64s, c->tr, c->sflag, c->scstart);
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceScan::InclusiveSum(t, b, c->sflag, c->sincl, (int)m, st);
+        }));
+        int nnext = 0;
+        HIPCHK(c, hipMemcpyAsync(&nnext, c->sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (nnext == 0) break;
+        ACHK(grow_nodes(c, (size_t)total + nnext));
+        launch_emit(st, l, first, count, total, c->sflag, c->sincl, c->scstart, c->tr);
+        first = total;
+        count = nnext;
+        total += nnext;
+        c->lev_first.push_back(first);
+        c->lev_count.push_back(count);
+    }
+    HIPCHK(c, hipGetLastError());
+    const int nn = total;
+    c->nn = nn;
+    const int maxlev = (int)c->lev_first.size() - 1;
+    for (int l = 1; l <= maxlev; ++l) launch_nb(st, c->lev_first[l], c->lev_count[l], c->tr);
+    launch_leaf_of(st, nn, c->tr, c->leaf_of);
+
+    // U, W, X lists: count, scan, fill
+    const size_t n1 = (size_t)nn + 1;
+    ACHK(grow(c, c->lcnt, c->lcnt_cap, 3 * n1, false));
+    ACHK(grow(c, c->loff, c->loff_cap, 3 * n1, false));
+    int32_t *uc = c->lcnt, *wc = c->lcnt + n1, *xc = c->lcnt + 2 * n1;
+    int32_t *uo = c->loff, *wo = c->loff + n1, *xo = c->loff + 2 * n1;
+    HIPCHK(c, hipMemsetAsync(c->lcnt, 0, 3 * n1 * sizeof(int32_t), st));
+    launch_lists(st, false, nn, c->tr, uc, wc, xc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    for (int k = 0; k < 3; ++k) {
+        int32_t* in = c->lcnt + k * n1;
+        int32_t* out = c->loff + k * n1;
+        SCHK(cub_run(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, in, out, (int)n1, st); }));
+    }
+    int tot[3];
+    for (int k = 0; k < 3; ++k)
+        HIPCHK(c, hipMemcpyAsync(&tot[k], c->loff + k * n1 + nn, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->tot_u = tot[0];
+    c->tot_w = tot[1];
+    c->tot_x = tot[2];
+    ACHK(grow(c, c->ulist, c->ulist_cap, (size_t)tot[0], false));
+    ACHK(grow(c, c->wlist, c->wlist_cap, (size_t)tot[1], false));
+    ACHK(grow(c, c->xlist, c->xlist_cap, (size_t)tot[2], false));
+    launch_lists(st, true, nn, c->tr, uc, wc, xc, uo, wo, xo, c->ulist, c->wlist, c->xlist);
+
+    // M2L tiles: nodes grouped by (level, octant), Morton order inside, 64 per tile
+    ACHK(grow(c, c->lok, c->lok_cap, (size_t)nn, false));
+    ACHK(grow(c, c->loks, c->loks_cap, (size_t)nn, false));
+    ACHK(grow(c, c->lov, c->lov_cap, (size_t)nn, false));
+    ACHK(grow(c, c->lovs, c->lovs_cap, (size_t)nn, false));
+    launch_lvloct(st, nn, c->tr, c->lok, c->lov);
+    SCHK(cub_run(c, [&](void* t, size_t& b) {
+        return hipcub::DeviceRadixSort::SortPairs(t, b, c->lok, c->loks, c->lov, c->lovs, nn, 0, 8, st);
+    }));
+    launch_buckets(st, nn, c->loks, c->bse, c->bse + 256);
+    int hb[512];
+    HIPCHK(c, hipMemcpyAsync(hb, c->bse, sizeof(hb), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->tiles_host.clear();
+    c->tile_first.assign(maxlev + 1, 0);
+    c->tile_count.assign(maxlev + 1, 0);
+    for (int l = 2; l <= maxlev; ++l) {
+        c->tile_first[l] = (int)c->tiles_host.size();
+        for (int o = 0; o < 8; ++o) {
+            const int k = (l << 3) | o;
+            const int b = hb[k], e = hb[256 + k];
+            for (int s0 = b; s0 < e; s0 += 64) c->tiles_host.push_back(make_int4(o, s0, std::min(64, e - s0), l));
+        }
+        c->tile_count[l] = (int)c->tiles_host.size() - c->tile_first[l];
+    }
+    const size_t ntiles = c->tiles_host.size();
+    if (ntiles) {
+        ACHK(grow(c, c->tiles, c->tiles_cap, ntiles, false));
+        ACHK(grow(c, c->tgt_tab, c->tgt_cap, 64 * ntiles, false));
+        ACHK(grow(c, c->src_tab, c->src_cap, 189 * 64 * ntiles, false));
+        ACHK(grow(c, c->vcount, c->vcount_cap, 189 * ntiles, false));
+        HIPCHK(c, hipMemcpyAsync(c->tiles, c->tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice, st));
+        launch_m2l_tables(st, (int)ntiles, c->tiles, c->lovs, c->tr, c->alist, c->tgt_tab, c->src_tab, c->vcount);
+    }
+    HIPCHK(c, hipGetLastError());
+    c->v_pairs = -1;
+    return CTFMM_OK;
+}
+
+// (target, source) pairs of the M2L tiles built last (waits for the stream)
+ctfmm_status count_v_pairs(ctfmm_ctx* c) {
+    if (c->v_pairs >= 0) return CTFMM_OK;
+    const int m = 189 * (int)c->tiles_host.size();
+    int v = 0;
+    if (m > 0) {
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceReduce::Sum(t, b, c->vcount, c->vsum, m, c->stream);
+        }));
+        HIPCHK(c, hipMemcpyAsync(&v, c->vsum, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->v_pairs = v;
+    return CTFMM_OK;
+}
+
+ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const double* q, double* phi,
+                               double* grad) {
+    hipStream_t st = c->stream;
+    const int p = c->prm.order_p;
+    const int prec = c->prm.precision;
+    const size_t ldm = (size_t)ldm_of(p);
+    // events: 0 start, 1 tree built, 2 P2M, 3 M2M, 4 conversions, 5 before the near field, then 4 per level
+    rec(c, 0);
+    HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), st));
+    SCHK(build_adaptive(c, n, xyz, q));
+    rec(c, 1);
+    const int nn = c->nn;
+    const int maxlev = (int)c->lev_first.size() - 1;
+    ACHK(grow(c, c->aM, c->aM_cap, (size_t)nn * ldm, false));
+    ACHK(grow(c, c->aL, c->aL_cap, (size_t)nn * ldm, false));
+    const ABox box = c->abox;
+    launch_p2m_nodes(st, p, 0, nn, box, c->tr, c->a_P, c->T, c->aM);
+    rec(c, 2);
+    for (int l = maxlev - 1; l >= 2; --l) launch_m2m_nodes(st, p, c->lev_first[l], c->lev_count[l], c->tr, c->aM, c->T);
+    rec(c, 3);
+    const void* msrc = c->aM;
+    if (maxlev >= 2) {
+        const int f2 = c->lev_first[2];
+        if (c->tot_w > 0) {
+            ACHK(grow(c, c->aMh, c->aMh_cap, (size_t)nn * ldm, false));
+            launch_mhat(st, p, f2, nn - f2, c->aM, c->aMh);
+        }
+        if (prec != CTFMM_PREC_FP64) {
+            ACHK(grow(c, c->aM32, c->aM32_cap, (size_t)nn * s32_of(p), false));
+            launch_to_f32(st, p, nn, c->aM, c->aM32);
+            msrc = c->aM32;
+        }
+    }
+    rec(c, 4);
+    int evi = 6;
+    for (int l = 2; l <= maxlev; ++l) {
+        rec(c, evi);
+        const AdaptM2L ad{c->tiles, c->tgt_tab, c->src_tab, c->alist + 8 * 189, c->tile_first[l]};
+        HIPCHK(c, launch_m2l_tables(st, p, prec, c->tile_count[l], ad, msrc, c->aL, c->Kpk, c->zero_row));
+        rec(c, evi + 1);
+        if (l >= 3) launch_l2l_nodes(st, p, c->lev_first[l - 1], c->lev_count[l - 1], c->tr, c->aL, c->T);
+        rec(c, evi + 2);
+        if (c->tot_x > 0)
+            launch_p2l(st, p, c->lev_first[l], c->lev_count[l], box, c->tr, c->loff + 2 * ((size_t)nn + 1), c->xlist,
+                       c->a_P, c->aL);
+        rec(c, evi + 3);
+        evi += 4;
+    }
+    rec(c, 5);
+    const size_t n1 = (size_t)nn + 1;
+    launch_near_adaptive(st, p, n, box, c->tr, c->leaf_of, c->a_P, c->aL, c->aMh, c->loff + n1, c->wlist, c->loff,
+                         c->ulist, c->a_idxs, c->a_F, phi, grad);
+    HIPCHK(c, hipGetLastError());
+    const int ev_end = NPHASE_EV - 1;
+    rec(c, ev_end);
+    c->have_result = true;
+    c->st.evaluations += 1;
+    c->st.m2l_launches += std::max(0, maxlev - 1);
+    c->st.p2p_leaf_pairs += c->tot_u;
+    if (c->timing) {
+        SCHK(count_v_pairs(c));
+        c->st.m2l_pairs += c->v_pairs;
+        HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
+        c->st.ms_total += elapsed(c, 0, ev_end);
+        c->st.ms_tree += elapsed(c, 0, 1);
+        c->st.ms_p2m += elapsed(c, 1, 2);
+        c->st.ms_m2m += elapsed(c, 2, 3);
+        c->st.ms_convert += elapsed(c, 3, 4);
+        c->st.ms_near += elapsed(c, 5, ev_end);
+        int e = 6;
+        for (int l = 2; l <= maxlev; ++l) {
+            c->st.ms_m2l += elapsed(c, e, e + 1);
+            c->st.ms_l2l += elapsed(c, e + 1, e + 2);
+            c->st.ms_p2l += elapsed(c, e + 2, e + 3);
+            e += 4;
+        }
+    }
+    return CTFMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -330,6 +729,7 @@ ctfmm_status ctfmm_default_params(ctfmm_params* prm) {
     prm->depth = 3;
     prm->ws = 1;
     prm->precision = CTFMM_PREC_FP64;
+    prm->leaf_max = 64;
     prm->root_side = 1.0;
     return CTFMM_OK;
 }
@@ -341,15 +741,19 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
         return CTFMM_EINVAL;
     }
     *out = nullptr;
-    if (prm->order_p < 0 || prm->order_p > CTFMM_P_MAX || prm->depth < 0 || prm->depth > CTFMM_DEPTH_MAX ||
-        prm->ws != 1 || !(prm->root_side > 0.0) || !std::isfinite(prm->root_side) ||
-        !std::isfinite(prm->root_lo[0]) || !std::isfinite(prm->root_lo[1]) || !std::isfinite(prm->root_lo[2])) {
-        g_create_err = "invalid parameters (p in 0..10, depth in 0..9, ws == 1, finite root box)";
-        return CTFMM_EINVAL;
-    }
-    if (prm->tree != CTFMM_TREE_UNIFORM) {
-        g_create_err = "only the uniform octree is implemented";
+    if (prm->tree != CTFMM_TREE_UNIFORM && prm->tree != CTFMM_TREE_ADAPTIVE) {
+        g_create_err = "unknown tree type";
         return CTFMM_EUNSUPPORTED;
+    }
+    const bool adaptive = prm->tree == CTFMM_TREE_ADAPTIVE;
+    const bool box_ok = std::isfinite(prm->root_side) && std::isfinite(prm->root_lo[0]) &&
+                        std::isfinite(prm->root_lo[1]) && std::isfinite(prm->root_lo[2]) &&
+                        (adaptive || prm->root_side > 0.0);
+    if (prm->order_p < 0 || prm->order_p > CTFMM_P_MAX || prm->ws != 1 || !box_ok ||
+        (!adaptive && (prm->depth < 0 || prm->depth > CTFMM_DEPTH_MAX)) || (adaptive && prm->leaf_max < 1)) {
+        g_create_err = "invalid parameters (p in 0..10, ws == 1, finite root box; uniform: depth in 0..9, "
+                       "root_side > 0; adaptive: leaf_max >= 1)";
+        return CTFMM_EINVAL;
     }
     if (prm->precision != CTFMM_PREC_FP64 && prm->precision != CTFMM_PREC_FP32 &&
         prm->precision != CTFMM_PREC_BF16X3) {
@@ -388,6 +792,7 @@ ctfmm_status ctfmm_set_allocator(ctfmm_ctx* c, ctfmm_alloc_fn alloc, ctfmm_free_
     if (alloc && !free_fn) return fail(c, CTFMM_EINVAL, "allocator needs a free function");
     // move everything to the new allocator: release, then rebuild tables/operators
     dev_free_all(c);
+    reset_adaptive(c);
     c->cap_n = -1;
     c->have_result = false;
     c->ualloc = alloc;
@@ -407,6 +812,7 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "n out of range");
     if (n == 0) return CTFMM_OK;
     if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
+    if (c->prm.tree == CTFMM_TREE_ADAPTIVE) return evaluate_adaptive(c, (int)n, xyz, q, phi, grad);
     ctfmm_status s = ensure_workspace(c, n);
     if (s != CTFMM_OK) return s;
     const int d = c->prm.depth;
@@ -491,6 +897,7 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* c, int32_t level, int32_t which, d
     if (!c || !host_out) return CTFMM_EINVAL;
     const int p = c->prm.order_p;
     const size_t nc = (size_t)(p + 1) * (p + 1);
+    if (c->prm.tree != CTFMM_TREE_UNIFORM) return fail(c, CTFMM_EUNSUPPORTED, "expansion copies need the uniform tree");
     if (!c->have_result) return fail(c, CTFMM_EINVAL, "no evaluate yet");
     if (level < 2 || level > c->prm.depth || (which != 0 && which != 1))
         return fail(c, CTFMM_EINVAL, "level must be in 2..depth and which 0 or 1");
@@ -505,6 +912,38 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* c, int32_t level, int32_t which, d
     hipError_t e3 = hipStreamSynchronize(c->stream);
     (void)hipFree(tmp);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(c, CTFMM_EDEVICE, "copy failed");
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
+    if (!c || !out) return CTFMM_EINVAL;
+    if (!c->have_result) return fail(c, CTFMM_EINVAL, "no evaluate yet");
+    std::memset(out, 0, sizeof(*out));
+    if (c->prm.tree == CTFMM_TREE_UNIFORM) {
+        const int d = c->prm.depth;
+        for (int l = 0; l <= d; ++l) out->nodes += 1ll << (3 * l);
+        out->leaves = 1ll << (3 * d);
+        out->max_level = d;
+        for (int l = 2; l <= d; ++l) out->v_pairs += m2l_pairs_level(l);
+        out->u_pairs = near_pairs(d);
+        for (int k = 0; k < 3; ++k) out->root_lo[k] = c->prm.root_lo[k];
+        out->root_side = c->prm.root_side;
+        return CTFMM_OK;
+    }
+    ctfmm_status s = count_v_pairs(c);
+    if (s != CTFMM_OK) return s;
+    std::vector<int32_t> info((size_t)c->nn);
+    HIPCHK(c, hipMemcpyAsync(info.data(), c->tr.info, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int32_t v : info) out->leaves += (v >> 8) & 1;
+    out->nodes = c->nn;
+    out->max_level = (int64_t)c->lev_first.size() - 1;
+    out->v_pairs = c->v_pairs;
+    out->u_pairs = c->tot_u;
+    out->w_pairs = c->tot_w;
+    out->x_pairs = c->tot_x;
+    for (int k = 0; k < 3; ++k) out->root_lo[k] = c->abox.lo[k];
+    out->root_side = c->abox.side;
     return CTFMM_OK;
 }
 

@@ -65,6 +65,117 @@ struct Box {
     int depth;
 };
 
+// ---- adaptive octree ----
+constexpr int AMAX = 21;  // deepest level: 3 x 21-bit Morton keys
+
+// Morton interleave of 21-bit coordinates into 63-bit keys (x in bit 0)
+__host__ __device__ inline uint64_t spread21(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+__host__ __device__ inline uint32_t compact21(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
+// root cube of the adaptive tree
+struct ABox {
+    double lo[3];
+    double side;
+};
+
+// Node arrays of the adaptive tree (structure of arrays, levels contiguous).
+struct ATree {
+    uint64_t* key;   // Morton prefix at the node's level (3 * level bits)
+    int32_t* pb;     // first sorted particle
+    int32_t* pe;     // one past the last
+    int32_t* par;    // parent node, -1 for the root
+    int32_t* info;   // level | (leaf << 8)
+    int32_t* child;  // [8] child per octant (x = bit 0), -1 = empty
+    int32_t* nb;     // [27] same-level neighbour at offset d = (dx+1)+3(dy+1)+9(dz+1),
+                     // else the coarser leaf covering that cell, else -1
+};
+
+// M2L over tables: tile t has 64 target rows tgt[64 t ..] (-1 = none) of
+// octant tiles[t].x, and for offset i of that octant the source rows
+// src[(189 t + i) 64 ..] (-1 = none); kslot[o][i] = slot of its operator.
+struct AdaptM2L {
+    const int4* tiles;
+    const int32_t* tgt;
+    const int32_t* src;
+    const int16_t* kslot;
+    int tile_base;
+};
+
+// P2M of one cell by one wavefront, two phases.  (1) Full monomial moments
+// S_f = sum_a q_a u_a^f, u = (z - x)/h, |f| <= p, with the power tables of up
+// to 64 particles at a time in LDS and lanes over f.  (2) The detracer:
+// M~_n = sum_f DET[n][f] S_f for the independent n (Eq. P2M with Eq.
+// Detracer).  Particles [b, e) of P; writes the ldm_of(p) entries of Mc.
+__device__ inline void p2m_cell(int p, double zx, double zy, double zz, double h, int b, int e,
+                                const double4* __restrict__ P, const DevTables& T, double* __restrict__ Mc) {
+    const int lane = threadIdx.x;
+    const int nc = (p + 1) * (p + 1);
+    const int nf = (p + 1) * (p + 2) * (p + 3) / 6;
+    const int ldm = ldm_of(p);
+    __shared__ double pw[64][3][PMAX + 1];
+    __shared__ double qs[64];
+    __shared__ double S[NFULL];
+    constexpr int FPL = (NFULL + 63) / 64;  // full components per lane
+    double acc[FPL];
+    int fa[FPL], fb[FPL], fc[FPL];
+#pragma unroll
+    for (int k = 0; k < FPL; ++k) {
+        acc[k] = 0.0;
+        const int f = lane + 64 * k;
+        fa[k] = f < nf ? T.full[3 * f] : 0;
+        fb[k] = f < nf ? T.full[3 * f + 1] : 0;
+        fc[k] = f < nf ? T.full[3 * f + 2] : 0;
+    }
+    for (int s0 = b; s0 < e; s0 += 64) {
+        const int cnt = min(64, e - s0);
+        if (lane < cnt) {
+            const double4 pt = P[s0 + lane];
+            const double u[3] = {(zx - pt.x) / h, (zy - pt.y) / h, (zz - pt.z) / h};
+            for (int dim = 0; dim < 3; ++dim) {
+                double v = 1.0;
+                for (int k = 0; k <= p; ++k) {
+                    pw[lane][dim][k] = v;
+                    v *= u[dim];
+                }
+            }
+            qs[lane] = pt.w;
+        }
+        __syncthreads();
+        for (int i = 0; i < cnt; ++i) {
+            const double q = qs[i];
+#pragma unroll
+            for (int k = 0; k < FPL; ++k) acc[k] += q * pw[i][0][fa[k]] * pw[i][1][fb[k]] * pw[i][2][fc[k]];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < FPL; ++k)
+        if (lane + 64 * k < nf) S[lane + 64 * k] = acc[k];
+    __syncthreads();
+    for (int n = lane; n < ldm; n += 64) {
+        double v = 0.0;
+        if (n < nc)
+            for (int t = T.det_start[n]; t < T.det_start[n + 1]; ++t) v += T.det_coef[t] * S[T.det_full[t]];
+        Mc[n] = v;  // padding is kept zero
+    }
+}
+
 // ---- launchers (ctfmm_kernels.hip); every one enqueues on `s` ----
 void launch_keys(hipStream_t s, int n, const double* xyz, Box box, uint32_t* keys, int32_t* idx, int* err);
 void launch_gather(hipStream_t s, int n, const int32_t* idx, const double* xyz, const double* q, double4* P);
@@ -86,8 +197,41 @@ void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned ch
 void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32);
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L,
                       const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row);
+// M2L of ntiles tiles of the adaptive tree (any precision; rows are node indices)
+hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int ntiles, const AdaptM2L& ad, const void* Msrc,
+                             double* L, const unsigned char* Kpk, const unsigned char* zero_row);
+size_t m2l_tile_lds_bytes(int p, int prec);
 // row stride of the FP32 multipole copy: (p+1)^2 rounded up to a multiple of 32
 __host__ __device__ constexpr int s32_of(int p) { return (((p + 1) * (p + 1) + 31) / 32) * 32; }
 void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side, const double* X, double* out);
+
+// ---- adaptive tree launchers (ctfmm_adaptive.hip) ----
+void launch_bbox(hipStream_t s, int n, const double* xyz, double* part, int nparts, double* out);
+void launch_keys64(hipStream_t s, int n, const double* xyz, ABox box, uint64_t* keys, int32_t* idx, int* err);
+void launch_root(hipStream_t s, int n, const ATree& t);
+void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, const uint64_t* keys, const ATree& t,
+                  int32_t* flag, int32_t* cstart);
+void launch_emit(hipStream_t s, int level, int first, int count, int next_first, const int32_t* flag,
+                 const int32_t* incl, const int32_t* cstart, const ATree& t);
+void launch_nb(hipStream_t s, int first, int count, const ATree& t);
+void launch_leaf_of(hipStream_t s, int nn, const ATree& t, int32_t* leaf_of);
+void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucnt, int32_t* wcnt, int32_t* xcnt,
+                  const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist, int32_t* wlist,
+                  int32_t* xlist);
+void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* v);
+void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
+void launch_m2l_tables(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
+                       const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount);
+void launch_p2m_nodes(hipStream_t s, int p, int first, int count, ABox box, const ATree& t, const double4* P,
+                      const DevTables& T, double* M);
+void launch_m2m_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* M, const DevTables& T);
+void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* L, const DevTables& T);
+void launch_p2l(hipStream_t s, int p, int first, int count, ABox box, const ATree& t, const int32_t* xoff,
+                const int32_t* xlist, const double4* P, double* L);
+void launch_mhat(hipStream_t s, int p, int first, int count, const double* M, double* Mh);
+void launch_near_adaptive(hipStream_t s, int p, int n, ABox box, const ATree& t, const int32_t* leaf_of,
+                          const double4* P, const double* L, const double* Mh, const int32_t* woff,
+                          const int32_t* wlist, const int32_t* uoff, const int32_t* ulist, const int32_t* idx,
+                          double4* F, double* phi, double* grad);
 
 }  // namespace ctfmm

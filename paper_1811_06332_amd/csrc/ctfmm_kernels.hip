@@ -83,70 +83,15 @@ void launch_leaf_start(hipStream_t s, int nleaves, const uint32_t* keys, int n, 
 
 // ------------------------------------------------------------------ P2M
 
-// One wavefront per leaf, two phases.  (1) Full monomial moments
-// S_f = sum_a q_a u_a^f, u = (z - x)/h, |f| <= p, with the power tables of up
-// to 64 particles at a time in LDS and lanes over f.  (2) The detracer:
-// M~_n = sum_f DET[n][f] S_f for the independent n (Eq. P2M with Eq. Detracer).
+// One wavefront per leaf (the P2M of p2m_cell, ctfmm_internal.h).
 __global__ __launch_bounds__(64) void k_p2m(int p, Box box, const int32_t* __restrict__ start,
                                             const double4* __restrict__ P, DevTables T, double* __restrict__ M) {
     const uint32_t c = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int nc = (p + 1) * (p + 1);
-    const int nf = (p + 1) * (p + 2) * (p + 3) / 6;
-    const int ldm = ldm_of(p);
-    const int d = box.depth;
-    const double h = box.side / (double)(1 << d);
+    const double h = box.side / (double)(1 << box.depth);
     const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
     const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
     const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
-    __shared__ double pw[64][3][PMAX + 1];
-    __shared__ double qs[64];
-    __shared__ double S[NFULL];
-    constexpr int FPL = (NFULL + 63) / 64;  // full components per lane
-    double acc[FPL];
-    int fa[FPL], fb[FPL], fc[FPL];
-#pragma unroll
-    for (int k = 0; k < FPL; ++k) {
-        acc[k] = 0.0;
-        const int f = lane + 64 * k;
-        fa[k] = f < nf ? T.full[3 * f] : 0;
-        fb[k] = f < nf ? T.full[3 * f + 1] : 0;
-        fc[k] = f < nf ? T.full[3 * f + 2] : 0;
-    }
-    const int b = start[c], e = start[c + 1];
-    for (int s0 = b; s0 < e; s0 += 64) {
-        const int cnt = min(64, e - s0);
-        if (lane < cnt) {
-            const double4 pt = P[s0 + lane];
-            const double u[3] = {(zx - pt.x) / h, (zy - pt.y) / h, (zz - pt.z) / h};
-            for (int dim = 0; dim < 3; ++dim) {
-                double v = 1.0;
-                for (int k = 0; k <= p; ++k) {
-                    pw[lane][dim][k] = v;
-                    v *= u[dim];
-                }
-            }
-            qs[lane] = pt.w;
-        }
-        __syncthreads();
-        for (int i = 0; i < cnt; ++i) {
-            const double q = qs[i];
-#pragma unroll
-            for (int k = 0; k < FPL; ++k) acc[k] += q * pw[i][0][fa[k]] * pw[i][1][fb[k]] * pw[i][2][fc[k]];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < FPL; ++k)
-        if (lane + 64 * k < nf) S[lane + 64 * k] = acc[k];
-    __syncthreads();
-    double* Mc = M + (size_t)c * ldm;
-    for (int n = lane; n < ldm; n += 64) {
-        double v = 0.0;
-        if (n < nc)
-            for (int t = T.det_start[n]; t < T.det_start[n + 1]; ++t) v += T.det_coef[t] * S[T.det_full[t]];
-        Mc[n] = v;  // padding is kept zero
-    }
+    p2m_cell(p, zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(p));
 }
 
 void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M) {
@@ -552,11 +497,14 @@ __device__ inline void lds_copy16(const void* g, void* lds) {
     __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-template <int P, int PREC>
+// ADAPT = true: the work unit is a tile of the adaptive tree (AdaptM2L):
+// targets, sources and the octant come from the tables instead of the
+// uniform grid, and rows are node indices.
+template <int P, int PREC, bool ADAPT>
 __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restrict__ Msrc, double* __restrict__ L,
                                                   const unsigned char* __restrict__ Kpk,
                                                   const int16_t* __restrict__ offlist,
-                                                  const unsigned char* __restrict__ zero_row) {
+                                                  const unsigned char* __restrict__ zero_row, const AdaptM2L ad) {
     using S = Tile<P, PREC>;
     constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB;
     constexpr int KU = S::KBYTES / 16;        // 16-byte units of one K_v
@@ -568,14 +516,14 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
 
     // work item = 8 * parent block + target octant; each XCD takes a contiguous
     // range, so the 8 octants of a block and neighbouring blocks share its L2
-    const long long work = xcd_remap(blockIdx.x, gridDim.x);
-    const int o = (int)(work & 7);
+    const long long work = ADAPT ? ad.tile_base + xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x);
+    const int o = ADAPT ? ad.tiles[work].x : (int)(work & 7);
     const long long pb = work >> 3;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int n1 = 1 << level;
-    const long long nparents = 1ll << (3 * (level - 1));
-    if (tid < 64) {
+    const long long nparents = ADAPT ? 0 : 1ll << (3 * (level - 1));
+    if (!ADAPT && tid < 64) {
         const long long par = (long long)pb * 64 + tid;
         int packed = -1;
         if (par < nparents) {
@@ -587,9 +535,9 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
     __syncthreads();
 
     auto stage_k = [&](int iv, int buf) {
-        const int vs = offlist[o * 189 + iv];
         // v is source - target; the operator is built for r = target - source = -v
-        const unsigned char* src = Kpk + (size_t)(NOFF - 1 - vs) * S::KBYTES;
+        const int ks = ADAPT ? ad.kslot[o * 189 + iv] : NOFF - 1 - offlist[o * 189 + iv];
+        const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
         unsigned char* dst = Kb + buf * S::KBYTES;
         for (int i = w; i * 64 < KU; i += 4) {
             const int u = i * 64 + lane;
@@ -600,6 +548,7 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
     // then every copy instruction moves whole rows whose address is read with
     // readlane (wave-uniform), so the per-lane work is one add
     auto src_rows = [&](int iv) -> int {
+        if (ADAPT) return ad.src[(189 * (size_t)work + iv) * 64 + lane];
         const int vs = offlist[o * 189 + iv];
         const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
         const int tc = tco[lane];
@@ -725,9 +674,16 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
             __syncthreads();
         }
     }
-    const long long par = (long long)pb * 64 + w * 16 + (lane & 15);
-    if (par >= nparents) return;
-    double* Lt = L + (size_t)(par * 8 + o) * LDM;
+    long long trow_out;
+    if (ADAPT) {
+        trow_out = ad.tgt[64 * (size_t)work + w * 16 + (lane & 15)];
+        if (trow_out < 0) return;
+    } else {
+        const long long par = (long long)pb * 64 + w * 16 + (lane & 15);
+        if (par >= nparents) return;
+        trow_out = par * 8 + o;
+    }
+    double* Lt = L + (size_t)trow_out * LDM;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (PREC == PREC_F64) {
@@ -922,22 +878,29 @@ hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L
     return hipGetLastError();
 }
 
-template <int P, int PREC>
-hipError_t m2l_tile_impl(hipStream_t s, int level, const void* Msrc, double* L, const unsigned char* Kpk,
-                         const int16_t* offlist, const unsigned char* zero_row) {
+template <int P, int PREC, bool ADAPT>
+hipError_t m2l_tile_impl(hipStream_t s, int level, long long nwork, const void* Msrc, double* L,
+                         const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row,
+                         const AdaptM2L& ad) {
     using S = Tile<P, PREC>;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC, ADAPT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
+    hipLaunchKernelGGL((k_m2l_tile<P, PREC, ADAPT>), dim3((unsigned)nwork), dim3(256), S::LDS, s, level, Msrc, L, Kpk,
+                       offlist, zero_row, ad);
+    return hipGetLastError();
+}
+
+template <int P, int PREC>
+hipError_t m2l_tile_impl(hipStream_t s, int level, const void* Msrc, double* L, const unsigned char* Kpk,
+                         const int16_t* offlist, const unsigned char* zero_row) {
     const long long nparents = 1ll << (3 * (level - 1));
     const long long nblk = (nparents + 63) / 64;
-    hipLaunchKernelGGL((k_m2l_tile<P, PREC>), dim3((unsigned)(8 * nblk)), dim3(256), S::LDS, s, level, Msrc, L,
-                       Kpk, offlist, zero_row);
-    return hipGetLastError();
+    return m2l_tile_impl<P, PREC, false>(s, level, 8 * nblk, Msrc, L, Kpk, offlist, zero_row, AdaptM2L{});
 }
 
 template <int P, int PREC>
@@ -963,6 +926,11 @@ static size_t tile_query(int p, int what) {
 size_t m2l_packed_bytes(int p, int prec) {
     return prec == PREC_F64 ? tile_query<PREC_F64>(p, 0) : prec == PREC_F32 ? tile_query<PREC_F32>(p, 0)
                                                                             : tile_query<PREC_BF16X3>(p, 0);
+}
+
+size_t m2l_tile_lds_bytes(int p, int prec) {
+    return prec == PREC_F64 ? tile_query<PREC_F64>(p, 1) : prec == PREC_F32 ? tile_query<PREC_F32>(p, 1)
+                                                                            : tile_query<PREC_BF16X3>(p, 1);
 }
 
 size_t m2l_lds_bytes(int p, int prec) {
@@ -1005,6 +973,23 @@ hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msr
         if (prec == PREC_F64) return m2l_tile_impl<PP, PREC_F64>(s, level, Msrc, L, Kpk, offlist, zero_row); \
         if (prec == PREC_F32) return m2l_halo32_impl<PP>(s, level, (const float*)Msrc, L, Kpk, offlist, zero_row); \
         return m2l_tile_impl<PP, PREC_BF16X3>(s, level, Msrc, L, Kpk, offlist, zero_row);
+        CTFMM_P_CASES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int ntiles, const AdaptM2L& ad, const void* Msrc,
+                             double* L, const unsigned char* Kpk, const unsigned char* zero_row) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (p) {
+#define CASE(PP)                                                                                                    \
+    case PP:                                                                                                        \
+        if (prec == PREC_F64)                                                                                       \
+            return m2l_tile_impl<PP, PREC_F64, true>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);            \
+        if (prec == PREC_F32)                                                                                       \
+            return m2l_tile_impl<PP, PREC_F32, true>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);            \
+        return m2l_tile_impl<PP, PREC_BF16X3, true>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
         CTFMM_P_CASES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

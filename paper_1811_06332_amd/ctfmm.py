@@ -14,13 +14,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libctfmm.so")
 
 CTFMM_OK, CTFMM_EINVAL, CTFMM_ENOMEM, CTFMM_EDEVICE, CTFMM_EUNSUPPORTED = 0, 1, 2, 3, 4
-CTFMM_TREE_UNIFORM = 0
+CTFMM_TREE_UNIFORM, CTFMM_TREE_ADAPTIVE = 0, 1
+TREES = {"uniform": CTFMM_TREE_UNIFORM, "adaptive": CTFMM_TREE_ADAPTIVE}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 CTFMM_P_MAX = 10
 CTFMM_DEPTH_MAX = 9
+CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
-            "ctfmm_evaluate", "ctfmm_copy_expansions", "ctfmm_set_timing", "ctfmm_stats",
+            "ctfmm_evaluate", "ctfmm_copy_expansions", "ctfmm_tree_stats", "ctfmm_set_timing", "ctfmm_stats",
             "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
 
@@ -32,15 +34,22 @@ class CtfmmError(RuntimeError):
 
 class ctfmm_params(C.Structure):
     _fields_ = [("order_p", C.c_int32), ("tree", C.c_int32), ("depth", C.c_int32), ("ws", C.c_int32),
-                ("precision", C.c_int32), ("reserved0", C.c_int32), ("root_lo", C.c_double * 3),
+                ("precision", C.c_int32), ("leaf_max", C.c_int32), ("root_lo", C.c_double * 3),
                 ("root_side", C.c_double)]
 
 
 class ctfmm_stats_t(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_tree", C.c_double), ("ms_p2m", C.c_double),
                 ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
-                ("ms_near", C.c_double), ("ms_convert", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
+                ("ms_near", C.c_double), ("ms_convert", C.c_double), ("ms_p2l", C.c_double),
+                ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
                 ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64)]
+
+
+class ctfmm_tree_stats_t(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("leaves", C.c_int64), ("max_level", C.c_int64), ("v_pairs", C.c_int64),
+                ("u_pairs", C.c_int64), ("w_pairs", C.c_int64), ("x_pairs", C.c_int64),
+                ("root_lo", C.c_double * 3), ("root_side", C.c_double)]
 
 
 _lib = None
@@ -60,6 +69,7 @@ def load():
         L.ctfmm_set_allocator.argtypes = [vp, vp, vp, vp]
         L.ctfmm_evaluate.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
+        L.ctfmm_tree_stats.argtypes = [vp, C.POINTER(ctfmm_tree_stats_t)]
         L.ctfmm_set_timing.argtypes = [vp, i32]
         L.ctfmm_stats.argtypes = [vp, C.POINTER(ctfmm_stats_t)]
         L.ctfmm_reset_stats.argtypes = [vp]
@@ -126,6 +136,14 @@ def ctfmm_copy_expansions(ctx, level: int, which: int, out) -> None:
            C.c_void_p(ctx))
 
 
+def ctfmm_tree_stats(ctx) -> dict:
+    st = ctfmm_tree_stats_t()
+    _check(load().ctfmm_tree_stats(C.c_void_p(ctx), C.byref(st)), C.c_void_p(ctx))
+    out = {name: getattr(st, name) for name, _ in ctfmm_tree_stats_t._fields_ if name != "root_lo"}
+    out["root_lo"] = tuple(st.root_lo)
+    return out
+
+
 def ctfmm_set_timing(ctx, on: bool) -> None:
     _check(load().ctfmm_set_timing(C.c_void_p(ctx), 1 if on else 0), C.c_void_p(ctx))
 
@@ -156,16 +174,25 @@ def ctfmm_destroy(ctx) -> None:
 # ---------------------------------------------------------------- convenience
 
 class FMM:
-    """A context bound to torch's current stream on the current device."""
+    """A context bound to torch's current stream on the current device.
 
-    def __init__(self, p: int, depth: int, precision: str = "fp64", root_lo=(0.0, 0.0, 0.0),
-                 root_side: float = 1.0, stream: int | None = None):
+    tree="uniform": octree of the given depth over the cube (root_lo, root_side).
+    tree="adaptive": leaves of at most leaf_max particles; depth is ignored and
+    root_side=None (or <= 0) selects the automatic root cube."""
+
+    def __init__(self, p: int, depth: int = 0, precision: str = "fp64", root_lo=(0.0, 0.0, 0.0),
+                 root_side: float | None = 1.0, stream: int | None = None, tree: str = "uniform",
+                 leaf_max: int = 64):
         prm = ctfmm_default_params()
         prm.order_p, prm.depth, prm.precision = p, depth, PRECISIONS[precision]
+        prm.tree, prm.leaf_max = TREES[tree], leaf_max
         prm.root_lo[0], prm.root_lo[1], prm.root_lo[2] = root_lo
-        prm.root_side = root_side
-        self.p, self.depth = p, depth
+        prm.root_side = 0.0 if root_side is None else root_side
+        self.p, self.depth, self.tree = p, depth, tree
         self.ctx = ctfmm_create(prm, stream)
+
+    def tree_stats(self) -> dict:
+        return ctfmm_tree_stats(self.ctx)
 
     def evaluate(self, xyz, q, phi=None, grad=None, sync=False):
         import torch

@@ -27,19 +27,26 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert F.ctfmm_version() == 1
+    assert F.ctfmm_version() == 2
     prm = F.ctfmm_default_params()
     assert (prm.order_p, prm.depth, prm.ws, prm.precision, prm.root_side) == (4, 3, 1, 0, 1.0)
+    assert (prm.tree, prm.leaf_max) == (F.CTFMM_TREE_UNIFORM, 64)
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("order_p", 11, F.CTFMM_EINVAL), ("order_p", -1, F.CTFMM_EINVAL), ("depth", 10, F.CTFMM_EINVAL),
     ("ws", 2, F.CTFMM_EINVAL), ("root_side", 0.0, F.CTFMM_EINVAL), ("root_side", float("nan"), F.CTFMM_EINVAL),
     ("tree", 7, F.CTFMM_EUNSUPPORTED),
+    # adaptive tree: leaf_max >= 1; root_side <= 0 is the automatic cube but must be finite
+    ("adaptive:leaf_max", 0, F.CTFMM_EINVAL), ("adaptive:root_side", float("inf"), F.CTFMM_EINVAL),
+    ("adaptive:order_p", 11, F.CTFMM_EINVAL),
 ])
 def test_create_rejects_bad_params(field, value, status):
     lib = F.load()
     prm = F.ctfmm_default_params()
+    if field.startswith("adaptive:"):
+        prm.tree = F.CTFMM_TREE_ADAPTIVE
+        field = field.split(":", 1)[1]
     setattr(prm, field, value)
     h = C.c_void_p()
     assert lib.ctfmm_create(C.byref(prm), None, C.byref(h)) == status
