@@ -100,14 +100,29 @@ __global__ __launch_bounds__(256) void k_bbox_partial(int n, const double* __res
 
 // reduce the partials; out = (lo[3], side): the cube centred on the bounding
 // box with side = largest extent * (1 + 2^-20), or 1 when all points coincide
-__global__ __launch_bounds__(64) void k_bbox_final(int nparts, const double* __restrict__ part, double* __restrict__ out) {
-    if (threadIdx.x != 0) return;
-    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nparts; ++b)
+__global__ __launch_bounds__(256) void k_bbox_final(int nparts, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double s6[6][256];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nparts; b += 256)
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
-            mn[d] = fmin(mn[d], part[6 * b + d]);
-            mx[d] = fmax(mx[d], part[6 * b + 3 + d]);
+            v[d] = fmin(v[d], part[6 * b + d]);
+            v[3 + d] = fmax(v[3 + d], part[6 * b + 3 + d]);
         }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s6[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                s6[d][threadIdx.x] = fmin(s6[d][threadIdx.x], s6[d][threadIdx.x + w]);
+                s6[3 + d][threadIdx.x] = fmax(s6[3 + d][threadIdx.x], s6[3 + d][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double mn[3] = {s6[0][0], s6[1][0], s6[2][0]}, mx[3] = {s6[3][0], s6[4][0], s6[5][0]};
     double s = 0.0;
     for (int d = 0; d < 3; ++d)
         if (mx[d] - mn[d] > s) s = mx[d] - mn[d];
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(64) void k_bbox_final(int nparts, const double* __r
 
 void launch_bbox(hipStream_t s, int n, const double* xyz, double* part, int nparts, double* out) {
     hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, s, n, xyz, part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, nparts, part, out);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, nparts, part, out);
 }
 
 // ------------------------------------------------------------------ keys
@@ -547,15 +562,17 @@ void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t
 
 // L~_n(B) += q D~_n((z_B - x_a)/h_B) for the particles a of every leaf in
 // X(B) (Eq. M2L with the multipole of a single charge at its own position,
-// in the scaled variables).  One wavefront per node of [first, first+count);
-// lanes take one particle each, their derivative tensors meet in LDS.
+// in the scaled variables).  One wavefront per node; the particles of all its
+// X leaves are taken 64 at a time as one sequence (lane i takes the i-th
+// particle after a wave-uniform cursor), and the lanes' derivative tensors
+// meet in LDS, where lane k sums component k.
 template <int P>
-__global__ __launch_bounds__(64) void k_p2l(int first, ABox box, ATree t, const int32_t* __restrict__ xoff,
+__global__ __launch_bounds__(64) void k_p2l(ABox box, ATree t, const int32_t* __restrict__ xoff,
                                             const int32_t* __restrict__ xlist, const double4* __restrict__ Pt,
                                             double* __restrict__ L) {
     constexpr int NC = (P + 1) * (P + 1);
     constexpr int STR = NC | 1;
-    const int B = first + blockIdx.x;
+    const int B = blockIdx.x;
     const int x0 = xoff[B], x1 = xoff[B + 1];
     if (x0 == x1) return;
     const int lane = threadIdx.x;
@@ -565,29 +582,52 @@ __global__ __launch_bounds__(64) void k_p2l(int first, ABox box, ATree t, const 
     double acc[KPL];
 #pragma unroll
     for (int k = 0; k < KPL; ++k) acc[k] = 0.0;
+    int total = 0;
     for (int xi = x0; xi < x1; ++xi) {
         const int C = xlist[xi];
-        const int b = t.pb[C], e = t.pe[C];
-        for (int s0 = b; s0 < e; s0 += 64) {
+        total += t.pe[C] - t.pb[C];
+    }
+    int cx = x0, cs = t.pb[xlist[x0]];  // cursor: X entry and particle of the next chunk
+    for (int base = 0; base < total; base += 64) {
+        const int cnt = min(64, total - base);
+        if (lane < cnt) {
+            int li = cx, ls = cs, rem = lane;
+            while (true) {
+                const int avail = t.pe[xlist[li]] - ls;
+                if (rem < avail) {
+                    ls += rem;
+                    break;
+                }
+                rem -= avail;
+                ++li;
+                ls = t.pb[xlist[li]];
+            }
+            const double4 pt = Pt[ls];
             double D[NC];
-            if (s0 + lane < e) {
-                const double4 pt = Pt[s0 + lane];
-                gen_dtensor<P>((G.zx - pt.x) / G.h, (G.zy - pt.y) / G.h, (G.zz - pt.z) / G.h, D);
+            gen_dtensor<P>((G.zx - pt.x) / G.h, (G.zy - pt.y) / G.h, (G.zz - pt.z) / G.h, D);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) Ds[lane * STR + k] = pt.w * D[k];
+            for (int k = 0; k < NC; ++k) Ds[lane * STR + k] = pt.w * D[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KPL; ++k) {
+            const int kk = lane + 64 * k;
+            if (kk < NC)
+                for (int i = 0; i < cnt; ++i) acc[k] += Ds[i * STR + kk];
+        }
+        __syncthreads();
+        // advance the cursor by the chunk
+        int rem = cnt;
+        while (rem > 0) {
+            const int avail = t.pe[xlist[cx]] - cs;
+            if (rem < avail) {
+                cs += rem;
+                rem = 0;
             } else {
-#pragma unroll
-                for (int k = 0; k < NC; ++k) Ds[lane * STR + k] = 0.0;
+                rem -= avail;
+                ++cx;
+                if (cx < x1) cs = t.pb[xlist[cx]];
             }
-            __syncthreads();
-            const int cnt = min(64, e - s0);
-#pragma unroll
-            for (int k = 0; k < KPL; ++k) {
-                const int kk = lane + 64 * k;
-                if (kk < NC)
-                    for (int i = 0; i < cnt; ++i) acc[k] += Ds[i * STR + kk];
-            }
-            __syncthreads();
         }
     }
     double* Lb = L + (size_t)B * ldm_of(P);
@@ -638,65 +678,110 @@ __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, 
     gz -= ir3 * dz;
 }
 
-// Far field of one sorted particle s in leaf B (one thread each), into F[s]:
-//   L2P of L~(B) (Eq. L2P), for B at level >= 2
-//   W(B): the multipole of each cell C evaluated at x (Eq. M2L at the
-//   particle, ranks 0 and 1 of the result).  Against a traceless M only the
-//   r^n part of D_n survives:
-//     sum_{|m|=n} M_m D_m(r)/m! = (-1)^n (2n-1)!! |r|^(-2n-1) sum_{|m|=n} M_m r^m/m!
-//   which is |r|^-1 times the rank-n polynomial of the weighted M^ at the
-//   inverted point w = r/|r|^2, so the generated L2P evaluates it.  The
-//   potential takes ranks 0..p; the gradient takes ranks 0..p-1 (the rank-1
-//   local components are truncated at |m| <= p-1) through the chain rule in w.
+// Far field of one sorted particle s (one thread each) from the local
+// expansion of its leaf B (Eq. L2P), into F[s]; zero for leaves above level 2.
 template <int P>
-__global__ __launch_bounds__(256) void k_far_adaptive(int n, ABox box, ATree t, const int32_t* __restrict__ leaf_of,
+__global__ __launch_bounds__(256) void k_l2p_adaptive(int n, ABox box, ATree t, const int32_t* __restrict__ leaf_of,
                                                       const double4* __restrict__ Pt, const double* __restrict__ L,
-                                                      const double* __restrict__ Mh,
-                                                      const int32_t* __restrict__ woff,
-                                                      const int32_t* __restrict__ wlist, double4* __restrict__ F) {
+                                                      double4* __restrict__ F) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int B = leaf_of[s];
     const int lb = node_level(t.info[B]);
-    const double4 pt = Pt[s];
-    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    double4 out = make_double4(0.0, 0.0, 0.0, 0.0);
     if (lb >= 2) {
+        const double4 pt = Pt[s];
         const NodeGeom G = node_geom(box, t.key[B], lb);
         double lf = 0.0, lx = 0.0, ly = 0.0, lz = 0.0;
         gen_l2p<P>((pt.x - G.zx) / G.h, (pt.y - G.zy) / G.h, (pt.z - G.zz) / G.h, L + (size_t)B * ldm_of(P), lf, lx,
                    ly, lz);
         const double ih2 = 1.0 / (G.h * G.h);
-        f = lf / G.h;
-        gx = lx * ih2;
-        gy = ly * ih2;
-        gz = lz * ih2;
+        out = make_double4(lf / G.h, lx * ih2, ly * ih2, lz * ih2);
     }
-    for (int j = woff[B]; j < woff[B + 1]; ++j) {
-        const int C = wlist[j];
-        const NodeGeom G = node_geom(box, t.key[C], node_level(t.info[C]));
-        const double ux = (pt.x - G.zx) / G.h, uy = (pt.y - G.zy) / G.h, uz = (pt.z - G.zz) / G.h;
-        const double r2 = ux * ux + uy * uy + uz * uz;
-        const double ir2 = 1.0 / r2;
-        const double ir = sqrt(ir2);
-        const double wx = ux * ir2, wy = uy * ir2, wz = uz * ir2;
-        const double* Mc = Mh + (size_t)C * ldm_of(P);
-        double f1 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
-        gen_l2p<P>(wx, wy, wz, Mc, f1, d0, d1, d2);
-        f += ir * f1 / G.h;
-        if (P >= 1) {
-            double f2 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-            gen_l2p<(P >= 1 ? P - 1 : 0)>(wx, wy, wz, Mc, f2, g0, g1, g2);
-            // grad_u [ |u|^-1 Q(w) ] = -u |u|^-3 Q + |u|^-1 (g/|u|^2 - 2 u (u.g)/|u|^4)
-            const double ug = ux * g0 + uy * g1 + uz * g2;
-            const double a = -ir * ir2 * f2 - 2.0 * ir * ir2 * ir2 * ug;
-            const double b = ir * ir2;
-            const double ih2 = 1.0 / (G.h * G.h);
-            gx += (a * ux + b * g0) * ih2;
-            gy += (a * uy + b * g1) * ih2;
-            gz += (a * uz + b * g2) * ih2;
-        }
+    F[s] = out;
+}
+
+// W(B): the multipole of each cell C in W(B) evaluated at B's particles (Eq.
+// M2L at the particle, ranks 0 and 1 of the result).  Against a traceless M
+// only the r^n part of D_n survives:
+//   sum_{|m|=n} M_m D_m(r)/m! = (-1)^n (2n-1)!! |r|^(-2n-1) sum_{|m|=n} M_m r^m/m!
+// which is |r|^-1 times the rank-n polynomial of the weighted M^ at the
+// inverted point w = r/|r|^2.  The potential takes ranks 0..p; the gradient
+// takes ranks 0..p-1 (the rank-1 local components are truncated at
+// |m| <= p-1), by the chain rule through w.
+template <int P>
+__device__ inline double4 m2p_eval(const ABox& box, const ATree& t, int C, double4 pt, const double* __restrict__ Mh) {
+    const NodeGeom G = node_geom(box, t.key[C], node_level(t.info[C]));
+    const double ux = (pt.x - G.zx) / G.h, uy = (pt.y - G.zy) / G.h, uz = (pt.z - G.zz) / G.h;
+    const double r2 = ux * ux + uy * uy + uz * uz;
+    const double ir2 = 1.0 / r2;
+    const double ir = sqrt(ir2);
+    double fl = 0.0, ft = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    gen_m2p<P>(ux * ir2, uy * ir2, uz * ir2, Mh + (size_t)C * ldm_of(P), fl, ft, g0, g1, g2);
+    const double ih = 1.0 / G.h;
+    // grad_u [ |u|^-1 Q(w) ] = -u |u|^-3 Q + |u|^-1 (g/|u|^2 - 2 u (u.g)/|u|^4), Q = ranks < p
+    const double ug = ux * g0 + uy * g1 + uz * g2;
+    const double a = -ir * ir2 * fl - 2.0 * ir * ir2 * ir2 * ug;
+    const double b = ir * ir2;
+    const double ih2 = ih * ih;
+    return make_double4(ir * (fl + ft) * ih, (a * ux + b * g0) * ih2, (a * uy + b * g1) * ih2,
+                        (a * uz + b * g2) * ih2);
+}
+
+// number of (target particle, W entry) pairs of every node
+__global__ void k_wpairs_count(int nn, ATree t, const int32_t* __restrict__ woff, long long* __restrict__ cnt) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nn) return;
+    cnt[B] = (long long)(woff[B + 1] - woff[B]) * (t.pe[B] - t.pb[B]);
+}
+
+void launch_wpairs_count(hipStream_t s, int nn, const ATree& t, const int32_t* woff, long long* cnt) {
+    hipLaunchKernelGGL(k_wpairs_count, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, t, woff, cnt);
+}
+
+// One thread per pair g, ordered [leaf B][W entry i][target]: the pair's
+// contribution into buf[g] (consecutive threads share the source cell)
+template <int P>
+__global__ __launch_bounds__(256) void k_m2p_pairs(long long npairs, int nn, ABox box, ATree t,
+                                                   const double4* __restrict__ Pt, const double* __restrict__ Mh,
+                                                   const int32_t* __restrict__ woff,
+                                                   const int32_t* __restrict__ wlist,
+                                                   const long long* __restrict__ poff, double4* __restrict__ buf) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npairs) return;
+    int lo = 0, hi = nn;  // last B with poff[B] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (poff[mid] <= g) lo = mid; else hi = mid;
     }
-    F[s] = make_double4(f, gx, gy, gz);
+    const int B = lo;
+    const int nt = t.pe[B] - t.pb[B];
+    const long long r = g - poff[B];
+    const int i = (int)(r / nt), tt = (int)(r % nt);
+    buf[g] = m2p_eval<P>(box, t, wlist[woff[B] + i], Pt[t.pb[B] + tt], Mh);
+}
+
+// F[s] += the W contributions of particle s, summed in list order
+__global__ __launch_bounds__(256) void k_m2p_reduce(int n, ATree t, const int32_t* __restrict__ leaf_of,
+                                                    const int32_t* __restrict__ woff,
+                                                    const long long* __restrict__ poff,
+                                                    const double4* __restrict__ buf, double4* __restrict__ F) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int B = leaf_of[s];
+    const int nw = woff[B + 1] - woff[B];
+    if (nw == 0) return;
+    const int nt = t.pe[B] - t.pb[B];
+    const int tt = s - t.pb[B];
+    double4 v = F[s];
+    for (int i = 0; i < nw; ++i) {
+        const double4 c = buf[poff[B] + (long long)i * nt + tt];
+        v.x += c.x;
+        v.y += c.y;
+        v.z += c.z;
+        v.w += c.w;
+    }
+    F[s] = v;
 }
 
 // Near field: one thread per sorted particle s in leaf B; direct sum over the
@@ -731,28 +816,34 @@ __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int3
     }
 }
 
-void launch_p2l(hipStream_t s, int p, int first, int count, ABox box, const ATree& t, const int32_t* xoff,
-                const int32_t* xlist, const double4* P, double* L) {
-    if (count <= 0) return;
+void launch_p2l(hipStream_t s, int p, int nn, ABox box, const ATree& t, const int32_t* xoff, const int32_t* xlist,
+                const double4* P, double* L) {
+    if (nn <= 0) return;
     switch (p) {
-#define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_p2l<PP>, dim3(count), dim3(64), 0, s, first, box, t, xoff, xlist, P, L); break;
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2l<PP>, dim3(nn), dim3(64), 0, s, box, t, xoff, xlist, P, L); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;
     }
 }
 
-void launch_near_adaptive(hipStream_t s, int p, int n, ABox box, const ATree& t, const int32_t* leaf_of,
-                          const double4* P, const double* L, const double* Mh, const int32_t* woff,
-                          const int32_t* wlist, const int32_t* uoff, const int32_t* ulist, const int32_t* idx,
-                          double4* F, double* phi, double* grad) {
+void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, ABox box, const ATree& t,
+                          const int32_t* leaf_of, const double4* P, const double* L, const double* Mh,
+                          const int32_t* woff, const int32_t* wlist, const long long* wpoff, double4* wbuf,
+                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, double* phi,
+                          double* grad) {
     if (n <= 0) return;
     const dim3 grid(cdiv(n, 256)), blk(256);
+    const dim3 wgrid((unsigned)((wpairs + 255) / 256));
     switch (p) {
-#define CASE(PP)                                                                                                    \
-    case PP:                                                                                                        \
-        hipLaunchKernelGGL(k_far_adaptive<PP>, grid, blk, 0, s, n, box, t, leaf_of, P, L, Mh, woff, wlist, F);      \
+#define CASE(PP)                                                                                                  \
+    case PP:                                                                                                      \
+        hipLaunchKernelGGL(k_l2p_adaptive<PP>, grid, blk, 0, s, n, box, t, leaf_of, P, L, F);                     \
+        if (wpairs > 0) {                                                                                         \
+            hipLaunchKernelGGL(k_m2p_pairs<PP>, wgrid, blk, 0, s, wpairs, nn, box, t, P, Mh, woff, wlist, wpoff,  \
+                               wbuf);                                                                             \
+            hipLaunchKernelGGL(k_m2p_reduce, grid, blk, 0, s, n, t, leaf_of, woff, wpoff, wbuf, F);               \
+        }                                                                                                         \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE

@@ -110,6 +110,11 @@ struct ctfmm_ctx {
     std::vector<int> lev_first, lev_count, tile_first, tile_count;
     std::vector<int4> tiles_host;
     int64_t tot_u = 0, tot_w = 0, tot_x = 0, v_pairs = -1;
+    long long* wcnt = nullptr;  // [nn+1] (target, W entry) pairs per node
+    long long* wpoff = nullptr; // [nn+1] their exclusive scan
+    double4* wbuf = nullptr;    // one contribution per pair
+    size_t wcnt_cap = 0, wpoff_cap = 0, wbuf_cap = 0;
+    long long wpairs = 0;
 
     // timing
     bool timing = false;
@@ -207,6 +212,9 @@ void reset_adaptive(ctfmm_ctx* c) {
     c->aM = c->aL = c->aMh = nullptr;
     c->aM32 = nullptr;
     c->aM_cap = c->aL_cap = c->aMh_cap = c->aM32_cap = 0;
+    c->wcnt = c->wpoff = nullptr;
+    c->wbuf = nullptr;
+    c->wcnt_cap = c->wpoff_cap = c->wbuf_cap = 0;
 }
 
 void dev_free_all(ctfmm_ctx* c) {
@@ -579,6 +587,22 @@ ctfmm_status build_adaptive(ctfmm_ctx* c, int n, const double* xyz, const double
     ACHK(grow(c, c->wlist, c->wlist_cap, (size_t)tot[1], false));
     ACHK(grow(c, c->xlist, c->xlist_cap, (size_t)tot[2], false));
     launch_lists(st, true, nn, c->tr, uc, wc, xc, uo, wo, xo, c->ulist, c->wlist, c->xlist);
+    // (target particle, W entry) pairs of the multipole evaluations
+    c->wpairs = 0;
+    if (c->tot_w > 0) {
+        ACHK(grow(c, c->wcnt, c->wcnt_cap, n1, false));
+        ACHK(grow(c, c->wpoff, c->wpoff_cap, n1, false));
+        HIPCHK(c, hipMemsetAsync(c->wcnt + nn, 0, sizeof(long long), st));
+        launch_wpairs_count(st, nn, c->tr, wo, c->wcnt);
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceScan::ExclusiveSum(t, b, c->wcnt, c->wpoff, (int)n1, st);
+        }));
+        long long wp = 0;
+        HIPCHK(c, hipMemcpyAsync(&wp, c->wpoff + nn, sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        c->wpairs = wp;
+        ACHK(grow(c, c->wbuf, c->wbuf_cap, (size_t)wp, false));
+    }
 
     // M2L tiles: nodes grouped by (level, octant), Morton order inside, 64 per tile
     ACHK(grow(c, c->lok, c->lok_cap, (size_t)nn, false));
@@ -641,7 +665,7 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
     const int p = c->prm.order_p;
     const int prec = c->prm.precision;
     const size_t ldm = (size_t)ldm_of(p);
-    // events: 0 start, 1 tree built, 2 P2M, 3 M2M, 4 conversions, 5 before the near field, then 4 per level
+    // events: 0 start, 1 tree built, 2 P2M, 3 M2M, 4 conversions, 6-9 M2L / P2L / L2L, 5 before the near field
     rec(c, 0);
     HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), st));
     SCHK(build_adaptive(c, n, xyz, q));
@@ -669,30 +693,29 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
         }
     }
     rec(c, 4);
-    int evi = 6;
-    for (int l = 2; l <= maxlev; ++l) {
-        rec(c, evi);
-        const AdaptM2L ad{c->tiles, c->tgt_tab, c->src_tab, c->alist + 8 * 189, c->tile_first[l]};
-        HIPCHK(c, launch_m2l_tables(st, p, prec, c->tile_count[l], ad, msrc, c->aL, c->Kpk, c->zero_row));
-        rec(c, evi + 1);
-        if (l >= 3) launch_l2l_nodes(st, p, c->lev_first[l - 1], c->lev_count[l - 1], c->tr, c->aL, c->T);
-        rec(c, evi + 2);
-        if (c->tot_x > 0)
-            launch_p2l(st, p, c->lev_first[l], c->lev_count[l], box, c->tr, c->loff + 2 * ((size_t)nn + 1), c->xlist,
-                       c->a_P, c->aL);
-        rec(c, evi + 3);
-        evi += 4;
+    // downward: L(B) = M2L(V) + P2L(X) + L2L(parent).  M2L over the tiles of
+    // every level at once (it reads only M), then the X lists, then L2L top-down.
+    rec(c, 6);
+    if (!c->tiles_host.empty()) {
+        const AdaptM2L ad{c->tiles, c->tgt_tab, c->src_tab, c->alist + 8 * 189, 0};
+        HIPCHK(c, launch_m2l_tables(st, p, prec, (int)c->tiles_host.size(), ad, msrc, c->aL, c->Kpk, c->zero_row));
     }
+    rec(c, 7);
+    if (c->tot_x > 0) launch_p2l(st, p, nn, box, c->tr, c->loff + 2 * ((size_t)nn + 1), c->xlist, c->a_P, c->aL);
+    rec(c, 8);
+    for (int l = 3; l <= maxlev; ++l)
+        launch_l2l_nodes(st, p, c->lev_first[l - 1], c->lev_count[l - 1], c->tr, c->aL, c->T);
+    rec(c, 9);
     rec(c, 5);
     const size_t n1 = (size_t)nn + 1;
-    launch_near_adaptive(st, p, n, box, c->tr, c->leaf_of, c->a_P, c->aL, c->aMh, c->loff + n1, c->wlist, c->loff,
-                         c->ulist, c->a_idxs, c->a_F, phi, grad);
+    launch_near_adaptive(st, p, n, nn, c->wpairs, box, c->tr, c->leaf_of, c->a_P, c->aL, c->aMh, c->loff + n1,
+                         c->wlist, c->wpoff, c->wbuf, c->loff, c->ulist, c->a_idxs, c->a_F, phi, grad);
     HIPCHK(c, hipGetLastError());
     const int ev_end = NPHASE_EV - 1;
     rec(c, ev_end);
     c->have_result = true;
     c->st.evaluations += 1;
-    c->st.m2l_launches += std::max(0, maxlev - 1);
+    c->st.m2l_launches += c->tiles_host.empty() ? 0 : 1;
     c->st.p2p_leaf_pairs += c->tot_u;
     if (c->timing) {
         SCHK(count_v_pairs(c));
@@ -704,13 +727,9 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
         c->st.ms_m2m += elapsed(c, 2, 3);
         c->st.ms_convert += elapsed(c, 3, 4);
         c->st.ms_near += elapsed(c, 5, ev_end);
-        int e = 6;
-        for (int l = 2; l <= maxlev; ++l) {
-            c->st.ms_m2l += elapsed(c, e, e + 1);
-            c->st.ms_l2l += elapsed(c, e + 1, e + 2);
-            c->st.ms_p2l += elapsed(c, e + 2, e + 3);
-            e += 4;
-        }
+        c->st.ms_m2l += elapsed(c, 6, 7);
+        c->st.ms_p2l += elapsed(c, 7, 8);
+        c->st.ms_l2l += elapsed(c, 8, 9);
     }
     return CTFMM_OK;
 }

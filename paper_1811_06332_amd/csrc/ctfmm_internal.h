@@ -226,12 +226,14 @@ void launch_p2m_nodes(hipStream_t s, int p, int first, int count, ABox box, cons
                       const DevTables& T, double* M);
 void launch_m2m_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* M, const DevTables& T);
 void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* L, const DevTables& T);
-void launch_p2l(hipStream_t s, int p, int first, int count, ABox box, const ATree& t, const int32_t* xoff,
-                const int32_t* xlist, const double4* P, double* L);
+void launch_p2l(hipStream_t s, int p, int nn, ABox box, const ATree& t, const int32_t* xoff, const int32_t* xlist,
+                const double4* P, double* L);
 void launch_mhat(hipStream_t s, int p, int first, int count, const double* M, double* Mh);
-void launch_near_adaptive(hipStream_t s, int p, int n, ABox box, const ATree& t, const int32_t* leaf_of,
-                          const double4* P, const double* L, const double* Mh, const int32_t* woff,
-                          const int32_t* wlist, const int32_t* uoff, const int32_t* ulist, const int32_t* idx,
-                          double4* F, double* phi, double* grad);
+void launch_wpairs_count(hipStream_t s, int nn, const ATree& t, const int32_t* woff, long long* cnt);
+void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, ABox box, const ATree& t,
+                          const int32_t* leaf_of, const double4* P, const double* L, const double* Mh,
+                          const int32_t* woff, const int32_t* wlist, const long long* wpoff, double4* wbuf,
+                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, double* phi,
+                          double* grad);
 
 }  // namespace ctfmm
