@@ -112,10 +112,12 @@ typedef struct ctfmm_stats_t {
     double ms_convert;      /* FP32 copies of the multipoles for the FP32/BF16 M2L modes
                                (adaptive tree: also the weighted multipoles of the W list) */
     double ms_p2l;          /* adaptive tree: local expansions formed from X-list particles */
+    double ms_numeric;      /* batched evaluation: every numeric pass (one graph launch) */
     int64_t evaluations;
     int64_t m2l_launches;
     int64_t m2l_pairs;      /* cell pairs translated by M2L, summed over calls */
     int64_t p2p_leaf_pairs; /* leaf pairs of the near field, summed over calls */
+    int64_t graph_launches; /* batched evaluations replayed from the captured graph */
 } ctfmm_stats_t;
 
 /* Shape of the tree and interaction lists built by the last evaluate. */
@@ -167,6 +169,25 @@ ctfmm_status ctfmm_set_allocator(ctfmm_ctx* ctx, ctfmm_alloc_fn alloc, ctfmm_fre
  * The workspace grows to fit n and is kept for later calls. */
 ctfmm_status ctfmm_evaluate(ctfmm_ctx* ctx, int64_t n, const double* xyz, const double* q,
                             double* phi, double* grad);
+
+/* Potential and gradient of nsys independent systems in one call (adaptive
+ * tree only).  System s is particles offsets[s] .. offsets[s+1]-1 of the
+ * concatenated arrays (same layouts as ctfmm_evaluate) and is expanded to
+ * order orders[s] (0..CTFMM_P_MAX) in its own automatic root cube; systems
+ * never interact.  Systems of one order share every launch: the trees of
+ * all of them form one forest, built on the device (the call waits for the
+ * stream once per tree level and a few times more), and one M2L launch
+ * serves every level of every system of that order.  The numeric passes of
+ * all forests are replayed from a captured HIP graph when the launch
+ * signature (sizes and buffers) equals that of the previous call, and run
+ * eagerly (then captured on the next call) when it changed.
+ *   offsets  host, nsys+1 int64, offsets[0] = 0, non-decreasing, total < 2^31
+ *   orders   host, nsys int32
+ * Outputs are in input order.  Timing reports ms_total, ms_tree (keys,
+ * trees, lists) and ms_numeric.  Errors: EINVAL (bad offsets or orders,
+ * null pointers), EUNSUPPORTED (uniform tree), ENOMEM, EDEVICE. */
+ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* ctx, int32_t nsys, const int64_t* offsets, const int32_t* orders,
+                                    const double* xyz, const double* q, double* phi, double* grad);
 
 /* Copy the expansions of one level of the last evaluate to host memory:
  * which = 0 for the multipoles M, 1 for the local expansions L.  The

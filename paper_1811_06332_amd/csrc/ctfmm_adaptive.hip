@@ -64,6 +64,20 @@ __device__ inline bool adjacent(uint64_t ka, int la, uint64_t kb, int lb) {
     return true;
 }
 
+__device__ inline NodeGeom node_geom(const ABox* boxes, const ATree& t, int g) {
+    return node_geom(boxes[t.sys[g]], t.key[g], node_level(t.info[g]));
+}
+
+// position of i among the sorted offsets off[0..m] (off[k] <= i < off[k+1])
+__device__ inline int seg_of(const int32_t* off, int m, int i) {
+    int lo = 0, hi = m;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ root cube
@@ -136,6 +150,52 @@ __global__ __launch_bounds__(256) void k_bbox_final(int nparts, const double* __
     out[3] = s;
 }
 
+// one block per system: its automatic root cube (as k_bbox_final)
+__global__ __launch_bounds__(256) void k_bbox_systems(ASys sy, const double* __restrict__ xyz, ABox* __restrict__ boxes) {
+    const int sidx = blockIdx.x;
+    const long long b = sy.gbase[sidx], cnt = sy.goff[sidx + 1] - sy.goff[sidx];
+    __shared__ double s6[6][256];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (long long i = threadIdx.x; i < cnt; i += 256)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double x = xyz[3 * (b + i) + d];
+            v[d] = fmin(v[d], x);
+            v[3 + d] = fmax(v[3 + d], x);
+        }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s6[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                s6[d][threadIdx.x] = fmin(s6[d][threadIdx.x], s6[d][threadIdx.x + w]);
+                s6[3 + d][threadIdx.x] = fmax(s6[3 + d][threadIdx.x], s6[3 + d][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double mn[3] = {s6[0][0], s6[1][0], s6[2][0]}, mx[3] = {s6[3][0], s6[4][0], s6[5][0]};
+    double sd = 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (mx[d] - mn[d] > sd) sd = mx[d] - mn[d];
+    if (!(sd > 0.0)) sd = 1.0;
+    sd = sd * (1.0 + 1.0 / 1048576.0);
+    ABox bx;
+    for (int d = 0; d < 3; ++d) {
+        const double mid = (mn[d] + mx[d]) * 0.5;
+        const double half = sd * 0.5;
+        bx.lo[d] = cnt > 0 ? mid - half : 0.0;
+    }
+    bx.side = sd;
+    boxes[sidx] = bx;
+}
+
+void launch_bbox_systems(hipStream_t s, const ASys& sy, const double* xyz, ABox* boxes) {
+    hipLaunchKernelGGL(k_bbox_systems, dim3(sy.nsys), dim3(256), 0, s, sy, xyz, boxes);
+}
+
 void launch_bbox(hipStream_t s, int n, const double* xyz, double* part, int nparts, double* out) {
     hipLaunchKernelGGL(k_bbox_partial, dim3(nparts), dim3(256), 0, s, n, xyz, part);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, nparts, part, out);
@@ -152,36 +212,44 @@ __device__ inline uint64_t acoord(double x, double lo, double side) {
     return (uint64_t)s;
 }
 
-__global__ void k_keys64(int n, const double* __restrict__ xyz, ABox box, uint64_t* __restrict__ keys,
-                         int32_t* __restrict__ idx, int* __restrict__ err) {
+__global__ void k_keys64(int n, ASys sy, const double* __restrict__ xyz, const ABox* __restrict__ boxes,
+                         uint64_t* __restrict__ keys, int32_t* __restrict__ idx, int* __restrict__ err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
+    const int sidx = sy.nsys == 1 ? 0 : seg_of(sy.goff, sy.nsys, i);
+    const size_t gi = (size_t)sy.gbase[sidx] + (size_t)(i - sy.goff[sidx]);
+    const ABox box = boxes[sidx];
+    const double x = xyz[3 * gi], y = xyz[3 * gi + 1], z = xyz[3 * gi + 2];
     if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(err, 1);
     keys[i] = spread21(acoord(x, box.lo[0], box.side)) | (spread21(acoord(y, box.lo[1], box.side)) << 1) |
               (spread21(acoord(z, box.lo[2], box.side)) << 2);
-    idx[i] = i;
+    idx[i] = (int32_t)gi;
 }
 
-void launch_keys64(hipStream_t s, int n, const double* xyz, ABox box, uint64_t* keys, int32_t* idx, int* err) {
+void launch_keys64(hipStream_t s, int n, const ASys& sy, const double* xyz, const ABox* boxes, uint64_t* keys,
+                   int32_t* idx, int* err) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_keys64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, xyz, box, keys, idx, err);
+    hipLaunchKernelGGL(k_keys64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, xyz, boxes, keys, idx, err);
 }
 
 // ------------------------------------------------------------------ tree
 
-__global__ void k_root(int n, ATree t) {
-    if (threadIdx.x == 0) {
-        t.key[0] = 0;
-        t.pb[0] = 0;
-        t.pe[0] = n;
-        t.par[0] = -1;
-        t.info[0] = 0;
-    }
-    if (threadIdx.x < 27) t.nb[threadIdx.x] = threadIdx.x == 13 ? 0 : -1;
+// one root per system: its forest positions, level 0, neighbour table = itself
+__global__ void k_roots(ASys sy, ATree t) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= sy.nsys) return;
+    t.key[r] = 0;
+    t.pb[r] = sy.goff[r];
+    t.pe[r] = sy.goff[r + 1];
+    t.par[r] = -1;
+    t.info[r] = 0;
+    t.sys[r] = r;
+    for (int d = 0; d < 27; ++d) t.nb[27 * (size_t)r + d] = d == 13 ? r : -1;
 }
 
-void launch_root(hipStream_t s, int n, const ATree& t) { hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, s, n, t); }
+void launch_roots(hipStream_t s, const ASys& sy, const ATree& t) {
+    hipLaunchKernelGGL(k_roots, dim3(cdiv(sy.nsys, 64)), dim3(64), 0, s, sy, t);
+}
 
 // For each node of one level: leaf flag, and for a split node the particle
 // range of each octant (binary search of the sorted keys inside its range).
@@ -239,6 +307,7 @@ __global__ void k_emit(int level, int first, int count, int next_first, const in
     t.pe[c] = ce;
     t.par[c] = g;
     t.info[c] = level + 1;
+    t.sys[c] = t.sys[g];
     t.child[8 * (size_t)g + o] = c;
 }
 
@@ -452,19 +521,19 @@ void launch_m2l_tables(hipStream_t s, int ntiles, const int4* tiles, const int32
 // ------------------------------------------------------------------ P2M, M2M, L2L on node lists
 
 // P2M of every leaf among nodes [first, first+count): one wavefront per node
-__global__ __launch_bounds__(64) void k_p2m_nodes(int p, int first, ABox box, ATree t, const double4* __restrict__ P,
+__global__ __launch_bounds__(64) void k_p2m_nodes(int p, int first, const ABox* __restrict__ boxes, ATree t, const double4* __restrict__ P,
                                                   DevTables T, double* __restrict__ M) {
     const int g = first + blockIdx.x;
     const int info = t.info[g];
     if (!node_leaf(info)) return;
-    const NodeGeom G = node_geom(box, t.key[g], node_level(info));
+    const NodeGeom G = node_geom(boxes, t, g);
     p2m_cell(p, G.zx, G.zy, G.zz, G.h, t.pb[g], t.pe[g], P, T, M + (size_t)g * ldm_of(p));
 }
 
-void launch_p2m_nodes(hipStream_t s, int p, int first, int count, ABox box, const ATree& t, const double4* P,
+void launch_p2m_nodes(hipStream_t s, int p, int first, int count, const ABox* boxes, const ATree& t, const double4* P,
                       const DevTables& T, double* M) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_p2m_nodes, dim3(count), dim3(64), 0, s, p, first, box, t, P, T, M);
+    hipLaunchKernelGGL(k_p2m_nodes, dim3(count), dim3(64), 0, s, p, first, boxes, t, P, T, M);
 }
 
 constexpr int ANP = 8;  // parents per workgroup in M2M/L2L
@@ -567,7 +636,7 @@ void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t
 // particle after a wave-uniform cursor), and the lanes' derivative tensors
 // meet in LDS, where lane k sums component k.
 template <int P>
-__global__ __launch_bounds__(64) void k_p2l(ABox box, ATree t, const int32_t* __restrict__ xoff,
+__global__ __launch_bounds__(64) void k_p2l(const ABox* __restrict__ boxes, ATree t, const int32_t* __restrict__ xoff,
                                             const int32_t* __restrict__ xlist, const double4* __restrict__ Pt,
                                             double* __restrict__ L) {
     constexpr int NC = (P + 1) * (P + 1);
@@ -576,7 +645,7 @@ __global__ __launch_bounds__(64) void k_p2l(ABox box, ATree t, const int32_t* __
     const int x0 = xoff[B], x1 = xoff[B + 1];
     if (x0 == x1) return;
     const int lane = threadIdx.x;
-    const NodeGeom G = node_geom(box, t.key[B], node_level(t.info[B]));
+    const NodeGeom G = node_geom(boxes, t, B);
     __shared__ double Ds[64 * STR];
     constexpr int KPL = (NC + 63) / 64;
     double acc[KPL];
@@ -681,7 +750,7 @@ __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, 
 // Far field of one sorted particle s (one thread each) from the local
 // expansion of its leaf B (Eq. L2P), into F[s]; zero for leaves above level 2.
 template <int P>
-__global__ __launch_bounds__(256) void k_l2p_adaptive(int n, ABox box, ATree t, const int32_t* __restrict__ leaf_of,
+__global__ __launch_bounds__(256) void k_l2p_adaptive(int n, const ABox* __restrict__ boxes, ATree t, const int32_t* __restrict__ leaf_of,
                                                       const double4* __restrict__ Pt, const double* __restrict__ L,
                                                       double4* __restrict__ F) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -691,7 +760,7 @@ __global__ __launch_bounds__(256) void k_l2p_adaptive(int n, ABox box, ATree t, 
     double4 out = make_double4(0.0, 0.0, 0.0, 0.0);
     if (lb >= 2) {
         const double4 pt = Pt[s];
-        const NodeGeom G = node_geom(box, t.key[B], lb);
+        const NodeGeom G = node_geom(boxes, t, B);
         double lf = 0.0, lx = 0.0, ly = 0.0, lz = 0.0;
         gen_l2p<P>((pt.x - G.zx) / G.h, (pt.y - G.zy) / G.h, (pt.z - G.zz) / G.h, L + (size_t)B * ldm_of(P), lf, lx,
                    ly, lz);
@@ -710,8 +779,8 @@ __global__ __launch_bounds__(256) void k_l2p_adaptive(int n, ABox box, ATree t, 
 // takes ranks 0..p-1 (the rank-1 local components are truncated at
 // |m| <= p-1), by the chain rule through w.
 template <int P>
-__device__ inline double4 m2p_eval(const ABox& box, const ATree& t, int C, double4 pt, const double* __restrict__ Mh) {
-    const NodeGeom G = node_geom(box, t.key[C], node_level(t.info[C]));
+__device__ inline double4 m2p_eval(const ABox* __restrict__ boxes, const ATree& t, int C, double4 pt, const double* __restrict__ Mh) {
+    const NodeGeom G = node_geom(boxes, t, C);
     const double ux = (pt.x - G.zx) / G.h, uy = (pt.y - G.zy) / G.h, uz = (pt.z - G.zz) / G.h;
     const double r2 = ux * ux + uy * uy + uz * uz;
     const double ir2 = 1.0 / r2;
@@ -742,7 +811,7 @@ void launch_wpairs_count(hipStream_t s, int nn, const ATree& t, const int32_t* w
 // One thread per pair g, ordered [leaf B][W entry i][target]: the pair's
 // contribution into buf[g] (consecutive threads share the source cell)
 template <int P>
-__global__ __launch_bounds__(256) void k_m2p_pairs(long long npairs, int nn, ABox box, ATree t,
+__global__ __launch_bounds__(256) void k_m2p_pairs(long long npairs, int nn, const ABox* __restrict__ boxes, ATree t,
                                                    const double4* __restrict__ Pt, const double* __restrict__ Mh,
                                                    const int32_t* __restrict__ woff,
                                                    const int32_t* __restrict__ wlist,
@@ -758,7 +827,7 @@ __global__ __launch_bounds__(256) void k_m2p_pairs(long long npairs, int nn, ABo
     const int nt = t.pe[B] - t.pb[B];
     const long long r = g - poff[B];
     const int i = (int)(r / nt), tt = (int)(r % nt);
-    buf[g] = m2p_eval<P>(box, t, wlist[woff[B] + i], Pt[t.pb[B] + tt], Mh);
+    buf[g] = m2p_eval<P>(boxes, t, wlist[woff[B] + i], Pt[t.pb[B] + tt], Mh);
 }
 
 // F[s] += the W contributions of particle s, summed in list order
@@ -786,13 +855,13 @@ __global__ __launch_bounds__(256) void k_m2p_reduce(int n, ATree t, const int32_
 
 // Near field: one thread per sorted particle s in leaf B; direct sum over the
 // particles of the leaves in U(B), self excluded, plus the far field F[s].
-// Writes phi and grad in input order.
+// Writes phi and grad in input order, or with to_F the total back into F[s].
 __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int32_t* __restrict__ leaf_of,
-                                                      const double4* __restrict__ Pt, const double4* __restrict__ F,
+                                                      const double4* __restrict__ Pt, double4* __restrict__ F,
                                                       const int32_t* __restrict__ uoff,
                                                       const int32_t* __restrict__ ulist,
-                                                      const int32_t* __restrict__ idx, double* __restrict__ phi,
-                                                      double* __restrict__ grad) {
+                                                      const int32_t* __restrict__ idx, bool to_F,
+                                                      double* __restrict__ phi, double* __restrict__ grad) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int B = leaf_of[s];
@@ -807,6 +876,10 @@ __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int3
             pair_add_a(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
         }
     }
+    if (to_F) {
+        F[s] = make_double4(f, gx, gy, gz);
+        return;
+    }
     const size_t o = (size_t)idx[s];
     if (phi) phi[o] = f;
     if (grad) {
@@ -816,31 +889,52 @@ __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int3
     }
 }
 
-void launch_p2l(hipStream_t s, int p, int nn, ABox box, const ATree& t, const int32_t* xoff, const int32_t* xlist,
+// F (sorted order) -> phi, grad (input order)
+__global__ __launch_bounds__(256) void k_scatter_out(int n, const int32_t* __restrict__ idx,
+                                                     const double4* __restrict__ F, double* __restrict__ phi,
+                                                     double* __restrict__ grad) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double4 v = F[s];
+    const size_t o = (size_t)idx[s];
+    if (phi) phi[o] = v.x;
+    if (grad) {
+        grad[3 * o] = v.y;
+        grad[3 * o + 1] = v.z;
+        grad[3 * o + 2] = v.w;
+    }
+}
+
+void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scatter_out, dim3(cdiv(n, 256)), dim3(256), 0, s, n, idx, F, phi, grad);
+}
+
+void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const int32_t* xoff, const int32_t* xlist,
                 const double4* P, double* L) {
     if (nn <= 0) return;
     switch (p) {
-#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2l<PP>, dim3(nn), dim3(64), 0, s, box, t, xoff, xlist, P, L); break;
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2l<PP>, dim3(nn), dim3(64), 0, s, boxes, t, xoff, xlist, P, L); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;
     }
 }
 
-void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, ABox box, const ATree& t,
+void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, const ABox* boxes, const ATree& t,
                           const int32_t* leaf_of, const double4* P, const double* L, const double* Mh,
                           const int32_t* woff, const int32_t* wlist, const long long* wpoff, double4* wbuf,
-                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, double* phi,
-                          double* grad) {
+                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, bool to_F,
+                          double* phi, double* grad) {
     if (n <= 0) return;
     const dim3 grid(cdiv(n, 256)), blk(256);
     const dim3 wgrid((unsigned)((wpairs + 255) / 256));
     switch (p) {
 #define CASE(PP)                                                                                                  \
     case PP:                                                                                                      \
-        hipLaunchKernelGGL(k_l2p_adaptive<PP>, grid, blk, 0, s, n, box, t, leaf_of, P, L, F);                     \
+        hipLaunchKernelGGL(k_l2p_adaptive<PP>, grid, blk, 0, s, n, boxes, t, leaf_of, P, L, F);                     \
         if (wpairs > 0) {                                                                                         \
-            hipLaunchKernelGGL(k_m2p_pairs<PP>, wgrid, blk, 0, s, wpairs, nn, box, t, P, Mh, woff, wlist, wpoff,  \
+            hipLaunchKernelGGL(k_m2p_pairs<PP>, wgrid, blk, 0, s, wpairs, nn, boxes, t, P, Mh, woff, wlist, wpoff,  \
                                wbuf);                                                                             \
             hipLaunchKernelGGL(k_m2p_reduce, grid, blk, 0, s, n, t, leaf_of, woff, wpoff, wbuf, F);               \
         }                                                                                                         \
@@ -849,7 +943,7 @@ void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs,
 #undef CASE
         default: break;
     }
-    hipLaunchKernelGGL(k_p2p_adaptive, grid, blk, 0, s, n, t, leaf_of, P, F, uoff, ulist, idx, phi, grad);
+    hipLaunchKernelGGL(k_p2p_adaptive, grid, blk, 0, s, n, t, leaf_of, P, F, uoff, ulist, idx, to_F, phi, grad);
 }
 
 }  // namespace ctfmm

@@ -23,6 +23,82 @@ constexpr int NPHASE_EV = 8 + 4 * (AMAX + 1);
 
 }  // namespace
 
+// Operators of one expansion order in the context's M2L precision.
+struct OpSet {
+    int p = -1;
+    double* Dv = nullptr;
+    double* Kt = nullptr;
+    unsigned char* Kpk = nullptr;
+};
+
+// Workspace of one forest of adaptive trees (all systems of one order p);
+// every device buffer grows on demand.
+struct Forest {
+    int p = 0;
+    int nsys = 0;
+    int n = 0;
+    std::vector<int32_t> goff_h, gbase_h;
+    int32_t* goff = nullptr;
+    int32_t* gbase = nullptr;
+    size_t goff_cap = 0, gbase_cap = 0;
+    ABox* boxes = nullptr;
+    size_t boxes_cap = 0;
+    uint64_t* k64 = nullptr;
+    uint64_t* k64s = nullptr;
+    size_t k64_cap = 0, k64s_cap = 0;
+    int32_t* a_idx = nullptr;
+    int32_t* a_idxs = nullptr;
+    int32_t* leaf_of = nullptr;
+    size_t a_idx_cap = 0, a_idxs_cap = 0, leaf_of_cap = 0;
+    double4* a_P = nullptr;
+    double4* a_F = nullptr;  // far field per sorted particle
+    size_t a_P_cap = 0, a_F_cap = 0;
+    double* bbox = nullptr;  // [NBB][6] partial bounds, then lo[3], side
+    size_t bbox_cap = 0;
+    ATree tr{};
+    size_t ncap = 0;
+    int nn = 0;
+    int32_t* sflag = nullptr;
+    int32_t* sincl = nullptr;
+    int32_t* scstart = nullptr;
+    size_t sflag_cap = 0, sincl_cap = 0, scstart_cap = 0;
+    int32_t* lcnt = nullptr;  // [3][nn+1] U, W, X counts
+    int32_t* loff = nullptr;  // [3][nn+1] exclusive scans
+    size_t lcnt_cap = 0, loff_cap = 0;
+    int32_t* ulist = nullptr;
+    int32_t* wlist = nullptr;
+    int32_t* xlist = nullptr;
+    size_t ulist_cap = 0, wlist_cap = 0, xlist_cap = 0;
+    uint32_t* lok = nullptr;
+    uint32_t* loks = nullptr;
+    int32_t* lov = nullptr;
+    int32_t* lovs = nullptr;
+    size_t lok_cap = 0, loks_cap = 0, lov_cap = 0, lovs_cap = 0;
+    int32_t* bse = nullptr;  // [2][256] (level, octant) bucket bounds
+    size_t bse_cap = 0;
+    int4* tiles = nullptr;
+    int32_t* tgt_tab = nullptr;
+    int32_t* src_tab = nullptr;
+    int32_t* vcount = nullptr;
+    size_t tiles_cap = 0, tgt_cap = 0, src_cap = 0, vcount_cap = 0;
+    int32_t* vsum = nullptr;
+    size_t vsum_cap = 0;
+    double* aM = nullptr;
+    double* aL = nullptr;
+    double* aMh = nullptr;
+    float* aM32 = nullptr;
+    size_t aM_cap = 0, aL_cap = 0, aMh_cap = 0, aM32_cap = 0;
+    long long* wcnt = nullptr;  // [nn+1] (target, W entry) pairs per node
+    long long* wpoff = nullptr; // [nn+1] their exclusive scan
+    double4* wbuf = nullptr;    // one contribution per pair
+    size_t wcnt_cap = 0, wpoff_cap = 0, wbuf_cap = 0;
+    long long wpairs = 0;
+    std::vector<int> lev_first, lev_count;
+    std::vector<int4> tiles_host;
+    int64_t tot_u = 0, tot_w = 0, tot_x = 0, v_pairs = -1;
+    const unsigned char* Kpk = nullptr;  // operators of order p
+};
+
 struct ctfmm_ctx {
     ctfmm_params prm{};
     hipStream_t stream = nullptr;
@@ -61,60 +137,18 @@ struct ctfmm_ctx {
 
     int16_t* alist = nullptr;      // [8][189] (q << 5 | u) per target octant, then [8][189] operator slots
 
-    // adaptive tree workspace (every buffer grows on demand)
-    ABox abox{};
-    uint64_t* k64 = nullptr;
-    uint64_t* k64s = nullptr;
-    size_t k64_cap = 0, k64s_cap = 0;
-    int32_t* a_idx = nullptr;
-    int32_t* a_idxs = nullptr;
-    int32_t* leaf_of = nullptr;
-    size_t a_idx_cap = 0, a_idxs_cap = 0, leaf_of_cap = 0;
-    double4* a_P = nullptr;
-    double4* a_F = nullptr;  // far field per sorted particle
-    size_t a_P_cap = 0, a_F_cap = 0;
-    double* bbox = nullptr;  // [NBB][6] partial bounds, then lo[3], side
-    ATree tr{};
-    size_t ncap = 0;
-    int nn = 0;
-    int32_t* sflag = nullptr;
-    int32_t* sincl = nullptr;
-    int32_t* scstart = nullptr;
-    size_t sflag_cap = 0, sincl_cap = 0, scstart_cap = 0;
+    // adaptive trees: operators of further orders, forests (one per order in a
+    // batch; [0] for a single system), the shared hipcub scratch buffer and the
+    // graph of the batched numeric passes
+    std::vector<OpSet> opsets;
+    std::vector<Forest> forests;
+    int nforests = 0;
     unsigned char* tmp = nullptr;
     size_t tmp_cap = 0;
-    int32_t* lcnt = nullptr;  // [3][nn+1] U, W, X counts
-    int32_t* loff = nullptr;  // [3][nn+1] exclusive scans
-    size_t lcnt_cap = 0, loff_cap = 0;
-    int32_t* ulist = nullptr;
-    int32_t* wlist = nullptr;
-    int32_t* xlist = nullptr;
-    size_t ulist_cap = 0, wlist_cap = 0, xlist_cap = 0;
-    uint32_t* lok = nullptr;
-    uint32_t* loks = nullptr;
-    int32_t* lov = nullptr;
-    int32_t* lovs = nullptr;
-    size_t lok_cap = 0, loks_cap = 0, lov_cap = 0, lovs_cap = 0;
-    int32_t* bse = nullptr;  // [2][256] (level, octant) bucket bounds
-    int4* tiles = nullptr;
-    int32_t* tgt_tab = nullptr;
-    int32_t* src_tab = nullptr;
-    int32_t* vcount = nullptr;
-    size_t tiles_cap = 0, tgt_cap = 0, src_cap = 0, vcount_cap = 0;
-    int32_t* vsum = nullptr;
-    double* aM = nullptr;
-    double* aL = nullptr;
-    double* aMh = nullptr;
-    float* aM32 = nullptr;
-    size_t aM_cap = 0, aL_cap = 0, aMh_cap = 0, aM32_cap = 0;
-    std::vector<int> lev_first, lev_count, tile_first, tile_count;
-    std::vector<int4> tiles_host;
-    int64_t tot_u = 0, tot_w = 0, tot_x = 0, v_pairs = -1;
-    long long* wcnt = nullptr;  // [nn+1] (target, W entry) pairs per node
-    long long* wpoff = nullptr; // [nn+1] their exclusive scan
-    double4* wbuf = nullptr;    // one contribution per pair
-    size_t wcnt_cap = 0, wpoff_cap = 0, wbuf_cap = 0;
-    long long wpairs = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+    std::vector<long long> gsig;
 
     // timing
     bool timing = false;
@@ -183,38 +217,16 @@ bool grow(ctfmm_ctx* c, T*& ptr, size_t& cap, size_t need, bool keep) {
 
 void reset_adaptive(ctfmm_ctx* c) {
     // pointers only: the buffers themselves are released with the rest
-    c->k64 = c->k64s = nullptr;
-    c->k64_cap = c->k64s_cap = 0;
-    c->a_idx = c->a_idxs = c->leaf_of = nullptr;
-    c->a_idx_cap = c->a_idxs_cap = c->leaf_of_cap = 0;
-    c->a_P = c->a_F = nullptr;
-    c->a_P_cap = c->a_F_cap = 0;
-    c->bbox = nullptr;
-    c->tr = ATree{};
-    c->ncap = 0;
-    c->nn = 0;
-    c->sflag = c->sincl = c->scstart = nullptr;
-    c->sflag_cap = c->sincl_cap = c->scstart_cap = 0;
+    c->opsets.clear();
+    c->forests.clear();
+    c->nforests = 0;
     c->tmp = nullptr;
     c->tmp_cap = 0;
-    c->lcnt = c->loff = nullptr;
-    c->lcnt_cap = c->loff_cap = 0;
-    c->ulist = c->wlist = c->xlist = nullptr;
-    c->ulist_cap = c->wlist_cap = c->xlist_cap = 0;
-    c->lok = c->loks = nullptr;
-    c->lov = c->lovs = nullptr;
-    c->lok_cap = c->loks_cap = c->lov_cap = c->lovs_cap = 0;
-    c->bse = nullptr;
-    c->tiles = nullptr;
-    c->tgt_tab = c->src_tab = c->vcount = nullptr;
-    c->tiles_cap = c->tgt_cap = c->src_cap = c->vcount_cap = 0;
-    c->vsum = nullptr;
-    c->aM = c->aL = c->aMh = nullptr;
-    c->aM32 = nullptr;
-    c->aM_cap = c->aL_cap = c->aMh_cap = c->aM32_cap = 0;
-    c->wcnt = c->wpoff = nullptr;
-    c->wbuf = nullptr;
-    c->wcnt_cap = c->wpoff_cap = c->wbuf_cap = 0;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gsig.clear();
 }
 
 void dev_free_all(ctfmm_ctx* c) {
@@ -305,7 +317,7 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     if (m2l_lds_bytes(p, prec) > (size_t)max_lds || m2l_tile_lds_bytes(p, prec) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
     c->Kpk = (unsigned char*)dev_alloc(c, m2l_packed_bytes(p, prec));
-    const size_t zbytes = std::max((size_t)ldm_of(p) * 8, (size_t)s32_of(p) * 4);
+    const size_t zbytes = std::max((size_t)ldm_of(PMAX) * 8, (size_t)s32_of(PMAX) * 4);
     c->zero_row = (unsigned char*)dev_alloc(c, zbytes);
     if (!c->Kpk || !c->zero_row) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
     HIPCHK(c, hipMemsetAsync(c->zero_row, 0, zbytes, c->stream));
@@ -447,30 +459,31 @@ int64_t near_pairs(int d) {
 
 constexpr int NBB = 1024;  // blocks of the bounding-box reduction
 
-bool grow_nodes(ctfmm_ctx* c, size_t need) {
-    if (c->tr.key && need <= c->ncap) return true;
-    const size_t ncap = std::max<size_t>(std::max<size_t>(need, 1024), c->ncap + c->ncap / 2);
-    const size_t old = c->ncap;
+bool grow_nodes(ctfmm_ctx* c, Forest& f, size_t need) {
+    if (f.tr.key && need <= f.ncap) return true;
+    const size_t ncap = std::max<size_t>(std::max<size_t>(need, 1024), f.ncap + f.ncap / 2);
+    const size_t old = f.ncap;
     size_t k;
-    k = old; if (!grow(c, c->tr.key, k, ncap, true)) return false;
-    k = old; if (!grow(c, c->tr.pb, k, ncap, true)) return false;
-    k = old; if (!grow(c, c->tr.pe, k, ncap, true)) return false;
-    k = old; if (!grow(c, c->tr.par, k, ncap, true)) return false;
-    k = old; if (!grow(c, c->tr.info, k, ncap, true)) return false;
-    k = 8 * old; if (!grow(c, c->tr.child, k, 8 * ncap, true)) return false;
-    k = 27 * old; if (!grow(c, c->tr.nb, k, 27 * ncap, true)) return false;
-    c->ncap = ncap;
+    k = old; if (!grow(c, f.tr.key, k, ncap, true)) return false;
+    k = old; if (!grow(c, f.tr.pb, k, ncap, true)) return false;
+    k = old; if (!grow(c, f.tr.pe, k, ncap, true)) return false;
+    k = old; if (!grow(c, f.tr.par, k, ncap, true)) return false;
+    k = old; if (!grow(c, f.tr.info, k, ncap, true)) return false;
+    k = old; if (!grow(c, f.tr.sys, k, ncap, true)) return false;
+    k = 8 * old; if (!grow(c, f.tr.child, k, 8 * ncap, true)) return false;
+    k = 27 * old; if (!grow(c, f.tr.nb, k, 27 * ncap, true)) return false;
+    f.ncap = ncap;
     return true;
 }
 
 // run a hipcub algorithm with the shared temporary buffer
 template <class F>
-ctfmm_status cub_run(ctfmm_ctx* c, F f) {
+ctfmm_status cub_run(ctfmm_ctx* c, F fn) {
     size_t bytes = 0;
-    HIPCHK(c, f(nullptr, bytes));
+    HIPCHK(c, fn(nullptr, bytes));
     if (!grow(c, c->tmp, c->tmp_cap, bytes, false)) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
     bytes = c->tmp_cap;
-    HIPCHK(c, f((void*)c->tmp, bytes));
+    HIPCHK(c, fn((void*)c->tmp, bytes));
     return CTFMM_OK;
 }
 
@@ -484,252 +497,306 @@ ctfmm_status cub_run(ctfmm_ctx* c, F f) {
         if (s_ != CTFMM_OK) return s_;      \
     } while (0)
 
-// keys, sort, the tree level by level, neighbour tables, U/W/X lists and the
-// M2L tile tables.  Waits for the stream once per tree level and a few
-// times more (sizes decide the next launches).
-ctfmm_status build_adaptive(ctfmm_ctx* c, int n, const double* xyz, const double* q) {
+// operators of order p in the context's precision (built on first use)
+ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
+    if (p == c->prm.order_p) {
+        *kpk = c->Kpk;
+        return CTFMM_OK;
+    }
+    for (const OpSet& o : c->opsets)
+        if (o.p == p) {
+            *kpk = o.Kpk;
+            return CTFMM_OK;
+        }
+    const int prec = c->prm.precision;
+    int max_lds = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    if (m2l_tile_lds_bytes(p, prec) > (size_t)max_lds)
+        return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
+    const size_t nc = (size_t)(p + 1) * (p + 1);
+    OpSet o;
+    o.p = p;
+    o.Dv = (double*)dev_alloc(c, (size_t)NOFF * NIND * sizeof(double));
+    o.Kt = (double*)dev_alloc(c, (size_t)NOFF * nc * nc * sizeof(double));
+    o.Kpk = (unsigned char*)dev_alloc(c, m2l_packed_bytes(p, prec));
+    if (!o.Dv || !o.Kt || !o.Kpk) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+    launch_offset_dtensors(c->stream, p, o.Dv);
+    launch_build_k(c->stream, p, o.Dv, c->T, o.Kt);
+    launch_pack_k(c->stream, p, prec, o.Kt, o.Kpk);
+    HIPCHK(c, hipGetLastError());
+    c->opsets.push_back(o);
+    *kpk = o.Kpk;
+    return CTFMM_OK;
+}
+
+// Keys, sort, the trees level by level, neighbour tables, U/W/X lists, the
+// (particle, W entry) pairs and the M2L tile tables of one forest.  Waits for
+// the stream once per tree level and a few times more (sizes decide the next
+// launches).  f.p, f.nsys, f.goff_h and f.gbase_h are set by the caller.
+ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const double* q, bool explicit_box) {
     hipStream_t st = c->stream;
-    const size_t nn_ = (size_t)n;
-    ACHK(grow(c, c->k64, c->k64_cap, nn_, false));
-    ACHK(grow(c, c->k64s, c->k64s_cap, nn_, false));
-    ACHK(grow(c, c->a_idx, c->a_idx_cap, nn_, false));
-    ACHK(grow(c, c->a_idxs, c->a_idxs_cap, nn_, false));
-    ACHK(grow(c, c->leaf_of, c->leaf_of_cap, nn_, false));
-    ACHK(grow(c, c->a_P, c->a_P_cap, nn_, false));
-    ACHK(grow(c, c->a_F, c->a_F_cap, nn_, false));
-    if (!c->bbox) {
-        size_t cap = 0;
-        ACHK(grow(c, c->bbox, cap, 6 * NBB + 4, false));
-    }
-    if (!c->bse) {
-        size_t cap = 0;
-        ACHK(grow(c, c->bse, cap, 512, false));
-    }
-    if (!c->vsum) {
-        size_t cap = 0;
-        ACHK(grow(c, c->vsum, cap, 1, false));
-    }
-    // root cube
-    if (c->prm.root_side > 0.0) {
-        c->abox = ABox{{c->prm.root_lo[0], c->prm.root_lo[1], c->prm.root_lo[2]}, c->prm.root_side};
-    } else {
-        const int nparts = std::min(NBB, std::max(1, (n + 255) / 256));
-        launch_bbox(st, n, xyz, c->bbox, nparts, c->bbox + 6 * NBB);
-        double hb[4];
-        HIPCHK(c, hipMemcpyAsync(hb, c->bbox + 6 * NBB, sizeof(hb), hipMemcpyDeviceToHost, st));
+    const int n = f.n;
+    const size_t nn_ = (size_t)std::max(n, 1);
+    SCHK(get_ops(c, f.p, &f.Kpk));
+    ACHK(grow(c, f.k64, f.k64_cap, nn_, false));
+    ACHK(grow(c, f.k64s, f.k64s_cap, nn_, false));
+    ACHK(grow(c, f.a_idx, f.a_idx_cap, nn_, false));
+    ACHK(grow(c, f.a_idxs, f.a_idxs_cap, nn_, false));
+    ACHK(grow(c, f.leaf_of, f.leaf_of_cap, nn_, false));
+    ACHK(grow(c, f.a_P, f.a_P_cap, nn_, false));
+    ACHK(grow(c, f.a_F, f.a_F_cap, nn_, false));
+    ACHK(grow(c, f.bbox, f.bbox_cap, 6 * NBB + 4, false));
+    ACHK(grow(c, f.bse, f.bse_cap, 512, false));
+    ACHK(grow(c, f.vsum, f.vsum_cap, 1, false));
+    ACHK(grow(c, f.boxes, f.boxes_cap, (size_t)f.nsys, false));
+    ACHK(grow(c, f.goff, f.goff_cap, (size_t)f.nsys + 1, false));
+    ACHK(grow(c, f.gbase, f.gbase_cap, (size_t)f.nsys, false));
+    HIPCHK(c, hipMemcpyAsync(f.goff, f.goff_h.data(), (f.nsys + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(f.gbase, f.gbase_h.data(), f.nsys * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const ASys sy{f.nsys, f.goff, f.gbase};
+    // root cubes
+    if (explicit_box) {
+        const ABox b{{c->prm.root_lo[0], c->prm.root_lo[1], c->prm.root_lo[2]}, c->prm.root_side};
+        HIPCHK(c, hipMemcpyAsync(f.boxes, &b, sizeof(ABox), hipMemcpyHostToDevice, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        if (!std::isfinite(hb[0]) || !std::isfinite(hb[1]) || !std::isfinite(hb[2]) || !std::isfinite(hb[3]))
-            return fail(c, CTFMM_EINVAL, "non-finite particle coordinate");
-        c->abox = ABox{{hb[0], hb[1], hb[2]}, hb[3]};
+    } else if (f.nsys == 1) {
+        const int nparts = std::min(NBB, std::max(1, (n + 255) / 256));
+        launch_bbox(st, n, xyz + 3 * (size_t)f.gbase_h[0], f.bbox, nparts, f.bbox + 6 * NBB);
+        HIPCHK(c, hipMemcpyAsync(f.boxes, f.bbox + 6 * NBB, sizeof(ABox), hipMemcpyDeviceToDevice, st));
+    } else {
+        launch_bbox_systems(st, sy, xyz, f.boxes);
     }
-    launch_keys64(st, n, xyz, c->abox, c->k64, c->a_idx, c->err_flag);
-    SCHK(cub_run(c, [&](void* t, size_t& b) {
-        return hipcub::DeviceRadixSort::SortPairs(t, b, c->k64, c->k64s, c->a_idx, c->a_idxs, n, 0, 3 * AMAX, st);
-    }));
-    launch_gather(st, n, c->a_idxs, xyz, q, c->a_P);
+    launch_keys64(st, n, sy, xyz, f.boxes, f.k64, f.a_idx, c->err_flag);
+    if (f.nsys == 1) {
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, 0, 3 * AMAX, st);
+        }));
+    } else {
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceSegmentedRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, f.nsys,
+                                                                f.goff, f.goff + 1, 0, 3 * AMAX, st);
+        }));
+    }
+    launch_gather(st, n, f.a_idxs, xyz, q, f.a_P);
     HIPCHK(c, hipGetLastError());
 
-    // tree, level by level
-    ACHK(grow_nodes(c, 1));
-    launch_root(st, n, c->tr);
-    c->lev_first.assign(1, 0);
-    c->lev_count.assign(1, 1);
-    int first = 0, count = 1, total = 1;
+    // trees, level by level (level 0 holds one root per system)
+    ACHK(grow_nodes(c, f, (size_t)f.nsys));
+    launch_roots(st, sy, f.tr);
+    f.lev_first.assign(1, 0);
+    f.lev_count.assign(1, f.nsys);
+    int first = 0, count = f.nsys, total = f.nsys;
     for (int l = 0;; ++l) {
         const size_t m = 8 * (size_t)count;
-        ACHK(grow(c, c->sflag, c->sflag_cap, m, false));
-        ACHK(grow(c, c->sincl, c->sincl_cap, m, false));
-        ACHK(grow(c, c->scstart, c->scstart_cap, m, false));
-        launch_split(st, l, first, count, c->prm.leaf_max, c->k64s, c->tr, c->sflag, c->scstart);
+        ACHK(grow(c, f.sflag, f.sflag_cap, m, false));
+        ACHK(grow(c, f.sincl, f.sincl_cap, m, false));
+        ACHK(grow(c, f.scstart, f.scstart_cap, m, false));
+        launch_split(st, l, first, count, c->prm.leaf_max, f.k64s, f.tr, f.sflag, f.scstart);
         SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceScan::InclusiveSum(t, b, c->sflag, c->sincl, (int)m, st);
+            return hipcub::DeviceScan::InclusiveSum(t, b, f.sflag, f.sincl, (int)m, st);
         }));
         int nnext = 0;
-        HIPCHK(c, hipMemcpyAsync(&nnext, c->sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(&nnext, f.sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         if (nnext == 0) break;
-        ACHK(grow_nodes(c, (size_t)total + nnext));
-        launch_emit(st, l, first, count, total, c->sflag, c->sincl, c->scstart, c->tr);
+        ACHK(grow_nodes(c, f, (size_t)total + nnext));
+        launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr);
         first = total;
         count = nnext;
         total += nnext;
-        c->lev_first.push_back(first);
-        c->lev_count.push_back(count);
+        f.lev_first.push_back(first);
+        f.lev_count.push_back(count);
     }
     HIPCHK(c, hipGetLastError());
     const int nn = total;
-    c->nn = nn;
-    const int maxlev = (int)c->lev_first.size() - 1;
-    for (int l = 1; l <= maxlev; ++l) launch_nb(st, c->lev_first[l], c->lev_count[l], c->tr);
-    launch_leaf_of(st, nn, c->tr, c->leaf_of);
+    f.nn = nn;
+    const int maxlev = (int)f.lev_first.size() - 1;
+    for (int l = 1; l <= maxlev; ++l) launch_nb(st, f.lev_first[l], f.lev_count[l], f.tr);
+    launch_leaf_of(st, nn, f.tr, f.leaf_of);
 
     // U, W, X lists: count, scan, fill
     const size_t n1 = (size_t)nn + 1;
-    ACHK(grow(c, c->lcnt, c->lcnt_cap, 3 * n1, false));
-    ACHK(grow(c, c->loff, c->loff_cap, 3 * n1, false));
-    int32_t *uc = c->lcnt, *wc = c->lcnt + n1, *xc = c->lcnt + 2 * n1;
-    int32_t *uo = c->loff, *wo = c->loff + n1, *xo = c->loff + 2 * n1;
-    HIPCHK(c, hipMemsetAsync(c->lcnt, 0, 3 * n1 * sizeof(int32_t), st));
-    launch_lists(st, false, nn, c->tr, uc, wc, xc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    ACHK(grow(c, f.lcnt, f.lcnt_cap, 3 * n1, false));
+    ACHK(grow(c, f.loff, f.loff_cap, 3 * n1, false));
+    int32_t *uc = f.lcnt, *wc = f.lcnt + n1, *xc = f.lcnt + 2 * n1;
+    int32_t *uo = f.loff, *wo = f.loff + n1, *xo = f.loff + 2 * n1;
+    HIPCHK(c, hipMemsetAsync(f.lcnt, 0, 3 * n1 * sizeof(int32_t), st));
+    launch_lists(st, false, nn, f.tr, uc, wc, xc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     for (int k = 0; k < 3; ++k) {
-        int32_t* in = c->lcnt + k * n1;
-        int32_t* out = c->loff + k * n1;
+        int32_t* in = f.lcnt + k * n1;
+        int32_t* out = f.loff + k * n1;
         SCHK(cub_run(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, in, out, (int)n1, st); }));
     }
     int tot[3];
     for (int k = 0; k < 3; ++k)
-        HIPCHK(c, hipMemcpyAsync(&tot[k], c->loff + k * n1 + nn, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(&tot[k], f.loff + k * n1 + nn, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    c->tot_u = tot[0];
-    c->tot_w = tot[1];
-    c->tot_x = tot[2];
-    ACHK(grow(c, c->ulist, c->ulist_cap, (size_t)tot[0], false));
-    ACHK(grow(c, c->wlist, c->wlist_cap, (size_t)tot[1], false));
-    ACHK(grow(c, c->xlist, c->xlist_cap, (size_t)tot[2], false));
-    launch_lists(st, true, nn, c->tr, uc, wc, xc, uo, wo, xo, c->ulist, c->wlist, c->xlist);
+    f.tot_u = tot[0];
+    f.tot_w = tot[1];
+    f.tot_x = tot[2];
+    ACHK(grow(c, f.ulist, f.ulist_cap, (size_t)tot[0], false));
+    ACHK(grow(c, f.wlist, f.wlist_cap, (size_t)tot[1], false));
+    ACHK(grow(c, f.xlist, f.xlist_cap, (size_t)tot[2], false));
+    launch_lists(st, true, nn, f.tr, uc, wc, xc, uo, wo, xo, f.ulist, f.wlist, f.xlist);
     // (target particle, W entry) pairs of the multipole evaluations
-    c->wpairs = 0;
-    if (c->tot_w > 0) {
-        ACHK(grow(c, c->wcnt, c->wcnt_cap, n1, false));
-        ACHK(grow(c, c->wpoff, c->wpoff_cap, n1, false));
-        HIPCHK(c, hipMemsetAsync(c->wcnt + nn, 0, sizeof(long long), st));
-        launch_wpairs_count(st, nn, c->tr, wo, c->wcnt);
+    f.wpairs = 0;
+    if (f.tot_w > 0) {
+        ACHK(grow(c, f.wcnt, f.wcnt_cap, n1, false));
+        ACHK(grow(c, f.wpoff, f.wpoff_cap, n1, false));
+        HIPCHK(c, hipMemsetAsync(f.wcnt + nn, 0, sizeof(long long), st));
+        launch_wpairs_count(st, nn, f.tr, wo, f.wcnt);
         SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceScan::ExclusiveSum(t, b, c->wcnt, c->wpoff, (int)n1, st);
+            return hipcub::DeviceScan::ExclusiveSum(t, b, f.wcnt, f.wpoff, (int)n1, st);
         }));
         long long wp = 0;
-        HIPCHK(c, hipMemcpyAsync(&wp, c->wpoff + nn, sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(&wp, f.wpoff + nn, sizeof(long long), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        c->wpairs = wp;
-        ACHK(grow(c, c->wbuf, c->wbuf_cap, (size_t)wp, false));
+        f.wpairs = wp;
+        ACHK(grow(c, f.wbuf, f.wbuf_cap, (size_t)wp, false));
     }
 
     // M2L tiles: nodes grouped by (level, octant), Morton order inside, 64 per tile
-    ACHK(grow(c, c->lok, c->lok_cap, (size_t)nn, false));
-    ACHK(grow(c, c->loks, c->loks_cap, (size_t)nn, false));
-    ACHK(grow(c, c->lov, c->lov_cap, (size_t)nn, false));
-    ACHK(grow(c, c->lovs, c->lovs_cap, (size_t)nn, false));
-    launch_lvloct(st, nn, c->tr, c->lok, c->lov);
+    ACHK(grow(c, f.lok, f.lok_cap, (size_t)nn, false));
+    ACHK(grow(c, f.loks, f.loks_cap, (size_t)nn, false));
+    ACHK(grow(c, f.lov, f.lov_cap, (size_t)nn, false));
+    ACHK(grow(c, f.lovs, f.lovs_cap, (size_t)nn, false));
+    launch_lvloct(st, nn, f.tr, f.lok, f.lov);
     SCHK(cub_run(c, [&](void* t, size_t& b) {
-        return hipcub::DeviceRadixSort::SortPairs(t, b, c->lok, c->loks, c->lov, c->lovs, nn, 0, 8, st);
+        return hipcub::DeviceRadixSort::SortPairs(t, b, f.lok, f.loks, f.lov, f.lovs, nn, 0, 8, st);
     }));
-    launch_buckets(st, nn, c->loks, c->bse, c->bse + 256);
+    launch_buckets(st, nn, f.loks, f.bse, f.bse + 256);
     int hb[512];
-    HIPCHK(c, hipMemcpyAsync(hb, c->bse, sizeof(hb), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(hb, f.bse, sizeof(hb), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    c->tiles_host.clear();
-    c->tile_first.assign(maxlev + 1, 0);
-    c->tile_count.assign(maxlev + 1, 0);
-    for (int l = 2; l <= maxlev; ++l) {
-        c->tile_first[l] = (int)c->tiles_host.size();
+    f.tiles_host.clear();
+    for (int l = 2; l <= maxlev; ++l)
         for (int o = 0; o < 8; ++o) {
             const int k = (l << 3) | o;
             const int b = hb[k], e = hb[256 + k];
-            for (int s0 = b; s0 < e; s0 += 64) c->tiles_host.push_back(make_int4(o, s0, std::min(64, e - s0), l));
+            for (int s0 = b; s0 < e; s0 += 64) f.tiles_host.push_back(make_int4(o, s0, std::min(64, e - s0), l));
         }
-        c->tile_count[l] = (int)c->tiles_host.size() - c->tile_first[l];
-    }
-    const size_t ntiles = c->tiles_host.size();
+    const size_t ntiles = f.tiles_host.size();
     if (ntiles) {
-        ACHK(grow(c, c->tiles, c->tiles_cap, ntiles, false));
-        ACHK(grow(c, c->tgt_tab, c->tgt_cap, 64 * ntiles, false));
-        ACHK(grow(c, c->src_tab, c->src_cap, 189 * 64 * ntiles, false));
-        ACHK(grow(c, c->vcount, c->vcount_cap, 189 * ntiles, false));
-        HIPCHK(c, hipMemcpyAsync(c->tiles, c->tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice, st));
-        launch_m2l_tables(st, (int)ntiles, c->tiles, c->lovs, c->tr, c->alist, c->tgt_tab, c->src_tab, c->vcount);
+        ACHK(grow(c, f.tiles, f.tiles_cap, ntiles, false));
+        ACHK(grow(c, f.tgt_tab, f.tgt_cap, 64 * ntiles, false));
+        ACHK(grow(c, f.src_tab, f.src_cap, 189 * 64 * ntiles, false));
+        ACHK(grow(c, f.vcount, f.vcount_cap, 189 * ntiles, false));
+        HIPCHK(c, hipMemcpyAsync(f.tiles, f.tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice, st));
+        launch_m2l_tables(st, (int)ntiles, f.tiles, f.lovs, f.tr, c->alist, f.tgt_tab, f.src_tab, f.vcount);
     }
+    // expansion buffers
+    const size_t ldm = (size_t)ldm_of(f.p);
+    ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm, false));
+    ACHK(grow(c, f.aL, f.aL_cap, (size_t)nn * ldm, false));
+    if (f.tot_w > 0) ACHK(grow(c, f.aMh, f.aMh_cap, (size_t)nn * ldm, false));
+    if (c->prm.precision != CTFMM_PREC_FP64) ACHK(grow(c, f.aM32, f.aM32_cap, (size_t)nn * s32_of(f.p), false));
     HIPCHK(c, hipGetLastError());
-    c->v_pairs = -1;
+    f.v_pairs = -1;
     return CTFMM_OK;
 }
 
 // (target, source) pairs of the M2L tiles built last (waits for the stream)
-ctfmm_status count_v_pairs(ctfmm_ctx* c) {
-    if (c->v_pairs >= 0) return CTFMM_OK;
-    const int m = 189 * (int)c->tiles_host.size();
+ctfmm_status count_v_pairs(ctfmm_ctx* c, Forest& f) {
+    if (f.v_pairs >= 0) return CTFMM_OK;
+    const int m = 189 * (int)f.tiles_host.size();
     int v = 0;
     if (m > 0) {
         SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceReduce::Sum(t, b, c->vcount, c->vsum, m, c->stream);
+            return hipcub::DeviceReduce::Sum(t, b, f.vcount, f.vsum, m, c->stream);
         }));
-        HIPCHK(c, hipMemcpyAsync(&v, c->vsum, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&v, f.vsum, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    c->v_pairs = v;
+    f.v_pairs = v;
     return CTFMM_OK;
+}
+
+// The numeric passes of one forest (no waits, no memsets: graph-capturable).
+// ev >= 0 records the phase events ev.. (0 start, 1 P2M, 2 M2M, 3 conversions,
+// 4 M2L, 5 P2L, 6 L2L, 7 near field).  to_F leaves the results in sorted
+// order in f.a_F (for launch_scatter_out) instead of writing phi and grad.
+ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, int ev, bool to_F = false) {
+    hipStream_t st = c->stream;
+    const int p = f.p;
+    const int prec = c->prm.precision;
+    const int nn = f.nn;
+    const int maxlev = (int)f.lev_first.size() - 1;
+    auto mark = [&](int k) {
+        if (ev >= 0) rec(c, ev + k);
+    };
+    mark(0);
+    launch_p2m_nodes(st, p, 0, nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
+    mark(1);
+    for (int l = maxlev - 1; l >= 2; --l) launch_m2m_nodes(st, p, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
+    mark(2);
+    const void* msrc = f.aM;
+    if (maxlev >= 2) {
+        const int f2 = f.lev_first[2];
+        if (f.tot_w > 0) launch_mhat(st, p, f2, nn - f2, f.aM, f.aMh);
+        if (prec != CTFMM_PREC_FP64) {
+            launch_to_f32(st, p, nn, f.aM, f.aM32);
+            msrc = f.aM32;
+        }
+    }
+    mark(3);
+    // downward: L(B) = M2L(V) + P2L(X) + L2L(parent).  M2L over the tiles of
+    // every level at once (it reads only M), then the X lists, then L2L top-down.
+    if (!f.tiles_host.empty()) {
+        const AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+        HIPCHK(c, launch_m2l_tables(st, p, prec, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk, c->zero_row));
+    }
+    mark(4);
+    if (f.tot_x > 0) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * ((size_t)nn + 1), f.xlist, f.a_P, f.aL);
+    mark(5);
+    for (int l = 3; l <= maxlev; ++l) launch_l2l_nodes(st, p, f.lev_first[l - 1], f.lev_count[l - 1], f.tr, f.aL, c->T);
+    mark(6);
+    const size_t n1 = (size_t)nn + 1;
+    launch_near_adaptive(st, p, f.n, nn, f.wpairs, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aMh, f.loff + n1, f.wlist,
+                         f.wpoff, f.wbuf, f.loff, f.ulist, f.a_idxs, f.a_F, to_F, phi, grad);
+    mark(7);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+void add_forest_stats(ctfmm_ctx* c, Forest& f) {
+    c->st.m2l_launches += f.tiles_host.empty() ? 0 : 1;
+    c->st.p2p_leaf_pairs += f.tot_u;
 }
 
 ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const double* q, double* phi,
                                double* grad) {
-    hipStream_t st = c->stream;
-    const int p = c->prm.order_p;
-    const int prec = c->prm.precision;
-    const size_t ldm = (size_t)ldm_of(p);
-    // events: 0 start, 1 tree built, 2 P2M, 3 M2M, 4 conversions, 6-9 M2L / P2L / L2L, 5 before the near field
+    if (c->forests.empty()) c->forests.resize(1);
+    Forest& f = c->forests[0];
+    c->nforests = 1;
+    f.p = c->prm.order_p;
+    f.nsys = 1;
+    f.n = n;
+    f.goff_h = {0, n};
+    f.gbase_h = {0};
+    // events: 0 start, 1 tree built, 2.. the numeric phases, then the end
     rec(c, 0);
-    HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), st));
-    SCHK(build_adaptive(c, n, xyz, q));
+    HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
+    SCHK(build_forest(c, f, xyz, q, c->prm.root_side > 0.0));
     rec(c, 1);
-    const int nn = c->nn;
-    const int maxlev = (int)c->lev_first.size() - 1;
-    ACHK(grow(c, c->aM, c->aM_cap, (size_t)nn * ldm, false));
-    ACHK(grow(c, c->aL, c->aL_cap, (size_t)nn * ldm, false));
-    const ABox box = c->abox;
-    launch_p2m_nodes(st, p, 0, nn, box, c->tr, c->a_P, c->T, c->aM);
-    rec(c, 2);
-    for (int l = maxlev - 1; l >= 2; --l) launch_m2m_nodes(st, p, c->lev_first[l], c->lev_count[l], c->tr, c->aM, c->T);
-    rec(c, 3);
-    const void* msrc = c->aM;
-    if (maxlev >= 2) {
-        const int f2 = c->lev_first[2];
-        if (c->tot_w > 0) {
-            ACHK(grow(c, c->aMh, c->aMh_cap, (size_t)nn * ldm, false));
-            launch_mhat(st, p, f2, nn - f2, c->aM, c->aMh);
-        }
-        if (prec != CTFMM_PREC_FP64) {
-            ACHK(grow(c, c->aM32, c->aM32_cap, (size_t)nn * s32_of(p), false));
-            launch_to_f32(st, p, nn, c->aM, c->aM32);
-            msrc = c->aM32;
-        }
-    }
-    rec(c, 4);
-    // downward: L(B) = M2L(V) + P2L(X) + L2L(parent).  M2L over the tiles of
-    // every level at once (it reads only M), then the X lists, then L2L top-down.
-    rec(c, 6);
-    if (!c->tiles_host.empty()) {
-        const AdaptM2L ad{c->tiles, c->tgt_tab, c->src_tab, c->alist + 8 * 189, 0};
-        HIPCHK(c, launch_m2l_tables(st, p, prec, (int)c->tiles_host.size(), ad, msrc, c->aL, c->Kpk, c->zero_row));
-    }
-    rec(c, 7);
-    if (c->tot_x > 0) launch_p2l(st, p, nn, box, c->tr, c->loff + 2 * ((size_t)nn + 1), c->xlist, c->a_P, c->aL);
-    rec(c, 8);
-    for (int l = 3; l <= maxlev; ++l)
-        launch_l2l_nodes(st, p, c->lev_first[l - 1], c->lev_count[l - 1], c->tr, c->aL, c->T);
-    rec(c, 9);
-    rec(c, 5);
-    const size_t n1 = (size_t)nn + 1;
-    launch_near_adaptive(st, p, n, nn, c->wpairs, box, c->tr, c->leaf_of, c->a_P, c->aL, c->aMh, c->loff + n1,
-                         c->wlist, c->wpoff, c->wbuf, c->loff, c->ulist, c->a_idxs, c->a_F, phi, grad);
-    HIPCHK(c, hipGetLastError());
+    SCHK(numeric_forest(c, f, phi, grad, 2));
     const int ev_end = NPHASE_EV - 1;
     rec(c, ev_end);
     c->have_result = true;
     c->st.evaluations += 1;
-    c->st.m2l_launches += c->tiles_host.empty() ? 0 : 1;
-    c->st.p2p_leaf_pairs += c->tot_u;
+    add_forest_stats(c, f);
     if (c->timing) {
-        SCHK(count_v_pairs(c));
-        c->st.m2l_pairs += c->v_pairs;
+        SCHK(count_v_pairs(c, f));
+        c->st.m2l_pairs += f.v_pairs;
         HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
         c->st.ms_total += elapsed(c, 0, ev_end);
         c->st.ms_tree += elapsed(c, 0, 1);
-        c->st.ms_p2m += elapsed(c, 1, 2);
-        c->st.ms_m2m += elapsed(c, 2, 3);
-        c->st.ms_convert += elapsed(c, 3, 4);
-        c->st.ms_near += elapsed(c, 5, ev_end);
-        c->st.ms_m2l += elapsed(c, 6, 7);
-        c->st.ms_p2l += elapsed(c, 7, 8);
-        c->st.ms_l2l += elapsed(c, 8, 9);
+        c->st.ms_p2m += elapsed(c, 2, 3);
+        c->st.ms_m2m += elapsed(c, 3, 4);
+        c->st.ms_convert += elapsed(c, 4, 5);
+        c->st.ms_m2l += elapsed(c, 5, 6);
+        c->st.ms_p2l += elapsed(c, 6, 7);
+        c->st.ms_l2l += elapsed(c, 7, 8);
+        c->st.ms_near += elapsed(c, 8, 9);
     }
     return CTFMM_OK;
 }
@@ -912,6 +979,113 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
     return CTFMM_OK;
 }
 
+ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* offsets, const int32_t* orders,
+                                    const double* xyz, const double* q, double* phi, double* grad) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "batched evaluation needs the adaptive tree");
+    if (nsys < 1 || !offsets || !orders) return fail(c, CTFMM_EINVAL, "nsys >= 1 and host offsets/orders required");
+    if (offsets[0] != 0) return fail(c, CTFMM_EINVAL, "offsets[0] must be 0");
+    for (int s = 0; s < nsys; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(c, CTFMM_EINVAL, "offsets must not decrease");
+        if (orders[s] < 0 || orders[s] > CTFMM_P_MAX) return fail(c, CTFMM_EINVAL, "order out of range 0..10");
+    }
+    const int64_t total = offsets[nsys];
+    if (total >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "total particle count must be < 2^31");
+    if (total == 0) return CTFMM_OK;
+    if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
+    // one forest per order, systems in input order inside it
+    std::vector<int> ps(orders, orders + nsys);
+    std::sort(ps.begin(), ps.end());
+    ps.erase(std::unique(ps.begin(), ps.end()), ps.end());
+    if (c->forests.size() < ps.size()) c->forests.resize(ps.size());
+    c->nforests = (int)ps.size();
+    for (int k = 0; k < c->nforests; ++k) {
+        Forest& f = c->forests[k];
+        f.p = ps[k];
+        f.goff_h.assign(1, 0);
+        f.gbase_h.clear();
+        for (int s = 0; s < nsys; ++s)
+            if (orders[s] == f.p) {
+                f.gbase_h.push_back((int32_t)offsets[s]);
+                f.goff_h.push_back(f.goff_h.back() + (int32_t)(offsets[s + 1] - offsets[s]));
+            }
+        f.nsys = (int)f.gbase_h.size();
+        f.n = f.goff_h.back();
+    }
+    rec(c, 0);
+    HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
+    for (int k = 0; k < c->nforests; ++k) SCHK(build_forest(c, c->forests[k], xyz, q, false));
+    rec(c, 1);
+    // every value the numeric launches depend on
+    // (the outputs are not among them: the graph leaves results in sorted order)
+    std::vector<long long> sig = {c->nforests};
+    for (int k = 0; k < c->nforests; ++k) {
+        const Forest& f = c->forests[k];
+        const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys,
+                              f.a_P, f.a_F, f.aM, f.aL, f.aMh, f.aM32, f.loff, f.xlist, f.wlist, f.ulist, f.wpoff,
+                              f.wbuf, f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk};
+        for (const void* q2 : ptrs) sig.push_back((long long)(uintptr_t)q2);
+        sig.insert(sig.end(), {f.p, f.n, f.nn, f.wpairs, (long long)f.tiles_host.size(), f.tot_w, f.tot_x});
+        sig.insert(sig.end(), f.lev_first.begin(), f.lev_first.end());
+        sig.insert(sig.end(), f.lev_count.begin(), f.lev_count.end());
+    }
+    if (sig != c->gsig) {
+        // new shapes: run eagerly (also sets kernel attributes) and capture on the next call
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->gexec = nullptr;
+        c->graph = nullptr;
+        for (int k = 0; k < c->nforests; ++k) SCHK(numeric_forest(c, c->forests[k], nullptr, nullptr, -1, true));
+        c->gsig = sig;
+    } else {
+        if (!c->gexec) {
+            if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipStream_t user = c->stream;
+            c->stream = c->cap_stream;
+            ctfmm_status cs = CTFMM_OK;
+            hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int k = 0; k < c->nforests && cs == CTFMM_OK; ++k)
+                    cs = numeric_forest(c, c->forests[k], nullptr, nullptr, -1, true);
+                hipGraph_t g = nullptr;
+                const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+                if (e2 == hipSuccess && cs == CTFMM_OK) c->graph = g;
+                else if (g) (void)hipGraphDestroy(g);
+                if (e2 != hipSuccess && cs == CTFMM_OK) cs = fail(c, CTFMM_EDEVICE, "hipStreamEndCapture failed");
+            } else {
+                cs = fail(c, CTFMM_EDEVICE, "hipStreamBeginCapture failed");
+            }
+            c->stream = user;
+            if (cs != CTFMM_OK) return cs;
+            HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+        c->st.graph_launches += 1;
+    }
+    for (int k = 0; k < c->nforests; ++k) {
+        const Forest& f = c->forests[k];
+        launch_scatter_out(c->stream, f.n, f.a_idxs, f.a_F, phi, grad);
+    }
+    HIPCHK(c, hipGetLastError());
+    const int ev_end = NPHASE_EV - 1;
+    rec(c, ev_end);
+    c->have_result = true;
+    c->st.evaluations += 1;
+    for (int k = 0; k < c->nforests; ++k) add_forest_stats(c, c->forests[k]);
+    if (c->timing) {
+        for (int k = 0; k < c->nforests; ++k) {
+            SCHK(count_v_pairs(c, c->forests[k]));
+            c->st.m2l_pairs += c->forests[k].v_pairs;
+        }
+        HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
+        c->st.ms_total += elapsed(c, 0, ev_end);
+        c->st.ms_tree += elapsed(c, 0, 1);
+        c->st.ms_numeric += elapsed(c, 1, ev_end);
+    }
+    return CTFMM_OK;
+}
+
 ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* c, int32_t level, int32_t which, double* host_out, size_t cap) {
     if (!c || !host_out) return CTFMM_EINVAL;
     const int p = c->prm.order_p;
@@ -949,20 +1123,28 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
         out->root_side = c->prm.root_side;
         return CTFMM_OK;
     }
-    ctfmm_status s = count_v_pairs(c);
-    if (s != CTFMM_OK) return s;
-    std::vector<int32_t> info((size_t)c->nn);
-    HIPCHK(c, hipMemcpyAsync(info.data(), c->tr.info, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int32_t v : info) out->leaves += (v >> 8) & 1;
-    out->nodes = c->nn;
-    out->max_level = (int64_t)c->lev_first.size() - 1;
-    out->v_pairs = c->v_pairs;
-    out->u_pairs = c->tot_u;
-    out->w_pairs = c->tot_w;
-    out->x_pairs = c->tot_x;
-    for (int k = 0; k < 3; ++k) out->root_lo[k] = c->abox.lo[k];
-    out->root_side = c->abox.side;
+    for (int k = 0; k < c->nforests; ++k) {
+        Forest& f = c->forests[k];
+        ctfmm_status s = count_v_pairs(c, f);
+        if (s != CTFMM_OK) return s;
+        std::vector<int32_t> info((size_t)f.nn);
+        HIPCHK(c, hipMemcpyAsync(info.data(), f.tr.info, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int32_t v : info) out->leaves += (v >> 8) & 1;
+        out->nodes += f.nn;
+        out->max_level = std::max<int64_t>(out->max_level, (int64_t)f.lev_first.size() - 1);
+        out->v_pairs += f.v_pairs;
+        out->u_pairs += f.tot_u;
+        out->w_pairs += f.tot_w;
+        out->x_pairs += f.tot_x;
+    }
+    if (c->nforests > 0) {
+        ABox b{};
+        HIPCHK(c, hipMemcpy(&b, c->forests[0].boxes, sizeof(ABox), hipMemcpyDeviceToHost));
+        for (int k = 0; k < 3; ++k) out->root_lo[k] = b.lo[k];
+        out->root_side = b.side;
+    }
     return CTFMM_OK;
 }
 
@@ -1003,6 +1185,8 @@ const char* ctfmm_last_error(const ctfmm_ctx* c) { return c ? c->err.c_str() : g
 void ctfmm_destroy(ctfmm_ctx* c) {
     if (!c) return;
     dev_free_all(c);
+    reset_adaptive(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;

@@ -88,7 +88,7 @@ __host__ __device__ inline uint32_t compact21(uint64_t v) {
     return (uint32_t)v;
 }
 
-// root cube of the adaptive tree
+// root cube of one adaptive tree
 struct ABox {
     double lo[3];
     double side;
@@ -104,6 +104,15 @@ struct ATree {
     int32_t* child;  // [8] child per octant (x = bit 0), -1 = empty
     int32_t* nb;     // [27] same-level neighbour at offset d = (dx+1)+3(dy+1)+9(dz+1),
                      // else the coarser leaf covering that cell, else -1
+    int32_t* sys;    // system (tree of the forest) the node belongs to
+};
+
+// Systems of a forest: particles of system s are forest positions
+// [goff[s], goff[s+1]) and global indices gbase[s] + (i - goff[s]).
+struct ASys {
+    int nsys;
+    const int32_t* goff;
+    const int32_t* gbase;
 };
 
 // M2L over tables: tile t has 64 target rows tgt[64 t ..] (-1 = none) of
@@ -207,8 +216,10 @@ void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side
 
 // ---- adaptive tree launchers (ctfmm_adaptive.hip) ----
 void launch_bbox(hipStream_t s, int n, const double* xyz, double* part, int nparts, double* out);
-void launch_keys64(hipStream_t s, int n, const double* xyz, ABox box, uint64_t* keys, int32_t* idx, int* err);
-void launch_root(hipStream_t s, int n, const ATree& t);
+void launch_bbox_systems(hipStream_t s, const ASys& sy, const double* xyz, ABox* boxes);
+void launch_keys64(hipStream_t s, int n, const ASys& sy, const double* xyz, const ABox* boxes, uint64_t* keys,
+                   int32_t* idx, int* err);
+void launch_roots(hipStream_t s, const ASys& sy, const ATree& t);
 void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, const uint64_t* keys, const ATree& t,
                   int32_t* flag, int32_t* cstart);
 void launch_emit(hipStream_t s, int level, int first, int count, int next_first, const int32_t* flag,
@@ -222,18 +233,19 @@ void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* 
 void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
 void launch_m2l_tables(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount);
-void launch_p2m_nodes(hipStream_t s, int p, int first, int count, ABox box, const ATree& t, const double4* P,
+void launch_p2m_nodes(hipStream_t s, int p, int first, int count, const ABox* boxes, const ATree& t, const double4* P,
                       const DevTables& T, double* M);
 void launch_m2m_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* M, const DevTables& T);
 void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* L, const DevTables& T);
-void launch_p2l(hipStream_t s, int p, int nn, ABox box, const ATree& t, const int32_t* xoff, const int32_t* xlist,
+void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const int32_t* xoff, const int32_t* xlist,
                 const double4* P, double* L);
 void launch_mhat(hipStream_t s, int p, int first, int count, const double* M, double* Mh);
 void launch_wpairs_count(hipStream_t s, int nn, const ATree& t, const int32_t* woff, long long* cnt);
-void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, ABox box, const ATree& t,
+void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, const ABox* boxes, const ATree& t,
                           const int32_t* leaf_of, const double4* P, const double* L, const double* Mh,
                           const int32_t* woff, const int32_t* wlist, const long long* wpoff, double4* wbuf,
-                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, double* phi,
-                          double* grad);
+                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, bool to_F,
+                          double* phi, double* grad);
+void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
 
 }  // namespace ctfmm

@@ -22,7 +22,7 @@ CTFMM_DEPTH_MAX = 9
 CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
-            "ctfmm_evaluate", "ctfmm_copy_expansions", "ctfmm_tree_stats", "ctfmm_set_timing", "ctfmm_stats",
+            "ctfmm_evaluate", "ctfmm_evaluate_batched", "ctfmm_copy_expansions", "ctfmm_tree_stats", "ctfmm_set_timing", "ctfmm_stats",
             "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
 
@@ -42,8 +42,8 @@ class ctfmm_stats_t(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_tree", C.c_double), ("ms_p2m", C.c_double),
                 ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
                 ("ms_near", C.c_double), ("ms_convert", C.c_double), ("ms_p2l", C.c_double),
-                ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
-                ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64)]
+                ("ms_numeric", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
+                ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64), ("graph_launches", C.c_int64)]
 
 
 class ctfmm_tree_stats_t(C.Structure):
@@ -68,6 +68,7 @@ def load():
         L.ctfmm_create.argtypes = [C.POINTER(ctfmm_params), vp, C.POINTER(vp)]
         L.ctfmm_set_allocator.argtypes = [vp, vp, vp, vp]
         L.ctfmm_evaluate.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ctfmm_evaluate_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.ctfmm_tree_stats.argtypes = [vp, C.POINTER(ctfmm_tree_stats_t)]
         L.ctfmm_set_timing.argtypes = [vp, i32]
@@ -128,6 +129,26 @@ def ctfmm_evaluate(ctx, xyz, q, phi=None, grad=None):
         if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous() or tuple(t.shape) != shape:
             raise ValueError("tensors must be contiguous cuda float64 of shapes [n,3], [n], [n], [n,3]")
     _check(load().ctfmm_evaluate(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)), C.c_void_p(ctx))
+
+
+def ctfmm_evaluate_batched(ctx, offsets, orders, xyz, q, phi=None, grad=None):
+    """offsets: host int64 [nsys+1]; orders: host int32 [nsys]; xyz, q, phi,
+    grad as in ctfmm_evaluate for the concatenated systems."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    ords = np.ascontiguousarray(orders, dtype=np.int32)
+    nsys = int(ords.size)
+    if off.size != nsys + 1:
+        raise ValueError("offsets must have nsys+1 entries")
+    n = int(q.shape[0])
+    for t, shape in ((xyz, (n, 3)), (q, (n,)), (phi, (n,)), (grad, (n, 3))):
+        if t is None:
+            continue
+        if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError("tensors must be contiguous cuda float64 of shapes [n,3], [n], [n], [n,3]")
+    _check(load().ctfmm_evaluate_batched(C.c_void_p(ctx), nsys, C.c_void_p(off.ctypes.data),
+                                         C.c_void_p(ords.ctypes.data), _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)),
+           C.c_void_p(ctx))
 
 
 def ctfmm_copy_expansions(ctx, level: int, which: int, out) -> None:
@@ -205,6 +226,21 @@ class FMM:
         if sync:
             ctfmm_sync(self.ctx)
         return phi, grad
+
+    def evaluate_batched(self, offsets, orders, xyz, q, phi=None, grad=None, sync=False):
+        import torch
+        n = int(q.shape[0])
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float64, device=q.device)
+        if grad is None:
+            grad = torch.empty((n, 3), dtype=torch.float64, device=q.device)
+        ctfmm_evaluate_batched(self.ctx, offsets, orders, xyz, q, phi, grad)
+        if sync:
+            ctfmm_sync(self.ctx)
+        return phi, grad
+
+    def stats(self) -> dict:
+        return ctfmm_stats(self.ctx)
 
     def expansions(self, level: int, which: str):
         import numpy as np

@@ -58,6 +58,7 @@ def test_null_arguments():
     lib = F.load()
     assert lib.ctfmm_create(None, None, None) == F.CTFMM_EINVAL
     assert lib.ctfmm_evaluate(None, 1, None, None, None, None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_evaluate_batched(None, 1, None, None, None, None, None, None) == F.CTFMM_EINVAL
     assert lib.ctfmm_sync(None) == F.CTFMM_EINVAL
     assert lib.ctfmm_default_params(None) == F.CTFMM_EINVAL
     lib.ctfmm_destroy(None)
