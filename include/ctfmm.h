@@ -204,6 +204,17 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* ctx, int32_t level, int32_t which,
  * Errors: EINVAL (null argument, no evaluate yet), EDEVICE. */
 ctfmm_status ctfmm_tree_stats(ctfmm_ctx* ctx, ctfmm_tree_stats_t* out);
 
+/* M2L tile shape of the adaptive tree for order p: targets per workgroup
+ * tile, 32, 64 or 128 (one 16-target block per wavefront).  By default
+ * (targets = 0) the first evaluation that needs order p times every shape
+ * the device's LDS admits on its own tables and keeps the fastest for the
+ * context's lifetime.  Errors: EINVAL (p or targets out of range),
+ * EUNSUPPORTED (the tile does not fit the device's LDS). */
+ctfmm_status ctfmm_set_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t targets);
+
+/* The tile shape in use for order p (0 if none has been chosen yet). */
+ctfmm_status ctfmm_get_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t* targets);
+
 /* Turn per-phase HIP-event timing on (1) or off (0; default). */
 ctfmm_status ctfmm_set_timing(ctfmm_ctx* ctx, int32_t on);
 

@@ -488,34 +488,37 @@ void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, 
     hipLaunchKernelGGL(k_buckets, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, sk, bstart, bend);
 }
 
-// One wave per (tile, offset): the target of each lane and the source cell of
-// the offset (child q of the parent's neighbour u, or -1).  vcount = sources
-// that exist.
-__global__ __launch_bounds__(64) void k_m2l_tables(const int4* __restrict__ tiles, const int32_t* __restrict__ sorted,
-                                                   ATree t, const int16_t* __restrict__ qu_list,
-                                                   int32_t* __restrict__ tgt_tab, int32_t* __restrict__ src_tab,
-                                                   int32_t* __restrict__ vcount) {
+// One wave per (tile, offset): the targets of the tile (tt of them, lanes
+// take slots lane, lane + 64) and the source cell of the offset for each
+// (child q of the parent's neighbour u, or -1).  vcount = sources that exist.
+__global__ __launch_bounds__(64) void k_m2l_tables(int tt, const int4* __restrict__ tiles,
+                                                   const int32_t* __restrict__ sorted, ATree t,
+                                                   const int16_t* __restrict__ qu_list, int32_t* __restrict__ tgt_tab,
+                                                   int32_t* __restrict__ src_tab, int32_t* __restrict__ vcount) {
     const int tile = blockIdx.x / 189, iv = blockIdx.x % 189;
     const int lane = threadIdx.x;
     const int4 d = tiles[tile];  // (octant, first sorted position, count, level)
-    const int tg = lane < d.z ? sorted[d.y + lane] : -1;
-    if (iv == 0) tgt_tab[64 * (size_t)tile + lane] = tg;
-    int src = -1;
-    if (tg >= 0) {
-        const int qu = qu_list[d.x * 189 + iv];
-        const int Q = t.nb[27 * (size_t)t.par[tg] + (qu & 31)];
-        if (Q >= 0 && !node_leaf(t.info[Q])) src = t.child[8 * (size_t)Q + (qu >> 5)];
+    const int qu = qu_list[d.x * 189 + iv];
+    int cnt = 0;
+    for (int r = lane; r < tt; r += 64) {
+        const int tg = r < d.z ? sorted[d.y + r] : -1;
+        if (iv == 0) tgt_tab[tt * (size_t)tile + r] = tg;
+        int src = -1;
+        if (tg >= 0) {
+            const int Q = t.nb[27 * (size_t)t.par[tg] + (qu & 31)];
+            if (Q >= 0 && !node_leaf(t.info[Q])) src = t.child[8 * (size_t)Q + (qu >> 5)];
+        }
+        src_tab[(189 * (size_t)tile + iv) * tt + r] = src;
+        cnt += __popcll(__ballot(src >= 0));
     }
-    src_tab[(189 * (size_t)tile + iv) * 64 + lane] = src;
-    const unsigned long long m = __ballot(src >= 0);
-    if (lane == 0) vcount[blockIdx.x] = __popcll(m);
+    if (lane == 0) vcount[blockIdx.x] = cnt;
 }
 
-void launch_m2l_tables(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
+void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_m2l_tables, dim3(189 * ntiles), dim3(64), 0, s, tiles, sorted, t, qu_list, tgt_tab, src_tab,
-                       vcount);
+    hipLaunchKernelGGL(k_m2l_tables, dim3(189 * ntiles), dim3(64), 0, s, tt, tiles, sorted, t, qu_list, tgt_tab,
+                       src_tab, vcount);
 }
 
 // ------------------------------------------------------------------ P2M, M2M, L2L on node lists

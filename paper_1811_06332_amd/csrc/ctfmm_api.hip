@@ -97,6 +97,8 @@ struct Forest {
     std::vector<int4> tiles_host;
     int64_t tot_u = 0, tot_w = 0, tot_x = 0, v_pairs = -1;
     const unsigned char* Kpk = nullptr;  // operators of order p
+    int tt = 64;                         // targets per M2L tile
+    int hb[512] = {};                    // (level, octant) bucket bounds on the host
 };
 
 struct ctfmm_ctx {
@@ -148,6 +150,9 @@ struct ctfmm_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+    int tile_forced[CTFMM_P_MAX + 1] = {};  // M2L targets per tile set by the caller (0 = tune)
+    int tile_tuned[CTFMM_P_MAX + 1] = {};   // ... chosen by the tuner (0 = not yet)
+    hipEvent_t tev[2] = {};                 // events of the tuner
     std::vector<long long> gsig;
 
     // timing
@@ -314,7 +319,7 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    if (m2l_lds_bytes(p, prec) > (size_t)max_lds || m2l_tile_lds_bytes(p, prec) > (size_t)max_lds)
+    if (m2l_lds_bytes(p, prec) > (size_t)max_lds || m2l_tile_lds_bytes(p, prec, 64) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
     c->Kpk = (unsigned char*)dev_alloc(c, m2l_packed_bytes(p, prec));
     const size_t zbytes = std::max((size_t)ldm_of(PMAX) * 8, (size_t)s32_of(PMAX) * 4);
@@ -511,7 +516,7 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
     const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    if (m2l_tile_lds_bytes(p, prec) > (size_t)max_lds)
+    if (m2l_tile_lds_bytes(p, prec, 64) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
     const size_t nc = (size_t)(p + 1) * (p + 1);
     OpSet o;
@@ -526,6 +531,62 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
     HIPCHK(c, hipGetLastError());
     c->opsets.push_back(o);
     *kpk = o.Kpk;
+    return CTFMM_OK;
+}
+
+// M2L tiles of tt targets from the (level, octant) buckets, and their tables
+ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
+    const int maxlev = (int)f.lev_first.size() - 1;
+    f.tiles_host.clear();
+    for (int l = 2; l <= maxlev; ++l)
+        for (int o = 0; o < 8; ++o) {
+            const int k = (l << 3) | o;
+            const int b = f.hb[k], e = f.hb[256 + k];
+            for (int s0 = b; s0 < e; s0 += tt) f.tiles_host.push_back(make_int4(o, s0, std::min(tt, e - s0), l));
+        }
+    f.tt = tt;
+    const size_t ntiles = f.tiles_host.size();
+    if (!ntiles) return CTFMM_OK;
+    ACHK(grow(c, f.tiles, f.tiles_cap, ntiles, false));
+    ACHK(grow(c, f.tgt_tab, f.tgt_cap, (size_t)tt * ntiles, false));
+    ACHK(grow(c, f.src_tab, f.src_cap, (size_t)189 * tt * ntiles, false));
+    ACHK(grow(c, f.vcount, f.vcount_cap, 189 * ntiles, false));
+    HIPCHK(c, hipMemcpyAsync(f.tiles, f.tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+    launch_m2l_tables(c->stream, tt, (int)ntiles, f.tiles, f.lovs, f.tr, c->alist, f.tgt_tab, f.src_tab, f.vcount);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+// The tile-shape tuner: times one M2L launch (after a warm-up launch) of
+// every tile size the device's LDS admits on this forest's own tables and
+// returns the fastest.  The multipole buffer's contents do not matter for
+// the timing; the local expansions it writes are overwritten by the real pass.
+ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best) {
+    const int prec = c->prm.precision;
+    int max_lds = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    for (auto& e : c->tev)
+        if (!e) HIPCHK(c, hipEventCreate(&e));
+    const void* msrc = prec == CTFMM_PREC_FP64 ? (const void*)f.aM : (const void*)f.aM32;
+    float tbest = 0.f;
+    *best = 64;
+    for (int tt : {32, 64, 128}) {
+        if (m2l_tile_lds_bytes(f.p, prec, tt) > (size_t)max_lds) continue;
+        SCHK(make_tiles(c, f, tt));
+        const AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+        const int nt = (int)f.tiles_host.size();
+        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, f.aL, f.Kpk, c->zero_row));
+        HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
+        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, f.aL, f.Kpk, c->zero_row));
+        HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
+        HIPCHK(c, hipEventSynchronize(c->tev[1]));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+        if (tbest == 0.f || ms < tbest) {
+            tbest = ms;
+            *best = tt;
+        }
+    }
     return CTFMM_OK;
 }
 
@@ -655,7 +716,14 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         ACHK(grow(c, f.wbuf, f.wbuf_cap, (size_t)wp, false));
     }
 
-    // M2L tiles: nodes grouped by (level, octant), Morton order inside, 64 per tile
+    // expansion buffers
+    const size_t ldm = (size_t)ldm_of(f.p);
+    ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm, false));
+    ACHK(grow(c, f.aL, f.aL_cap, (size_t)nn * ldm, false));
+    if (f.tot_w > 0) ACHK(grow(c, f.aMh, f.aMh_cap, (size_t)nn * ldm, false));
+    if (c->prm.precision != CTFMM_PREC_FP64) ACHK(grow(c, f.aM32, f.aM32_cap, (size_t)nn * s32_of(f.p), false));
+
+    // M2L tiles: nodes grouped by (level, octant), Morton order inside
     ACHK(grow(c, f.lok, f.lok_cap, (size_t)nn, false));
     ACHK(grow(c, f.loks, f.loks_cap, (size_t)nn, false));
     ACHK(grow(c, f.lov, f.lov_cap, (size_t)nn, false));
@@ -665,31 +733,14 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         return hipcub::DeviceRadixSort::SortPairs(t, b, f.lok, f.loks, f.lov, f.lovs, nn, 0, 8, st);
     }));
     launch_buckets(st, nn, f.loks, f.bse, f.bse + 256);
-    int hb[512];
-    HIPCHK(c, hipMemcpyAsync(hb, f.bse, sizeof(hb), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(f.hb, f.bse, sizeof(f.hb), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    f.tiles_host.clear();
-    for (int l = 2; l <= maxlev; ++l)
-        for (int o = 0; o < 8; ++o) {
-            const int k = (l << 3) | o;
-            const int b = hb[k], e = hb[256 + k];
-            for (int s0 = b; s0 < e; s0 += 64) f.tiles_host.push_back(make_int4(o, s0, std::min(64, e - s0), l));
-        }
-    const size_t ntiles = f.tiles_host.size();
-    if (ntiles) {
-        ACHK(grow(c, f.tiles, f.tiles_cap, ntiles, false));
-        ACHK(grow(c, f.tgt_tab, f.tgt_cap, 64 * ntiles, false));
-        ACHK(grow(c, f.src_tab, f.src_cap, 189 * 64 * ntiles, false));
-        ACHK(grow(c, f.vcount, f.vcount_cap, 189 * ntiles, false));
-        HIPCHK(c, hipMemcpyAsync(f.tiles, f.tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice, st));
-        launch_m2l_tables(st, (int)ntiles, f.tiles, f.lovs, f.tr, c->alist, f.tgt_tab, f.src_tab, f.vcount);
+    int tt = c->tile_forced[f.p] ? c->tile_forced[f.p] : c->tile_tuned[f.p];
+    if (tt == 0 && maxlev >= 2) {
+        SCHK(tune_tile(c, f, &tt));
+        c->tile_tuned[f.p] = tt;
     }
-    // expansion buffers
-    const size_t ldm = (size_t)ldm_of(f.p);
-    ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm, false));
-    ACHK(grow(c, f.aL, f.aL_cap, (size_t)nn * ldm, false));
-    if (f.tot_w > 0) ACHK(grow(c, f.aMh, f.aMh_cap, (size_t)nn * ldm, false));
-    if (c->prm.precision != CTFMM_PREC_FP64) ACHK(grow(c, f.aM32, f.aM32_cap, (size_t)nn * s32_of(f.p), false));
+    SCHK(make_tiles(c, f, tt ? tt : 64));
     HIPCHK(c, hipGetLastError());
     f.v_pairs = -1;
     return CTFMM_OK;
@@ -743,7 +794,7 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     // every level at once (it reads only M), then the X lists, then L2L top-down.
     if (!f.tiles_host.empty()) {
         const AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
-        HIPCHK(c, launch_m2l_tables(st, p, prec, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk, c->zero_row));
+        HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk, c->zero_row));
     }
     mark(4);
     if (f.tot_x > 0) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * ((size_t)nn + 1), f.xlist, f.a_P, f.aL);
@@ -1026,7 +1077,7 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
                               f.a_P, f.a_F, f.aM, f.aL, f.aMh, f.aM32, f.loff, f.xlist, f.wlist, f.ulist, f.wpoff,
                               f.wbuf, f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk};
         for (const void* q2 : ptrs) sig.push_back((long long)(uintptr_t)q2);
-        sig.insert(sig.end(), {f.p, f.n, f.nn, f.wpairs, (long long)f.tiles_host.size(), f.tot_w, f.tot_x});
+        sig.insert(sig.end(), {f.p, f.n, f.nn, f.wpairs, (long long)f.tiles_host.size(), f.tot_w, f.tot_x, f.tt});
         sig.insert(sig.end(), f.lev_first.begin(), f.lev_first.end());
         sig.insert(sig.end(), f.lev_count.begin(), f.lev_count.end());
     }
@@ -1148,6 +1199,26 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
     return CTFMM_OK;
 }
 
+ctfmm_status ctfmm_set_m2l_tile(ctfmm_ctx* c, int32_t p, int32_t targets) {
+    if (!c) return CTFMM_EINVAL;
+    if (p < 0 || p > CTFMM_P_MAX || (targets != 0 && targets != 32 && targets != 64 && targets != 128))
+        return fail(c, CTFMM_EINVAL, "p in 0..10 and targets in {0, 32, 64, 128}");
+    if (targets) {
+        int max_lds = 0;
+        HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+        if (m2l_tile_lds_bytes(p, c->prm.precision, targets) > (size_t)max_lds)
+            return fail(c, CTFMM_EUNSUPPORTED, "this tile does not fit the device's LDS");
+    }
+    c->tile_forced[p] = targets;
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_get_m2l_tile(ctfmm_ctx* c, int32_t p, int32_t* targets) {
+    if (!c || !targets || p < 0 || p > CTFMM_P_MAX) return CTFMM_EINVAL;
+    *targets = c->tile_forced[p] ? c->tile_forced[p] : c->tile_tuned[p];
+    return CTFMM_OK;
+}
+
 ctfmm_status ctfmm_set_timing(ctfmm_ctx* c, int32_t on) {
     if (!c) return CTFMM_EINVAL;
     c->timing = on != 0;
@@ -1187,6 +1258,8 @@ void ctfmm_destroy(ctfmm_ctx* c) {
     dev_free_all(c);
     reset_adaptive(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto& e : c->tev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;

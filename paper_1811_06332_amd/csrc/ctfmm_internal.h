@@ -115,9 +115,9 @@ struct ASys {
     const int32_t* gbase;
 };
 
-// M2L over tables: tile t has 64 target rows tgt[64 t ..] (-1 = none) of
+// M2L over tables: tile t has TT target rows tgt[TT t ..] (-1 = none) of
 // octant tiles[t].x, and for offset i of that octant the source rows
-// src[(189 t + i) 64 ..] (-1 = none); kslot[o][i] = slot of its operator.
+// src[(189 t + i) TT ..] (-1 = none); kslot[o][i] = slot of its operator.
 struct AdaptM2L {
     const int4* tiles;
     const int32_t* tgt;
@@ -206,10 +206,11 @@ void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned ch
 void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32);
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L,
                       const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row);
-// M2L of ntiles tiles of the adaptive tree (any precision; rows are node indices)
-hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int ntiles, const AdaptM2L& ad, const void* Msrc,
+// M2L of ntiles tiles of tt targets (32, 64 or 128) of the adaptive tree (any
+// precision; rows are node indices)
+hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles, const AdaptM2L& ad, const void* Msrc,
                              double* L, const unsigned char* Kpk, const unsigned char* zero_row);
-size_t m2l_tile_lds_bytes(int p, int prec);
+size_t m2l_tile_lds_bytes(int p, int prec, int tt);
 // row stride of the FP32 multipole copy: (p+1)^2 rounded up to a multiple of 32
 __host__ __device__ constexpr int s32_of(int p) { return (((p + 1) * (p + 1) + 31) / 32) * 32; }
 void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side, const double* X, double* out);
@@ -231,7 +232,7 @@ void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucn
                   int32_t* xlist);
 void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* v);
 void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
-void launch_m2l_tables(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
+void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount);
 void launch_p2m_nodes(hipStream_t s, int p, int first, int count, const ABox* boxes, const ATree& t, const double4* P,
                       const DevTables& T, double* M);

@@ -411,7 +411,7 @@ constexpr int LDS_LIMIT = 163840;
 
 }  // namespace
 
-template <int P, int PREC>
+template <int P, int PREC, int TT = 64>
 struct Tile {
     static constexpr int NC = (P + 1) * (P + 1);
     static constexpr int LDM = (NC + 3) & ~3;                 // FP64 expansion row stride
@@ -434,7 +434,7 @@ struct Tile {
     static constexpr int KBYTES = NCH * CHB;
     // one source row in LDS: FP64 rows of LDM doubles, or FP32 rows of S32 floats
     static constexpr int BROW = PREC == PREC_F64 ? LDM * 8 : S32 * 4;
-    static constexpr int BBYTES = 64 * BROW;
+    static constexpr int BBYTES = TT * BROW;  // the source rows of one offset for TT targets
     static constexpr int KBUF = (2 * KBYTES + 2 * BBYTES + 1024 <= LDS_LIMIT) ? 2 : 1;
     static constexpr int LDS = KBUF * KBYTES + 2 * BBYTES;
 };
@@ -500,18 +500,22 @@ __device__ inline void lds_copy16(const void* g, void* lds) {
 // ADAPT = true: the work unit is a tile of the adaptive tree (AdaptM2L):
 // targets, sources and the octant come from the tables instead of the
 // uniform grid, and rows are node indices.
-template <int P, int PREC, bool ADAPT>
-__global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restrict__ Msrc, double* __restrict__ L,
-                                                  const unsigned char* __restrict__ Kpk,
-                                                  const int16_t* __restrict__ offlist,
-                                                  const unsigned char* __restrict__ zero_row, const AdaptM2L ad) {
-    using S = Tile<P, PREC>;
+// NW waves of 16 targets each: TT = 16 NW targets per tile (the uniform
+// grid's work unit has 64).
+template <int P, int PREC, bool ADAPT, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __restrict__ Msrc, double* __restrict__ L,
+                                                      const unsigned char* __restrict__ Kpk,
+                                                      const int16_t* __restrict__ offlist,
+                                                      const unsigned char* __restrict__ zero_row, const AdaptM2L ad) {
+    constexpr int TT = 16 * NW;
+    static_assert(ADAPT || NW == 4, "the uniform work unit has 64 targets");
+    using S = Tile<P, PREC, TT>;
     constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB;
     constexpr int KU = S::KBYTES / 16;        // 16-byte units of one K_v
     constexpr int RU = S::BROW / 16;          // 16-byte units of one source row
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     unsigned char* Kb = lds;                              // [KBUF][KBYTES]
-    unsigned char* Bb = lds + S::KBUF * S::KBYTES;        // [2][64 rows][BROW]
+    unsigned char* Bb = lds + S::KBUF * S::KBYTES;        // [2][TT rows][BROW]
     __shared__ int tco[64];                               // packed target coords, -1 = none
 
     // work item = 8 * parent block + target octant; each XCD takes a contiguous
@@ -539,16 +543,21 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
         const int ks = ADAPT ? ad.kslot[o * 189 + iv] : NOFF - 1 - offlist[o * 189 + iv];
         const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
         unsigned char* dst = Kb + buf * S::KBYTES;
-        for (int i = w; i * 64 < KU; i += 4) {
+        for (int i = w; i * 64 < KU; i += NW) {
             const int u = i * 64 + lane;
             if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
         }
     };
-    // source rows of offset iv: lane = target slot (each wave computes all 64),
-    // then every copy instruction moves whole rows whose address is read with
-    // readlane (wave-uniform), so the per-lane work is one add
-    auto src_rows = [&](int iv) -> int {
-        if (ADAPT) return ad.src[(189 * (size_t)work + iv) * 64 + lane];
+    // source rows of offset iv: lane = target slot (each wave computes all of
+    // them; slot lane + 64 k in register k), then every copy instruction moves
+    // whole rows whose address is read with readlane (wave-uniform), so the
+    // per-lane work is one add
+    constexpr int RL = (TT + 63) / 64;
+    auto src_row = [&](int iv, int k) -> int {
+        if (ADAPT) {
+            const int r = lane + 64 * k;
+            return r < TT ? ad.src[(189 * (size_t)work + iv) * TT + r] : -1;
+        }
         const int vs = offlist[o * 189 + iv];
         const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
         const int tc = tco[lane];
@@ -560,17 +569,22 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
         return row;
     };
     auto stage_b = [&](int iv, int buf) {
-        const int myrow = src_rows(iv);
+        int myrow[RL];
+#pragma unroll
+        for (int k = 0; k < RL; ++k) myrow[k] = src_row(iv, k);
         unsigned char* dst = Bb + buf * S::BBYTES;
         const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
         // RPI rows per copy instruction (RU units each); RPI = 1 unless RU divides 64
         constexpr int RPI = (RU <= 64 && 64 % RU == 0) ? 64 / RU : 1;
-        constexpr int NI = 64 / RPI;
-        for (int i = w; i < NI; i += 4) {
+        constexpr int NI = TT >= RPI ? TT / RPI : 1;
+        for (int i = w; i < NI; i += NW) {
+            // the RPI rows of instruction i lie in one 64-row group (RPI divides 64)
+            const int r0 = i * RPI;
+            const int v = RL == 1 ? myrow[0] : myrow[(r0 >> 6) < RL ? (r0 >> 6) : 0];
             int row;
-            if (RPI == 1) row = __builtin_amdgcn_readlane(myrow, i);
-            else row = __shfl(myrow, i * RPI + lane / RU);
-            if (lane < RPI * RU) {
+            if (RPI == 1) row = __builtin_amdgcn_readlane(v, r0 & 63);
+            else row = __shfl(v, (r0 & 63) + lane / RU);
+            if (lane < RPI * RU && r0 + lane / RU < TT) {
                 const int ul = lane % RU;
                 const unsigned char* g = row >= 0 ? Mb + (size_t)row * S::BROW + ul * 16 : zero_row + ul * 16;
                 lds_copy16(g, dst + (size_t)i * RPI * S::BROW);
@@ -676,7 +690,7 @@ __global__ __launch_bounds__(256) void k_m2l_tile(int level, const void* __restr
     }
     long long trow_out;
     if (ADAPT) {
-        trow_out = ad.tgt[64 * (size_t)work + w * 16 + (lane & 15)];
+        trow_out = ad.tgt[TT * (size_t)work + w * 16 + (lane & 15)];
         if (trow_out < 0) return;
     } else {
         const long long par = (long long)pb * 64 + w * 16 + (lane & 15);
@@ -878,20 +892,20 @@ hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L
     return hipGetLastError();
 }
 
-template <int P, int PREC, bool ADAPT>
+template <int P, int PREC, bool ADAPT, int NW = 4>
 hipError_t m2l_tile_impl(hipStream_t s, int level, long long nwork, const void* Msrc, double* L,
                          const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row,
                          const AdaptM2L& ad) {
-    using S = Tile<P, PREC>;
+    using S = Tile<P, PREC, 16 * NW>;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC, ADAPT>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC, ADAPT, NW>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_m2l_tile<P, PREC, ADAPT>), dim3((unsigned)nwork), dim3(256), S::LDS, s, level, Msrc, L, Kpk,
-                       offlist, zero_row, ad);
+    hipLaunchKernelGGL((k_m2l_tile<P, PREC, ADAPT, NW>), dim3((unsigned)nwork), dim3(64 * NW), S::LDS, s, level, Msrc,
+                       L, Kpk, offlist, zero_row, ad);
     return hipGetLastError();
 }
 
@@ -928,9 +942,24 @@ size_t m2l_packed_bytes(int p, int prec) {
                                                                             : tile_query<PREC_BF16X3>(p, 0);
 }
 
-size_t m2l_tile_lds_bytes(int p, int prec) {
-    return prec == PREC_F64 ? tile_query<PREC_F64>(p, 1) : prec == PREC_F32 ? tile_query<PREC_F32>(p, 1)
-                                                                            : tile_query<PREC_BF16X3>(p, 1);
+template <int PREC, int TT>
+static size_t tile_lds(int p) {
+    switch (p) {
+#define CASE(PP) case PP: return (size_t)Tile<PP, PREC, TT>::LDS;
+        CTFMM_P_CASES(CASE)
+#undef CASE
+        default: return 0;
+    }
+}
+
+template <int TT>
+static size_t tile_lds_prec(int p, int prec) {
+    return prec == PREC_F64 ? tile_lds<PREC_F64, TT>(p) : prec == PREC_F32 ? tile_lds<PREC_F32, TT>(p)
+                                                                           : tile_lds<PREC_BF16X3, TT>(p);
+}
+
+size_t m2l_tile_lds_bytes(int p, int prec, int tt) {
+    return tt == 32 ? tile_lds_prec<32>(p, prec) : tt == 128 ? tile_lds_prec<128>(p, prec) : tile_lds_prec<64>(p, prec);
 }
 
 size_t m2l_lds_bytes(int p, int prec) {
@@ -979,17 +1008,24 @@ hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msr
     }
 }
 
-hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int ntiles, const AdaptM2L& ad, const void* Msrc,
+template <int P, int NW>
+hipError_t m2l_tables_prec(hipStream_t s, int prec, int ntiles, const AdaptM2L& ad, const void* Msrc, double* L,
+                           const unsigned char* Kpk, const unsigned char* zero_row) {
+    if (prec == PREC_F64) return m2l_tile_impl<P, PREC_F64, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+    if (prec == PREC_F32) return m2l_tile_impl<P, PREC_F32, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+    return m2l_tile_impl<P, PREC_BF16X3, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+}
+
+hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles, const AdaptM2L& ad, const void* Msrc,
                              double* L, const unsigned char* Kpk, const unsigned char* zero_row) {
     if (ntiles <= 0) return hipSuccess;
+    if (tt != 32 && tt != 64 && tt != 128) return hipErrorInvalidValue;
     switch (p) {
-#define CASE(PP)                                                                                                    \
-    case PP:                                                                                                        \
-        if (prec == PREC_F64)                                                                                       \
-            return m2l_tile_impl<PP, PREC_F64, true>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);            \
-        if (prec == PREC_F32)                                                                                       \
-            return m2l_tile_impl<PP, PREC_F32, true>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);            \
-        return m2l_tile_impl<PP, PREC_BF16X3, true>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+#define CASE(PP)                                                                                         \
+    case PP:                                                                                             \
+        if (tt == 32) return m2l_tables_prec<PP, 2>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);        \
+        if (tt == 128) return m2l_tables_prec<PP, 8>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);       \
+        return m2l_tables_prec<PP, 4>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);
         CTFMM_P_CASES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

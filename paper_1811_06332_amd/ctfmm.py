@@ -22,7 +22,8 @@ CTFMM_DEPTH_MAX = 9
 CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
-            "ctfmm_evaluate", "ctfmm_evaluate_batched", "ctfmm_copy_expansions", "ctfmm_tree_stats", "ctfmm_set_timing", "ctfmm_stats",
+            "ctfmm_evaluate", "ctfmm_evaluate_batched", "ctfmm_copy_expansions", "ctfmm_tree_stats",
+            "ctfmm_set_m2l_tile", "ctfmm_get_m2l_tile", "ctfmm_set_timing", "ctfmm_stats",
             "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
 
@@ -71,6 +72,8 @@ def load():
         L.ctfmm_evaluate_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.ctfmm_tree_stats.argtypes = [vp, C.POINTER(ctfmm_tree_stats_t)]
+        L.ctfmm_set_m2l_tile.argtypes = [vp, i32, i32]
+        L.ctfmm_get_m2l_tile.argtypes = [vp, i32, C.POINTER(C.c_int32)]
         L.ctfmm_set_timing.argtypes = [vp, i32]
         L.ctfmm_stats.argtypes = [vp, C.POINTER(ctfmm_stats_t)]
         L.ctfmm_reset_stats.argtypes = [vp]
@@ -165,6 +168,16 @@ def ctfmm_tree_stats(ctx) -> dict:
     return out
 
 
+def ctfmm_set_m2l_tile(ctx, p: int, targets: int) -> None:
+    _check(load().ctfmm_set_m2l_tile(C.c_void_p(ctx), p, targets), C.c_void_p(ctx))
+
+
+def ctfmm_get_m2l_tile(ctx, p: int) -> int:
+    v = C.c_int32()
+    _check(load().ctfmm_get_m2l_tile(C.c_void_p(ctx), p, C.byref(v)), C.c_void_p(ctx))
+    return v.value
+
+
 def ctfmm_set_timing(ctx, on: bool) -> None:
     _check(load().ctfmm_set_timing(C.c_void_p(ctx), 1 if on else 0), C.c_void_p(ctx))
 
@@ -241,6 +254,12 @@ class FMM:
 
     def stats(self) -> dict:
         return ctfmm_stats(self.ctx)
+
+    def set_m2l_tile(self, p: int, targets: int) -> None:
+        ctfmm_set_m2l_tile(self.ctx, p, targets)
+
+    def m2l_tile(self, p: int) -> int:
+        return ctfmm_get_m2l_tile(self.ctx, p)
 
     def expansions(self, level: int, which: str):
         import numpy as np

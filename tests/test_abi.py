@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "ctfmm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ctfmm_[a-z_]+)\s*\(", src)) - {"ctfmm_alloc_fn", "ctfmm_free_fn"})
+    return sorted(set(re.findall(r"\b(ctfmm_[a-z0-9_]+)\s*\(", src)) - {"ctfmm_alloc_fn", "ctfmm_free_fn"})
 
 
 def test_library_exports_every_declared_symbol():

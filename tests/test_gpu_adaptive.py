@@ -167,3 +167,46 @@ def test_config1_fullsize_sampled():
     eP, eF = rel(pg[idx], po), rel(gg[idx], go)
     print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e}", flush=True)
     assert eP <= TOL and eF <= TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("targets", [32, 64, 128])
+def test_adaptive_every_m2l_tile_shape(precision, targets):
+    """Each M2L tile shape the tuner may pick gives the oracle's result."""
+    import torch
+    from paper_1811_06332_amd import ctfmm as F
+    xyz, q = W.plummer(6000, 23)
+    p = 8
+    print(f"[case] adaptive tile {targets} {precision}", flush=True)
+    f = F.FMM(p, 0, precision, root_side=None, tree="adaptive", leaf_max=32)
+    try:
+        try:
+            f.set_m2l_tile(p, targets)
+        except F.CtfmmError as e:
+            assert e.status == F.CTFMM_EUNSUPPORTED
+            pytest.skip(f"tile of {targets} targets does not fit this device's LDS in {precision}")
+        phi, grad = f.evaluate(torch.from_numpy(xyz).cuda(), torch.from_numpy(q).cuda(), sync=True)
+        assert f.m2l_tile(p) == targets
+    finally:
+        f.close()
+    po, go = oracle.fmm_adaptive(xyz, q, p, 32)
+    tol = TOL if precision == "fp64" else 1e-6
+    eP, eF = rel(phi.cpu().numpy(), po), rel(grad.cpu().numpy(), go)
+    print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e}", flush=True)
+    assert eP <= tol and eF <= tol
+
+
+def test_adaptive_tile_tuner_picks_a_shape():
+    import torch
+    from paper_1811_06332_amd import ctfmm as F
+    xyz, q = W.plummer(20000, 24)
+    f = F.FMM(6, 0, "fp32", root_side=None, tree="adaptive", leaf_max=64)
+    try:
+        assert f.m2l_tile(6) == 0
+        print("[case] adaptive tile tuner", flush=True)
+        f.evaluate(torch.from_numpy(xyz).cuda(), torch.from_numpy(q).cuda(), sync=True)
+        chosen = f.m2l_tile(6)
+        print(f"[case] tuner chose {chosen}", flush=True)
+        assert chosen in (32, 64, 128)
+    finally:
+        f.close()
