@@ -65,6 +65,9 @@ def _lib():
                                           C.c_void_p, C.c_void_p, i32]
         L.oracle_fmm_adaptive.restype = i32
         L.oracle_auto_root.argtypes = [i64, _dp, _dp, C.c_void_p]
+        L.oracle_fmm_adaptive_orders.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
+                                                 C.c_void_p, C.c_void_p, i32, C.c_void_p]
+        L.oracle_fmm_adaptive_orders.restype = i32
         _lib_handle = L
     return _lib_handle
 
@@ -218,10 +221,13 @@ def auto_root(xyz):
     return lo, float(side[0])
 
 
-def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=0, stats=False):
+def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=0, stats=False,
+                 order_r2=None):
     """Full FMM on the adaptive octree (see oracle_fmm_adaptive).  lo/side
     None/0 selects the automatic root cube.  With stats=True also returns a
-    dict of tree and list sizes and the root box."""
+    dict of tree and list sizes and the root box.  order_r2 (28 ints, index
+    |v|^2) sets the M2L order of every V-list pair by its offset (see
+    oracle_fmm_adaptive_orders)."""
     xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
     n = xyz.shape[0]
     if targets is None:
@@ -232,9 +238,14 @@ def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=
     phi = np.zeros(nt); grad = np.zeros(3 * nt)
     st = np.zeros(8, dtype=np.int64); root = np.zeros(4)
     lo_arr = _vec(lo if lo is not None else (0.0, 0.0, 0.0), 3)
-    rc = _lib().oracle_fmm_adaptive(n, np.ascontiguousarray(xyz.ravel()), q, p, leaf_max, lo_arr,
-                                    float(side) if lo is not None else 0.0, nt, tp, phi, grad,
-                                    st.ctypes.data, root.ctypes.data, nthreads)
+    args = (n, np.ascontiguousarray(xyz.ravel()), q, p, leaf_max, lo_arr, float(side) if lo is not None else 0.0,
+            nt, tp, phi, grad, st.ctypes.data, root.ctypes.data, nthreads)
+    if order_r2 is None:
+        rc = _lib().oracle_fmm_adaptive(*args)
+    else:
+        otab = np.ascontiguousarray(np.asarray(order_r2, dtype=np.int32))
+        assert otab.size == 28
+        rc = _lib().oracle_fmm_adaptive_orders(*args, otab.ctypes.data)
     del keep
     if rc != 0:
         raise RuntimeError(f"oracle_fmm_adaptive failed with code {rc}")

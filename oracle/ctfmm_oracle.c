@@ -913,9 +913,42 @@ static void oa_free(oatree *T)
  * |W|, |X| totals, and the root box is written to root_out[4] (lo, side) if
  * given.  Returns 0, -1 (arguments) or -2 (allocation).
  */
+static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
+                             const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
+                             double *phi, double *grad, int64_t *stats, double *root_out, int nthreads,
+                             const int *order_r2);
+
 int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
                         const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
                         double *phi, double *grad, int64_t *stats, double *root_out, int nthreads)
+{
+    return fmm_adaptive_impl(n, xyz, q, p, leaf_max, lo_in, side_in, nt, tgt, phi, grad, stats, root_out,
+                             nthreads, NULL);
+}
+
+/*
+ * The adaptive FMM with the M2L order of every V-list pair taken from a
+ * table indexed by |v|^2, v the integer offset between the two same-level
+ * cells (4 <= |v|^2 <= 27 for the ws=1 lists): M2L of that pair is Eq. M2L
+ * truncated at |n| + |m| <= order_r2[|v|^2] (<= p), acting on the order-p
+ * expansions.  Every other operator keeps order p.
+ */
+int oracle_fmm_adaptive_orders(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
+                               const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
+                               double *phi, double *grad, int64_t *stats, double *root_out, int nthreads,
+                               const int *order_r2)
+{
+    if (!order_r2) return -1;
+    for (int k = 4; k <= 27; ++k)
+        if (order_r2[k] < 0 || order_r2[k] > p) return -1;
+    return fmm_adaptive_impl(n, xyz, q, p, leaf_max, lo_in, side_in, nt, tgt, phi, grad, stats, root_out,
+                             nthreads, order_r2);
+}
+
+static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
+                             const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
+                             double *phi, double *grad, int64_t *stats, double *root_out, int nthreads,
+                             const int *order_r2)
 {
     init_tables();
     if (p < 0 || p > OR_PMAX || n < 1 || leaf_max < 1) return -1;
@@ -1031,7 +1064,12 @@ int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, in
                 double za[3], r[3];
                 oa_center(&T, &T.nd[C], za);
                 r[0] = zb[0] - za[0]; r[1] = zb[1] - za[1]; r[2] = zb[2] - za[2];
-                oracle_m2l(p, r, T.M[C], T.L[i]);
+                int order = p;
+                if (order_r2) {
+                    int64_t dx = T.nd[i].ix - T.nd[C].ix, dy = T.nd[i].iy - T.nd[C].iy, dz = T.nd[i].iz - T.nd[C].iz;
+                    order = order_r2[dx * dx + dy * dy + dz * dz];
+                }
+                oracle_m2l(order, r, T.M[C], T.L[i]);
             }
             for (int k = 0; k < T.X[i].n; ++k) {
                 int C = T.X[i].v[k];

@@ -482,4 +482,44 @@ def pin_adaptive_two_density(o):
     assert rel(pa, pd) < 1e-4 and rel(ga, gd) < 2e-3, (rel(pa, pd), rel(ga, gd), info)
 
 
+def pin_order_table(o):
+    """M2L orders per offset class (|v|^2) in the adaptive FMM: the table that
+    keeps order p everywhere reproduces the fixed-order FMM bit for bit; the
+    error against the direct sum grows as the table's order falls; lowering
+    only the farthest class (|v|^2 = 27) costs less accuracy than lowering
+    only the nearest (|v|^2 = 4), since the expansion converges faster with
+    distance."""
+    from paper_1811_06332_amd.workloads import plummer
+    xyz, q = plummer(1500, 44)
+    p = 8
+    pf, gf = o.fmm_adaptive(xyz, q, p, 16)
+    full = np.full(28, p, dtype=np.int32)
+    pt, gt = o.fmm_adaptive(xyz, q, p, 16, order_r2=full)
+    assert np.array_equal(pf, pt) and np.array_equal(gf, gt)
+    pd, gd = o.direct(xyz, q)
+    errs = []
+    for pp in (2, 4, 6):
+        pt, gt = o.fmm_adaptive(xyz, q, p, 16, order_r2=np.full(28, pp, dtype=np.int32))
+        errs.append(rel(gt, gd))
+    assert errs[0] > errs[1] > errs[2] > rel(gf, gd), errs
+    far = full.copy(); far[27] = 2
+    near = full.copy(); near[4] = 2
+    _, gfar = o.fmm_adaptive(xyz, q, p, 16, order_r2=far)
+    _, gnear = o.fmm_adaptive(xyz, q, p, 16, order_r2=near)
+    assert 0.0 < rel(gfar, gf) < rel(gnear, gf), (rel(gfar, gf), rel(gnear, gf))
+    # class membership: |v|^2 of a ws=1 pair is a sum of three squares of
+    # integers in [-3, 3] with at least one of magnitude >= 2; lowering one
+    # such class alone changes the result, lowering an empty class does not
+    occupied = sorted({a * a + b * b + c * c for a in range(4) for b in range(4) for c in range(4)
+                       if max(a, b, c) >= 2})
+    assert occupied == [4, 5, 6, 8, 9, 10, 11, 12, 13, 14, 17, 18, 19, 22, 27]
+    for k in range(4, 28):
+        tab = full.copy(); tab[k] = p - 2
+        _, gk = o.fmm_adaptive(xyz, q, p, 16, order_r2=tab)
+        if k in occupied:
+            assert rel(gk, gf) > 1e-14, k
+        else:
+            assert np.array_equal(gk, gf), k
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -68,6 +68,9 @@ MUTANTS = [
     ("adaptive_l2l_dropped", "oracle_l2l(p, dd, T.L[par], T.L[i]);", "(void)dd;", None),
     ("adaptive_split_threshold", "if (nd.e - nd.b <= T->leaf_max || nd.level >= OA_DMAX) return;",
      "if (nd.e - nd.b < T->leaf_max / 2 || nd.level >= OA_DMAX) return;", None),
+    ("order_table_ignored", "order = order_r2[dx * dx + dy * dy + dz * dz];", "order = p;", None),
+    ("order_table_wrong_offset", "order = order_r2[dx * dx + dy * dy + dz * dz];",
+     "order = order_r2[dx * dx + dy * dy + dz * dz >= 9 ? 27 : 4];", None),
 ]
 
 
