@@ -1,18 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark: full FMM throughput (particles/s) and M2L GFLOP/s on one MI355X.
 
-Workload (default): N = 2^24 particles uniform in the unit cube, charges
-U(-1,1), uniform octree of depth 7 (128^3 leaves), expansion order p = 10,
-ws = 1.  One step = one whole evaluation (keys, sort, P2M, M2M, M2L, L2L,
-L2P, P2P) with inputs resident in HBM.  The chosen M2L precision is timed
+Headline workload (the mixed-precision configuration): a Plummer sphere of
+N = 2^20 particles (scale radius 1, truncated at 20, charges 1/N), adaptive
+octree with at most 64 particles per leaf, expansion order p = 8, ws = 1.
+One step = one whole evaluation (root cube, keys, sort, tree and lists, P2M,
+M2M, M2L, P2L, L2L, L2P, multipoles at particles, P2P) with inputs resident
+in HBM.  The chosen M2L precision (FP32 matrix cores by default) is timed
 next to plain FP64 on the same input, and the relative force error of the
 chosen mode against FP64 is reported.
 
+Further workloads, reported in "extras" of the same JSON line:
+  uniform16M  N = 2^24 uniform in the unit cube, charges U(-1,1), uniform
+              octree of depth 7, p = 10 (chosen precision vs FP64)
+  batched256  256 independent systems, N log-uniform in [1e4, 5e5], half
+              uniform cubes, half Plummer spheres, p in {4, 6, 8}, FP32, one
+              batched call replayed from a HIP graph
+  learned4M   N = 2^22 Hernquist cluster (cut 50, charges 1/N), p = 10:
+              M2L orders chosen by the network (trained here on pairs of
+              another cluster, decision margin tuned on a third) against the
+              fixed order 10 (FP64 M2L both)
+
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3]
+                    [--no-extras] [--no-cpu-baseline]
 
 Prints one JSON line.  M2L roofline: algorithmic flops 2*S(p) per cell pair,
 S(p) = (p+1)(p+2)((p+1)^2+(p+1)+1)/6 (non-zero entries of the traceless
-operator), over the M2L kernel time measured with HIP events on the
+operator), over the M2L phase time measured with HIP events on the
 library's stream during the timed steps.
 """
 from __future__ import annotations
@@ -37,8 +51,15 @@ def s_of_p(p: int) -> int:
     return q * (q + 1) * (q * q + q + 1) // 6
 
 
-def run_leg(F, torch, X, Q, p, depth, precision, steps, warmup):
-    f = F.FMM(p, depth, precision)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_leg(F, torch, X, Q, p, precision, steps, warmup, tree="adaptive", depth=0, leaf_max=64, root_side=None,
+            setup=None):
+    f = F.FMM(p, depth, precision, root_side=root_side, tree=tree, leaf_max=leaf_max)
+    if setup is not None:
+        setup(f)
     n = int(Q.shape[0])
     phi = torch.empty(n, dtype=torch.float64, device=Q.device)
     grad = torch.empty((n, 3), dtype=torch.float64, device=Q.device)
@@ -51,61 +72,197 @@ def run_leg(F, torch, X, Q, p, depth, precision, steps, warmup):
     t0 = time.perf_counter()
     for i in range(steps):
         f.evaluate(X, Q, phi, grad)
-        print(f"[bench] {precision} step {i + 1}/{steps}", file=sys.stderr, flush=True)
+        log(f"{precision} {tree} step {i + 1}/{steps}")
     F.ctfmm_sync(f.ctx)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = F.ctfmm_stats(f.ctx)
+    ts = f.tree_stats()
     f.close()
     ms = (t1 - t0) * 1e3 / steps
-    flops_pair = 2 * s_of_p(p)
-    m2l_flops = st["m2l_pairs"] * flops_pair  # over all timed steps
-    m2l_s = st["ms_m2l"] * 1e-3
+    pairs = st["m2l_pairs"] // steps
+    flops_pairs = sum(h * 2 * s_of_p(k) for k, h in enumerate(st["m2l_order_pairs"])) // steps
+    if flops_pairs == 0:
+        flops_pairs = pairs * 2 * s_of_p(p)
+    launches = max(1, st["m2l_launches"] // steps)
+    m2l_ms = st["ms_m2l"] / steps
     leg = {
         "precision": precision,
         "ms_per_step": ms,
         "particles_per_s": n / (ms * 1e-3),
-        "m2l_gflops": m2l_flops / m2l_s / 1e9 if m2l_s > 0 else None,
+        "m2l_gflops": flops_pairs / (m2l_ms * 1e-3) / 1e9 if m2l_ms > 0 else None,
         "phase_ms_per_step": {k[3:]: st[k] / steps for k in st if k.startswith("ms_")},
-        "m2l_launches_per_step": st["m2l_launches"] // steps,
-        "m2l_pairs_per_step": st["m2l_pairs"] // steps,
-        "m2l_avg_launch_ms": st["ms_m2l"] / st["m2l_launches"] if st["m2l_launches"] else None,
+        "m2l_launches_per_step": launches,
+        "m2l_pairs_per_step": pairs,
+        "m2l_alg_flops_per_step": flops_pairs,
+        "m2l_ms_per_launch": m2l_ms / launches,
+        "m2l_order_pairs_per_step": [h // steps for h in st["m2l_order_pairs"]],
+        "tree": {k: v for k, v in ts.items() if k not in ("root_lo",)},
     }
     return leg, phi, grad
 
 
-def m2l_traffic(precision: str):
+def rel_err(torch, a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def m2l_traffic(name: str):
     """HBM bytes per M2L launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    record, or None when it does not describe the kernel source built now."""
+    record, or None when it does not describe the kernel sources built now."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", f"m2l_{precision}_uniform16M_p10_traffic.json")
-    src = os.path.join(ROOT, "paper_1811_06332_amd", "csrc", "ctfmm_kernels.hip")
+    rec_path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
     if not os.path.exists(rec_path):
         return None
     rec = json.load(open(rec_path))
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
+    h = hashlib.sha256()
+    for src in rec.get("kernel_sources", []):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != rec.get("kernel_sources_sha256_16"):
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(p: int, depth_full: int):
-    """The oracle on a 1/64 sub-volume of the same workload: a uniform cube at
-    the same density (8 particles per leaf), same p and ws, depth - 2."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(p: int, leaf_max: int):
+    """The adaptive oracle on a smaller Plummer sphere of the same profile
+    (1/8 of the particles), same p and leaf size, all host cores."""
     import oracle
     from paper_1811_06332_amd import workloads as W
-    depth = depth_full - 2
-    n = 8 * 8 ** depth
-    xyz, q = W.uniform_cube(n, 1002, -1.0, 1.0)
+    n = 1 << 17
+    xyz, q = W.plummer(n, 1001)
     threads = len(os.sched_getaffinity(0))
     oracle.fmm_uniform(xyz[:64], q[:64], 1, 1, nthreads=threads)  # load and set threads
     used = oracle.max_threads()
     t0 = time.perf_counter()
-    oracle.fmm_uniform(xyz, q, p, depth, nthreads=threads)
+    oracle.fmm_adaptive(xyz, q, p, leaf_max, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "particles/s", "cores": used, "kind": "oracle",
-            "sample": f"full oracle FMM of N={n} uniform particles (a 1/64 sub-volume of the workload at the "
-                      f"same 8/leaf density: depth {depth}, p={p}, ws=1), one run of {dt:.1f} s"}
+            "sample": f"full adaptive oracle FMM of a Plummer sphere of N={n} (1/8 of the workload's particles, same "
+                      f"profile, p={p}, leaf <= {leaf_max}, ws=1), one run of {dt:.1f} s"}
+
+
+# ------------------------------------------------------------------ extras
+
+def extra_uniform16m(F, torch, W, args, dev):
+    cfg = W.CONFIGS[2]
+    xyz, q = W.make(cfg)
+    X = torch.from_numpy(xyz).to(dev)
+    Q = torch.from_numpy(q).to(dev)
+    del xyz, q
+    log("uniform16M")
+    kw = dict(tree="uniform", depth=cfg["depth"], root_side=1.0)
+    chosen, phi_c, grad_c = run_leg(F, torch, X, Q, cfg["p"], args.precision, args.steps, args.warmup, **kw)
+    plain, phi_p, grad_p = run_leg(F, torch, X, Q, cfg["p"], "fp64", args.steps, args.warmup, **kw)
+    flops_launch = chosen["m2l_alg_flops_per_step"] / chosen["m2l_launches_per_step"]
+    ach = flops_launch / (chosen["m2l_ms_per_launch"] * 1e-3) / 1e12
+    out = {"workload": cfg["name"], "n": cfg["n"], "p": cfg["p"], "depth": cfg["depth"],
+           "particles_per_s": chosen["particles_per_s"], "ms_per_step": chosen["ms_per_step"],
+           "fp64_particles_per_s": plain["particles_per_s"],
+           "rel_force_err_vs_fp64": rel_err(torch, grad_c, grad_p),
+           "m2l_roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
+                            "frac": ach / PEAK_TFLOPS[args.precision],
+                            "traffic": m2l_traffic(f"m2l_{args.precision}_uniform16M_p10")},
+           "chosen": chosen, "plain_fp64": plain}
+    del X, Q, phi_c, grad_c, phi_p, grad_p
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_batched(F, torch, W, args, dev):
+    import numpy as np
+    systems = W.batched_systems()
+    offs = np.zeros(len(systems) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(s[1]) for s in systems])
+    orders = np.array([s[2] for s in systems], dtype=np.int32)
+    X = torch.from_numpy(np.ascontiguousarray(np.concatenate([s[0] for s in systems]))).to(dev)
+    Q = torch.from_numpy(np.ascontiguousarray(np.concatenate([s[1] for s in systems]))).to(dev)
+    del systems
+    n = int(offs[-1])
+    log(f"batched256 total N={n}")
+    f = F.FMM(8, 0, "fp32", root_side=None, tree="adaptive", leaf_max=64)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    grad = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    try:
+        for _ in range(max(2, args.warmup)):  # eager, then captured
+            f.evaluate_batched(offs, orders, X, Q, phi, grad)
+        F.ctfmm_sync(f.ctx)
+        F.ctfmm_set_timing(f.ctx, True)
+        F.ctfmm_reset_stats(f.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            f.evaluate_batched(offs, orders, X, Q, phi, grad)
+            log(f"batched step {i + 1}/{args.steps}")
+        F.ctfmm_sync(f.ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        st = f.stats()
+        tiles = {p: f.m2l_tile(p) for p in (4, 6, 8)}
+    finally:
+        f.close()
+    del X, Q, phi, grad
+    torch.cuda.empty_cache()
+    return {"workload": "batched256_p468_fp32", "systems": len(orders), "n_total": n,
+            "particles_per_s": n / (ms * 1e-3), "ms_per_step": ms,
+            "ms_tree_per_step": st["ms_tree"] / args.steps, "ms_numeric_per_step": st["ms_numeric"] / args.steps,
+            "graph_launches": st["graph_launches"], "m2l_tile_targets_by_p": tiles,
+            "m2l_pairs_per_step": st["m2l_pairs"] // args.steps}
+
+
+def extra_learned(F, torch, W, args, dev):
+    import numpy as np
+    log("learned4M: training pairs")
+    xyz_t, q_t = W.hernquist(1 << 22, 1004)
+    nsamp = 1 << 17
+    f = F.FMM(10, 0, "fp64", root_side=None, tree="adaptive", leaf_max=64)
+    try:
+        x = torch.empty((nsamp, 12), dtype=torch.float32, device=dev)
+        y = torch.empty((nsamp, 9), dtype=torch.float32, device=dev)
+        F.ctfmm_mlp_samples(f.ctx, torch.from_numpy(xyz_t).to(dev), torch.from_numpy(q_t).to(dev), nsamp, 11, x, y)
+        mean, std = x.mean(dim=0), x.std(dim=0).clamp_min(1e-3)
+        xn = ((x - mean) / std).contiguous()
+        prm = torch.from_numpy(F.mlp_init_params(12)).to(dev)
+        t0 = time.perf_counter()
+        losses = F.ctfmm_mlp_train(f.ctx, xn, y, prm, 3000, 4096, 2e-3)
+        t_train = time.perf_counter() - t0
+        params = prm.cpu().numpy()
+        norm = np.concatenate([mean.cpu().numpy(), std.cpu().numpy()]).astype(np.float32)
+    finally:
+        f.close()
+    del xyz_t, q_t
+
+    def evaluate(xyz, q, margin, steps, warmup):
+        X = torch.from_numpy(xyz).to(dev)
+        Q = torch.from_numpy(q).to(dev)
+        setup = None if margin is None else (lambda g: g.set_order_model(params, norm, 1e-5, margin))
+        leg, phi, grad = run_leg(F, torch, X, Q, 10, "fp64", steps, warmup, setup=setup)
+        return leg, grad
+
+    log("learned4M: margin on a held-out cluster")
+    xyz_h, q_h = W.hernquist(1 << 20, 1006)
+    _, g_fix = evaluate(xyz_h, q_h, None, 1, 1)
+    margin, tuning = None, []
+    for m in (0.5, 0.0, -0.5, -1.0, -1.5, -2.0, -2.5, -3.0):
+        _, g_l = evaluate(xyz_h, q_h, m, 1, 1)
+        e = rel_err(torch, g_l, g_fix)
+        tuning.append({"margin": m, "rel_force_err_vs_fixed": e})
+        if e <= 1e-5:
+            margin = m
+        else:
+            break
+    log(f"learned4M: evaluation (margin {margin})")
+    cfg = W.CONFIGS[4]
+    xyz_e, q_e = W.make(cfg)
+    fixed, g_f = evaluate(xyz_e, q_e, None, args.steps, args.warmup)
+    learned, g_l = evaluate(xyz_e, q_e, margin, args.steps, args.warmup)
+    return {"workload": "hernquist4M_p10_learned_orders", "n": cfg["n"], "target_rel_err": 1e-5, "margin": margin,
+            "margin_tuning": tuning, "train_loss_first_last": [float(losses[0]), float(losses[-1])],
+            "train_seconds": t_train,
+            "particles_per_s_learned": learned["particles_per_s"], "particles_per_s_fixed_p10": fixed["particles_per_s"],
+            "m2l_ms_learned": learned["m2l_ms_per_launch"] * learned["m2l_launches_per_step"],
+            "m2l_ms_fixed_p10": fixed["m2l_ms_per_launch"] * fixed["m2l_launches_per_step"],
+            "m2l_alg_flops_ratio": learned["m2l_alg_flops_per_step"] / fixed["m2l_alg_flops_per_step"],
+            "rel_force_err_vs_fixed_p10": rel_err(torch, g_l, g_f),
+            "order_pairs_per_step": learned["m2l_order_pairs_per_step"], "learned": learned, "fixed_p10": fixed}
 
 
 def main():
@@ -114,21 +271,19 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default=DEFAULT_PRECISION, choices=sorted(PEAK_TFLOPS))
-    ap.add_argument("--n", type=int, default=1 << 24)
-    ap.add_argument("--depth", type=int, default=7)
-    ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="uniform16M,batched256,learned4M")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build evaluates on exactly one GPU; multi-GPU sharding is designed (DESIGN.md) "
-              "but not implemented, so --gpus must be 1", file=sys.stderr)
+        print("bench.py: this build evaluates on exactly one GPU (the sharded design is described, not built), "
+              "so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1811_06332_amd import ctfmm as F
@@ -136,7 +291,8 @@ def main():
 
     F.load()
     dev = torch.device("cuda:0")
-    xyz, q = W.uniform_cube(args.n, 1002, -1.0, 1.0)
+    cfg = W.CONFIGS[1]
+    xyz, q = W.make(cfg)
     X = torch.from_numpy(xyz).to(dev)
     Q = torch.from_numpy(q).to(dev)
     del xyz, q
@@ -146,31 +302,36 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {a.numel() * 8} bytes done", file=sys.stderr, flush=True)
+        log(f"calibration copy of {a.numel() * 8} bytes done")
         del a, b
-    print(f"[bench] N={args.n} p={args.p} depth={args.depth} precision={args.precision}", file=sys.stderr, flush=True)
-
-    chosen, phi_c, grad_c = run_leg(F, torch, X, Q, args.p, args.depth, args.precision, args.steps, args.warmup)
+    log(f"{cfg['name']} N={cfg['n']} p={cfg['p']} precision={args.precision}")
+    kw = dict(tree="adaptive", leaf_max=cfg["leaf_max"])
+    chosen, phi_c, grad_c = run_leg(F, torch, X, Q, cfg["p"], args.precision, args.steps, args.warmup, **kw)
     plain = None
     err = {"rel_force_err_vs_fp64": 0.0, "rel_potential_err_vs_fp64": 0.0}
     if args.precision != "fp64" and not args.no_fp64_leg:
-        plain, phi_p, grad_p = run_leg(F, torch, X, Q, args.p, args.depth, "fp64", args.steps, args.warmup)
-        err = {
-            "rel_force_err_vs_fp64": float(torch.linalg.norm(grad_c - grad_p) / torch.linalg.norm(grad_p)),
-            "rel_potential_err_vs_fp64": float(torch.linalg.norm(phi_c - phi_p) / torch.linalg.norm(phi_p)),
-        }
+        plain, phi_p, grad_p = run_leg(F, torch, X, Q, cfg["p"], "fp64", args.steps, args.warmup, **kw)
+        err = {"rel_force_err_vs_fp64": rel_err(torch, grad_c, grad_p),
+               "rel_potential_err_vs_fp64": rel_err(torch, phi_c, phi_p)}
+        del phi_p, grad_p
     elif args.precision == "fp64":
         plain = chosen
+    del X, Q, phi_c, grad_c
+    torch.cuda.empty_cache()
 
     peak = PEAK_TFLOPS[args.precision]
-    flops_launch = chosen["m2l_pairs_per_step"] * 2 * s_of_p(args.p) / max(1, chosen["m2l_launches_per_step"])
-    achieved = flops_launch / (chosen["m2l_avg_launch_ms"] * 1e-3) / 1e12 if chosen["m2l_avg_launch_ms"] else None
-    traffic = m2l_traffic(args.precision) if (args.n, args.p, args.depth) == (1 << 24, 10, 7) else None
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak if achieved else None, "traffic": traffic,
-                "kernel": "M2L (all levels; algorithmic 2*S(p) flops per cell pair)",
-                "flops_per_launch": flops_launch, "avg_launch_ms": chosen["m2l_avg_launch_ms"]}
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.p, args.depth)
+    flops_launch = chosen["m2l_alg_flops_per_step"] / chosen["m2l_launches_per_step"]
+    achieved = flops_launch / (chosen["m2l_ms_per_launch"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": m2l_traffic(f"m2l_{args.precision}_plummer1M_p8"),
+                "kernel": "adaptive M2L (one launch per evaluation; algorithmic 2*S(p) flops per cell pair)",
+                "flops_per_launch": flops_launch, "avg_launch_ms": chosen["m2l_ms_per_launch"]}
+    extras = {}
+    if not args.no_extras:
+        for name in [e for e in args.extras.split(",") if e]:
+            fn = {"uniform16M": extra_uniform16m, "batched256": extra_batched, "learned4M": extra_learned}[name]
+            extras[name] = fn(F, torch, W, args, dev)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg["p"], cfg["leaf_max"])
     out = {
         "metric": METRIC,
         "value": chosen["particles_per_s"],
@@ -184,14 +345,16 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"uniform{args.n}_p{args.p}_d{args.depth}", "n": args.n, "p": args.p,
-                   "depth": args.depth, "ws": 1, "charges": "U(-1,1)", "precision": args.precision},
+        "config": {"workload": cfg["name"], "n": cfg["n"], "distribution": "plummer(scale 1, cut 20)",
+                   "charges": "1/N", "tree": "adaptive", "leaf_max": cfg["leaf_max"], "p": cfg["p"], "ws": 1,
+                   "precision": args.precision},
         "m2l_gflops": chosen["m2l_gflops"],
         "chosen": chosen,
         "plain_fp64": plain,
         **err,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -118,6 +118,8 @@ typedef struct ctfmm_stats_t {
     int64_t m2l_pairs;      /* cell pairs translated by M2L, summed over calls */
     int64_t p2p_leaf_pairs; /* leaf pairs of the near field, summed over calls */
     int64_t graph_launches; /* batched evaluations replayed from the captured graph */
+    int64_t m2l_order_pairs[CTFMM_P_MAX + 1]; /* adaptive tree with timing on: M2L pairs per
+                               order actually used (the chosen-order histogram) */
 } ctfmm_stats_t;
 
 /* Shape of the tree and interaction lists built by the last evaluate. */
@@ -214,6 +216,85 @@ ctfmm_status ctfmm_set_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t targets);
 
 /* The tile shape in use for order p (0 if none has been chosen yet). */
 ctfmm_status ctfmm_get_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t* targets);
+
+/* ---- M2L order per interaction (adaptive tree) ----
+ *
+ * By default every M2L (V-list) pair uses the context order p.  Two other
+ * rules choose an order p' <= p per pair; M2L of a pair is then Eq. M2L
+ * truncated at |n| + |m| <= p' (the order-p' operator acting on the order-p
+ * expansions), and every other operator keeps order p.  The M2L tile of a
+ * group of same-level targets (one octant, up to 128 of them) at one offset
+ * runs at the largest order chosen for its pairs, so no pair gets less than
+ * its rule asks for; tiles are grouped by order and each group runs as one
+ * accumulating M2L launch.  Per-pair orders apply to the systems whose
+ * order is the context's (others of a batch keep their own order). */
+
+/* Order by separation: order_r2 (host, 28 ints) gives the order of a pair
+ * whose integer cell offset v has |v|^2 = k (4 <= k <= 27 occur); entries
+ * must lie in 0..p.  NULL restores the fixed order.  Errors: EINVAL,
+ * EUNSUPPORTED (uniform tree). */
+ctfmm_status ctfmm_set_order_table(ctfmm_ctx* ctx, const int32_t* order_r2);
+
+/* The expansion-order network: 12 inputs -> 64 -> 64 -> 9 outputs, ReLU
+ * after both hidden layers.  Parameters are CTFMM_MLP_NPARAM floats in this
+ * order: W1[64][12], b1[64], W2[64][64], b2[64], W3[9][64], b3[9]
+ * (row-major, y = W x + b per layer).  Output k predicts log10 of the
+ * relative field error of M2L truncated at order k + 2 for one (source
+ * cell, separation) pair; the inputs are |v| / (sqrt(3)/2) and, for ranks
+ * n = 0..10, log10 of the 2-norm of the source's rank-n multipole
+ * components relative to the largest rank norm. */
+#define CTFMM_MLP_NIN 12
+#define CTFMM_MLP_NOUT 9
+#define CTFMM_MLP_NPARAM 5577
+
+/* Choose orders with the network (context order must be 10): for every
+ * (source cell, |v|^2 class) the inputs are standardised with norm (host,
+ * 24 floats: mean[12], then std[12] > 0), the network runs in FP16 on the
+ * matrix cores, and the order is the smallest p' whose prediction is at
+ * most log10(target_rel_err) - margin, else 10 (the fixed order is the
+ * fallback).  params (host) NULL restores the fixed order.  Errors: EINVAL,
+ * EUNSUPPORTED (uniform tree, or p != 10). */
+ctfmm_status ctfmm_set_order_model(ctfmm_ctx* ctx, const float* params, const float* norm, double target_rel_err,
+                                   double margin);
+
+/* Network forward pass on n samples: x dev [n][12], params dev, y dev
+ * [n][9]; precision 0 = FP32, 1 = FP16 operands with FP32 accumulation on
+ * the matrix cores.  Asynchronous.  Errors: EINVAL. */
+ctfmm_status ctfmm_mlp_forward(ctfmm_ctx* ctx, int64_t n, const float* x, const float* params, int32_t precision,
+                               float* y);
+
+/* Gradient of the mean squared error mean_{b,k} (y_bk - t_bk)^2 over n >= 1
+ * samples (x dev [n][12], t dev [n][9]) with respect to params (dev): grad
+ * dev [CTFMM_MLP_NPARAM], loss dev [1].  FP32, summed in a fixed order.
+ * Asynchronous.  Errors: EINVAL, ENOMEM. */
+ctfmm_status ctfmm_mlp_backward(ctfmm_ctx* ctx, int64_t n, const float* x, const float* t, const float* params,
+                                float* grad, float* loss);
+
+/* Adam training (beta 0.9, 0.999, eps 1e-8, step lr) of params (dev, in
+ * place) for `steps` steps, step s using samples ((s-1) mod (n/batch)) *
+ * batch .. + batch - 1 of x, t (dev).  loss_host (may be NULL) receives the
+ * loss of every step.  Synchronises when loss_host is given.  Errors:
+ * EINVAL, ENOMEM. */
+ctfmm_status ctfmm_mlp_train(ctfmm_ctx* ctx, int64_t n, const float* x, const float* t, float* params, int32_t steps,
+                             int32_t batch, float lr, float* loss_host);
+
+/* Inputs and targets of the network for n given pairs (context order 10):
+ * M dev [n][121] scaled order-10 multipoles of cells of side 1 (the
+ * library's independent components), v_host [n][3] integer offsets target -
+ * source with 2 <= |v|_inf <= 3.  x dev [n][12]; y dev [n][9] with
+ * y_k = log10(max(e, 1e-15)), e the relative 2-norm difference of (phi,
+ * grad phi) at the eight points (+-3/8)^3 of the target cell between M2L
+ * truncated at order k + 2 and at order 10 (both evaluated by order-10 L2P).
+ * Synchronises.  Errors: EINVAL, EUNSUPPORTED (p != 10). */
+ctfmm_status ctfmm_mlp_labels(ctfmm_ctx* ctx, int64_t n, const double* M, const int32_t* v_host, float* x, float* y);
+
+/* Training pairs drawn from a particle system (adaptive context of order
+ * 10): builds its tree and multipoles, then sample i takes a cell of level
+ * >= 2 and a far offset chosen by a counter-based hash of (seed, i), and
+ * writes its inputs and targets as ctfmm_mlp_labels.  x, y dev.
+ * Synchronises.  Errors: EINVAL (no cell below level 2), EUNSUPPORTED. */
+ctfmm_status ctfmm_mlp_samples(ctfmm_ctx* ctx, int64_t npart, const double* xyz, const double* q, int64_t nsamp,
+                               uint64_t seed, float* x, float* y);
 
 /* Turn per-phase HIP-event timing on (1) or off (0; default). */
 ctfmm_status ctfmm_set_timing(ctfmm_ctx* ctx, int32_t on);

@@ -949,4 +949,92 @@ void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs,
     hipLaunchKernelGGL(k_p2p_adaptive, grid, blk, 0, s, n, t, leaf_of, P, F, uoff, ulist, idx, to_F, phi, grad);
 }
 
+// ------------------------------------------------------------------ M2L orders per pair
+
+// class of |v|^2 among the 15 occupied values (see k_mlp_decide)
+__device__ inline int class_of_r2_a(int r2) {
+    constexpr int8_t tab[28] = {-1, -1, -1, -1, 0, 1, 2, -1, 3, 4, 5, 6, 7, 8, 9, -1,
+                                -1, 10, 11, 12, -1, -1, 13, -1, -1, -1, -1, 14};
+    return (r2 >= 0 && r2 < 28) ? tab[r2] : -1;
+}
+
+// One wavefront per (tile, offset): the order of its pairs into ord_tab
+// (same layout as src_tab) and as a one-bit mask.  Each pair asks for
+// ordn[source * 15 + class of |v|^2]; the tile's M2L at this offset runs at
+// the largest order asked among its pairs (no pair gets less than it asked
+// for, and the source rows are staged once).  With a table by |v|^2 every
+// pair of a (tile, offset) asks for the same order.
+__global__ __launch_bounds__(64) void k_m2l_orders(int tt, const int4* __restrict__ tiles,
+                                                   const int32_t* __restrict__ src_tab,
+                                                   const int16_t* __restrict__ kslot, const int8_t* __restrict__ ordn,
+                                                   int8_t* __restrict__ ord_tab, uint16_t* __restrict__ omask,
+                                                   int32_t* __restrict__ ocnt) {
+    const int tile = blockIdx.x / 189, iv = blockIdx.x % 189;
+    const int lane = threadIdx.x;
+    const int ks = kslot[tiles[tile].x * 189 + iv];  // slot of r = target - source
+    const int rx = ks % 7 - 3, ry = (ks / 7) % 7 - 3, rz = ks / 49 - 3;
+    const int cls = class_of_r2_a(rx * rx + ry * ry + rz * rz);
+    int omax = -1;
+    for (int r = lane; r < tt; r += 64) {
+        const int src = src_tab[(189 * (size_t)tile + iv) * tt + r];
+        if (src >= 0) omax = max(omax, (int)ordn[(size_t)src * NCLASS + cls]);
+    }
+    for (int off = 1; off < 64; off <<= 1) omax = max(omax, __shfl_xor(omax, off));
+    for (int r = lane; r < tt; r += 64) {
+        const size_t e = (189 * (size_t)tile + iv) * tt + r;
+        ord_tab[e] = src_tab[e] >= 0 ? (int8_t)omax : (int8_t)-1;
+    }
+    if (lane == 0) omask[blockIdx.x] = omax >= 0 ? (uint16_t)(1u << omax) : (uint16_t)0;
+    // pairs per order (the chosen-order histogram)
+    const size_t stride = (size_t)gridDim.x;
+    for (int o = 0; o <= 10; ++o) {
+        int cnt = 0;
+        for (int r = lane; r < tt; r += 64) cnt += ord_tab[(189 * (size_t)tile + iv) * tt + r] == o;
+        for (int off = 1; off < 64; off <<= 1) cnt += __shfl_xor(cnt, off);
+        if (lane == 0) ocnt[o * stride + blockIdx.x] = cnt;
+    }
+}
+
+// One wavefront per tile: for every order p' = 0..10 the offsets whose
+// mask has p', in order: ivlist[p' ntiles 189 + 189 t ..], ivcnt[p' ntiles + t]
+__global__ __launch_bounds__(64) void k_class_lists(int ntiles, const uint16_t* __restrict__ omask,
+                                                    int16_t* __restrict__ ivlist, int32_t* __restrict__ ivcnt) {
+    const int tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int c = 0; c <= 10; ++c) {
+        int16_t* out = ivlist + ((size_t)c * ntiles + tile) * 189;
+        int cnt = 0;
+        for (int b = 0; b < 189; b += 64) {
+            const int iv = b + lane;
+            const bool on = iv < 189 && ((omask[(size_t)tile * 189 + iv] >> c) & 1u);
+            const unsigned long long bal = __ballot(on);
+            if (on) out[cnt + __popcll(bal & ((1ull << lane) - 1ull))] = (int16_t)iv;
+            cnt += __popcll(bal);
+        }
+        if (lane == 0) ivcnt[(size_t)c * ntiles + tile] = cnt;
+    }
+}
+
+__global__ void k_fill0(long long n, double* __restrict__ a) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0;
+}
+
+void launch_m2l_orders(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* src_tab,
+                       const int16_t* kslot, const int8_t* ordn, int8_t* ord_tab, uint16_t* omask, int32_t* ocnt) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_m2l_orders, dim3(189 * ntiles), dim3(64), 0, s, tt, tiles, src_tab, kslot, ordn, ord_tab,
+                       omask, ocnt);
+}
+
+void launch_class_lists(hipStream_t s, int ntiles, const uint16_t* omask, int16_t* ivlist, int32_t* ivcnt) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_class_lists, dim3(ntiles), dim3(64), 0, s, ntiles, omask, ivlist, ivcnt);
+}
+
+void launch_fill0(hipStream_t s, long long n, double* a) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill0, dim3(cdiv(n, 256)), dim3(256), 0, s, n, a);
+}
+
 }  // namespace ctfmm

@@ -99,6 +99,20 @@ struct Forest {
     const unsigned char* Kpk = nullptr;  // operators of order p
     int tt = 64;                         // targets per M2L tile
     int hb[512] = {};                    // (level, octant) bucket bounds on the host
+    // M2L orders per pair
+    int8_t* ordn = nullptr;      // [nn][15] order per (source node, distance class)
+    int8_t* ord_tab = nullptr;   // order of every tile entry (layout of src_tab)
+    uint16_t* omask = nullptr;   // [ntiles][189] orders present
+    int16_t* ivl = nullptr;      // [11][ntiles][189] active offsets per order
+    int32_t* ivc = nullptr;      // [11][ntiles]
+    int32_t* ocnt = nullptr;     // [11][ntiles * 189] pairs per order
+    float* mx = nullptr;         // network inputs of (node, class)
+    float* my = nullptr;         // network outputs
+    size_t ordn_cap = 0, ord_tab_cap = 0, omask_cap = 0, ivl_cap = 0, ivc_cap = 0, ocnt_cap = 0, mx_cap = 0, my_cap = 0;
+    const unsigned char* Kord[CTFMM_P_MAX + 1] = {};  // operators of every order <= p
+    int nchunk = 1;              // M2L workgroups per tile (offset chunks)
+    double* part = nullptr;      // [nchunk][nn][ldm] partial local expansions
+    size_t part_cap = 0;
 };
 
 struct ctfmm_ctx {
@@ -150,6 +164,25 @@ struct ctfmm_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+    hipStream_t ord_stream[CTFMM_P_MAX + 1] = {};  // per-order M2L launches run side by side
+    hipEvent_t ord_ev[CTFMM_P_MAX + 2] = {};
+    // M2L order per pair (adaptive tree): 0 = the fixed order p, 1 = a table
+    // by |v|^2, 2 = the network's decision per (source cell, distance class)
+    int order_mode = 0;
+    int32_t* order_tab = nullptr;  // device [28]
+    float* model = nullptr;        // device [MLP_NPARAM + 24]: parameters, input mean, input std
+    float order_thr = 0.f;         // log10(target error) - margin
+    // network training scratch
+    float* mlp_act = nullptr;
+    float* mlp_err = nullptr;
+    float* mlp_grad = nullptr;
+    float* mlp_m = nullptr;
+    float* mlp_v = nullptr;
+    float* mlp_loss = nullptr;
+    size_t mlp_act_cap = 0, mlp_err_cap = 0, mlp_grad_cap = 0, mlp_m_cap = 0, mlp_v_cap = 0, mlp_loss_cap = 0;
+    int32_t* mlp_sel = nullptr;
+    int32_t* mlp_vs = nullptr;
+    size_t mlp_sel_cap = 0, mlp_vs_cap = 0;
     int tile_forced[CTFMM_P_MAX + 1] = {};  // M2L targets per tile set by the caller (0 = tune)
     int tile_tuned[CTFMM_P_MAX + 1] = {};   // ... chosen by the tuner (0 = not yet)
     hipEvent_t tev[2] = {};                 // events of the tuner
@@ -232,6 +265,13 @@ void reset_adaptive(ctfmm_ctx* c) {
     c->gexec = nullptr;
     c->graph = nullptr;
     c->gsig.clear();
+    c->order_mode = 0;
+    c->order_tab = nullptr;
+    c->model = nullptr;
+    c->mlp_act = c->mlp_err = c->mlp_grad = c->mlp_m = c->mlp_v = c->mlp_loss = nullptr;
+    c->mlp_act_cap = c->mlp_err_cap = c->mlp_grad_cap = c->mlp_m_cap = c->mlp_v_cap = c->mlp_loss_cap = 0;
+    c->mlp_sel = c->mlp_vs = nullptr;
+    c->mlp_sel_cap = c->mlp_vs_cap = 0;
 }
 
 void dev_free_all(ctfmm_ctx* c) {
@@ -534,6 +574,18 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
     return CTFMM_OK;
 }
 
+// The M2L order rule of a forest: per-pair orders (table or network) apply
+// to the forests of the context's own order; other forests keep their order.
+int order_mode_of(const ctfmm_ctx* c, const Forest& f) { return f.p == c->prm.order_p ? c->order_mode : 0; }
+
+// Workgroups per M2L tile: the 189 offsets of a tile are split into chunks
+// until there are about 2048 workgroups (8 per CU), at most 8 per tile.
+int chunks_for(size_t ntiles) {
+    if (ntiles == 0) return 1;
+    const size_t want = (2048 + ntiles - 1) / ntiles;
+    return (int)std::min<size_t>(8, std::max<size_t>(1, want));
+}
+
 // M2L tiles of tt targets from the (level, octant) buckets, and their tables
 ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     const int maxlev = (int)f.lev_first.size() - 1;
@@ -546,7 +598,9 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
         }
     f.tt = tt;
     const size_t ntiles = f.tiles_host.size();
+    f.nchunk = chunks_for(ntiles);
     if (!ntiles) return CTFMM_OK;
+    if (f.nchunk > 1) ACHK(grow(c, f.part, f.part_cap, (size_t)f.nchunk * f.nn * ldm_of(f.p), false));
     ACHK(grow(c, f.tiles, f.tiles_cap, ntiles, false));
     ACHK(grow(c, f.tgt_tab, f.tgt_cap, (size_t)tt * ntiles, false));
     ACHK(grow(c, f.src_tab, f.src_cap, (size_t)189 * tt * ntiles, false));
@@ -573,11 +627,18 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best) {
     for (int tt : {32, 64, 128}) {
         if (m2l_tile_lds_bytes(f.p, prec, tt) > (size_t)max_lds) continue;
         SCHK(make_tiles(c, f, tt));
-        const AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+        AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+        double* out = f.aL;
+        if (f.nchunk > 1) {
+            ad.acc = true;
+            ad.nchunk = f.nchunk;
+            ad.chunk_stride = (size_t)f.nn * ldm_of(f.p);
+            out = f.part;
+        }
         const int nt = (int)f.tiles_host.size();
-        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, f.aL, f.Kpk, c->zero_row));
+        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, out, f.Kpk, c->zero_row));
         HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
-        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, f.aL, f.Kpk, c->zero_row));
+        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, out, f.Kpk, c->zero_row));
         HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
         HIPCHK(c, hipEventSynchronize(c->tev[1]));
         float ms = 0.f;
@@ -741,6 +802,25 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         c->tile_tuned[f.p] = tt;
     }
     SCHK(make_tiles(c, f, tt ? tt : 64));
+    if (order_mode_of(c, f) != 0 && !f.tiles_host.empty()) {
+        const size_t nt = f.tiles_host.size();
+        for (int k = 0; k <= f.p; ++k) SCHK(get_ops(c, k, &f.Kord[k]));
+        ACHK(grow(c, f.ordn, f.ordn_cap, (size_t)nn * NCLASS, false));
+        ACHK(grow(c, f.ord_tab, f.ord_tab_cap, (size_t)189 * f.tt * nt, false));
+        ACHK(grow(c, f.omask, f.omask_cap, 189 * nt, false));
+        ACHK(grow(c, f.ivl, f.ivl_cap, (size_t)11 * 189 * nt, false));
+        ACHK(grow(c, f.ivc, f.ivc_cap, 11 * nt, false));
+        ACHK(grow(c, f.ocnt, f.ocnt_cap, (size_t)11 * 189 * nt, false));
+        ACHK(grow(c, f.part, f.part_cap, (size_t)(f.p + 1) * f.nn * ldm_of(f.p), false));
+        for (int k = 0; k <= f.p; ++k)
+            if (!c->ord_stream[k]) HIPCHK(c, hipStreamCreateWithFlags(&c->ord_stream[k], hipStreamNonBlocking));
+        for (auto& e : c->ord_ev)
+            if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        if (order_mode_of(c, f) == 2) {
+            ACHK(grow(c, f.mx, f.mx_cap, (size_t)nn * NCLASS * MLP_NIN, false));
+            ACHK(grow(c, f.my, f.my_cap, (size_t)nn * NCLASS * MLP_NOUT, false));
+        }
+    }
     HIPCHK(c, hipGetLastError());
     f.v_pairs = -1;
     return CTFMM_OK;
@@ -792,9 +872,61 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     mark(3);
     // downward: L(B) = M2L(V) + P2L(X) + L2L(parent).  M2L over the tiles of
     // every level at once (it reads only M), then the X lists, then L2L top-down.
-    if (!f.tiles_host.empty()) {
-        const AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
-        HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk, c->zero_row));
+    const int omode = order_mode_of(c, f);
+    const size_t lsz = (size_t)nn * ldm_of(p);
+    if (!f.tiles_host.empty() && omode == 0) {
+        AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+        if (f.nchunk == 1) {
+            HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk,
+                                        c->zero_row));
+        } else {
+            launch_fill0(st, (long long)(f.nchunk * lsz), f.part);
+            ad.acc = true;
+            ad.nchunk = f.nchunk;
+            ad.chunk_stride = lsz;
+            HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.part, f.Kpk,
+                                        c->zero_row));
+            launch_sum_chunks(st, f.nchunk, lsz, f.part, f.aL);
+        }
+    } else if (!f.tiles_host.empty()) {
+        // orders per (source cell, distance class), then one accumulating
+        // M2L launch per order over the offsets where that order occurs
+        const int nt = (int)f.tiles_host.size();
+        const int f2 = f.lev_first[2];
+        if (omode == 1) {
+            launch_order_table(st, nn, c->order_tab, f.ordn);
+        } else {
+            const long long rows = (long long)(nn - f2) * NCLASS;
+            launch_mlp_node_features(st, f2, nn - f2, f.aM, ldm_of(p), f.mx);
+            launch_mlp_forward16(st, rows, f.mx, c->model, c->model + MLP_NPARAM, f.my);
+            launch_mlp_decide(st, f2, nn - f2, f.my, c->order_thr, f.ordn);
+        }
+        launch_m2l_orders(st, f.tt, nt, f.tiles, f.src_tab, c->alist + 8 * 189, f.ordn, f.ord_tab, f.omask, f.ocnt);
+        launch_class_lists(st, nt, f.omask, f.ivl, f.ivc);
+        // one launch per order, side by side on their own streams (the tails
+        // of one overlap the others), each adding into its own slot of part;
+        // the slots are then summed in order
+        launch_fill0(st, (long long)((p + 1) * lsz), f.part);
+        HIPCHK(c, hipEventRecord(c->ord_ev[CTFMM_P_MAX + 1], st));
+        const int ld_in = prec == CTFMM_PREC_FP64 ? ldm_of(p) * 8 : s32_of(p) * 4;
+        for (int k = 0; k <= p; ++k) {
+            hipStream_t sk = c->ord_stream[k];
+            HIPCHK(c, hipStreamWaitEvent(sk, c->ord_ev[CTFMM_P_MAX + 1], 0));
+            AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+            ad.ivlist = f.ivl + (size_t)k * nt * 189;
+            ad.ivcnt = f.ivc + (size_t)k * nt;
+            ad.ord = f.ord_tab;
+            ad.cls = k;
+            ad.ld_in = ld_in;
+            ad.ld_out = ldm_of(p);
+            ad.acc = true;
+            ad.nchunk = 1;
+            HIPCHK(c, launch_m2l_tables(sk, k, prec, f.tt, nt, ad, msrc, f.part + (size_t)k * lsz, f.Kord[k],
+                                        c->zero_row));
+            HIPCHK(c, hipEventRecord(c->ord_ev[k], sk));
+            HIPCHK(c, hipStreamWaitEvent(st, c->ord_ev[k], 0));
+        }
+        launch_sum_chunks(st, p + 1, lsz, f.part, f.aL);
     }
     mark(4);
     if (f.tot_x > 0) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * ((size_t)nn + 1), f.xlist, f.a_P, f.aL);
@@ -806,6 +938,26 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
                          f.wpoff, f.wbuf, f.loff, f.ulist, f.a_idxs, f.a_F, to_F, phi, grad);
     mark(7);
     HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+// pairs per M2L order of the last numeric pass of f (waits for the stream)
+ctfmm_status add_order_hist(ctfmm_ctx* c, Forest& f) {
+    const int m = 189 * (int)f.tiles_host.size();
+    if (m == 0) return CTFMM_OK;
+    if (order_mode_of(c, f) == 0) {
+        SCHK(count_v_pairs(c, f));
+        c->st.m2l_order_pairs[f.p] += f.v_pairs;
+        return CTFMM_OK;
+    }
+    for (int o = 0; o <= f.p; ++o) {
+        int v = 0;
+        const int32_t* in = f.ocnt + (size_t)o * m;
+        SCHK(cub_run(c, [&](void* t, size_t& b) { return hipcub::DeviceReduce::Sum(t, b, in, f.vsum, m, c->stream); }));
+        HIPCHK(c, hipMemcpyAsync(&v, f.vsum, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->st.m2l_order_pairs[o] += v;
+    }
     return CTFMM_OK;
 }
 
@@ -838,6 +990,7 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
     if (c->timing) {
         SCHK(count_v_pairs(c, f));
         c->st.m2l_pairs += f.v_pairs;
+        SCHK(add_order_hist(c, f));
         HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
         c->st.ms_total += elapsed(c, 0, ev_end);
         c->st.ms_tree += elapsed(c, 0, 1);
@@ -1070,14 +1223,16 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
     rec(c, 1);
     // every value the numeric launches depend on
     // (the outputs are not among them: the graph leaves results in sorted order)
-    std::vector<long long> sig = {c->nforests};
+    std::vector<long long> sig = {c->nforests, c->order_mode};
     for (int k = 0; k < c->nforests; ++k) {
         const Forest& f = c->forests[k];
         const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys,
                               f.a_P, f.a_F, f.aM, f.aL, f.aMh, f.aM32, f.loff, f.xlist, f.wlist, f.ulist, f.wpoff,
-                              f.wbuf, f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk};
+                              f.wbuf, f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.ordn,
+                              f.ord_tab, f.omask, f.ivl, f.ivc, f.mx, f.my, c->order_tab, c->model, f.part};
         for (const void* q2 : ptrs) sig.push_back((long long)(uintptr_t)q2);
-        sig.insert(sig.end(), {f.p, f.n, f.nn, f.wpairs, (long long)f.tiles_host.size(), f.tot_w, f.tot_x, f.tt});
+        sig.insert(sig.end(), {f.p, f.n, f.nn, f.wpairs, (long long)f.tiles_host.size(), f.tot_w, f.tot_x, f.tt,
+                               f.nchunk});
         sig.insert(sig.end(), f.lev_first.begin(), f.lev_first.end());
         sig.insert(sig.end(), f.lev_count.begin(), f.lev_count.end());
     }
@@ -1128,6 +1283,7 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
         for (int k = 0; k < c->nforests; ++k) {
             SCHK(count_v_pairs(c, c->forests[k]));
             c->st.m2l_pairs += c->forests[k].v_pairs;
+            SCHK(add_order_hist(c, c->forests[k]));
         }
         HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
         c->st.ms_total += elapsed(c, 0, ev_end);
@@ -1199,6 +1355,173 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
     return CTFMM_OK;
 }
 
+ctfmm_status ctfmm_set_order_table(ctfmm_ctx* c, const int32_t* order_r2) {
+    if (!c) return CTFMM_EINVAL;
+    if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "per-pair orders need the adaptive tree");
+    if (!order_r2) {
+        c->order_mode = 0;
+        return CTFMM_OK;
+    }
+    for (int k = 4; k <= 27; ++k)
+        if (order_r2[k] < 0 || order_r2[k] > c->prm.order_p)
+            return fail(c, CTFMM_EINVAL, "orders must lie in 0..p for |v|^2 in 4..27");
+    if (!c->order_tab) {
+        size_t cap = 0;
+        if (!grow(c, c->order_tab, cap, 28, false)) return fail(c, CTFMM_ENOMEM, "allocation failed");
+    }
+    int32_t tab[28];
+    std::memcpy(tab, order_r2, sizeof(tab));
+    HIPCHK(c, hipMemcpyAsync(c->order_tab, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->order_mode = 1;
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_set_order_model(ctfmm_ctx* c, const float* params, const float* norm, double target_rel_err,
+                                   double margin) {
+    if (!c) return CTFMM_EINVAL;
+    if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "per-pair orders need the adaptive tree");
+    if (!params) {
+        c->order_mode = 0;
+        return CTFMM_OK;
+    }
+    if (c->prm.order_p != 10) return fail(c, CTFMM_EUNSUPPORTED, "the network chooses orders 2..10: use p = 10");
+    if (!norm || !(target_rel_err > 0.0) || !std::isfinite(margin)) return fail(c, CTFMM_EINVAL, "bad model arguments");
+    for (int k = 0; k < MLP_NIN; ++k)
+        if (!(norm[MLP_NIN + k] > 0.f)) return fail(c, CTFMM_EINVAL, "input scales must be positive");
+    if (!c->model) {
+        size_t cap = 0;
+        if (!grow(c, c->model, cap, MLP_NPARAM + 2 * MLP_NIN, false)) return fail(c, CTFMM_ENOMEM, "allocation failed");
+    }
+    std::vector<float> buf(MLP_NPARAM + 2 * MLP_NIN);
+    std::memcpy(buf.data(), params, MLP_NPARAM * sizeof(float));
+    std::memcpy(buf.data() + MLP_NPARAM, norm, 2 * MLP_NIN * sizeof(float));
+    HIPCHK(c, hipMemcpyAsync(c->model, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->order_thr = (float)(std::log10(target_rel_err) - margin);
+    c->order_mode = 2;
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_mlp_forward(ctfmm_ctx* c, int64_t n, const float* x, const float* params, int32_t precision,
+                               float* y) {
+    if (!c) return CTFMM_EINVAL;
+    if (n < 0 || (n > 0 && (!x || !params || !y)) || (precision != 0 && precision != 1))
+        return fail(c, CTFMM_EINVAL, "n >= 0, device x, params, y and precision 0 (FP32) or 1 (FP16)");
+    if (precision == 0) launch_mlp_forward32(c->stream, n, x, params, y);
+    else launch_mlp_forward16(c->stream, n, x, params, nullptr, y);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_mlp_backward(ctfmm_ctx* c, int64_t n, const float* x, const float* t, const float* params,
+                                float* grad, float* loss) {
+    if (!c) return CTFMM_EINVAL;
+    if (n < 1 || !x || !t || !params || !grad || !loss) return fail(c, CTFMM_EINVAL, "n >= 1 and device pointers");
+    if (!grow(c, c->mlp_act, c->mlp_act_cap, (size_t)n * 5 * MLP_NH + mlp_backward_part_floats(n), false) ||
+        !grow(c, c->mlp_err, c->mlp_err_cap, (size_t)n, false))
+        return fail(c, CTFMM_ENOMEM, "allocation failed");
+    launch_mlp_backward(c->stream, n, x, t, params, c->mlp_act, c->mlp_err, grad, loss);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_mlp_train(ctfmm_ctx* c, int64_t n, const float* x, const float* t, float* params, int32_t steps,
+                             int32_t batch, float lr, float* loss_host) {
+    if (!c) return CTFMM_EINVAL;
+    if (!x || !t || !params || steps < 1 || batch < 1 || batch > n || !(lr > 0.f))
+        return fail(c, CTFMM_EINVAL, "1 <= batch <= n, steps >= 1, lr > 0 and device pointers");
+    if (!grow(c, c->mlp_act, c->mlp_act_cap, (size_t)batch * 5 * MLP_NH + mlp_backward_part_floats(batch), false) ||
+        !grow(c, c->mlp_err, c->mlp_err_cap, (size_t)batch, false) ||
+        !grow(c, c->mlp_grad, c->mlp_grad_cap, MLP_NPARAM, false) ||
+        !grow(c, c->mlp_m, c->mlp_m_cap, MLP_NPARAM, false) || !grow(c, c->mlp_v, c->mlp_v_cap, MLP_NPARAM, false) ||
+        !grow(c, c->mlp_loss, c->mlp_loss_cap, (size_t)steps, false))
+        return fail(c, CTFMM_ENOMEM, "allocation failed");
+    HIPCHK(c, hipMemsetAsync(c->mlp_m, 0, MLP_NPARAM * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->mlp_v, 0, MLP_NPARAM * sizeof(float), c->stream));
+    const int64_t windows = n / batch;
+    for (int step = 1; step <= steps; ++step) {
+        const int64_t start = ((step - 1) % windows) * batch;
+        launch_mlp_backward(c->stream, batch, x + start * MLP_NIN, t + start * MLP_NOUT, params, c->mlp_act,
+                            c->mlp_err, c->mlp_grad, c->mlp_loss + (step - 1));
+        launch_adam(c->stream, step, lr, params, c->mlp_grad, c->mlp_m, c->mlp_v);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (loss_host) {
+        HIPCHK(c, hipMemcpyAsync(loss_host, c->mlp_loss, steps * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return CTFMM_OK;
+}
+
+namespace {
+
+// offset slot of v (2 <= |v|_inf <= 3), or -1
+int far_slot(const int32_t* v) {
+    const int a = std::abs(v[0]), b = std::abs(v[1]), d = std::abs(v[2]);
+    const int m = std::max(a, std::max(b, d));
+    if (m < 2 || m > 3) return -1;
+    return (v[0] + 3) + 7 * (v[1] + 3) + 49 * (v[2] + 3);
+}
+
+}  // namespace
+
+ctfmm_status ctfmm_mlp_labels(ctfmm_ctx* c, int64_t n, const double* M, const int32_t* v_host, float* x, float* y) {
+    if (!c) return CTFMM_EINVAL;
+    if (c->prm.order_p != 10) return fail(c, CTFMM_EUNSUPPORTED, "training data needs a context of order 10");
+    if (n < 0 || (n > 0 && (!M || !v_host || !x || !y))) return fail(c, CTFMM_EINVAL, "bad arguments");
+    if (n == 0) return CTFMM_OK;
+    std::vector<int32_t> slots((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        slots[i] = far_slot(v_host + 3 * i);
+        if (slots[i] < 0) return fail(c, CTFMM_EINVAL, "offsets need 2 <= |v|_inf <= 3");
+    }
+    if (!grow(c, c->mlp_vs, c->mlp_vs_cap, (size_t)n, false)) return fail(c, CTFMM_ENOMEM, "allocation failed");
+    HIPCHK(c, hipMemcpyAsync(c->mlp_vs, slots.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    launch_mlp_labels(c->stream, n, M, 121, nullptr, c->mlp_vs, c->Kt, x, y);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_mlp_samples(ctfmm_ctx* c, int64_t npart, const double* xyz, const double* q, int64_t nsamp,
+                               uint64_t seed, float* x, float* y) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (c->prm.tree != CTFMM_TREE_ADAPTIVE || c->prm.order_p != 10)
+        return fail(c, CTFMM_EUNSUPPORTED, "training data needs an adaptive context of order 10");
+    if (npart < 1 || npart >= (int64_t(1) << 31) || nsamp < 0 || !xyz || !q || (nsamp > 0 && (!x || !y)))
+        return fail(c, CTFMM_EINVAL, "bad arguments");
+    if (c->forests.empty()) c->forests.resize(1);
+    Forest& f = c->forests[0];
+    c->nforests = 1;
+    f.p = 10;
+    f.nsys = 1;
+    f.n = (int)npart;
+    f.goff_h = {0, (int)npart};
+    f.gbase_h = {0};
+    const int saved_mode = c->order_mode;
+    c->order_mode = 0;
+    ctfmm_status s = build_forest(c, f, xyz, q, c->prm.root_side > 0.0);
+    c->order_mode = saved_mode;
+    if (s != CTFMM_OK) return s;
+    const int maxlev = (int)f.lev_first.size() - 1;
+    if (maxlev < 2) return fail(c, CTFMM_EINVAL, "the tree has no cells below level 2 to sample");
+    launch_p2m_nodes(c->stream, 10, 0, f.nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
+    for (int l = maxlev - 1; l >= 2; --l)
+        launch_m2m_nodes(c->stream, 10, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
+    if (!grow(c, c->mlp_sel, c->mlp_sel_cap, (size_t)std::max<int64_t>(nsamp, 1), false) ||
+        !grow(c, c->mlp_vs, c->mlp_vs_cap, (size_t)std::max<int64_t>(nsamp, 1), false))
+        return fail(c, CTFMM_ENOMEM, "allocation failed");
+    const int f2 = f.lev_first[2];
+    launch_mlp_pick(c->stream, nsamp, seed, f2, f.nn - f2, c->mlp_sel, c->mlp_vs);
+    launch_mlp_labels(c->stream, nsamp, f.aM, ldm_of(10), c->mlp_sel, c->mlp_vs, c->Kt, x, y);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_result = false;
+    return CTFMM_OK;
+}
+
 ctfmm_status ctfmm_set_m2l_tile(ctfmm_ctx* c, int32_t p, int32_t targets) {
     if (!c) return CTFMM_EINVAL;
     if (p < 0 || p > CTFMM_P_MAX || (targets != 0 && targets != 32 && targets != 64 && targets != 128))
@@ -1260,6 +1583,10 @@ void ctfmm_destroy(ctfmm_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& e : c->tev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->ord_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& x : c->ord_stream)
+        if (x) (void)hipStreamDestroy(x);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;

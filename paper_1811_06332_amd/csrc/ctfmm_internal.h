@@ -88,6 +88,11 @@ __host__ __device__ inline uint32_t compact21(uint64_t v) {
     return (uint32_t)v;
 }
 
+// ---- expansion-order network (ctfmm_mlp.hip) ----
+constexpr int MLP_NIN = 12, MLP_NH = 64, MLP_NOUT = 9;  // outputs: orders 2..10
+constexpr int MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NOUT * MLP_NH + MLP_NOUT;
+constexpr int NCLASS = 15;  // occupied |v|^2 classes of the ws=1 offsets
+
 // root cube of one adaptive tree
 struct ABox {
     double lo[3];
@@ -118,12 +123,28 @@ struct ASys {
 // M2L over tables: tile t has TT target rows tgt[TT t ..] (-1 = none) of
 // octant tiles[t].x, and for offset i of that octant the source rows
 // src[(189 t + i) TT ..] (-1 = none); kslot[o][i] = slot of its operator.
+// Optional, for M2L orders that vary by pair: ivcnt[t] offsets of tile t
+// are active, listed in ivlist[189 t ..]; only pairs whose ord entry
+// (same index as src) equals cls contribute; rows of Msrc are ld_in bytes
+// apart and rows of L ld_out doubles apart (0 = the kernel order's own
+// strides); acc adds to L instead of writing it.
 struct AdaptM2L {
     const int4* tiles;
     const int32_t* tgt;
     const int32_t* src;
     const int16_t* kslot;
     int tile_base;
+    const int16_t* ivlist = nullptr;
+    const int32_t* ivcnt = nullptr;
+    const int8_t* ord = nullptr;
+    int cls = 0;
+    int ld_in = 0;
+    int ld_out = 0;
+    bool acc = false;
+    // the offsets of a tile split over nchunk workgroups (balanced, in list
+    // order); chunk c adds into L + c * chunk_stride (nchunk > 1 needs acc)
+    int nchunk = 1;
+    size_t chunk_stride = 0;
 };
 
 // P2M of one cell by one wavefront, two phases.  (1) Full monomial moments
@@ -248,5 +269,27 @@ void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs,
                           const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, bool to_F,
                           double* phi, double* grad);
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
+
+// ---- expansion orders per pair (ctfmm_adaptive.hip, ctfmm_mlp.hip) ----
+void launch_m2l_orders(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* src_tab,
+                       const int16_t* kslot, const int8_t* ordn, int8_t* ord_tab, uint16_t* omask, int32_t* ocnt);
+void launch_class_lists(hipStream_t s, int ntiles, const uint16_t* omask, int16_t* ivlist, int32_t* ivcnt);
+void launch_fill0(hipStream_t s, long long n, double* a);
+void launch_mlp_forward32(hipStream_t s, long long n, const float* x, const float* prm, float* y);
+void launch_mlp_forward16(hipStream_t s, long long n, const float* x, const float* prm, const float* norm, float* y);
+void launch_mlp_backward(hipStream_t s, long long n, const float* x, const float* t, const float* prm, float* act,
+                         float* err, float* grad, float* loss);
+size_t mlp_backward_part_floats(long long n);
+void launch_adam(hipStream_t s, int step, float lr, float* prm, const float* g, float* m, float* v);
+void launch_mlp_labels(hipStream_t s, long long n, const double* M, long long mstride, const int32_t* sel,
+                       const int32_t* vslot, const double* Kt, float* x, float* y);
+void launch_mlp_pick(hipStream_t s, long long n, unsigned long long seed, int first, int count, int32_t* sel,
+                     int32_t* vs);
+void launch_gather_rows(hipStream_t s, long long n, const int32_t* sel, const double* M, int ldm, double* out);
+void launch_mlp_node_features(hipStream_t s, int first, int count, const double* M, int ldm, float* x);
+void launch_mlp_decide(hipStream_t s, int first, int count, const float* y, float thr, int8_t* ord);
+void launch_order_table(hipStream_t s, int count, const int32_t* tab, int8_t* ord);
+
+void launch_sum_chunks(hipStream_t s, int nchunk, size_t stride, const double* part, double* L);
 
 }  // namespace ctfmm

@@ -520,7 +520,18 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
 
     // work item = 8 * parent block + target octant; each XCD takes a contiguous
     // range, so the 8 octants of a block and neighbouring blocks share its L2
-    const long long work = ADAPT ? ad.tile_base + xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x);
+    const long long blk = xcd_remap(blockIdx.x, gridDim.x);
+    const long long work = ADAPT ? ad.tile_base + blk / ad.nchunk : blk;
+    const int chunk = ADAPT ? (int)(blk % ad.nchunk) : 0;
+    // offsets of this tile: all 189, or the active ones listed for it; this
+    // workgroup takes list entries [j0, j0 + nv)
+    const int nv_all = (ADAPT && ad.ivcnt) ? ad.ivcnt[work] : 189;
+    const int j0 = ADAPT ? (int)((long long)nv_all * chunk / ad.nchunk) : 0;
+    const int nv = ADAPT ? (int)((long long)nv_all * (chunk + 1) / ad.nchunk) - j0 : 189;
+    if (nv == 0) return;  // nothing to add (only with ad.acc)
+    auto ivof = [&](int j) -> int {
+        return (ADAPT && ad.ivlist) ? (int)ad.ivlist[189 * work + j0 + j] : j0 + j;
+    };
     const int o = ADAPT ? ad.tiles[work].x : (int)(work & 7);
     const long long pb = work >> 3;
     const int tid = threadIdx.x;
@@ -556,7 +567,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     auto src_row = [&](int iv, int k) -> int {
         if (ADAPT) {
             const int r = lane + 64 * k;
-            return r < TT ? ad.src[(189 * (size_t)work + iv) * TT + r] : -1;
+            if (r >= TT) return -1;
+            const size_t e = (189 * (size_t)work + iv) * TT + r;
+            const int sr = ad.src[e];
+            return (ad.ord && ad.ord[e] != ad.cls) ? -1 : sr;
         }
         const int vs = offlist[o * 189 + iv];
         const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
@@ -574,6 +588,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         for (int k = 0; k < RL; ++k) myrow[k] = src_row(iv, k);
         unsigned char* dst = Bb + buf * S::BBYTES;
         const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
+        const size_t gstride = (ADAPT && ad.ld_in) ? (size_t)ad.ld_in : (size_t)S::BROW;
         // RPI rows per copy instruction (RU units each); RPI = 1 unless RU divides 64
         constexpr int RPI = (RU <= 64 && 64 % RU == 0) ? 64 / RU : 1;
         constexpr int NI = TT >= RPI ? TT / RPI : 1;
@@ -586,7 +601,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             else row = __shfl(v, (r0 & 63) + lane / RU);
             if (lane < RPI * RU && r0 + lane / RU < TT) {
                 const int ul = lane % RU;
-                const unsigned char* g = row >= 0 ? Mb + (size_t)row * S::BROW + ul * 16 : zero_row + ul * 16;
+                const unsigned char* g = row >= 0 ? Mb + (size_t)row * gstride + ul * 16 : zero_row + ul * 16;
                 lds_copy16(g, dst + (size_t)i * RPI * S::BROW);
             }
         }
@@ -604,18 +619,18 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             for (int k = 0; k < 6; ++k) accb[r][k] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
-    stage_k(0, 0);
-    stage_b(0, 0);
+    stage_k(ivof(0), 0);
+    stage_b(ivof(0), 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int trow = w * 16 + (lane & 15);  // this lane's target slot in B fragments
     const int kq = lane >> 4;
-    for (int iv = 0; iv < 189; ++iv) {
-        const int kb = S::KBUF == 2 ? (iv & 1) : 0;
-        const int bb = iv & 1;
-        if (iv + 1 < 189) {
-            if (S::KBUF == 2) stage_k(iv + 1, kb ^ 1);
-            stage_b(iv + 1, bb ^ 1);
+    for (int j = 0; j < nv; ++j) {
+        const int kb = S::KBUF == 2 ? (j & 1) : 0;
+        const int bb = j & 1;
+        if (j + 1 < nv) {
+            if (S::KBUF == 2) stage_k(ivof(j + 1), kb ^ 1);
+            stage_b(ivof(j + 1), bb ^ 1);
         }
         const unsigned char* Kc = Kb + kb * S::KBYTES;
         const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROW;
@@ -679,10 +694,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
                     }
             }
         }
-        if (iv + 1 < 189) {
+        if (j + 1 < nv) {
             if (S::KBUF == 1) {
                 __syncthreads();  // every wave is done with this offset's K_v
-                stage_k(iv + 1, 0);
+                stage_k(ivof(j + 1), 0);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
@@ -697,7 +712,9 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         if (par >= nparents) return;
         trow_out = par * 8 + o;
     }
-    double* Lt = L + (size_t)trow_out * LDM;
+    const int ldo = (ADAPT && ad.ld_out) ? ad.ld_out : LDM;
+    const bool acc_out = ADAPT && ad.acc;
+    double* Lt = L + (ADAPT ? (size_t)chunk * ad.chunk_stride : 0) + (size_t)trow_out * ldo;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (PREC == PREC_F64) {
@@ -706,7 +723,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             const int row0 = 16 * r + (lane >> 4);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (row0 + 4 * j < NC) Lt[row0 + 4 * j] = sacc[j];
+                if (row0 + 4 * j < NC) {
+                    if (acc_out) Lt[row0 + 4 * j] += sacc[j];
+                    else Lt[row0 + 4 * j] = sacc[j];
+                }
         } else {
             // FP32 16x16 accumulator: element j holds row 16r + 4*(lane/16) + j
             const int row0 = 16 * r + 4 * (lane >> 4);
@@ -720,7 +740,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
 #pragma unroll
                     for (int k = 0; k < 6; ++k) v += (double)accb[r][k][j];
                 }
-                if (row0 + j < NC) Lt[row0 + j] = v;
+                if (row0 + j < NC) {
+                    if (acc_out) Lt[row0 + j] += v;
+                    else Lt[row0 + j] = v;
+                }
             }
         }
     }
@@ -1016,10 +1039,25 @@ hipError_t m2l_tables_prec(hipStream_t s, int prec, int ntiles, const AdaptM2L& 
     return m2l_tile_impl<P, PREC_BF16X3, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
 }
 
-hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles, const AdaptM2L& ad, const void* Msrc,
-                             double* L, const unsigned char* Kpk, const unsigned char* zero_row) {
-    if (ntiles <= 0) return hipSuccess;
+__global__ void k_sum_chunks(int nchunk, size_t stride, const double* __restrict__ part, double* __restrict__ L) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= stride) return;
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += part[c * stride + i];
+    L[i] = v;
+}
+
+void launch_sum_chunks(hipStream_t s, int nchunk, size_t stride, const double* part, double* L) {
+    if (stride == 0) return;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(cdiv((long long)stride, 256)), dim3(256), 0, s, nchunk, stride, part, L);
+}
+
+hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles_in, const AdaptM2L& ad,
+                             const void* Msrc, double* L, const unsigned char* Kpk, const unsigned char* zero_row) {
+    if (ntiles_in <= 0) return hipSuccess;
     if (tt != 32 && tt != 64 && tt != 128) return hipErrorInvalidValue;
+    if (ad.nchunk < 1 || (ad.nchunk > 1 && !ad.acc)) return hipErrorInvalidValue;
+    const int ntiles = ntiles_in * ad.nchunk;  // workgroups
     switch (p) {
 #define CASE(PP)                                                                                         \
     case PP:                                                                                             \

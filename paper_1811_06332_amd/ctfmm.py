@@ -23,7 +23,8 @@ CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
             "ctfmm_evaluate", "ctfmm_evaluate_batched", "ctfmm_copy_expansions", "ctfmm_tree_stats",
-            "ctfmm_set_m2l_tile", "ctfmm_get_m2l_tile", "ctfmm_set_timing", "ctfmm_stats",
+            "ctfmm_set_m2l_tile", "ctfmm_get_m2l_tile", "ctfmm_set_order_table", "ctfmm_set_order_model",
+            "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_train", "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats",
             "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
 
@@ -44,7 +45,8 @@ class ctfmm_stats_t(C.Structure):
                 ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
                 ("ms_near", C.c_double), ("ms_convert", C.c_double), ("ms_p2l", C.c_double),
                 ("ms_numeric", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
-                ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64), ("graph_launches", C.c_int64)]
+                ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64), ("graph_launches", C.c_int64),
+                ("m2l_order_pairs", C.c_int64 * 11)]
 
 
 class ctfmm_tree_stats_t(C.Structure):
@@ -73,6 +75,13 @@ def load():
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.ctfmm_tree_stats.argtypes = [vp, C.POINTER(ctfmm_tree_stats_t)]
         L.ctfmm_set_m2l_tile.argtypes = [vp, i32, i32]
+        L.ctfmm_set_order_table.argtypes = [vp, vp]
+        L.ctfmm_set_order_model.argtypes = [vp, vp, vp, C.c_double, C.c_double]
+        L.ctfmm_mlp_forward.argtypes = [vp, i64, vp, vp, i32, vp]
+        L.ctfmm_mlp_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.ctfmm_mlp_train.argtypes = [vp, i64, vp, vp, vp, i32, i32, C.c_float, vp]
+        L.ctfmm_mlp_labels.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ctfmm_mlp_samples.argtypes = [vp, i64, vp, vp, i64, C.c_uint64, vp, vp]
         L.ctfmm_get_m2l_tile.argtypes = [vp, i32, C.POINTER(C.c_int32)]
         L.ctfmm_set_timing.argtypes = [vp, i32]
         L.ctfmm_stats.argtypes = [vp, C.POINTER(ctfmm_stats_t)]
@@ -178,6 +187,93 @@ def ctfmm_get_m2l_tile(ctx, p: int) -> int:
     return v.value
 
 
+MLP_NIN, MLP_NOUT, MLP_NPARAM = 12, 9, 5577
+
+
+def mlp_init_params(seed: int):
+    """Starting parameters of the order network (flat layout of
+    CTFMM_MLP_NPARAM): He-uniform weights, zero biases, float32."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((MLP_NIN, 64), (64, 64), (64, MLP_NOUT)):
+        lim = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, (fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _f32dev(t, shape=None):
+    if t is None or not t.is_cuda or str(t.dtype) != "torch.float32" or not t.is_contiguous():
+        raise ValueError("expected a contiguous cuda float32 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return _ptr(t)
+
+
+def ctfmm_set_order_table(ctx, order_r2) -> None:
+    import numpy as np
+    if order_r2 is None:
+        _check(load().ctfmm_set_order_table(C.c_void_p(ctx), None), C.c_void_p(ctx))
+        return
+    tab = np.ascontiguousarray(order_r2, dtype=np.int32)
+    assert tab.size == 28
+    _check(load().ctfmm_set_order_table(C.c_void_p(ctx), C.c_void_p(tab.ctypes.data)), C.c_void_p(ctx))
+
+
+def ctfmm_set_order_model(ctx, params, norm, target_rel_err: float, margin: float) -> None:
+    import numpy as np
+    if params is None:
+        _check(load().ctfmm_set_order_model(C.c_void_p(ctx), None, None, 1.0, 0.0), C.c_void_p(ctx))
+        return
+    prm = np.ascontiguousarray(params, dtype=np.float32)
+    nrm = np.ascontiguousarray(norm, dtype=np.float32)
+    assert prm.size == MLP_NPARAM and nrm.size == 2 * MLP_NIN
+    _check(load().ctfmm_set_order_model(C.c_void_p(ctx), C.c_void_p(prm.ctypes.data), C.c_void_p(nrm.ctypes.data),
+                                        float(target_rel_err), float(margin)), C.c_void_p(ctx))
+
+
+def ctfmm_mlp_forward(ctx, x, params, y, precision: int = 0) -> None:
+    n = int(x.shape[0])
+    _check(load().ctfmm_mlp_forward(C.c_void_p(ctx), n, _f32dev(x, (n, MLP_NIN)), _f32dev(params, (MLP_NPARAM,)),
+                                    precision, _f32dev(y, (n, MLP_NOUT))), C.c_void_p(ctx))
+
+
+def ctfmm_mlp_backward(ctx, x, t, params, grad, loss) -> None:
+    n = int(x.shape[0])
+    _check(load().ctfmm_mlp_backward(C.c_void_p(ctx), n, _f32dev(x, (n, MLP_NIN)), _f32dev(t, (n, MLP_NOUT)),
+                                     _f32dev(params, (MLP_NPARAM,)), _f32dev(grad, (MLP_NPARAM,)),
+                                     _f32dev(loss, (1,))), C.c_void_p(ctx))
+
+
+def ctfmm_mlp_train(ctx, x, t, params, steps: int, batch: int, lr: float):
+    """Trains params (cuda float32, in place); returns the per-step losses."""
+    import numpy as np
+    n = int(x.shape[0])
+    losses = np.zeros(steps, dtype=np.float32)
+    _check(load().ctfmm_mlp_train(C.c_void_p(ctx), n, _f32dev(x, (n, MLP_NIN)), _f32dev(t, (n, MLP_NOUT)),
+                                  _f32dev(params, (MLP_NPARAM,)), steps, batch, float(lr),
+                                  C.c_void_p(losses.ctypes.data)), C.c_void_p(ctx))
+    return losses
+
+
+def ctfmm_mlp_labels(ctx, M, v, x, y) -> None:
+    """M: cuda float64 [n,121]; v: host int array [n,3]; x, y: cuda float32."""
+    import numpy as np
+    n = int(M.shape[0])
+    vv = np.ascontiguousarray(v, dtype=np.int32).reshape(n, 3)
+    if not M.is_cuda or str(M.dtype) != "torch.float64" or not M.is_contiguous() or tuple(M.shape) != (n, 121):
+        raise ValueError("M must be contiguous cuda float64 [n,121]")
+    _check(load().ctfmm_mlp_labels(C.c_void_p(ctx), n, _ptr(M), C.c_void_p(vv.ctypes.data),
+                                   _f32dev(x, (n, MLP_NIN)), _f32dev(y, (n, MLP_NOUT))), C.c_void_p(ctx))
+
+
+def ctfmm_mlp_samples(ctx, xyz, q, nsamp: int, seed: int, x, y) -> None:
+    n = int(q.shape[0])
+    _check(load().ctfmm_mlp_samples(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), nsamp, seed,
+                                    _f32dev(x, (nsamp, MLP_NIN)), _f32dev(y, (nsamp, MLP_NOUT))), C.c_void_p(ctx))
+
+
 def ctfmm_set_timing(ctx, on: bool) -> None:
     _check(load().ctfmm_set_timing(C.c_void_p(ctx), 1 if on else 0), C.c_void_p(ctx))
 
@@ -185,7 +281,9 @@ def ctfmm_set_timing(ctx, on: bool) -> None:
 def ctfmm_stats(ctx) -> dict:
     st = ctfmm_stats_t()
     _check(load().ctfmm_stats(C.c_void_p(ctx), C.byref(st)), C.c_void_p(ctx))
-    return {name: getattr(st, name) for name, _ in ctfmm_stats_t._fields_}
+    out = {name: getattr(st, name) for name, _ in ctfmm_stats_t._fields_}
+    out["m2l_order_pairs"] = list(st.m2l_order_pairs)
+    return out
 
 
 def ctfmm_reset_stats(ctx) -> None:
@@ -254,6 +352,12 @@ class FMM:
 
     def stats(self) -> dict:
         return ctfmm_stats(self.ctx)
+
+    def set_order_table(self, order_r2) -> None:
+        ctfmm_set_order_table(self.ctx, order_r2)
+
+    def set_order_model(self, params, norm, target_rel_err: float, margin: float) -> None:
+        ctfmm_set_order_model(self.ctx, params, norm, target_rel_err, margin)
 
     def set_m2l_tile(self, p: int, targets: int) -> None:
         ctfmm_set_m2l_tile(self.ctx, p, targets)
