@@ -124,10 +124,10 @@ def m2l_traffic(name: str):
 
 def cpu_baseline(p: int, leaf_max: int):
     """The adaptive oracle on a smaller Plummer sphere of the same profile
-    (1/8 of the particles), same p and leaf size, all host cores."""
+    (half the particles), same p and leaf size, all host cores."""
     import oracle
     from paper_1811_06332_amd import workloads as W
-    n = 1 << 17
+    n = 1 << 19
     xyz, q = W.plummer(n, 1001)
     threads = len(os.sched_getaffinity(0))
     oracle.fmm_uniform(xyz[:64], q[:64], 1, 1, nthreads=threads)  # load and set threads
@@ -136,7 +136,7 @@ def cpu_baseline(p: int, leaf_max: int):
     oracle.fmm_adaptive(xyz, q, p, leaf_max, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "particles/s", "cores": used, "kind": "oracle",
-            "sample": f"full adaptive oracle FMM of a Plummer sphere of N={n} (1/8 of the workload's particles, same "
+            "sample": f"full adaptive oracle FMM of a Plummer sphere of N={n} (half the workload's particles, same "
                       f"profile, p={p}, leaf <= {leaf_max}, ws=1), one run of {dt:.1f} s"}
 
 
