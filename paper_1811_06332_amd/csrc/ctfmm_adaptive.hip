@@ -539,7 +539,9 @@ void launch_p2m_nodes(hipStream_t s, int p, int first, int count, const ABox* bo
     hipLaunchKernelGGL(k_p2m_nodes, dim3(count), dim3(64), 0, s, p, first, boxes, t, P, T, M);
 }
 
-constexpr int ANP = 8;  // parents per workgroup in M2M/L2L
+constexpr int ANP = 4;  // parents per workgroup in M2M/L2L
+
+__host__ __device__ constexpr int m2m_block(int p) { return (8 * (p + 1) * (p + 1) + 63) & ~63; }
 
 __device__ inline int rank_of_a(int k) {
     int r = 0;
@@ -548,86 +550,135 @@ __device__ inline int rank_of_a(int k) {
 }
 
 // M~(parent) = sum over existing children of A_o M~(child), for the non-leaf
-// nodes among [first, first+count) (the leaves keep their P2M result)
-__global__ __launch_bounds__(128) void k_m2m_nodes(int p, int first, int count, ATree t, double* __restrict__ M,
-                                                   const double* __restrict__ m2m_t) {
-    const int P0 = blockIdx.x * ANP;
-    const int nc = (p + 1) * (p + 1);
-    const int ldm = ldm_of(p);
-    __shared__ double ch[ANP][8][NIND];
-    __shared__ int isleaf[ANP];
-    const int np = min(ANP, count - P0);
-    if ((int)threadIdx.x < ANP) isleaf[threadIdx.x] = (int)threadIdx.x < np ? node_leaf(t.info[first + P0 + threadIdx.x]) : 1;
-    for (int x = threadIdx.x; x < np * 8 * nc; x += 128) {
-        const int pp = x / (8 * nc), r = x % (8 * nc), o = r / nc, j = r % nc;
-        const int c = t.child[8 * (size_t)(first + P0 + pp) + o];
+// nodes among [first, first+count) (the leaves keep their P2M result).  One
+// thread per (octant o, component n) and ANP parents per workgroup: the
+// children rows sit in LDS, each operator coefficient A_o[n][j] (rank(j) <=
+// rank(n)) is read once per workgroup and used for every parent, and the 8
+// octant sums meet in LDS, added in octant order.
+template <int P>
+__global__ __launch_bounds__(1024) void k_m2m_nodes(int first, int count, ATree t, double* __restrict__ M,
+                                                    const double* __restrict__ m2m_t) {
+    constexpr int NC = (P + 1) * (P + 1);
+    const int P0 = first + blockIdx.x * ANP;
+    const int np = min(ANP, first + count - P0);
+    const int ldm = ldm_of(P);
+    __shared__ double ch[ANP][8][NC];
+    __shared__ double red[ANP][8][NC];
+    __shared__ int live;
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int pp = 0; pp < np; ++pp) any |= !node_leaf(t.info[P0 + pp]);
+        live = any;
+    }
+    __syncthreads();
+    if (!live) return;
+    for (int x = threadIdx.x; x < ANP * 8 * NC; x += blockDim.x) {
+        const int pp = x / (8 * NC), r = x % (8 * NC), o = r / NC, j = r % NC;
+        const int c = pp < np ? t.child[8 * (size_t)(P0 + pp) + o] : -1;
         ch[pp][o][j] = c >= 0 ? M[(size_t)c * ldm + j] : 0.0;
     }
     __syncthreads();
-    for (int n = threadIdx.x; n < ldm; n += 128) {
+    const int o = threadIdx.x / NC, n = threadIdx.x % NC;
+    if (o < 8) {
+        const int r = rank_of_a(n);
+        const int jmax = (r + 1) * (r + 1);
+        const double* A = m2m_t + (size_t)o * NIND * NIND + n;
         double acc[ANP];
 #pragma unroll
         for (int pp = 0; pp < ANP; ++pp) acc[pp] = 0.0;
-        if (n < nc) {
-            const int r = rank_of_a(n);
-            const int jmax = (r + 1) * (r + 1);
-            for (int o = 0; o < 8; ++o) {
-                const double* A = m2m_t + (size_t)o * NIND * NIND;
-                for (int j = 0; j < jmax; ++j) {
-                    const double a = A[(size_t)j * NIND + n];
+#pragma unroll 4
+        for (int j = 0; j < jmax; ++j) {
+            const double a = A[(size_t)j * NIND];
 #pragma unroll
-                    for (int pp = 0; pp < ANP; ++pp) acc[pp] += a * ch[pp][o][j];
-                }
-            }
+            for (int pp = 0; pp < ANP; ++pp) acc[pp] += a * ch[pp][o][j];
         }
-        for (int pp = 0; pp < np; ++pp)
-            if (!isleaf[pp]) M[(size_t)(first + P0 + pp) * ldm + n] = acc[pp];
+#pragma unroll
+        for (int pp = 0; pp < ANP; ++pp) red[pp][o][n] = acc[pp];
+    }
+    __syncthreads();
+    // whole rows: the padding after the (P+1)^2 components is kept zero (M2L
+    // stages complete rows)
+    for (int x = threadIdx.x; x < np * ldm; x += blockDim.x) {
+        const int pp = x / ldm, k = x % ldm;
+        if (node_leaf(t.info[P0 + pp])) continue;
+        double v = 0.0;
+        if (k < NC)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v += red[pp][q][k];
+        M[(size_t)(P0 + pp) * ldm + k] = v;
     }
 }
 
 void launch_m2m_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* M, const DevTables& T) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_m2m_nodes, dim3(cdiv(count, ANP)), dim3(128), 0, s, p, first, count, t, M, T.m2m_t);
+    switch (p) {
+#define CASE(PP)                                                                                                  \
+    case PP:                                                                                                      \
+        hipLaunchKernelGGL(k_m2m_nodes<PP>, dim3(cdiv(count, ANP)), dim3(m2m_block(PP)), 0, s, first, count, t, M,  \
+                           T.m2m_t);                                                                              \
+        break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#undef CASE
+        default: break;
+    }
 }
 
 // L~(child) += B_o L~(parent) for the existing children of the non-leaf nodes
-// among [first, first+count)
-__global__ __launch_bounds__(256) void k_l2l_nodes(int p, int first, int count, ATree t, double* __restrict__ L,
-                                                   const double* __restrict__ l2l_t) {
-    const int P0 = blockIdx.x * ANP;
-    const int nc = (p + 1) * (p + 1);
-    const int ldm = ldm_of(p);
-    __shared__ double lp[ANP][NIND];
+// among [first, first+count).  One thread per (octant o, component n) and ANP
+// parents per workgroup; each coefficient B_o[n][j] (rank(j) >= rank(n)) is
+// read once per workgroup.
+template <int P>
+__global__ __launch_bounds__(1024) void k_l2l_nodes(int first, int count, ATree t, double* __restrict__ L,
+                                                    const double* __restrict__ l2l_t) {
+    constexpr int NC = (P + 1) * (P + 1);
+    const int P0 = first + blockIdx.x * ANP;
+    const int np = min(ANP, first + count - P0);
+    const int ldm = ldm_of(P);
+    __shared__ double lp[ANP][NC];
     __shared__ int cid[ANP][8];
-    const int np = min(ANP, count - P0);
     if ((int)threadIdx.x < ANP * 8) {
         const int pp = threadIdx.x / 8, o = threadIdx.x % 8;
-        cid[pp][o] = pp < np ? t.child[8 * (size_t)(first + P0 + pp) + o] : -1;
+        cid[pp][o] = pp < np ? t.child[8 * (size_t)(P0 + pp) + o] : -1;
     }
-    for (int x = threadIdx.x; x < np * nc; x += 256) lp[x / nc][x % nc] = L[(size_t)(first + P0 + x / nc) * ldm + x % nc];
+    for (int x = threadIdx.x; x < ANP * NC; x += blockDim.x)
+        lp[x / NC][x % NC] = x / NC < np ? L[(size_t)(P0 + x / NC) * ldm + x % NC] : 0.0;
     __syncthreads();
-    for (int x = threadIdx.x; x < 8 * nc; x += 256) {
-        const int o = x / nc, n = x % nc;
-        const double* Bm = l2l_t + (size_t)o * NIND * NIND;
-        double acc[ANP];
+    const int o = threadIdx.x / NC, n = threadIdx.x % NC;
+    if (o >= 8) return;
+    bool any = false;
 #pragma unroll
-        for (int pp = 0; pp < ANP; ++pp) acc[pp] = 0.0;
-        const int r = rank_of_a(n);
-        for (int j = r * r; j < nc; ++j) {
-            const double bcoef = Bm[(size_t)j * NIND + n];
+    for (int pp = 0; pp < ANP; ++pp) any |= cid[pp][o] >= 0;
+    if (!any) return;
+    const int r = rank_of_a(n);
+    const double* Bm = l2l_t + (size_t)o * NIND * NIND + n;
+    double acc[ANP];
 #pragma unroll
-            for (int pp = 0; pp < ANP; ++pp) acc[pp] += bcoef * lp[pp][j];
-        }
-        for (int pp = 0; pp < np; ++pp) {
-            const int c = cid[pp][o];
-            if (c >= 0) L[(size_t)c * ldm + n] += acc[pp];
-        }
+    for (int pp = 0; pp < ANP; ++pp) acc[pp] = 0.0;
+#pragma unroll 4
+    for (int j = r * r; j < NC; ++j) {
+        const double bcoef = Bm[(size_t)j * NIND];
+#pragma unroll
+        for (int pp = 0; pp < ANP; ++pp) acc[pp] += bcoef * lp[pp][j];
+    }
+#pragma unroll
+    for (int pp = 0; pp < ANP; ++pp) {
+        const int c = cid[pp][o];
+        if (c >= 0) L[(size_t)c * ldm + n] += acc[pp];
     }
 }
 
 void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* L, const DevTables& T) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_l2l_nodes, dim3(cdiv(count, ANP)), dim3(256), 0, s, p, first, count, t, L, T.l2l_t);
+    switch (p) {
+#define CASE(PP)                                                                                                  \
+    case PP:                                                                                                      \
+        hipLaunchKernelGGL(k_l2l_nodes<PP>, dim3(cdiv(count, ANP)), dim3(m2m_block(PP)), 0, s, first, count, t, L,  \
+                           T.l2l_t);                                                                              \
+        break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#undef CASE
+        default: break;
+    }
 }
 
 // ------------------------------------------------------------------ X list: direct local expansions
@@ -712,28 +763,75 @@ __global__ __launch_bounds__(64) void k_p2l(const ABox* __restrict__ boxes, ATre
 
 // ------------------------------------------------------------------ W list and near field
 
-// (-1)^n (2n-1)!! times the rank-n components: with these weights the
-// multipole potential is a polynomial at the inverted point (k_near_adaptive)
-__global__ void k_mhat(int p, int first, int count, const double* __restrict__ M, double* __restrict__ Mh) {
-    const int nc = (p + 1) * (p + 1);
-    const int ldm = ldm_of(p);
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (long long)count * ldm) return;
-    const int k = (int)(gid % ldm);
-    const size_t row = (size_t)first + gid / ldm;
-    double w = 0.0;
-    if (k < nc) {
-        const int r = rank_of_a(k);
-        w = 1.0;
-        for (int i = 1; i <= r; ++i) w *= -(double)(2 * i - 1);
-    }
-    Mh[row * ldm + k] = w * M[row * ldm + k];
+// Coefficients of the multipole-at-a-particle polynomial (W list).  Against
+// a traceless M only the r^n part of D_n survives:
+//   sum_{|m|=n} M_m D_m(r)/m! = (-1)^n (2n-1)!! |r|^(-2n-1) sum_{|m|=n} M_m r^m/m!
+// so the potential of cell C at scaled offset u is |u|^-1 Q(w), w = u/|u|^2,
+// with the polynomial Q(w) = sum_{|m|<=p} c_m w^m and
+//   c_m = (-1)^|m| (2|m|-1)!! M~_m / m!
+// over every full component m (the dependent ones expanded from the
+// independent ones by the trace relation).  Row layout (rows of ldc_of(p)
+// doubles), the order in which m2p_horner consumes the coefficients: first
+// the ranks < p with a, b and c descending, then the rank-p ones with a and
+// b descending (hpos).
+__host__ __device__ constexpr int nfull_of(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int ldc_of(int p) { return (nfull_of(p) + 7) & ~7; }
+// position of (a, b, c) in a row (a + b + c <= p)
+__host__ __device__ constexpr int hidx(int p, int a, int b, int c) {
+    int r = c;
+    for (int i = 0; i < a; ++i) r += (p - i + 1) * (p - i + 2) / 2;  // rows a' < a
+    for (int j = 0; j < b; ++j) r += p - a - j + 1;                  // rows b' < b within a
+    return r;
+}
+// position of c_(a,b,c) in a coefficient row of order p
+__host__ __device__ constexpr int hpos(int p, int a, int b, int c) {
+    return a + b + c < p ? nfull_of(p - 1) - 1 - hidx(p - 1, a, b, c)
+                         : nfull_of(p - 1) + (p - a) * (p - a + 1) / 2 + (p - a - b);
 }
 
-void launch_mhat(hipStream_t s, int p, int first, int count, const double* M, double* Mh) {
-    if (count <= 0) return;
-    hipLaunchKernelGGL(k_mhat, dim3(cdiv((long long)count * ldm_of(p), 256)), dim3(256), 0, s, p, first, count, M, Mh);
+__global__ void k_m2p_coef(int p, int first, int count, const double* __restrict__ M, DevTables T,
+                           double* __restrict__ Cm) {
+    const int ldc = ldc_of(p);
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)count * ldc) return;
+    const int k = (int)(gid % ldc);
+    const size_t row = (size_t)first + gid / ldc;
+    double v = 0.0;
+    if (k < nfull_of(p)) {
+        int a = 0, b = 0, c = 0;  // invert hpos
+        const int n1 = nfull_of(p - 1);
+        if (k < n1) {
+            const int d = p - 1;
+            int r = n1 - 1 - k;
+            while (r >= (d - a + 1) * (d - a + 2) / 2) r -= (d - a + 1) * (d - a + 2) / 2, ++a;
+            while (r >= d - a - b + 1) r -= d - a - b + 1, ++b;
+            c = r;
+        } else {
+            const int t = k - n1;
+            int j = 0;
+            while ((j + 1) * (j + 2) / 2 <= t) ++j;
+            a = p - j;
+            b = p - a - (t - j * (j + 1) / 2);
+            c = p - a - b;
+        }
+        const int n = a + b + c;
+        const int f = n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);  // full slot
+        const double* Mr = M + row * ldm_of(p);
+        for (int t = T.exp_start[f]; t < T.exp_start[f + 1]; ++t) v += (double)T.exp_coef[t] * Mr[T.exp_slot[t]];
+        double w = T.inv_mfact[f];
+        for (int i = 1; i <= n; ++i) w *= -(double)(2 * i - 1);
+        v *= w;
+    }
+    Cm[row * ldc + k] = v;
 }
+
+void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M, const DevTables& T, double* Cm) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_m2p_coef, dim3(cdiv((long long)count * ldc_of(p), 256)), dim3(256), 0, s, p, first, count, M,
+                       T, Cm);
+}
+
+size_t m2p_coef_ld(int p) { return (size_t)ldc_of(p); }
 
 __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, double& f, double& gx, double& gy,
                                   double& gz) {
@@ -773,87 +871,237 @@ __global__ __launch_bounds__(256) void k_l2p_adaptive(int n, const ABox* __restr
     F[s] = out;
 }
 
+// A wave-uniform zero that depends on dep0, dep1 and dep2: loads at
+// c + after(...) cannot be issued before those are computed, and keep c's
+// address space and aliasing facts (scalar loads).  Without it every load of the
+// unrolled polynomial is hoisted to the top and the rows' values stay live.
+__device__ __forceinline__ int after(double dep0, double dep1, double dep2) {
+    int z = 0;
+    __asm__ volatile("" : "+s"(z) : "v"(dep0), "v"(dep1), "v"(dep2));
+    return z;
+}
+
+// The rows of a coefficient row, in memory order: first the Horner rows of
+// fl, (a, b) for a = P-1..0, b = P-1-a..0, holding c = P-1-a-b..0; then the
+// rows of ft, a = P..0, holding b = P-a..0 (c = P-a-b).
+struct HRow {
+    int kind, a, b, start, len;  // kind 0: fl row, 1: ft row
+};
+__host__ __device__ constexpr int hrows(int P) { return P * (P + 1) / 2 + P + 1; }
+__host__ __device__ constexpr HRow hrow(int P, int r) {
+    int start = 0;
+    for (int a = P - 1; a >= 0; --a)
+        for (int b = P - 1 - a; b >= 0; --b) {
+            const int len = P - a - b;
+            if (r == 0) return HRow{0, a, b, start, len};
+            --r;
+            start += len;
+        }
+    for (int a = P; a >= 0; --a) {
+        const int len = P - a + 1;
+        if (r == 0) return HRow{1, a, 0, start, len};
+        --r;
+        start += len;
+    }
+    return HRow{2, 0, 0, start, 0};
+}
+
+struct HState {
+    double V, Vx, Vy, Vz, T, U, Uy, Uz;
+};
+
+// Rows are fetched in groups of consecutive rows holding at most HG
+// coefficients (a group is a contiguous range of the coefficient row).
+constexpr int HG = 16;
+struct HGroup {
+    int r0, r1, start, len;  // rows [r0, r1)
+};
+__host__ __device__ constexpr int hgroups(int P) {
+    int g = 0, len = 0;
+    for (int r = 0; r < hrows(P); ++r) {
+        const int l = hrow(P, r).len;
+        if (r == 0 || len + l > HG) {
+            ++g;
+            len = 0;
+        }
+        len += l;
+    }
+    return g;
+}
+__host__ __device__ constexpr HGroup hgroup(int P, int g) {
+    int k = -1, len = 0, r0 = 0;
+    for (int r = 0; r < hrows(P); ++r) {
+        const int l = hrow(P, r).len;
+        if (r == 0 || len + l > HG) {
+            if (k == g) return HGroup{r0, r, hrow(P, r0).start, len};
+            ++k;
+            len = 0;
+            r0 = r;
+        }
+        len += l;
+    }
+    return HGroup{r0, hrows(P), hrow(P, r0).start, len};
+}
+
+// Evaluates row r (held in w, a group buffer starting at coefficient w0),
+// then the rows after it up to r1.
+template <int P, int r, int r1>
+__device__ __forceinline__ void hrows_run(double x, double y, double z, const double (&zp)[P + 1], int w0,
+                                          const double (&w)[HG], HState& s) {
+    constexpr int D = P - 1;
+    constexpr HRow R = hrow(P, r);
+    const int o = R.start - w0;
+    if constexpr (R.kind == 0) {
+        constexpr int a = R.a, b = R.b;
+        double v = w[o], d = 0.0;
+#pragma unroll
+        for (int j = 1; j < R.len; ++j) {
+            d = (j == 1) ? v : d * z + v;
+            v = v * z + w[o + j];
+        }
+        if constexpr (b == D - a) {  // first row of the group: no derivatives yet
+            s.U = v;
+            s.Uy = 0.0;
+            s.Uz = 0.0;
+        } else if constexpr (b == D - a - 1) {
+            s.Uy = s.U;
+            s.U = s.U * y + v;
+            s.Uz = d;
+        } else {
+            s.Uy = s.Uy * y + s.U;
+            s.U = s.U * y + v;
+            s.Uz = s.Uz * y + d;
+        }
+        if constexpr (b == 0) {  // last row of the group: fold into the x level
+            if constexpr (a == D) {
+                s.V = s.U;
+            } else if constexpr (a == D - 1) {
+                s.Vx = s.V;
+                s.V = s.V * x + s.U;
+                s.Vy = s.Uy;
+                s.Vz = s.Uz;
+            } else {
+                s.Vx = s.Vx * x + s.V;
+                s.V = s.V * x + s.U;
+                s.Vy = s.Vy * x + s.Uy;
+                s.Vz = s.Vz * x + s.Uz;
+            }
+        }
+    } else {
+        double S = w[o];
+#pragma unroll
+        for (int j = 1; j < R.len; ++j) S = S * y + w[o + j] * zp[j];
+        s.T = (R.a == P) ? S : s.T * x + S;
+    }
+    if constexpr (r + 1 < r1) hrows_run<P, r + 1, r1>(x, y, z, zp, w0, w, s);
+}
+
+// Group g (held in cur): the loads of group g+1 are issued first (they wait
+// only for the result of group g-1), then the rows of group g are evaluated;
+// group g+1 follows with the buffers swapped.
+template <int P, int g>
+__device__ __forceinline__ void hgroups_run(double x, double y, double z, const double (&zp)[P + 1],
+                                            const double* __restrict__ c, HState& s, double (&cur)[HG],
+                                            double (&nxt)[HG]) {
+    constexpr HGroup G = hgroup(P, g);
+    if constexpr (g + 1 < hgroups(P)) {
+        constexpr HGroup Gn = hgroup(P, g + 1);
+        const double* cn = c + after(s.U, s.T, s.V);
+#pragma unroll
+        for (int k = 0; k < Gn.len; ++k) nxt[k] = cn[Gn.start + k];
+    }
+    hrows_run<P, G.r0, G.r1>(x, y, z, zp, G.start, cur, s);
+    if constexpr (g + 1 < hgroups(P)) hgroups_run<P, g + 1>(x, y, z, zp, c, s, nxt, cur);
+}
+
+// Q(w) of one cell from its coefficient row c: fl = sum_{|m|<=P-1} c_m w^m
+// and its gradient by nested Horner (z innermost, derivatives carried along;
+// the first step of every chain peeled, so no products with zero), and
+// ft = the rank-P part.  The gradient takes ranks 0..P-1 only: the rank-1
+// local components of M2L are truncated at |m| <= P-1.  Coefficients arrive
+// by scalar loads, one group ahead of their use.
+template <int P>
+__device__ __forceinline__ void m2p_horner(double x, double y, double z, const double* __restrict__ c, double& fl,
+                                           double& ft, double& gx, double& gy, double& gz) {
+    double zp[P + 1];
+    zp[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= P; ++k) zp[k] = zp[k - 1] * z;
+    HState s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double b0[HG], b1[HG];
+    constexpr HGroup G0 = hgroup(P, 0);
+#pragma unroll
+    for (int k = 0; k < G0.len; ++k) b0[k] = c[G0.start + k];
+    hgroups_run<P, 0>(x, y, z, zp, c, s, b0, b1);
+    fl = s.V;
+    ft = s.T;
+    gx = s.Vx;
+    gy = s.Vy;
+    gz = s.Vz;
+}
+
 // W(B): the multipole of each cell C in W(B) evaluated at B's particles (Eq.
-// M2L at the particle, ranks 0 and 1 of the result).  Against a traceless M
-// only the r^n part of D_n survives:
-//   sum_{|m|=n} M_m D_m(r)/m! = (-1)^n (2n-1)!! |r|^(-2n-1) sum_{|m|=n} M_m r^m/m!
-// which is |r|^-1 times the rank-n polynomial of the weighted M^ at the
-// inverted point w = r/|r|^2.  The potential takes ranks 0..p; the gradient
-// takes ranks 0..p-1 (the rank-1 local components are truncated at
-// |m| <= p-1), by the chain rule through w.
+// M2L taken to the particle position, ranks 0 and 1 of the result), as
+// |u|^-1 Q(w) (see k_m2p_coef) with the gradient by the chain rule through w.
+// One workgroup of MW wavefronts per leaf B, lanes over its particles (64 at
+// a time); wavefront k takes the entries k, k + MW, ... of W(B), which are
+// wave-uniform, so each coefficient row arrives through scalar loads.  The
+// MW partial sums meet in LDS and are added to F[s] (the L2P result) in
+// wavefront order.
+constexpr int MW = 4;
 template <int P>
-__device__ inline double4 m2p_eval(const ABox* __restrict__ boxes, const ATree& t, int C, double4 pt, const double* __restrict__ Mh) {
-    const NodeGeom G = node_geom(boxes, t, C);
-    const double ux = (pt.x - G.zx) / G.h, uy = (pt.y - G.zy) / G.h, uz = (pt.z - G.zz) / G.h;
-    const double r2 = ux * ux + uy * uy + uz * uz;
-    const double ir2 = 1.0 / r2;
-    const double ir = sqrt(ir2);
-    double fl = 0.0, ft = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    gen_m2p<P>(ux * ir2, uy * ir2, uz * ir2, Mh + (size_t)C * ldm_of(P), fl, ft, g0, g1, g2);
-    const double ih = 1.0 / G.h;
-    // grad_u [ |u|^-1 Q(w) ] = -u |u|^-3 Q + |u|^-1 (g/|u|^2 - 2 u (u.g)/|u|^4), Q = ranks < p
-    const double ug = ux * g0 + uy * g1 + uz * g2;
-    const double a = -ir * ir2 * fl - 2.0 * ir * ir2 * ir2 * ug;
-    const double b = ir * ir2;
-    const double ih2 = ih * ih;
-    return make_double4(ir * (fl + ft) * ih, (a * ux + b * g0) * ih2, (a * uy + b * g1) * ih2,
-                        (a * uz + b * g2) * ih2);
-}
-
-// number of (target particle, W entry) pairs of every node
-__global__ void k_wpairs_count(int nn, ATree t, const int32_t* __restrict__ woff, long long* __restrict__ cnt) {
-    const int B = blockIdx.x * blockDim.x + threadIdx.x;
-    if (B >= nn) return;
-    cnt[B] = (long long)(woff[B + 1] - woff[B]) * (t.pe[B] - t.pb[B]);
-}
-
-void launch_wpairs_count(hipStream_t s, int nn, const ATree& t, const int32_t* woff, long long* cnt) {
-    hipLaunchKernelGGL(k_wpairs_count, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, t, woff, cnt);
-}
-
-// One thread per pair g, ordered [leaf B][W entry i][target]: the pair's
-// contribution into buf[g] (consecutive threads share the source cell)
-template <int P>
-__global__ __launch_bounds__(256) void k_m2p_pairs(long long npairs, int nn, const ABox* __restrict__ boxes, ATree t,
-                                                   const double4* __restrict__ Pt, const double* __restrict__ Mh,
-                                                   const int32_t* __restrict__ woff,
-                                                   const int32_t* __restrict__ wlist,
-                                                   const long long* __restrict__ poff, double4* __restrict__ buf) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= npairs) return;
-    int lo = 0, hi = nn;  // last B with poff[B] <= g
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (poff[mid] <= g) lo = mid; else hi = mid;
+__global__ __launch_bounds__(64 * MW) void k_m2p_leaf(const ABox* __restrict__ boxes, ATree t,
+                                                      const double4* __restrict__ Pt, const double* __restrict__ Cm,
+                                                      const int32_t* __restrict__ woff,
+                                                      const int32_t* __restrict__ wlist, double4* __restrict__ F) {
+    __shared__ double4 part[MW][64];
+    const int B = blockIdx.x;
+    const int w0 = woff[B], w1 = woff[B + 1];
+    if (w0 == w1) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = t.pb[B], e = t.pe[B];
+    for (int s0 = b; s0 < e; s0 += 64) {
+        const int s = s0 + lane;
+        const bool act = s < e;
+        const double4 pt = Pt[act ? s : b];
+        double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma nounroll
+        for (int i = w0 + wv; i < w1; i += MW) {
+            const int C = __builtin_amdgcn_readfirstlane(wlist[i]);
+            const NodeGeom G = node_geom(boxes, t, C);
+            const double ux = (pt.x - G.zx) / G.h, uy = (pt.y - G.zy) / G.h, uz = (pt.z - G.zz) / G.h;
+            const double r2 = ux * ux + uy * uy + uz * uz;
+            const double ir2 = 1.0 / r2;
+            const double ir = sqrt(ir2);
+            double fl, ft, g0, g1, g2;
+            m2p_horner<P>(ux * ir2, uy * ir2, uz * ir2, Cm + (size_t)C * ldc_of(P), fl, ft, g0, g1, g2);
+            const double ih = 1.0 / G.h;
+            // grad_u [ |u|^-1 Q(w) ] = -u |u|^-3 Q + |u|^-1 (g/|u|^2 - 2 u (u.g)/|u|^4), Q = ranks < P
+            const double ug = ux * g0 + uy * g1 + uz * g2;
+            const double aa = -ir * ir2 * fl - 2.0 * ir * ir2 * ir2 * ug;
+            const double bb = ir * ir2;
+            const double ih2 = ih * ih;
+            v.x += ir * (fl + ft) * ih;
+            v.y += (aa * ux + bb * g0) * ih2;
+            v.z += (aa * uy + bb * g1) * ih2;
+            v.w += (aa * uz + bb * g2) * ih2;
+        }
+        part[wv][lane] = v;
+        __syncthreads();
+        if (wv == 0 && act) {
+            double4 f = F[s];
+#pragma unroll
+            for (int k = 0; k < MW; ++k) {
+                const double4 c = part[k][lane];
+                f.x += c.x;
+                f.y += c.y;
+                f.z += c.z;
+                f.w += c.w;
+            }
+            F[s] = f;
+        }
+        __syncthreads();
     }
-    const int B = lo;
-    const int nt = t.pe[B] - t.pb[B];
-    const long long r = g - poff[B];
-    const int i = (int)(r / nt), tt = (int)(r % nt);
-    buf[g] = m2p_eval<P>(boxes, t, wlist[woff[B] + i], Pt[t.pb[B] + tt], Mh);
-}
-
-// F[s] += the W contributions of particle s, summed in list order
-__global__ __launch_bounds__(256) void k_m2p_reduce(int n, ATree t, const int32_t* __restrict__ leaf_of,
-                                                    const int32_t* __restrict__ woff,
-                                                    const long long* __restrict__ poff,
-                                                    const double4* __restrict__ buf, double4* __restrict__ F) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int B = leaf_of[s];
-    const int nw = woff[B + 1] - woff[B];
-    if (nw == 0) return;
-    const int nt = t.pe[B] - t.pb[B];
-    const int tt = s - t.pb[B];
-    double4 v = F[s];
-    for (int i = 0; i < nw; ++i) {
-        const double4 c = buf[poff[B] + (long long)i * nt + tt];
-        v.x += c.x;
-        v.y += c.y;
-        v.z += c.z;
-        v.w += c.w;
-    }
-    F[s] = v;
 }
 
 // Near field: one thread per sorted particle s in leaf B; direct sum over the
@@ -924,23 +1172,17 @@ void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t,
     }
 }
 
-void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, const ABox* boxes, const ATree& t,
-                          const int32_t* leaf_of, const double4* P, const double* L, const double* Mh,
-                          const int32_t* woff, const int32_t* wlist, const long long* wpoff, double4* wbuf,
-                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, bool to_F,
-                          double* phi, double* grad) {
+void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
+                          const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
+                          const int32_t* woff, const int32_t* wlist, const int32_t* uoff, const int32_t* ulist,
+                          const int32_t* idx, double4* F, bool to_F, double* phi, double* grad) {
     if (n <= 0) return;
     const dim3 grid(cdiv(n, 256)), blk(256);
-    const dim3 wgrid((unsigned)((wpairs + 255) / 256));
     switch (p) {
 #define CASE(PP)                                                                                                  \
     case PP:                                                                                                      \
         hipLaunchKernelGGL(k_l2p_adaptive<PP>, grid, blk, 0, s, n, boxes, t, leaf_of, P, L, F);                     \
-        if (wpairs > 0) {                                                                                         \
-            hipLaunchKernelGGL(k_m2p_pairs<PP>, wgrid, blk, 0, s, wpairs, nn, boxes, t, P, Mh, woff, wlist, wpoff,  \
-                               wbuf);                                                                             \
-            hipLaunchKernelGGL(k_m2p_reduce, grid, blk, 0, s, n, t, leaf_of, woff, wpoff, wbuf, F);               \
-        }                                                                                                         \
+        if (wlists) hipLaunchKernelGGL(k_m2p_leaf<PP>, dim3(nn), dim3(64 * MW), 0, s, boxes, t, P, Cm, woff, wlist, F);  \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE

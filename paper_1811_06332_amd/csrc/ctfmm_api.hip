@@ -85,14 +85,9 @@ struct Forest {
     size_t vsum_cap = 0;
     double* aM = nullptr;
     double* aL = nullptr;
-    double* aMh = nullptr;
+    double* aWc = nullptr;  // W-list polynomial coefficients [node][m2p_coef_ld(p)]
     float* aM32 = nullptr;
-    size_t aM_cap = 0, aL_cap = 0, aMh_cap = 0, aM32_cap = 0;
-    long long* wcnt = nullptr;  // [nn+1] (target, W entry) pairs per node
-    long long* wpoff = nullptr; // [nn+1] their exclusive scan
-    double4* wbuf = nullptr;    // one contribution per pair
-    size_t wcnt_cap = 0, wpoff_cap = 0, wbuf_cap = 0;
-    long long wpairs = 0;
+    size_t aM_cap = 0, aL_cap = 0, aWc_cap = 0, aM32_cap = 0;
     std::vector<int> lev_first, lev_count;
     std::vector<int4> tiles_host;
     int64_t tot_u = 0, tot_w = 0, tot_x = 0, v_pairs = -1;
@@ -760,28 +755,11 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     ACHK(grow(c, f.wlist, f.wlist_cap, (size_t)tot[1], false));
     ACHK(grow(c, f.xlist, f.xlist_cap, (size_t)tot[2], false));
     launch_lists(st, true, nn, f.tr, uc, wc, xc, uo, wo, xo, f.ulist, f.wlist, f.xlist);
-    // (target particle, W entry) pairs of the multipole evaluations
-    f.wpairs = 0;
-    if (f.tot_w > 0) {
-        ACHK(grow(c, f.wcnt, f.wcnt_cap, n1, false));
-        ACHK(grow(c, f.wpoff, f.wpoff_cap, n1, false));
-        HIPCHK(c, hipMemsetAsync(f.wcnt + nn, 0, sizeof(long long), st));
-        launch_wpairs_count(st, nn, f.tr, wo, f.wcnt);
-        SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceScan::ExclusiveSum(t, b, f.wcnt, f.wpoff, (int)n1, st);
-        }));
-        long long wp = 0;
-        HIPCHK(c, hipMemcpyAsync(&wp, f.wpoff + nn, sizeof(long long), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        f.wpairs = wp;
-        ACHK(grow(c, f.wbuf, f.wbuf_cap, (size_t)wp, false));
-    }
-
     // expansion buffers
     const size_t ldm = (size_t)ldm_of(f.p);
     ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm, false));
     ACHK(grow(c, f.aL, f.aL_cap, (size_t)nn * ldm, false));
-    if (f.tot_w > 0) ACHK(grow(c, f.aMh, f.aMh_cap, (size_t)nn * ldm, false));
+    if (f.tot_w > 0) ACHK(grow(c, f.aWc, f.aWc_cap, (size_t)nn * m2p_coef_ld(f.p), false));
     if (c->prm.precision != CTFMM_PREC_FP64) ACHK(grow(c, f.aM32, f.aM32_cap, (size_t)nn * s32_of(f.p), false));
 
     // M2L tiles: nodes grouped by (level, octant), Morton order inside
@@ -863,7 +841,7 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     const void* msrc = f.aM;
     if (maxlev >= 2) {
         const int f2 = f.lev_first[2];
-        if (f.tot_w > 0) launch_mhat(st, p, f2, nn - f2, f.aM, f.aMh);
+        if (f.tot_w > 0) launch_m2p_coef(st, p, f2, nn - f2, f.aM, c->T, f.aWc);
         if (prec != CTFMM_PREC_FP64) {
             launch_to_f32(st, p, nn, f.aM, f.aM32);
             msrc = f.aM32;
@@ -934,8 +912,8 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     for (int l = 3; l <= maxlev; ++l) launch_l2l_nodes(st, p, f.lev_first[l - 1], f.lev_count[l - 1], f.tr, f.aL, c->T);
     mark(6);
     const size_t n1 = (size_t)nn + 1;
-    launch_near_adaptive(st, p, f.n, nn, f.wpairs, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aMh, f.loff + n1, f.wlist,
-                         f.wpoff, f.wbuf, f.loff, f.ulist, f.a_idxs, f.a_F, to_F, phi, grad);
+    launch_near_adaptive(st, p, f.n, nn, f.tot_w > 0, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1,
+                         f.wlist, f.loff, f.ulist, f.a_idxs, f.a_F, to_F, phi, grad);
     mark(7);
     HIPCHK(c, hipGetLastError());
     return CTFMM_OK;
@@ -1227,11 +1205,11 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
     for (int k = 0; k < c->nforests; ++k) {
         const Forest& f = c->forests[k];
         const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys,
-                              f.a_P, f.a_F, f.aM, f.aL, f.aMh, f.aM32, f.loff, f.xlist, f.wlist, f.ulist, f.wpoff,
-                              f.wbuf, f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.ordn,
+                              f.a_P, f.a_F, f.aM, f.aL, f.aWc, f.aM32, f.loff, f.xlist, f.wlist, f.ulist,
+                              f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.ordn,
                               f.ord_tab, f.omask, f.ivl, f.ivc, f.mx, f.my, c->order_tab, c->model, f.part};
         for (const void* q2 : ptrs) sig.push_back((long long)(uintptr_t)q2);
-        sig.insert(sig.end(), {f.p, f.n, f.nn, f.wpairs, (long long)f.tiles_host.size(), f.tot_w, f.tot_x, f.tt,
+        sig.insert(sig.end(), {f.p, f.n, f.nn, (long long)f.tiles_host.size(), f.tot_w, f.tot_x, f.tt,
                                f.nchunk});
         sig.insert(sig.end(), f.lev_first.begin(), f.lev_first.end());
         sig.insert(sig.end(), f.lev_count.begin(), f.lev_count.end());

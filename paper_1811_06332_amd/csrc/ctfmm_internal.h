@@ -261,13 +261,12 @@ void launch_m2m_nodes(hipStream_t s, int p, int first, int count, const ATree& t
 void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* L, const DevTables& T);
 void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const int32_t* xoff, const int32_t* xlist,
                 const double4* P, double* L);
-void launch_mhat(hipStream_t s, int p, int first, int count, const double* M, double* Mh);
-void launch_wpairs_count(hipStream_t s, int nn, const ATree& t, const int32_t* woff, long long* cnt);
-void launch_near_adaptive(hipStream_t s, int p, int n, int nn, long long wpairs, const ABox* boxes, const ATree& t,
-                          const int32_t* leaf_of, const double4* P, const double* L, const double* Mh,
-                          const int32_t* woff, const int32_t* wlist, const long long* wpoff, double4* wbuf,
-                          const int32_t* uoff, const int32_t* ulist, const int32_t* idx, double4* F, bool to_F,
-                          double* phi, double* grad);
+void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M, const DevTables& T, double* Cm);
+size_t m2p_coef_ld(int p);  // row stride of the W-list coefficient rows
+void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
+                          const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
+                          const int32_t* woff, const int32_t* wlist, const int32_t* uoff, const int32_t* ulist,
+                          const int32_t* idx, double4* F, bool to_F, double* phi, double* grad);
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
 
 // ---- expansion orders per pair (ctfmm_adaptive.hip, ctfmm_mlp.hip) ----

@@ -368,43 +368,6 @@ def l2p_code(p):
     return lines + out, nterms
 
 
-def m2p_code(p):
-    """Straight-line evaluation of a traceless expansion's polynomial for the
-    multipole-at-a-particle step: with w the (inverted, scaled) position and
-    the independent coefficients Lt[j] (rank-weighted multipole components),
-        f  = sum_{|n|<=p-1} w^n/n! L_n,   ft = sum_{|n|=p} w^n/n! L_n,
-        g_i = sum_{|n|<=p-2} w^n/n! L_{n+e_i}   (the gradient of f),
-    i.e. the L2P polynomial with its top rank kept apart and the gradient of
-    the order p-1 part only.  Same monomial order and coefficients as L2P."""
-    lines = []
-    for v in "xyz":
-        lines.append(f"double {v}0 = 1.0;")
-        for k in range(1, p + 1):
-            lines.append(f"const double {v}{k} = {v}{k - 1} * {v};")
-    nterms = 0
-    out = []
-    for c in range(p + 1):
-        for b in range(p + 1 - c):
-            out.append(f"{{ const double* Lg = gen_launder(L); const double yz = y{b} * z{c};")
-            for a in range(p + 1 - b - c):
-                n = (a, b, c)
-                inv = Fraction(1, mfact(n))
-                out.append(f"  {{ const double m = x{a} * yz;")
-                t = [(j, inv * cj) for j, cj in sorted(expand(n).items())]
-                acc = "ft" if a + b + c == p else "f"
-                out.append(f"    {acc} += m * (" + " + ".join(f"({float(cf)!r}) * LD({j})" for j, cf in t) + ");")
-                nterms += len(t)
-                if a + b + c < p - 1:
-                    for nm, e in (("gx", (1, 0, 0)), ("gy", (0, 1, 0)), ("gz", (0, 0, 1))):
-                        n2 = (a + e[0], b + e[1], c + e[2])
-                        t = [(j, inv * cj) for j, cj in sorted(expand(n2).items())]
-                        out.append(f"    {nm} += m * (" + " + ".join(f"({float(cf)!r}) * LD({j})" for j, cf in t) + ");")
-                        nterms += len(t)
-                out.append("  }")
-            out.append("__builtin_amdgcn_sched_barrier(0); }")
-    return lines + out, nterms
-
-
 # ------------------------------------------------------------------ emit
 
 def _hexf(v):
@@ -520,21 +483,7 @@ def emit(outdir):
         for ln in lines:
             w("  " + ln)
         w("}")
-    for p in range(PMAX + 1):
-        lines, nt = m2p_code(p)
-        w(f"// Multipole-at-a-particle polynomial at order {p}: f (ranks < p), ft (rank p) and the gradient of f, "
-          f"{nt} coefficient terms")
-        w(f"__device__ static inline void gen_m2p_p{p}(double x, double y, double z, const double* __restrict__ L,")
-        w("                                          double& f, double& ft, double& gx, double& gy, double& gz) {")
-        for ln in lines:
-            w("  " + ln)
-        w("}")
     w("#undef LD")
-    w("template <int P> __device__ inline void gen_m2p(double x, double y, double z, const double* L, double& f,")
-    w("                                            double& ft, double& gx, double& gy, double& gz);")
-    for p in range(PMAX + 1):
-        w(f"template <> __device__ inline void gen_m2p<{p}>(double x, double y, double z, const double* L, double& f, "
-          f"double& ft, double& gx, double& gy, double& gz) {{ gen_m2p_p{p}(x, y, z, L, f, ft, gx, gy, gz); }}")
     w("template <int P> __device__ inline void gen_l2p(double x, double y, double z, const double* L, double& f,")
     w("                                            double& gx, double& gy, double& gz);")
     for p in range(PMAX + 1):

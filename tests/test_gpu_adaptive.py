@@ -120,6 +120,29 @@ def test_adaptive_repeat_and_regrow():
     assert rel(outs[1][0], po) <= TOL and rel(outs[1][1], go) <= TOL
 
 
+def test_adaptive_workspace_not_assumed_zero():
+    """Workspace from the caching allocator holds whatever was freed before:
+    poison the cache with NaN, then every context must still match the
+    oracle (padding and partial sums are written, never assumed zero)."""
+    import torch
+    from paper_1811_06332_amd import ctfmm as F
+    cases = [(W.plummer(1500, 19), 6, "fp64"), (two_density(6000, 20), 6, "fp64"), (two_density(6000, 20), 8, "fp32")]
+    for (xyz, q), p, prec in cases:
+        junk = [torch.full((1 << k,), float("nan"), dtype=torch.float64, device="cuda") for k in range(10, 25)]
+        del junk
+        print(f"[case] adaptive poisoned workspace n={len(q)} p={p} {prec}", flush=True)
+        f = F.FMM(p, 0, prec, root_side=None, tree="adaptive", leaf_max=16)
+        try:
+            phi, grad = f.evaluate(torch.from_numpy(xyz).cuda(), torch.from_numpy(q).cuda(), sync=True)
+        finally:
+            f.close()
+        phi, grad = phi.cpu().numpy(), grad.cpu().numpy()
+        assert np.all(np.isfinite(phi)) and np.all(np.isfinite(grad))
+        po, go = oracle.fmm_adaptive(xyz, q, p, 16)
+        tol = TOL if prec == "fp64" else 1e-6
+        assert rel(phi, po) <= tol and rel(grad, go) <= tol, (p, prec, rel(phi, po), rel(grad, go))
+
+
 def test_adaptive_decays_to_direct_sum():
     """The approximation itself: error against the direct sum falls with p."""
     xyz, q = W.plummer(4000, 21)
