@@ -64,8 +64,10 @@ __device__ inline bool adjacent(uint64_t ka, int la, uint64_t kb, int lb) {
     return true;
 }
 
+// from the table filled by k_node_geo once per tree
 __device__ inline NodeGeom node_geom(const ABox* boxes, const ATree& t, int g) {
-    return node_geom(boxes[t.sys[g]], t.key[g], node_level(t.info[g]));
+    const double4 q = t.geo[g];
+    return NodeGeom{q.x, q.y, q.z, q.w};
 }
 
 // position of i among the sorted offsets off[0..m] (off[k] <= i < off[k+1])
@@ -360,6 +362,19 @@ __global__ void k_leaf_of(int nn, ATree t, int32_t* __restrict__ leaf_of) {
 
 void launch_leaf_of(hipStream_t s, int nn, const ATree& t, int32_t* leaf_of) {
     hipLaunchKernelGGL(k_leaf_of, dim3(cdiv(nn, 128)), dim3(128), 0, s, nn, t, leaf_of);
+}
+
+// (centre, side) of every node's cube, from its key, level and root cube
+__global__ void k_node_geo(int nn, const ABox* __restrict__ boxes, ATree t) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nn) return;
+    const NodeGeom G = node_geom(boxes[t.sys[g]], t.key[g], node_level(t.info[g]));
+    t.geo[g] = make_double4(G.zx, G.zy, G.zz, G.h);
+}
+
+void launch_node_geo(hipStream_t s, int nn, const ABox* boxes, const ATree& t) {
+    if (nn <= 0) return;
+    hipLaunchKernelGGL(k_node_geo, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, boxes, t);
 }
 
 // ------------------------------------------------------------------ U, W, X lists
@@ -683,81 +698,193 @@ void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t
 
 // ------------------------------------------------------------------ X list: direct local expansions
 
-// L~_n(B) += q D~_n((z_B - x_a)/h_B) for the particles a of every leaf in
-// X(B) (Eq. M2L with the multipole of a single charge at its own position,
-// in the scaled variables).  One wavefront per node; the particles of all its
-// X leaves are taken 64 at a time as one sequence (lane i takes the i-th
-// particle after a wave-uniform cursor), and the lanes' derivative tensors
-// meet in LDS, where lane k sums component k.
+// L~_n(B) += q D~_n(u), u = (z_B - x_a)/h_B, for the particles a of every
+// leaf in X(B) (Eq. M2L with the multipole of a single charge at its own
+// position, in the scaled variables).  With D_n(u) = (-1)^n (2n-1)!! D[u^n]
+// |u|^-(2n+1) (D the traceless projection) and w = u/|u|^2 this is
+//   L~_n(B) += (-1)^n (2n-1)!! D[S]_n,   S_f = sum_a (q_a/|u_a|) w_a^f,
+// i.e. the detracer rows of P2M applied to the full monomial moments S of
+// the inverted points.  One wavefront per node B: lanes over the particles
+// of X(B) (P2L_KP per lane per round), the moments in blocks of at most MB
+// monomials (compile-time blocks of whole (a, b) rows, hidx order) summed
+// over the lanes through LDS; then the detracer rows, once per node.
+constexpr int MB = 40;
+struct MRow {
+    int a, b, start, len;  // w^(a, b, c) for c = 0..len-1 at positions start..
+};
+__host__ __device__ constexpr int mrows(int P) { return (P + 1) * (P + 2) / 2; }
+__host__ __device__ constexpr MRow mrow(int P, int r) {
+    int start = 0;
+    for (int a = 0; a <= P; ++a)
+        for (int b = 0; b <= P - a; ++b) {
+            const int len = P - a - b + 1;
+            if (r == 0) return MRow{a, b, start, len};
+            --r;
+            start += len;
+        }
+    return MRow{0, 0, start, 0};
+}
+struct MBlock {
+    int r0, r1, start, len;
+};
+__host__ __device__ constexpr int mblocks(int P) {
+    int g = 0, len = 0;
+    for (int r = 0; r < mrows(P); ++r) {
+        const int l = mrow(P, r).len;
+        if (r == 0 || len + l > MB) {
+            ++g;
+            len = 0;
+        }
+        len += l;
+    }
+    return g;
+}
+__host__ __device__ constexpr MBlock mblock(int P, int g) {
+    int k = -1, len = 0, r0 = 0;
+    for (int r = 0; r < mrows(P); ++r) {
+        const int l = mrow(P, r).len;
+        if (r == 0 || len + l > MB) {
+            if (k == g) return MBlock{r0, r, mrow(P, r0).start, len};
+            ++k;
+            len = 0;
+            r0 = r;
+        }
+        len += l;
+    }
+    return MBlock{r0, mrows(P), mrow(P, r0).start, len};
+}
+
+// acc[start - m0 + c] += q x^a y^b z^c over the rows [r, r1)
+template <int P, int r, int r1>
+__device__ __forceinline__ void mrows_acc(double q, const double (&xp)[P + 1], const double (&yp)[P + 1], double z,
+                                          int m0, double (&acc)[MB]) {
+    constexpr MRow R = mrow(P, r);
+    double m = q * xp[R.a] * yp[R.b];
+#pragma unroll
+    for (int c = 0; c < R.len; ++c) {
+        acc[R.start - m0 + c] += m;
+        if (c + 1 < R.len) m *= z;
+    }
+    if constexpr (r + 1 < r1) mrows_acc<P, r + 1, r1>(q, xp, yp, z, m0, acc);
+}
+
+// Moment block g over the KP particles each lane holds (q = 0 for an empty
+// slot), summed over the lanes through red and added into S (LDS, full-slot
+// order); then the next block.
+template <int P, int g, int KP>
+__device__ __forceinline__ void p2l_blocks(const double (&wx)[KP], const double (&wy)[KP], const double (&wz)[KP],
+                                           const double (&qq)[KP], double* S, double (*red)[65], double tok) {
+    constexpr MBlock K = mblock(P, g);
+    const int lane = threadIdx.x;
+    double acc[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        // particle j's powers only after particle j-1 is accumulated (one set
+        // of power tables live at a time), the first after the previous block
+        double x1 = wx[j], y1 = wy[j];
+        __asm__ volatile("" : "+v"(x1), "+v"(y1) : "v"(j == 0 ? tok : acc[K.len - 1]));
+        double xp[P + 1], yp[P + 1];
+        xp[0] = yp[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+            xp[k] = xp[k - 1] * x1;
+            yp[k] = yp[k - 1] * y1;
+        }
+        mrows_acc<P, K.r0, K.r1>(qq[j], xp, yp, wz[j], K.start, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < K.len; ++j) red[j][lane] = acc[j];
+    __syncthreads();
+    if (lane < K.len) {
+        double v = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < 64; ++k) v += red[lane][k];
+        // (a, b, c) of position K.start + lane, then its full slot
+        int a = 0, bb = 0, r = K.start + lane;
+        while (r >= (P - a + 1) * (P - a + 2) / 2) r -= (P - a + 1) * (P - a + 2) / 2, ++a;
+        while (r >= P - a - bb + 1) r -= P - a - bb + 1, ++bb;
+        const int n = a + bb + r;
+        S[n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - bb)] += v;
+    }
+    __syncthreads();
+    if constexpr (g + 1 < mblocks(P)) p2l_blocks<P, g + 1, KP>(wx, wy, wz, qq, S, red, acc[K.len - 1]);
+}
+
+// The particles of X(B) are numbered in list order, 64 entries at a time
+// (their first particles and the prefix sums of their sizes staged in LDS);
+// each round, lane l holds numbers base + l + 64 j (j < KP) in registers for
+// every moment block.
+constexpr int P2L_KP = 5;
 template <int P>
 __global__ __launch_bounds__(64) void k_p2l(const ABox* __restrict__ boxes, ATree t, const int32_t* __restrict__ xoff,
                                             const int32_t* __restrict__ xlist, const double4* __restrict__ Pt,
-                                            double* __restrict__ L) {
+                                            DevTables T, double* __restrict__ L) {
     constexpr int NC = (P + 1) * (P + 1);
-    constexpr int STR = NC | 1;
+    constexpr int NF = (P + 1) * (P + 2) * (P + 3) / 6;
+    constexpr int KP = P2L_KP;
     const int B = blockIdx.x;
     const int x0 = xoff[B], x1 = xoff[B + 1];
     if (x0 == x1) return;
     const int lane = threadIdx.x;
+    __shared__ double S[NF];
+    __shared__ double red[MB][65];
+    __shared__ int epb[64], epre[65];
+    for (int k = lane; k < NF; k += 64) S[k] = 0.0;
     const NodeGeom G = node_geom(boxes, t, B);
-    __shared__ double Ds[64 * STR];
-    constexpr int KPL = (NC + 63) / 64;
-    double acc[KPL];
+    for (int e0 = x0; e0 < x1; e0 += 64) {
+        const int ne = min(64, x1 - e0);
+        int sz = 0;
+        if (lane < ne) {
+            const int C = xlist[e0 + lane];
+            epb[lane] = t.pb[C];
+            sz = t.pe[C] - t.pb[C];
+        }
+        int incl = sz;  // inclusive scan over the lanes
 #pragma unroll
-    for (int k = 0; k < KPL; ++k) acc[k] = 0.0;
-    int total = 0;
-    for (int xi = x0; xi < x1; ++xi) {
-        const int C = xlist[xi];
-        total += t.pe[C] - t.pb[C];
-    }
-    int cx = x0, cs = t.pb[xlist[x0]];  // cursor: X entry and particle of the next chunk
-    for (int base = 0; base < total; base += 64) {
-        const int cnt = min(64, total - base);
-        if (lane < cnt) {
-            int li = cx, ls = cs, rem = lane;
-            while (true) {
-                const int avail = t.pe[xlist[li]] - ls;
-                if (rem < avail) {
-                    ls += rem;
-                    break;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d);
+            if (lane >= d) incl += o;
+        }
+        epre[lane + 1] = incl;
+        if (lane == 0) epre[0] = 0;
+        __syncthreads();
+        const int tot = epre[ne];
+        for (int base = 0; base < tot; base += 64 * KP) {
+            double wx[KP], wy[KP], wz[KP], qq[KP];
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                const int gi = base + lane + 64 * j;
+                wx[j] = wy[j] = wz[j] = qq[j] = 0.0;
+                if (gi < tot) {
+                    int lo = 0, hi = ne;  // entry e with epre[e] <= gi < epre[e + 1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (epre[mid] <= gi) lo = mid; else hi = mid;
+                    }
+                    const double4 pt = Pt[epb[lo] + gi - epre[lo]];
+                    const double ux = (G.zx - pt.x) / G.h, uy = (G.zy - pt.y) / G.h, uz = (G.zz - pt.z) / G.h;
+                    const double ir2 = 1.0 / (ux * ux + uy * uy + uz * uz);
+                    qq[j] = pt.w * sqrt(ir2);
+                    wx[j] = ux * ir2;
+                    wy[j] = uy * ir2;
+                    wz[j] = uz * ir2;
                 }
-                rem -= avail;
-                ++li;
-                ls = t.pb[xlist[li]];
             }
-            const double4 pt = Pt[ls];
-            double D[NC];
-            gen_dtensor<P>((G.zx - pt.x) / G.h, (G.zy - pt.y) / G.h, (G.zz - pt.z) / G.h, D);
-#pragma unroll
-            for (int k = 0; k < NC; ++k) Ds[lane * STR + k] = pt.w * D[k];
+            p2l_blocks<P, 0, KP>(wx, wy, wz, qq, S, red, 0.0);
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KPL; ++k) {
-            const int kk = lane + 64 * k;
-            if (kk < NC)
-                for (int i = 0; i < cnt; ++i) acc[k] += Ds[i * STR + kk];
-        }
-        __syncthreads();
-        // advance the cursor by the chunk
-        int rem = cnt;
-        while (rem > 0) {
-            const int avail = t.pe[xlist[cx]] - cs;
-            if (rem < avail) {
-                cs += rem;
-                rem = 0;
-            } else {
-                rem -= avail;
-                ++cx;
-                if (cx < x1) cs = t.pb[xlist[cx]];
-            }
-        }
+        __syncthreads();  // the entry table is read before it is restaged
     }
     double* Lb = L + (size_t)B * ldm_of(P);
-#pragma unroll
-    for (int k = 0; k < KPL; ++k) {
-        const int kk = lane + 64 * k;
-        if (kk < NC) Lb[kk] += acc[k];
+    for (int n = lane; n < NC; n += 64) {
+        double v = 0.0;
+        for (int k = T.det_start[n]; k < T.det_start[n + 1]; ++k) v += T.det_coef[k] * S[T.det_full[k]];
+        int r = 0;
+        while ((r + 1) * (r + 1) <= n) ++r;
+        double w = 1.0;  // (-1)^r (2r-1)!!
+        for (int i = 1; i <= r; ++i) w *= -(double)(2 * i - 1);
+        Lb[n] += w * v;
     }
 }
 
@@ -833,14 +960,17 @@ void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M
 
 size_t m2p_coef_ld(int p) { return (size_t)ldc_of(p); }
 
+// one source: phi += q/r, grad -= q (x_b - x_a)/r^3; a pair at distance 0
+// (the particle itself, or a coincident one) contributes nothing (no branch:
+// the reciprocal distance is selected to 0)
 __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, double& f, double& gx, double& gy,
                                   double& gz) {
     const double dx = xb - src.x, dy = yb - src.y, dz = zb - src.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 == 0.0) return;  // coincident pair: contributes nothing
     double y = __builtin_amdgcn_rsq(r2);
     y = y * (1.5 - 0.5 * r2 * y * y);
     y = y * (1.5 - 0.5 * r2 * y * y);
+    y = r2 > 0.0 ? y : 0.0;
     f += src.w * y;
     const double ir3 = src.w * y * y * y;
     gx -= ir3 * dx;
@@ -1105,7 +1235,8 @@ __global__ __launch_bounds__(64 * MW) void k_m2p_leaf(const ABox* __restrict__ b
 }
 
 // Near field: one thread per sorted particle s in leaf B; direct sum over the
-// particles of the leaves in U(B), self excluded, plus the far field F[s].
+// particles of the leaves in U(B) (the particle itself contributes nothing),
+// plus the far field F[s].
 // Writes phi and grad in input order, or with to_F the total back into F[s].
 __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int32_t* __restrict__ leaf_of,
                                                       const double4* __restrict__ Pt, double4* __restrict__ F,
@@ -1122,10 +1253,15 @@ __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int3
     for (int j = uoff[B]; j < uoff[B + 1]; ++j) {
         const int C = ulist[j];
         const int e = t.pe[C];
-        for (int s2 = t.pb[C]; s2 < e; ++s2) {
-            if (s2 == s) continue;
-            pair_add_a(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
+        int s2 = t.pb[C];
+        for (; s2 + 4 <= e; s2 += 4) {  // four loads in flight
+            const double4 q0 = Pt[s2], q1 = Pt[s2 + 1], q2 = Pt[s2 + 2], q3 = Pt[s2 + 3];
+            pair_add_a(pt.x, pt.y, pt.z, q0, f, gx, gy, gz);
+            pair_add_a(pt.x, pt.y, pt.z, q1, f, gx, gy, gz);
+            pair_add_a(pt.x, pt.y, pt.z, q2, f, gx, gy, gz);
+            pair_add_a(pt.x, pt.y, pt.z, q3, f, gx, gy, gz);
         }
+        for (; s2 < e; ++s2) pair_add_a(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
     }
     if (to_F) {
         F[s] = make_double4(f, gx, gy, gz);
@@ -1162,10 +1298,10 @@ void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4*
 }
 
 void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const int32_t* xoff, const int32_t* xlist,
-                const double4* P, double* L) {
+                const double4* P, const DevTables& T, double* L) {
     if (nn <= 0) return;
     switch (p) {
-#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2l<PP>, dim3(nn), dim3(64), 0, s, boxes, t, xoff, xlist, P, L); break;
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2l<PP>, dim3(nn), dim3(64), 0, s, boxes, t, xoff, xlist, P, T, L); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;

@@ -512,6 +512,7 @@ bool grow_nodes(ctfmm_ctx* c, Forest& f, size_t need) {
     k = old; if (!grow(c, f.tr.sys, k, ncap, true)) return false;
     k = 8 * old; if (!grow(c, f.tr.child, k, 8 * ncap, true)) return false;
     k = 27 * old; if (!grow(c, f.tr.nb, k, 27 * ncap, true)) return false;
+    k = old; if (!grow(c, f.tr.geo, k, ncap, true)) return false;
     f.ncap = ncap;
     return true;
 }
@@ -728,6 +729,7 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     const int nn = total;
     f.nn = nn;
     const int maxlev = (int)f.lev_first.size() - 1;
+    launch_node_geo(st, nn, f.boxes, f.tr);
     for (int l = 1; l <= maxlev; ++l) launch_nb(st, f.lev_first[l], f.lev_count[l], f.tr);
     launch_leaf_of(st, nn, f.tr, f.leaf_of);
 
@@ -907,7 +909,7 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
         launch_sum_chunks(st, p + 1, lsz, f.part, f.aL);
     }
     mark(4);
-    if (f.tot_x > 0) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * ((size_t)nn + 1), f.xlist, f.a_P, f.aL);
+    if (f.tot_x > 0) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * ((size_t)nn + 1), f.xlist, f.a_P, c->T, f.aL);
     mark(5);
     for (int l = 3; l <= maxlev; ++l) launch_l2l_nodes(st, p, f.lev_first[l - 1], f.lev_count[l - 1], f.tr, f.aL, c->T);
     mark(6);
@@ -1204,7 +1206,7 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
     std::vector<long long> sig = {c->nforests, c->order_mode};
     for (int k = 0; k < c->nforests; ++k) {
         const Forest& f = c->forests[k];
-        const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys,
+        const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys, f.tr.geo,
                               f.a_P, f.a_F, f.aM, f.aL, f.aWc, f.aM32, f.loff, f.xlist, f.wlist, f.ulist,
                               f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.ordn,
                               f.ord_tab, f.omask, f.ivl, f.ivc, f.mx, f.my, c->order_tab, c->model, f.part};

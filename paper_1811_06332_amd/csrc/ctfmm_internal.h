@@ -110,6 +110,7 @@ struct ATree {
     int32_t* nb;     // [27] same-level neighbour at offset d = (dx+1)+3(dy+1)+9(dz+1),
                      // else the coarser leaf covering that cell, else -1
     int32_t* sys;    // system (tree of the forest) the node belongs to
+    double4* geo;    // (centre x, y, z, side) of the node's cube
 };
 
 // Systems of a forest: particles of system s are forest positions
@@ -255,12 +256,13 @@ void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* 
 void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
 void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount);
+void launch_node_geo(hipStream_t s, int nn, const ABox* boxes, const ATree& t);
 void launch_p2m_nodes(hipStream_t s, int p, int first, int count, const ABox* boxes, const ATree& t, const double4* P,
                       const DevTables& T, double* M);
 void launch_m2m_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* M, const DevTables& T);
 void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t, double* L, const DevTables& T);
 void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const int32_t* xoff, const int32_t* xlist,
-                const double4* P, double* L);
+                const double4* P, const DevTables& T, double* L);
 void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M, const DevTables& T, double* Cm);
 size_t m2p_coef_ld(int p);  // row stride of the W-list coefficient rows
 void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
