@@ -434,7 +434,11 @@ struct Tile {
     static constexpr int KBYTES = NCH * CHB;
     // one source row in LDS: FP64 rows of LDM doubles, or FP32 rows of S32 floats
     static constexpr int BROW = PREC == PREC_F64 ? LDM * 8 : S32 * 4;
-    static constexpr int BBYTES = TT * BROW;  // the source rows of one offset for TT targets
+    // LDS row stride: 16 bytes of padding, so that the 16 targets of a
+    // B-fragment read start on different banks (row strides that are
+    // multiples of the bank count made every such read a 16-way conflict)
+    static constexpr int BROWL = BROW + 16;
+    static constexpr int BBYTES = TT * BROWL;  // the source rows of one offset for TT targets
     static constexpr int KBUF = (2 * KBYTES + 2 * BBYTES + 1024 <= LDS_LIMIT) ? 2 : 1;
     static constexpr int LDS = KBUF * KBYTES + 2 * BBYTES;
 };
@@ -589,20 +593,17 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         unsigned char* dst = Bb + buf * S::BBYTES;
         const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
         const size_t gstride = (ADAPT && ad.ld_in) ? (size_t)ad.ld_in : (size_t)S::BROW;
-        // RPI rows per copy instruction (RU units each); RPI = 1 unless RU divides 64
-        constexpr int RPI = (RU <= 64 && 64 % RU == 0) ? 64 / RU : 1;
-        constexpr int NI = TT >= RPI ? TT / RPI : 1;
-        for (int i = w; i < NI; i += NW) {
-            // the RPI rows of instruction i lie in one 64-row group (RPI divides 64)
-            const int r0 = i * RPI;
-            const int v = RL == 1 ? myrow[0] : myrow[(r0 >> 6) < RL ? (r0 >> 6) : 0];
-            int row;
-            if (RPI == 1) row = __builtin_amdgcn_readlane(v, r0 & 63);
-            else row = __shfl(v, (r0 & 63) + lane / RU);
-            if (lane < RPI * RU && r0 + lane / RU < TT) {
-                const int ul = lane % RU;
-                const unsigned char* g = row >= 0 ? Mb + (size_t)row * gstride + ul * 16 : zero_row + ul * 16;
-                lds_copy16(g, dst + (size_t)i * RPI * S::BROW);
+        // one row per copy instruction (RU units; the padded LDS rows are not
+        // contiguous, so rows cannot share an instruction)
+        for (int i = w; i < TT; i += NW) {
+            const int v = RL == 1 ? myrow[0] : myrow[(i >> 6) < RL ? (i >> 6) : 0];
+            const int row = __builtin_amdgcn_readlane(v, i & 63);
+            for (int u0 = 0; u0 < RU; u0 += 64) {
+                const int ul = u0 + lane;
+                if (ul < RU) {
+                    const unsigned char* g = row >= 0 ? Mb + (size_t)row * gstride + ul * 16 : zero_row + ul * 16;
+                    lds_copy16(g, dst + (size_t)i * S::BROWL + u0 * 16);
+                }
             }
         }
     };
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             stage_b(ivof(j + 1), bb ^ 1);
         }
         const unsigned char* Kc = Kb + kb * S::KBYTES;
-        const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROW;
+        const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROWL;
         if (PREC == PREC_F64) {
             const double* Bd = reinterpret_cast<const double*>(Bc);
             const double* Kd = reinterpret_cast<const double*>(Kc);
