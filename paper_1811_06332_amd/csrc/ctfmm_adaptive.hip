@@ -254,36 +254,48 @@ void launch_roots(hipStream_t s, const ASys& sy, const ATree& t) {
 }
 
 // For each node of one level: leaf flag, and for a split node the particle
-// range of each octant (binary search of the sorted keys inside its range).
-// flag[8i+o] = 1 for every non-empty octant of a split node.
-__global__ void k_split(int level, int first, int count, int leaf_max, const uint64_t* __restrict__ keys, ATree t,
-                        int32_t* __restrict__ flag, int32_t* __restrict__ cstart) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// range of each octant.  One wavefront per node; lanes 8o..8o+7 find the
+// first particle of the node whose octant exceeds o by an 8-ary search of
+// the sorted keys (8 probes per step, so about log8 of the node's size
+// dependent loads).  flag[8i+o] = 1 for every non-empty octant of a split
+// node, cstart[8i+o] its first particle.
+__global__ __launch_bounds__(64) void k_split(int level, int first, int count, int leaf_max,
+                                              const uint64_t* __restrict__ keys, ATree t, int32_t* __restrict__ flag,
+                                              int32_t* __restrict__ cstart) {
+    const int i = blockIdx.x;
     if (i >= count) return;
+    const int lane = threadIdx.x;
     const int g = first + i;
     const int b = t.pb[g], e = t.pe[g];
     const bool split = (e - b) > leaf_max && level < AMAX;
-    t.info[g] = level | (split ? 0 : 1 << 8);
-#pragma unroll
-    for (int o = 0; o < 8; ++o) t.child[8 * (size_t)g + o] = -1;
+    if (lane == 0) t.info[g] = level | (split ? 0 : 1 << 8);
+    if (lane < 8) t.child[8 * (size_t)g + lane] = -1;
     if (!split) {
-#pragma unroll
-        for (int o = 0; o < 8; ++o) flag[8 * i + o] = 0;
+        if (lane < 8) flag[8 * i + lane] = 0;
         return;
     }
     const int sh = 3 * (AMAX - level - 1);
-    const uint64_t base = t.key[g] * 8;
-    int s0 = b;
-    for (int o = 0; o < 8; ++o) {
-        // first position in [s0, e) whose octant prefix exceeds base + o
-        int lo = s0, hi = e;
-        while (lo < hi) {
-            const int mid = lo + ((hi - lo) >> 1);
-            if ((keys[mid] >> sh) <= base + (uint64_t)o) lo = mid + 1; else hi = mid;
+    const uint64_t lim = t.key[g] * 8 + (uint64_t)(lane >> 3);  // octant prefix bound of this group
+    const int o = lane >> 3, k = lane & 7;
+    int lo = b, hi = e;  // the bound lies in [lo, hi]
+    while (__any(lo < hi)) {
+        const bool more = lo < hi;
+        const int pk = lo + (int)(((long long)(hi - lo) * k) >> 3);
+        const bool pred = more ? (keys[pk] >> sh) > lim : true;
+        const unsigned bits = (unsigned)(__ballot(pred) >> (8 * o)) & 0xFFu;
+        const int c = 8 - __popc(bits);  // probes at or below the bound's octant
+        if (more) {
+            const int nlo = c >= 1 ? lo + (int)(((long long)(hi - lo) * (c - 1)) >> 3) + 1 : lo;
+            const int nhi = c < 8 ? lo + (int)(((long long)(hi - lo) * c) >> 3) : hi;
+            lo = nlo;
+            hi = nhi;
         }
+    }
+    const int prev = __shfl(lo, (lane + 56) & 63);  // the bound of octant o - 1
+    if (k == 0) {
+        const int s0 = o == 0 ? b : prev;
         flag[8 * i + o] = lo > s0 ? 1 : 0;
         cstart[8 * i + o] = s0;
-        s0 = lo;
     }
 }
 
@@ -315,8 +327,7 @@ __global__ void k_emit(int level, int first, int count, int next_first, const in
 
 void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, const uint64_t* keys, const ATree& t,
                   int32_t* flag, int32_t* cstart) {
-    hipLaunchKernelGGL(k_split, dim3(cdiv(count, 128)), dim3(128), 0, s, level, first, count, leaf_max, keys, t, flag,
-                       cstart);
+    hipLaunchKernelGGL(k_split, dim3(count), dim3(64), 0, s, level, first, count, leaf_max, keys, t, flag, cstart);
 }
 
 void launch_emit(hipStream_t s, int level, int first, int count, int next_first, const int32_t* flag,

@@ -127,6 +127,7 @@ struct ctfmm_ctx {
     unsigned char* Kpk = nullptr;  // K_v as MFMA A-fragments of the M2L precision
     int16_t* offlist = nullptr;    // [8][189] offset slots of each target octant
     unsigned char* zero_row = nullptr;  // a zero source row (out-of-domain sources)
+    int* pinned = nullptr;              // pinned host words for small device-to-host reads
     float* M32 = nullptr;          // FP32 copy of one level's multipoles (FP32/BF16 modes)
 
     // workspace, grown on demand
@@ -354,7 +355,7 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    if (m2l_lds_bytes(p, prec) > (size_t)max_lds || m2l_tile_lds_bytes(p, prec, 64) > (size_t)max_lds)
+    if (m2l_lds_bytes(p, prec) > (size_t)max_lds || m2l_tile_lds_bytes(p, prec, 32) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
     c->Kpk = (unsigned char*)dev_alloc(c, m2l_packed_bytes(p, prec));
     const size_t zbytes = std::max((size_t)ldm_of(PMAX) * 8, (size_t)s32_of(PMAX) * 4);
@@ -517,6 +518,13 @@ bool grow_nodes(ctfmm_ctx* c, Forest& f, size_t need) {
     return true;
 }
 
+// the pinned host words (at least 1024), allocated on first use
+int* pinned_words(ctfmm_ctx* c) {
+    if (!c->pinned && hipHostMalloc((void**)&c->pinned, 1024 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        c->pinned = nullptr;
+    return c->pinned;
+}
+
 // run a hipcub algorithm with the shared temporary buffer
 template <class F>
 ctfmm_status cub_run(ctfmm_ctx* c, F fn) {
@@ -552,7 +560,7 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
     const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    if (m2l_tile_lds_bytes(p, prec, 64) > (size_t)max_lds)
+    if (m2l_tile_lds_bytes(p, prec, 32) > (size_t)max_lds)
         return fail(c, CTFMM_EUNSUPPORTED, "device LDS per workgroup too small for the M2L tile");
     const size_t nc = (size_t)(p + 1) * (p + 1);
     OpSet o;
@@ -619,7 +627,7 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best) {
         if (!e) HIPCHK(c, hipEventCreate(&e));
     const void* msrc = prec == CTFMM_PREC_FP64 ? (const void*)f.aM : (const void*)f.aM32;
     float tbest = 0.f;
-    *best = 64;
+    *best = 32;  // fits wherever the context could be created
     for (int tt : {32, 64, 128}) {
         if (m2l_tile_lds_bytes(f.p, prec, tt) > (size_t)max_lds) continue;
         SCHK(make_tiles(c, f, tt));
@@ -713,9 +721,11 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         SCHK(cub_run(c, [&](void* t, size_t& b) {
             return hipcub::DeviceScan::InclusiveSum(t, b, f.sflag, f.sincl, (int)m, st);
         }));
-        int nnext = 0;
-        HIPCHK(c, hipMemcpyAsync(&nnext, f.sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        int* pw = pinned_words(c);
+        if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
+        HIPCHK(c, hipMemcpyAsync(pw, f.sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
+        const int nnext = pw[0];
         if (nnext == 0) break;
         ACHK(grow_nodes(c, f, (size_t)total + nnext));
         launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr);
@@ -747,9 +757,12 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         SCHK(cub_run(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, in, out, (int)n1, st); }));
     }
     int tot[3];
+    int* pw = pinned_words(c);
+    if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
     for (int k = 0; k < 3; ++k)
-        HIPCHK(c, hipMemcpyAsync(&tot[k], f.loff + k * n1 + nn, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(pw + k, f.loff + k * n1 + nn, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    for (int k = 0; k < 3; ++k) tot[k] = pw[k];
     f.tot_u = tot[0];
     f.tot_w = tot[1];
     f.tot_x = tot[2];
@@ -774,8 +787,10 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         return hipcub::DeviceRadixSort::SortPairs(t, b, f.lok, f.loks, f.lov, f.lovs, nn, 0, 8, st);
     }));
     launch_buckets(st, nn, f.loks, f.bse, f.bse + 256);
-    HIPCHK(c, hipMemcpyAsync(f.hb, f.bse, sizeof(f.hb), hipMemcpyDeviceToHost, st));
+    static_assert(sizeof(f.hb) <= 1024 * sizeof(int), "pinned words too few");
+    HIPCHK(c, hipMemcpyAsync(pw, f.bse, sizeof(f.hb), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    std::memcpy(f.hb, pw, sizeof(f.hb));
     int tt = c->tile_forced[f.p] ? c->tile_forced[f.p] : c->tile_tuned[f.p];
     if (tt == 0 && maxlev >= 2) {
         SCHK(tune_tile(c, f, &tt));
@@ -1569,6 +1584,7 @@ void ctfmm_destroy(ctfmm_ctx* c) {
         if (x) (void)hipStreamDestroy(x);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
 }
 

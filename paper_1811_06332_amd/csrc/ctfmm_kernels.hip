@@ -408,6 +408,7 @@ __host__ __device__ constexpr int rank_ce(int k) {
 }
 
 constexpr int LDS_LIMIT = 163840;
+constexpr int STATIC_LDS = 2048;  // the tile kernel's static LDS (target coordinates, offset tables), rounded up
 
 }  // namespace
 
@@ -436,10 +437,12 @@ struct Tile {
     static constexpr int BROW = PREC == PREC_F64 ? LDM * 8 : S32 * 4;
     // LDS row stride: 16 bytes of padding, so that the 16 targets of a
     // B-fragment read start on different banks (row strides that are
-    // multiples of the bank count made every such read a 16-way conflict)
-    static constexpr int BROWL = BROW + 16;
+    // multiples of the bank count made every such read a 16-way conflict),
+    // where the padded rows still fit
+    static constexpr bool PADOK = KBYTES + 2 * TT * (BROW + 16) + STATIC_LDS <= LDS_LIMIT;
+    static constexpr int BROWL = PADOK ? BROW + 16 : BROW;
     static constexpr int BBYTES = TT * BROWL;  // the source rows of one offset for TT targets
-    static constexpr int KBUF = (2 * KBYTES + 2 * BBYTES + 1024 <= LDS_LIMIT) ? 2 : 1;
+    static constexpr int KBUF = (2 * KBYTES + 2 * BBYTES + STATIC_LDS <= LDS_LIMIT) ? 2 : 1;
     static constexpr int LDS = KBUF * KBYTES + 2 * BBYTES;
 };
 
@@ -553,9 +556,21 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     }
     __syncthreads();
 
-    auto stage_k = [&](int iv, int buf) {
-        // v is source - target; the operator is built for r = target - source = -v
-        const int ks = ADAPT ? ad.kslot[o * 189 + iv] : NOFF - 1 - offlist[o * 189 + iv];
+    // Tables of this workgroup in LDS (read before any copy of an iteration
+    // is issued, see below): the offsets it takes (list position j -> offset
+    // iv) and, per offset, the operator slot and (uniform grid) the packed
+    // offset.
+    __shared__ int16_t s_iv[189], s_ks[189], s_off[ADAPT ? 1 : 189];
+    for (int x = tid; x < 189; x += 64 * NW) {
+        if (x < nv) s_iv[x] = (int16_t)ivof(x);
+        if (ADAPT) {
+            s_ks[x] = ad.kslot[o * 189 + x];
+        } else {
+            s_off[ADAPT ? 0 : x] = offlist[o * 189 + x];
+            s_ks[x] = (int16_t)(NOFF - 1 - offlist[o * 189 + x]);  // the operator is built for r = -v
+        }
+    }
+    auto stage_k = [&](int ks, int buf) {
         const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
         unsigned char* dst = Kb + buf * S::KBYTES;
         for (int i = w; i * 64 < KU; i += NW) {
@@ -564,39 +579,64 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         }
     };
     // source rows of offset iv: lane = target slot (each wave computes all of
-    // them; slot lane + 64 k in register k), then every copy instruction moves
-    // whole rows whose address is read with readlane (wave-uniform), so the
-    // per-lane work is one add
+    // them; slot lane + 64 k in register k); adaptive tiles read them from the
+    // tables (vector loads), the uniform grid computes them (LDS reads)
     constexpr int RL = (TT + 63) / 64;
-    auto src_row = [&](int iv, int k) -> int {
-        if (ADAPT) {
-            const int r = lane + 64 * k;
-            if (r >= TT) return -1;
-            const size_t e = (189 * (size_t)work + iv) * TT + r;
-            const int sr = ad.src[e];
-            return (ad.ord && ad.ord[e] != ad.cls) ? -1 : sr;
-        }
-        const int vs = offlist[o * 189 + iv];
-        const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
-        const int tc = tco[lane];
-        int row = -1;
-        if (tc >= 0) {
-            const int sx = (tc & 1023) + vx, sy = ((tc >> 10) & 1023) + vy, sz = (tc >> 20) + vz;
-            if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1) row = (int)morton3(sx, sy, sz);
-        }
-        return row;
-    };
-    auto stage_b = [&](int iv, int buf) {
-        int myrow[RL];
+    // adaptive tiles: raw table entries (source row, order byte); the order
+    // filter is applied by rows_filter once the loads are known to be in
+    // (without an order table the byte is read from the row table itself,
+    // in bounds and unused: no branch, which would make the loads wait)
+    const int8_t* obase = ad.ord ? ad.ord : reinterpret_cast<const int8_t*>(ad.src);
+    auto rows_load = [&](int iv, int (&rows)[RL], int (&ords)[RL]) {
 #pragma unroll
-        for (int k = 0; k < RL; ++k) myrow[k] = src_row(iv, k);
+        for (int k = 0; k < RL; ++k) {
+            const int r = lane + 64 * k;
+            rows[k] = -1;
+            ords[k] = 0;
+            if (r < TT) {
+                const size_t e = (189 * (size_t)work + iv) * TT + r;
+                rows[k] = ad.src[e];
+                ords[k] = obase[e];
+            }
+        }
+    };
+    auto rows_filter = [&](int (&rows)[RL], const int (&ords)[RL]) {
+        if (ad.ord)
+#pragma unroll
+            for (int k = 0; k < RL; ++k)
+                if (ords[k] != ad.cls) rows[k] = -1;
+    };
+    auto rows_of = [&](int iv, int (&rows)[RL]) {
+        if (ADAPT) {
+            int ords[RL];
+            rows_load(iv, rows, ords);
+            rows_filter(rows, ords);
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+            int row = -1;
+            {
+                const int vs = s_off[ADAPT ? 0 : iv];
+                const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
+                const int tc = tco[lane];
+                if (tc >= 0) {
+                    const int sx = (tc & 1023) + vx, sy = ((tc >> 10) & 1023) + vy, sz = (tc >> 20) + vz;
+                    if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1) row = (int)morton3(sx, sy, sz);
+                }
+            }
+            rows[k] = row;
+        }
+    };
+    // every copy instruction moves one whole row, whose address is read with
+    // readlane (wave-uniform); the padded LDS rows are not contiguous, so rows
+    // cannot share an instruction
+    auto stage_b = [&](const int (&rows)[RL], int buf) {
         unsigned char* dst = Bb + buf * S::BBYTES;
         const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
         const size_t gstride = (ADAPT && ad.ld_in) ? (size_t)ad.ld_in : (size_t)S::BROW;
-        // one row per copy instruction (RU units; the padded LDS rows are not
-        // contiguous, so rows cannot share an instruction)
         for (int i = w; i < TT; i += NW) {
-            const int v = RL == 1 ? myrow[0] : myrow[(i >> 6) < RL ? (i >> 6) : 0];
+            const int v = RL == 1 ? rows[0] : rows[(i >> 6) < RL ? (i >> 6) : 0];
             const int row = __builtin_amdgcn_readlane(v, i & 63);
             for (int u0 = 0; u0 < RU; u0 += 64) {
                 const int ul = u0 + lane;
@@ -620,21 +660,52 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             for (int k = 0; k < 6; ++k) accb[r][k] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
-    stage_k(ivof(0), 0);
-    stage_b(ivof(0), 0);
+    __syncthreads();  // the tables
+    int rows_cur[RL], rows_nxt[RL];
+    rows_of(s_iv[0], rows_cur);
+    stage_k(s_ks[s_iv[0]], 0);
+    stage_b(rows_cur, 0);
+    if (nv > 1) rows_of(s_iv[1], rows_nxt);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int trow = w * 16 + (lane & 15);  // this lane's target slot in B fragments
     const int kq = lane >> 4;
+    // Each iteration first does all its LDS reads (FP32: this offset's
+    // operands; the next offsets' table entries and, on the uniform grid,
+    // source rows), then issues the copies of offset j + 1, then loads the
+    // row indices of offset j + 2: reads of LDS behind outstanding
+    // global->LDS copies wait for those copies, and the row indices of a
+    // copy are in registers an iteration before it is issued.
+    // FP32: this offset's operands are read from LDS into registers before
+    // the next offset's copies are issued.  Reads of LDS behind outstanding
+    // global->LDS copies wait for those copies, so issuing the copies first
+    // would serialise them with this offset's matrix-core work.
+    constexpr bool PRE = PREC == PREC_F32;
+    float apre[PRE ? S::NCH : 1], bpre[PRE ? NB : 1];
     for (int j = 0; j < nv; ++j) {
         const int kb = S::KBUF == 2 ? (j & 1) : 0;
         const int bb = j & 1;
-        if (j + 1 < nv) {
-            if (S::KBUF == 2) stage_k(ivof(j + 1), kb ^ 1);
-            stage_b(ivof(j + 1), bb ^ 1);
-        }
         const unsigned char* Kc = Kb + kb * S::KBYTES;
         const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROWL;
+        if (PRE) {
+            const float* Kf = reinterpret_cast<const float*>(Kc);
+            const float* Bf = reinterpret_cast<const float*>(Bc);
+#pragma unroll
+            for (int ch = 0; ch < (PRE ? S::NCH : 1); ++ch) apre[ch] = Kf[ch * 64 + lane];
+#pragma unroll
+            for (int c = 0; c < (PRE ? NB : 1); ++c) bpre[c] = Bf[4 * c + kq];
+        }
+        const int iv1 = j + 1 < nv ? s_iv[j + 1] : 0;
+        const int ks1 = s_ks[iv1];
+        const int iv2 = j + 2 < nv ? s_iv[j + 2] : 0;
+        int rows_nn[RL], ords_nn[RL];
+        if (!ADAPT && j + 2 < nv) rows_of(iv2, rows_nn);
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): every LDS read of the iteration is done
+        if (j + 1 < nv) {
+            if (S::KBUF == 2) stage_k(ks1, kb ^ 1);
+            stage_b(rows_nxt, bb ^ 1);
+        }
+        if (ADAPT && j + 2 < nv) rows_load(iv2, rows_nn, ords_nn);  // used after this iteration's wait
         if (PREC == PREC_F64) {
             const double* Bd = reinterpret_cast<const double*>(Bc);
             const double* Kd = reinterpret_cast<const double*>(Kc);
@@ -649,15 +720,13 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
                     }
             }
         } else if (PREC == PREC_F32) {
-            const float* Bf = reinterpret_cast<const float*>(Bc);
-            const float* Kf = reinterpret_cast<const float*>(Kc);
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                const float b = Bf[4 * c + kq];
+                const float b = bpre[PRE ? c : 0];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (c < S::nch(r)) {
-                        const float a = Kf[(S::cb(r) + c) * 64 + lane];
+                        const float a = apre[PRE ? S::cb(r) + c : 0];
                         acc32[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc32[r][c & 1], 0, 0, 0);
                     }
             }
@@ -698,10 +767,13 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         if (j + 1 < nv) {
             if (S::KBUF == 1) {
                 __syncthreads();  // every wave is done with this offset's K_v
-                stage_k(ivof(j + 1), 0);
+                stage_k(ks1, 0);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
+            if (ADAPT && j + 2 < nv) rows_filter(rows_nn, ords_nn);
+#pragma unroll
+            for (int k = 0; k < RL; ++k) rows_nxt[k] = rows_nn[k];
         }
     }
     long long trow_out;
@@ -983,7 +1055,8 @@ static size_t tile_lds_prec(int p, int prec) {
 }
 
 size_t m2l_tile_lds_bytes(int p, int prec, int tt) {
-    return tt == 32 ? tile_lds_prec<32>(p, prec) : tt == 128 ? tile_lds_prec<128>(p, prec) : tile_lds_prec<64>(p, prec);
+    return STATIC_LDS +
+           (tt == 32 ? tile_lds_prec<32>(p, prec) : tt == 128 ? tile_lds_prec<128>(p, prec) : tile_lds_prec<64>(p, prec));
 }
 
 size_t m2l_lds_bytes(int p, int prec) {
