@@ -390,93 +390,99 @@ void launch_node_geo(hipStream_t s, int nn, const ABox* boxes, const ATree& t) {
 
 // ------------------------------------------------------------------ U, W, X lists
 
-// One thread per node.  FILL = false counts the entries of each list,
-// FILL = true writes them at the offsets of the exclusive scans.  Both passes
-// enumerate in the same order.
+// One thread per node c, from the neighbour tables only:
+//   U_d(c), c a leaf: the adjacent leaves of c's level or coarser (c itself
+//           included), the distinct leaf entries of its table;
+//   X(c):   the coarser leaves touching parent(c) but not c.
+// The rest of the lists are transposes of these:
+//   U(B) = U_d(B) + {finer leaves c : B in U_d(c)} (every finer adjacent
+//          leaf lists B, the coarser leaf covering its neighbour cell);
+//   W(B) = {c : B in X(c)} (c is below a same-level neighbour of B, not
+//          adjacent to B while its parent is).
+// FILL = false counts (the transposed entries with integer atomics), FILL =
+// true writes: own entries in table order, transposed ones at atomically
+// taken slots, put in ascending order afterwards (segmented sorts).
 template <bool FILL>
 __global__ void k_lists(int nn, ATree t, int32_t* __restrict__ ucnt, int32_t* __restrict__ wcnt,
-                        int32_t* __restrict__ xcnt, const int32_t* __restrict__ uoff, const int32_t* __restrict__ woff,
-                        const int32_t* __restrict__ xoff, int32_t* __restrict__ ulist, int32_t* __restrict__ wlist,
-                        int32_t* __restrict__ xlist) {
-    const int B = blockIdx.x * blockDim.x + threadIdx.x;
-    if (B >= nn) return;
-    const int info = t.info[B];
-    const int lb = node_level(info);
-    const uint64_t kb = t.key[B];
-    int nu = 0, nw = 0, nx = 0;
-    auto put_u = [&](int c) {
-        if (FILL) ulist[uoff[B] + nu] = c;
-        ++nu;
-    };
-    auto put_w = [&](int c) {
-        if (FILL) wlist[woff[B] + nw] = c;
-        ++nw;
-    };
-    auto put_x = [&](int c) {
-        if (FILL) xlist[xoff[B] + nx] = c;
-        ++nx;
-    };
-    const int32_t* nbB = t.nb + 27 * (size_t)B;
+                        int32_t* __restrict__ xcnt, int32_t* __restrict__ ufcnt, const int32_t* __restrict__ uoff,
+                        const int32_t* __restrict__ woff, const int32_t* __restrict__ xoff,
+                        int32_t* __restrict__ ulist, int32_t* __restrict__ wlist, int32_t* __restrict__ xlist,
+                        int32_t* __restrict__ wfill, int32_t* __restrict__ ufill) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    const int info = t.info[c];
+    const int lc = node_level(info);
+    const uint64_t kc = t.key[c];
+    int nu = 0, nx = 0;
+    int nbv[27];  // a neighbour table in registers (the duplicate checks compare all pairs)
     if (node_leaf(info)) {
-        // same-level and coarser adjacent leaves (a coarser leaf can fill several entries)
+        const int32_t* nbc = t.nb + 27 * (size_t)c;
+#pragma unroll
+        for (int d = 0; d < 27; ++d) nbv[d] = nbc[d];
+#pragma unroll
         for (int d = 0; d < 27; ++d) {
-            const int C = nbB[d];
-            if (C < 0 || !node_leaf(t.info[C])) continue;
-            bool dup = false;
-            for (int e = 0; e < d; ++e) dup |= nbB[e] == C;
-            if (!dup) put_u(C);
-        }
-        // finer cells inside the same-level non-leaf neighbours: adjacent leaves
-        // join U, non-adjacent cells (whose parent is adjacent) join W
-        int stack[8 * AMAX + 8];
-        for (int d = 0; d < 27; ++d) {
-            const int Q = nbB[d];
-            if (Q < 0 || node_leaf(t.info[Q])) continue;  // a non-leaf entry is always same-level
-            int sp = 0;
-            stack[sp++] = Q;
-            while (sp > 0) {
-                const int A = stack[--sp];
-                for (int o = 0; o < 8; ++o) {
-                    const int c = t.child[8 * (size_t)A + o];
-                    if (c < 0) continue;
-                    const int ci = t.info[c];
-                    if (!adjacent(t.key[c], node_level(ci), kb, lb)) put_w(c);
-                    else if (node_leaf(ci)) put_u(c);
-                    else stack[sp++] = c;
-                }
+            const int C = nbv[d];
+            bool dup = C < 0;
+#pragma unroll
+            for (int e = 0; e < d; ++e) dup |= nbv[e] == C;
+            if (dup) continue;
+            const int ci = t.info[C];
+            if (!node_leaf(ci)) continue;
+            if (FILL) ulist[uoff[c] + nu] = C;
+            ++nu;
+            if (node_level(ci) < lc) {  // c is a finer adjacent leaf of C
+                if (!FILL) atomicAdd(&ufcnt[C], 1);
+                else ulist[uoff[C] + ucnt[C] + atomicAdd(&ufill[C], 1)] = c;
             }
         }
     }
-    // X: leaves coarser than B that touch parent(B) but not B
-    if (lb >= 2) {
-        const int32_t* nbP = t.nb + 27 * (size_t)t.par[B];
+    if (lc >= 2) {
+        const int32_t* nbP = t.nb + 27 * (size_t)t.par[c];
+#pragma unroll
+        for (int d = 0; d < 27; ++d) nbv[d] = nbP[d];
+#pragma unroll
         for (int d = 0; d < 27; ++d) {
-            const int C = nbP[d];
-            if (C < 0) continue;
+            const int C = nbv[d];
+            bool dup = C < 0;
+#pragma unroll
+            for (int e = 0; e < d; ++e) dup |= nbv[e] == C;
+            if (dup) continue;
             const int ci = t.info[C];
             if (!node_leaf(ci)) continue;
-            bool dup = false;
-            for (int e = 0; e < d; ++e) dup |= nbP[e] == C;
-            if (dup) continue;
-            if (!adjacent(t.key[C], node_level(ci), kb, lb)) put_x(C);
+            if (adjacent(t.key[C], node_level(ci), kc, lc)) continue;
+            if (FILL) xlist[xoff[c] + nx] = C;
+            ++nx;
+            if (!FILL) atomicAdd(&wcnt[C], 1);
+            else wlist[woff[C] + atomicAdd(&wfill[C], 1)] = c;
         }
     }
     if (!FILL) {
-        ucnt[B] = nu;
-        wcnt[B] = nw;
-        xcnt[B] = nx;
+        ucnt[c] = nu;
+        xcnt[c] = nx;
     }
 }
 
+__global__ void k_add_i32(int n, const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                          int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
 void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucnt, int32_t* wcnt, int32_t* xcnt,
-                  const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist, int32_t* wlist,
-                  int32_t* xlist) {
+                  int32_t* ufcnt, const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist,
+                  int32_t* wlist, int32_t* xlist, int32_t* wfill, int32_t* ufill) {
+    if (nn <= 0) return;
     if (fill)
-        hipLaunchKernelGGL(k_lists<true>, dim3(cdiv(nn, 64)), dim3(64), 0, s, nn, t, ucnt, wcnt, xcnt, uoff, woff,
-                           xoff, ulist, wlist, xlist);
+        hipLaunchKernelGGL(k_lists<true>, dim3(cdiv(nn, 128)), dim3(128), 0, s, nn, t, ucnt, wcnt, xcnt, ufcnt, uoff,
+                           woff, xoff, ulist, wlist, xlist, wfill, ufill);
     else
-        hipLaunchKernelGGL(k_lists<false>, dim3(cdiv(nn, 64)), dim3(64), 0, s, nn, t, ucnt, wcnt, xcnt, uoff, woff,
-                           xoff, ulist, wlist, xlist);
+        hipLaunchKernelGGL(k_lists<false>, dim3(cdiv(nn, 128)), dim3(128), 0, s, nn, t, ucnt, wcnt, xcnt, ufcnt, uoff,
+                           woff, xoff, ulist, wlist, xlist, wfill, ufill);
+}
+
+void launch_add_i32(hipStream_t s, int n, const int32_t* a, const int32_t* b, int32_t* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_add_i32, dim3(cdiv(n, 256)), dim3(256), 0, s, n, a, b, out);
 }
 
 // ------------------------------------------------------------------ M2L tiles

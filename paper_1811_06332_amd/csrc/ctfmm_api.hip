@@ -62,7 +62,9 @@ struct Forest {
     int32_t* sincl = nullptr;
     int32_t* scstart = nullptr;
     size_t sflag_cap = 0, sincl_cap = 0, scstart_cap = 0;
-    int32_t* lcnt = nullptr;  // [3][nn+1] U, W, X counts
+    int32_t* lcnt = nullptr;  // [7][nn+1]: own U, W, X, finer U counts, U totals, fill cursors
+    int32_t* lsort = nullptr;  // sort output of the transposed list entries
+    size_t lsort_cap = 0;
     int32_t* loff = nullptr;  // [3][nn+1] exclusive scans
     size_t lcnt_cap = 0, loff_cap = 0;
     int32_t* ulist = nullptr;
@@ -743,16 +745,19 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     for (int l = 1; l <= maxlev; ++l) launch_nb(st, f.lev_first[l], f.lev_count[l], f.tr);
     launch_leaf_of(st, nn, f.tr, f.leaf_of);
 
-    // U, W, X lists: count, scan, fill
+    // U, W, X lists: count, scan, fill, order the transposed entries
     const size_t n1 = (size_t)nn + 1;
-    ACHK(grow(c, f.lcnt, f.lcnt_cap, 3 * n1, false));
+    ACHK(grow(c, f.lcnt, f.lcnt_cap, 7 * n1, false));
     ACHK(grow(c, f.loff, f.loff_cap, 3 * n1, false));
-    int32_t *uc = f.lcnt, *wc = f.lcnt + n1, *xc = f.lcnt + 2 * n1;
+    int32_t *uc = f.lcnt, *wc = f.lcnt + n1, *xc = f.lcnt + 2 * n1, *ufc = f.lcnt + 3 * n1;
+    int32_t *ut = f.lcnt + 4 * n1, *wfl = f.lcnt + 5 * n1, *ufl = f.lcnt + 6 * n1;
     int32_t *uo = f.loff, *wo = f.loff + n1, *xo = f.loff + 2 * n1;
-    HIPCHK(c, hipMemsetAsync(f.lcnt, 0, 3 * n1 * sizeof(int32_t), st));
-    launch_lists(st, false, nn, f.tr, uc, wc, xc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    HIPCHK(c, hipMemsetAsync(f.lcnt, 0, 7 * n1 * sizeof(int32_t), st));
+    launch_lists(st, false, nn, f.tr, uc, wc, xc, ufc, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                 nullptr);
+    launch_add_i32(st, (int)n1, uc, ufc, ut);
     for (int k = 0; k < 3; ++k) {
-        int32_t* in = f.lcnt + k * n1;
+        int32_t* in = k == 0 ? ut : f.lcnt + k * n1;
         int32_t* out = f.loff + k * n1;
         SCHK(cub_run(c, [&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, in, out, (int)n1, st); }));
     }
@@ -769,7 +774,31 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     ACHK(grow(c, f.ulist, f.ulist_cap, (size_t)tot[0], false));
     ACHK(grow(c, f.wlist, f.wlist_cap, (size_t)tot[1], false));
     ACHK(grow(c, f.xlist, f.xlist_cap, (size_t)tot[2], false));
-    launch_lists(st, true, nn, f.tr, uc, wc, xc, uo, wo, xo, f.ulist, f.wlist, f.xlist);
+    launch_lists(st, true, nn, f.tr, uc, wc, xc, ufc, uo, wo, xo, f.ulist, f.wlist, f.xlist, wfl, ufl);
+    // the transposed entries in ascending node order: segmented radix sorts of
+    // the W lists and of the finer part of each U list ([uoff + own, uoff'))
+    {
+        int bits = 1;
+        while ((1ll << bits) < (long long)nn) ++bits;
+        ACHK(grow(c, f.lsort, f.lsort_cap, (size_t)std::max(tot[0], tot[1]) + 1, false));
+        int32_t* ubeg = ut;  // the U totals are no longer needed
+        launch_add_i32(st, nn, uo, uc, ubeg);
+        if (tot[0] > 0) {
+            HIPCHK(c, hipMemcpyAsync(f.lsort, f.ulist, (size_t)tot[0] * 4, hipMemcpyDeviceToDevice, st));
+            SCHK(cub_run(c, [&](void* t, size_t& b) {
+                return hipcub::DeviceSegmentedRadixSort::SortKeys(t, b, f.ulist, f.lsort, tot[0], nn, ubeg, uo + 1, 0,
+                                                                  bits, st);
+            }));
+            HIPCHK(c, hipMemcpyAsync(f.ulist, f.lsort, (size_t)tot[0] * 4, hipMemcpyDeviceToDevice, st));
+        }
+        if (tot[1] > 0) {
+            SCHK(cub_run(c, [&](void* t, size_t& b) {
+                return hipcub::DeviceSegmentedRadixSort::SortKeys(t, b, f.wlist, f.lsort, tot[1], nn, wo, wo + 1, 0,
+                                                                  bits, st);
+            }));
+            HIPCHK(c, hipMemcpyAsync(f.wlist, f.lsort, (size_t)tot[1] * 4, hipMemcpyDeviceToDevice, st));
+        }
+    }
     // expansion buffers
     const size_t ldm = (size_t)ldm_of(f.p);
     ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm, false));

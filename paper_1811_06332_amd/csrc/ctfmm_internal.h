@@ -250,8 +250,9 @@ void launch_emit(hipStream_t s, int level, int first, int count, int next_first,
 void launch_nb(hipStream_t s, int first, int count, const ATree& t);
 void launch_leaf_of(hipStream_t s, int nn, const ATree& t, int32_t* leaf_of);
 void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucnt, int32_t* wcnt, int32_t* xcnt,
-                  const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist, int32_t* wlist,
-                  int32_t* xlist);
+                  int32_t* ufcnt, const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist,
+                  int32_t* wlist, int32_t* xlist, int32_t* wfill, int32_t* ufill);
+void launch_add_i32(hipStream_t s, int n, const int32_t* a, const int32_t* b, int32_t* out);
 void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* v);
 void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
 void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
