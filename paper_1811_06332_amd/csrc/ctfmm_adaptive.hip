@@ -984,10 +984,7 @@ __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, 
                                   double& gz) {
     const double dx = xb - src.x, dy = yb - src.y, dz = zb - src.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    double y = __builtin_amdgcn_rsq(r2);
-    y = y * (1.5 - 0.5 * r2 * y * y);
-    y = y * (1.5 - 0.5 * r2 * y * y);
-    y = r2 > 0.0 ? y : 0.0;
+    const double y = r2 > 0.0 ? rsqrt(r2) : 0.0;  // the math library's FP64 reciprocal square root
     f += src.w * y;
     const double ir3 = src.w * y * y * y;
     gx -= ir3 * dx;

@@ -234,14 +234,8 @@ __host__ __device__ constexpr int full_slot(int a, int b, int c) {
     return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
 }
 
-// 1/sqrt(r2) in FP64: the hardware reciprocal square root refined by two
-// Newton steps y <- y (3 - r2 y^2)/2 (quadratic convergence to FP64 rounding)
-__device__ inline double rsqrt64(double r2) {
-    double y = __builtin_amdgcn_rsq(r2);
-    y = y * (1.5 - 0.5 * r2 * y * y);
-    y = y * (1.5 - 0.5 * r2 * y * y);
-    return y;
-}
+// 1/sqrt(r2) in FP64 (the math library's reciprocal square root)
+__device__ inline double rsqrt64(double r2) { return rsqrt(r2); }
 
 __device__ inline void pair_add(double xb, double yb, double zb, double4 src, double& f, double& gx, double& gy,
                                 double& gz) {
