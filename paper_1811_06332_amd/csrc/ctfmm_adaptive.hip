@@ -1290,6 +1290,108 @@ __global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int3
     }
 }
 
+// Near field, one wavefront per leaf B: the particles of the leaves in U(B)
+// (B included; the particle itself contributes nothing) are staged in LDS,
+// P2P_KS per lane per round, numbered in list order (entry offsets and
+// first particles in LDS, found by binary search).  Lane = (target t,
+// source group g): with n targets of a 64-target chunk the sources are split
+// over G = 64/n groups (source j to group j mod G), whose sums are added in
+// group order.  The total with the far field F[s] goes to phi and grad in
+// input order, or with to_F back into F[s].
+constexpr int P2P_KS = 4;
+__global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restrict__ Pt, double4* __restrict__ F,
+                                                 const int32_t* __restrict__ uoff, const int32_t* __restrict__ ulist,
+                                                 const int32_t* __restrict__ idx, bool to_F, double* __restrict__ phi,
+                                                 double* __restrict__ grad) {
+    constexpr int KS = P2P_KS;
+    __shared__ double4 S[64 * KS];
+    __shared__ double4 red[64];
+    __shared__ int epb[64], epre[65];
+    const int B = blockIdx.x;
+    if (!node_leaf(t.info[B])) return;
+    const int lane = threadIdx.x;
+    const int b = t.pb[B], e = t.pe[B];
+    const int u0 = uoff[B], u1 = uoff[B + 1];
+    for (int t0 = b; t0 < e; t0 += 64) {
+        const int ntc = min(64, e - t0);
+        const int G = 64 / ntc;
+        const int g = lane / ntc, tl = lane % ntc;
+        const bool active = g < G;
+        const int s = t0 + tl;
+        const double4 pt = Pt[s];
+        double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, f2 = 0.0, gx2 = 0.0, gy2 = 0.0, gz2 = 0.0;
+        for (int e0 = u0; e0 < u1; e0 += 64) {
+            const int ne = min(64, u1 - e0);
+            int sz = 0;
+            if (lane < ne) {
+                const int C = ulist[e0 + lane];
+                epb[lane] = t.pb[C];
+                sz = t.pe[C] - t.pb[C];
+            }
+            int incl = sz;  // inclusive scan over the lanes
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int o = __shfl_up(incl, d);
+                if (lane >= d) incl += o;
+            }
+            epre[lane + 1] = incl;
+            if (lane == 0) epre[0] = 0;
+            __syncthreads();
+            const int tot = epre[ne];
+            for (int base = 0; base < tot; base += 64 * KS) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const int j = base + lane + 64 * k;
+                    if (j < tot) {
+                        int lo = 0, hi = ne;  // entry with epre[lo] <= j < epre[lo + 1]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (epre[mid] <= j) lo = mid; else hi = mid;
+                        }
+                        S[lane + 64 * k] = Pt[epb[lo] + j - epre[lo]];
+                    }
+                }
+                __syncthreads();
+                const int cnt = min(64 * KS, tot - base);
+                if (active) {  // two independent accumulator chains
+                    int jj = g;
+                    for (; jj + G < cnt; jj += 2 * G) {
+                        pair_add_a(pt.x, pt.y, pt.z, S[jj], f, gx, gy, gz);
+                        pair_add_a(pt.x, pt.y, pt.z, S[jj + G], f2, gx2, gy2, gz2);
+                    }
+                    if (jj < cnt) pair_add_a(pt.x, pt.y, pt.z, S[jj], f, gx, gy, gz);
+                }
+                __syncthreads();
+            }
+        }
+        red[lane] = make_double4(f + f2, gx + gx2, gy + gy2, gz + gz2);
+        __syncthreads();
+        if (g == 0) {
+            const double4 fv = F[s];
+            double tf = fv.x, tx = fv.y, ty = fv.z, tz = fv.w;
+            for (int gg = 0; gg < G; ++gg) {
+                const double4 r = red[tl + ntc * gg];
+                tf += r.x;
+                tx += r.y;
+                ty += r.z;
+                tz += r.w;
+            }
+            if (to_F) {
+                F[s] = make_double4(tf, tx, ty, tz);
+            } else {
+                const size_t o = (size_t)idx[s];
+                if (phi) phi[o] = tf;
+                if (grad) {
+                    grad[3 * o] = tx;
+                    grad[3 * o + 1] = ty;
+                    grad[3 * o + 2] = tz;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // F (sorted order) -> phi, grad (input order)
 __global__ __launch_bounds__(256) void k_scatter_out(int n, const int32_t* __restrict__ idx,
                                                      const double4* __restrict__ F, double* __restrict__ phi,
@@ -1338,7 +1440,7 @@ void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, cons
 #undef CASE
         default: break;
     }
-    hipLaunchKernelGGL(k_p2p_adaptive, grid, blk, 0, s, n, t, leaf_of, P, F, uoff, ulist, idx, to_F, phi, grad);
+    hipLaunchKernelGGL(k_p2p_leaf, dim3(nn), dim3(64), 0, s, t, P, F, uoff, ulist, idx, to_F, phi, grad);
 }
 
 // ------------------------------------------------------------------ M2L orders per pair
