@@ -546,6 +546,36 @@ __global__ __launch_bounds__(64) void k_m2l_tables(int tt, const int4* __restric
     if (lane == 0) vcount[blockIdx.x] = cnt;
 }
 
+// Sort key of an M2L tile: the parent of its first target, then the octant.
+// Nodes are numbered level by level in the order of the sorted keys, so the
+// tiles of the 8 octants over the same parents come out next to each other:
+// they read nearly the same source rows.
+__global__ void k_tile_keys(int ntiles, const int4* __restrict__ tiles, const int32_t* __restrict__ sorted, ATree t,
+                            uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntiles) return;
+    const int4 d = tiles[i];  // (octant, first sorted position, count, level)
+    key[i] = ((uint64_t)t.par[sorted[d.y]] << 3) | (uint64_t)d.x;
+    idx[i] = i;
+}
+
+__global__ void k_gather_int4(int n, const int32_t* __restrict__ idx, const int4* __restrict__ in,
+                              int4* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+
+void launch_tile_keys(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
+                      uint64_t* key, int32_t* idx) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_tile_keys, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, tiles, sorted, t, key, idx);
+}
+
+void launch_gather_int4(hipStream_t s, int n, const int32_t* idx, const int4* in, int4* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_int4, dim3(cdiv(n, 256)), dim3(256), 0, s, n, idx, in, out);
+}
+
 void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount) {
     if (ntiles <= 0) return;

@@ -79,6 +79,10 @@ struct Forest {
     int32_t* bse = nullptr;  // [2][256] (level, octant) bucket bounds
     size_t bse_cap = 0;
     int4* tiles = nullptr;
+    int4* tiles_tmp = nullptr;   // tiles in bucket order, before the sort
+    uint64_t* tkey = nullptr;    // [2][ntiles] tile sort keys
+    int32_t* tidx = nullptr;     // [2][ntiles] tile sort values
+    size_t tiles_tmp_cap = 0, tkey_cap = 0, tidx_cap = 0;
     int32_t* tgt_tab = nullptr;
     int32_t* src_tab = nullptr;
     int32_t* vcount = nullptr;
@@ -611,7 +615,22 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     ACHK(grow(c, f.tgt_tab, f.tgt_cap, (size_t)tt * ntiles, false));
     ACHK(grow(c, f.src_tab, f.src_cap, (size_t)189 * tt * ntiles, false));
     ACHK(grow(c, f.vcount, f.vcount_cap, 189 * ntiles, false));
-    HIPCHK(c, hipMemcpyAsync(f.tiles, f.tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+    ACHK(grow(c, f.tiles_tmp, f.tiles_tmp_cap, ntiles, false));
+    ACHK(grow(c, f.tkey, f.tkey_cap, 2 * ntiles, false));
+    ACHK(grow(c, f.tidx, f.tidx_cap, 2 * ntiles, false));
+    HIPCHK(c, hipMemcpyAsync(f.tiles_tmp, f.tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice,
+                             c->stream));
+    // Tiles in the order of their first target's parent: the workgroups that
+    // run together on one XCD then share their source rows in its L2.
+    const int nt = (int)ntiles;
+    int kbits = 3;
+    while (kbits < 64 && (1ll << (kbits - 3)) < (long long)f.nn) ++kbits;
+    launch_tile_keys(c->stream, nt, f.tiles_tmp, f.lovs, f.tr, f.tkey, f.tidx);
+    SCHK(cub_run(c, [&](void* t, size_t& b) {
+        return hipcub::DeviceRadixSort::SortPairs(t, b, f.tkey, f.tkey + nt, f.tidx, f.tidx + nt, nt, 0, kbits,
+                                                  c->stream);
+    }));
+    launch_gather_int4(c->stream, nt, f.tidx + nt, f.tiles_tmp, f.tiles);
     launch_m2l_tables(c->stream, tt, (int)ntiles, f.tiles, f.lovs, f.tr, c->alist, f.tgt_tab, f.src_tab, f.vcount);
     HIPCHK(c, hipGetLastError());
     return CTFMM_OK;

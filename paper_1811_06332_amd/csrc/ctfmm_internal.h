@@ -255,6 +255,9 @@ void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucn
 void launch_add_i32(hipStream_t s, int n, const int32_t* a, const int32_t* b, int32_t* out);
 void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* v);
 void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
+void launch_tile_keys(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
+                      uint64_t* key, int32_t* idx);
+void launch_gather_int4(hipStream_t s, int n, const int32_t* idx, const int4* in, int4* out);
 void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount);
 void launch_node_geo(hipStream_t s, int nn, const ABox* boxes, const ATree& t);

@@ -251,10 +251,12 @@ __device__ inline void pair_add(double xb, double yb, double zb, double4 src, do
 }
 
 // hardware dispatches workgroups round-robin over the 8 XCDs (each with its
-// own L2); give every XCD a contiguous range of the work instead
+// own L2); give every XCD a contiguous range of the work instead (XCD x,
+// which receives workgroups x, x + 8, ..., takes nb/8 items, one more when
+// x < nb % 8)
 __device__ inline long long xcd_remap(long long b, long long nb) {
-    if (nb % 8) return b;
-    return (b % 8) * (nb / 8) + b / 8;
+    const long long x = b % 8, per = nb / 8, rem = nb % 8;
+    return x * per + (x < rem ? x : rem) + b / 8;
 }
 
 // L2P: one thread per (sorted) particle; the generated straight-line L2P
@@ -427,15 +429,16 @@ struct Tile {
     // bytes of one packed A-fragment chunk (64 lanes)
     static constexpr int CHB = PREC == PREC_F64 ? 512 : PREC == PREC_F32 ? 256 : 3 * 64 * 16;
     static constexpr int KBYTES = NCH * CHB;
-    // one source row in LDS: FP64 rows of LDM doubles, or FP32 rows of S32 floats
+    // one source row: FP64 rows of LDM doubles, or FP32 rows of S32 floats;
+    // in LDS the rows of one offset are contiguous (no padding), so that one
+    // global->LDS copy instruction can fill parts of several rows
     static constexpr int BROW = PREC == PREC_F64 ? LDM * 8 : S32 * 4;
-    // LDS row stride: 16 bytes of padding, so that the 16 targets of a
-    // B-fragment read start on different banks (row strides that are
-    // multiples of the bank count made every such read a 16-way conflict),
-    // where the padded rows still fit
-    static constexpr bool PADOK = KBYTES + 2 * TT * (BROW + 16) + STATIC_LDS <= LDS_LIMIT;
-    static constexpr int BROWL = PADOK ? BROW + 16 : BROW;
-    static constexpr int BBYTES = TT * BROWL;  // the source rows of one offset for TT targets
+    static constexpr int RU = BROW / 16;       // 16-byte units of a row
+    // Rows whose unit count is a multiple of 8 would put the 16 targets of a
+    // B-fragment read on the same LDS banks; their units are rotated by the
+    // row slot instead (LDS unit (u + s) mod RU of slot s holds unit u).
+    static constexpr bool ROT = RU % 8 == 0;
+    static constexpr int BBYTES = TT * BROW;   // the source rows of one offset for TT targets
     static constexpr int KBUF = (2 * KBYTES + 2 * BBYTES + STATIC_LDS <= LDS_LIMIT) ? 2 : 1;
     static constexpr int LDS = KBUF * KBYTES + 2 * BBYTES;
 };
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     const int o = ADAPT ? ad.tiles[work].x : (int)(work & 7);
     const long long pb = work >> 3;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n1 = 1 << level;
     const long long nparents = ADAPT ? 0 : 1ll << (3 * (level - 1));
     if (!ADAPT && tid < 64) {
@@ -572,26 +575,34 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
         }
     };
-    // source rows of offset iv: lane = target slot (each wave computes all of
-    // them; slot lane + 64 k in register k); adaptive tiles read them from the
-    // tables (vector loads), the uniform grid computes them (LDS reads)
-    constexpr int RL = (TT + 63) / 64;
+    // Source rows of offset iv.  The TT rows fill TT * RU units of LDS; copy
+    // instruction k of wave w moves units g = 64 (k NW + w) + lane, i.e. unit
+    // g % RU of row slot g / RU, so each lane needs the source row of the slot
+    // of each of its NI copies.  Adaptive tiles read them from the tables
+    // (vector loads), the uniform grid computes them (LDS reads).
+    constexpr int NU = TT * RU;
+    constexpr int NI = (NU + 64 * NW - 1) / (64 * NW);
+    constexpr int RL = NI;
+    // lanes past the last unit (only in the last copy, when NU is not a
+    // multiple of 64 NW) are masked off in the copy and take the last slot
+    auto unit_ok = [&](int k) { return (NU % (64 * NW) == 0 || k < NI - 1) || 64 * (k * NW + w) + lane < NU; };
+    auto slot_of = [&](int k) {
+        const int sl = (64 * (k * NW + w) + lane) / RU;
+        return sl < TT ? sl : TT - 1;
+    };
     // adaptive tiles: raw table entries (source row, order byte); the order
     // filter is applied by rows_filter once the loads are known to be in
     // (without an order table the byte is read from the row table itself,
     // in bounds and unused: no branch, which would make the loads wait)
     const int8_t* obase = ad.ord ? ad.ord : reinterpret_cast<const int8_t*>(ad.src);
     auto rows_load = [&](int iv, int (&rows)[RL], int (&ords)[RL]) {
+        // unconditional loads: a register written before a load into it
+        // would make the compiler wait for every outstanding copy
+        const size_t e0 = (189 * (size_t)work + iv) * TT;
 #pragma unroll
         for (int k = 0; k < RL; ++k) {
-            const int r = lane + 64 * k;
-            rows[k] = -1;
-            ords[k] = 0;
-            if (r < TT) {
-                const size_t e = (189 * (size_t)work + iv) * TT + r;
-                rows[k] = ad.src[e];
-                ords[k] = obase[e];
-            }
+            rows[k] = ad.src[e0 + slot_of(k)];
+            ords[k] = obase[e0 + slot_of(k)];
         }
     };
     auto rows_filter = [&](int (&rows)[RL], const int (&ords)[RL]) {
@@ -613,7 +624,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             {
                 const int vs = s_off[ADAPT ? 0 : iv];
                 const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
-                const int tc = tco[lane];
+                const int tc = tco[slot_of(k)];
                 if (tc >= 0) {
                     const int sx = (tc & 1023) + vx, sy = ((tc >> 10) & 1023) + vy, sz = (tc >> 20) + vz;
                     if (sx >= 0 && sy >= 0 && sz >= 0 && sx < n1 && sy < n1 && sz < n1) row = (int)morton3(sx, sy, sz);
@@ -622,22 +633,22 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             rows[k] = row;
         }
     };
-    // every copy instruction moves one whole row, whose address is read with
-    // readlane (wave-uniform); the padded LDS rows are not contiguous, so rows
-    // cannot share an instruction
+    // every lane copies one 16-byte unit per instruction; the destination of
+    // an instruction is contiguous (64 units from its wave-uniform base)
     auto stage_b = [&](const int (&rows)[RL], int buf) {
         unsigned char* dst = Bb + buf * S::BBYTES;
         const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
         const size_t gstride = (ADAPT && ad.ld_in) ? (size_t)ad.ld_in : (size_t)S::BROW;
-        for (int i = w; i < TT; i += NW) {
-            const int v = RL == 1 ? rows[0] : rows[(i >> 6) < RL ? (i >> 6) : 0];
-            const int row = __builtin_amdgcn_readlane(v, i & 63);
-            for (int u0 = 0; u0 < RU; u0 += 64) {
-                const int ul = u0 + lane;
-                if (ul < RU) {
-                    const unsigned char* g = row >= 0 ? Mb + (size_t)row * gstride + ul * 16 : zero_row + ul * 16;
-                    lds_copy16(g, dst + (size_t)i * S::BROWL + u0 * 16);
-                }
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            if (unit_ok(k)) {
+                const int g = 64 * (k * NW + w) + lane;
+                const int sl = g / RU, u = g - sl * RU;
+                const int rot = S::ROT ? sl % RU : 0;
+                const int gu = u >= rot ? u - rot : u + RU - rot;  // the row's unit that LDS unit u holds
+                const int row = rows[k];
+                const unsigned char* src = row >= 0 ? Mb + (size_t)row * gstride + gu * 16 : zero_row + gu * 16;
+                lds_copy16(src, dst + (size_t)64 * 16 * (k * NW + w));
             }
         }
     };
@@ -664,6 +675,12 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     __syncthreads();
     const int trow = w * 16 + (lane & 15);  // this lane's target slot in B fragments
     const int kq = lane >> 4;
+    const int trot = S::ROT ? trow % RU : 0;
+    // LDS address of unit u (< RU) of this lane's B-fragment row
+    auto bunit = [&](const unsigned char* Bc, int u) {
+        const int x = u + trot;
+        return Bc + 16 * (x >= RU ? x - RU : x);
+    };
     // Each iteration first does all its LDS reads (FP32: this offset's
     // operands; the next offsets' table entries and, on the uniform grid,
     // source rows), then issues the copies of offset j + 1, then loads the
@@ -680,14 +697,13 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         const int kb = S::KBUF == 2 ? (j & 1) : 0;
         const int bb = j & 1;
         const unsigned char* Kc = Kb + kb * S::KBYTES;
-        const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROWL;
+        const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROW;
         if (PRE) {
             const float* Kf = reinterpret_cast<const float*>(Kc);
-            const float* Bf = reinterpret_cast<const float*>(Bc);
 #pragma unroll
             for (int ch = 0; ch < (PRE ? S::NCH : 1); ++ch) apre[ch] = Kf[ch * 64 + lane];
 #pragma unroll
-            for (int c = 0; c < (PRE ? NB : 1); ++c) bpre[c] = Bf[4 * c + kq];
+            for (int c = 0; c < (PRE ? NB : 1); ++c) bpre[c] = reinterpret_cast<const float*>(bunit(Bc, c))[kq];
         }
         const int iv1 = j + 1 < nv ? s_iv[j + 1] : 0;
         const int ks1 = s_ks[iv1];
@@ -701,11 +717,11 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         }
         if (ADAPT && j + 2 < nv) rows_load(iv2, rows_nn, ords_nn);  // used after this iteration's wait
         if (PREC == PREC_F64) {
-            const double* Bd = reinterpret_cast<const double*>(Bc);
             const double* Kd = reinterpret_cast<const double*>(Kc);
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                const double b = Bd[4 * c + kq];
+                // double 4c + kq of the row: unit 2c + kq/2, half kq % 2
+                const double b = reinterpret_cast<const double*>(bunit(Bc, 2 * c + (kq >> 1)))[kq & 1];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (c < S::nch(r)) {
@@ -725,12 +741,12 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
                     }
             }
         } else {
-            const float* Bf = reinterpret_cast<const float*>(Bc);
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                // this lane's 8 consecutive k of its target, split into three BF16 pieces
-                const v4f x0 = *reinterpret_cast<const v4f*>(Bf + 32 * c + 8 * kq);
-                const v4f x1 = *reinterpret_cast<const v4f*>(Bf + 32 * c + 8 * kq + 4);
+                // this lane's 8 consecutive k of its target (units 8c + 2kq and
+                // the next), split into three BF16 pieces
+                const v4f x0 = *reinterpret_cast<const v4f*>(bunit(Bc, 8 * c + 2 * kq));
+                const v4f x1 = *reinterpret_cast<const v4f*>(bunit(Bc, 8 * c + 2 * kq + 1));
                 bf16x8 b0, b1, b2;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
@@ -758,13 +774,18 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
                     }
             }
         }
+        if (S::KBUF == 1 && j + 1 < nv) {
+            __syncthreads();  // every wave is done with this offset's K_v
+            stage_k(ks1, 0);
+        }
+        // unconditional, so that no load is outstanding at the top of the
+        // loop on any path (the compiler turns any wait behind a mix of
+        // loads and global->LDS copies into a wait for all of them); the
+        // scheduling barrier keeps the matrix-core work above the wait
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         if (j + 1 < nv) {
-            if (S::KBUF == 1) {
-                __syncthreads();  // every wave is done with this offset's K_v
-                stage_k(ks1, 0);
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
             if (ADAPT && j + 2 < nv) rows_filter(rows_nn, ords_nn);
 #pragma unroll
             for (int k = 0; k < RL; ++k) rows_nxt[k] = rows_nn[k];
