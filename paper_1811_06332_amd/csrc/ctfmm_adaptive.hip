@@ -1010,16 +1010,29 @@ size_t m2p_coef_ld(int p) { return (size_t)ldc_of(p); }
 // one source: phi += q/r, grad -= q (x_b - x_a)/r^3; a pair at distance 0
 // (the particle itself, or a coincident one) contributes nothing (no branch:
 // the reciprocal distance is selected to 0)
+// 1/sqrt(x) for x > 0: the hardware estimate y0, refined by the second-order
+// expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ... with e = 1 - x y0^2
+// (the estimate's relative error is far below 2^-17, so the neglected e^3
+// term is below double rounding); x = 0 gives a NaN, selected away by the caller.
+__device__ inline double rsqrt_pos(double x) {
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
+// Eq. PhiAB for one pair: potential and gradient at (xb, yb, zb) of the
+// charge src.w at src.xyz; coincident points (the particle itself) add nothing.
 __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, double& f, double& gx, double& gy,
                                   double& gz) {
     const double dx = xb - src.x, dy = yb - src.y, dz = zb - src.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double y = r2 > 0.0 ? rsqrt(r2) : 0.0;  // the math library's FP64 reciprocal square root
-    f += src.w * y;
-    const double ir3 = src.w * y * y * y;
-    gx -= ir3 * dx;
-    gy -= ir3 * dy;
-    gz -= ir3 * dz;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double y = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;  // a select: both sides are computed
+    const double qy = src.w * y;
+    f += qy;
+    const double ir3 = qy * y * y;
+    gx = fma(-ir3, dx, gx);
+    gy = fma(-ir3, dy, gy);
+    gz = fma(-ir3, dz, gz);
 }
 
 // Far field of one sorted particle s (one thread each) from the local
@@ -1278,56 +1291,16 @@ __global__ __launch_bounds__(64 * MW) void k_m2p_leaf(const ABox* __restrict__ b
     }
 }
 
-// Near field: one thread per sorted particle s in leaf B; direct sum over the
-// particles of the leaves in U(B) (the particle itself contributes nothing),
-// plus the far field F[s].
-// Writes phi and grad in input order, or with to_F the total back into F[s].
-__global__ __launch_bounds__(256) void k_p2p_adaptive(int n, ATree t, const int32_t* __restrict__ leaf_of,
-                                                      const double4* __restrict__ Pt, double4* __restrict__ F,
-                                                      const int32_t* __restrict__ uoff,
-                                                      const int32_t* __restrict__ ulist,
-                                                      const int32_t* __restrict__ idx, bool to_F,
-                                                      double* __restrict__ phi, double* __restrict__ grad) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int B = leaf_of[s];
-    const double4 pt = Pt[s];
-    const double4 fv = F[s];
-    double f = fv.x, gx = fv.y, gy = fv.z, gz = fv.w;
-    for (int j = uoff[B]; j < uoff[B + 1]; ++j) {
-        const int C = ulist[j];
-        const int e = t.pe[C];
-        int s2 = t.pb[C];
-        for (; s2 + 4 <= e; s2 += 4) {  // four loads in flight
-            const double4 q0 = Pt[s2], q1 = Pt[s2 + 1], q2 = Pt[s2 + 2], q3 = Pt[s2 + 3];
-            pair_add_a(pt.x, pt.y, pt.z, q0, f, gx, gy, gz);
-            pair_add_a(pt.x, pt.y, pt.z, q1, f, gx, gy, gz);
-            pair_add_a(pt.x, pt.y, pt.z, q2, f, gx, gy, gz);
-            pair_add_a(pt.x, pt.y, pt.z, q3, f, gx, gy, gz);
-        }
-        for (; s2 < e; ++s2) pair_add_a(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
-    }
-    if (to_F) {
-        F[s] = make_double4(f, gx, gy, gz);
-        return;
-    }
-    const size_t o = (size_t)idx[s];
-    if (phi) phi[o] = f;
-    if (grad) {
-        grad[3 * o] = gx;
-        grad[3 * o + 1] = gy;
-        grad[3 * o + 2] = gz;
-    }
-}
-
 // Near field, one wavefront per leaf B: the particles of the leaves in U(B)
 // (B included; the particle itself contributes nothing) are staged in LDS,
 // P2P_KS per lane per round, numbered in list order (entry offsets and
 // first particles in LDS, found by binary search).  Lane = (target t,
-// source group g): with n targets of a 64-target chunk the sources are split
-// over G = 64/n groups (source j to group j mod G), whose sums are added in
-// group order.  The total with the far field F[s] goes to phi and grad in
-// input order, or with to_F back into F[s].
+// source group g): with n targets in a chunk the sources are split over
+// G = 64/n groups (source j to group j mod G), whose sums are added in group
+// order.  A chunk takes every remaining target when its G n lanes fill at
+// least 7/8 of the wavefront, else the largest power of two of them (which
+// fills it exactly).  The total with the far field F[s] goes to phi and grad
+// in input order, or with to_F back into F[s].
 constexpr int P2P_KS = 4;
 __global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restrict__ Pt, double4* __restrict__ F,
                                                  const int32_t* __restrict__ uoff, const int32_t* __restrict__ ulist,
@@ -1342,8 +1315,9 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restr
     const int lane = threadIdx.x;
     const int b = t.pb[B], e = t.pe[B];
     const int u0 = uoff[B], u1 = uoff[B + 1];
-    for (int t0 = b; t0 < e; t0 += 64) {
-        const int ntc = min(64, e - t0);
+    for (int t0 = b; t0 < e;) {
+        int ntc = min(64, e - t0);
+        if ((64 / ntc) * ntc * 8 < 64 * 7) ntc = 1 << (31 - __builtin_clz(ntc));
         const int G = 64 / ntc;
         const int g = lane / ntc, tl = lane % ntc;
         const bool active = g < G;
@@ -1383,13 +1357,21 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restr
                 }
                 __syncthreads();
                 const int cnt = min(64 * KS, tot - base);
-                if (active) {  // two independent accumulator chains
+                if (active) {
+                    // two independent accumulator chains; the next two sources
+                    // are read ahead (indices clamped into the array, values
+                    // past cnt unused)
+                    constexpr int LIM = 64 * KS - 1;
                     int jj = g;
+                    double4 a0 = S[min(jj, LIM)], a1 = S[min(jj + G, LIM)];
                     for (; jj + G < cnt; jj += 2 * G) {
-                        pair_add_a(pt.x, pt.y, pt.z, S[jj], f, gx, gy, gz);
-                        pair_add_a(pt.x, pt.y, pt.z, S[jj + G], f2, gx2, gy2, gz2);
+                        const double4 c0 = a0, c1 = a1;
+                        a0 = S[min(jj + 2 * G, LIM)];
+                        a1 = S[min(jj + 3 * G, LIM)];
+                        pair_add_a(pt.x, pt.y, pt.z, c0, f, gx, gy, gz);
+                        pair_add_a(pt.x, pt.y, pt.z, c1, f2, gx2, gy2, gz2);
                     }
-                    if (jj < cnt) pair_add_a(pt.x, pt.y, pt.z, S[jj], f, gx, gy, gz);
+                    if (jj < cnt) pair_add_a(pt.x, pt.y, pt.z, a0, f, gx, gy, gz);
                 }
                 __syncthreads();
             }
@@ -1419,6 +1401,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restr
             }
         }
         __syncthreads();
+        t0 += ntc;
     }
 }
 
