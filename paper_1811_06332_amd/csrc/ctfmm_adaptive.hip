@@ -815,12 +815,13 @@ __device__ __forceinline__ void mrows_acc(double q, const double (&xp)[P + 1], c
     if constexpr (r + 1 < r1) mrows_acc<P, r + 1, r1>(q, xp, yp, z, m0, acc);
 }
 
-// Moment block g over the KP particles each lane holds (q = 0 for an empty
-// slot), summed over the lanes through red and added into S (LDS, full-slot
-// order); then the next block.
+// Moment block g over the first kp of the KP particles each lane holds
+// (q = 0 for an empty slot; slots past kp are empty in every lane), summed
+// over the lanes through red and added into S (LDS, full-slot order); then
+// the next block.
 template <int P, int g, int KP>
 __device__ __forceinline__ void p2l_blocks(const double (&wx)[KP], const double (&wy)[KP], const double (&wz)[KP],
-                                           const double (&qq)[KP], double* S, double (*red)[65], double tok) {
+                                           const double (&qq)[KP], int kp, double* S, double (*red)[65], double tok) {
     constexpr MBlock K = mblock(P, g);
     const int lane = threadIdx.x;
     double acc[MB];
@@ -828,6 +829,7 @@ __device__ __forceinline__ void p2l_blocks(const double (&wx)[KP], const double 
     for (int j = 0; j < MB; ++j) acc[j] = 0.0;
 #pragma unroll
     for (int j = 0; j < KP; ++j) {
+        if (j >= kp) break;  // wave-uniform
         // particle j's powers only after particle j-1 is accumulated (one set
         // of power tables live at a time), the first after the previous block
         double x1 = wx[j], y1 = wy[j];
@@ -856,7 +858,7 @@ __device__ __forceinline__ void p2l_blocks(const double (&wx)[KP], const double 
         S[n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - bb)] += v;
     }
     __syncthreads();
-    if constexpr (g + 1 < mblocks(P)) p2l_blocks<P, g + 1, KP>(wx, wy, wz, qq, S, red, acc[K.len - 1]);
+    if constexpr (g + 1 < mblocks(P)) p2l_blocks<P, g + 1, KP>(wx, wy, wz, qq, kp, S, red, acc[K.len - 1]);
 }
 
 // The particles of X(B) are numbered in list order, 64 entries at a time
@@ -919,7 +921,7 @@ __global__ __launch_bounds__(64) void k_p2l(const ABox* __restrict__ boxes, ATre
                     wz[j] = uz * ir2;
                 }
             }
-            p2l_blocks<P, 0, KP>(wx, wy, wz, qq, S, red, 0.0);
+            p2l_blocks<P, 0, KP>(wx, wy, wz, qq, min(KP, (tot - base + 63) / 64), S, red, 0.0);
         }
         __syncthreads();  // the entry table is read before it is restaged
     }
@@ -1300,13 +1302,12 @@ __global__ __launch_bounds__(64 * MW) void k_m2p_leaf(const ABox* __restrict__ b
 // G = 64/n groups (source j to group j mod G), whose sums are added in group
 // order.  A chunk takes every remaining target when its G n lanes fill at
 // least 7/8 of the wavefront, else the largest power of two of them (which
-// fills it exactly).  The total with the far field F[s] goes to phi and grad
-// in input order, or with to_F back into F[s].
+// fills it exactly).  The near field goes to Fn[s] (sorted order); it needs
+// nothing of the far field, so it runs beside the expansion passes.
 constexpr int P2P_KS = 3;
-__global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restrict__ Pt, double4* __restrict__ F,
+__global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restrict__ Pt,
                                                  const int32_t* __restrict__ uoff, const int32_t* __restrict__ ulist,
-                                                 const int32_t* __restrict__ idx, bool to_F, double* __restrict__ phi,
-                                                 double* __restrict__ grad) {
+                                                 double4* __restrict__ Fn) {
     constexpr int KS = P2P_KS;
     __shared__ double4 S[64 * KS];
     double4* red = S;  // the group sums, once the sources are no longer read
@@ -1380,30 +1381,47 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restr
         red[lane] = make_double4(f + f2, gx + gx2, gy + gy2, gz + gz2);
         __syncthreads();
         if (g == 0) {
-            const double4 fv = F[s];
-            double tf = fv.x, tx = fv.y, ty = fv.z, tz = fv.w;
-            for (int gg = 0; gg < G; ++gg) {
-                const double4 r = red[tl + ntc * gg];
-                tf += r.x;
-                tx += r.y;
-                ty += r.z;
-                tz += r.w;
+            double4 r = red[tl];
+            for (int gg = 1; gg < G; ++gg) {
+                const double4 v = red[tl + ntc * gg];
+                r.x += v.x;
+                r.y += v.y;
+                r.z += v.z;
+                r.w += v.w;
             }
-            if (to_F) {
-                F[s] = make_double4(tf, tx, ty, tz);
-            } else {
-                const size_t o = (size_t)idx[s];
-                if (phi) phi[o] = tf;
-                if (grad) {
-                    grad[3 * o] = tx;
-                    grad[3 * o + 1] = ty;
-                    grad[3 * o + 2] = tz;
-                }
-            }
+            Fn[s] = r;
         }
         __syncthreads();
         t0 += ntc;
     }
+}
+
+// far field F plus near field Fn (sorted order) -> phi, grad (input order),
+// or with to_F back into F
+__global__ __launch_bounds__(256) void k_add_near(int n, const int32_t* __restrict__ idx, double4* __restrict__ F,
+                                                  const double4* __restrict__ Fn, bool to_F, double* __restrict__ phi,
+                                                  double* __restrict__ grad) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double4 a = F[s], b = Fn[s];
+    const double4 v = make_double4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+    if (to_F) {
+        F[s] = v;
+        return;
+    }
+    const size_t o = (size_t)idx[s];
+    if (phi) phi[o] = v.x;
+    if (grad) {
+        grad[3 * o] = v.y;
+        grad[3 * o + 1] = v.z;
+        grad[3 * o + 2] = v.w;
+    }
+}
+
+void launch_add_near(hipStream_t s, int n, const int32_t* idx, double4* F, const double4* Fn, bool to_F, double* phi,
+                     double* grad) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_add_near, dim3(cdiv(n, 256)), dim3(256), 0, s, n, idx, F, Fn, to_F, phi, grad);
 }
 
 // F (sorted order) -> phi, grad (input order)
@@ -1438,10 +1456,15 @@ void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t,
     }
 }
 
-void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
-                          const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
-                          const int32_t* woff, const int32_t* wlist, const int32_t* uoff, const int32_t* ulist,
-                          const int32_t* idx, double4* F, bool to_F, double* phi, double* grad) {
+void launch_p2p_near(hipStream_t s, int n, int nn, const ATree& t, const double4* P, const int32_t* uoff,
+                     const int32_t* ulist, double4* Fn) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_p2p_leaf, dim3(nn), dim3(64), 0, s, t, P, uoff, ulist, Fn);
+}
+
+void launch_far_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
+                         const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
+                         const int32_t* woff, const int32_t* wlist, double4* F) {
     if (n <= 0) return;
     const dim3 grid(cdiv(n, 256)), blk(256);
     switch (p) {
@@ -1454,7 +1477,6 @@ void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, cons
 #undef CASE
         default: break;
     }
-    hipLaunchKernelGGL(k_p2p_leaf, dim3(nn), dim3(64), 0, s, t, P, F, uoff, ulist, idx, to_F, phi, grad);
 }
 
 // ------------------------------------------------------------------ M2L orders per pair

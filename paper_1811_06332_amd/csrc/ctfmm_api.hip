@@ -51,8 +51,9 @@ struct Forest {
     int32_t* leaf_of = nullptr;
     size_t a_idx_cap = 0, a_idxs_cap = 0, leaf_of_cap = 0;
     double4* a_P = nullptr;
-    double4* a_F = nullptr;  // far field per sorted particle
-    size_t a_P_cap = 0, a_F_cap = 0;
+    double4* a_F = nullptr;   // far field per sorted particle
+    double4* a_Fn = nullptr;  // near field per sorted particle
+    size_t a_P_cap = 0, a_F_cap = 0, a_Fn_cap = 0;
     double* bbox = nullptr;  // [NBB][6] partial bounds, then lo[3], side
     size_t bbox_cap = 0;
     ATree tr{};
@@ -168,6 +169,8 @@ struct ctfmm_ctx {
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     hipStream_t ord_stream[CTFMM_P_MAX + 1] = {};  // per-order M2L launches run side by side
     hipEvent_t ord_ev[CTFMM_P_MAX + 2] = {};
+    hipStream_t side[2] = {};  // the near field (P2P) and the X lists (P2L) beside the expansion passes
+    hipEvent_t side_ev[4] = {};
     // M2L order per pair (adaptive tree): 0 = the fixed order p, 1 = a table
     // by |v|^2, 2 = the network's decision per (source cell, distance class)
     int order_mode = 0;
@@ -610,7 +613,8 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     const size_t ntiles = f.tiles_host.size();
     f.nchunk = chunks_for(ntiles);
     if (!ntiles) return CTFMM_OK;
-    if (f.nchunk > 1) ACHK(grow(c, f.part, f.part_cap, (size_t)f.nchunk * f.nn * ldm_of(f.p), false));
+    // slots of part: one per offset chunk, and one for the X lists (P2L)
+    ACHK(grow(c, f.part, f.part_cap, (size_t)(f.nchunk + 1) * f.nn * ldm_of(f.p), false));
     ACHK(grow(c, f.tiles, f.tiles_cap, ntiles, false));
     ACHK(grow(c, f.tgt_tab, f.tgt_cap, (size_t)tt * ntiles, false));
     ACHK(grow(c, f.src_tab, f.src_cap, (size_t)189 * tt * ntiles, false));
@@ -692,6 +696,7 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     ACHK(grow(c, f.leaf_of, f.leaf_of_cap, nn_, false));
     ACHK(grow(c, f.a_P, f.a_P_cap, nn_, false));
     ACHK(grow(c, f.a_F, f.a_F_cap, nn_, false));
+    ACHK(grow(c, f.a_Fn, f.a_Fn_cap, nn_, false));
     ACHK(grow(c, f.bbox, f.bbox_cap, 6 * NBB + 4, false));
     ACHK(grow(c, f.bse, f.bse_cap, 512, false));
     ACHK(grow(c, f.vsum, f.vsum_cap, 1, false));
@@ -845,6 +850,10 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         c->tile_tuned[f.p] = tt;
     }
     SCHK(make_tiles(c, f, tt ? tt : 64));
+    for (auto& x : c->side)
+        if (!x) HIPCHK(c, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    for (auto& e : c->side_ev)
+        if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (order_mode_of(c, f) != 0 && !f.tiles_host.empty()) {
         const size_t nt = f.tiles_host.size();
         for (int k = 0; k <= f.p; ++k) SCHK(get_ops(c, k, &f.Kord[k]));
@@ -885,10 +894,15 @@ ctfmm_status count_v_pairs(ctfmm_ctx* c, Forest& f) {
     return CTFMM_OK;
 }
 
-// The numeric passes of one forest (no waits, no memsets: graph-capturable).
-// ev >= 0 records the phase events ev.. (0 start, 1 P2M, 2 M2M, 3 conversions,
-// 4 M2L, 5 P2L, 6 L2L, 7 near field).  to_F leaves the results in sorted
-// order in f.a_F (for launch_scatter_out) instead of writing phi and grad.
+// The numeric passes of one forest (no host waits, no memsets: graph-capturable).
+// The near field (P2P) runs on a side stream from the start, and with fixed
+// orders the X lists (P2L) on another beside M2L; the main stream joins them
+// before the sum of the M2L slots and before the final sum of far and near
+// field.  ev >= 0 records the phase events ev.. on the main stream (0 start,
+// 1 P2M, 2 M2M, 3 conversions, 4 M2L (with the X lists when they run beside
+// it), 5 P2L, 6 L2L, 7 far field and the join with the near field).  to_F
+// leaves the results in sorted order in f.a_F (for launch_scatter_out)
+// instead of writing phi and grad.
 ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, int ev, bool to_F = false) {
     hipStream_t st = c->stream;
     const int p = f.p;
@@ -899,6 +913,13 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
         if (ev >= 0) rec(c, ev + k);
     };
     mark(0);
+    // the near field needs only the particles and the U lists: it runs on a
+    // side stream beside everything up to the final sum
+    const size_t n1 = (size_t)nn + 1;
+    HIPCHK(c, hipEventRecord(c->side_ev[0], st));
+    HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[0], 0));
+    launch_p2p_near(c->side[0], f.n, nn, f.tr, f.a_P, f.loff, f.ulist, f.a_Fn);
+    HIPCHK(c, hipEventRecord(c->side_ev[1], c->side[0]));
     launch_p2m_nodes(st, p, 0, nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
     mark(1);
     for (int l = maxlev - 1; l >= 2; --l) launch_m2m_nodes(st, p, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
@@ -917,20 +938,34 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     // every level at once (it reads only M), then the X lists, then L2L top-down.
     const int omode = order_mode_of(c, f);
     const size_t lsz = (size_t)nn * ldm_of(p);
+    bool x_done = false;
     if (!f.tiles_host.empty() && omode == 0) {
+        // M2L chunks into slots 0 .. nchunk-1 of part; the X lists (P2L, on a
+        // side stream beside M2L) into slot nchunk; then the slots are summed
         AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
-        if (f.nchunk == 1) {
+        const bool xs = f.tot_x > 0;
+        const int slots = f.nchunk + (xs ? 1 : 0);
+        if (slots == 1) {
             HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk,
                                         c->zero_row));
         } else {
-            launch_fill0(st, (long long)(f.nchunk * lsz), f.part);
+            launch_fill0(st, (long long)(slots * lsz), f.part);
+            if (xs) {
+                HIPCHK(c, hipEventRecord(c->side_ev[2], st));
+                HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[2], 0));
+                launch_p2l(c->side[1], p, nn, f.boxes, f.tr, f.loff + 2 * n1, f.xlist, f.a_P, c->T,
+                           f.part + (size_t)f.nchunk * lsz);
+                HIPCHK(c, hipEventRecord(c->side_ev[3], c->side[1]));
+            }
             ad.acc = true;
             ad.nchunk = f.nchunk;
             ad.chunk_stride = lsz;
             HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.part, f.Kpk,
                                         c->zero_row));
-            launch_sum_chunks(st, f.nchunk, lsz, f.part, f.aL);
+            if (xs) HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[3], 0));
+            launch_sum_chunks(st, slots, lsz, f.part, f.aL);
         }
+        x_done = true;
     } else if (!f.tiles_host.empty()) {
         // orders per (source cell, distance class), then one accumulating
         // M2L launch per order over the offsets where that order occurs
@@ -972,13 +1007,14 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
         launch_sum_chunks(st, p + 1, lsz, f.part, f.aL);
     }
     mark(4);
-    if (f.tot_x > 0) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * ((size_t)nn + 1), f.xlist, f.a_P, c->T, f.aL);
+    if (f.tot_x > 0 && !x_done) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * n1, f.xlist, f.a_P, c->T, f.aL);
     mark(5);
     for (int l = 3; l <= maxlev; ++l) launch_l2l_nodes(st, p, f.lev_first[l - 1], f.lev_count[l - 1], f.tr, f.aL, c->T);
     mark(6);
-    const size_t n1 = (size_t)nn + 1;
-    launch_near_adaptive(st, p, f.n, nn, f.tot_w > 0, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1,
-                         f.wlist, f.loff, f.ulist, f.a_idxs, f.a_F, to_F, phi, grad);
+    launch_far_adaptive(st, p, f.n, nn, f.tot_w > 0, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1,
+                        f.wlist, f.a_F);
+    HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[1], 0));
+    launch_add_near(st, f.n, f.a_idxs, f.a_F, f.a_Fn, to_F, phi, grad);
     mark(7);
     HIPCHK(c, hipGetLastError());
     return CTFMM_OK;
@@ -1270,7 +1306,7 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
     for (int k = 0; k < c->nforests; ++k) {
         const Forest& f = c->forests[k];
         const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys, f.tr.geo,
-                              f.a_P, f.a_F, f.aM, f.aL, f.aWc, f.aM32, f.loff, f.xlist, f.wlist, f.ulist,
+                              f.a_P, f.a_F, f.a_Fn, f.aM, f.aL, f.aWc, f.aM32, f.loff, f.xlist, f.wlist, f.ulist,
                               f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.ordn,
                               f.ord_tab, f.omask, f.ivl, f.ivc, f.mx, f.my, c->order_tab, c->model, f.part};
         for (const void* q2 : ptrs) sig.push_back((long long)(uintptr_t)q2);
@@ -1629,6 +1665,10 @@ void ctfmm_destroy(ctfmm_ctx* c) {
     for (auto& e : c->ord_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& x : c->ord_stream)
+        if (x) (void)hipStreamDestroy(x);
+    for (auto& e : c->side_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& x : c->side)
         if (x) (void)hipStreamDestroy(x);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);

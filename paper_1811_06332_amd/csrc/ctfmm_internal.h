@@ -269,10 +269,13 @@ void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t,
                 const double4* P, const DevTables& T, double* L);
 void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M, const DevTables& T, double* Cm);
 size_t m2p_coef_ld(int p);  // row stride of the W-list coefficient rows
-void launch_near_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
-                          const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
-                          const int32_t* woff, const int32_t* wlist, const int32_t* uoff, const int32_t* ulist,
-                          const int32_t* idx, double4* F, bool to_F, double* phi, double* grad);
+void launch_far_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
+                         const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
+                         const int32_t* woff, const int32_t* wlist, double4* F);
+void launch_p2p_near(hipStream_t s, int n, int nn, const ATree& t, const double4* P, const int32_t* uoff,
+                     const int32_t* ulist, double4* Fn);
+void launch_add_near(hipStream_t s, int n, const int32_t* idx, double4* F, const double4* Fn, bool to_F, double* phi,
+                     double* grad);
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
 
 // ---- expansion orders per pair (ctfmm_adaptive.hip, ctfmm_mlp.hip) ----
