@@ -106,12 +106,17 @@ typedef struct ctfmm_stats_t {
                                and the M2L tables) */
     double ms_p2m;
     double ms_m2m;
-    double ms_m2l;          /* all M2L launches */
+    double ms_m2l;          /* all M2L launches (adaptive tree: the M2L kernel itself) */
     double ms_l2l;
-    double ms_near;         /* L2P + P2P (adaptive: also the W-list multipole evaluations) */
+    double ms_near;         /* L2P + P2P (adaptive tree: L2P, the W-list multipole evaluations
+                               and the wait for the near field, whose P2P runs on a side
+                               stream from the start of the numeric pass) */
     double ms_convert;      /* FP32 copies of the multipoles for the FP32/BF16 M2L modes
                                (adaptive tree: also the weighted multipoles of the W list) */
-    double ms_p2l;          /* adaptive tree: local expansions formed from X-list particles */
+    double ms_p2l;          /* adaptive tree: the rest of the downward M2L/X-list step (local
+                               expansions formed from X-list particles, on a side stream
+                               beside M2L where the orders are fixed, the partial-sum
+                               clear and sum) */
     double ms_numeric;      /* batched evaluation: every numeric pass (one graph launch) */
     int64_t evaluations;
     int64_t m2l_launches;

@@ -591,6 +591,21 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
 // to the forests of the context's own order; other forests keep their order.
 int order_mode_of(const ctfmm_ctx* c, const Forest& f) { return f.p == c->prm.order_p ? c->order_mode : 0; }
 
+// FP32 M2L with fixed orders runs the kernel that loads the source rows into
+// registers (k_m2l_rb), from k-quad-major FP32 rows; every other case the
+// tile kernel that stages them in LDS.
+bool rb_m2l(const ctfmm_ctx* c, const Forest& f) {
+    return c->prm.precision == CTFMM_PREC_FP32 && order_mode_of(c, f) == 0;
+}
+
+hipError_t m2l_adaptive(ctfmm_ctx* c, const Forest& f, hipStream_t st, const AdaptM2L& ad, const void* msrc,
+                        double* out) {
+    const int nt = (int)f.tiles_host.size();
+    if (rb_m2l(c, f))
+        return launch_m2l_rb(st, f.p, f.tt, nt, ad, static_cast<const float*>(msrc), out, f.Kpk, c->zero_row);
+    return launch_m2l_tables(st, f.p, c->prm.precision, f.tt, nt, ad, msrc, out, f.Kpk, c->zero_row);
+}
+
 // Workgroups per M2L tile: the 189 offsets of a tile are split into chunks
 // until there are about 2048 workgroups (8 per CU), at most 8 per tile.
 int chunks_for(size_t ntiles) {
@@ -664,10 +679,9 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best) {
             ad.chunk_stride = (size_t)f.nn * ldm_of(f.p);
             out = f.part;
         }
-        const int nt = (int)f.tiles_host.size();
-        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, out, f.Kpk, c->zero_row));
+        HIPCHK(c, m2l_adaptive(c, f, c->stream, ad, msrc, out));
         HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
-        HIPCHK(c, launch_m2l_tables(c->stream, f.p, prec, tt, nt, ad, msrc, out, f.Kpk, c->zero_row));
+        HIPCHK(c, m2l_adaptive(c, f, c->stream, ad, msrc, out));
         HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
         HIPCHK(c, hipEventSynchronize(c->tev[1]));
         float ms = 0.f;
@@ -900,7 +914,8 @@ ctfmm_status count_v_pairs(ctfmm_ctx* c, Forest& f) {
 // before the sum of the M2L slots and before the final sum of far and near
 // field.  ev >= 0 records the phase events ev.. on the main stream (0 start,
 // 1 P2M, 2 M2M, 3 conversions, 4 M2L (with the X lists when they run beside
-// it), 5 P2L, 6 L2L, 7 far field and the join with the near field).  to_F
+// it), 5 P2L, 6 L2L, 7 far field and the join with the near field; 8 and 9
+// around the M2L launch itself, or around all of the per-order M2L work).  to_F
 // leaves the results in sorted order in f.a_F (for launch_scatter_out)
 // instead of writing phi and grad.
 ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, int ev, bool to_F = false) {
@@ -929,7 +944,8 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
         const int f2 = f.lev_first[2];
         if (f.tot_w > 0) launch_m2p_coef(st, p, f2, nn - f2, f.aM, c->T, f.aWc);
         if (prec != CTFMM_PREC_FP64) {
-            launch_to_f32(st, p, nn, f.aM, f.aM32);
+            if (rb_m2l(c, f)) launch_to_f32_kq(st, p, nn, f.aM, f.aM32);
+            else launch_to_f32(st, p, nn, f.aM, f.aM32);
             msrc = f.aM32;
         }
     }
@@ -946,8 +962,9 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
         const bool xs = f.tot_x > 0;
         const int slots = f.nchunk + (xs ? 1 : 0);
         if (slots == 1) {
-            HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.aL, f.Kpk,
-                                        c->zero_row));
+            mark(8);
+            HIPCHK(c, m2l_adaptive(c, f, st, ad, msrc, f.aL));
+            mark(9);
         } else {
             launch_fill0(st, (long long)(slots * lsz), f.part);
             if (xs) {
@@ -960,13 +977,15 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             ad.acc = true;
             ad.nchunk = f.nchunk;
             ad.chunk_stride = lsz;
-            HIPCHK(c, launch_m2l_tables(st, p, prec, f.tt, (int)f.tiles_host.size(), ad, msrc, f.part, f.Kpk,
-                                        c->zero_row));
+            mark(8);
+            HIPCHK(c, m2l_adaptive(c, f, st, ad, msrc, f.part));
+            mark(9);
             if (xs) HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[3], 0));
             launch_sum_chunks(st, slots, lsz, f.part, f.aL);
         }
         x_done = true;
     } else if (!f.tiles_host.empty()) {
+        mark(8);
         // orders per (source cell, distance class), then one accumulating
         // M2L launch per order over the offsets where that order occurs
         const int nt = (int)f.tiles_host.size();
@@ -1005,6 +1024,10 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             HIPCHK(c, hipStreamWaitEvent(st, c->ord_ev[k], 0));
         }
         launch_sum_chunks(st, p + 1, lsz, f.part, f.aL);
+        mark(9);
+    } else {
+        mark(8);
+        mark(9);
     }
     mark(4);
     if (f.tot_x > 0 && !x_done) launch_p2l(st, p, nn, f.boxes, f.tr, f.loff + 2 * n1, f.xlist, f.a_P, c->T, f.aL);
@@ -1076,8 +1099,9 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
         c->st.ms_p2m += elapsed(c, 2, 3);
         c->st.ms_m2m += elapsed(c, 3, 4);
         c->st.ms_convert += elapsed(c, 4, 5);
-        c->st.ms_m2l += elapsed(c, 5, 6);
-        c->st.ms_p2l += elapsed(c, 6, 7);
+        const double m2l = elapsed(c, 10, 11);
+        c->st.ms_m2l += m2l;
+        c->st.ms_p2l += elapsed(c, 5, 7) - m2l;
         c->st.ms_l2l += elapsed(c, 7, 8);
         c->st.ms_near += elapsed(c, 8, 9);
     }

@@ -226,12 +226,17 @@ size_t m2l_packed_bytes(int p, int prec);
 size_t m2l_lds_bytes(int p, int prec);
 void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk);
 void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32);
+// the k-quad-major FP32 rows read by launch_m2l_rb
+void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, float* M32);
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L,
                       const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row);
 // M2L of ntiles tiles of tt targets (32, 64 or 128) of the adaptive tree (any
 // precision; rows are node indices)
 hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles, const AdaptM2L& ad, const void* Msrc,
                              double* L, const unsigned char* Kpk, const unsigned char* zero_row);
+// FP32 adaptive M2L with fixed orders (no ivlist, ord or ld_in) from k-quad-major rows
+hipError_t launch_m2l_rb(hipStream_t s, int p, int tt, int ntiles, const AdaptM2L& ad, const float* M32k, double* L,
+                         const unsigned char* Kpk, const unsigned char* zero_row);
 size_t m2l_tile_lds_bytes(int p, int prec, int tt);
 // row stride of the FP32 multipole copy: (p+1)^2 rounded up to a multiple of 32
 __host__ __device__ constexpr int s32_of(int p) { return (((p + 1) * (p + 1) + 31) / 32) * 32; }

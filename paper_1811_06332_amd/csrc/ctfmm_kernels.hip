@@ -837,6 +837,133 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     }
 }
 
+// ------------------------------------------------------------------ FP32 tile M2L, source rows in registers
+//
+// The adaptive tile M2L in FP32 with every wave loading the B fragments of
+// its 16 targets straight into registers.  The FP32 copy of the multipoles
+// is then stored k-quad major (k_to_f32_kq): element k of a row at
+// (k mod 4) S32/4 + k/4, so the values of lane (target n, k-quad kq),
+// B[4c + kq][n] for c < NB, are contiguous and arrive in 16-byte loads.
+// Only K_v goes through LDS (global->LDS copies, double-buffered, shared by
+// the waves).  Per offset, a wave first reads its A fragments from LDS, then
+// issues the copies of the next K_v, the loads of the next B fragments and
+// the row-table loads of the offset after, then the MFMAs; every load of the
+// iteration is waited for at its end.
+template <int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M32k, double* __restrict__ L,
+                                                    const unsigned char* __restrict__ Kpk,
+                                                    const float* __restrict__ zero_row, const AdaptM2L ad) {
+    constexpr int TT = 16 * NW;
+    using S = Tile<P, PREC_F32, TT>;
+    constexpr int NC = S::NC, R = S::R, NB = S::NB, NCH = S::NCH;
+    constexpr int SEG = S::S32 / 4;    // floats of one k-quad segment of a row
+    constexpr int NBL = (NB + 3) / 4;  // 16-byte loads per lane and offset
+    static_assert(4 * NBL <= SEG, "a lane's loads stay in its segment of the row");
+    constexpr int KU = S::KBYTES / 16;
+    __shared__ __attribute__((aligned(16))) unsigned char Kb[2][S::KBYTES];
+    __shared__ int16_t s_ks[189];
+    const long long blk = xcd_remap(blockIdx.x, gridDim.x);
+    const long long work = ad.tile_base + blk / ad.nchunk;
+    const int chunk = (int)(blk % ad.nchunk);
+    // this workgroup takes offsets [j0, j0 + nv) of the tile
+    const int j0 = 189 * chunk / ad.nchunk;
+    const int nv = 189 * (chunk + 1) / ad.nchunk - j0;
+    if (nv == 0) return;
+    const int o = ad.tiles[work].x;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int x = tid; x < 189; x += 64 * NW) s_ks[x] = ad.kslot[o * 189 + x];
+    auto stage_k = [&](int ks, int buf) {
+        const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
+        for (int i = w; i * 64 < KU; i += NW) {
+            const int u = i * 64 + lane;
+            if (u < KU) lds_copy16(src + (size_t)u * 16, &Kb[buf][i * 1024]);
+        }
+    };
+    const int kq = lane >> 4;
+    // table entry of (offset 0, this lane's target slot 16 w + n)
+    const size_t tab0 = 189 * (size_t)work * TT + 16 * w + (lane & 15);
+    auto row_of = [&](int iv) { return ad.src[tab0 + (size_t)iv * TT]; };
+    auto load_b = [&](int row, float (&b)[4 * NBL]) {
+        const float* src = (row >= 0 ? M32k + (size_t)row * S::S32 : zero_row) + kq * SEG;
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            const float4 v = reinterpret_cast<const float4*>(src)[i];
+            b[4 * i] = v.x;
+            b[4 * i + 1] = v.y;
+            b[4 * i + 2] = v.z;
+            b[4 * i + 3] = v.w;
+        }
+    };
+    v4f acc[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bcur[4 * NBL], bnxt[4 * NBL], apre[NCH];
+    __syncthreads();  // s_ks
+    stage_k(s_ks[j0], 0);
+    load_b(row_of(j0), bcur);
+    int rnxt = nv > 1 ? row_of(j0 + 1) : -1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int j = 0; j < nv; ++j) {
+        const float* Kf = reinterpret_cast<const float*>(Kb[j & 1]);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) apre[ch] = Kf[ch * 64 + lane];
+        const int ks1 = s_ks[j + 1 < nv ? j0 + j + 1 : j0];
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the LDS reads of the iteration are done
+        int rnn = -1;
+        if (j + 1 < nv) {
+            stage_k(ks1, (j + 1) & 1);
+            load_b(rnxt, bnxt);
+        }
+        if (j + 2 < nv) rnn = row_of(j0 + j + 2);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (c < S::nch(r))
+                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(apre[S::cb(r) + c], bcur[c], acc[r][c & 1],
+                                                                         0, 0, 0);
+        }
+        // every load of the iteration is waited for here (on every path); the
+        // scheduling barrier keeps the MFMAs above the wait
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4 * NBL; ++i) bcur[i] = bnxt[i];
+        rnxt = rnn;
+    }
+    const long long trow_out = ad.tgt[TT * (size_t)work + 16 * w + (lane & 15)];
+    if (trow_out < 0) return;
+    const int ldo = ad.ld_out ? ad.ld_out : S::LDM;
+    double* Lt = L + (size_t)chunk * ad.chunk_stride + (size_t)trow_out * ldo;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        // FP32 16x16 accumulator: element i holds row 16r + 4 kq + i
+        const int row0 = 16 * r + 4 * kq;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double v = (double)acc[r][0][i] + (double)acc[r][1][i];
+            if (row0 + i < NC) {
+                if (ad.acc) Lt[row0 + i] += v;
+                else Lt[row0 + i] = v;
+            }
+        }
+    }
+}
+
+// FP32 copy of multipole rows in the k-quad-major order of k_m2l_rb: rows
+// of S32 floats, element k at (k mod 4) S32/4 + k/4, zero past nc
+__global__ void k_to_f32_kq(long long ncell, int nc, int ldm, int s32, const double* __restrict__ M,
+                            float* __restrict__ M32) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= ncell * s32) return;
+    const long long cell = gid / s32;
+    const int pos = (int)(gid % s32), seg = s32 / 4;
+    const int k = 4 * (pos % seg) + pos / seg;
+    M32[gid] = k < nc ? (float)M[cell * ldm + k] : 0.0f;
+}
+
 // ------------------------------------------------------------------ FP32 halo M2L
 //
 // Same work unit (target octant o, 4x4x4 parent block), reorganised around
@@ -1139,6 +1266,39 @@ __global__ void k_sum_chunks(int nchunk, size_t stride, const double* __restrict
 void launch_sum_chunks(hipStream_t s, int nchunk, size_t stride, const double* part, double* L) {
     if (stride == 0) return;
     hipLaunchKernelGGL(k_sum_chunks, dim3(cdiv((long long)stride, 256)), dim3(256), 0, s, nchunk, stride, part, L);
+}
+
+void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, float* M32) {
+    const int s32 = s32_of(p);
+    if (ncell <= 0) return;
+    hipLaunchKernelGGL(k_to_f32_kq, dim3(cdiv(ncell * s32, 256)), dim3(256), 0, s, ncell, (p + 1) * (p + 1), ldm_of(p),
+                       s32, M, M32);
+}
+
+template <int P, int NW>
+hipError_t m2l_rb_impl(hipStream_t s, int nwork, const AdaptM2L& ad, const float* M32k, double* L,
+                       const unsigned char* Kpk, const unsigned char* zero_row) {
+    hipLaunchKernelGGL((k_m2l_rb<P, NW>), dim3((unsigned)nwork), dim3(64 * NW), 0, s, M32k, L, Kpk,
+                       reinterpret_cast<const float*>(zero_row), ad);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2l_rb(hipStream_t s, int p, int tt, int ntiles_in, const AdaptM2L& ad, const float* M32k, double* L,
+                         const unsigned char* Kpk, const unsigned char* zero_row) {
+    if (ntiles_in <= 0) return hipSuccess;
+    if (tt != 32 && tt != 64 && tt != 128) return hipErrorInvalidValue;
+    if (ad.nchunk < 1 || (ad.nchunk > 1 && !ad.acc) || ad.ivlist || ad.ord || ad.ld_in) return hipErrorInvalidValue;
+    const int nwork = ntiles_in * ad.nchunk;
+    switch (p) {
+#define CASE(PP)                                                                           \
+    case PP:                                                                               \
+        if (tt == 32) return m2l_rb_impl<PP, 2>(s, nwork, ad, M32k, L, Kpk, zero_row);     \
+        if (tt == 128) return m2l_rb_impl<PP, 8>(s, nwork, ad, M32k, L, Kpk, zero_row);    \
+        return m2l_rb_impl<PP, 4>(s, nwork, ad, M32k, L, Kpk, zero_row);
+        CTFMM_P_CASES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles_in, const AdaptM2L& ad,
