@@ -586,19 +586,25 @@ void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, con
 // ------------------------------------------------------------------ P2M, M2M, L2L on node lists
 
 // P2M of every leaf among nodes [first, first+count): one wavefront per node
-__global__ __launch_bounds__(64) void k_p2m_nodes(int p, int first, const ABox* __restrict__ boxes, ATree t, const double4* __restrict__ P,
-                                                  DevTables T, double* __restrict__ M) {
+template <int PP>
+__global__ __launch_bounds__(64) void k_p2m_nodes(int first, const ABox* __restrict__ boxes, ATree t,
+                                                  const double4* __restrict__ P, DevTables T, double* __restrict__ M) {
     const int g = first + blockIdx.x;
     const int info = t.info[g];
     if (!node_leaf(info)) return;
     const NodeGeom G = node_geom(boxes, t, g);
-    p2m_cell(p, G.zx, G.zy, G.zz, G.h, t.pb[g], t.pe[g], P, T, M + (size_t)g * ldm_of(p));
+    p2m_cell<PP>(G.zx, G.zy, G.zz, G.h, t.pb[g], t.pe[g], P, T, M + (size_t)g * ldm_of(PP));
 }
 
 void launch_p2m_nodes(hipStream_t s, int p, int first, int count, const ABox* boxes, const ATree& t, const double4* P,
                       const DevTables& T, double* M) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_p2m_nodes, dim3(count), dim3(64), 0, s, p, first, boxes, t, P, T, M);
+    switch (p) {
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2m_nodes<PP>, dim3(count), dim3(64), 0, s, first, boxes, t, P, T, M); break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#undef CASE
+        default: break;
+    }
 }
 
 constexpr int ANP = 4;  // parents per workgroup in M2M/L2L
@@ -755,7 +761,7 @@ void launch_l2l_nodes(hipStream_t s, int p, int first, int count, const ATree& t
 // of X(B) (P2L_KP per lane per round), the moments in blocks of at most MB
 // monomials (compile-time blocks of whole (a, b) rows, hidx order) summed
 // over the lanes through LDS; then the detracer rows, once per node.
-constexpr int MB = 40;
+constexpr int MB = 24;
 struct MRow {
     int a, b, start, len;  // w^(a, b, c) for c = 0..len-1 at positions start..
 };

@@ -149,20 +149,21 @@ struct AdaptM2L {
 };
 
 // P2M of one cell by one wavefront, two phases.  (1) Full monomial moments
-// S_f = sum_a q_a u_a^f, u = (z - x)/h, |f| <= p, with the power tables of up
+// S_f = sum_a q_a u_a^f, u = (z - x)/h, |f| <= P, with the power tables of up
 // to 64 particles at a time in LDS and lanes over f.  (2) The detracer:
 // M~_n = sum_f DET[n][f] S_f for the independent n (Eq. P2M with Eq.
-// Detracer).  Particles [b, e) of P; writes the ldm_of(p) entries of Mc.
-__device__ inline void p2m_cell(int p, double zx, double zy, double zz, double h, int b, int e,
+// Detracer).  Particles [b, e) of P; writes the ldm_of(P) entries of Mc.
+template <int PP>
+__device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b, int e,
                                 const double4* __restrict__ P, const DevTables& T, double* __restrict__ Mc) {
     const int lane = threadIdx.x;
-    const int nc = (p + 1) * (p + 1);
-    const int nf = (p + 1) * (p + 2) * (p + 3) / 6;
-    const int ldm = ldm_of(p);
-    __shared__ double pw[64][3][PMAX + 1];
+    constexpr int nc = (PP + 1) * (PP + 1);
+    constexpr int nf = (PP + 1) * (PP + 2) * (PP + 3) / 6;
+    constexpr int ldm = ldm_of(PP);
+    __shared__ double pw[64][3][PP + 1];
     __shared__ double qs[64];
-    __shared__ double S[NFULL];
-    constexpr int FPL = (NFULL + 63) / 64;  // full components per lane
+    __shared__ double S[nf];
+    constexpr int FPL = (nf + 63) / 64;  // full components per lane
     double acc[FPL];
     int fa[FPL], fb[FPL], fc[FPL];
 #pragma unroll
@@ -178,9 +179,11 @@ __device__ inline void p2m_cell(int p, double zx, double zy, double zz, double h
         if (lane < cnt) {
             const double4 pt = P[s0 + lane];
             const double u[3] = {(zx - pt.x) / h, (zy - pt.y) / h, (zz - pt.z) / h};
+#pragma unroll
             for (int dim = 0; dim < 3; ++dim) {
                 double v = 1.0;
-                for (int k = 0; k <= p; ++k) {
+#pragma unroll
+                for (int k = 0; k <= PP; ++k) {
                     pw[lane][dim][k] = v;
                     v *= u[dim];
                 }

@@ -84,19 +84,25 @@ void launch_leaf_start(hipStream_t s, int nleaves, const uint32_t* keys, int n, 
 // ------------------------------------------------------------------ P2M
 
 // One wavefront per leaf (the P2M of p2m_cell, ctfmm_internal.h).
-__global__ __launch_bounds__(64) void k_p2m(int p, Box box, const int32_t* __restrict__ start,
+template <int PP>
+__global__ __launch_bounds__(64) void k_p2m(Box box, const int32_t* __restrict__ start,
                                             const double4* __restrict__ P, DevTables T, double* __restrict__ M) {
     const uint32_t c = blockIdx.x;
     const double h = box.side / (double)(1 << box.depth);
     const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
     const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
     const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
-    p2m_cell(p, zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(p));
+    p2m_cell<PP>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP));
 }
 
 void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M) {
     const long long nleaves = 1ll << (3 * box.depth);
-    hipLaunchKernelGGL(k_p2m, dim3((unsigned)nleaves), dim3(64), 0, s, p, box, start, P, T, M);
+    switch (p) {
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2m<PP>, dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, T, M); break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#undef CASE
+        default: break;
+    }
 }
 
 // ------------------------------------------------------------------ M2M
