@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
+#include <chrono>
+#include <climits>
 #include <cstring>
 #include <new>
 #include <string>
@@ -534,6 +536,31 @@ int* pinned_words(ctfmm_ctx* c) {
     return c->pinned;
 }
 
+// Small device-to-host reads of non-negative words.  arm() sets the first
+// count pinned words to a sentinel before the copies into them are enqueued;
+// wait_words() then spins until the copies have written every word, which
+// comes back sooner than a stream synchronisation.  After a bounded spin it
+// falls back to the synchronisation (which also returns any device error).
+constexpr int WORD_UNSET = INT_MIN;
+void arm_words(int* pw, int count) {
+    for (int k = 0; k < count; ++k) reinterpret_cast<volatile int*>(pw)[k] = WORD_UNSET;
+}
+ctfmm_status wait_words(ctfmm_ctx* c, const int* pw, int count) {
+    const volatile int* v = pw;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        int k = 0;
+        while (k < count && v[k] != WORD_UNSET) ++k;
+        if (k == count) return CTFMM_OK;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) break;
+        __builtin_ia32_pause();
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < count; ++k)
+        if (v[k] == WORD_UNSET) return fail(c, CTFMM_EDEVICE, "device-to-host read did not arrive");
+    return CTFMM_OK;
+}
+
 // run a hipcub algorithm with the shared temporary buffer
 template <class F>
 ctfmm_status cub_run(ctfmm_ctx* c, F fn) {
@@ -765,14 +792,17 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         SCHK(cub_run(c, [&](void* t, size_t& b) {
             return hipcub::DeviceScan::InclusiveSum(t, b, f.sflag, f.sincl, (int)m, st);
         }));
+        // the children go to [total, total + nnext) with nnext <= m: they are
+        // emitted before the host learns nnext
+        ACHK(grow_nodes(c, f, (size_t)total + m));
+        launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr);
         int* pw = pinned_words(c);
         if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
+        arm_words(pw, 1);
         HIPCHK(c, hipMemcpyAsync(pw, f.sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
+        SCHK(wait_words(c, pw, 1));
         const int nnext = pw[0];
         if (nnext == 0) break;
-        ACHK(grow_nodes(c, f, (size_t)total + nnext));
-        launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr);
         first = total;
         count = nnext;
         total += nnext;
@@ -806,9 +836,10 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     int tot[3];
     int* pw = pinned_words(c);
     if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
+    arm_words(pw, 3);
     for (int k = 0; k < 3; ++k)
         HIPCHK(c, hipMemcpyAsync(pw + k, f.loff + k * n1 + nn, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    SCHK(wait_words(c, pw, 3));
     for (int k = 0; k < 3; ++k) tot[k] = pw[k];
     f.tot_u = tot[0];
     f.tot_w = tot[1];
@@ -859,8 +890,9 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     }));
     launch_buckets(st, nn, f.loks, f.bse, f.bse + 256);
     static_assert(sizeof(f.hb) <= 1024 * sizeof(int), "pinned words too few");
+    arm_words(pw, 512);
     HIPCHK(c, hipMemcpyAsync(pw, f.bse, sizeof(f.hb), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    SCHK(wait_words(c, pw, 512));
     std::memcpy(f.hb, pw, sizeof(f.hb));
     int tt = c->tile_forced[f.p] ? c->tile_forced[f.p] : c->tile_tuned[f.p];
     if (tt == 0 && maxlev >= 2) {
