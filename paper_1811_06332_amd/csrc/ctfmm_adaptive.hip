@@ -214,8 +214,21 @@ __device__ inline uint64_t acoord(double x, double lo, double side) {
     return (uint64_t)s;
 }
 
+__global__ void k_clear_i32(int n, int32_t* __restrict__ a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+__device__ inline uint64_t morton63(double x, double y, double z, const ABox& box) {
+    return spread21(acoord(x, box.lo[0], box.side)) | (spread21(acoord(y, box.lo[1], box.side)) << 1) |
+           (spread21(acoord(z, box.lo[2], box.side)) << 2);
+}
+
+// keys[i]: the 63-bit Morton key of particle i of its system; k32[i] its top
+// 32 bits (levels 1..10 and two bits of level 11)
 __global__ void k_keys64(int n, ASys sy, const double* __restrict__ xyz, const ABox* __restrict__ boxes,
-                         uint64_t* __restrict__ keys, int32_t* __restrict__ idx, int* __restrict__ err) {
+                         uint64_t* __restrict__ keys, uint32_t* __restrict__ k32, int32_t* __restrict__ idx,
+                         int* __restrict__ err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int sidx = sy.nsys == 1 ? 0 : seg_of(sy.goff, sy.nsys, i);
@@ -223,15 +236,52 @@ __global__ void k_keys64(int n, ASys sy, const double* __restrict__ xyz, const A
     const ABox box = boxes[sidx];
     const double x = xyz[3 * gi], y = xyz[3 * gi + 1], z = xyz[3 * gi + 2];
     if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(err, 1);
-    keys[i] = spread21(acoord(x, box.lo[0], box.side)) | (spread21(acoord(y, box.lo[1], box.side)) << 1) |
-              (spread21(acoord(z, box.lo[2], box.side)) << 2);
+    const uint64_t k = morton63(x, y, z, box);
+    keys[i] = k;
+    k32[i] = (uint32_t)(k >> (3 * AMAX - 32));
     idx[i] = (int32_t)gi;
 }
 
 void launch_keys64(hipStream_t s, int n, const ASys& sy, const double* xyz, const ABox* boxes, uint64_t* keys,
-                   int32_t* idx, int* err) {
+                   uint32_t* k32, int32_t* idx, int* err) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_keys64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, xyz, boxes, keys, idx, err);
+    hipLaunchKernelGGL(k_keys64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, xyz, boxes, keys, k32, idx, err);
+}
+
+// P and the full key of every sorted position j (the particle idx[j] of its system)
+__global__ void k_gather_keyed(int n, ASys sy, const int32_t* __restrict__ idx, const double* __restrict__ xyz,
+                               const double* __restrict__ q, const ABox* __restrict__ boxes, double4* __restrict__ P,
+                               uint64_t* __restrict__ keys) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int sidx = sy.nsys == 1 ? 0 : seg_of(sy.goff, sy.nsys, j);
+    const size_t gi = (size_t)idx[j];
+    const double x = xyz[3 * gi], y = xyz[3 * gi + 1], z = xyz[3 * gi + 2];
+    P[j] = make_double4(x, y, z, q[gi]);
+    keys[j] = morton63(x, y, z, boxes[sidx]);
+}
+
+void launch_gather_keyed(hipStream_t s, int n, const ASys& sy, const int32_t* idx, const double* xyz, const double* q,
+                         const ABox* boxes, double4* P, uint64_t* keys) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_keyed, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, idx, xyz, q, boxes, P, keys);
+}
+
+// *flag |= 1 when some cell of level 10 holds more than leaf_max particles of
+// one system (positions j and j + leaf_max share the 30-bit prefix), i.e. when
+// the tree goes deeper than the 32-bit sort orders
+__global__ void k_deep_check(int n, ASys sy, const uint32_t* __restrict__ k32s, int leaf_max, int* __restrict__ flag) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j + leaf_max >= n) return;
+    if ((k32s[j] >> 2) != (k32s[j + leaf_max] >> 2)) return;
+    if (sy.nsys > 1 && seg_of(sy.goff, sy.nsys, j) != seg_of(sy.goff, sy.nsys, j + leaf_max)) return;
+    atomicOr(flag, 1);
+}
+
+void launch_deep_check(hipStream_t s, int n, const ASys& sy, const uint32_t* k32s, int leaf_max, int* flag) {
+    hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, s, 1, flag);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_deep_check, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, k32s, leaf_max, flag);
 }
 
 // ------------------------------------------------------------------ tree
@@ -495,10 +545,6 @@ __global__ void k_lvloct(int nn, ATree t, uint32_t* __restrict__ k, int32_t* __r
     v[g] = g;
 }
 
-__global__ void k_clear_i32(int n, int32_t* __restrict__ a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0;
-}
 
 // bucket [bstart, bend) of every (level, octant) key in the sorted order
 __global__ void k_buckets(int nn, const uint32_t* __restrict__ sk, int32_t* __restrict__ bstart,
@@ -1043,6 +1089,7 @@ __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, 
     gy = fma(-ir3, dy, gy);
     gz = fma(-ir3, dz, gz);
 }
+
 
 // Far field of one sorted particle s (one thread each) from the local
 // expansion of its leaf B (Eq. L2P), into F[s]; zero for leaves above level 2.

@@ -48,6 +48,10 @@ struct Forest {
     uint64_t* k64 = nullptr;
     uint64_t* k64s = nullptr;
     size_t k64_cap = 0, k64s_cap = 0;
+    uint32_t* k32 = nullptr;   // top 32 key bits
+    uint32_t* k32s = nullptr;
+    int32_t* deep = nullptr;   // set when the tree goes deeper than the 32-bit sort orders
+    size_t k32_cap = 0, k32s_cap = 0, deep_cap = 0;
     int32_t* a_idx = nullptr;
     int32_t* a_idxs = nullptr;
     int32_t* leaf_of = nullptr;
@@ -736,6 +740,9 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     SCHK(get_ops(c, f.p, &f.Kpk));
     ACHK(grow(c, f.k64, f.k64_cap, nn_, false));
     ACHK(grow(c, f.k64s, f.k64s_cap, nn_, false));
+    ACHK(grow(c, f.k32, f.k32_cap, nn_, false));
+    ACHK(grow(c, f.k32s, f.k32s_cap, nn_, false));
+    ACHK(grow(c, f.deep, f.deep_cap, 1, false));
     ACHK(grow(c, f.a_idx, f.a_idx_cap, nn_, false));
     ACHK(grow(c, f.a_idxs, f.a_idxs_cap, nn_, false));
     ACHK(grow(c, f.leaf_of, f.leaf_of_cap, nn_, false));
@@ -763,22 +770,46 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     } else {
         launch_bbox_systems(st, sy, xyz, f.boxes);
     }
-    launch_keys64(st, n, sy, xyz, f.boxes, f.k64, f.a_idx, c->err_flag);
+    launch_keys64(st, n, sy, xyz, f.boxes, f.k64, f.k32, f.a_idx, c->err_flag);
+    // The particles are sorted by the top 32 key bits (4 radix passes instead
+    // of 8), which orders every cell down to level 10, and the full keys are
+    // recomputed in sorted order.  A tree that goes deeper (some level-10 cell
+    // holds more than leaf_max particles) is detected with the first level's
+    // count; the particles are then sorted on all 63 bits and the tree built
+    // again.
     if (f.nsys == 1) {
         SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, 0, 3 * AMAX, st);
+            return hipcub::DeviceRadixSort::SortPairs(t, b, f.k32, f.k32s, f.a_idx, f.a_idxs, n, 0, 32, st);
         }));
     } else {
         SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceSegmentedRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, f.nsys,
-                                                                f.goff, f.goff + 1, 0, 3 * AMAX, st);
+            return hipcub::DeviceSegmentedRadixSort::SortPairs(t, b, f.k32, f.k32s, f.a_idx, f.a_idxs, n, f.nsys,
+                                                                f.goff, f.goff + 1, 0, 32, st);
         }));
     }
-    launch_gather(st, n, f.a_idxs, xyz, q, f.a_P);
+    launch_gather_keyed(st, n, sy, f.a_idxs, xyz, q, f.boxes, f.a_P, f.k64s);
+    launch_deep_check(st, n, sy, f.k32s, c->prm.leaf_max, f.deep);
     HIPCHK(c, hipGetLastError());
+    auto full_sort = [&]() -> ctfmm_status {
+        if (f.nsys == 1) {
+            SCHK(cub_run(c, [&](void* t, size_t& b) {
+                return hipcub::DeviceRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, 0, 3 * AMAX, st);
+            }));
+        } else {
+            SCHK(cub_run(c, [&](void* t, size_t& b) {
+                return hipcub::DeviceSegmentedRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n,
+                                                                    f.nsys, f.goff, f.goff + 1, 0, 3 * AMAX, st);
+            }));
+        }
+        launch_gather(st, n, f.a_idxs, xyz, q, f.a_P);
+        HIPCHK(c, hipGetLastError());
+        return CTFMM_OK;
+    };
+    bool sorted_full = false;
 
     // trees, level by level (level 0 holds one root per system)
     ACHK(grow_nodes(c, f, (size_t)f.nsys));
+tree_again:
     launch_roots(st, sy, f.tr);
     f.lev_first.assign(1, 0);
     f.lev_count.assign(1, f.nsys);
@@ -798,9 +829,16 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
         launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr);
         int* pw = pinned_words(c);
         if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
-        arm_words(pw, 1);
+        const int nw = (l == 0 && !sorted_full) ? 2 : 1;  // level 0 also reads the depth check
+        arm_words(pw, nw);
         HIPCHK(c, hipMemcpyAsync(pw, f.sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
-        SCHK(wait_words(c, pw, 1));
+        if (nw == 2) HIPCHK(c, hipMemcpyAsync(pw + 1, f.deep, sizeof(int), hipMemcpyDeviceToHost, st));
+        SCHK(wait_words(c, pw, nw));
+        if (nw == 2 && pw[1] != 0) {
+            SCHK(full_sort());
+            sorted_full = true;
+            goto tree_again;
+        }
         const int nnext = pw[0];
         if (nnext == 0) break;
         first = total;

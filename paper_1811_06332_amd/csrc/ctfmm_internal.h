@@ -249,7 +249,10 @@ void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side
 void launch_bbox(hipStream_t s, int n, const double* xyz, double* part, int nparts, double* out);
 void launch_bbox_systems(hipStream_t s, const ASys& sy, const double* xyz, ABox* boxes);
 void launch_keys64(hipStream_t s, int n, const ASys& sy, const double* xyz, const ABox* boxes, uint64_t* keys,
-                   int32_t* idx, int* err);
+                   uint32_t* k32, int32_t* idx, int* err);
+void launch_gather_keyed(hipStream_t s, int n, const ASys& sy, const int32_t* idx, const double* xyz, const double* q,
+                         const ABox* boxes, double4* P, uint64_t* keys);
+void launch_deep_check(hipStream_t s, int n, const ASys& sy, const uint32_t* k32s, int leaf_max, int* flag);
 void launch_roots(hipStream_t s, const ASys& sy, const ATree& t);
 void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, const uint64_t* keys, const ATree& t,
                   int32_t* flag, int32_t* cstart);
