@@ -201,7 +201,15 @@ struct ctfmm_ctx {
 
     // timing
     bool timing = false;
-    hipEvent_t ev[NPHASE_EV] = {};
+    // phase events, two sets: an adaptive evaluation with fixed orders leaves
+    // its timings pending in one set while the next evaluation records the other
+    hipEvent_t evs[2][NPHASE_EV] = {};
+    hipEvent_t* ev = evs[0];
+    struct Pending {
+        bool on = false;
+        hipEvent_t* ev = nullptr;  // the event set of the pending evaluation
+        int word = 0;              // pinned word with its M2L pair count
+    } pend;
     ctfmm_stats_t st{};
 
     std::vector<void*> owned;  // every workspace allocation (released on destroy)
@@ -486,6 +494,12 @@ inline void rec(ctfmm_ctx* c, int i) {
 float elapsed(ctfmm_ctx* c, int a, int b) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev[a], c->ev[b]);
+    return ms;
+}
+
+float elapsed_in(hipEvent_t* ev, int a, int b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
     return ms;
 }
 
@@ -1137,6 +1151,34 @@ ctfmm_status add_order_hist(ctfmm_ctx* c, Forest& f) {
     return CTFMM_OK;
 }
 
+// phase times of one adaptive evaluation from its event set
+void add_adaptive_times(ctfmm_ctx* c, hipEvent_t* ev) {
+    const int ev_end = NPHASE_EV - 1;
+    c->st.ms_total += elapsed_in(ev, 0, ev_end);
+    c->st.ms_tree += elapsed_in(ev, 0, 1);
+    c->st.ms_p2m += elapsed_in(ev, 2, 3);
+    c->st.ms_m2m += elapsed_in(ev, 3, 4);
+    c->st.ms_convert += elapsed_in(ev, 4, 5);
+    const double m2l = elapsed_in(ev, 10, 11);
+    c->st.ms_m2l += m2l;
+    c->st.ms_p2l += elapsed_in(ev, 5, 7) - m2l;
+    c->st.ms_l2l += elapsed_in(ev, 7, 8);
+    c->st.ms_near += elapsed_in(ev, 8, 9);
+}
+
+// adds the timings and pair count left pending by an adaptive evaluation
+// (waits for that evaluation to finish)
+ctfmm_status finish_pending(ctfmm_ctx* c) {
+    if (!c->pend.on) return CTFMM_OK;
+    c->pend.on = false;
+    HIPCHK(c, hipEventSynchronize(c->pend.ev[NPHASE_EV - 1]));
+    int* pw = pinned_words(c);
+    SCHK(wait_words(c, pw + c->pend.word, 1));
+    c->st.m2l_pairs += pw[c->pend.word];
+    add_adaptive_times(c, c->pend.ev);
+    return CTFMM_OK;
+}
+
 void add_forest_stats(ctfmm_ctx* c, Forest& f) {
     c->st.m2l_launches += f.tiles_host.empty() ? 0 : 1;
     c->st.p2p_leaf_pairs += f.tot_u;
@@ -1164,20 +1206,36 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
     c->st.evaluations += 1;
     add_forest_stats(c, f);
     if (c->timing) {
-        SCHK(count_v_pairs(c, f));
-        c->st.m2l_pairs += f.v_pairs;
-        SCHK(add_order_hist(c, f));
-        HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
-        c->st.ms_total += elapsed(c, 0, ev_end);
-        c->st.ms_tree += elapsed(c, 0, 1);
-        c->st.ms_p2m += elapsed(c, 2, 3);
-        c->st.ms_m2m += elapsed(c, 3, 4);
-        c->st.ms_convert += elapsed(c, 4, 5);
-        const double m2l = elapsed(c, 10, 11);
-        c->st.ms_m2l += m2l;
-        c->st.ms_p2l += elapsed(c, 5, 7) - m2l;
-        c->st.ms_l2l += elapsed(c, 7, 8);
-        c->st.ms_near += elapsed(c, 8, 9);
+        // The previous evaluation's timings are complete by now (this one's
+        // tree build waited on the stream behind it): add them.  This one's
+        // stay pending, with its pair count on its way to a pinned word, so
+        // that the call returns without waiting for the GPU.
+        SCHK(finish_pending(c));
+        if (order_mode_of(c, f) == 0) {
+            const int m = 189 * (int)f.tiles_host.size();
+            int* pw = pinned_words(c);
+            if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
+            const int word = c->ev == c->evs[0] ? 1000 : 1001;
+            arm_words(pw + word, 1);
+            if (m > 0) {
+                SCHK(cub_run(c, [&](void* t, size_t& b) {
+                    return hipcub::DeviceReduce::Sum(t, b, f.vcount, f.vsum, m, c->stream);
+                }));
+                HIPCHK(c, hipMemcpyAsync(pw + word, f.vsum, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            } else {
+                pw[word] = 0;
+            }
+            c->pend.on = true;
+            c->pend.ev = c->ev;
+            c->pend.word = word;
+            c->ev = c->ev == c->evs[0] ? c->evs[1] : c->evs[0];
+        } else {
+            SCHK(count_v_pairs(c, f));
+            c->st.m2l_pairs += f.v_pairs;
+            SCHK(add_order_hist(c, f));
+            HIPCHK(c, hipEventSynchronize(c->ev[ev_end]));
+            add_adaptive_times(c, c->ev);
+        }
     }
     return CTFMM_OK;
 }
@@ -1239,11 +1297,9 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
     }
     if (s == CTFMM_OK) s = build_operators(c);
     if (s == CTFMM_OK) {
-        for (auto& e : c->ev)
-            if (hipEventCreate(&e) != hipSuccess) {
-                s = fail(c, CTFMM_EDEVICE, "hipEventCreate failed");
-                break;
-            }
+        for (auto& set : c->evs)
+            for (auto& e : set)
+                if (s == CTFMM_OK && hipEventCreate(&e) != hipSuccess) s = fail(c, CTFMM_EDEVICE, "hipEventCreate failed");
     }
     if (s != CTFMM_OK) {
         g_create_err = c->err;
@@ -1727,12 +1783,15 @@ ctfmm_status ctfmm_set_timing(ctfmm_ctx* c, int32_t on) {
 
 ctfmm_status ctfmm_stats(ctfmm_ctx* c, ctfmm_stats_t* out) {
     if (!c || !out) return CTFMM_EINVAL;
+    SCHK(finish_pending(c));
     *out = c->st;
     return CTFMM_OK;
 }
 
 ctfmm_status ctfmm_reset_stats(ctfmm_ctx* c) {
     if (!c) return CTFMM_EINVAL;
+    if (c->pend.on) HIPCHK(c, hipEventSynchronize(c->pend.ev[NPHASE_EV - 1]));
+    c->pend.on = false;  // an evaluation from before the reset is not counted
     std::memset(&c->st, 0, sizeof(c->st));
     return CTFMM_OK;
 }
@@ -1740,6 +1799,7 @@ ctfmm_status ctfmm_reset_stats(ctfmm_ctx* c) {
 ctfmm_status ctfmm_sync(ctfmm_ctx* c) {
     if (!c) return CTFMM_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    SCHK(finish_pending(c));
     if (c->err_flag) {
         int h = 0;
         HIPCHK(c, hipMemcpy(&h, c->err_flag, sizeof(int), hipMemcpyDeviceToHost));
@@ -1768,8 +1828,9 @@ void ctfmm_destroy(ctfmm_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (auto& x : c->side)
         if (x) (void)hipStreamDestroy(x);
-    for (auto& e : c->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto& set : c->evs)
+        for (auto& e : set)
+            if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
 }

@@ -233,3 +233,37 @@ def test_adaptive_tile_tuner_picks_a_shape():
         assert chosen in (32, 64, 128)
     finally:
         f.close()
+
+
+def test_adaptive_timing_stats_deferred():
+    """With timing on, a fixed-order evaluation returns before its timings are
+    read; they are added at the next call or when the statistics are read.
+    Three timed evaluations count three times the tree's M2L pairs, every
+    phase time is positive, and a reset drops an evaluation still pending."""
+    import torch
+    from paper_1811_06332_amd import ctfmm as F
+    xyz, q = W.plummer(3000, 7)
+    print("[case] adaptive timing stats plummer3000 p=6 leaf_max=24", flush=True)
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(np.ascontiguousarray(xyz)).to(dev)
+    Q = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
+    f = F.FMM(6, 0, "fp32", root_side=None, tree="adaptive", leaf_max=24)
+    try:
+        f.evaluate(X, Q, sync=True)
+        F.ctfmm_set_timing(f.ctx, True)
+        f.evaluate(X, Q)  # pending when the statistics are reset
+        F.ctfmm_reset_stats(f.ctx)
+        for _ in range(3):
+            f.evaluate(X, Q)
+        st, ts = f.stats(), f.tree_stats()
+        assert st["evaluations"] == 3
+        assert st["m2l_pairs"] == 3 * ts["v_pairs"] and ts["v_pairs"] > 0
+        for k in ("ms_total", "ms_tree", "ms_p2m", "ms_m2m", "ms_m2l", "ms_l2l", "ms_near"):
+            assert st[k] > 0.0, (k, st[k])
+        parts = sum(st[k] for k in ("ms_tree", "ms_p2m", "ms_m2m", "ms_convert", "ms_m2l", "ms_p2l", "ms_l2l",
+                                    "ms_near"))
+        assert abs(parts - st["ms_total"]) <= 1e-3 * st["ms_total"] + 0.05, (parts, st["ms_total"])
+        # a second read adds nothing
+        assert f.stats()["m2l_pairs"] == st["m2l_pairs"]
+    finally:
+        f.close()
