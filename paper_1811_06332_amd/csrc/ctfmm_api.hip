@@ -196,6 +196,7 @@ struct ctfmm_ctx {
     size_t mlp_sel_cap = 0, mlp_vs_cap = 0;
     int tile_forced[CTFMM_P_MAX + 1] = {};  // M2L targets per tile set by the caller (0 = tune)
     int tile_tuned[CTFMM_P_MAX + 1] = {};   // ... chosen by the tuner (0 = not yet)
+    int chunk_tuned[CTFMM_P_MAX + 1] = {};  // M2L workgroups per tile chosen by the tuner (0 = the default rule)
     hipEvent_t tev[2] = {};                 // events of the tuner
     std::vector<long long> gsig;
 
@@ -659,6 +660,15 @@ int chunks_for(size_t ntiles) {
     return (int)std::min<size_t>(8, std::max<size_t>(1, want));
 }
 
+// offset chunks per M2L tile, and the partial-sum slots they need (one per
+// chunk, and one for the X lists)
+ctfmm_status set_chunks(ctfmm_ctx* c, Forest& f, int nchunk) {
+    f.nchunk = nchunk;
+    if (!f.tiles_host.empty())
+        ACHK(grow(c, f.part, f.part_cap, (size_t)(f.nchunk + 1) * f.nn * ldm_of(f.p), false));
+    return CTFMM_OK;
+}
+
 // M2L tiles of tt targets from the (level, octant) buckets, and their tables
 ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     const int maxlev = (int)f.lev_first.size() - 1;
@@ -671,10 +681,8 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
         }
     f.tt = tt;
     const size_t ntiles = f.tiles_host.size();
-    f.nchunk = chunks_for(ntiles);
+    SCHK(set_chunks(c, f, c->chunk_tuned[f.p] ? c->chunk_tuned[f.p] : chunks_for(ntiles)));
     if (!ntiles) return CTFMM_OK;
-    // slots of part: one per offset chunk, and one for the X lists (P2L)
-    ACHK(grow(c, f.part, f.part_cap, (size_t)(f.nchunk + 1) * f.nn * ldm_of(f.p), false));
     ACHK(grow(c, f.tiles, f.tiles_cap, ntiles, false));
     ACHK(grow(c, f.tgt_tab, f.tgt_cap, (size_t)tt * ntiles, false));
     ACHK(grow(c, f.src_tab, f.src_cap, (size_t)189 * tt * ntiles, false));
@@ -700,44 +708,63 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     return CTFMM_OK;
 }
 
-// The tile-shape tuner: times three M2L launches (after a warm-up launch) of
-// every tile size the device's LDS admits on this forest's own tables and
-// returns the fastest.  The multipole buffer's contents do not matter for
-// the timing; the local expansions it writes are overwritten by the real pass.
-ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best) {
+// The tile-shape tuner: for every tile size the device's LDS admits (on this
+// forest's own tables) and, with fixed orders, every split of a tile's
+// offsets over 1 to 4 workgroups, times three runs (after a warm-up run) of
+// the M2L launch with the clear and the sum of its partial-sum slots, and
+// returns the fastest.  The multipole buffer's contents do not matter for the
+// timing; what it writes is overwritten by the real pass.
+ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
     const int prec = c->prm.precision;
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     for (auto& e : c->tev)
         if (!e) HIPCHK(c, hipEventCreate(&e));
     const void* msrc = prec == CTFMM_PREC_FP64 ? (const void*)f.aM : (const void*)f.aM32;
+    const bool fixed = order_mode_of(c, f) == 0;
+    const size_t lsz = (size_t)f.nn * ldm_of(f.p);
     float tbest = 0.f;
     *best = 32;  // fits wherever the context could be created
+    *best_chunks = 0;
     for (int tt : {32, 64, 128}) {
         if (m2l_tile_lds_bytes(f.p, prec, tt) > (size_t)max_lds) continue;
         SCHK(make_tiles(c, f, tt));
-        AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
-        double* out = f.aL;
-        if (f.nchunk > 1) {
-            ad.acc = true;
-            ad.nchunk = f.nchunk;
-            ad.chunk_stride = (size_t)f.nn * ldm_of(f.p);
-            out = f.part;
-        }
-        HIPCHK(c, m2l_adaptive(c, f, c->stream, ad, msrc, out));
-        float ms = 0.f;
-        for (int rep = 0; rep < 3; ++rep) {  // the fastest of three timed launches
-            HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
-            HIPCHK(c, m2l_adaptive(c, f, c->stream, ad, msrc, out));
-            HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
-            HIPCHK(c, hipEventSynchronize(c->tev[1]));
-            float t = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&t, c->tev[0], c->tev[1]));
-            ms = rep == 0 ? t : std::min(ms, t);
-        }
-        if (tbest == 0.f || ms < tbest) {
-            tbest = ms;
-            *best = tt;
+        const int nc_default = chunks_for(f.tiles_host.size());
+        for (int nc = 1; nc <= 4; ++nc) {
+            if (!fixed && nc > 1) break;
+            const int nchunk = fixed ? nc : nc_default;
+            SCHK(set_chunks(c, f, nchunk));
+            const int slots = nchunk + (fixed && f.tot_x > 0 ? 1 : 0);
+            AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+            double* out = f.aL;
+            if (slots > 1) {
+                ad.acc = true;
+                ad.nchunk = nchunk;
+                ad.chunk_stride = lsz;
+                out = f.part;
+            }
+            auto run = [&]() -> ctfmm_status {
+                if (slots > 1) launch_fill0(c->stream, (long long)(slots * lsz), f.part);
+                HIPCHK(c, m2l_adaptive(c, f, c->stream, ad, msrc, out));
+                if (slots > 1) launch_sum_chunks(c->stream, slots, lsz, f.part, f.aL);
+                return CTFMM_OK;
+            };
+            SCHK(run());
+            float ms = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {  // the fastest of three timed runs
+                HIPCHK(c, hipEventRecord(c->tev[0], c->stream));
+                SCHK(run());
+                HIPCHK(c, hipEventRecord(c->tev[1], c->stream));
+                HIPCHK(c, hipEventSynchronize(c->tev[1]));
+                float t = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&t, c->tev[0], c->tev[1]));
+                ms = rep == 0 ? t : std::min(ms, t);
+            }
+            if (tbest == 0.f || ms < tbest) {
+                tbest = ms;
+                *best = tt;
+                *best_chunks = fixed ? nchunk : 0;
+            }
         }
     }
     return CTFMM_OK;
@@ -948,8 +975,10 @@ tree_again:
     std::memcpy(f.hb, pw, sizeof(f.hb));
     int tt = c->tile_forced[f.p] ? c->tile_forced[f.p] : c->tile_tuned[f.p];
     if (tt == 0 && maxlev >= 2) {
-        SCHK(tune_tile(c, f, &tt));
+        int nc = 0;
+        SCHK(tune_tile(c, f, &tt, &nc));
         c->tile_tuned[f.p] = tt;
+        c->chunk_tuned[f.p] = nc;
     }
     SCHK(make_tiles(c, f, tt ? tt : 64));
     for (auto& x : c->side)
