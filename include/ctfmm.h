@@ -108,9 +108,9 @@ typedef struct ctfmm_stats_t {
     double ms_m2m;
     double ms_m2l;          /* all M2L launches (adaptive tree: the M2L kernel itself) */
     double ms_l2l;
-    double ms_near;         /* L2P + P2P (adaptive tree: L2P, the W-list multipole evaluations
-                               and the wait for the near field, whose P2P runs on a side
-                               stream from the start of the numeric pass) */
+    double ms_near;         /* L2P + P2P (adaptive tree: L2P and the wait for the near field,
+                               whose P2P and W-list multipole evaluations run on a side
+                               stream beside the expansion passes) */
     double ms_convert;      /* FP32 copies of the multipoles for the FP32/BF16 M2L modes
                                (adaptive tree: also the weighted multipoles of the W list) */
     double ms_p2l;          /* adaptive tree: the rest of the downward M2L/X-list step (local

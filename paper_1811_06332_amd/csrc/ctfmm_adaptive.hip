@@ -1532,6 +1532,20 @@ void launch_far_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const
     }
 }
 
+void launch_wlist_adaptive(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const double4* P,
+                           const double* Cm, const int32_t* woff, const int32_t* wlist, double4* F) {
+    if (nn <= 0) return;
+    switch (p) {
+#define CASE(PP)                                                                                                   \
+    case PP:                                                                                                       \
+        hipLaunchKernelGGL(k_m2p_leaf<PP>, dim3(nn), dim3(64 * MW), 0, s, boxes, t, P, Cm, woff, wlist, F);         \
+        break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#undef CASE
+        default: break;
+    }
+}
+
 // ------------------------------------------------------------------ M2L orders per pair
 
 // class of |v|^2 among the 15 occupied values (see k_mlp_decide)

@@ -176,7 +176,7 @@ struct ctfmm_ctx {
     hipStream_t ord_stream[CTFMM_P_MAX + 1] = {};  // per-order M2L launches run side by side
     hipEvent_t ord_ev[CTFMM_P_MAX + 2] = {};
     hipStream_t side[2] = {};  // the near field (P2P) and the X lists (P2L) beside the expansion passes
-    hipEvent_t side_ev[4] = {};
+    hipEvent_t side_ev[5] = {};
     // M2L order per pair (adaptive tree): 0 = the fixed order p, 1 = a table
     // by |v|^2, 2 = the network's decision per (source cell, distance class)
     int order_mode = 0;
@@ -1026,10 +1026,10 @@ ctfmm_status count_v_pairs(ctfmm_ctx* c, Forest& f) {
 }
 
 // The numeric passes of one forest (no host waits, no memsets: graph-capturable).
-// The near field (P2P) runs on a side stream from the start, and with fixed
-// orders the X lists (P2L) on another beside M2L; the main stream joins them
-// before the sum of the M2L slots and before the final sum of far and near
-// field.  ev >= 0 records the phase events ev.. on the main stream (0 start,
+// The near field (P2P) runs on a side stream from the start, followed there
+// by the W lists once their coefficients are formed, and with fixed orders the
+// X lists (P2L) on another beside M2L; the main stream joins them before the
+// sum of the M2L slots and before the final sum of far and near field.  ev >= 0 records the phase events ev.. on the main stream (0 start,
 // 1 P2M, 2 M2M, 3 conversions, 4 M2L (with the X lists when they run beside
 // it), 5 P2L, 6 L2L, 7 far field and the join with the near field; 8 and 9
 // around the M2L launch itself, or around all of the per-order M2L work).  to_F
@@ -1051,7 +1051,6 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     HIPCHK(c, hipEventRecord(c->side_ev[0], st));
     HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[0], 0));
     launch_p2p_near(c->side[0], f.n, nn, f.tr, f.a_P, f.loff, f.ulist, f.a_Fn);
-    HIPCHK(c, hipEventRecord(c->side_ev[1], c->side[0]));
     launch_p2m_nodes(st, p, 0, nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
     mark(1);
     for (int l = maxlev - 1; l >= 2; --l) launch_m2m_nodes(st, p, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
@@ -1059,7 +1058,14 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     const void* msrc = f.aM;
     if (maxlev >= 2) {
         const int f2 = f.lev_first[2];
-        if (f.tot_w > 0) launch_m2p_coef(st, p, f2, nn - f2, f.aM, c->T, f.aWc);
+        if (f.tot_w > 0) {
+            // the W lists need only the multipoles: they follow P2P on its side
+            // stream, adding into the near field
+            launch_m2p_coef(st, p, f2, nn - f2, f.aM, c->T, f.aWc);
+            HIPCHK(c, hipEventRecord(c->side_ev[4], st));
+            HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[4], 0));
+            launch_wlist_adaptive(c->side[0], p, nn, f.boxes, f.tr, f.a_P, f.aWc, f.loff + n1, f.wlist, f.a_Fn);
+        }
         if (prec != CTFMM_PREC_FP64) {
             if (rb_m2l(c, f)) launch_to_f32_kq(st, p, nn, f.aM, f.aM32);
             else launch_to_f32(st, p, nn, f.aM, f.aM32);
@@ -1151,8 +1157,9 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     mark(5);
     for (int l = 3; l <= maxlev; ++l) launch_l2l_nodes(st, p, f.lev_first[l - 1], f.lev_count[l - 1], f.tr, f.aL, c->T);
     mark(6);
-    launch_far_adaptive(st, p, f.n, nn, f.tot_w > 0, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1,
-                        f.wlist, f.a_F);
+    HIPCHK(c, hipEventRecord(c->side_ev[1], c->side[0]));  // P2P and the W lists are done
+    launch_far_adaptive(st, p, f.n, nn, false, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1, f.wlist,
+                        f.a_F);
     HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[1], 0));
     launch_add_near(st, f.n, f.a_idxs, f.a_F, f.a_Fn, to_F, phi, grad);
     mark(7);

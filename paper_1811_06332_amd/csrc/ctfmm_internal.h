@@ -285,6 +285,9 @@ void launch_far_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const
                          const int32_t* woff, const int32_t* wlist, double4* F);
 void launch_p2p_near(hipStream_t s, int n, int nn, const ATree& t, const double4* P, const int32_t* uoff,
                      const int32_t* ulist, double4* Fn);
+// the W-list multipole evaluations alone, added into F
+void launch_wlist_adaptive(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const double4* P,
+                           const double* Cm, const int32_t* woff, const int32_t* wlist, double4* F);
 void launch_add_near(hipStream_t s, int n, const int32_t* idx, double4* F, const double4* Fn, bool to_F, double* phi,
                      double* grad);
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
