@@ -119,6 +119,7 @@ struct Forest {
     size_t ordn_cap = 0, ord_tab_cap = 0, omask_cap = 0, ivl_cap = 0, ivc_cap = 0, ocnt_cap = 0, mx_cap = 0, my_cap = 0;
     const unsigned char* Kord[CTFMM_P_MAX + 1] = {};  // operators of every order <= p
     int nchunk = 1;              // M2L workgroups per tile (offset chunks)
+    bool up_early = false;       // P2M and M2M already launched by the tree build
     double* part = nullptr;      // [nchunk][nn][ldm] partial local expansions
     size_t part_cap = 0;
 };
@@ -176,7 +177,7 @@ struct ctfmm_ctx {
     hipStream_t ord_stream[CTFMM_P_MAX + 1] = {};  // per-order M2L launches run side by side
     hipEvent_t ord_ev[CTFMM_P_MAX + 2] = {};
     hipStream_t side[2] = {};  // the near field (P2P) and the X lists (P2L) beside the expansion passes
-    hipEvent_t side_ev[5] = {};
+    hipEvent_t side_ev[7] = {};
     // M2L order per pair (adaptive tree): 0 = the fixed order p, 1 = a table
     // by |v|^2, 2 = the network's decision per (source cell, distance class)
     int order_mode = 0;
@@ -774,7 +775,8 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
 // (particle, W entry) pairs and the M2L tile tables of one forest.  Waits for
 // the stream once per tree level and a few times more (sizes decide the next
 // launches).  f.p, f.nsys, f.goff_h and f.gbase_h are set by the caller.
-ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const double* q, bool explicit_box) {
+ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const double* q, bool explicit_box,
+                          bool early_up = false) {
     hipStream_t st = c->stream;
     const int n = f.n;
     const size_t nn_ = (size_t)std::max(n, 1);
@@ -895,6 +897,23 @@ tree_again:
     launch_node_geo(st, nn, f.boxes, f.tr);
     for (int l = 1; l <= maxlev; ++l) launch_nb(st, f.lev_first[l], f.lev_count[l], f.tr);
     launch_leaf_of(st, nn, f.tr, f.leaf_of);
+    for (auto& x : c->side)
+        if (!x) HIPCHK(c, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    for (auto& e : c->side_ev)
+        if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // P2M and M2M need only the nodes: with early_up they start here on a side
+    // stream, beside the list and M2L-table construction, and the numeric
+    // pass joins them
+    f.up_early = early_up;
+    if (early_up) {
+        ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm_of(f.p), false));
+        HIPCHK(c, hipEventRecord(c->side_ev[5], st));
+        HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[5], 0));
+        launch_p2m_nodes(c->side[1], f.p, 0, nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
+        for (int l = maxlev - 1; l >= 2; --l)
+            launch_m2m_nodes(c->side[1], f.p, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
+        HIPCHK(c, hipEventRecord(c->side_ev[6], c->side[1]));
+    }
 
     // U, W, X lists: count, scan, fill, order the transposed entries
     const size_t n1 = (size_t)nn + 1;
@@ -981,10 +1000,6 @@ tree_again:
         c->chunk_tuned[f.p] = nc;
     }
     SCHK(make_tiles(c, f, tt ? tt : 64));
-    for (auto& x : c->side)
-        if (!x) HIPCHK(c, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    for (auto& e : c->side_ev)
-        if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (order_mode_of(c, f) != 0 && !f.tiles_host.empty()) {
         const size_t nt = f.tiles_host.size();
         for (int k = 0; k <= f.p; ++k) SCHK(get_ops(c, k, &f.Kord[k]));
@@ -1051,9 +1066,15 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     HIPCHK(c, hipEventRecord(c->side_ev[0], st));
     HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[0], 0));
     launch_p2p_near(c->side[0], f.n, nn, f.tr, f.a_P, f.loff, f.ulist, f.a_Fn);
-    launch_p2m_nodes(st, p, 0, nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
-    mark(1);
-    for (int l = maxlev - 1; l >= 2; --l) launch_m2m_nodes(st, p, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
+    if (f.up_early) {
+        HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[6], 0));
+        mark(1);
+    } else {
+        launch_p2m_nodes(st, p, 0, nn, f.boxes, f.tr, f.a_P, c->T, f.aM);
+        mark(1);
+        for (int l = maxlev - 1; l >= 2; --l)
+            launch_m2m_nodes(st, p, f.lev_first[l], f.lev_count[l], f.tr, f.aM, c->T);
+    }
     mark(2);
     const void* msrc = f.aM;
     if (maxlev >= 2) {
@@ -1233,7 +1254,7 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
     // events: 0 start, 1 tree built, 2.. the numeric phases, then the end
     rec(c, 0);
     HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));
-    SCHK(build_forest(c, f, xyz, q, c->prm.root_side > 0.0));
+    SCHK(build_forest(c, f, xyz, q, c->prm.root_side > 0.0, true));
     rec(c, 1);
     SCHK(numeric_forest(c, f, phi, grad, 2));
     const int ev_end = NPHASE_EV - 1;
