@@ -2,8 +2,12 @@
 
     python -m paper_1811_06332_amd.profile_summary stats   RESULTS.db
     python -m paper_1811_06332_amd.profile_summary counter RESULTS.db COUNTER [COPY_BYTES]
+    python -m paper_1811_06332_amd.profile_summary tail    RESULTS.db PREFIX K
 
 `stats`: per-kernel dispatch count, total and average duration.
+`tail`: the last K dispatches (in start order) of the kernels whose name
+starts with PREFIX, and their average duration: the timed steps of a run whose
+earlier dispatches of the same kernel are warm-up and tuning launches.
 `counter`: per-kernel average of one PMC counter (e.g. FETCH_SIZE, WRITE_SIZE,
 in KiB per dispatch as rocprofv3 reports them).  With COPY_BYTES, the counter
 of the largest plain copy kernel in the run (a device-to-device copy of known
@@ -54,9 +58,24 @@ def counter(db: str, cname: str, copy_bytes: float | None = None) -> str:
     return "\n".join(out)
 
 
+def tail(db: str, prefix: str, k: int) -> str:
+    cur = sqlite3.connect(db).cursor()
+    rows = [r for r in cur.execute("select name, start, duration from kernels order by start").fetchall()
+            if _short(r[0]).startswith(prefix)]
+    last = rows[-k:]
+    if not last:
+        return f"no dispatch of {prefix}"
+    avg = sum(r[2] for r in last) / len(last)
+    names = sorted({_short(r[0]) for r in last})
+    return (f"last {len(last)} dispatches of {prefix}* (the timed steps): average {avg / 1e6:.4f} ms; "
+            f"kernel {', '.join(names)}")
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         print(stats(argv[1]))
+    elif len(argv) >= 4 and argv[0] == "tail":
+        print(tail(argv[1], argv[2], int(argv[3])))
     elif len(argv) >= 3 and argv[0] == "counter":
         print(counter(argv[1], argv[2], float(argv[3]) if len(argv) > 3 else None))
     else:
