@@ -518,6 +518,38 @@ __global__ void k_add_i32(int n, const int32_t* __restrict__ a, const int32_t* _
     if (i < n) out[i] = a[i] + b[i];
 }
 
+// Each segment [beg[g], end[g]) of in, sorted ascending into the same range of
+// out, one wavefront per segment: an entry's position is the number of entries
+// of its segment that are smaller, or equal and earlier (segments are short
+// lists of node indices; chunks of 64 entries are compared lane by lane).
+__global__ __launch_bounds__(64) void k_rank_sort(const int32_t* __restrict__ beg, const int32_t* __restrict__ end,
+                                                  const int32_t* __restrict__ in, int32_t* __restrict__ out) {
+    const int g = blockIdx.x;
+    const int b = beg[g], len = end[g] - b;
+    if (len <= 0) return;
+    const int lane = threadIdx.x;
+    for (int i0 = 0; i0 < len; i0 += 64) {
+        const int i = i0 + lane;
+        const int v = i < len ? in[b + i] : 0;
+        int rank = 0;
+        for (int j0 = 0; j0 < len; j0 += 64) {
+            const int w = j0 + lane < len ? in[b + j0 + lane] : 0;
+            const int m = min(64, len - j0);
+            for (int k = 0; k < m; ++k) {
+                const int u = __builtin_amdgcn_readlane(w, k);
+                rank += (u < v || (u == v && j0 + k < i)) ? 1 : 0;
+            }
+        }
+        if (i < len) out[b + rank] = v;
+    }
+}
+
+void launch_rank_sort(hipStream_t s, int nseg, const int32_t* beg, const int32_t* end, const int32_t* in,
+                      int32_t* out) {
+    if (nseg <= 0) return;
+    hipLaunchKernelGGL(k_rank_sort, dim3(nseg), dim3(64), 0, s, beg, end, in, out);
+}
+
 void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucnt, int32_t* wcnt, int32_t* xcnt,
                   int32_t* ufcnt, const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist,
                   int32_t* wlist, int32_t* xlist, int32_t* wfill, int32_t* ufill) {

@@ -946,27 +946,19 @@ tree_again:
     ACHK(grow(c, f.wlist, f.wlist_cap, (size_t)tot[1], false));
     ACHK(grow(c, f.xlist, f.xlist_cap, (size_t)tot[2], false));
     launch_lists(st, true, nn, f.tr, uc, wc, xc, ufc, uo, wo, xo, f.ulist, f.wlist, f.xlist, wfl, ufl);
-    // the transposed entries in ascending node order: segmented radix sorts of
-    // the W lists and of the finer part of each U list ([uoff + own, uoff'))
+    // the transposed entries in ascending node order: segment sorts of the W
+    // lists and of the finer part of each U list ([uoff + own, uoff'))
     {
-        int bits = 1;
-        while ((1ll << bits) < (long long)nn) ++bits;
         ACHK(grow(c, f.lsort, f.lsort_cap, (size_t)std::max(tot[0], tot[1]) + 1, false));
         int32_t* ubeg = ut;  // the U totals are no longer needed
         launch_add_i32(st, nn, uo, uc, ubeg);
         if (tot[0] > 0) {
             HIPCHK(c, hipMemcpyAsync(f.lsort, f.ulist, (size_t)tot[0] * 4, hipMemcpyDeviceToDevice, st));
-            SCHK(cub_run(c, [&](void* t, size_t& b) {
-                return hipcub::DeviceSegmentedRadixSort::SortKeys(t, b, f.ulist, f.lsort, tot[0], nn, ubeg, uo + 1, 0,
-                                                                  bits, st);
-            }));
+            launch_rank_sort(st, nn, ubeg, uo + 1, f.ulist, f.lsort);
             HIPCHK(c, hipMemcpyAsync(f.ulist, f.lsort, (size_t)tot[0] * 4, hipMemcpyDeviceToDevice, st));
         }
         if (tot[1] > 0) {
-            SCHK(cub_run(c, [&](void* t, size_t& b) {
-                return hipcub::DeviceSegmentedRadixSort::SortKeys(t, b, f.wlist, f.lsort, tot[1], nn, wo, wo + 1, 0,
-                                                                  bits, st);
-            }));
+            launch_rank_sort(st, nn, wo, wo + 1, f.wlist, f.lsort);
             HIPCHK(c, hipMemcpyAsync(f.wlist, f.lsort, (size_t)tot[1] * 4, hipMemcpyDeviceToDevice, st));
         }
     }

@@ -264,6 +264,9 @@ void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucn
                   int32_t* ufcnt, const int32_t* uoff, const int32_t* woff, const int32_t* xoff, int32_t* ulist,
                   int32_t* wlist, int32_t* xlist, int32_t* wfill, int32_t* ufill);
 void launch_add_i32(hipStream_t s, int n, const int32_t* a, const int32_t* b, int32_t* out);
+// segments [beg[g], end[g]) of in sorted ascending into out (one wavefront per segment)
+void launch_rank_sort(hipStream_t s, int nseg, const int32_t* beg, const int32_t* end, const int32_t* in,
+                      int32_t* out);
 void launch_lvloct(hipStream_t s, int nn, const ATree& t, uint32_t* k, int32_t* v);
 void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, int32_t* bend);
 void launch_tile_keys(hipStream_t s, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
