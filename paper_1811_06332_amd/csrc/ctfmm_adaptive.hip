@@ -598,30 +598,48 @@ void launch_buckets(hipStream_t s, int nn, const uint32_t* sk, int32_t* bstart, 
     hipLaunchKernelGGL(k_buckets, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, sk, bstart, bend);
 }
 
-// One wave per (tile, offset): the targets of the tile (tt of them, lanes
-// take slots lane, lane + 64) and the source cell of the offset for each
-// (child q of the parent's neighbour u, or -1).  vcount = sources that exist.
+// One wavefront per tile: the targets of the tile (tt of them, 64 slots per
+// pass) and, for each offset, the source cell of each target (child q of the
+// parent's neighbour u, or -1); vcount = sources that exist per (tile,
+// offset).  An offset of octant o is one (u, q) pair (qu_list[o][iv] =
+// u | q << 5); the wavefront walks the 27 neighbours u of each target's parent
+// once, reads their 8 children, and files child q under the offset of (u, q)
+// (inverse table in LDS), so the loads per target are independent and few.
 __global__ __launch_bounds__(64) void k_m2l_tables(int tt, const int4* __restrict__ tiles,
                                                    const int32_t* __restrict__ sorted, ATree t,
                                                    const int16_t* __restrict__ qu_list, int32_t* __restrict__ tgt_tab,
                                                    int32_t* __restrict__ src_tab, int32_t* __restrict__ vcount) {
-    const int tile = blockIdx.x / 189, iv = blockIdx.x % 189;
+    const int tile = blockIdx.x;
     const int lane = threadIdx.x;
     const int4 d = tiles[tile];  // (octant, first sorted position, count, level)
-    const int qu = qu_list[d.x * 189 + iv];
-    int cnt = 0;
-    for (int r = lane; r < tt; r += 64) {
+    __shared__ int16_t inv[256];
+    __shared__ int cnt[189];
+    for (int x = lane; x < 256; x += 64) inv[x] = -1;
+    for (int x = lane; x < 189; x += 64) cnt[x] = 0;
+    __syncthreads();
+    for (int x = lane; x < 189; x += 64) inv[qu_list[d.x * 189 + x]] = (int16_t)x;
+    __syncthreads();
+    for (int r0 = 0; r0 < tt; r0 += 64) {
+        const int r = r0 + lane;
         const int tg = r < d.z ? sorted[d.y + r] : -1;
-        if (iv == 0) tgt_tab[tt * (size_t)tile + r] = tg;
-        int src = -1;
-        if (tg >= 0) {
-            const int Q = t.nb[27 * (size_t)t.par[tg] + (qu & 31)];
-            if (Q >= 0 && !node_leaf(t.info[Q])) src = t.child[8 * (size_t)Q + (qu >> 5)];
+        if (r < tt) tgt_tab[tt * (size_t)tile + r] = tg;
+        const int par = tg >= 0 ? t.par[tg] : -1;
+        for (int u = 0; u < 27; ++u) {
+            const int Q = par >= 0 ? t.nb[27 * (size_t)par + u] : -1;
+            const bool inner = Q >= 0 && !node_leaf(t.info[Q]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int iv = inv[u | (q << 5)];  // the same in every lane
+                if (iv < 0) continue;
+                const int src = inner ? t.child[8 * (size_t)Q + q] : -1;
+                if (r < tt) src_tab[(189 * (size_t)tile + iv) * tt + r] = src;
+                const int c = __popcll(__ballot(src >= 0));
+                if (lane == 0) cnt[iv] += c;
+            }
         }
-        src_tab[(189 * (size_t)tile + iv) * tt + r] = src;
-        cnt += __popcll(__ballot(src >= 0));
     }
-    if (lane == 0) vcount[blockIdx.x] = cnt;
+    __syncthreads();
+    for (int x = lane; x < 189; x += 64) vcount[189 * (size_t)tile + x] = cnt[x];
 }
 
 // Sort key of an M2L tile: the parent of its first target, then the octant.
@@ -657,8 +675,8 @@ void launch_gather_int4(hipStream_t s, int n, const int32_t* idx, const int4* in
 void launch_m2l_tables(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* sorted, const ATree& t,
                        const int16_t* qu_list, int32_t* tgt_tab, int32_t* src_tab, int32_t* vcount) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_m2l_tables, dim3(189 * ntiles), dim3(64), 0, s, tt, tiles, sorted, t, qu_list, tgt_tab,
-                       src_tab, vcount);
+    hipLaunchKernelGGL(k_m2l_tables, dim3(ntiles), dim3(64), 0, s, tt, tiles, sorted, t, qu_list, tgt_tab, src_tab,
+                       vcount);
 }
 
 // ------------------------------------------------------------------ P2M, M2M, L2L on node lists
