@@ -1142,11 +1142,15 @@ __device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, 
 
 
 // Far field of one sorted particle s (one thread each) from the local
-// expansion of its leaf B (Eq. L2P), into F[s]; zero for leaves above level 2.
+// expansion of its leaf B (Eq. L2P; zero for leaves above level 2), plus its
+// near field Fn[s]: the total goes to phi and grad in input order, or with
+// to_F back into F[s].
 template <int P>
 __global__ __launch_bounds__(256) void k_l2p_adaptive(int n, const ABox* __restrict__ boxes, ATree t, const int32_t* __restrict__ leaf_of,
                                                       const double4* __restrict__ Pt, const double* __restrict__ L,
-                                                      double4* __restrict__ F) {
+                                                      double4* __restrict__ F, const double4* __restrict__ Fn,
+                                                      const int32_t* __restrict__ idx, bool to_F,
+                                                      double* __restrict__ phi, double* __restrict__ grad) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int B = leaf_of[s];
@@ -1161,7 +1165,19 @@ __global__ __launch_bounds__(256) void k_l2p_adaptive(int n, const ABox* __restr
         const double ih2 = 1.0 / (G.h * G.h);
         out = make_double4(lf / G.h, lx * ih2, ly * ih2, lz * ih2);
     }
-    F[s] = out;
+    const double4 b = Fn[s];
+    const double4 v = make_double4(out.x + b.x, out.y + b.y, out.z + b.z, out.w + b.w);
+    if (to_F) {
+        F[s] = v;
+        return;
+    }
+    const size_t o = (size_t)idx[s];
+    if (phi) phi[o] = v.x;
+    if (grad) {
+        grad[3 * o] = v.y;
+        grad[3 * o + 1] = v.z;
+        grad[3 * o + 2] = v.w;
+    }
 }
 
 // A wave-uniform zero that depends on dep0, dep1 and dep2: loads at
@@ -1499,34 +1515,6 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(ATree t, const double4* __restr
     }
 }
 
-// far field F plus near field Fn (sorted order) -> phi, grad (input order),
-// or with to_F back into F
-__global__ __launch_bounds__(256) void k_add_near(int n, const int32_t* __restrict__ idx, double4* __restrict__ F,
-                                                  const double4* __restrict__ Fn, bool to_F, double* __restrict__ phi,
-                                                  double* __restrict__ grad) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double4 a = F[s], b = Fn[s];
-    const double4 v = make_double4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
-    if (to_F) {
-        F[s] = v;
-        return;
-    }
-    const size_t o = (size_t)idx[s];
-    if (phi) phi[o] = v.x;
-    if (grad) {
-        grad[3 * o] = v.y;
-        grad[3 * o + 1] = v.z;
-        grad[3 * o + 2] = v.w;
-    }
-}
-
-void launch_add_near(hipStream_t s, int n, const int32_t* idx, double4* F, const double4* Fn, bool to_F, double* phi,
-                     double* grad) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_add_near, dim3(cdiv(n, 256)), dim3(256), 0, s, n, idx, F, Fn, to_F, phi, grad);
-}
-
 // F (sorted order) -> phi, grad (input order)
 __global__ __launch_bounds__(256) void k_scatter_out(int n, const int32_t* __restrict__ idx,
                                                      const double4* __restrict__ F, double* __restrict__ phi,
@@ -1567,14 +1555,16 @@ void launch_p2p_near(hipStream_t s, int n, int nn, const ATree& t, const double4
 
 void launch_far_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
                          const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
-                         const int32_t* woff, const int32_t* wlist, double4* F) {
+                         const int32_t* woff, const int32_t* wlist, double4* F, double4* Fn, const int32_t* idx,
+                         bool to_F, double* phi, double* grad) {
     if (n <= 0) return;
     const dim3 grid(cdiv(n, 256)), blk(256);
     switch (p) {
 #define CASE(PP)                                                                                                  \
     case PP:                                                                                                      \
-        hipLaunchKernelGGL(k_l2p_adaptive<PP>, grid, blk, 0, s, n, boxes, t, leaf_of, P, L, F);                     \
-        if (wlists) hipLaunchKernelGGL(k_m2p_leaf<PP>, dim3(nn), dim3(64 * MW), 0, s, boxes, t, P, Cm, woff, wlist, F);  \
+        if (wlists) hipLaunchKernelGGL(k_m2p_leaf<PP>, dim3(nn), dim3(64 * MW), 0, s, boxes, t, P, Cm, woff, wlist, Fn); \
+        hipLaunchKernelGGL(k_l2p_adaptive<PP>, grid, blk, 0, s, n, boxes, t, leaf_of, P, L, F, Fn, idx, to_F, phi,     \
+                           grad);                                                                                  \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE

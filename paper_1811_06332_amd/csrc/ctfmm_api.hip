@@ -1171,10 +1171,9 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     for (int l = 3; l <= maxlev; ++l) launch_l2l_nodes(st, p, f.lev_first[l - 1], f.lev_count[l - 1], f.tr, f.aL, c->T);
     mark(6);
     HIPCHK(c, hipEventRecord(c->side_ev[1], c->side[0]));  // P2P and the W lists are done
-    launch_far_adaptive(st, p, f.n, nn, false, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1, f.wlist,
-                        f.a_F);
     HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[1], 0));
-    launch_add_near(st, f.n, f.a_idxs, f.a_F, f.a_Fn, to_F, phi, grad);
+    launch_far_adaptive(st, p, f.n, nn, false, f.boxes, f.tr, f.leaf_of, f.a_P, f.aL, f.aWc, f.loff + n1, f.wlist,
+                        f.a_F, f.a_Fn, f.a_idxs, to_F, phi, grad);
     mark(7);
     HIPCHK(c, hipGetLastError());
     return CTFMM_OK;

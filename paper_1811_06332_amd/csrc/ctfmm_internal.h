@@ -283,16 +283,17 @@ void launch_p2l(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t,
                 const double4* P, const DevTables& T, double* L);
 void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M, const DevTables& T, double* Cm);
 size_t m2p_coef_ld(int p);  // row stride of the W-list coefficient rows
+// the W lists (wlists: added into Fn, before) and L2P, whose far field plus
+// the near field Fn goes to phi and grad in input order (or with to_F to F)
 void launch_far_adaptive(hipStream_t s, int p, int n, int nn, bool wlists, const ABox* boxes, const ATree& t,
                          const int32_t* leaf_of, const double4* P, const double* L, const double* Cm,
-                         const int32_t* woff, const int32_t* wlist, double4* F);
+                         const int32_t* woff, const int32_t* wlist, double4* F, double4* Fn, const int32_t* idx,
+                         bool to_F, double* phi, double* grad);
 void launch_p2p_near(hipStream_t s, int n, int nn, const ATree& t, const double4* P, const int32_t* uoff,
                      const int32_t* ulist, double4* Fn);
 // the W-list multipole evaluations alone, added into F
 void launch_wlist_adaptive(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const double4* P,
                            const double* Cm, const int32_t* woff, const int32_t* wlist, double4* F);
-void launch_add_near(hipStream_t s, int n, const int32_t* idx, double4* F, const double4* Fn, bool to_F, double* phi,
-                     double* grad);
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
 
 // ---- expansion orders per pair (ctfmm_adaptive.hip, ctfmm_mlp.hip) ----
