@@ -351,8 +351,13 @@ __global__ __launch_bounds__(64) void k_split(int level, int first, int count, i
 
 // children of the split nodes of a level, at next_first + (inclusive scan - 1)
 __global__ void k_emit(int level, int first, int count, int next_first, const int32_t* __restrict__ flag,
-                       const int32_t* __restrict__ incl, const int32_t* __restrict__ cstart, ATree t) {
+                       const int32_t* __restrict__ incl, const int32_t* __restrict__ cstart, ATree t,
+                       int* __restrict__ host, const int32_t* __restrict__ deep) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0 && host) {  // the next level's node count (and the depth check) for the host, in pinned memory
+        host[0] = incl[8 * count - 1];
+        if (deep) host[1] = *deep;
+    }
     if (j >= 8 * count) return;
     if (!flag[j]) return;
     const int i = j >> 3, o = j & 7;
@@ -381,9 +386,9 @@ void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, 
 }
 
 void launch_emit(hipStream_t s, int level, int first, int count, int next_first, const int32_t* flag,
-                 const int32_t* incl, const int32_t* cstart, const ATree& t) {
+                 const int32_t* incl, const int32_t* cstart, const ATree& t, int* host, const int32_t* deep) {
     hipLaunchKernelGGL(k_emit, dim3(cdiv(8ll * count, 256)), dim3(256), 0, s, level, first, count, next_first, flag,
-                       incl, cstart, t);
+                       incl, cstart, t, host, deep);
 }
 
 // neighbour tables of one level (level >= 1) from the parents' tables

@@ -142,6 +142,7 @@ struct ctfmm_ctx {
     int16_t* offlist = nullptr;    // [8][189] offset slots of each target octant
     unsigned char* zero_row = nullptr;  // a zero source row (out-of-domain sources)
     int* pinned = nullptr;              // pinned host words for small device-to-host reads
+    int* pinned_dev = nullptr;          // their address for kernels
     float* M32 = nullptr;          // FP32 copy of one level's multipoles (FP32/BF16 modes)
 
     // workspace, grown on demand
@@ -551,8 +552,15 @@ bool grow_nodes(ctfmm_ctx* c, Forest& f, size_t need) {
 
 // the pinned host words (at least 1024), allocated on first use
 int* pinned_words(ctfmm_ctx* c) {
-    if (!c->pinned && hipHostMalloc((void**)&c->pinned, 1024 * sizeof(int), hipHostMallocDefault) != hipSuccess)
-        c->pinned = nullptr;
+    if (!c->pinned) {
+        if (hipHostMalloc((void**)&c->pinned, 1024 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            c->pinned = nullptr;
+        } else if (hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0) != hipSuccess) {
+            (void)hipHostFree(c->pinned);
+            c->pinned = nullptr;
+            c->pinned_dev = nullptr;
+        }
+    }
     return c->pinned;
 }
 
@@ -869,13 +877,13 @@ tree_again:
         // the children go to [total, total + nnext) with nnext <= m: they are
         // emitted before the host learns nnext
         ACHK(grow_nodes(c, f, (size_t)total + m));
-        launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr);
         int* pw = pinned_words(c);
         if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
         const int nw = (l == 0 && !sorted_full) ? 2 : 1;  // level 0 also reads the depth check
         arm_words(pw, nw);
-        HIPCHK(c, hipMemcpyAsync(pw, f.sincl + m - 1, sizeof(int), hipMemcpyDeviceToHost, st));
-        if (nw == 2) HIPCHK(c, hipMemcpyAsync(pw + 1, f.deep, sizeof(int), hipMemcpyDeviceToHost, st));
+        // k_emit writes the count (and the depth check) into the pinned words
+        launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr, c->pinned_dev,
+                    nw == 2 ? f.deep : nullptr);
         SCHK(wait_words(c, pw, nw));
         if (nw == 2 && pw[1] != 0) {
             SCHK(full_sort());

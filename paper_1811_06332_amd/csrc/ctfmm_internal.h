@@ -256,8 +256,10 @@ void launch_deep_check(hipStream_t s, int n, const ASys& sy, const uint32_t* k32
 void launch_roots(hipStream_t s, const ASys& sy, const ATree& t);
 void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, const uint64_t* keys, const ATree& t,
                   int32_t* flag, int32_t* cstart);
+// also writes the next level's node count to host[0] (and *deep to host[1]
+// when deep is given), host being device-accessible pinned memory (or null)
 void launch_emit(hipStream_t s, int level, int first, int count, int next_first, const int32_t* flag,
-                 const int32_t* incl, const int32_t* cstart, const ATree& t);
+                 const int32_t* incl, const int32_t* cstart, const ATree& t, int* host, const int32_t* deep);
 void launch_nb(hipStream_t s, int first, int count, const ATree& t);
 void launch_leaf_of(hipStream_t s, int nn, const ATree& t, int32_t* leaf_of);
 void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucnt, int32_t* wcnt, int32_t* xcnt,
