@@ -309,9 +309,11 @@ void launch_roots(hipStream_t s, const ASys& sy, const ATree& t) {
 // the sorted keys (8 probes per step, so about log8 of the node's size
 // dependent loads).  flag[8i+o] = 1 for every non-empty octant of a split
 // node, cstart[8i+o] its first particle.
-__device__ __forceinline__ void split_node(int level, int i, int first, int leaf_max,
-                                           const uint64_t* __restrict__ keys, const ATree& t,
-                                           int32_t* __restrict__ flag, int32_t* __restrict__ cstart) {
+__global__ __launch_bounds__(64) void k_split(int level, int first, int count, int leaf_max,
+                                              const uint64_t* __restrict__ keys, ATree t, int32_t* __restrict__ flag,
+                                              int32_t* __restrict__ cstart) {
+    const int i = blockIdx.x;
+    if (i >= count) return;
     const int lane = threadIdx.x;
     const int g = first + i;
     const int b = t.pb[g], e = t.pe[g];
@@ -347,33 +349,16 @@ __device__ __forceinline__ void split_node(int level, int i, int first, int leaf
     }
 }
 
-__global__ __launch_bounds__(64) void k_split(int level, int first, int count, int leaf_max,
-                                              const uint64_t* __restrict__ keys, ATree t, int32_t* __restrict__ flag,
-                                              int32_t* __restrict__ cstart) {
-    const int i = blockIdx.x;
-    if (i >= count) return;
-    split_node(level, i, first, leaf_max, keys, t, flag, cstart);
-}
-
-// The same with the level's first node and count read from lv[2 level],
-// lv[2 level + 1] (written by the previous level's k_emit_dev): one
-// wavefront per node over a grid-stride loop up to cap, the bound the host
-// sized the buffers for; the flags of nodes in [count, cap) are cleared so
-// that a scan over 8 cap entries ends with the level's child count.
-__global__ __launch_bounds__(64) void k_split_dev(int level, const int32_t* __restrict__ lv, int cap, int leaf_max,
-                                                  const uint64_t* __restrict__ keys, ATree t,
-                                                  int32_t* __restrict__ flag, int32_t* __restrict__ cstart) {
-    const int first = lv[2 * level], count = lv[2 * level + 1];
-    for (int i = blockIdx.x; i < cap; i += gridDim.x) {
-        if (i < count) split_node(level, i, first, leaf_max, keys, t, flag, cstart);
-        else if (threadIdx.x < 8) flag[8 * i + threadIdx.x] = 0;
-    }
-}
-
 // children of the split nodes of a level, at next_first + (inclusive scan - 1)
-__device__ __forceinline__ void emit_child(int level, int j, int first, int next_first,
-                                           const int32_t* __restrict__ flag, const int32_t* __restrict__ incl,
-                                           const int32_t* __restrict__ cstart, const ATree& t) {
+__global__ void k_emit(int level, int first, int count, int next_first, const int32_t* __restrict__ flag,
+                       const int32_t* __restrict__ incl, const int32_t* __restrict__ cstart, ATree t,
+                       int* __restrict__ host, const int32_t* __restrict__ deep) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0 && host) {  // the next level's node count (and the depth check) for the host, in pinned memory
+        host[0] = incl[8 * count - 1];
+        if (deep) host[1] = *deep;
+    }
+    if (j >= 8 * count) return;
     if (!flag[j]) return;
     const int i = j >> 3, o = j & 7;
     const int g = first + i;
@@ -393,70 +378,6 @@ __device__ __forceinline__ void emit_child(int level, int j, int first, int next
     t.info[c] = level + 1;
     t.sys[c] = t.sys[g];
     t.child[8 * (size_t)g + o] = c;
-}
-
-__global__ void k_emit(int level, int first, int count, int next_first, const int32_t* __restrict__ flag,
-                       const int32_t* __restrict__ incl, const int32_t* __restrict__ cstart, ATree t,
-                       int* __restrict__ host, const int32_t* __restrict__ deep) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0 && host) {  // the next level's node count (and the depth check) for the host, in pinned memory
-        host[0] = incl[8 * count - 1];
-        if (deep) host[1] = *deep;
-    }
-    if (j >= 8 * count) return;
-    emit_child(level, j, first, next_first, flag, incl, cstart, t);
-}
-
-// The same with first and count from lv (grid-stride); it stores the next
-// level's first node and count in lv[2 level + 2], lv[2 level + 3].
-__global__ void k_emit_dev(int level, int32_t* __restrict__ lv, const int32_t* __restrict__ flag,
-                           const int32_t* __restrict__ incl, const int32_t* __restrict__ cstart, ATree t) {
-    const int first = lv[2 * level], count = lv[2 * level + 1];
-    const int next_first = first + count;
-    const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j0 == 0) {
-        lv[2 * level + 2] = next_first;
-        lv[2 * level + 3] = count > 0 ? incl[8 * count - 1] : 0;
-    }
-    for (int j = j0; j < 8 * count; j += gridDim.x * blockDim.x)
-        emit_child(level, j, first, next_first, flag, incl, cstart, t);
-}
-
-// lv[0..1] = (0, nsys) and every later level empty until its parent level
-// is emitted
-__global__ void k_levels_init(int nsys, int n, int32_t* __restrict__ lv) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) lv[j] = j == 1 ? nsys : 0;
-}
-
-// host[0, n) = lv[0, n) and host[n] = *deep, into pinned host memory
-__global__ void k_levels_out(int n, const int32_t* __restrict__ lv, const int32_t* __restrict__ deep,
-                             int* __restrict__ host) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) host[j] = lv[j];
-    if (j == n) host[n] = *deep;
-}
-
-void launch_split_dev(hipStream_t s, int level, const int32_t* lv, int cap, int leaf_max, const uint64_t* keys,
-                      const ATree& t, int32_t* flag, int32_t* cstart) {
-    if (cap <= 0) return;
-    hipLaunchKernelGGL(k_split_dev, dim3((unsigned)std::min(cap, 32768)), dim3(64), 0, s, level, lv, cap, leaf_max,
-                       keys, t, flag, cstart);
-}
-
-void launch_emit_dev(hipStream_t s, int level, int32_t* lv, int cap, const int32_t* flag, const int32_t* incl,
-                     const int32_t* cstart, const ATree& t) {
-    if (cap <= 0) return;
-    hipLaunchKernelGGL(k_emit_dev, dim3((unsigned)std::min<long long>(cdiv(8ll * cap, 256), 1024)), dim3(256), 0, s,
-                       level, lv, flag, incl, cstart, t);
-}
-
-void launch_levels_init(hipStream_t s, int nsys, int n, int32_t* lv) {
-    hipLaunchKernelGGL(k_levels_init, dim3(cdiv(n, 64)), dim3(64), 0, s, nsys, n, lv);
-}
-
-void launch_levels_out(hipStream_t s, int n, const int32_t* lv, const int32_t* deep, int* host) {
-    hipLaunchKernelGGL(k_levels_out, dim3(cdiv(n + 1, 64)), dim3(64), 0, s, n, lv, deep, host);
 }
 
 void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, const uint64_t* keys, const ATree& t,

@@ -51,8 +51,7 @@ struct Forest {
     uint32_t* k32 = nullptr;   // top 32 key bits
     uint32_t* k32s = nullptr;
     int32_t* deep = nullptr;   // set when the tree goes deeper than the 32-bit sort orders
-    int32_t* lv = nullptr;     // (first node, count) per level while the levels are built on the device
-    size_t k32_cap = 0, k32s_cap = 0, deep_cap = 0, lv_cap = 0;
+    size_t k32_cap = 0, k32s_cap = 0, deep_cap = 0;
     int32_t* a_idx = nullptr;
     int32_t* a_idxs = nullptr;
     int32_t* leaf_of = nullptr;
@@ -826,8 +825,9 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     // The particles are sorted by the top 32 key bits (4 radix passes instead
     // of 8), which orders every cell down to level 10, and the full keys are
     // recomputed in sorted order.  A tree that goes deeper (some level-10 cell
-    // holds more than leaf_max particles) is detected with the level counts;
-    // the particles are then sorted on all 63 bits and the tree built again.
+    // holds more than leaf_max particles) is detected with the first level's
+    // count; the particles are then sorted on all 63 bits and the tree built
+    // again.
     if (f.nsys == 1) {
         SCHK(cub_run(c, [&](void* t, size_t& b) {
             return hipcub::DeviceRadixSort::SortPairs(t, b, f.k32, f.k32s, f.a_idx, f.a_idxs, n, 0, 32, st);
@@ -858,108 +858,49 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     };
     bool sorted_full = false;
 
-    // Trees, level by level (level 0 holds one root per system).  In the
-    // 32-bit order no level deeper than K32 is split unless the depth check
-    // fires, so the levels 0..K32 are built without host reads: a split node
-    // holds more than leaf_max particles, so a level has at most
-    // n / (leaf_max + 1) of them and the next level at most 8 times as many
-    // nodes, and the node and scan buffers are sized for that bound.  The
-    // level counts come back once, with the depth check.
-    constexpr int K32 = 10;
-    size_t lcap[K32 + 2];
-    size_t capsum = 0;
-    {
-        const size_t nsplit = (size_t)n / ((size_t)c->prm.leaf_max + 1);
-        lcap[0] = (size_t)f.nsys;
-        for (int l = 0; l <= K32; ++l) lcap[l + 1] = 8 * std::min(lcap[l], nsplit);
-        for (int l = 0; l <= K32 + 1; ++l) capsum += lcap[l];
-    }
-    if (capsum <= ((size_t)1 << 27)) {
-        size_t mmax = 0;
-        for (int l = 0; l <= K32; ++l) mmax = std::max(mmax, 8 * lcap[l]);
-        ACHK(grow_nodes(c, f, capsum));
-        ACHK(grow(c, f.sflag, f.sflag_cap, mmax, false));
-        ACHK(grow(c, f.sincl, f.sincl_cap, mmax, false));
-        ACHK(grow(c, f.scstart, f.scstart_cap, mmax, false));
-        constexpr int NLV = 2 * (K32 + 2);
-        ACHK(grow(c, f.lv, f.lv_cap, NLV, false));
+    // trees, level by level (level 0 holds one root per system)
+    ACHK(grow_nodes(c, f, (size_t)f.nsys));
+tree_again:
+    launch_roots(st, sy, f.tr);
+    f.lev_first.assign(1, 0);
+    f.lev_count.assign(1, f.nsys);
+    int first = 0, count = f.nsys, total = f.nsys;
+    for (int l = 0;; ++l) {
+        const size_t m = 8 * (size_t)count;
+        ACHK(grow(c, f.sflag, f.sflag_cap, m, false));
+        ACHK(grow(c, f.sincl, f.sincl_cap, m, false));
+        ACHK(grow(c, f.scstart, f.scstart_cap, m, false));
+        launch_split(st, l, first, count, c->prm.leaf_max, f.k64s, f.tr, f.sflag, f.scstart);
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceScan::InclusiveSum(t, b, f.sflag, f.sincl, (int)m, st);
+        }));
+        // the children go to [total, total + nnext) with nnext <= m: they are
+        // emitted before the host learns nnext
+        ACHK(grow_nodes(c, f, (size_t)total + m));
         int* pw = pinned_words(c);
         if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
-        launch_roots(st, sy, f.tr);
-        launch_levels_init(st, f.nsys, NLV, f.lv);
-        for (int l = 0; l <= K32; ++l) {
-            const int cap = (int)lcap[l];
-            if (cap == 0) break;
-            launch_split_dev(st, l, f.lv, cap, c->prm.leaf_max, f.k64s, f.tr, f.sflag, f.scstart);
-            SCHK(cub_run(c, [&](void* t, size_t& b) {
-                return hipcub::DeviceScan::InclusiveSum(t, b, f.sflag, f.sincl, 8 * cap, st);
-            }));
-            launch_emit_dev(st, l, f.lv, cap, f.sflag, f.sincl, f.scstart, f.tr);
+        const int nw = (l == 0 && !sorted_full) ? 2 : 1;  // level 0 also reads the depth check
+        arm_words(pw, nw);
+        // k_emit writes the count (and the depth check) into the pinned words
+        launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr, c->pinned_dev,
+                    nw == 2 ? f.deep : nullptr);
+        SCHK(wait_words(c, pw, nw));
+        if (nw == 2 && pw[1] != 0) {
+            SCHK(full_sort());
+            sorted_full = true;
+            goto tree_again;
         }
-        arm_words(pw, NLV + 1);
-        launch_levels_out(st, NLV, f.lv, f.deep, c->pinned_dev);
-        HIPCHK(c, hipGetLastError());
-        SCHK(wait_words(c, pw, NLV + 1));
-        if (pw[NLV] == 0) {
-            f.lev_first.clear();
-            f.lev_count.clear();
-            int total = 0;
-            for (int l = 0; l <= K32 + 1 && pw[2 * l + 1] > 0; ++l) {
-                f.lev_first.push_back(pw[2 * l]);
-                f.lev_count.push_back(pw[2 * l + 1]);
-                total += pw[2 * l + 1];
-            }
-            f.nn = total;
-            goto tree_done;
-        }
-        SCHK(full_sort());
-        sorted_full = true;
+        const int nnext = pw[0];
+        if (nnext == 0) break;
+        first = total;
+        count = nnext;
+        total += nnext;
+        f.lev_first.push_back(first);
+        f.lev_count.push_back(count);
     }
-    {
-        ACHK(grow_nodes(c, f, (size_t)f.nsys));
-tree_again:
-        launch_roots(st, sy, f.tr);
-        f.lev_first.assign(1, 0);
-        f.lev_count.assign(1, f.nsys);
-        int first = 0, count = f.nsys, total = f.nsys;
-        for (int l = 0;; ++l) {
-            const size_t m = 8 * (size_t)count;
-            ACHK(grow(c, f.sflag, f.sflag_cap, m, false));
-            ACHK(grow(c, f.sincl, f.sincl_cap, m, false));
-            ACHK(grow(c, f.scstart, f.scstart_cap, m, false));
-            launch_split(st, l, first, count, c->prm.leaf_max, f.k64s, f.tr, f.sflag, f.scstart);
-            SCHK(cub_run(c, [&](void* t, size_t& b) {
-                return hipcub::DeviceScan::InclusiveSum(t, b, f.sflag, f.sincl, (int)m, st);
-            }));
-            // the children go to [total, total + nnext) with nnext <= m: they are
-            // emitted before the host learns nnext
-            ACHK(grow_nodes(c, f, (size_t)total + m));
-            int* pw = pinned_words(c);
-            if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
-            const int nw = (l == 0 && !sorted_full) ? 2 : 1;  // level 0 also reads the depth check
-            arm_words(pw, nw);
-            // k_emit writes the count (and the depth check) into the pinned words
-            launch_emit(st, l, first, count, total, f.sflag, f.sincl, f.scstart, f.tr, c->pinned_dev,
-                        nw == 2 ? f.deep : nullptr);
-            SCHK(wait_words(c, pw, nw));
-            if (nw == 2 && pw[1] != 0) {
-                SCHK(full_sort());
-                sorted_full = true;
-                goto tree_again;
-            }
-            const int nnext = pw[0];
-            if (nnext == 0) break;
-            first = total;
-            count = nnext;
-            total += nnext;
-            f.lev_first.push_back(first);
-            f.lev_count.push_back(count);
-        }
-        HIPCHK(c, hipGetLastError());
-        f.nn = total;
-    }
-tree_done:
-    const int nn = f.nn;
+    HIPCHK(c, hipGetLastError());
+    const int nn = total;
+    f.nn = nn;
     const int maxlev = (int)f.lev_first.size() - 1;
     launch_node_geo(st, nn, f.boxes, f.tr);
     for (int l = 1; l <= maxlev; ++l) launch_nb(st, f.lev_first[l], f.lev_count[l], f.tr);

@@ -260,17 +260,6 @@ void launch_split(hipStream_t s, int level, int first, int count, int leaf_max, 
 // when deep is given), host being device-accessible pinned memory (or null)
 void launch_emit(hipStream_t s, int level, int first, int count, int next_first, const int32_t* flag,
                  const int32_t* incl, const int32_t* cstart, const ATree& t, int* host, const int32_t* deep);
-// The same two steps with each level's first node and count on the device
-// (lv[2 level], lv[2 level + 1]), in grid-stride kernels bounded by cap
-// nodes; k_emit_dev stores the next level's pair.  levels_init sets level 0
-// to (0, nsys) and the rest empty; levels_out copies lv[0, n) and the depth
-// check into pinned host words.
-void launch_split_dev(hipStream_t s, int level, const int32_t* lv, int cap, int leaf_max, const uint64_t* keys,
-                      const ATree& t, int32_t* flag, int32_t* cstart);
-void launch_emit_dev(hipStream_t s, int level, int32_t* lv, int cap, const int32_t* flag, const int32_t* incl,
-                     const int32_t* cstart, const ATree& t);
-void launch_levels_init(hipStream_t s, int nsys, int n, int32_t* lv);
-void launch_levels_out(hipStream_t s, int n, const int32_t* lv, const int32_t* deep, int* host);
 void launch_nb(hipStream_t s, int first, int count, const ATree& t);
 void launch_leaf_of(hipStream_t s, int nn, const ATree& t, int32_t* leaf_of);
 void launch_lists(hipStream_t s, bool fill, int nn, const ATree& t, int32_t* ucnt, int32_t* wcnt, int32_t* xcnt,
