@@ -107,42 +107,44 @@ void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const doubl
 
 // ------------------------------------------------------------------ M2M
 
-constexpr int SHIFT_NP = 8;  // parents per workgroup in M2M/L2L
+constexpr int SHIFT_NP = 16;  // parents per workgroup in M2M/L2L
+static_assert(ldm_of(PMAX) <= 128, "one thread per component in M2M");
 
 // parent M~ = sum over the 8 children o of A_o M~_child (Eq. M2M in scaled
 // form).  A_o[n][j] vanishes for rank(j) > rank(n) (the shift is exact and
-// rank-lowering), so row n only reads the first (rank(n)+1)^2 columns.  Each
-// matrix element is loaded once per SHIFT_NP parents.
+// rank-lowering), so row n only reads the first (rank(n)+1)^2 columns.  One
+// thread per component n; the children of one octant at a time are staged
+// in LDS, component-major (15.5 KB at p = 10, so several workgroups share a
+// CU), and each matrix element is loaded once per SHIFT_NP parents.
 __global__ __launch_bounds__(128) void k_m2m(int p, long long nparents, const double* __restrict__ Mc,
                                              double* __restrict__ Mp, const double* __restrict__ m2m_t) {
     const long long P0 = (long long)blockIdx.x * SHIFT_NP;
     const int nc = (p + 1) * (p + 1);
     const int ldm = ldm_of(p);
-    __shared__ double ch[SHIFT_NP][8][NIND];
+    __shared__ double ch[NIND][SHIFT_NP];
     const int np = (int)min((long long)SHIFT_NP, nparents - P0);
-    for (int t = threadIdx.x; t < np * 8 * nc; t += 128) {
-        const int pp = t / (8 * nc), r = t % (8 * nc), o = r / nc, j = r % nc;
-        ch[pp][o][j] = Mc[((size_t)(P0 + pp) * 8 + o) * ldm + j];
-    }
-    __syncthreads();
-    for (int n = threadIdx.x; n < ldm; n += 128) {
-        double acc[SHIFT_NP];
+    const int n = threadIdx.x;
+    const int jmax = n < nc ? (rank_of(n) + 1) * (rank_of(n) + 1) : 0;
+    double acc[SHIFT_NP];
 #pragma unroll
-        for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] = 0.0;
-        if (n < nc) {
-            const int r = rank_of(n);
-            const int jmax = (r + 1) * (r + 1);
-            for (int o = 0; o < 8; ++o) {
-                const double* A = m2m_t + (size_t)o * NIND * NIND;
-                for (int j = 0; j < jmax; ++j) {
-                    const double a = A[(size_t)j * NIND + n];
-#pragma unroll
-                    for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += a * ch[pp][o][j];
-                }
-            }
+    for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] = 0.0;
+    for (int o = 0; o < 8; ++o) {
+        __syncthreads();  // the previous octant's reads are done
+        for (int t = threadIdx.x; t < SHIFT_NP * nc; t += 128) {
+            const int pp = t / nc, j = t % nc;
+            ch[j][pp] = pp < np ? Mc[((size_t)(P0 + pp) * 8 + o) * ldm + j] : 0.0;
         }
-        for (int pp = 0; pp < np; ++pp) Mp[(size_t)(P0 + pp) * ldm + n] = acc[pp];  // padding stays zero
+        __syncthreads();
+        const double* A = m2m_t + (size_t)o * NIND * NIND + n;
+#pragma unroll 4
+        for (int j = 0; j < jmax; ++j) {
+            const double a = A[(size_t)j * NIND];
+#pragma unroll
+            for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += a * ch[j][pp];
+        }
     }
+    if (n < ldm)
+        for (int pp = 0; pp < np; ++pp) Mp[(size_t)(P0 + pp) * ldm + n] = acc[pp];  // padding stays zero
 }
 
 void launch_m2m(hipStream_t s, int p, int parent_level, const double* Mchild, double* Mparent, const DevTables& T) {
@@ -206,21 +208,27 @@ __global__ __launch_bounds__(256) void k_l2l(int p, long long nparents, const do
     const long long P0 = (long long)blockIdx.x * SHIFT_NP;
     const int nc = (p + 1) * (p + 1);
     const int ldm = ldm_of(p);
-    __shared__ double lp[SHIFT_NP][NIND];
+    // component-major; the lanes of a wave start at different rows j =
+    // rank(n)^2, so rows are padded by two doubles to fall on different banks
+    __shared__ __attribute__((aligned(16))) double lp[NIND][SHIFT_NP + 2];
     const int np = (int)min((long long)SHIFT_NP, nparents - P0);
-    for (int t = threadIdx.x; t < np * nc; t += 256) lp[t / nc][t % nc] = Lp[(size_t)(P0 + t / nc) * ldm + t % nc];
+    for (int t = threadIdx.x; t < SHIFT_NP * nc; t += 256) {
+        const int pp = t / nc, k = t % nc;
+        lp[k][pp] = pp < np ? Lp[(size_t)(P0 + pp) * ldm + k] : 0.0;
+    }
     __syncthreads();
     for (int t = threadIdx.x; t < 8 * nc; t += 256) {
         const int o = t / nc, n = t % nc;
-        const double* B = l2l_t + (size_t)o * NIND * NIND;
+        const double* B = l2l_t + (size_t)o * NIND * NIND + n;
         double acc[SHIFT_NP];
 #pragma unroll
         for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] = 0.0;
         const int r = rank_of(n);
+#pragma unroll 4
         for (int j = r * r; j < nc; ++j) {
-            const double bcoef = B[(size_t)j * NIND + n];
+            const double bcoef = B[(size_t)j * NIND];
 #pragma unroll
-            for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += bcoef * lp[pp][j];
+            for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += bcoef * lp[j][pp];
         }
         for (int pp = 0; pp < np; ++pp) Lc[((size_t)(P0 + pp) * 8 + o) * ldm + n] += acc[pp];
     }
