@@ -204,8 +204,13 @@ __device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b
     __syncthreads();
     for (int n = lane; n < ldm; n += 64) {
         double v = 0.0;
-        if (n < nc)
-            for (int t = T.det_start[n]; t < T.det_start[n + 1]; ++t) v += T.det_coef[t] * S[T.det_full[t]];
+        // unrolled so that several of the independent table loads are in
+        // flight (the sum keeps its order)
+        if (n < nc) {
+            const int t1 = T.det_start[n + 1];
+#pragma unroll 8
+            for (int t = T.det_start[n]; t < t1; ++t) v += T.det_coef[t] * S[T.det_full[t]];
+        }
         Mc[n] = v;  // padding is kept zero
     }
 }
