@@ -201,16 +201,15 @@ void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, 
 // ------------------------------------------------------------------ L2L
 
 // child L~_o += B_o L~_parent (Eq. L2L in scaled form).  B_o[n][j] vanishes
-// for rank(j) < rank(n), so row n reads columns from rank(n)^2 on.  Each
+// for rank(j) < rank(n), so row n needs only the columns from rank(n)^2 on.
+// One thread per (octant, component) and SHIFT_NP parents per workgroup; each
 // matrix element is loaded once per SHIFT_NP parents.
 __global__ __launch_bounds__(256) void k_l2l(int p, long long nparents, const double* __restrict__ Lp,
                                              double* __restrict__ Lc, const double* __restrict__ l2l_t) {
     const long long P0 = (long long)blockIdx.x * SHIFT_NP;
     const int nc = (p + 1) * (p + 1);
     const int ldm = ldm_of(p);
-    // component-major; the lanes of a wave start at different rows j =
-    // rank(n)^2, so rows are padded by two doubles to fall on different banks
-    __shared__ __attribute__((aligned(16))) double lp[NIND][SHIFT_NP + 2];
+    __shared__ __attribute__((aligned(16))) double lp[NIND][SHIFT_NP];  // component-major
     const int np = (int)min((long long)SHIFT_NP, nparents - P0);
     for (int t = threadIdx.x; t < SHIFT_NP * nc; t += 256) {
         const int pp = t / nc, k = t % nc;
@@ -223,9 +222,14 @@ __global__ __launch_bounds__(256) void k_l2l(int p, long long nparents, const do
         double acc[SHIFT_NP];
 #pragma unroll
         for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] = 0.0;
-        const int r = rank_of(n);
+        // Every lane of the wave starts at the smallest rank(n)^2 among its
+        // lanes, so that all read the same LDS row (a broadcast); the extra
+        // terms have B_o[n][j] = 0 exactly and leave the sums unchanged.
+        const int t0 = t & ~63, t1 = min(t0 + 63, 8 * nc - 1);
+        const int r0 = t0 / nc == t1 / nc ? rank_of(t0 % nc) : 0;
+        const int js = __builtin_amdgcn_readfirstlane(r0 * r0);
 #pragma unroll 4
-        for (int j = r * r; j < nc; ++j) {
+        for (int j = js; j < nc; ++j) {
             const double bcoef = B[(size_t)j * NIND];
 #pragma unroll
             for (int pp = 0; pp < SHIFT_NP; ++pp) acc[pp] += bcoef * lp[j][pp];
