@@ -1600,61 +1600,61 @@ __device__ inline int class_of_r2_a(int r2) {
     return (r2 >= 0 && r2 < 28) ? tab[r2] : -1;
 }
 
-// One wavefront per (tile, offset): the order of its pairs into ord_tab
-// (same layout as src_tab) and as a one-bit mask.  Each pair asks for
-// ordn[source * 15 + class of |v|^2]; the tile's M2L at this offset runs at
-// the largest order asked among its pairs (no pair gets less than it asked
-// for, and the source rows are staged once).  With a table by |v|^2 every
-// pair of a (tile, offset) asks for the same order.
+// One wavefront per (tile, offset): the order of its M2L.  Each pair asks
+// for ordn[source * 15 + class of |v|^2]; the tile's M2L at this offset runs
+// at the largest order asked among its pairs (no pair gets less than it
+// asked for, and the source rows are read once).  With a table by |v|^2
+// every pair of a (tile, offset) asks for the same order.
 __global__ __launch_bounds__(64) void k_m2l_orders(int tt, const int4* __restrict__ tiles,
                                                    const int32_t* __restrict__ src_tab,
                                                    const int16_t* __restrict__ kslot, const int8_t* __restrict__ ordn,
-                                                   int8_t* __restrict__ ord_tab, uint16_t* __restrict__ omask,
-                                                   int32_t* __restrict__ ocnt) {
+                                                   int8_t* __restrict__ tq, int32_t* __restrict__ ocnt) {
     const int tile = blockIdx.x / 189, iv = blockIdx.x % 189;
     const int lane = threadIdx.x;
     const int ks = kslot[tiles[tile].x * 189 + iv];  // slot of r = target - source
     const int rx = ks % 7 - 3, ry = (ks / 7) % 7 - 3, rz = ks / 49 - 3;
     const int cls = class_of_r2_a(rx * rx + ry * ry + rz * rz);
-    int omax = -1;
+    int omax = -1, npair = 0;
     for (int r = lane; r < tt; r += 64) {
         const int src = src_tab[(189 * (size_t)tile + iv) * tt + r];
-        if (src >= 0) omax = max(omax, (int)ordn[(size_t)src * NCLASS + cls]);
+        if (src >= 0) {
+            omax = max(omax, (int)ordn[(size_t)src * NCLASS + cls]);
+            ++npair;
+        }
     }
-    for (int off = 1; off < 64; off <<= 1) omax = max(omax, __shfl_xor(omax, off));
-    for (int r = lane; r < tt; r += 64) {
-        const size_t e = (189 * (size_t)tile + iv) * tt + r;
-        ord_tab[e] = src_tab[e] >= 0 ? (int8_t)omax : (int8_t)-1;
+    for (int off = 1; off < 64; off <<= 1) {
+        omax = max(omax, __shfl_xor(omax, off));
+        npair += __shfl_xor(npair, off);
     }
-    if (lane == 0) omask[blockIdx.x] = omax >= 0 ? (uint16_t)(1u << omax) : (uint16_t)0;
+    if (lane == 0) tq[blockIdx.x] = (int8_t)omax;
     // pairs per order (the chosen-order histogram)
-    const size_t stride = (size_t)gridDim.x;
-    for (int o = 0; o <= 10; ++o) {
-        int cnt = 0;
-        for (int r = lane; r < tt; r += 64) cnt += ord_tab[(189 * (size_t)tile + iv) * tt + r] == o;
-        for (int off = 1; off < 64; off <<= 1) cnt += __shfl_xor(cnt, off);
-        if (lane == 0) ocnt[o * stride + blockIdx.x] = cnt;
-    }
+    if (lane <= 10) ocnt[(size_t)lane * gridDim.x + blockIdx.x] = lane == omax ? npair : 0;
 }
 
-// One wavefront per tile: for every order p' = 0..10 the offsets whose
-// mask has p', in order: ivlist[p' ntiles 189 + 189 t ..], ivcnt[p' ntiles + t]
-__global__ __launch_bounds__(64) void k_class_lists(int ntiles, const uint16_t* __restrict__ omask,
-                                                    int16_t* __restrict__ ivlist, int32_t* __restrict__ ivcnt) {
+// One wavefront per tile: its active offsets in offset order (an order in
+// tq >= 0, or with tq null a source in vcount), their orders (tq, or p).
+__global__ __launch_bounds__(64) void k_active_offsets(int p, const int8_t* __restrict__ tq,
+                                                       const int32_t* __restrict__ vcount,
+                                                       int16_t* __restrict__ ivlist, int8_t* __restrict__ ivord,
+                                                       int32_t* __restrict__ ivcnt) {
     const int tile = blockIdx.x;
     const int lane = threadIdx.x;
-    for (int c = 0; c <= 10; ++c) {
-        int16_t* out = ivlist + ((size_t)c * ntiles + tile) * 189;
-        int cnt = 0;
-        for (int b = 0; b < 189; b += 64) {
-            const int iv = b + lane;
-            const bool on = iv < 189 && ((omask[(size_t)tile * 189 + iv] >> c) & 1u);
-            const unsigned long long bal = __ballot(on);
-            if (on) out[cnt + __popcll(bal & ((1ull << lane) - 1ull))] = (int16_t)iv;
-            cnt += __popcll(bal);
+    int cnt = 0;
+    for (int b = 0; b < 189; b += 64) {
+        const int iv = b + lane;
+        const size_t e = (size_t)tile * 189 + iv;
+        int q = -1;
+        if (iv < 189) q = tq ? (int)tq[e] : (vcount[e] > 0 ? p : -1);
+        const bool on = q >= 0;
+        const unsigned long long bal = __ballot(on);
+        if (on) {
+            const int k = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+            ivlist[(size_t)tile * 189 + k] = (int16_t)iv;
+            ivord[(size_t)tile * 189 + k] = (int8_t)q;
         }
-        if (lane == 0) ivcnt[(size_t)c * ntiles + tile] = cnt;
+        cnt += __popcll(bal);
     }
+    if (lane == 0) ivcnt[tile] = cnt;
 }
 
 __global__ void k_fill0(long long n, double* __restrict__ a) {
@@ -1663,15 +1663,15 @@ __global__ void k_fill0(long long n, double* __restrict__ a) {
 }
 
 void launch_m2l_orders(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* src_tab,
-                       const int16_t* kslot, const int8_t* ordn, int8_t* ord_tab, uint16_t* omask, int32_t* ocnt) {
+                       const int16_t* kslot, const int8_t* ordn, int8_t* tq, int32_t* ocnt) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_m2l_orders, dim3(189 * ntiles), dim3(64), 0, s, tt, tiles, src_tab, kslot, ordn, ord_tab,
-                       omask, ocnt);
+    hipLaunchKernelGGL(k_m2l_orders, dim3(189 * ntiles), dim3(64), 0, s, tt, tiles, src_tab, kslot, ordn, tq, ocnt);
 }
 
-void launch_class_lists(hipStream_t s, int ntiles, const uint16_t* omask, int16_t* ivlist, int32_t* ivcnt) {
+void launch_active_offsets(hipStream_t s, int ntiles, int p, const int8_t* tq, const int32_t* vcount,
+                           int16_t* ivlist, int8_t* ivord, int32_t* ivcnt) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_class_lists, dim3(ntiles), dim3(64), 0, s, ntiles, omask, ivlist, ivcnt);
+    hipLaunchKernelGGL(k_active_offsets, dim3(ntiles), dim3(64), 0, s, p, tq, vcount, ivlist, ivord, ivcnt);
 }
 
 void launch_fill0(hipStream_t s, long long n, double* a) {

@@ -25,12 +25,15 @@ constexpr int NPHASE_EV = 8 + 4 * (AMAX + 1);
 
 }  // namespace
 
-// Operators of one expansion order in the context's M2L precision.
+// Operators of one expansion order in the context's M2L precision; Kmix
+// (built when orders per pair are first used) holds the operators of every
+// order q <= p in the order-p fragment layout, one set after the other.
 struct OpSet {
     int p = -1;
     double* Dv = nullptr;
     double* Kt = nullptr;
     unsigned char* Kpk = nullptr;
+    unsigned char* Kmix = nullptr;
 };
 
 // Workspace of one forest of adaptive trees (all systems of one order p);
@@ -107,17 +110,20 @@ struct Forest {
     const unsigned char* Kpk = nullptr;  // operators of order p
     int tt = 64;                         // targets per M2L tile
     int hb[512] = {};                    // (level, octant) bucket bounds on the host
+    // active offsets of every M2L tile: [ntiles][189] offsets and their
+    // orders, [ntiles] counts
+    int16_t* ivl = nullptr;
+    int8_t* ivo = nullptr;
+    int32_t* ivc = nullptr;
+    size_t ivl_cap = 0, ivo_cap = 0, ivc_cap = 0;
     // M2L orders per pair
     int8_t* ordn = nullptr;      // [nn][15] order per (source node, distance class)
-    int8_t* ord_tab = nullptr;   // order of every tile entry (layout of src_tab)
-    uint16_t* omask = nullptr;   // [ntiles][189] orders present
-    int16_t* ivl = nullptr;      // [11][ntiles][189] active offsets per order
-    int32_t* ivc = nullptr;      // [11][ntiles]
+    int8_t* tq = nullptr;        // [ntiles][189] order of every (tile, offset), -1 = no pair
     int32_t* ocnt = nullptr;     // [11][ntiles * 189] pairs per order
     float* mx = nullptr;         // network inputs of (node, class)
     float* my = nullptr;         // network outputs
-    size_t ordn_cap = 0, ord_tab_cap = 0, omask_cap = 0, ivl_cap = 0, ivc_cap = 0, ocnt_cap = 0, mx_cap = 0, my_cap = 0;
-    const unsigned char* Kord[CTFMM_P_MAX + 1] = {};  // operators of every order <= p
+    size_t ordn_cap = 0, tq_cap = 0, ocnt_cap = 0, mx_cap = 0, my_cap = 0;
+    const unsigned char* Kmix = nullptr;  // operators of every order <= p (order-p layout)
     int nchunk = 1;              // M2L workgroups per tile (offset chunks)
     bool up_early = false;       // P2M and M2M already launched by the tree build
     double* part = nullptr;      // [nchunk][nn][ldm] partial local expansions
@@ -139,6 +145,7 @@ struct ctfmm_ctx {
     double* Dv = nullptr;  // [NOFF][NIND] derivative tensors of the offsets
     double* Kt = nullptr;  // [NOFF][nc][nc] K_v transposed
     unsigned char* Kpk = nullptr;  // K_v as MFMA A-fragments of the M2L precision
+    unsigned char* Kmix = nullptr; // the operators of every order <= p (per-pair orders)
     int16_t* offlist = nullptr;    // [8][189] offset slots of each target octant
     unsigned char* zero_row = nullptr;  // a zero source row (out-of-domain sources)
     int* pinned = nullptr;              // pinned host words for small device-to-host reads
@@ -175,8 +182,6 @@ struct ctfmm_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
-    hipStream_t ord_stream[CTFMM_P_MAX + 1] = {};  // per-order M2L launches run side by side
-    hipEvent_t ord_ev[CTFMM_P_MAX + 2] = {};
     hipStream_t side[2] = {};  // the near field (P2P) and the X lists (P2L) beside the expansion passes
     hipEvent_t side_ev[7] = {};
     // M2L order per pair (adaptive tree): 0 = the fixed order p, 1 = a table
@@ -278,6 +283,7 @@ bool grow(ctfmm_ctx* c, T*& ptr, size_t& cap, size_t need, bool keep) {
 void reset_adaptive(ctfmm_ctx* c) {
     // pointers only: the buffers themselves are released with the rest
     c->opsets.clear();
+    c->Kmix = nullptr;
     c->forests.clear();
     c->nforests = 0;
     c->tmp = nullptr;
@@ -388,7 +394,7 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     c->zero_row = (unsigned char*)dev_alloc(c, zbytes);
     if (!c->Kpk || !c->zero_row) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
     HIPCHK(c, hipMemsetAsync(c->zero_row, 0, zbytes, c->stream));
-    launch_pack_k(c->stream, p, prec, c->Kt, c->Kpk);
+    launch_pack_k(c->stream, p, prec, c->Kt, c->Kpk, p);
     HIPCHK(c, hipGetLastError());
     // offsets v of the ws=1 list for a target in octant o: v_d in [-2-o_d, 3-o_d], max|v_d| >= 2
     std::vector<int16_t> off(8 * 189);
@@ -635,10 +641,38 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
     if (!o.Dv || !o.Kt || !o.Kpk) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
     launch_offset_dtensors(c->stream, p, o.Dv);
     launch_build_k(c->stream, p, o.Dv, c->T, o.Kt);
-    launch_pack_k(c->stream, p, prec, o.Kt, o.Kpk);
+    launch_pack_k(c->stream, p, prec, o.Kt, o.Kpk, p);
     HIPCHK(c, hipGetLastError());
     c->opsets.push_back(o);
     *kpk = o.Kpk;
+    return CTFMM_OK;
+}
+
+// operators of every order q <= p in the order-p layout (built on first use)
+ctfmm_status get_mixed_ops(ctfmm_ctx* c, int p, const unsigned char** kmix) {
+    const unsigned char* dummy = nullptr;
+    SCHK(get_ops(c, p, &dummy));
+    const double* Kt = nullptr;
+    unsigned char** slot = nullptr;
+    if (p == c->prm.order_p) {
+        Kt = c->Kt;
+        slot = &c->Kmix;
+    } else {
+        for (OpSet& o : c->opsets)
+            if (o.p == p) {
+                Kt = o.Kt;
+                slot = &o.Kmix;
+            }
+    }
+    if (!Kt || !slot) return fail(c, CTFMM_EDEVICE, "operator set missing");
+    if (!*slot) {
+        const size_t per = m2l_packed_bytes(p, c->prm.precision);
+        *slot = (unsigned char*)dev_alloc(c, per * (size_t)(p + 1));
+        if (!*slot) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+        for (int q = 0; q <= p; ++q) launch_pack_k(c->stream, p, c->prm.precision, Kt, *slot + per * q, q);
+        HIPCHK(c, hipGetLastError());
+    }
+    *kmix = *slot;
     return CTFMM_OK;
 }
 
@@ -646,19 +680,30 @@ ctfmm_status get_ops(ctfmm_ctx* c, int p, const unsigned char** kpk) {
 // to the forests of the context's own order; other forests keep their order.
 int order_mode_of(const ctfmm_ctx* c, const Forest& f) { return f.p == c->prm.order_p ? c->order_mode : 0; }
 
-// FP32 M2L with fixed orders runs the kernel that loads the source rows into
-// registers (k_m2l_rb), from k-quad-major FP32 rows; every other case the
-// tile kernel that stages them in LDS.
-bool rb_m2l(const ctfmm_ctx* c, const Forest& f) {
-    return c->prm.precision == CTFMM_PREC_FP32 && order_mode_of(c, f) == 0;
+// FP32 M2L runs the kernel that loads the source rows into registers
+// (k_m2l_rb), from k-quad-major FP32 rows; the other precisions the tile
+// kernel that stages them in LDS.
+bool rb_m2l(const ctfmm_ctx* c) { return c->prm.precision == CTFMM_PREC_FP32; }
+
+// M2L arguments of the forest's tiles over their active offsets; with
+// orders, each active offset at the order of its (tile, offset)
+AdaptM2L m2l_args(ctfmm_ctx* c, const Forest& f, bool orders) {
+    AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+    ad.ivlist = f.ivl;
+    ad.ivcnt = f.ivc;
+    if (orders) {
+        ad.ivord = f.ivo;
+        ad.kord_stride = m2l_packed_bytes(f.p, c->prm.precision);
+    }
+    return ad;
 }
 
 hipError_t m2l_adaptive(ctfmm_ctx* c, const Forest& f, hipStream_t st, const AdaptM2L& ad, const void* msrc,
                         double* out) {
     const int nt = (int)f.tiles_host.size();
-    if (rb_m2l(c, f))
-        return launch_m2l_rb(st, f.p, f.tt, nt, ad, static_cast<const float*>(msrc), out, f.Kpk, c->zero_row);
-    return launch_m2l_tables(st, f.p, c->prm.precision, f.tt, nt, ad, msrc, out, f.Kpk, c->zero_row);
+    const unsigned char* K = ad.ivord ? f.Kmix : f.Kpk;
+    if (rb_m2l(c)) return launch_m2l_rb(st, f.p, f.tt, nt, ad, static_cast<const float*>(msrc), out, K, c->zero_row);
+    return launch_m2l_tables(st, f.p, c->prm.precision, f.tt, nt, ad, msrc, out, K, c->zero_row);
 }
 
 // Workgroups per M2L tile: the 189 offsets of a tile are split into chunks
@@ -699,6 +744,9 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     ACHK(grow(c, f.tiles_tmp, f.tiles_tmp_cap, ntiles, false));
     ACHK(grow(c, f.tkey, f.tkey_cap, 2 * ntiles, false));
     ACHK(grow(c, f.tidx, f.tidx_cap, 2 * ntiles, false));
+    ACHK(grow(c, f.ivl, f.ivl_cap, 189 * ntiles, false));
+    ACHK(grow(c, f.ivo, f.ivo_cap, 189 * ntiles, false));
+    ACHK(grow(c, f.ivc, f.ivc_cap, ntiles, false));
     HIPCHK(c, hipMemcpyAsync(f.tiles_tmp, f.tiles_host.data(), ntiles * sizeof(int4), hipMemcpyHostToDevice,
                              c->stream));
     // Tiles in the order of their first target's parent: the workgroups that
@@ -713,16 +761,19 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
     }));
     launch_gather_int4(c->stream, nt, f.tidx + nt, f.tiles_tmp, f.tiles);
     launch_m2l_tables(c->stream, tt, (int)ntiles, f.tiles, f.lovs, f.tr, c->alist, f.tgt_tab, f.src_tab, f.vcount);
+    // the offsets with at least one source, at the forest's order (per-pair
+    // orders rewrite these lists in the numeric pass)
+    launch_active_offsets(c->stream, nt, f.p, nullptr, f.vcount, f.ivl, f.ivo, f.ivc);
     HIPCHK(c, hipGetLastError());
     return CTFMM_OK;
 }
 
 // The tile-shape tuner: for every tile size the device's LDS admits (on this
-// forest's own tables) and, with fixed orders, every split of a tile's
-// offsets over 1 to 4 workgroups, times three runs (after a warm-up run) of
-// the M2L launch with the clear and the sum of its partial-sum slots, and
-// returns the fastest.  The multipole buffer's contents do not matter for the
-// timing; what it writes is overwritten by the real pass.
+// forest's own tables) and every split of a tile's offsets over 1 to 4
+// workgroups, times three runs (after a warm-up run) of the M2L launch (at
+// the forest's order) with the clear and the sum of its partial-sum slots,
+// and returns the fastest.  The multipole buffer's contents do not matter
+// for the timing; what it writes is overwritten by the real pass.
 ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
     const int prec = c->prm.precision;
     int max_lds = 0;
@@ -730,7 +781,6 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
     for (auto& e : c->tev)
         if (!e) HIPCHK(c, hipEventCreate(&e));
     const void* msrc = prec == CTFMM_PREC_FP64 ? (const void*)f.aM : (const void*)f.aM32;
-    const bool fixed = order_mode_of(c, f) == 0;
     const size_t lsz = (size_t)f.nn * ldm_of(f.p);
     float tbest = 0.f;
     *best = 32;  // fits wherever the context could be created
@@ -738,13 +788,10 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
     for (int tt : {32, 64, 128}) {
         if (m2l_tile_lds_bytes(f.p, prec, tt) > (size_t)max_lds) continue;
         SCHK(make_tiles(c, f, tt));
-        const int nc_default = chunks_for(f.tiles_host.size());
-        for (int nc = 1; nc <= 4; ++nc) {
-            if (!fixed && nc > 1) break;
-            const int nchunk = fixed ? nc : nc_default;
+        for (int nchunk = 1; nchunk <= 4; ++nchunk) {
             SCHK(set_chunks(c, f, nchunk));
-            const int slots = nchunk + (fixed && f.tot_x > 0 ? 1 : 0);
-            AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+            const int slots = nchunk + (f.tot_x > 0 ? 1 : 0);
+            AdaptM2L ad = m2l_args(c, f, false);
             double* out = f.aL;
             if (slots > 1) {
                 ad.acc = true;
@@ -772,7 +819,7 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
             if (tbest == 0.f || ms < tbest) {
                 tbest = ms;
                 *best = tt;
-                *best_chunks = fixed ? nchunk : 0;
+                *best_chunks = nchunk;
             }
         }
     }
@@ -1002,18 +1049,10 @@ tree_again:
     SCHK(make_tiles(c, f, tt ? tt : 64));
     if (order_mode_of(c, f) != 0 && !f.tiles_host.empty()) {
         const size_t nt = f.tiles_host.size();
-        for (int k = 0; k <= f.p; ++k) SCHK(get_ops(c, k, &f.Kord[k]));
+        SCHK(get_mixed_ops(c, f.p, &f.Kmix));
         ACHK(grow(c, f.ordn, f.ordn_cap, (size_t)nn * NCLASS, false));
-        ACHK(grow(c, f.ord_tab, f.ord_tab_cap, (size_t)189 * f.tt * nt, false));
-        ACHK(grow(c, f.omask, f.omask_cap, 189 * nt, false));
-        ACHK(grow(c, f.ivl, f.ivl_cap, (size_t)11 * 189 * nt, false));
-        ACHK(grow(c, f.ivc, f.ivc_cap, 11 * nt, false));
+        ACHK(grow(c, f.tq, f.tq_cap, 189 * nt, false));
         ACHK(grow(c, f.ocnt, f.ocnt_cap, (size_t)11 * 189 * nt, false));
-        ACHK(grow(c, f.part, f.part_cap, (size_t)(f.p + 1) * f.nn * ldm_of(f.p), false));
-        for (int k = 0; k <= f.p; ++k)
-            if (!c->ord_stream[k]) HIPCHK(c, hipStreamCreateWithFlags(&c->ord_stream[k], hipStreamNonBlocking));
-        for (auto& e : c->ord_ev)
-            if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
         if (order_mode_of(c, f) == 2) {
             ACHK(grow(c, f.mx, f.mx_cap, (size_t)nn * NCLASS * MLP_NIN, false));
             ACHK(grow(c, f.my, f.my_cap, (size_t)nn * NCLASS * MLP_NOUT, false));
@@ -1042,14 +1081,14 @@ ctfmm_status count_v_pairs(ctfmm_ctx* c, Forest& f) {
 
 // The numeric passes of one forest (no host waits, no memsets: graph-capturable).
 // The near field (P2P) runs on a side stream from the start, followed there
-// by the W lists once their coefficients are formed, and with fixed orders the
-// X lists (P2L) on another beside M2L; the main stream joins them before the
-// sum of the M2L slots and before the final sum of far and near field.  ev >= 0 records the phase events ev.. on the main stream (0 start,
-// 1 P2M, 2 M2M, 3 conversions, 4 M2L (with the X lists when they run beside
-// it), 5 P2L, 6 L2L, 7 far field and the join with the near field; 8 and 9
-// around the M2L launch itself, or around all of the per-order M2L work).  to_F
-// leaves the results in sorted order in f.a_F (for launch_scatter_out)
-// instead of writing phi and grad.
+// by the W lists once their coefficients are formed, and the X lists (P2L) on
+// another beside M2L; the main stream joins them before the sum of the M2L
+// slots and before the final sum of far and near field.  ev >= 0 records the
+// phase events ev.. on the main stream (0 start, 1 P2M, 2 M2M, 3 conversions,
+// 4 M2L with the X lists beside it and the order choice, 5 the rest of the
+// X lists, 6 L2L, 7 far field and the join with the near field; 8 and 9
+// around the M2L launch itself).  to_F leaves the results in sorted order in
+// f.a_F (for launch_scatter_out) instead of writing phi and grad.
 ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, int ev, bool to_F = false) {
     hipStream_t st = c->stream;
     const int p = f.p;
@@ -1088,21 +1127,39 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             launch_wlist_adaptive(c->side[0], p, nn, f.boxes, f.tr, f.a_P, f.aWc, f.loff + n1, f.wlist, f.a_Fn);
         }
         if (prec != CTFMM_PREC_FP64) {
-            if (rb_m2l(c, f)) launch_to_f32_kq(st, p, nn, f.aM, f.aM32);
+            if (rb_m2l(c)) launch_to_f32_kq(st, p, nn, f.aM, f.aM32);
             else launch_to_f32(st, p, nn, f.aM, f.aM32);
             msrc = f.aM32;
         }
     }
     mark(3);
     // downward: L(B) = M2L(V) + P2L(X) + L2L(parent).  M2L over the tiles of
-    // every level at once (it reads only M), then the X lists, then L2L top-down.
+    // every level at once (it reads only M), the X lists beside it, then L2L
+    // top-down.
     const int omode = order_mode_of(c, f);
     const size_t lsz = (size_t)nn * ldm_of(p);
     bool x_done = false;
-    if (!f.tiles_host.empty() && omode == 0) {
+    if (!f.tiles_host.empty()) {
+        const int nt = (int)f.tiles_host.size();
+        if (omode != 0) {
+            // orders per (source cell, distance class), then per (tile,
+            // offset) the largest its pairs ask for; the active-offset lists
+            // are rewritten with those orders
+            const int f2 = f.lev_first[2];
+            if (omode == 1) {
+                launch_order_table(st, nn, c->order_tab, f.ordn);
+            } else {
+                const long long rows = (long long)(nn - f2) * NCLASS;
+                launch_mlp_node_features(st, f2, nn - f2, f.aM, ldm_of(p), f.mx);
+                launch_mlp_forward16(st, rows, f.mx, c->model, c->model + MLP_NPARAM, f.my);
+                launch_mlp_decide(st, f2, nn - f2, f.my, c->order_thr, f.ordn);
+            }
+            launch_m2l_orders(st, f.tt, nt, f.tiles, f.src_tab, c->alist + 8 * 189, f.ordn, f.tq, f.ocnt);
+            launch_active_offsets(st, nt, p, f.tq, nullptr, f.ivl, f.ivo, f.ivc);
+        }
         // M2L chunks into slots 0 .. nchunk-1 of part; the X lists (P2L, on a
         // side stream beside M2L) into slot nchunk; then the slots are summed
-        AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
+        AdaptM2L ad = m2l_args(c, f, omode != 0);
         const bool xs = f.tot_x > 0;
         const int slots = f.nchunk + (xs ? 1 : 0);
         if (slots == 1) {
@@ -1128,47 +1185,6 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             launch_sum_chunks(st, slots, lsz, f.part, f.aL);
         }
         x_done = true;
-    } else if (!f.tiles_host.empty()) {
-        mark(8);
-        // orders per (source cell, distance class), then one accumulating
-        // M2L launch per order over the offsets where that order occurs
-        const int nt = (int)f.tiles_host.size();
-        const int f2 = f.lev_first[2];
-        if (omode == 1) {
-            launch_order_table(st, nn, c->order_tab, f.ordn);
-        } else {
-            const long long rows = (long long)(nn - f2) * NCLASS;
-            launch_mlp_node_features(st, f2, nn - f2, f.aM, ldm_of(p), f.mx);
-            launch_mlp_forward16(st, rows, f.mx, c->model, c->model + MLP_NPARAM, f.my);
-            launch_mlp_decide(st, f2, nn - f2, f.my, c->order_thr, f.ordn);
-        }
-        launch_m2l_orders(st, f.tt, nt, f.tiles, f.src_tab, c->alist + 8 * 189, f.ordn, f.ord_tab, f.omask, f.ocnt);
-        launch_class_lists(st, nt, f.omask, f.ivl, f.ivc);
-        // one launch per order, side by side on their own streams (the tails
-        // of one overlap the others), each adding into its own slot of part;
-        // the slots are then summed in order
-        launch_fill0(st, (long long)((p + 1) * lsz), f.part);
-        HIPCHK(c, hipEventRecord(c->ord_ev[CTFMM_P_MAX + 1], st));
-        const int ld_in = prec == CTFMM_PREC_FP64 ? ldm_of(p) * 8 : s32_of(p) * 4;
-        for (int k = 0; k <= p; ++k) {
-            hipStream_t sk = c->ord_stream[k];
-            HIPCHK(c, hipStreamWaitEvent(sk, c->ord_ev[CTFMM_P_MAX + 1], 0));
-            AdaptM2L ad{f.tiles, f.tgt_tab, f.src_tab, c->alist + 8 * 189, 0};
-            ad.ivlist = f.ivl + (size_t)k * nt * 189;
-            ad.ivcnt = f.ivc + (size_t)k * nt;
-            ad.ord = f.ord_tab;
-            ad.cls = k;
-            ad.ld_in = ld_in;
-            ad.ld_out = ldm_of(p);
-            ad.acc = true;
-            ad.nchunk = 1;
-            HIPCHK(c, launch_m2l_tables(sk, k, prec, f.tt, nt, ad, msrc, f.part + (size_t)k * lsz, f.Kord[k],
-                                        c->zero_row));
-            HIPCHK(c, hipEventRecord(c->ord_ev[k], sk));
-            HIPCHK(c, hipStreamWaitEvent(st, c->ord_ev[k], 0));
-        }
-        launch_sum_chunks(st, p + 1, lsz, f.part, f.aL);
-        mark(9);
     } else {
         mark(8);
         mark(9);
@@ -1517,8 +1533,8 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
         const Forest& f = c->forests[k];
         const void* ptrs[] = {f.boxes, f.tr.key, f.tr.pb, f.tr.pe, f.tr.par, f.tr.info, f.tr.child, f.tr.nb, f.tr.sys, f.tr.geo,
                               f.a_P, f.a_F, f.a_Fn, f.aM, f.aL, f.aWc, f.aM32, f.loff, f.xlist, f.wlist, f.ulist,
-                              f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.ordn,
-                              f.ord_tab, f.omask, f.ivl, f.ivc, f.mx, f.my, c->order_tab, c->model, f.part};
+                              f.a_idxs, f.leaf_of, f.tiles, f.tgt_tab, f.src_tab, f.Kpk, f.Kmix, f.ordn,
+                              f.tq, f.ocnt, f.ivl, f.ivo, f.ivc, f.mx, f.my, c->order_tab, c->model, f.part};
         for (const void* q2 : ptrs) sig.push_back((long long)(uintptr_t)q2);
         sig.insert(sig.end(), {f.p, f.n, f.nn, (long long)f.tiles_host.size(), f.tot_w, f.tot_x, f.tt,
                                f.nchunk});
@@ -1876,10 +1892,6 @@ void ctfmm_destroy(ctfmm_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& e : c->tev)
         if (e) (void)hipEventDestroy(e);
-    for (auto& e : c->ord_ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto& x : c->ord_stream)
-        if (x) (void)hipStreamDestroy(x);
     for (auto& e : c->side_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& x : c->side)

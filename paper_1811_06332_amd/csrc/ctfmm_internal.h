@@ -124,11 +124,12 @@ struct ASys {
 // M2L over tables: tile t has TT target rows tgt[TT t ..] (-1 = none) of
 // octant tiles[t].x, and for offset i of that octant the source rows
 // src[(189 t + i) TT ..] (-1 = none); kslot[o][i] = slot of its operator.
-// Optional, for M2L orders that vary by pair: ivcnt[t] offsets of tile t
-// are active, listed in ivlist[189 t ..]; only pairs whose ord entry
-// (same index as src) equals cls contribute; rows of Msrc are ld_in bytes
-// apart and rows of L ld_out doubles apart (0 = the kernel order's own
-// strides); acc adds to L instead of writing it.
+// The offsets a tile runs are all 189, or (ivlist) the ivcnt[t] listed in
+// ivlist[189 t ..]; with ivord, list entry j of tile t runs at order
+// ivord[189 t + j] (<= the kernel order P), using the operators of that
+// order at Kpk + order * kord_stride (each order's set in the order-P chunk
+// layout, of which the first nup[order] chunks are non-zero; the launcher
+// fills nup).  acc adds to L instead of writing it.
 struct AdaptM2L {
     const int4* tiles;
     const int32_t* tgt;
@@ -137,10 +138,9 @@ struct AdaptM2L {
     int tile_base;
     const int16_t* ivlist = nullptr;
     const int32_t* ivcnt = nullptr;
-    const int8_t* ord = nullptr;
-    int cls = 0;
-    int ld_in = 0;
-    int ld_out = 0;
+    const int8_t* ivord = nullptr;
+    size_t kord_stride = 0;
+    int nup[11] = {};
     bool acc = false;
     // the offsets of a tile split over nchunk workgroups (balanced, in list
     // order); chunk c adds into L + c * chunk_stride (nchunk > 1 needs acc)
@@ -232,7 +232,9 @@ void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 size_t m2l_packed_bytes(int p, int prec);
 size_t m2l_lds_bytes(int p, int prec);
-void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk);
+// K_v fragments of order p in the M2L precision; pmask < p packs the
+// order-pmask operators in the same layout
+void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk, int pmask);
 void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32);
 // the k-quad-major FP32 rows read by launch_m2l_rb
 void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, float* M32);
@@ -304,9 +306,14 @@ void launch_wlist_adaptive(hipStream_t s, int p, int nn, const ABox* boxes, cons
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
 
 // ---- expansion orders per pair (ctfmm_adaptive.hip, ctfmm_mlp.hip) ----
+// order of every (tile, offset): the largest its pairs ask for (-1 = no pair),
+// into tq[189 tile + i]; ocnt[o][189 tile + i] = its pairs if that order is o
 void launch_m2l_orders(hipStream_t s, int tt, int ntiles, const int4* tiles, const int32_t* src_tab,
-                       const int16_t* kslot, const int8_t* ordn, int8_t* ord_tab, uint16_t* omask, int32_t* ocnt);
-void launch_class_lists(hipStream_t s, int ntiles, const uint16_t* omask, int16_t* ivlist, int32_t* ivcnt);
+                       const int16_t* kslot, const int8_t* ordn, int8_t* tq, int32_t* ocnt);
+// the active offsets of every tile (an order in tq, or with tq null a source
+// in vcount) in offset order, with their orders (tq, or p)
+void launch_active_offsets(hipStream_t s, int ntiles, int p, const int8_t* tq, const int32_t* vcount,
+                           int16_t* ivlist, int8_t* ivord, int32_t* ivcnt);
 void launch_fill0(hipStream_t s, long long n, double* a);
 void launch_mlp_forward32(hipStream_t s, long long n, const float* x, const float* prm, float* y);
 void launch_mlp_forward16(hipStream_t s, long long n, const float* x, const float* prm, const float* norm, float* y);

@@ -444,6 +444,30 @@ struct Tile {
     }
     static constexpr int NCH = cb(R);
     static constexpr int NB = nch(0);
+    // Chunk c of row tile r holds rows 16r.. and columns KW c..; its lowest
+    // total rank is rank(16r) + rank(KW c), so the order-q operator (Eq. M2L
+    // truncated at |n| + |m| <= q) is zero in it unless that sum is <= q.
+    // Chunks are stored sorted by that rank (then r, then c): the chunks of
+    // the order-q operator are then a prefix, nup(q) long, of every offset's
+    // fragments, whatever q <= P.
+    static constexpr int minord(int r, int c) { return rank_ce(16 * r) + rank_ce(KW * c); }
+    struct PosTab {
+        int v[R][NB > 0 ? NB : 1];
+        int nup[P + 1];
+    };
+    static constexpr PosTab make_pos() {
+        PosTab t{};
+        int k = 0;
+        for (int m = 0; m <= P; ++m) {
+            for (int r = 0; r < R; ++r)
+                for (int c = 0; c < nch(r); ++c)
+                    if (minord(r, c) == m) t.v[r][c] = k++;
+            t.nup[m] = k;
+        }
+        return t;
+    }
+    static constexpr PosTab PT = make_pos();
+    static constexpr int pos(int r, int c) { return PT.v[r][c]; }
     // bytes of one packed A-fragment chunk (64 lanes)
     static constexpr int CHB = PREC == PREC_F64 ? 512 : PREC == PREC_F32 ? 256 : 3 * 64 * 16;
     static constexpr int KBYTES = NCH * CHB;
@@ -467,21 +491,38 @@ __device__ inline uint16_t bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// K_v as MFMA A-fragments: Kpk[v slot][chunk][...], lane -> (row 16r + lane%16, k 16-lane group)
+// K_v as MFMA A-fragments: Kpk[v slot][chunk position][...], lane -> (row
+// 16r + lane%16, k 16-lane group); with pmask < P the order-pmask operator
+// (entries of rank(row) + rank(col) > pmask are zero), in the same layout.
 template <int P, int PREC>
-__global__ void k_pack_k(const double* __restrict__ Kt, unsigned char* __restrict__ Kpk) {
+__global__ void k_pack_k(const double* __restrict__ Kt, unsigned char* __restrict__ Kpk, int pmask) {
     using S = Tile<P, PREC>;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (long long)NOFF * S::NCH * 64) return;
     const int lane = (int)(gid % 64);
     const int ch = (int)((gid / 64) % S::NCH);
     const int v = (int)(gid / (64ll * S::NCH));
-    int r = 0;
-    while (r + 1 < S::R && S::cb(r + 1) <= ch) ++r;
-    const int c = ch - S::cb(r);
+    // the (row tile, chunk) stored at position ch (the order of Tile::make_pos)
+    int r = 0, c = 0;
+    {
+        int k = 0;
+        bool found = false;
+        for (int m = 0; m <= P && !found; ++m)
+            for (int rr = 0; rr < S::R && !found; ++rr)
+                for (int cc = 0; cc < S::nch(rr) && !found; ++cc)
+                    if (S::minord(rr, cc) == m) {
+                        if (k == ch) {
+                            r = rr;
+                            c = cc;
+                            found = true;
+                        }
+                        ++k;
+                    }
+    }
     const int row = 16 * r + (lane % 16);
     auto kval = [&](int col) -> double {
-        return (row < S::NC && col < S::NC) ? Kt[((size_t)v * S::NC + col) * S::NC + row] : 0.0;
+        if (row >= S::NC || col >= S::NC || rank_ce(row) + rank_ce(col) > pmask) return 0.0;
+        return Kt[((size_t)v * S::NC + col) * S::NC + row];
     };
     unsigned char* dst = Kpk + ((size_t)v * S::NCH + ch) * S::CHB;
     if (PREC == PREC_F64) {
@@ -521,19 +562,25 @@ __device__ inline void lds_copy16(const void* g, void* lds) {
 
 // ADAPT = true: the work unit is a tile of the adaptive tree (AdaptM2L):
 // targets, sources and the octant come from the tables instead of the
-// uniform grid, and rows are node indices.
+// uniform grid, and rows are node indices; the tile's offsets are all 189 or
+// the active ones listed for it.  ORD (adaptive only): list entry j runs at
+// order q_j = ivord[j] <= P, with the order-q_j operators (Eq. M2L truncated
+// at |n| + |m| <= q_j, stored in the order-P chunk layout, of which only the
+// first nup[q_j] chunks can be non-zero: only those are copied and
+// multiplied).
 // NW waves of 16 targets each: TT = 16 NW targets per tile (the uniform
 // grid's work unit has 64).
-template <int P, int PREC, bool ADAPT, int NW = 4>
+template <int P, int PREC, bool ADAPT, int NW = 4, bool ORD = false>
 __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __restrict__ Msrc, double* __restrict__ L,
                                                       const unsigned char* __restrict__ Kpk,
                                                       const int16_t* __restrict__ offlist,
                                                       const unsigned char* __restrict__ zero_row, const AdaptM2L ad) {
     constexpr int TT = 16 * NW;
     static_assert(ADAPT || NW == 4, "the uniform work unit has 64 targets");
+    static_assert(ADAPT || !ORD, "orders per offset need the adaptive tables");
     using S = Tile<P, PREC, TT>;
     constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB;
-    constexpr int KU = S::KBYTES / 16;        // 16-byte units of one K_v
+    constexpr int CU = S::CHB / 16;           // 16-byte units of one chunk
     constexpr int RU = S::BROW / 16;          // 16-byte units of one source row
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     unsigned char* Kb = lds;                              // [KBUF][KBYTES]
@@ -569,34 +616,38 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         }
         tco[tid] = packed;
     }
-    __syncthreads();
 
     // Tables of this workgroup in LDS (read before any copy of an iteration
-    // is issued, see below): the offsets it takes (list position j -> offset
-    // iv) and, per offset, the operator slot and (uniform grid) the packed
-    // offset.
+    // is issued, see below), per list position j: the offset, its operator
+    // slot, its order, and (uniform grid) the packed offset.
     __shared__ int16_t s_iv[189], s_ks[189], s_off[ADAPT ? 1 : 189];
-    for (int x = tid; x < 189; x += 64 * NW) {
-        if (x < nv) s_iv[x] = (int16_t)ivof(x);
+    __shared__ int8_t s_q[ORD ? 189 : 1];
+    for (int x = tid; x < nv; x += 64 * NW) {
+        const int iv = ivof(x);
+        s_iv[x] = (int16_t)iv;
         if (ADAPT) {
-            s_ks[x] = ad.kslot[o * 189 + x];
+            s_ks[x] = ad.kslot[o * 189 + iv];
         } else {
-            s_off[ADAPT ? 0 : x] = offlist[o * 189 + x];
-            s_ks[x] = (int16_t)(NOFF - 1 - offlist[o * 189 + x]);  // the operator is built for r = -v
+            s_off[ADAPT ? 0 : x] = offlist[o * 189 + iv];
+            s_ks[x] = (int16_t)(NOFF - 1 - offlist[o * 189 + iv]);  // the operator is built for r = -v
         }
+        if (ORD) s_q[ORD ? x : 0] = ad.ivord[189 * work + j0 + x];
     }
-    auto stage_k = [&](int ks, int buf) {
-        const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
+    // K_v of operator slot ks at order q: every chunk (fixed order) or the
+    // first nup[q]
+    auto stage_k = [&](int q, int ks, int buf) {
+        const unsigned char* src = Kpk + (ORD ? (size_t)q * ad.kord_stride : 0) + (size_t)ks * S::KBYTES;
         unsigned char* dst = Kb + buf * S::KBYTES;
-        for (int i = w; i * 64 < KU; i += NW) {
+        const int ku = ORD ? ad.nup[q] * CU : S::NCH * CU;
+        for (int i = w; i * 64 < ku; i += NW) {
             const int u = i * 64 + lane;
-            if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
+            if (u < ku) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
         }
     };
-    // Source rows of offset iv.  The TT rows fill TT * RU units of LDS; copy
-    // instruction k of wave w moves units g = 64 (k NW + w) + lane, i.e. unit
-    // g % RU of row slot g / RU, so each lane needs the source row of the slot
-    // of each of its NI copies.  Adaptive tiles read them from the tables
+    // Source rows of list position j.  The TT rows fill TT * RU units of LDS;
+    // copy instruction k of wave w moves units g = 64 (k NW + w) + lane, i.e.
+    // unit g % RU of row slot g / RU, so each lane needs the source row of the
+    // slot of each of its NI copies.  Adaptive tiles read them from the tables
     // (vector loads), the uniform grid computes them (LDS reads).
     constexpr int NU = TT * RU;
     constexpr int NI = (NU + 64 * NW - 1) / (64 * NW);
@@ -608,39 +659,22 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         const int sl = (64 * (k * NW + w) + lane) / RU;
         return sl < TT ? sl : TT - 1;
     };
-    // adaptive tiles: raw table entries (source row, order byte); the order
-    // filter is applied by rows_filter once the loads are known to be in
-    // (without an order table the byte is read from the row table itself,
-    // in bounds and unused: no branch, which would make the loads wait)
-    const int8_t* obase = ad.ord ? ad.ord : reinterpret_cast<const int8_t*>(ad.src);
-    auto rows_load = [&](int iv, int (&rows)[RL], int (&ords)[RL]) {
-        // unconditional loads: a register written before a load into it
-        // would make the compiler wait for every outstanding copy
-        const size_t e0 = (189 * (size_t)work + iv) * TT;
-#pragma unroll
-        for (int k = 0; k < RL; ++k) {
-            rows[k] = ad.src[e0 + slot_of(k)];
-            ords[k] = obase[e0 + slot_of(k)];
-        }
-    };
-    auto rows_filter = [&](int (&rows)[RL], const int (&ords)[RL]) {
-        if (ad.ord)
-#pragma unroll
-            for (int k = 0; k < RL; ++k)
-                if (ords[k] != ad.cls) rows[k] = -1;
-    };
-    auto rows_of = [&](int iv, int (&rows)[RL]) {
+    // (adaptive: j is the offset iv itself, read from the table beforehand;
+    // uniform grid: the list position)
+    auto rows_of = [&](int j, int (&rows)[RL]) {
         if (ADAPT) {
-            int ords[RL];
-            rows_load(iv, rows, ords);
-            rows_filter(rows, ords);
+            // unconditional loads: a register written before a load into it
+            // would make the compiler wait for every outstanding copy
+            const size_t e0 = (189 * (size_t)work + j) * TT;
+#pragma unroll
+            for (int k = 0; k < RL; ++k) rows[k] = ad.src[e0 + slot_of(k)];
             return;
         }
 #pragma unroll
         for (int k = 0; k < RL; ++k) {
             int row = -1;
             {
-                const int vs = s_off[ADAPT ? 0 : iv];
+                const int vs = s_off[ADAPT ? 0 : j];
                 const int vx = vs % 7 - 3, vy = (vs / 7) % 7 - 3, vz = vs / 49 - 3;
                 const int tc = tco[slot_of(k)];
                 if (tc >= 0) {
@@ -656,7 +690,6 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     auto stage_b = [&](const int (&rows)[RL], int buf) {
         unsigned char* dst = Bb + buf * S::BBYTES;
         const unsigned char* Mb = reinterpret_cast<const unsigned char*>(Msrc);
-        const size_t gstride = (ADAPT && ad.ld_in) ? (size_t)ad.ld_in : (size_t)S::BROW;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             if (unit_ok(k)) {
@@ -665,7 +698,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
                 const int rot = S::ROT ? sl % RU : 0;
                 const int gu = u >= rot ? u - rot : u + RU - rot;  // the row's unit that LDS unit u holds
                 const int row = rows[k];
-                const unsigned char* src = row >= 0 ? Mb + (size_t)row * gstride + gu * 16 : zero_row + gu * 16;
+                const unsigned char* src = row >= 0 ? Mb + (size_t)row * S::BROW + gu * 16 : zero_row + gu * 16;
                 lds_copy16(src, dst + (size_t)64 * 16 * (k * NW + w));
             }
         }
@@ -685,10 +718,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
 
     __syncthreads();  // the tables
     int rows_cur[RL], rows_nxt[RL];
-    rows_of(s_iv[0], rows_cur);
-    stage_k(s_ks[s_iv[0]], 0);
+    rows_of(ADAPT ? s_iv[0] : 0, rows_cur);
+    stage_k(ORD ? (int)s_q[0] : P, s_ks[0], 0);
     stage_b(rows_cur, 0);
-    if (nv > 1) rows_of(s_iv[1], rows_nxt);
+    if (nv > 1) rows_of(ADAPT ? s_iv[1] : 1, rows_nxt);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int trow = w * 16 + (lane & 15);  // this lane's target slot in B fragments
@@ -716,51 +749,62 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         const int bb = j & 1;
         const unsigned char* Kc = Kb + kb * S::KBYTES;
         const unsigned char* Bc = Bb + bb * S::BBYTES + trow * S::BROW;
+        // order of this offset (wave-uniform): chunks of lowest rank above it are zero
+        const int qj = ORD ? __builtin_amdgcn_readfirstlane((int)s_q[ORD ? j : 0]) : P;
         if (PRE) {
             const float* Kf = reinterpret_cast<const float*>(Kc);
+            const int nupj = ORD ? ad.nup[qj] : S::NCH;
 #pragma unroll
-            for (int ch = 0; ch < (PRE ? S::NCH : 1); ++ch) apre[ch] = Kf[ch * 64 + lane];
+            for (int ch = 0; ch < (PRE ? S::NCH : 1); ++ch) {
+                if (ORD && ch >= nupj) break;
+                apre[ch] = Kf[ch * 64 + lane];
+            }
 #pragma unroll
             for (int c = 0; c < (PRE ? NB : 1); ++c) bpre[c] = reinterpret_cast<const float*>(bunit(Bc, c))[kq];
         }
-        const int iv1 = j + 1 < nv ? s_iv[j + 1] : 0;
-        const int ks1 = s_ks[iv1];
-        const int iv2 = j + 2 < nv ? s_iv[j + 2] : 0;
-        int rows_nn[RL], ords_nn[RL];
-        if (!ADAPT && j + 2 < nv) rows_of(iv2, rows_nn);
+        // table entries of the next offsets, read before any copy is issued
+        const int j1 = j + 1 < nv ? j + 1 : 0;
+        const int ks1 = s_ks[j1];
+        const int q1 = ORD ? (int)s_q[ORD ? j1 : 0] : P;
+        const int iv2 = ADAPT ? s_iv[j + 2 < nv ? j + 2 : 0] : 0;
+        int rows_nn[RL];
+        if (!ADAPT && j + 2 < nv) rows_of(j + 2, rows_nn);
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): every LDS read of the iteration is done
         if (j + 1 < nv) {
-            if (S::KBUF == 2) stage_k(ks1, kb ^ 1);
+            if (S::KBUF == 2) stage_k(q1, ks1, kb ^ 1);
             stage_b(rows_nxt, bb ^ 1);
         }
-        if (ADAPT && j + 2 < nv) rows_load(iv2, rows_nn, ords_nn);  // used after this iteration's wait
+        if (ADAPT && j + 2 < nv) rows_of(iv2, rows_nn);  // used after this iteration's wait
         if (PREC == PREC_F64) {
             const double* Kd = reinterpret_cast<const double*>(Kc);
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
+                if (ORD && S::minord(0, c) > qj) break;
                 // double 4c + kq of the row: unit 2c + kq/2, half kq % 2
                 const double b = reinterpret_cast<const double*>(bunit(Bc, 2 * c + (kq >> 1)))[kq & 1];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (c < S::nch(r)) {
-                        const double a = Kd[(S::cb(r) + c) * 64 + lane];
+                    if (c < S::nch(r) && (!ORD || S::minord(r, c) <= qj)) {
+                        const double a = Kd[S::pos(r, c) * 64 + lane];
                         acc64[r][c & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[r][c & 1], 0, 0, 0);
                     }
             }
         } else if (PREC == PREC_F32) {
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
+                if (ORD && S::minord(0, c) > qj) break;
                 const float b = bpre[PRE ? c : 0];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (c < S::nch(r)) {
-                        const float a = apre[PRE ? S::cb(r) + c : 0];
+                    if (c < S::nch(r) && (!ORD || S::minord(r, c) <= qj)) {
+                        const float a = apre[PRE ? S::pos(r, c) : 0];
                         acc32[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc32[r][c & 1], 0, 0, 0);
                     }
             }
         } else {
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
+                if (ORD && S::minord(0, c) > qj) break;
                 // this lane's 8 consecutive k of its target (units 8c + 2kq and
                 // the next), split into three BF16 pieces
                 const v4f x0 = *reinterpret_cast<const v4f*>(bunit(Bc, 8 * c + 2 * kq));
@@ -780,8 +824,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (c < S::nch(r)) {
-                        const bf16x8* A = reinterpret_cast<const bf16x8*>(Kc + (S::cb(r) + c) * S::CHB);
+                    if (c < S::nch(r) && (!ORD || S::minord(r, c) <= qj)) {
+                        const bf16x8* A = reinterpret_cast<const bf16x8*>(Kc + S::pos(r, c) * S::CHB);
                         const bf16x8 a0 = A[lane], a1 = A[64 + lane], a2 = A[128 + lane];
                         accb[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, accb[r][0], 0, 0, 0);
                         accb[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, accb[r][1], 0, 0, 0);
@@ -794,7 +838,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         }
         if (S::KBUF == 1 && j + 1 < nv) {
             __syncthreads();  // every wave is done with this offset's K_v
-            stage_k(ks1, 0);
+            stage_k(q1, ks1, 0);
         }
         // unconditional, so that no load is outstanding at the top of the
         // loop on any path (the compiler turns any wait behind a mix of
@@ -804,7 +848,6 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (j + 1 < nv) {
-            if (ADAPT && j + 2 < nv) rows_filter(rows_nn, ords_nn);
 #pragma unroll
             for (int k = 0; k < RL; ++k) rows_nxt[k] = rows_nn[k];
         }
@@ -818,9 +861,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         if (par >= nparents) return;
         trow_out = par * 8 + o;
     }
-    const int ldo = (ADAPT && ad.ld_out) ? ad.ld_out : LDM;
     const bool acc_out = ADAPT && ad.acc;
-    double* Lt = L + (ADAPT ? (size_t)chunk * ad.chunk_stride : 0) + (size_t)trow_out * ldo;
+    double* Lt = L + (ADAPT ? (size_t)chunk * ad.chunk_stride : 0) + (size_t)trow_out * LDM;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (PREC == PREC_F64) {
@@ -867,7 +909,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
 // issues the copies of the next K_v, the loads of the next B fragments and
 // the row-table loads of the offset after, then the MFMAs; every load of the
 // iteration is waited for at its end.
-template <int P, int NW>
+template <int P, int NW, bool ORD = false>
 __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M32k, double* __restrict__ L,
                                                     const unsigned char* __restrict__ Kpk,
                                                     const float* __restrict__ zero_row, const AdaptM2L ad) {
@@ -878,23 +920,35 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     constexpr int NBL = (NB + 3) / 4;  // 16-byte loads per lane and offset
     static_assert(4 * NBL <= SEG, "a lane's loads stay in its segment of the row");
     constexpr int KU = S::KBYTES / 16;
+    constexpr int CU = S::CHB / 16;
     __shared__ __attribute__((aligned(16))) unsigned char Kb[2][S::KBYTES];
-    __shared__ int16_t s_ks[189];
+    __shared__ int16_t s_iv[189], s_ks[189];
+    __shared__ int8_t s_q[ORD ? 189 : 1];
     const long long blk = xcd_remap(blockIdx.x, gridDim.x);
     const long long work = ad.tile_base + blk / ad.nchunk;
     const int chunk = (int)(blk % ad.nchunk);
-    // this workgroup takes offsets [j0, j0 + nv) of the tile
-    const int j0 = 189 * chunk / ad.nchunk;
-    const int nv = 189 * (chunk + 1) / ad.nchunk - j0;
+    // this workgroup takes entries [j0, j0 + nv) of the tile's offsets (all
+    // 189, or the active ones listed for it)
+    const int nv_all = ad.ivcnt ? ad.ivcnt[work] : 189;
+    const int j0 = (int)((long long)nv_all * chunk / ad.nchunk);
+    const int nv = (int)((long long)nv_all * (chunk + 1) / ad.nchunk) - j0;
     if (nv == 0) return;
     const int o = ad.tiles[work].x;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int x = tid; x < 189; x += 64 * NW) s_ks[x] = ad.kslot[o * 189 + x];
-    auto stage_k = [&](int ks, int buf) {
-        const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
-        for (int i = w; i * 64 < KU; i += NW) {
+    for (int x = tid; x < nv; x += 64 * NW) {
+        const int iv = ad.ivlist ? (int)ad.ivlist[189 * work + j0 + x] : j0 + x;
+        s_iv[x] = (int16_t)iv;
+        s_ks[x] = ad.kslot[o * 189 + iv];
+        if (ORD) s_q[ORD ? x : 0] = ad.ivord[189 * work + j0 + x];
+    }
+    // K_v of operator slot ks at order q: every chunk (fixed order) or the
+    // first nup[q] (the others are zero)
+    auto stage_k = [&](int q, int ks, int buf) {
+        const unsigned char* src = Kpk + (ORD ? (size_t)q * ad.kord_stride : 0) + (size_t)ks * S::KBYTES;
+        const int ku = ORD ? ad.nup[q] * CU : KU;
+        for (int i = w; i * 64 < ku; i += NW) {
             const int u = i * 64 + lane;
-            if (u < KU) lds_copy16(src + (size_t)u * 16, &Kb[buf][i * 1024]);
+            if (u < ku) lds_copy16(src + (size_t)u * 16, &Kb[buf][i * 1024]);
         }
     };
     const int kq = lane >> 4;
@@ -916,30 +970,41 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
     float bcur[4 * NBL], bnxt[4 * NBL], apre[NCH];
-    __syncthreads();  // s_ks
-    stage_k(s_ks[j0], 0);
-    load_b(row_of(j0), bcur);
-    int rnxt = nv > 1 ? row_of(j0 + 1) : -1;
+    __syncthreads();  // the tables
+    stage_k(ORD ? (int)s_q[0] : P, s_ks[0], 0);
+    load_b(row_of(s_iv[0]), bcur);
+    int rnxt = nv > 1 ? row_of(s_iv[1]) : -1;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int j = 0; j < nv; ++j) {
         const float* Kf = reinterpret_cast<const float*>(Kb[j & 1]);
+        // this offset's order (wave-uniform) and the chunks it needs
+        const int qj = ORD ? __builtin_amdgcn_readfirstlane((int)s_q[ORD ? j : 0]) : P;
+        const int nupj = ORD ? ad.nup[qj] : NCH;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) apre[ch] = Kf[ch * 64 + lane];
-        const int ks1 = s_ks[j + 1 < nv ? j0 + j + 1 : j0];
+        for (int ch = 0; ch < NCH; ++ch) {
+            if (ORD && ch >= nupj) break;
+            apre[ch] = Kf[ch * 64 + lane];
+        }
+        // table entries of the next offsets, read before any copy is issued
+        const int j1 = j + 1 < nv ? j + 1 : 0;
+        const int ks1 = s_ks[j1];
+        const int q1 = ORD ? (int)s_q[ORD ? j1 : 0] : P;
+        const int iv2 = s_iv[j + 2 < nv ? j + 2 : 0];
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the LDS reads of the iteration are done
         int rnn = -1;
         if (j + 1 < nv) {
-            stage_k(ks1, (j + 1) & 1);
+            stage_k(q1, ks1, (j + 1) & 1);
             load_b(rnxt, bnxt);
         }
-        if (j + 2 < nv) rnn = row_of(j0 + j + 2);
+        if (j + 2 < nv) rnn = row_of(iv2);
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
+            if (ORD && S::minord(0, c) > qj) break;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (c < S::nch(r))
-                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(apre[S::cb(r) + c], bcur[c], acc[r][c & 1],
+                if (c < S::nch(r) && (!ORD || S::minord(r, c) <= qj))
+                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(apre[S::pos(r, c)], bcur[c], acc[r][c & 1],
                                                                          0, 0, 0);
         }
         // every load of the iteration is waited for here (on every path); the
@@ -953,8 +1018,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     }
     const long long trow_out = ad.tgt[TT * (size_t)work + 16 * w + (lane & 15)];
     if (trow_out < 0) return;
-    const int ldo = ad.ld_out ? ad.ld_out : S::LDM;
-    double* Lt = L + (size_t)chunk * ad.chunk_stride + (size_t)trow_out * ldo;
+    double* Lt = L + (size_t)chunk * ad.chunk_stride + (size_t)trow_out * S::LDM;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         // FP32 16x16 accumulator: element i holds row 16r + 4 kq + i
@@ -1103,11 +1167,11 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
             const float b = Bf[4 * c + kq];
-            acc0[c & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kf[c * 64 + lane], b, acc0[c & 3], 0, 0, 0);
+            acc0[c & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kf[S::pos(0, c) * 64 + lane], b, acc0[c & 3], 0, 0, 0);
 #pragma unroll
             for (int r = 1; r < R; ++r)
                 if (c < S::nch(r)) {
-                    const float a = Kf[(S::cb(r) + c) * 64 + lane];
+                    const float a = Kf[S::pos(r, c) * 64 + lane];
                     acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r][c & 1], 0, 0, 0);
                 }
         }
@@ -1148,20 +1212,22 @@ hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L
     return hipGetLastError();
 }
 
-template <int P, int PREC, bool ADAPT, int NW = 4>
+template <int P, int PREC, bool ADAPT, int NW = 4, bool ORD = false>
 hipError_t m2l_tile_impl(hipStream_t s, int level, long long nwork, const void* Msrc, double* L,
                          const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row,
-                         const AdaptM2L& ad) {
+                         const AdaptM2L& ad_in) {
     using S = Tile<P, PREC, 16 * NW>;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC, ADAPT, NW>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_m2l_tile<P, PREC, ADAPT, NW, ORD>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_m2l_tile<P, PREC, ADAPT, NW>), dim3((unsigned)nwork), dim3(64 * NW), S::LDS, s, level, Msrc,
-                       L, Kpk, offlist, zero_row, ad);
+    AdaptM2L ad = ad_in;
+    for (int q = 0; q <= P; ++q) ad.nup[q] = S::PT.nup[q];
+    hipLaunchKernelGGL((k_m2l_tile<P, PREC, ADAPT, NW, ORD>), dim3((unsigned)nwork), dim3(64 * NW), S::LDS, s, level,
+                       Msrc, L, Kpk, offlist, zero_row, ad);
     return hipGetLastError();
 }
 
@@ -1174,10 +1240,10 @@ hipError_t m2l_tile_impl(hipStream_t s, int level, const void* Msrc, double* L, 
 }
 
 template <int P, int PREC>
-void pack_k_impl(hipStream_t s, const double* Kt, unsigned char* Kpk) {
+void pack_k_impl(hipStream_t s, const double* Kt, unsigned char* Kpk, int pmask) {
     using S = Tile<P, PREC>;
     const long long tot = (long long)NOFF * S::NCH * 64;
-    hipLaunchKernelGGL((k_pack_k<P, PREC>), dim3(cdiv(tot, 256)), dim3(256), 0, s, Kt, Kpk);
+    hipLaunchKernelGGL((k_pack_k<P, PREC>), dim3(cdiv(tot, 256)), dim3(256), 0, s, Kt, Kpk, pmask);
 }
 
 #define CTFMM_P_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
@@ -1231,13 +1297,13 @@ size_t m2l_lds_bytes(int p, int prec) {
     return prec == PREC_F64 ? tile_query<PREC_F64>(p, 1) : tile_query<PREC_BF16X3>(p, 1);
 }
 
-void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk) {
+void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned char* Kpk, int pmask) {
     switch (p) {
-#define CASE(PP)                                                             \
-    case PP:                                                                 \
-        if (prec == PREC_F64) pack_k_impl<PP, PREC_F64>(s, Kt, Kpk);        \
-        else if (prec == PREC_F32) pack_k_impl<PP, PREC_F32>(s, Kt, Kpk);   \
-        else pack_k_impl<PP, PREC_BF16X3>(s, Kt, Kpk);                      \
+#define CASE(PP)                                                                    \
+    case PP:                                                                        \
+        if (prec == PREC_F64) pack_k_impl<PP, PREC_F64>(s, Kt, Kpk, pmask);        \
+        else if (prec == PREC_F32) pack_k_impl<PP, PREC_F32>(s, Kt, Kpk, pmask);   \
+        else pack_k_impl<PP, PREC_BF16X3>(s, Kt, Kpk, pmask);                      \
         break;
         CTFMM_P_CASES(CASE)
 #undef CASE
@@ -1265,12 +1331,14 @@ hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msr
     }
 }
 
-template <int P, int NW>
+template <int P, int NW, bool ORD>
 hipError_t m2l_tables_prec(hipStream_t s, int prec, int ntiles, const AdaptM2L& ad, const void* Msrc, double* L,
                            const unsigned char* Kpk, const unsigned char* zero_row) {
-    if (prec == PREC_F64) return m2l_tile_impl<P, PREC_F64, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
-    if (prec == PREC_F32) return m2l_tile_impl<P, PREC_F32, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
-    return m2l_tile_impl<P, PREC_BF16X3, true, NW>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+    if (prec == PREC_F64)
+        return m2l_tile_impl<P, PREC_F64, true, NW, ORD>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+    if (prec == PREC_F32)
+        return m2l_tile_impl<P, PREC_F32, true, NW, ORD>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
+    return m2l_tile_impl<P, PREC_BF16X3, true, NW, ORD>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
 }
 
 __global__ void k_sum_chunks(int nchunk, size_t stride, const double* __restrict__ part, double* __restrict__ L) {
@@ -1293,10 +1361,12 @@ void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, fl
                        s32, M, M32);
 }
 
-template <int P, int NW>
-hipError_t m2l_rb_impl(hipStream_t s, int nwork, const AdaptM2L& ad, const float* M32k, double* L,
+template <int P, int NW, bool ORD>
+hipError_t m2l_rb_impl(hipStream_t s, int nwork, const AdaptM2L& ad_in, const float* M32k, double* L,
                        const unsigned char* Kpk, const unsigned char* zero_row) {
-    hipLaunchKernelGGL((k_m2l_rb<P, NW>), dim3((unsigned)nwork), dim3(64 * NW), 0, s, M32k, L, Kpk,
+    AdaptM2L ad = ad_in;
+    for (int q = 0; q <= P; ++q) ad.nup[q] = Tile<P, PREC_F32, 16 * NW>::PT.nup[q];
+    hipLaunchKernelGGL((k_m2l_rb<P, NW, ORD>), dim3((unsigned)nwork), dim3(64 * NW), 0, s, M32k, L, Kpk,
                        reinterpret_cast<const float*>(zero_row), ad);
     return hipGetLastError();
 }
@@ -1305,14 +1375,18 @@ hipError_t launch_m2l_rb(hipStream_t s, int p, int tt, int ntiles_in, const Adap
                          const unsigned char* Kpk, const unsigned char* zero_row) {
     if (ntiles_in <= 0) return hipSuccess;
     if (tt != 32 && tt != 64 && tt != 128) return hipErrorInvalidValue;
-    if (ad.nchunk < 1 || (ad.nchunk > 1 && !ad.acc) || ad.ivlist || ad.ord || ad.ld_in) return hipErrorInvalidValue;
+    if (ad.nchunk < 1 || (ad.nchunk > 1 && !ad.acc) || (ad.ivord && !ad.ivlist)) return hipErrorInvalidValue;
     const int nwork = ntiles_in * ad.nchunk;
+    const bool ord = ad.ivord != nullptr;
     switch (p) {
-#define CASE(PP)                                                                           \
-    case PP:                                                                               \
-        if (tt == 32) return m2l_rb_impl<PP, 2>(s, nwork, ad, M32k, L, Kpk, zero_row);     \
-        if (tt == 128) return m2l_rb_impl<PP, 8>(s, nwork, ad, M32k, L, Kpk, zero_row);    \
-        return m2l_rb_impl<PP, 4>(s, nwork, ad, M32k, L, Kpk, zero_row);
+#define CASE(PP)                                                                                          \
+    case PP:                                                                                              \
+        if (tt == 32) return ord ? m2l_rb_impl<PP, 2, true>(s, nwork, ad, M32k, L, Kpk, zero_row)         \
+                                 : m2l_rb_impl<PP, 2, false>(s, nwork, ad, M32k, L, Kpk, zero_row);       \
+        if (tt == 128) return ord ? m2l_rb_impl<PP, 8, true>(s, nwork, ad, M32k, L, Kpk, zero_row)        \
+                                  : m2l_rb_impl<PP, 8, false>(s, nwork, ad, M32k, L, Kpk, zero_row);      \
+        return ord ? m2l_rb_impl<PP, 4, true>(s, nwork, ad, M32k, L, Kpk, zero_row)                       \
+                   : m2l_rb_impl<PP, 4, false>(s, nwork, ad, M32k, L, Kpk, zero_row);
         CTFMM_P_CASES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -1323,14 +1397,18 @@ hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles_
                              const void* Msrc, double* L, const unsigned char* Kpk, const unsigned char* zero_row) {
     if (ntiles_in <= 0) return hipSuccess;
     if (tt != 32 && tt != 64 && tt != 128) return hipErrorInvalidValue;
-    if (ad.nchunk < 1 || (ad.nchunk > 1 && !ad.acc)) return hipErrorInvalidValue;
+    if (ad.nchunk < 1 || (ad.nchunk > 1 && !ad.acc) || (ad.ivord && !ad.ivlist)) return hipErrorInvalidValue;
     const int ntiles = ntiles_in * ad.nchunk;  // workgroups
+    const bool ord = ad.ivord != nullptr;
     switch (p) {
-#define CASE(PP)                                                                                         \
-    case PP:                                                                                             \
-        if (tt == 32) return m2l_tables_prec<PP, 2>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);        \
-        if (tt == 128) return m2l_tables_prec<PP, 8>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);       \
-        return m2l_tables_prec<PP, 4>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);
+#define CASE(PP)                                                                                                  \
+    case PP:                                                                                                      \
+        if (tt == 32) return ord ? m2l_tables_prec<PP, 2, true>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row)      \
+                                 : m2l_tables_prec<PP, 2, false>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);    \
+        if (tt == 128) return ord ? m2l_tables_prec<PP, 8, true>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row)     \
+                                  : m2l_tables_prec<PP, 8, false>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);   \
+        return ord ? m2l_tables_prec<PP, 4, true>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row)                    \
+                   : m2l_tables_prec<PP, 4, false>(s, prec, ntiles, ad, Msrc, L, Kpk, zero_row);
         CTFMM_P_CASES(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

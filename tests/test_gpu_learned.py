@@ -14,7 +14,7 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle  # noqa: E402
-from helpers import oracle_columns, rel  # noqa: E402
+from helpers import MAXREL_FP64, MAXREL_MIXED, maxrel, oracle_columns, rel  # noqa: E402
 from oracle import mlp as omlp  # noqa: E402
 from paper_1811_06332_amd import workloads as W  # noqa: E402
 
@@ -137,9 +137,12 @@ ORDER_TABLES = {
 }
 
 
+@pytest.mark.parametrize("targets", [0, 32, 64, 128])
 @pytest.mark.parametrize("name", sorted(ORDER_TABLES))
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_order_table_matches_oracle(name, precision):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_order_table_matches_oracle(name, precision, targets):
+    """Every M2L tile shape (targets 0 = the tuner's choice) with orders per
+    pair from a table by |v|^2 against the oracle with the same table."""
     import torch
     from paper_1811_06332_amd import ctfmm as F
     tab = np.full(28, 8, dtype=np.int32)
@@ -148,18 +151,24 @@ def test_order_table_matches_oracle(name, precision):
     xyz, q = W.plummer(3000, 31)
     f = F.FMM(8, 0, precision, root_side=None, tree="adaptive", leaf_max=24)
     try:
+        if targets:
+            f.set_m2l_tile(8, targets)
         f.set_order_table(tab)
         F.ctfmm_set_timing(f.ctx, True)
-        print(f"[case] order table {name} {precision}", flush=True)
+        print(f"[case] order table {name} {precision} tile {targets}", flush=True)
         phi, grad = f.evaluate(torch.from_numpy(xyz).cuda(), torch.from_numpy(q).cuda(), sync=True)
         st, ts = f.stats(), f.tree_stats()
+        used = f.m2l_tile(8)
     finally:
         f.close()
     po, go = oracle.fmm_adaptive(xyz, q, 8, 24, order_r2=tab)
-    tol = TOL if precision == "fp64" else 1e-6
+    tol, mtol = (TOL, MAXREL_FP64) if precision == "fp64" else (1e-6, MAXREL_MIXED)
     eP, eF = rel(phi.cpu().numpy(), po), rel(grad.cpu().numpy(), go)
-    print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e} orders={st['m2l_order_pairs']}", flush=True)
+    mP, mF = maxrel(phi.cpu().numpy(), po), maxrel(grad.cpu().numpy(), go)
+    print(f"[case] tile {used}: e_phi={eP:.3e} e_grad={eF:.3e} max {mP:.3e} {mF:.3e} "
+          f"orders={st['m2l_order_pairs']}", flush=True)
     assert eP <= tol and eF <= tol
+    assert mP <= mtol and mF <= mtol
     assert sum(st["m2l_order_pairs"]) == ts["v_pairs"]
 
 
