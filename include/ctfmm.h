@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define CTFMM_ABI_VERSION 2
+#define CTFMM_ABI_VERSION 3
 /* largest expansion order compiled in */
 #define CTFMM_P_MAX 10
 /* deepest uniform octree (2^(3*depth) leaves) */
@@ -49,11 +49,13 @@ typedef struct ctfmm_ctx ctfmm_ctx;
 
 typedef enum ctfmm_status {
     CTFMM_OK = 0,
-    CTFMM_EINVAL = 1,       /* bad argument: null pointer, n < 0, p or depth out of range,
+    CTFMM_EINVAL = 1,       /* bad argument: null pointer, n < 0, p < 0, depth out of range,
                                non-finite coordinate (reported by ctfmm_sync) */
     CTFMM_ENOMEM = 2,       /* device allocation failed (or the allocator returned NULL) */
     CTFMM_EDEVICE = 3,      /* a HIP runtime call failed */
-    CTFMM_EUNSUPPORTED = 4  /* valid request this build does not implement */
+    CTFMM_EUNSUPPORTED = 4  /* valid request this build does not implement: p above
+                               CTFMM_P_MAX, or a tree, precision or tile the build or
+                               the device does not provide */
 } ctfmm_status;
 
 typedef enum ctfmm_tree {
@@ -149,25 +151,36 @@ ctfmm_status ctfmm_default_params(ctfmm_params* prm);
 
 /* Create a context on the current HIP device, bound to hip_stream (a
  * hipStream_t; NULL = the null stream).  Builds the per-offset M2L operator
- * matrices for the requested p and precision.  *out receives the context
- * (owned by the library; release with ctfmm_destroy).
- * Errors: EINVAL (null prm/out, p, depth or ws out of range, root_side <= 0
- * or not finite), EUNSUPPORTED (tree or precision unknown), ENOMEM, EDEVICE. */
+ * matrices for the requested p and precision: for each integer offset v of
+ * the ws = 1 lists, the linear map of Eq. M2L (Sec. 2.1) from the
+ * independent multipole components to the independent local components,
+ * with D(v) from Eq. traceless grad and Eq. Detracer3 (Appendix A).  *out
+ * receives the context (owned by the library; release with ctfmm_destroy).
+ * Errors: EINVAL (null prm/out, p < 0, depth or ws out of range, root_side
+ * <= 0 or not finite), EUNSUPPORTED (p > CTFMM_P_MAX, tree or precision
+ * unknown), ENOMEM, EDEVICE. */
 ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx** out);
 
 /* Route every device workspace allocation through alloc/free (called with
- * the user pointer and the context stream).  Call before the first
- * evaluate; buffers already held are released first.  NULL alloc restores
- * hipMalloc/hipFree.  An alloc returning NULL makes the call that needed
- * memory fail with ENOMEM. */
+ * the user pointer and the context stream; frees are stream-ordered on that
+ * stream, so a caching allocator bound to it may hand the memory out again
+ * to later work on the stream).  Buffers already held are released first
+ * and the operator tables rebuilt through the new allocator.  NULL alloc
+ * restores hipMalloc/hipFree.  An alloc returning NULL makes the call that
+ * needed memory fail with ENOMEM (this one included: the tables are
+ * rebuilt here).  The Python binding routes it to torch's caching
+ * allocator. */
 typedef void* (*ctfmm_alloc_fn)(size_t bytes, void* user, void* hip_stream);
 typedef void (*ctfmm_free_fn)(void* ptr, void* user, void* hip_stream);
 ctfmm_status ctfmm_set_allocator(ctfmm_ctx* ctx, ctfmm_alloc_fn alloc, ctfmm_free_fn free_fn, void* user);
 
-/* Potential and gradient of n particles.  With the adaptive tree the call
- * builds the tree and its lists on the device and waits for the stream a
- * few times while doing so (the sizes of each level decide the next
- * launches); the numeric passes that follow are asynchronous.
+/* Potential and gradient of n particles: Phi_b = sum_{a != b} q_a / |x_b -
+ * x_a| and its gradient (Appendix B, Eq. PhiAB; Sec. 2.1, Eq. L2P), by the
+ * FMM of Appendix C: P2M (Eq. P2M), M2M (Eq. M2M), M2L (Eq. M2L), L2L (Eq.
+ * L2L), L2P (Eq. L2P) and the direct near field.  With the adaptive tree
+ * the call builds the tree and its lists on the device and waits for the
+ * stream a few times while doing so (the sizes of each level decide the
+ * next launches); the numeric passes that follow are asynchronous.
  *   xyz  dev, n*3 doubles, row-major (x0,y0,z0,x1,...)
  *   q    dev, n doubles
  *   phi  dev, n doubles, may be NULL (not written)
@@ -176,6 +189,15 @@ ctfmm_status ctfmm_set_allocator(ctfmm_ctx* ctx, ctfmm_alloc_fn alloc, ctfmm_fre
  * The workspace grows to fit n and is kept for later calls. */
 ctfmm_status ctfmm_evaluate(ctfmm_ctx* ctx, int64_t n, const double* xyz, const double* q,
                             double* phi, double* grad);
+
+/* ctfmm_evaluate with FP32 inputs and outputs (same layouts, float
+ * instead of double).  The inputs are widened to FP64 on the device, the
+ * method runs as in ctfmm_evaluate (its M2L in the context's precision),
+ * and the outputs are rounded to FP32.  The FP64 copies (56 bytes per
+ * particle) are workspace kept for later calls.  Errors as
+ * ctfmm_evaluate. */
+ctfmm_status ctfmm_evaluate_f32(ctfmm_ctx* ctx, int64_t n, const float* xyz, const float* q, float* phi,
+                                float* grad);
 
 /* Potential and gradient of nsys independent systems in one call (adaptive
  * tree only).  System s is particles offsets[s] .. offsets[s+1]-1 of the
@@ -196,8 +218,14 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* ctx, int64_t n, const double* xyz, const 
 ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* ctx, int32_t nsys, const int64_t* offsets, const int32_t* orders,
                                     const double* xyz, const double* q, double* phi, double* grad);
 
+/* ctfmm_evaluate_batched with FP32 inputs and outputs, widened and rounded
+ * as in ctfmm_evaluate_f32.  Errors as ctfmm_evaluate_batched. */
+ctfmm_status ctfmm_evaluate_batched_f32(ctfmm_ctx* ctx, int32_t nsys, const int64_t* offsets, const int32_t* orders,
+                                        const float* xyz, const float* q, float* phi, float* grad);
+
 /* Copy the expansions of one level of the last evaluate to host memory:
- * which = 0 for the multipoles M, 1 for the local expansions L.  The
+ * which = 0 for the multipoles M (Eq. P2M, Eq. M2M), 1 for the local
+ * expansions L (Eq. M2L, Eq. L2L).  The
  * values are the physical (unscaled) traceless components M_n, L_n with
  * n_z in {0,1} ((p+1)^2 per cell, ordered by rank, then n_z, then n_x
  * descending); cells row-major with x fastest (index ix + 2^l (iy + 2^l iz)).
@@ -211,7 +239,9 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* ctx, int32_t level, int32_t which,
  * Errors: EINVAL (null argument, no evaluate yet), EDEVICE. */
 ctfmm_status ctfmm_tree_stats(ctfmm_ctx* ctx, ctfmm_tree_stats_t* out);
 
-/* M2L tile shape of the adaptive tree for order p: targets per workgroup
+/* M2L tile shape of the adaptive tree for order p (a scheduling choice with
+ * no counterpart in the paper; results do not depend on it beyond
+ * rounding): targets per workgroup
  * tile, 32, 64 or 128 (one 16-target block per wavefront).  By default
  * (targets = 0) the first evaluation that needs order p times every shape
  * the device's LDS admits on its own tables and keeps the fastest for the
@@ -227,12 +257,12 @@ ctfmm_status ctfmm_get_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t* targets);
  * By default every M2L (V-list) pair uses the context order p.  Two other
  * rules choose an order p' <= p per pair; M2L of a pair is then Eq. M2L
  * truncated at |n| + |m| <= p' (the order-p' operator acting on the order-p
- * expansions), and every other operator keeps order p.  The M2L tile of a
- * group of same-level targets (one octant, up to 128 of them) at one offset
- * runs at the largest order chosen for its pairs, so no pair gets less than
- * its rule asks for; tiles are grouped by order and each group runs as one
- * accumulating M2L launch.  Per-pair orders apply to the systems whose
- * order is the context's (others of a batch keep their own order). */
+ * expansions; the truncation rule is that of Sec. 2.1), and every other
+ * operator keeps order p.  The M2L tile of a group of same-level targets
+ * (one octant, up to 128 of them) at one offset runs at the largest order
+ * chosen for its pairs, so no pair gets less than its rule asks for; one
+ * M2L launch serves every order.  Per-pair orders apply to the systems
+ * whose order is the context's (others of a batch keep their own order). */
 
 /* Order by separation: order_r2 (host, 28 ints) gives the order of a pair
  * whose integer cell offset v has |v|^2 = k (4 <= k <= 27 occur); entries
@@ -301,7 +331,8 @@ ctfmm_status ctfmm_mlp_labels(ctfmm_ctx* ctx, int64_t n, const double* M, const 
 ctfmm_status ctfmm_mlp_samples(ctfmm_ctx* ctx, int64_t npart, const double* xyz, const double* q, int64_t nsamp,
                                uint64_t seed, float* x, float* y);
 
-/* Turn per-phase HIP-event timing on (1) or off (0; default). */
+/* Turn per-phase HIP-event timing on (1) or off (0; default).  The phases
+ * are the operators of Sec. 2.1 and the tree and list construction. */
 ctfmm_status ctfmm_set_timing(ctfmm_ctx* ctx, int32_t on);
 
 /* Accumulated statistics (synchronises the stream when timing is on). */

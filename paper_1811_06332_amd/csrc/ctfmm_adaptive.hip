@@ -1674,6 +1674,26 @@ void launch_active_offsets(hipStream_t s, int ntiles, int p, const int8_t* tq, c
     hipLaunchKernelGGL(k_active_offsets, dim3(ntiles), dim3(64), 0, s, p, tq, vcount, ivlist, ivord, ivcnt);
 }
 
+// FP32 <-> FP64 copies of the caller's arrays (the FP32 entry points)
+__global__ void k_widen(long long n, const float* __restrict__ in, double* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+__global__ void k_narrow(long long n, const double* __restrict__ in, float* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+void launch_widen(hipStream_t s, long long n, const float* in, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_widen, dim3(cdiv(n, 256)), dim3(256), 0, s, n, in, out);
+}
+
+void launch_narrow(hipStream_t s, long long n, const double* in, float* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_narrow, dim3(cdiv(n, 256)), dim3(256), 0, s, n, in, out);
+}
+
 void launch_fill0(hipStream_t s, long long n, double* a) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill0, dim3(cdiv(n, 256)), dim3(256), 0, s, n, a);

@@ -220,6 +220,10 @@ struct ctfmm_ctx {
     } pend;
     ctfmm_stats_t st{};
 
+    // FP64 copies of the caller's arrays for the FP32 entry points: xyz, q, phi, grad
+    double* io[4] = {};
+    size_t io_cap[4] = {};
+
     std::vector<void*> owned;  // every workspace allocation (released on destroy)
 };
 
@@ -284,6 +288,10 @@ void reset_adaptive(ctfmm_ctx* c) {
     // pointers only: the buffers themselves are released with the rest
     c->opsets.clear();
     c->Kmix = nullptr;
+    for (int k = 0; k < 4; ++k) {
+        c->io[k] = nullptr;
+        c->io_cap[k] = 0;
+    }
     c->forests.clear();
     c->nforests = 0;
     c->tmp = nullptr;
@@ -445,8 +453,9 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     if (n <= c->cap_n) return CTFMM_OK;
     // release the previous particle workspace (tables and operators are kept)
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<void*> keep = {c->tab_blob, (void*)c->Dv, (void*)c->Kt, (void*)c->Kpk, (void*)c->offlist,
-                               (void*)c->alist, (void*)c->zero_row, (void*)c->err_flag};
+    std::vector<void*> keep = {c->tab_blob,      (void*)c->Dv,       (void*)c->Kt,       (void*)c->Kpk,
+                               (void*)c->offlist, (void*)c->alist,    (void*)c->zero_row, (void*)c->err_flag,
+                               (void*)c->io[0],   (void*)c->io[1],    (void*)c->io[2],    (void*)c->io[3]};
     std::vector<void*> rest;
     for (void* p : c->owned) {
         bool k = false;
@@ -1342,6 +1351,10 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
         g_create_err = "unknown tree type";
         return CTFMM_EUNSUPPORTED;
     }
+    if (prm->order_p > CTFMM_P_MAX) {
+        g_create_err = "expansion order above the compiled maximum (10)";
+        return CTFMM_EUNSUPPORTED;
+    }
     const bool adaptive = prm->tree == CTFMM_TREE_ADAPTIVE;
     const bool box_ok = std::isfinite(prm->root_side) && std::isfinite(prm->root_lo[0]) &&
                         std::isfinite(prm->root_lo[1]) && std::isfinite(prm->root_lo[2]) &&
@@ -1497,7 +1510,8 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
     if (offsets[0] != 0) return fail(c, CTFMM_EINVAL, "offsets[0] must be 0");
     for (int s = 0; s < nsys; ++s) {
         if (offsets[s + 1] < offsets[s]) return fail(c, CTFMM_EINVAL, "offsets must not decrease");
-        if (orders[s] < 0 || orders[s] > CTFMM_P_MAX) return fail(c, CTFMM_EINVAL, "order out of range 0..10");
+        if (orders[s] < 0) return fail(c, CTFMM_EINVAL, "negative order");
+        if (orders[s] > CTFMM_P_MAX) return fail(c, CTFMM_EUNSUPPORTED, "order above the compiled maximum (10)");
     }
     const int64_t total = offsets[nsys];
     if (total >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "total particle count must be < 2^31");
@@ -1598,6 +1612,54 @@ ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* o
     return CTFMM_OK;
 }
 
+namespace {
+
+// FP64 copies of FP32 inputs (and room for the outputs) for the FP32 entry points
+ctfmm_status widen_inputs(ctfmm_ctx* c, int64_t n, const float* xyz, const float* q) {
+    const size_t want[4] = {(size_t)3 * n, (size_t)n, (size_t)n, (size_t)3 * n};
+    for (int k = 0; k < 4; ++k)
+        if (!grow(c, c->io[k], c->io_cap[k], want[k], false)) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
+    launch_widen(c->stream, 3 * n, xyz, c->io[0]);
+    launch_widen(c->stream, n, q, c->io[1]);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+ctfmm_status narrow_outputs(ctfmm_ctx* c, int64_t n, float* phi, float* grad) {
+    if (phi) launch_narrow(c->stream, n, c->io[2], phi);
+    if (grad) launch_narrow(c->stream, 3 * n, c->io[3], grad);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+}  // namespace
+
+ctfmm_status ctfmm_evaluate_f32(ctfmm_ctx* c, int64_t n, const float* xyz, const float* q, float* phi, float* grad) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "n out of range");
+    if (n == 0) return CTFMM_OK;
+    if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
+    SCHK(widen_inputs(c, n, xyz, q));
+    SCHK(ctfmm_evaluate(c, n, c->io[0], c->io[1], phi ? c->io[2] : nullptr, grad ? c->io[3] : nullptr));
+    return narrow_outputs(c, n, phi, grad);
+}
+
+ctfmm_status ctfmm_evaluate_batched_f32(ctfmm_ctx* c, int32_t nsys, const int64_t* offsets, const int32_t* orders,
+                                        const float* xyz, const float* q, float* phi, float* grad) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (nsys < 1 || !offsets || !orders) return fail(c, CTFMM_EINVAL, "nsys >= 1 and host offsets/orders required");
+    const int64_t n = offsets[nsys];
+    if (offsets[0] != 0 || n < 0 || n >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "bad offsets");
+    if (n == 0) return CTFMM_OK;
+    if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
+    SCHK(widen_inputs(c, n, xyz, q));
+    SCHK(ctfmm_evaluate_batched(c, nsys, offsets, orders, c->io[0], c->io[1], phi ? c->io[2] : nullptr,
+                                grad ? c->io[3] : nullptr));
+    return narrow_outputs(c, n, phi, grad);
+}
+
 ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* c, int32_t level, int32_t which, double* host_out, size_t cap) {
     if (!c || !host_out) return CTFMM_EINVAL;
     const int p = c->prm.order_p;
@@ -1608,14 +1670,14 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* c, int32_t level, int32_t which, d
         return fail(c, CTFMM_EINVAL, "level must be in 2..depth and which 0 or 1");
     const size_t cnt = ((size_t)1 << (3 * level)) * nc;
     if (cap < cnt) return fail(c, CTFMM_EINVAL, "host buffer too small");
-    double* tmp = nullptr;
-    HIPCHK(c, hipMalloc(&tmp, cnt * sizeof(double)));
+    double* tmp = (double*)dev_alloc(c, cnt * sizeof(double));
+    if (!tmp) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
     const double* X = (which == 0 ? c->M : c->L) + c->lvl_off[level] * (size_t)ldm_of(p);
     launch_unscale_copy(c->stream, p, level, which, c->prm.root_side, X, tmp);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipMemcpyAsync(host_out, tmp, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipError_t e3 = hipStreamSynchronize(c->stream);
-    (void)hipFree(tmp);
+    dev_release(c, tmp);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(c, CTFMM_EDEVICE, "copy failed");
     return CTFMM_OK;
 }

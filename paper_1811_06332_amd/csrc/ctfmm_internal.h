@@ -315,6 +315,8 @@ void launch_m2l_orders(hipStream_t s, int tt, int ntiles, const int4* tiles, con
 void launch_active_offsets(hipStream_t s, int ntiles, int p, const int8_t* tq, const int32_t* vcount,
                            int16_t* ivlist, int8_t* ivord, int32_t* ivcnt);
 void launch_fill0(hipStream_t s, long long n, double* a);
+void launch_widen(hipStream_t s, long long n, const float* in, double* out);
+void launch_narrow(hipStream_t s, long long n, const double* in, float* out);
 void launch_mlp_forward32(hipStream_t s, long long n, const float* x, const float* prm, float* y);
 void launch_mlp_forward16(hipStream_t s, long long n, const float* x, const float* prm, const float* norm, float* y);
 void launch_mlp_backward(hipStream_t s, long long n, const float* x, const float* t, const float* prm, float* act,

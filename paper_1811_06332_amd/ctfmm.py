@@ -22,9 +22,10 @@ CTFMM_DEPTH_MAX = 9
 CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
-            "ctfmm_evaluate", "ctfmm_evaluate_batched", "ctfmm_copy_expansions", "ctfmm_tree_stats",
-            "ctfmm_set_m2l_tile", "ctfmm_get_m2l_tile", "ctfmm_set_order_table", "ctfmm_set_order_model",
-            "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_train", "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats",
+            "ctfmm_evaluate", "ctfmm_evaluate_f32", "ctfmm_evaluate_batched", "ctfmm_evaluate_batched_f32",
+            "ctfmm_copy_expansions", "ctfmm_tree_stats", "ctfmm_set_m2l_tile", "ctfmm_get_m2l_tile",
+            "ctfmm_set_order_table", "ctfmm_set_order_model", "ctfmm_mlp_forward", "ctfmm_mlp_backward",
+            "ctfmm_mlp_train", "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats",
             "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
 
@@ -71,7 +72,9 @@ def load():
         L.ctfmm_create.argtypes = [C.POINTER(ctfmm_params), vp, C.POINTER(vp)]
         L.ctfmm_set_allocator.argtypes = [vp, vp, vp, vp]
         L.ctfmm_evaluate.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ctfmm_evaluate_f32.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ctfmm_evaluate_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.ctfmm_evaluate_batched_f32.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.ctfmm_tree_stats.argtypes = [vp, C.POINTER(ctfmm_tree_stats_t)]
         L.ctfmm_set_m2l_tile.argtypes = [vp, i32, i32]
@@ -131,36 +134,92 @@ def ctfmm_create(prm: ctfmm_params, stream: int | None = None):
     return h.value
 
 
+def _io_check(n, dtype, xyz, q, phi, grad):
+    for t, shape in ((xyz, (n, 3)), (q, (n,)), (phi, (n,)), (grad, (n, 3))):
+        if t is None:
+            continue
+        if not t.is_cuda or str(t.dtype) != dtype or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"tensors must be contiguous cuda {dtype} of shapes [n,3], [n], [n], [n,3]")
+
+
 def ctfmm_evaluate(ctx, xyz, q, phi=None, grad=None):
     """xyz: cuda float64 [n,3] contiguous; q: cuda float64 [n]; phi [n] and
     grad [n,3] cuda float64 outputs (either may be None)."""
     n = int(q.shape[0])
-    for t, shape in ((xyz, (n, 3)), (q, (n,)), (phi, (n,)), (grad, (n, 3))):
-        if t is None:
-            continue
-        if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous() or tuple(t.shape) != shape:
-            raise ValueError("tensors must be contiguous cuda float64 of shapes [n,3], [n], [n], [n,3]")
+    _io_check(n, "torch.float64", xyz, q, phi, grad)
     _check(load().ctfmm_evaluate(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)), C.c_void_p(ctx))
+
+
+def ctfmm_evaluate_f32(ctx, xyz, q, phi=None, grad=None):
+    """As ctfmm_evaluate with cuda float32 inputs and outputs."""
+    n = int(q.shape[0])
+    _io_check(n, "torch.float32", xyz, q, phi, grad)
+    _check(load().ctfmm_evaluate_f32(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)),
+           C.c_void_p(ctx))
+
+
+def _batch_args(offsets, orders):
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    ords = np.ascontiguousarray(orders, dtype=np.int32)
+    if off.size != ords.size + 1:
+        raise ValueError("offsets must have nsys+1 entries")
+    return off, ords
 
 
 def ctfmm_evaluate_batched(ctx, offsets, orders, xyz, q, phi=None, grad=None):
     """offsets: host int64 [nsys+1]; orders: host int32 [nsys]; xyz, q, phi,
     grad as in ctfmm_evaluate for the concatenated systems."""
-    import numpy as np
-    off = np.ascontiguousarray(offsets, dtype=np.int64)
-    ords = np.ascontiguousarray(orders, dtype=np.int32)
-    nsys = int(ords.size)
-    if off.size != nsys + 1:
-        raise ValueError("offsets must have nsys+1 entries")
+    off, ords = _batch_args(offsets, orders)
     n = int(q.shape[0])
-    for t, shape in ((xyz, (n, 3)), (q, (n,)), (phi, (n,)), (grad, (n, 3))):
-        if t is None:
-            continue
-        if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous() or tuple(t.shape) != shape:
-            raise ValueError("tensors must be contiguous cuda float64 of shapes [n,3], [n], [n], [n,3]")
-    _check(load().ctfmm_evaluate_batched(C.c_void_p(ctx), nsys, C.c_void_p(off.ctypes.data),
+    _io_check(n, "torch.float64", xyz, q, phi, grad)
+    _check(load().ctfmm_evaluate_batched(C.c_void_p(ctx), int(ords.size), C.c_void_p(off.ctypes.data),
                                          C.c_void_p(ords.ctypes.data), _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)),
            C.c_void_p(ctx))
+
+
+def ctfmm_evaluate_batched_f32(ctx, offsets, orders, xyz, q, phi=None, grad=None):
+    """As ctfmm_evaluate_batched with cuda float32 inputs and outputs."""
+    off, ords = _batch_args(offsets, orders)
+    n = int(q.shape[0])
+    _io_check(n, "torch.float32", xyz, q, phi, grad)
+    _check(load().ctfmm_evaluate_batched_f32(C.c_void_p(ctx), int(ords.size), C.c_void_p(off.ctypes.data),
+                                             C.c_void_p(ords.ctypes.data), _ptr(xyz), _ptr(q), _ptr(phi),
+                                             _ptr(grad)), C.c_void_p(ctx))
+
+
+# ---------------------------------------------------------------- allocator
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def torch_allocator():
+    """(alloc, free) callbacks that take the library's device workspace from
+    torch's caching allocator on the stream the library passes.  A failed
+    allocation returns NULL (the library then reports ENOMEM).  Keep the
+    returned objects alive as long as a context uses them."""
+    import torch
+
+    def _alloc(nbytes, user, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # out of memory: the library reports ENOMEM
+            return None
+
+    def _free(ptr, user, stream):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:  # interpreter shutdown: the memory goes with the process
+            pass
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
+def ctfmm_set_allocator(ctx, alloc=None, free=None) -> None:
+    """alloc/free: ALLOC_FN/FREE_FN callbacks (None restores hipMalloc)."""
+    _check(load().ctfmm_set_allocator(C.c_void_p(ctx), C.cast(alloc, C.c_void_p) if alloc else None,
+                                      C.cast(free, C.c_void_p) if free else None, None), C.c_void_p(ctx))
 
 
 def ctfmm_copy_expansions(ctx, level: int, which: int, out) -> None:
@@ -306,7 +365,9 @@ def ctfmm_destroy(ctx) -> None:
 # ---------------------------------------------------------------- convenience
 
 class FMM:
-    """A context bound to torch's current stream on the current device.
+    """A context bound to torch's current stream on the current device, its
+    device workspace taken from torch's caching allocator (torch_alloc=False:
+    hipMalloc).
 
     tree="uniform": octree of the given depth over the cube (root_lo, root_side).
     tree="adaptive": leaves of at most leaf_max particles; depth is ignored and
@@ -314,14 +375,19 @@ class FMM:
 
     def __init__(self, p: int, depth: int = 0, precision: str = "fp64", root_lo=(0.0, 0.0, 0.0),
                  root_side: float | None = 1.0, stream: int | None = None, tree: str = "uniform",
-                 leaf_max: int = 64):
+                 leaf_max: int = 64, torch_alloc: bool = True):
         prm = ctfmm_default_params()
         prm.order_p, prm.depth, prm.precision = p, depth, PRECISIONS[precision]
         prm.tree, prm.leaf_max = TREES[tree], leaf_max
         prm.root_lo[0], prm.root_lo[1], prm.root_lo[2] = root_lo
         prm.root_side = 0.0 if root_side is None else root_side
         self.p, self.depth, self.tree = p, depth, tree
+        self.ctx = None
+        self._alloc = None
         self.ctx = ctfmm_create(prm, stream)
+        if torch_alloc:
+            self._alloc = torch_allocator()
+            ctfmm_set_allocator(self.ctx, *self._alloc)
 
     def tree_stats(self) -> dict:
         return ctfmm_tree_stats(self.ctx)
@@ -334,6 +400,30 @@ class FMM:
         if grad is None:
             grad = torch.empty((n, 3), dtype=torch.float64, device=q.device)
         ctfmm_evaluate(self.ctx, xyz, q, phi, grad)
+        if sync:
+            ctfmm_sync(self.ctx)
+        return phi, grad
+
+    def evaluate_f32(self, xyz, q, phi=None, grad=None, sync=False):
+        import torch
+        n = int(q.shape[0])
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float32, device=q.device)
+        if grad is None:
+            grad = torch.empty((n, 3), dtype=torch.float32, device=q.device)
+        ctfmm_evaluate_f32(self.ctx, xyz, q, phi, grad)
+        if sync:
+            ctfmm_sync(self.ctx)
+        return phi, grad
+
+    def evaluate_batched_f32(self, offsets, orders, xyz, q, phi=None, grad=None, sync=False):
+        import torch
+        n = int(q.shape[0])
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float32, device=q.device)
+        if grad is None:
+            grad = torch.empty((n, 3), dtype=torch.float32, device=q.device)
+        ctfmm_evaluate_batched_f32(self.ctx, offsets, orders, xyz, q, phi, grad)
         if sync:
             ctfmm_sync(self.ctx)
         return phi, grad
@@ -372,9 +462,10 @@ class FMM:
         return out
 
     def close(self):
-        if self.ctx:
+        if getattr(self, "ctx", None):
             ctfmm_destroy(self.ctx)
             self.ctx = None
+        self._alloc = None
 
     def __del__(self):
         try:

@@ -27,19 +27,19 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert F.ctfmm_version() == 2
+    assert F.ctfmm_version() == 3
     prm = F.ctfmm_default_params()
     assert (prm.order_p, prm.depth, prm.ws, prm.precision, prm.root_side) == (4, 3, 1, 0, 1.0)
     assert (prm.tree, prm.leaf_max) == (F.CTFMM_TREE_UNIFORM, 64)
 
 
 @pytest.mark.parametrize("field,value,status", [
-    ("order_p", 11, F.CTFMM_EINVAL), ("order_p", -1, F.CTFMM_EINVAL), ("depth", 10, F.CTFMM_EINVAL),
+    ("order_p", 11, F.CTFMM_EUNSUPPORTED), ("order_p", -1, F.CTFMM_EINVAL), ("depth", 10, F.CTFMM_EINVAL),
     ("ws", 2, F.CTFMM_EINVAL), ("root_side", 0.0, F.CTFMM_EINVAL), ("root_side", float("nan"), F.CTFMM_EINVAL),
     ("tree", 7, F.CTFMM_EUNSUPPORTED),
     # adaptive tree: leaf_max >= 1; root_side <= 0 is the automatic cube but must be finite
     ("adaptive:leaf_max", 0, F.CTFMM_EINVAL), ("adaptive:root_side", float("inf"), F.CTFMM_EINVAL),
-    ("adaptive:order_p", 11, F.CTFMM_EINVAL),
+    ("adaptive:order_p", 11, F.CTFMM_EUNSUPPORTED),
 ])
 def test_create_rejects_bad_params(field, value, status):
     lib = F.load()
@@ -58,7 +58,10 @@ def test_null_arguments():
     lib = F.load()
     assert lib.ctfmm_create(None, None, None) == F.CTFMM_EINVAL
     assert lib.ctfmm_evaluate(None, 1, None, None, None, None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_evaluate_f32(None, 1, None, None, None, None) == F.CTFMM_EINVAL
     assert lib.ctfmm_evaluate_batched(None, 1, None, None, None, None, None, None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_evaluate_batched_f32(None, 1, None, None, None, None, None, None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_set_allocator(None, None, None, None) == F.CTFMM_EINVAL
     assert lib.ctfmm_sync(None) == F.CTFMM_EINVAL
     assert lib.ctfmm_default_params(None) == F.CTFMM_EINVAL
     lib.ctfmm_destroy(None)

@@ -152,7 +152,11 @@ def test_order_table_matches_oracle(name, precision, targets):
     f = F.FMM(8, 0, precision, root_side=None, tree="adaptive", leaf_max=24)
     try:
         if targets:
-            f.set_m2l_tile(8, targets)
+            try:
+                f.set_m2l_tile(8, targets)
+            except F.CtfmmError as e:
+                assert e.status == F.CTFMM_EUNSUPPORTED
+                pytest.skip(f"a tile of {targets} targets does not fit the LDS in {precision}")
         f.set_order_table(tab)
         F.ctfmm_set_timing(f.ctx, True)
         print(f"[case] order table {name} {precision} tile {targets}", flush=True)
