@@ -239,6 +239,33 @@ ctfmm_status ctfmm_copy_expansions(ctfmm_ctx* ctx, int32_t level, int32_t which,
  * Errors: EINVAL (null argument, no evaluate yet), EDEVICE. */
 ctfmm_status ctfmm_tree_stats(ctfmm_ctx* ctx, ctfmm_tree_stats_t* out);
 
+/* The adaptive tree and its interaction lists as built by the last
+ * evaluate (a batch: the forest of its first order), copied to host memory
+ * so that they can be compared entry by entry (Appendix C builds the same
+ * objects: the tree, and for every cell the cells it interacts with and
+ * how).  Every call writes the six sizes; each array the caller sets (non
+ * NULL) is filled and must hold the size it is documented with.  Nodes are
+ * numbered level by level, in Morton order within a level.
+ *   key[nodes]     Morton prefix of the node's cell at its level (3 * level
+ *                  bits, x in the lowest bit of each triple)
+ *   level, leaf, parent (-1 for roots), pb, pe [nodes]: the node's sorted
+ *                  particle range [pb, pe)
+ *   perm[particles] input index of the particle at sorted position s
+ *   u_off, w_off, x_off [nodes+1] and u_list, w_list, x_list: the U, W and X
+ *                  list of node i in L_list[L_off[i] .. L_off[i+1])
+ *   v_pairs[v_len][2] (target, source) of every M2L pair
+ * Synchronises the stream.  Errors: EINVAL (null io, no adaptive evaluate
+ * yet), EUNSUPPORTED (uniform tree), ENOMEM, EDEVICE. */
+typedef struct ctfmm_tree_copy_t {
+    int64_t nodes, particles, u_len, v_len, w_len, x_len;
+    uint64_t* key;
+    int32_t *level, *leaf, *parent, *pb, *pe;
+    int32_t* perm;
+    int32_t *u_off, *u_list, *w_off, *w_list, *x_off, *x_list;
+    int32_t* v_pairs;
+} ctfmm_tree_copy_t;
+ctfmm_status ctfmm_copy_tree(ctfmm_ctx* ctx, ctfmm_tree_copy_t* io);
+
 /* M2L tile shape of the adaptive tree for order p (a scheduling choice with
  * no counterpart in the paper; results do not depend on it beyond
  * rounding): targets per workgroup
@@ -269,6 +296,20 @@ ctfmm_status ctfmm_get_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t* targets);
  * must lie in 0..p.  NULL restores the fixed order.  Errors: EINVAL,
  * EUNSUPPORTED (uniform tree). */
 ctfmm_status ctfmm_set_order_table(ctfmm_ctx* ctx, const int32_t* order_r2);
+
+/* Orders from a reproducible map of (source cell, distance class), to check
+ * the per-pair-order machinery (the per-tile maximum, the operators of
+ * every order, the single M2L launch) against an independent
+ * implementation with the same map: the order of source cell C (Morton
+ * prefix key, level l, system s of a batch, 0 for a single system) in
+ * distance class k (0..14, the occupied |v|^2 values 4, 5, 6, 8, 9, 10,
+ * 11, 12, 13, 14, 17, 18, 19, 22, 27 in that order) is pmin + h mod (p -
+ * pmin + 1), h = S(S(S(seed ^ key) ^ l) ^ (16 s + k)), S the SplitMix64
+ * output function (increment 0x9E3779B97F4A7C15, then z ^= z >> 30,
+ * z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *= 0x94D049BB133111EB,
+ * z ^= z >> 31).  Errors: EINVAL (pmin outside 0..p), EUNSUPPORTED
+ * (uniform tree). */
+ctfmm_status ctfmm_set_order_hash(ctfmm_ctx* ctx, uint64_t seed, int32_t pmin);
 
 /* The expansion-order network: 12 inputs -> 64 -> 64 -> 9 outputs, ReLU
  * after both hidden layers.  Parameters are CTFMM_MLP_NPARAM floats in this

@@ -68,6 +68,11 @@ def _lib():
         L.oracle_fmm_adaptive_orders.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
                                                  C.c_void_p, C.c_void_p, i32, C.c_void_p]
         L.oracle_fmm_adaptive_orders.restype = i32
+        L.oracle_fmm_adaptive_pair_orders.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
+                                                      C.c_void_p, C.c_void_p, i32, C.c_void_p]
+        L.oracle_fmm_adaptive_pair_orders.restype = i32
+        L.oracle_adaptive_tree.argtypes = [i64, _dp, i32, _dp, d, C.c_void_p] + [C.c_void_p] * 15
+        L.oracle_adaptive_tree.restype = i32
         _lib_handle = L
     return _lib_handle
 
@@ -222,12 +227,14 @@ def auto_root(xyz):
 
 
 def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=0, stats=False,
-                 order_r2=None):
+                 order_r2=None, v_orders=None):
     """Full FMM on the adaptive octree (see oracle_fmm_adaptive).  lo/side
     None/0 selects the automatic root cube.  With stats=True also returns a
     dict of tree and list sizes and the root box.  order_r2 (28 ints, index
     |v|^2) sets the M2L order of every V-list pair by its offset (see
-    oracle_fmm_adaptive_orders)."""
+    oracle_fmm_adaptive_orders); v_orders (one per V-list entry, in the
+    V_list order of adaptive_tree) sets it pair by pair (see
+    oracle_fmm_adaptive_pair_orders)."""
     xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
     n = xyz.shape[0]
     if targets is None:
@@ -240,7 +247,10 @@ def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=
     lo_arr = _vec(lo if lo is not None else (0.0, 0.0, 0.0), 3)
     args = (n, np.ascontiguousarray(xyz.ravel()), q, p, leaf_max, lo_arr, float(side) if lo is not None else 0.0,
             nt, tp, phi, grad, st.ctypes.data, root.ctypes.data, nthreads)
-    if order_r2 is None:
+    if v_orders is not None:
+        vo = np.ascontiguousarray(np.asarray(v_orders, dtype=np.int8))
+        rc = _lib().oracle_fmm_adaptive_pair_orders(*args, vo.ctypes.data)
+    elif order_r2 is None:
         rc = _lib().oracle_fmm_adaptive(*args)
     else:
         otab = np.ascontiguousarray(np.asarray(order_r2, dtype=np.int32))
@@ -256,6 +266,40 @@ def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=
     info = {k: int(v) for k, v in zip(names, st[:7])}
     info["root_lo"] = root[:3].copy(); info["root_side"] = float(root[3])
     return phi, grad, info
+
+
+def adaptive_tree(xyz, leaf_max, lo=None, side=0.0):
+    """The adaptive tree and U/V/W/X lists of fmm_adaptive (see
+    oracle_adaptive_tree): a dict of numpy arrays level, key, leaf, parent,
+    pb, pe (per node, the oracle's numbering), order (input index of each
+    sorted position) and, for L in U, V, W, X, L_off [nodes+1] and L_list."""
+    xyz = _vec(xyz).reshape(-1, 3)
+    n = xyz.shape[0]
+    flat = np.ascontiguousarray(xyz.ravel())
+    lo_arr = _vec(lo if lo is not None else (0.0, 0.0, 0.0), 3)
+    sd = float(side) if lo is not None else 0.0
+    sizes = np.zeros(6, dtype=np.int64)
+    L = _lib()
+    nulls = [None] * 15
+    rc = L.oracle_adaptive_tree(n, flat, leaf_max, lo_arr, sd, sizes.ctypes.data, *nulls)
+    if rc != 0:
+        raise RuntimeError(f"oracle_adaptive_tree failed with code {rc}")
+    nn = int(sizes[0])
+    out = {"level": np.zeros(nn, np.int32), "key": np.zeros(nn, np.uint64), "leaf": np.zeros(nn, np.int32),
+           "parent": np.zeros(nn, np.int32), "pb": np.zeros(nn, np.int64), "pe": np.zeros(nn, np.int64),
+           "order": np.zeros(n, np.int64)}
+    for k, name in enumerate("UVWX"):
+        out[name + "_off"] = np.zeros(nn + 1, np.int64)
+        out[name + "_list"] = np.zeros(max(int(sizes[2 + k]), 1), np.int32)
+    args = [out[k].ctypes.data for k in ("level", "key", "leaf", "parent", "pb", "pe", "order")]
+    for name in "UVWX":
+        args += [out[name + "_off"].ctypes.data, out[name + "_list"].ctypes.data]
+    rc = L.oracle_adaptive_tree(n, flat, leaf_max, lo_arr, sd, sizes.ctypes.data, *args)
+    if rc != 0:
+        raise RuntimeError(f"oracle_adaptive_tree failed with code {rc}")
+    for k, name in enumerate("UVWX"):
+        out[name + "_list"] = out[name + "_list"][: int(sizes[2 + k])]
+    return out
 
 
 def max_threads() -> int:

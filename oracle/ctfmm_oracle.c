@@ -916,14 +916,14 @@ static void oa_free(oatree *T)
 static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
                              const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
                              double *phi, double *grad, int64_t *stats, double *root_out, int nthreads,
-                             const int *order_r2);
+                             const int *order_r2, const int8_t *vorder);
 
 int oracle_fmm_adaptive(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
                         const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
                         double *phi, double *grad, int64_t *stats, double *root_out, int nthreads)
 {
     return fmm_adaptive_impl(n, xyz, q, p, leaf_max, lo_in, side_in, nt, tgt, phi, grad, stats, root_out,
-                             nthreads, NULL);
+                             nthreads, NULL, NULL);
 }
 
 /*
@@ -942,13 +942,127 @@ int oracle_fmm_adaptive_orders(int64_t n, const double *xyz, const double *q, in
     for (int k = 4; k <= 27; ++k)
         if (order_r2[k] < 0 || order_r2[k] > p) return -1;
     return fmm_adaptive_impl(n, xyz, q, p, leaf_max, lo_in, side_in, nt, tgt, phi, grad, stats, root_out,
-                             nthreads, order_r2);
+                             nthreads, order_r2, NULL);
+}
+
+/*
+ * The adaptive FMM with the M2L order of every V-list pair given: entry k
+ * of node i's V list (the order of oracle_adaptive_tree) is translated by
+ * Eq. M2L truncated at |n| + |m| <= vorder[V_off[i] + k] (<= p), acting on
+ * the order-p expansions.  Every other operator keeps order p.
+ */
+int oracle_fmm_adaptive_pair_orders(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
+                                    const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
+                                    double *phi, double *grad, int64_t *stats, double *root_out, int nthreads,
+                                    const int8_t *vorder)
+{
+    if (!vorder) return -1;
+    return fmm_adaptive_impl(n, xyz, q, p, leaf_max, lo_in, side_in, nt, tgt, phi, grad, stats, root_out,
+                             nthreads, NULL, vorder);
+}
+
+/*
+ * The adaptive tree of n particles and its U/V/W/X lists: root cube (given,
+ * or the automatic cube), 63-bit keys, particles sorted by key (ties by
+ * index), nodes split while they hold more than leaf_max particles, then the
+ * lists by tree recursion.  Returns 0 or -2 (allocation).
+ */
+static int oa_make_tree(oatree *T, int64_t n, const double *xyz, const double *q, int p, int leaf_max,
+                        const double lo_in[3], double side_in)
+{
+    memset(T, 0, sizeof(*T));
+    T->p = p; T->leaf_max = leaf_max; T->n = n; T->xyz = xyz; T->q = q; T->nf = g_nfull[p];
+    if (side_in > 0.0) {
+        T->lo[0] = lo_in[0]; T->lo[1] = lo_in[1]; T->lo[2] = lo_in[2]; T->side = side_in;
+    } else {
+        oracle_auto_root(n, xyz, T->lo, &T->side);
+    }
+    T->order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    T->key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint64_t *pkey = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    T->leaf_of = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!T->order || !T->key || !pkey || !T->leaf_of) { free(pkey); return -2; }
+    for (int64_t a = 0; a < n; ++a) {
+        uint64_t c[3];
+        for (int d = 0; d < 3; ++d) {
+            double s = floor((xyz[3 * a + d] - T->lo[d]) / T->side * (double)((int64_t)1 << OA_DMAX));
+            int64_t i = (int64_t)s;
+            if (s < 0.0) i = 0;
+            if (i > ((int64_t)1 << OA_DMAX) - 1) i = ((int64_t)1 << OA_DMAX) - 1;
+            c[d] = (uint64_t)i;
+        }
+        pkey[a] = oa_spread(c[0]) | (oa_spread(c[1]) << 1) | (oa_spread(c[2]) << 2);
+        T->order[a] = a;
+    }
+    memcpy(T->key, pkey, (size_t)n * sizeof(uint64_t));
+    g_sort_tree = T;
+    qsort(T->order, (size_t)n, sizeof(int64_t), cmp_key);
+    for (int64_t s = 0; s < n; ++s) T->key[s] = pkey[T->order[s]];
+    free(pkey);
+    oa_new_node(T, 0, 0, 0, n, -1);
+    oa_split(T, 0);
+    for (int i = 0; i < T->nn; ++i)
+        if (T->nd[i].leaf)
+            for (int64_t s = T->nd[i].b; s < T->nd[i].e; ++s) T->leaf_of[T->order[s]] = i;
+    oa_build_lists(T);
+    return 0;
+}
+
+/*
+ * The adaptive tree and lists of oracle_fmm_adaptive, for an element-by-element
+ * comparison.  sizes[6] receives: nodes, particles, and the total lengths of
+ * the U, V, W and X lists.  With the arrays given (each may be NULL), node i
+ * (the oracle's numbering: depth-first creation order) gets its level, its
+ * Morton prefix key (3*level bits, x in bit 0 of each triple), leaf flag,
+ * parent (-1 for the root) and sorted particle range [pb, pe); order[s] is
+ * the input index at sorted position s; list L of node i is
+ * L_list[L_off[i] .. L_off[i+1]) (node indices, in the oracle's order).
+ * Returns 0, -1 (arguments) or -2 (allocation).
+ */
+int oracle_adaptive_tree(int64_t n, const double *xyz, int leaf_max, const double lo_in[3], double side_in,
+                         int64_t *sizes, int32_t *level, uint64_t *key, int32_t *leaf, int32_t *parent,
+                         int64_t *pb, int64_t *pe, int64_t *order, int64_t *u_off, int32_t *u_list,
+                         int64_t *v_off, int32_t *v_list, int64_t *w_off, int32_t *w_list, int64_t *x_off,
+                         int32_t *x_list)
+{
+    init_tables();
+    if (n < 1 || leaf_max < 1 || !sizes) return -1;
+    oatree T;
+    if (oa_make_tree(&T, n, xyz, NULL, 0, leaf_max, lo_in, side_in) != 0) { oa_free(&T); return -2; }
+    ivec *lists[4] = {T.U, T.V, T.W, T.X};
+    int64_t *offs[4] = {u_off, v_off, w_off, x_off};
+    int32_t *vals[4] = {u_list, v_list, w_list, x_list};
+    sizes[0] = T.nn;
+    sizes[1] = n;
+    for (int k = 0; k < 4; ++k) {
+        int64_t tot = 0;
+        for (int i = 0; i < T.nn; ++i) {
+            if (offs[k]) offs[k][i] = tot;
+            for (int j = 0; j < lists[k][i].n; ++j)
+                if (vals[k]) vals[k][tot + j] = lists[k][i].v[j];
+            tot += lists[k][i].n;
+        }
+        if (offs[k]) offs[k][T.nn] = tot;
+        sizes[2 + k] = tot;
+    }
+    for (int i = 0; i < T.nn; ++i) {
+        const oanode *x = &T.nd[i];
+        if (level) level[i] = x->level;
+        if (key) key[i] = x->pre;
+        if (leaf) leaf[i] = x->leaf;
+        if (parent) parent[i] = x->parent;
+        if (pb) pb[i] = x->b;
+        if (pe) pe[i] = x->e;
+    }
+    if (order) memcpy(order, T.order, (size_t)n * sizeof(int64_t));
+    oa_free(&T);
+    return 0;
 }
 
 static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int p, int leaf_max,
                              const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt,
                              double *phi, double *grad, int64_t *stats, double *root_out, int nthreads,
-                             const int *order_r2)
+                             const int *order_r2, const int8_t *vorder)
 {
     init_tables();
     if (p < 0 || p > OR_PMAX || n < 1 || leaf_max < 1) return -1;
@@ -958,42 +1072,15 @@ static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int 
     (void)nthreads;
 #endif
     oatree T;
-    memset(&T, 0, sizeof(T));
-    T.p = p; T.leaf_max = leaf_max; T.n = n; T.xyz = xyz; T.q = q; T.nf = g_nfull[p];
-    if (side_in > 0.0) {
-        T.lo[0] = lo_in[0]; T.lo[1] = lo_in[1]; T.lo[2] = lo_in[2]; T.side = side_in;
-    } else {
-        oracle_auto_root(n, xyz, T.lo, &T.side);
-    }
+    if (oa_make_tree(&T, n, xyz, q, p, leaf_max, lo_in, side_in) != 0) { oa_free(&T); return -2; }
     if (root_out) { root_out[0] = T.lo[0]; root_out[1] = T.lo[1]; root_out[2] = T.lo[2]; root_out[3] = T.side; }
-    T.order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
-    T.key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    uint64_t *pkey = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    T.leaf_of = (int64_t *)malloc((size_t)n * sizeof(int64_t));
-    if (!T.order || !T.key || !pkey || !T.leaf_of) { free(pkey); oa_free(&T); return -2; }
-    for (int64_t a = 0; a < n; ++a) {
-        uint64_t c[3];
-        for (int d = 0; d < 3; ++d) {
-            double s = floor((xyz[3 * a + d] - T.lo[d]) / T.side * (double)((int64_t)1 << OA_DMAX));
-            int64_t i = (int64_t)s;
-            if (s < 0.0) i = 0;
-            if (i > ((int64_t)1 << OA_DMAX) - 1) i = ((int64_t)1 << OA_DMAX) - 1;
-            c[d] = (uint64_t)i;
-        }
-        pkey[a] = oa_spread(c[0]) | (oa_spread(c[1]) << 1) | (oa_spread(c[2]) << 2);
-        T.order[a] = a;
-    }
-    memcpy(T.key, pkey, (size_t)n * sizeof(uint64_t));
-    g_sort_tree = &T;
-    qsort(T.order, (size_t)n, sizeof(int64_t), cmp_key);
-    for (int64_t s = 0; s < n; ++s) T.key[s] = pkey[T.order[s]];
-    free(pkey);
-    oa_new_node(&T, 0, 0, 0, n, -1);
-    oa_split(&T, 0);
-    for (int i = 0; i < T.nn; ++i)
-        if (T.nd[i].leaf)
-            for (int64_t s = T.nd[i].b; s < T.nd[i].e; ++s) T.leaf_of[T.order[s]] = i;
-    oa_build_lists(&T);
+    /* first entry of every node's V list in the V-list order of oracle_adaptive_tree */
+    int64_t *voff = (int64_t *)calloc((size_t)T.nn + 1, sizeof(int64_t));
+    if (!voff) { oa_free(&T); return -2; }
+    for (int i = 0; i < T.nn; ++i) voff[i + 1] = voff[i] + T.V[i].n;
+    if (vorder)
+        for (int64_t k = 0; k < voff[T.nn]; ++k)
+            if (vorder[k] < 0 || vorder[k] > p) { free(voff); oa_free(&T); return -1; }
     int nf = T.nf;
     size_t nnodes = T.nn > 0 ? (size_t)T.nn : 1;
     T.M = (double **)calloc(nnodes, sizeof(double *));
@@ -1069,6 +1156,7 @@ static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int 
                     int64_t dx = T.nd[i].ix - T.nd[C].ix, dy = T.nd[i].iy - T.nd[C].iy, dz = T.nd[i].iz - T.nd[C].iz;
                     order = order_r2[dx * dx + dy * dy + dz * dz];
                 }
+                if (vorder) order = vorder[voff[i] + k];
                 oracle_m2l(order, r, T.M[C], T.L[i]);
             }
             for (int k = 0; k < T.X[i].n; ++k) {
@@ -1085,6 +1173,7 @@ static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int 
         }
     }
     free(need);
+    free(voff);
     /* evaluation: L2P + W (M2L to the particle) + U (direct) */
     int64_t cnt = tgt ? nt : n;
 #pragma omp parallel for schedule(dynamic, 64)

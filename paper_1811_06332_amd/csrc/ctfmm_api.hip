@@ -185,8 +185,11 @@ struct ctfmm_ctx {
     hipStream_t side[2] = {};  // the near field (P2P) and the X lists (P2L) beside the expansion passes
     hipEvent_t side_ev[7] = {};
     // M2L order per pair (adaptive tree): 0 = the fixed order p, 1 = a table
-    // by |v|^2, 2 = the network's decision per (source cell, distance class)
+    // by |v|^2, 2 = the network's decision per (source cell, distance class),
+    // 3 = a reproducible hash of (source cell, distance class)
     int order_mode = 0;
+    unsigned long long order_seed = 0;
+    int order_pmin = 0;
     int32_t* order_tab = nullptr;  // device [28]
     float* model = nullptr;        // device [MLP_NPARAM + 24]: parameters, input mean, input std
     float order_thr = 0.f;         // log10(target error) - margin
@@ -1157,6 +1160,8 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             const int f2 = f.lev_first[2];
             if (omode == 1) {
                 launch_order_table(st, nn, c->order_tab, f.ordn);
+            } else if (omode == 3) {
+                launch_order_hash(st, nn, f.tr, c->order_seed, c->order_pmin, p, f.ordn);
             } else {
                 const long long rows = (long long)(nn - f2) * NCLASS;
                 launch_mlp_node_features(st, f2, nn - f2, f.aM, ldm_of(p), f.mx);
@@ -1722,6 +1727,67 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
     return CTFMM_OK;
 }
 
+ctfmm_status ctfmm_copy_tree(ctfmm_ctx* c, ctfmm_tree_copy_t* io) {
+    if (!c || !io) return CTFMM_EINVAL;
+    if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "tree copies need the adaptive tree");
+    if (!c->have_result || c->nforests < 1) return fail(c, CTFMM_EINVAL, "no evaluate yet");
+    Forest& f = c->forests[0];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t nn = (size_t)f.nn, n1 = nn + 1, nt = f.tiles_host.size(), tt = (size_t)f.tt;
+    std::vector<int32_t> tgt, src;
+    if (nt > 0 && io->v_pairs) {
+        tgt.resize(tt * nt);
+        src.resize(189 * tt * nt);
+        HIPCHK(c, hipMemcpy(tgt.data(), f.tgt_tab, tgt.size() * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(src.data(), f.src_tab, src.size() * 4, hipMemcpyDeviceToHost));
+    }
+    SCHK(count_v_pairs(c, f));
+    io->nodes = (int64_t)nn;
+    io->particles = f.n;
+    io->u_len = f.tot_u;
+    io->w_len = f.tot_w;
+    io->x_len = f.tot_x;
+    io->v_len = f.v_pairs;
+    auto get = [&](void* dst, const void* from, size_t bytes) -> ctfmm_status {
+        if (dst && bytes) HIPCHK(c, hipMemcpy(dst, from, bytes, hipMemcpyDeviceToHost));
+        return CTFMM_OK;
+    };
+    SCHK(get(io->key, f.tr.key, nn * 8));
+    SCHK(get(io->parent, f.tr.par, nn * 4));
+    SCHK(get(io->pb, f.tr.pb, nn * 4));
+    SCHK(get(io->pe, f.tr.pe, nn * 4));
+    SCHK(get(io->perm, f.a_idxs, (size_t)f.n * 4));
+    SCHK(get(io->u_off, f.loff, n1 * 4));
+    SCHK(get(io->w_off, f.loff + n1, n1 * 4));
+    SCHK(get(io->x_off, f.loff + 2 * n1, n1 * 4));
+    SCHK(get(io->u_list, f.ulist, (size_t)f.tot_u * 4));
+    SCHK(get(io->w_list, f.wlist, (size_t)f.tot_w * 4));
+    SCHK(get(io->x_list, f.xlist, (size_t)f.tot_x * 4));
+    if (io->level || io->leaf) {
+        std::vector<int32_t> info(nn);
+        SCHK(get(info.data(), f.tr.info, nn * 4));
+        for (size_t i = 0; i < nn; ++i) {
+            if (io->level) io->level[i] = info[i] & 0xff;
+            if (io->leaf) io->leaf[i] = (info[i] >> 8) & 1;
+        }
+    }
+    if (io->v_pairs) {
+        int64_t k = 0;
+        for (size_t t = 0; t < nt; ++t)
+            for (size_t iv = 0; iv < 189; ++iv)
+                for (size_t r = 0; r < tt; ++r) {
+                    const int32_t a = tgt[t * tt + r], b = src[(189 * t + iv) * tt + r];
+                    if (a < 0 || b < 0) continue;
+                    if (k >= f.v_pairs) return fail(c, CTFMM_EDEVICE, "M2L tables hold more pairs than counted");
+                    io->v_pairs[2 * k] = a;
+                    io->v_pairs[2 * k + 1] = b;
+                    ++k;
+                }
+        if (k != f.v_pairs) return fail(c, CTFMM_EDEVICE, "M2L tables hold fewer pairs than counted");
+    }
+    return CTFMM_OK;
+}
+
 ctfmm_status ctfmm_set_order_table(ctfmm_ctx* c, const int32_t* order_r2) {
     if (!c) return CTFMM_EINVAL;
     if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "per-pair orders need the adaptive tree");
@@ -1741,6 +1807,16 @@ ctfmm_status ctfmm_set_order_table(ctfmm_ctx* c, const int32_t* order_r2) {
     HIPCHK(c, hipMemcpyAsync(c->order_tab, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->order_mode = 1;
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_set_order_hash(ctfmm_ctx* c, uint64_t seed, int32_t pmin) {
+    if (!c) return CTFMM_EINVAL;
+    if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "per-pair orders need the adaptive tree");
+    if (pmin < 0 || pmin > c->prm.order_p) return fail(c, CTFMM_EINVAL, "pmin must lie in 0..p");
+    c->order_seed = seed;
+    c->order_pmin = pmin;
+    c->order_mode = 3;
     return CTFMM_OK;
 }
 

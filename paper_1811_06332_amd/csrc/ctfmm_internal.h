@@ -331,6 +331,8 @@ void launch_gather_rows(hipStream_t s, long long n, const int32_t* sel, const do
 void launch_mlp_node_features(hipStream_t s, int first, int count, const double* M, int ldm, float* x);
 void launch_mlp_decide(hipStream_t s, int first, int count, const float* y, float thr, int8_t* ord);
 void launch_order_table(hipStream_t s, int count, const int32_t* tab, int8_t* ord);
+void launch_order_hash(hipStream_t s, int count, const ATree& t, unsigned long long seed, int pmin, int p,
+                       int8_t* ord);
 
 void launch_sum_chunks(hipStream_t s, int nchunk, size_t stride, const double* part, double* L);
 

@@ -507,6 +507,36 @@ __global__ void k_order_table(int count, const int32_t* __restrict__ tab, int8_t
     ord[g] = (int8_t)tab[kClassR2[g % NCLASS]];
 }
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the increment, then the two xor-shift-multiply
+// rounds and the final xor-shift of its output function.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Reproducible orders per (source cell, distance class): pmin + h mod (p -
+// pmin + 1), h = SplitMix64 chained over (seed ^ cell key), the cell's level,
+// and 16 * its system + the class.
+__global__ void k_order_hash(int count, ATree t, unsigned long long seed, int pmin, int p, int8_t* __restrict__ ord) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long long)count * NCLASS) return;
+    const int node = (int)(g / NCLASS), cls = (int)(g % NCLASS);
+    uint64_t z = splitmix64(seed ^ t.key[node]);
+    z = splitmix64(z ^ (uint64_t)(t.info[node] & 0xff));
+    z = splitmix64(z ^ (uint64_t)(16 * t.sys[node] + cls));
+    ord[g] = (int8_t)(pmin + (int)(z % (uint64_t)(p - pmin + 1)));
+}
+
+void launch_order_hash(hipStream_t s, int count, const ATree& t, unsigned long long seed, int pmin, int p,
+                       int8_t* ord) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_order_hash, dim3(cdiv((long long)count * NCLASS, 256)), dim3(256), 0, s, count, t, seed, pmin,
+                       p, ord);
+}
+
 void launch_mlp_node_features(hipStream_t s, int first, int count, const double* M, int ldm, float* x) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_mlp_node_features, dim3(cdiv((long long)count * NCLASS, 128)), dim3(128), 0, s, first, count,

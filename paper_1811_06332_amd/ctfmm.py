@@ -23,10 +23,11 @@ CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
             "ctfmm_evaluate", "ctfmm_evaluate_f32", "ctfmm_evaluate_batched", "ctfmm_evaluate_batched_f32",
-            "ctfmm_copy_expansions", "ctfmm_tree_stats", "ctfmm_set_m2l_tile", "ctfmm_get_m2l_tile",
-            "ctfmm_set_order_table", "ctfmm_set_order_model", "ctfmm_mlp_forward", "ctfmm_mlp_backward",
-            "ctfmm_mlp_train", "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats",
-            "ctfmm_reset_stats", "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
+            "ctfmm_copy_expansions", "ctfmm_copy_tree", "ctfmm_tree_stats", "ctfmm_set_m2l_tile",
+            "ctfmm_get_m2l_tile", "ctfmm_set_order_table", "ctfmm_set_order_hash", "ctfmm_set_order_model",
+            "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_train",
+            "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats", "ctfmm_reset_stats",
+            "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
 
 class CtfmmError(RuntimeError):
@@ -48,6 +49,14 @@ class ctfmm_stats_t(C.Structure):
                 ("ms_numeric", C.c_double), ("evaluations", C.c_int64), ("m2l_launches", C.c_int64),
                 ("m2l_pairs", C.c_int64), ("p2p_leaf_pairs", C.c_int64), ("graph_launches", C.c_int64),
                 ("m2l_order_pairs", C.c_int64 * 11)]
+
+
+class ctfmm_tree_copy_t(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("particles", C.c_int64), ("u_len", C.c_int64), ("v_len", C.c_int64),
+                ("w_len", C.c_int64), ("x_len", C.c_int64), ("key", C.c_void_p), ("level", C.c_void_p),
+                ("leaf", C.c_void_p), ("parent", C.c_void_p), ("pb", C.c_void_p), ("pe", C.c_void_p),
+                ("perm", C.c_void_p), ("u_off", C.c_void_p), ("u_list", C.c_void_p), ("w_off", C.c_void_p),
+                ("w_list", C.c_void_p), ("x_off", C.c_void_p), ("x_list", C.c_void_p), ("v_pairs", C.c_void_p)]
 
 
 class ctfmm_tree_stats_t(C.Structure):
@@ -77,8 +86,10 @@ def load():
         L.ctfmm_evaluate_batched_f32.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.ctfmm_tree_stats.argtypes = [vp, C.POINTER(ctfmm_tree_stats_t)]
+        L.ctfmm_copy_tree.argtypes = [vp, C.POINTER(ctfmm_tree_copy_t)]
         L.ctfmm_set_m2l_tile.argtypes = [vp, i32, i32]
         L.ctfmm_set_order_table.argtypes = [vp, vp]
+        L.ctfmm_set_order_hash.argtypes = [vp, C.c_uint64, i32]
         L.ctfmm_set_order_model.argtypes = [vp, vp, vp, C.c_double, C.c_double]
         L.ctfmm_mlp_forward.argtypes = [vp, i64, vp, vp, i32, vp]
         L.ctfmm_mlp_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
@@ -228,6 +239,29 @@ def ctfmm_copy_expansions(ctx, level: int, which: int, out) -> None:
            C.c_void_p(ctx))
 
 
+def ctfmm_copy_tree(ctx) -> dict:
+    """The adaptive tree and lists of the last evaluate as numpy arrays
+    (keys of include/ctfmm.h's ctfmm_tree_copy_t)."""
+    import numpy as np
+    io = ctfmm_tree_copy_t()
+    _check(load().ctfmm_copy_tree(C.c_void_p(ctx), C.byref(io)), C.c_void_p(ctx))
+    nn, n = int(io.nodes), int(io.particles)
+    out = {"key": np.zeros(nn, np.uint64), "v_pairs": np.zeros((max(int(io.v_len), 1), 2), np.int32)}
+    for name in ("level", "leaf", "parent", "pb", "pe"):
+        out[name] = np.zeros(nn, np.int32)
+    out["perm"] = np.zeros(n, np.int32)
+    for L, ln in (("u", io.u_len), ("w", io.w_len), ("x", io.x_len)):
+        out[L + "_off"] = np.zeros(nn + 1, np.int32)
+        out[L + "_list"] = np.zeros(max(int(ln), 1), np.int32)
+    for name, arr in out.items():
+        setattr(io, name, arr.ctypes.data)
+    _check(load().ctfmm_copy_tree(C.c_void_p(ctx), C.byref(io)), C.c_void_p(ctx))
+    out["v_pairs"] = out["v_pairs"][: int(io.v_len)]
+    for L, ln in (("u", io.u_len), ("w", io.w_len), ("x", io.x_len)):
+        out[L + "_list"] = out[L + "_list"][: int(ln)]
+    return out
+
+
 def ctfmm_tree_stats(ctx) -> dict:
     st = ctfmm_tree_stats_t()
     _check(load().ctfmm_tree_stats(C.c_void_p(ctx), C.byref(st)), C.c_void_p(ctx))
@@ -278,6 +312,10 @@ def ctfmm_set_order_table(ctx, order_r2) -> None:
     tab = np.ascontiguousarray(order_r2, dtype=np.int32)
     assert tab.size == 28
     _check(load().ctfmm_set_order_table(C.c_void_p(ctx), C.c_void_p(tab.ctypes.data)), C.c_void_p(ctx))
+
+
+def ctfmm_set_order_hash(ctx, seed: int, pmin: int) -> None:
+    _check(load().ctfmm_set_order_hash(C.c_void_p(ctx), int(seed), int(pmin)), C.c_void_p(ctx))
 
 
 def ctfmm_set_order_model(ctx, params, norm, target_rel_err: float, margin: float) -> None:
@@ -392,6 +430,9 @@ class FMM:
     def tree_stats(self) -> dict:
         return ctfmm_tree_stats(self.ctx)
 
+    def tree_copy(self) -> dict:
+        return ctfmm_copy_tree(self.ctx)
+
     def evaluate(self, xyz, q, phi=None, grad=None, sync=False):
         import torch
         n = int(q.shape[0])
@@ -445,6 +486,9 @@ class FMM:
 
     def set_order_table(self, order_r2) -> None:
         ctfmm_set_order_table(self.ctx, order_r2)
+
+    def set_order_hash(self, seed: int, pmin: int) -> None:
+        ctfmm_set_order_hash(self.ctx, seed, pmin)
 
     def set_order_model(self, params, norm, target_rel_err: float, margin: float) -> None:
         ctfmm_set_order_model(self.ctx, params, norm, target_rel_err, margin)

@@ -522,4 +522,148 @@ def pin_order_table(o):
             assert np.array_equal(gk, gf), k
 
 
+def pin_auto_root_hand_boxes(o):
+    """The automatic root cube on boxes worked out by hand: centred on the
+    bounding box, side = largest extent * (1 + 2^-20), side 1 when all
+    points coincide; every point then lies strictly inside the cube."""
+    # extents (4, 1, 0.5): side 4 (1 + 2^-20) = 4.000003814697265625, centre (1, 0.5, 2.25)
+    lo, side = o.auto_root(np.array([[-1.0, 0.0, 2.0], [3.0, 1.0, 2.5], [0.0, 0.25, 2.1]]))
+    assert side == 4.000003814697265625
+    assert tuple(lo) == (-1.0000019073486328125, -1.5000019073486328125, 0.2499980926513671875)
+    # extents (0, 0, 6): the z extent decides; the cube is centred on (7, -3, 0)
+    lo, side = o.auto_root(np.array([[7.0, -3.0, -3.0], [7.0, -3.0, 3.0]]))
+    assert side == 6.00000572204589843750
+    assert tuple(lo) == (3.99999713897705078125, -6.00000286102294921875, -3.00000286102294921875)
+    # all points on one spot: side 1 (1 + 2^-20) around it
+    lo, side = o.auto_root(np.array([[0.5, 0.5, 0.5]] * 3))
+    assert side == 1.00000095367431640625 and tuple(lo) == (-0.000000476837158203125,) * 3
+    from paper_1811_06332_amd.workloads import plummer
+    xyz, _ = plummer(3000, 45)
+    lo, side = o.auto_root(xyz)
+    assert np.all(xyz > lo) and np.all(xyz < lo + side)
+
+
+def _tree_by_definition(xyz, leaf_max):
+    """The adaptive tree built from its definition (not the oracle's code):
+    cells at level l are the 2^l-grid cells of the root cube; a cell is a
+    node if it holds a particle and its parent is a node holding more than
+    leaf_max particles (down to level 21).  Returns {(l, ix, iy, iz):
+    (sorted particle indices, leaf)} and the root box."""
+    mn, mx = xyz.min(0), xyz.max(0)
+    side = float((mx - mn).max())
+    side = (side if side > 0 else 1.0) * (1.0 + 2.0 ** -20)
+    lo = (mn + mx) * 0.5 - side * 0.5
+    D = 21
+    c = np.clip(np.floor((xyz - lo) / side * 2.0 ** D), 0, 2 ** D - 1).astype(np.int64)
+    nodes = {}
+    todo = [(0, (0, 0, 0), np.arange(len(xyz)))]
+    while todo:
+        l, (i, j, k), idx = todo.pop()
+        leaf = len(idx) <= leaf_max or l >= D
+        nodes[(l, i, j, k)] = (np.sort(idx), leaf)
+        if not leaf:
+            sub = c[idx] >> (D - l - 1)
+            for ch in {tuple(r) for r in sub}:
+                todo.append((l + 1, ch, idx[np.all(sub == ch, axis=1)]))
+    return nodes, lo, side
+
+
+def _lists_by_definition(nodes):
+    """U, V, W, X of every node by brute force over node pairs:
+    V(B): same-level cells not adjacent to B whose parents are adjacent or equal;
+    U(B), B a leaf: the leaves whose closed cubes touch B's (B included);
+    W(B), B a leaf: finer cells not adjacent to B whose parent is adjacent to B;
+    X(B): the cells C with B in W(C)."""
+    D = 21
+    keys = list(nodes)
+
+    def span(n):
+        l, i, j, k = n
+        s = 1 << (D - l)
+        return [(i * s, (i + 1) * s), (j * s, (j + 1) * s), (k * s, (k + 1) * s)]
+
+    def touch(a, b):
+        return all(x0 <= y1 and y0 <= x1 for (x0, x1), (y0, y1) in zip(span(a), span(b)))
+
+    def parent(n):
+        l, i, j, k = n
+        return (l - 1, i >> 1, j >> 1, k >> 1)
+
+    U, V, W = {n: set() for n in keys}, {n: set() for n in keys}, {n: set() for n in keys}
+    for b in keys:
+        leaf_b = nodes[b][1]
+        for a in keys:
+            if a[0] == b[0] and b[0] >= 2 and touch(parent(a), parent(b)) and not touch(a, b):
+                V[b].add(a)
+            if leaf_b and nodes[a][1] and touch(a, b):
+                U[b].add(a)
+            if leaf_b and a[0] > b[0] and not touch(a, b) and touch(parent(a), b):
+                W[b].add(a)
+    X = {n: set() for n in keys}
+    for b in keys:
+        for a in W[b]:
+            X[a].add(b)
+    return U, V, W, X
+
+
+def _decode_key(level, key):
+    ix = iy = iz = 0
+    for l in range(level):
+        ix |= ((key >> (3 * l)) & 1) << l
+        iy |= ((key >> (3 * l + 1)) & 1) << l
+        iz |= ((key >> (3 * l + 2)) & 1) << l
+    return (level, ix, iy, iz)
+
+
+def pin_adaptive_tree_and_lists_by_definition(o):
+    """The oracle's adaptive tree (nodes, leaves, parents, particles of every
+    leaf) and every U/V/W/X list equal, entry by entry, the ones built from
+    their definitions by brute force, on a cluster with leaves at several
+    levels (W and X non-empty)."""
+    from paper_1811_06332_amd.workloads import plummer
+    for xyz, leaf_max in ((plummer(700, 46)[0], 6), (np.vstack([np.random.default_rng(47).random((200, 3)),
+                                                                0.3 + 0.02 * np.random.default_rng(48).random((250, 3))]),
+                                                     5)):
+        nodes, lo, side = _tree_by_definition(xyz, leaf_max)
+        U, V, W, X = _lists_by_definition(nodes)
+        t = o.adaptive_tree(xyz, leaf_max)
+        name = [_decode_key(int(l), int(k)) for l, k in zip(t["level"], t["key"])]
+        assert sorted(name) == sorted(nodes)
+        for i, nm in enumerate(name):
+            idx, leaf = nodes[nm]
+            assert bool(t["leaf"][i]) == leaf, nm
+            par = int(t["parent"][i])
+            assert (par < 0 and nm[0] == 0) or name[par] == (nm[0] - 1, nm[1] >> 1, nm[2] >> 1, nm[3] >> 1)
+            got = np.sort(t["order"][t["pb"][i]:t["pe"][i]])
+            assert np.array_equal(got, idx), nm
+            for L, ref in (("U", U), ("V", V), ("W", W), ("X", X)):
+                ent = t[L + "_list"][t[L + "_off"][i]:t[L + "_off"][i + 1]]
+                assert len(ent) == len(set(ent.tolist())), (L, nm)
+                assert {name[e] for e in ent} == ref[nm], (L, nm)
+        assert sum(len(v) for v in W.values()) > 0 and max(n[0] for n in nodes) >= 4
+
+
+def pin_pair_orders(o):
+    """M2L orders given pair by pair: all at p reproduce the fixed order bit
+    for bit, and the orders an |v|^2 table gives each V pair (worked out
+    here from the exported tree) reproduce the table mode bit for bit."""
+    from paper_1811_06332_amd.workloads import plummer
+    xyz, q = plummer(1500, 49)
+    p, leaf = 7, 16
+    t = o.adaptive_tree(xyz, leaf)
+    nv = int(t["V_off"][-1])
+    pf, gf = o.fmm_adaptive(xyz, q, p, leaf)
+    pa, ga = o.fmm_adaptive(xyz, q, p, leaf, v_orders=np.full(nv, p, dtype=np.int8))
+    assert np.array_equal(pf, pa) and np.array_equal(gf, ga)
+    tab = np.array([p] * 4 + [3, 0, 6, p, 2, 7, 1, 5, 4, 2, 3, p, p, 1, 6, 0, p, p, 5, p, p, p, p, 2], dtype=np.int32)
+    coords = np.array([_decode_key(int(l), int(k))[1:] for l, k in zip(t["level"], t["key"])])
+    tgt = np.repeat(np.arange(len(t["level"])), np.diff(t["V_off"]))
+    d = coords[tgt] - coords[t["V_list"]]
+    vo = tab[np.sum(d * d, axis=1)].astype(np.int8)
+    pt, gt = o.fmm_adaptive(xyz, q, p, leaf, order_r2=tab)
+    pv, gv = o.fmm_adaptive(xyz, q, p, leaf, v_orders=vo)
+    assert np.array_equal(pt, pv) and np.array_equal(gt, gv)
+    assert rel(gt, gf) > 1e-8
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -65,3 +65,15 @@ def test_null_arguments():
     assert lib.ctfmm_sync(None) == F.CTFMM_EINVAL
     assert lib.ctfmm_default_params(None) == F.CTFMM_EINVAL
     lib.ctfmm_destroy(None)
+
+
+def test_splitmix64_reference_values():
+    """The order-map hash of the tests is SplitMix64: its first outputs from
+    state 0 are the published ones."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import numpy as np
+    from helpers import splitmix64
+    golden = 0x9E3779B97F4A7C15
+    outs = [int(splitmix64(np.uint64((k * golden) & 0xFFFFFFFFFFFFFFFF))) for k in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]

@@ -13,7 +13,7 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle  # noqa: E402
-from helpers import rel  # noqa: E402
+from helpers import MAXREL_FP64, MAXREL_MIXED, compare_trees, maxrel, rel  # noqa: E402
 from paper_1811_06332_amd import workloads as W  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -82,8 +82,30 @@ def test_adaptive_fp64_matches_oracle(name):
     assert got == want, (got, want)
     assert tuple(st["root_lo"]) == tuple(info["root_lo"]) and st["root_side"] == info["root_side"]
     eP, eF = rel(pg, po), rel(gg, go)
-    print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e}", flush=True)
+    mP, mF = maxrel(pg, po), maxrel(gg, go)
+    print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e} worst particle {mP:.3e} {mF:.3e}", flush=True)
     assert eP <= TOL and eF <= TOL, (eP, eF)
+    assert mP <= MAXREL_FP64 and mF <= MAXREL_FP64, (mP, mF)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_adaptive_tree_and_lists_exact(name):
+    """Integer work, bit-exact: the GPU's tree (nodes, leaves, parents, the
+    particles of every leaf) and every U, V, W and X list equal the
+    oracle's entry by entry."""
+    import torch
+    from paper_1811_06332_amd import ctfmm as F
+    make, p, leaf = CASES[name]
+    xyz, q = make()
+    f = F.FMM(p, 0, "fp64", root_side=None, tree="adaptive", leaf_max=leaf)
+    try:
+        print(f"[case] adaptive tree {name}", flush=True)
+        f.evaluate(torch.from_numpy(xyz).cuda(), torch.from_numpy(q).cuda(), sync=True)
+        tg = f.tree_copy()
+    finally:
+        f.close()
+    sizes = compare_trees(tg, oracle.adaptive_tree(xyz, leaf))
+    print(f"[case] equal entry by entry: {sizes}", flush=True)
 
 
 def test_adaptive_explicit_root_box_clamps():

@@ -14,7 +14,8 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle  # noqa: E402
-from helpers import MAXREL_FP64, MAXREL_MIXED, maxrel, oracle_columns, rel  # noqa: E402
+from helpers import (MAXREL_FP64, MAXREL_MIXED, maxrel, oracle_columns, rel,  # noqa: E402
+                     tile_max_v_orders)
 from oracle import mlp as omlp  # noqa: E402
 from paper_1811_06332_amd import workloads as W  # noqa: E402
 
@@ -174,6 +175,46 @@ def test_order_table_matches_oracle(name, precision, targets):
     assert eP <= tol and eF <= tol
     assert mP <= mtol and mF <= mtol
     assert sum(st["m2l_order_pairs"]) == ts["v_pairs"]
+
+
+@pytest.mark.parametrize("targets", [32, 64, 128])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_order_map_matches_oracle(precision, targets):
+    """Orders per (source cell, distance class) from the reproducible map of
+    ctfmm_set_order_hash, the per-tile maximum rule of the learned mode:
+    against the oracle given, pair by pair, the orders that rule yields
+    (worked out from the oracle's own tree); the chosen-order histogram
+    equal pair for pair."""
+    import torch
+    from paper_1811_06332_amd import ctfmm as F
+    xyz, q = W.plummer(4000, 33)
+    p, leaf, seed, pmin = 8, 24, 0x5EED1234ABCD, 2
+    f = F.FMM(p, 0, precision, root_side=None, tree="adaptive", leaf_max=leaf)
+    try:
+        try:
+            f.set_m2l_tile(p, targets)
+        except F.CtfmmError as e:
+            assert e.status == F.CTFMM_EUNSUPPORTED
+            pytest.skip(f"a tile of {targets} targets does not fit the LDS in {precision}")
+        f.set_order_hash(seed, pmin)
+        F.ctfmm_set_timing(f.ctx, True)
+        print(f"[case] order map {precision} tile {targets}", flush=True)
+        phi, grad = f.evaluate(torch.from_numpy(xyz).cuda(), torch.from_numpy(q).cuda(), sync=True)
+        st = f.stats()
+    finally:
+        f.close()
+    tree = oracle.adaptive_tree(xyz, leaf)
+    vo = tile_max_v_orders(tree, targets, seed, pmin, p)
+    po, go = oracle.fmm_adaptive(xyz, q, p, leaf, v_orders=vo)
+    hist = np.bincount(vo, minlength=11).tolist()
+    tol, mtol = (TOL, MAXREL_FP64) if precision == "fp64" else (1e-6, MAXREL_MIXED)
+    eP, eF = rel(phi.cpu().numpy(), po), rel(grad.cpu().numpy(), go)
+    mP, mF = maxrel(phi.cpu().numpy(), po), maxrel(grad.cpu().numpy(), go)
+    print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e} max {mP:.3e} {mF:.3e} orders gpu {st['m2l_order_pairs']} "
+          f"oracle {hist}", flush=True)
+    assert st["m2l_order_pairs"] == hist
+    assert eP <= tol and eF <= tol
+    assert mP <= mtol and mF <= mtol
 
 
 def _learned_eval(params, norm, xyz, q, margin, reps=0):
