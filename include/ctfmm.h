@@ -346,6 +346,19 @@ ctfmm_status ctfmm_mlp_forward(ctfmm_ctx* ctx, int64_t n, const float* x, const 
 ctfmm_status ctfmm_mlp_backward(ctfmm_ctx* ctx, int64_t n, const float* x, const float* t, const float* params,
                                 float* grad, float* loss);
 
+/* ctfmm_mlp_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with their scratch (activations and
+ * per-chunk partial sums, about 5.6 MB) in a fixed device array of the
+ * library, one per GPU, held until the process ends; no allocation of any
+ * kind.  n may not exceed 4096.  Every call on one GPU uses that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other
+ * contexts, other host threads) race and give wrong results.  The array's
+ * address is looked up when a context is created on the device.
+ * Asynchronous.  Errors: EINVAL (n < 1, n > 4096, null pointer), EDEVICE. */
+ctfmm_status ctfmm_mlp_backward_noalloc(ctfmm_ctx* ctx, int64_t n, const float* x, const float* t,
+                                       const float* params, float* grad, float* loss);
+
 /* Adam training (beta 0.9, 0.999, eps 1e-8, step lr) of params (dev, in
  * place) for `steps` steps, step s using samples ((s-1) mod (n/batch)) *
  * batch .. + batch - 1 of x, t (dev).  loss_host (may be NULL) receives the

@@ -1381,6 +1381,8 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
     c->stream = (hipStream_t)hip_stream;
     (void)hipGetDevice(&c->device);
     ctfmm_status s = upload_tables(c);
+    if (s == CTFMM_OK && mlp_noalloc_setup(c->device) != hipSuccess)
+        s = fail(c, CTFMM_EDEVICE, "device address of the backward-pass scratch array");
     if (s == CTFMM_OK) {
         c->err_flag = (int*)dev_alloc(c, sizeof(int));
         if (!c->err_flag) s = fail(c, CTFMM_ENOMEM, "allocation failed");
@@ -1866,6 +1868,17 @@ ctfmm_status ctfmm_mlp_backward(ctfmm_ctx* c, int64_t n, const float* x, const f
         return fail(c, CTFMM_ENOMEM, "allocation failed");
     launch_mlp_backward(c->stream, n, x, t, params, c->mlp_act, c->mlp_err, grad, loss);
     HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_mlp_backward_noalloc(ctfmm_ctx* c, int64_t n, const float* x, const float* t, const float* params,
+                                       float* grad, float* loss) {
+    if (!c) return CTFMM_EINVAL;
+    if (n < 1 || !x || !t || !params || !grad || !loss) return fail(c, CTFMM_EINVAL, "n >= 1 and device pointers");
+    if (n > mlp_noalloc_max())
+        return fail(c, CTFMM_EINVAL, "n above the scratch capacity of the allocation-free backward pass (" +
+                                         std::to_string(mlp_noalloc_max()) + " samples)");
+    HIPCHK(c, launch_mlp_backward_noalloc(c->stream, c->device, n, x, t, params, grad, loss));
     return CTFMM_OK;
 }
 

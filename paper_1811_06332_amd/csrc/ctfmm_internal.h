@@ -322,6 +322,12 @@ void launch_mlp_forward16(hipStream_t s, long long n, const float* x, const floa
 void launch_mlp_backward(hipStream_t s, long long n, const float* x, const float* t, const float* prm, float* act,
                          float* err, float* grad, float* loss);
 size_t mlp_backward_part_floats(long long n);
+// the allocation-free backward pass: scratch in a device array (address
+// looked up per device by mlp_noalloc_setup, once, at context creation)
+long long mlp_noalloc_max();
+hipError_t mlp_noalloc_setup(int device);
+hipError_t launch_mlp_backward_noalloc(hipStream_t s, int device, long long n, const float* x, const float* t,
+                                       const float* prm, float* grad, float* loss);
 void launch_adam(hipStream_t s, int step, float lr, float* prm, const float* g, float* m, float* v);
 void launch_mlp_labels(hipStream_t s, long long n, const double* M, long long mstride, const int32_t* sel,
                        const int32_t* vslot, const double* Kt, float* x, float* y);

@@ -202,6 +202,49 @@ void launch_mlp_backward(hipStream_t s, long long n, const float* x, const float
     hipLaunchKernelGGL(k_mlp_back3, dim3(cdiv(MLP_NPARAM + 1, 256)), dim3(256), 0, s, n, nchunk, part, err, grad, loss);
 }
 
+// ------------------------------------------------------------------ allocation-free backward pass
+//
+// Scratch of the backward pass for callers that cannot allocate: a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Its device address is looked up once per device (with that device
+// current) and only that address is ever handed to kernels or copies.
+constexpr long long MLP_NOALLOC_MAX = 4096;  // samples per call
+constexpr size_t MLP_NOALLOC_FLOATS =
+    (size_t)MLP_NOALLOC_MAX * 5 * MLP_NH + (size_t)((MLP_NOALLOC_MAX + 255) / 256) * MLP_NPARAM + MLP_NOALLOC_MAX;
+static __device__ __align__(256) float scratch[MLP_NOALLOC_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+long long mlp_noalloc_max() { return MLP_NOALLOC_MAX; }
+
+hipError_t mlp_noalloc_setup(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<float*>(ptr);
+    return hipSuccess;
+}
+
+hipError_t launch_mlp_backward_noalloc(hipStream_t s, int device, long long n, const float* x, const float* t,
+                                       const float* prm, float* grad, float* loss) {
+    if (device < 0 || device >= MAX_DEVICES || !g_scratch_ptr[device]) return hipErrorNotInitialized;
+    if (n < 1 || n > MLP_NOALLOC_MAX) return hipErrorInvalidValue;
+    float* act = g_scratch_ptr[device];  // [n][5*64], then the chunk partials
+    float* err = act + (size_t)n * 5 * MLP_NH + mlp_backward_part_floats(n);
+    launch_mlp_backward(s, n, x, t, prm, act, err, grad, loss);
+    return hipGetLastError();
+}
+
 void launch_adam(hipStream_t s, int step, float lr, float* prm, const float* g, float* m, float* v) {
     hipLaunchKernelGGL(k_adam, dim3(cdiv(MLP_NPARAM, 256)), dim3(256), 0, s, step, lr, prm, g, m, v);
 }

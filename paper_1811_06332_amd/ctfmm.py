@@ -25,7 +25,7 @@ EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_
             "ctfmm_evaluate", "ctfmm_evaluate_f32", "ctfmm_evaluate_batched", "ctfmm_evaluate_batched_f32",
             "ctfmm_copy_expansions", "ctfmm_copy_tree", "ctfmm_tree_stats", "ctfmm_set_m2l_tile",
             "ctfmm_get_m2l_tile", "ctfmm_set_order_table", "ctfmm_set_order_hash", "ctfmm_set_order_model",
-            "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_train",
+            "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_backward_noalloc", "ctfmm_mlp_train",
             "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats", "ctfmm_reset_stats",
             "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
 
@@ -93,6 +93,7 @@ def load():
         L.ctfmm_set_order_model.argtypes = [vp, vp, vp, C.c_double, C.c_double]
         L.ctfmm_mlp_forward.argtypes = [vp, i64, vp, vp, i32, vp]
         L.ctfmm_mlp_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.ctfmm_mlp_backward_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ctfmm_mlp_train.argtypes = [vp, i64, vp, vp, vp, i32, i32, C.c_float, vp]
         L.ctfmm_mlp_labels.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ctfmm_mlp_samples.argtypes = [vp, i64, vp, vp, i64, C.c_uint64, vp, vp]
@@ -341,6 +342,14 @@ def ctfmm_mlp_backward(ctx, x, t, params, grad, loss) -> None:
     _check(load().ctfmm_mlp_backward(C.c_void_p(ctx), n, _f32dev(x, (n, MLP_NIN)), _f32dev(t, (n, MLP_NOUT)),
                                      _f32dev(params, (MLP_NPARAM,)), _f32dev(grad, (MLP_NPARAM,)),
                                      _f32dev(loss, (1,))), C.c_void_p(ctx))
+
+
+def ctfmm_mlp_backward_noalloc(ctx, x, t, params, grad, loss) -> None:
+    """As ctfmm_mlp_backward, with the library's fixed scratch (n <= 4096)."""
+    n = int(x.shape[0])
+    _check(load().ctfmm_mlp_backward_noalloc(C.c_void_p(ctx), n, _f32dev(x, (n, MLP_NIN)), _f32dev(t, (n, MLP_NOUT)),
+                                             _f32dev(params, (MLP_NPARAM,)), _f32dev(grad, (MLP_NPARAM,)),
+                                             _f32dev(loss, (1,))), C.c_void_p(ctx))
 
 
 def ctfmm_mlp_train(ctx, x, t, params, steps: int, batch: int, lr: float):
