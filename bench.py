@@ -122,22 +122,68 @@ def m2l_traffic(name: str):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(p: int, leaf_max: int):
-    """The adaptive oracle on a smaller Plummer sphere of the same profile
-    (half the particles), same p and leaf size, all host cores."""
+def kernel_record(name: str):
+    """The committed rocprofv3 record of a kernel (profiles/<name>_kernel.json:
+    average duration over the timed steps, MFMA counters), or None when it
+    does not describe the kernel sources built now."""
+    from paper_1811_06332_amd.profile_summary import source_hash
+    path = os.path.join(ROOT, "profiles", f"{name}_kernel.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if source_hash(ROOT, rec.get("kernel_sources", [])) != rec.get("kernel_sources_sha256_16"):
+        return None
+    return rec
+
+
+def profile_roofline(name: str, flops_per_launch: float, peak: float):
+    """The roofline fraction from the committed profile of the same
+    command: algorithmic flops per launch over rocprofv3's average kernel
+    duration, and the MFMA utilisation its counters give."""
+    rec = kernel_record(name)
+    if rec is None:
+        return None
+    ach = flops_per_launch / (rec["avg_launch_ms"] * 1e-3) / 1e12
+    return {"source": f"profiles/{name}_kernel.json", "avg_launch_ms": rec["avg_launch_ms"], "achieved": ach,
+            "frac": ach / peak, "mfma_util": rec.get("mfma_util"),
+            "issued_mfma_flops_per_launch": rec.get("issued_mfma_flops"),
+            "useful_share_of_issued": (flops_per_launch / rec["issued_mfma_flops"]
+                                       if rec.get("issued_mfma_flops") else None)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p: int, leaf_max: int, n_full: int):
+    """The adaptive oracle (as it stands) on Plummer spheres of the same
+    profile, p and leaf size as the workload: N = 2^18 on all host cores
+    and N = 2^15 on one thread, each one run, scaled to particles/s (the
+    method is O(N), so the rate carries over to the full N up to the tree
+    depth)."""
     import oracle
     from paper_1811_06332_amd import workloads as W
-    n = 1 << 19
-    xyz, q = W.plummer(n, 1001)
     threads = len(os.sched_getaffinity(0))
-    oracle.fmm_uniform(xyz[:64], q[:64], 1, 1, nthreads=threads)  # load and set threads
-    used = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.fmm_adaptive(xyz, q, p, leaf_max, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "particles/s", "cores": used, "kind": "oracle",
-            "sample": f"full adaptive oracle FMM of a Plummer sphere of N={n} (half the workload's particles, same "
-                      f"profile, p={p}, leaf <= {leaf_max}, ws=1), one run of {dt:.1f} s"}
+    runs = {}
+    for n, nth in ((1 << 18, threads), (1 << 15, 1)):
+        xyz, q = W.plummer(n, 1001)
+        oracle.fmm_uniform(xyz[:64], q[:64], 1, 1, nthreads=nth)  # load and set threads
+        used = oracle.max_threads()
+        t0 = time.perf_counter()
+        oracle.fmm_adaptive(xyz, q, p, leaf_max, nthreads=nth)
+        runs[nth] = (n, time.perf_counter() - t0, used)
+    (n_all, dt_all, used_all), (n_one, dt_one, _) = runs[threads], runs[1]
+    return {"value": n_all / dt_all, "unit": "particles/s", "cores": used_all, "kind": "oracle",
+            "single_thread_value": n_one / dt_one, "cpu_model": cpu_model(), "host_threads": threads,
+            "sample": f"full adaptive oracle FMM of Plummer spheres (the workload's profile, p={p}, leaf <= "
+                      f"{leaf_max}, ws=1) instead of N={n_full}: N={n_all} on {used_all} threads in {dt_all:.1f} s, "
+                      f"N={n_one} on 1 thread in {dt_one:.1f} s"}
 
 
 # ------------------------------------------------------------------ extras
@@ -160,7 +206,9 @@ def extra_uniform16m(F, torch, W, args, dev):
            "rel_force_err_vs_fp64": rel_err(torch, grad_c, grad_p),
            "m2l_roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
                             "frac": ach / PEAK_TFLOPS[args.precision],
-                            "traffic": m2l_traffic(f"m2l_{args.precision}_uniform16M_p10")},
+                            "traffic": m2l_traffic(f"m2l_{args.precision}_uniform16M_p10"),
+                            "profile": profile_roofline(f"m2l_{args.precision}_uniform16M_p10", flops_launch,
+                                                        PEAK_TFLOPS[args.precision])},
            "chosen": chosen, "plain_fp64": plain}
     del X, Q, phi_c, grad_c, phi_p, grad_p
     torch.cuda.empty_cache()
@@ -208,6 +256,32 @@ def extra_batched(F, torch, W, args, dev):
             "m2l_pairs_per_step": st["m2l_pairs"] // args.steps}
 
 
+def extra_bf16x3(F, torch, W, args, dev):
+    """The headline workload with BF16x3 M2L, against FP64."""
+    cfg = W.CONFIGS[1]
+    xyz, q = W.make(cfg)
+    X = torch.from_numpy(xyz).to(dev)
+    Q = torch.from_numpy(q).to(dev)
+    del xyz, q
+    log("bf16x3 plummer1M")
+    kw = dict(tree="adaptive", leaf_max=cfg["leaf_max"])
+    leg, phi_b, grad_b = run_leg(F, torch, X, Q, cfg["p"], "bf16x3", args.steps, args.warmup, **kw)
+    ref, phi_r, grad_r = run_leg(F, torch, X, Q, cfg["p"], "fp64", 1, 1, **kw)
+    flops_launch = leg["m2l_alg_flops_per_step"] / leg["m2l_launches_per_step"]
+    ach = flops_launch / (leg["m2l_ms_per_launch"] * 1e-3) / 1e12
+    out = {"workload": cfg["name"], "particles_per_s": leg["particles_per_s"], "ms_per_step": leg["ms_per_step"],
+           "m2l_ms": leg["m2l_ms_per_launch"] * leg["m2l_launches_per_step"],
+           "rel_force_err_vs_fp64": rel_err(torch, grad_b, grad_r),
+           "rel_potential_err_vs_fp64": rel_err(torch, phi_b, phi_r),
+           "m2l_roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["bf16x3"], "unit": "TFLOP/s",
+                            "frac": ach / PEAK_TFLOPS["bf16x3"],
+                            "note": "algorithmic flops counted once; the six BF16 piece products issue 6x"},
+           "leg": leg}
+    del X, Q, phi_b, grad_b, phi_r, grad_r
+    torch.cuda.empty_cache()
+    return out
+
+
 def extra_learned(F, torch, W, args, dev):
     import numpy as np
     log("learned4M: training pairs")
@@ -230,11 +304,11 @@ def extra_learned(F, torch, W, args, dev):
         f.close()
     del xyz_t, q_t
 
-    def evaluate(xyz, q, margin, steps, warmup):
+    def evaluate(xyz, q, margin, steps, warmup, precision="fp64"):
         X = torch.from_numpy(xyz).to(dev)
         Q = torch.from_numpy(q).to(dev)
         setup = None if margin is None else (lambda g: g.set_order_model(params, norm, 1e-5, margin))
-        leg, phi, grad = run_leg(F, torch, X, Q, 10, "fp64", steps, warmup, setup=setup)
+        leg, phi, grad = run_leg(F, torch, X, Q, 10, precision, steps, warmup, setup=setup)
         return leg, grad
 
     log("learned4M: margin on a held-out cluster")
@@ -254,7 +328,22 @@ def extra_learned(F, torch, W, args, dev):
     xyz_e, q_e = W.make(cfg)
     fixed, g_f = evaluate(xyz_e, q_e, None, args.steps, args.warmup)
     learned, g_l = evaluate(xyz_e, q_e, margin, args.steps, args.warmup)
+    fixed32, g_f32 = evaluate(xyz_e, q_e, None, args.steps, args.warmup, "fp32")
+    learned32, g_l32 = evaluate(xyz_e, q_e, margin, args.steps, args.warmup, "fp32")
+
+    def m2l_ms(leg):
+        return leg["m2l_ms_per_launch"] * leg["m2l_launches_per_step"]
+
+    fp32 = {"particles_per_s_learned": learned32["particles_per_s"],
+            "particles_per_s_fixed_p10": fixed32["particles_per_s"],
+            "m2l_ms_learned": m2l_ms(learned32), "m2l_ms_fixed_p10": m2l_ms(fixed32),
+            "rel_force_err_learned_vs_fixed_p10_fp64": rel_err(torch, g_l32, g_f),
+            "rel_force_err_fixed_vs_fixed_p10_fp64": rel_err(torch, g_f32, g_f),
+            "speedup_step_vs_plain_fp64_fixed_p10": learned32["particles_per_s"] / fixed["particles_per_s"],
+            "phase_ms_learned": learned32["phase_ms_per_step"], "phase_ms_fixed": fixed32["phase_ms_per_step"]}
     return {"workload": "hernquist4M_p10_learned_orders", "n": cfg["n"], "target_rel_err": 1e-5, "margin": margin,
+            "fp32_m2l": fp32,
+            "phase_ms_learned": learned["phase_ms_per_step"], "phase_ms_fixed": fixed["phase_ms_per_step"],
             "margin_tuning": tuning, "train_loss_first_last": [float(losses[0]), float(losses[-1])],
             "train_seconds": t_train,
             "particles_per_s_learned": learned["particles_per_s"], "particles_per_s_fixed_p10": fixed["particles_per_s"],
@@ -274,7 +363,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="uniform16M,batched256,learned4M")
+    ap.add_argument("--extras", default="uniform16M,batched256,learned4M,bf16x3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -308,7 +397,8 @@ def main():
     kw = dict(tree="adaptive", leaf_max=cfg["leaf_max"])
     chosen, phi_c, grad_c = run_leg(F, torch, X, Q, cfg["p"], args.precision, args.steps, args.warmup, **kw)
     plain = None
-    err = {"rel_force_err_vs_fp64": 0.0, "rel_potential_err_vs_fp64": 0.0}
+    # None: not measured (no FP64 leg)
+    err = {"rel_force_err_vs_fp64": None, "rel_potential_err_vs_fp64": None}
     if args.precision != "fp64" and not args.no_fp64_leg:
         plain, phi_p, grad_p = run_leg(F, torch, X, Q, cfg["p"], "fp64", args.steps, args.warmup, **kw)
         err = {"rel_force_err_vs_fp64": rel_err(torch, grad_c, grad_p),
@@ -316,6 +406,7 @@ def main():
         del phi_p, grad_p
     elif args.precision == "fp64":
         plain = chosen
+        err = {"rel_force_err_vs_fp64": 0.0, "rel_potential_err_vs_fp64": 0.0}
     del X, Q, phi_c, grad_c
     torch.cuda.empty_cache()
 
@@ -325,13 +416,23 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": m2l_traffic(f"m2l_{args.precision}_plummer1M_p8"),
                 "kernel": "adaptive M2L (one launch per evaluation; algorithmic 2*S(p) flops per cell pair)",
-                "flops_per_launch": flops_launch, "avg_launch_ms": chosen["m2l_ms_per_launch"]}
+                "flops_per_launch": flops_launch, "avg_launch_ms": chosen["m2l_ms_per_launch"],
+                "traffic_source": f"profiles/m2l_{args.precision}_plummer1M_p8_traffic.json",
+                "profile": profile_roofline(f"m2l_{args.precision}_plummer1M_p8", flops_launch, peak)}
+    if plain is not None and plain is not chosen:
+        f64_launch = plain["m2l_alg_flops_per_step"] / plain["m2l_launches_per_step"]
+        f64_ach = f64_launch / (plain["m2l_ms_per_launch"] * 1e-3) / 1e12
+        plain["m2l_roofline"] = {"bound": "mfma", "achieved": f64_ach, "peak": PEAK_TFLOPS["fp64"],
+                                 "unit": "TFLOP/s", "frac": f64_ach / PEAK_TFLOPS["fp64"],
+                                 "profile": profile_roofline("m2l_fp64_plummer1M_p8", f64_launch,
+                                                             PEAK_TFLOPS["fp64"])}
     extras = {}
     if not args.no_extras:
         for name in [e for e in args.extras.split(",") if e]:
-            fn = {"uniform16M": extra_uniform16m, "batched256": extra_batched, "learned4M": extra_learned}[name]
+            fn = {"uniform16M": extra_uniform16m, "batched256": extra_batched, "learned4M": extra_learned,
+                  "bf16x3": extra_bf16x3}[name]
             extras[name] = fn(F, torch, W, args, dev)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg["p"], cfg["leaf_max"])
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg["p"], cfg["leaf_max"], cfg["n"])
     out = {
         "metric": METRIC,
         "value": chosen["particles_per_s"],
