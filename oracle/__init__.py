@@ -60,6 +60,11 @@ def _lib():
         L.oracle_fmm_uniform.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p,
                                          _dp, _dp, C.c_void_p, C.c_void_p, i32]
         L.oracle_fmm_uniform.restype = i32
+        L.oracle_fmm_uniform_dipoles.argtypes = [i64, _dp, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p,
+                                                 _dp, _dp, i32]
+        L.oracle_fmm_uniform_dipoles.restype = i32
+        L.oracle_direct_dipoles.argtypes = [i64, _dp, _dp, _dp, i64, C.c_void_p, _dp, _dp, i32]
+        L.oracle_p2m_dipole.argtypes = [i32, _dp, i64, _dp, _dp, _dp]
         L.oracle_max_threads.restype = i32
         L.oracle_fmm_adaptive.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
                                           C.c_void_p, C.c_void_p, i32]
@@ -131,6 +136,50 @@ def p2m(p, z, xyz, q):
     M = np.zeros(nfull(p))
     _lib().oracle_p2m(p, _vec(z, 3), xyz.shape[0], np.ascontiguousarray(xyz.ravel()), q, M)
     return M
+
+
+def p2m_dipole(p, z, xyz, dip):
+    """Multipole (full storage) of point dipoles dip [n,3] at xyz about z."""
+    xyz = _vec(xyz).reshape(-1, 3); dip = _vec(dip).reshape(-1, 3)
+    M = np.zeros(nfull(p))
+    _lib().oracle_p2m_dipole(p, _vec(z, 3), xyz.shape[0], np.ascontiguousarray(xyz.ravel()),
+                             np.ascontiguousarray(dip.ravel()), M)
+    return M
+
+
+def direct_dipoles(xyz, q, dip, targets=None, nthreads=0):
+    """O(N^2) potential and gradient of charges q and point dipoles dip [n,3]."""
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0]); dip = _vec(dip).reshape(-1, 3)
+    n = xyz.shape[0]
+    if targets is None:
+        nt, tp, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt, tp = keep.size, keep.ctypes.data
+    phi = np.zeros(nt); grad = np.zeros(3 * nt)
+    _lib().oracle_direct_dipoles(n, np.ascontiguousarray(xyz.ravel()), q, np.ascontiguousarray(dip.ravel()), nt, tp,
+                                 phi, grad, nthreads)
+    del keep
+    return phi, grad.reshape(-1, 3)
+
+
+def fmm_uniform_dipoles(xyz, q, dip, p, depth, lo=(0.0, 0.0, 0.0), side=1.0, targets=None, nthreads=0):
+    """Uniform FMM of charges q and point dipoles dip [n,3] (see
+    oracle_fmm_uniform_dipoles)."""
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0]); dip = _vec(dip).reshape(-1, 3)
+    n = xyz.shape[0]
+    if targets is None:
+        nt, tp, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt, tp = keep.size, keep.ctypes.data
+    phi = np.zeros(nt); grad = np.zeros(3 * nt)
+    rc = _lib().oracle_fmm_uniform_dipoles(n, np.ascontiguousarray(xyz.ravel()), q, np.ascontiguousarray(dip.ravel()),
+                                           p, depth, _vec(lo, 3), float(side), nt, tp, phi, grad, nthreads)
+    del keep
+    if rc != 0:
+        raise RuntimeError(f"oracle_fmm_uniform_dipoles failed with code {rc}")
+    return phi, grad.reshape(-1, 3)
 
 
 def m2m(p, d, M):

@@ -219,6 +219,33 @@ void oracle_p2m(int p, const double z[3], int64_t n, const double *xyz, const do
 }
 
 /*
+ * P2M of point dipoles (Appendix B.1): each dipole p_a is a pure dipole at
+ * its own position x_a -- rank-1 components M'_{e_i} = -p_{a,i} (so that
+ * the expansion's potential is -p_a . grad (1/|x - x_a|)), every other
+ * component zero -- moved to the centre z by Eq. M2M (d = x_a - z).  M is
+ * ADDED to.
+ */
+void oracle_m2m(int p, const double d[3], const double *Min, double *Mout);
+
+void oracle_p2m_dipole(int p, const double z[3], int64_t n, const double *xyz, const double *dip, double *M)
+{
+    init_tables();
+    int nf = g_nfull[p];
+    double *Md = (double *)calloc((size_t)nf, sizeof(double));
+    for (int64_t a = 0; a < n; ++a) {
+        memset(Md, 0, (size_t)nf * sizeof(double));
+        if (p >= 1) {
+            Md[g_idx[1][0][0]] = -dip[3 * a + 0];
+            Md[g_idx[0][1][0]] = -dip[3 * a + 1];
+            Md[g_idx[0][0][1]] = -dip[3 * a + 2];
+        }
+        double d[3] = {xyz[3 * a] - z[0], xyz[3 * a + 1] - z[1], xyz[3 * a + 2] - z[2]};
+        oracle_m2m(p, d, Md, M);
+    }
+    free(Md);
+}
+
+/*
  * M2M (Eq. M2M, M2M part 2): move the expansion from centre z to z' = z - d,
  * i.e. d = z_child - z_parent.  M'_n = sum_{k<=n} n!/(k!(n-k)!) (-d)^(n-k) M_k,
  * then Mout += D[M'].
@@ -331,6 +358,53 @@ static void pair_kernel(const double *xb, const double *xa, double qa, double *p
 }
 
 /*
+ * One point dipole p_a at x_a on a target at x_b (Appendix B.1: the limit of
+ * charges +s at x_a + d/2 and -s at x_a - d/2 with s d = p_a): potential
+ * p_a.(x_b - x_a)/|x_b - x_a|^3 and its gradient with respect to x_b,
+ * p_a/|r|^3 - 3 (p_a.r) r/|r|^5.  Coincident: nothing.
+ */
+static void pair_kernel_dipole(const double *xb, const double *xa, const double *pa, double *phi, double *grad)
+{
+    double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) return;
+    double ir = 1.0 / sqrt(r2);
+    double ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+    double pr = pa[0] * dx + pa[1] * dy + pa[2] * dz;
+    phi[0] += pr * ir3;
+    grad[0] += pa[0] * ir3 - 3.0 * pr * dx * ir5;
+    grad[1] += pa[1] * ir3 - 3.0 * pr * dy * ir5;
+    grad[2] += pa[2] * ir3 - 3.0 * pr * dz * ir5;
+}
+
+/* Direct sum over charges q and point dipoles dip ([n][3]) at the targets
+ * tgt[0..nt) (NULL = all particles); self pairs skipped; overwritten. */
+void oracle_direct_dipoles(int64_t n, const double *xyz, const double *q, const double *dip, int64_t nt,
+                           const int64_t *tgt, double *phi, double *grad, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    if (!tgt) nt = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t b = tgt ? tgt[t] : t;
+        double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int64_t a = 0; a < n; ++a) {
+            if (a == b) continue;
+            pair_kernel(&xyz[3 * b], &xyz[3 * a], q[a], &f, g);
+            pair_kernel_dipole(&xyz[3 * b], &xyz[3 * a], &dip[3 * a], &f, g);
+        }
+        phi[t] = f;
+        grad[3 * t + 0] = g[0];
+        grad[3 * t + 1] = g[1];
+        grad[3 * t + 2] = g[2];
+    }
+}
+
+/*
  * Direct O(N^2) sum (Eq. PhiAB) at the targets tgt[0..nt) (particle
  * indices; NULL = all particles).  Self pairs are skipped.
  * phi[nt], grad[3*nt] are overwritten.
@@ -366,6 +440,7 @@ typedef struct {
     double lo[3], side;
     int64_t n;
     const double *xyz, *q;
+    const double *dip;  /* [n][3] point dipoles, or NULL */
     int64_t *leaf_of;   /* [n] linear leaf index (row-major, x fastest) */
     int64_t *start;     /* [nleaves+1] offsets into order */
     int64_t *order;     /* [n] particle indices grouped by leaf, input order within a leaf */
@@ -458,6 +533,13 @@ static int upward(otree *T)
                 pq[s - b] = T->q[a];
             }
             oracle_p2m(p, z, e - b, px, pq, &T->M[d][(size_t)c * nf]);
+            if (T->dip) {
+                double *pd = (double *)malloc((size_t)(e - b) * 3 * sizeof(double));
+                for (int64_t s = b; s < e; ++s)
+                    for (int x = 0; x < 3; ++x) pd[3 * (s - b) + x] = T->dip[3 * T->order[s] + x];
+                oracle_p2m_dipole(p, z, e - b, px, pd, &T->M[d][(size_t)c * nf]);
+                free(pd);
+            }
             free(px);
             free(pq);
         }
@@ -563,6 +645,7 @@ static void evaluate_particle(const otree *T, int64_t b, double *phi, double *gr
                     int64_t a = T->order[s];
                     if (a == b) continue;
                     pair_kernel(&T->xyz[3 * b], &T->xyz[3 * a], T->q[a], &f, g);
+                    if (T->dip) pair_kernel_dipole(&T->xyz[3 * b], &T->xyz[3 * a], &T->dip[3 * a], &f, g);
                 }
             }
     phi[0] = f;
@@ -584,9 +667,30 @@ static void evaluate_particle(const otree *T, int64_t b, double *phi, double *gr
  *
  * Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
  */
+static int fmm_uniform_impl(int64_t n, const double *xyz, const double *q, const double *dip, int p, int depth,
+                            const double lo[3], double side, int64_t nt, const int64_t *tgt, double *phi,
+                            double *grad, double *M_dump, double *L_dump, int nthreads);
+
 int oracle_fmm_uniform(int64_t n, const double *xyz, const double *q, int p, int depth,
                        const double lo[3], double side, int64_t nt, const int64_t *tgt,
                        double *phi, double *grad, double *M_dump, double *L_dump, int nthreads)
+{
+    return fmm_uniform_impl(n, xyz, q, NULL, p, depth, lo, side, nt, tgt, phi, grad, M_dump, L_dump, nthreads);
+}
+
+/* The uniform FMM with point dipoles dip ([n][3]) beside the charges: P2M
+ * adds oracle_p2m_dipole, the near field the dipole pair terms. */
+int oracle_fmm_uniform_dipoles(int64_t n, const double *xyz, const double *q, const double *dip, int p, int depth,
+                               const double lo[3], double side, int64_t nt, const int64_t *tgt, double *phi,
+                               double *grad, int nthreads)
+{
+    if (!dip) return -1;
+    return fmm_uniform_impl(n, xyz, q, dip, p, depth, lo, side, nt, tgt, phi, grad, NULL, NULL, nthreads);
+}
+
+static int fmm_uniform_impl(int64_t n, const double *xyz, const double *q, const double *dip, int p, int depth,
+                            const double lo[3], double side, int64_t nt, const int64_t *tgt, double *phi,
+                            double *grad, double *M_dump, double *L_dump, int nthreads)
 {
     init_tables();
     if (p < 0 || p > OR_PMAX || depth < 0 || depth > 9 || n < 0 || side <= 0.0) return -1;
@@ -599,7 +703,7 @@ int oracle_fmm_uniform(int64_t n, const double *xyz, const double *q, int p, int
     memset(&T, 0, sizeof(T));
     T.p = p; T.depth = depth; T.nf = g_nfull[p];
     T.lo[0] = lo[0]; T.lo[1] = lo[1]; T.lo[2] = lo[2]; T.side = side;
-    T.n = n; T.xyz = xyz; T.q = q;
+    T.n = n; T.xyz = xyz; T.q = q; T.dip = dip;
     int rc = 0;
     unsigned char **need = NULL;
     if (build_tree(&T)) { rc = -2; goto done; }

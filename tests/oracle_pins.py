@@ -666,4 +666,82 @@ def pin_pair_orders(o):
     assert rel(gt, gf) > 1e-8
 
 
+def _dipoles_as_charge_pairs(xyz, dip, eps):
+    """Each point dipole p at x as charges +s at x + d/2 and -s at x - d/2
+    with d = eps p/|p| and s = |p|/eps (s d = p): the definition of a point
+    dipole in the limit eps -> 0 (Appendix B.1)."""
+    norm = np.linalg.norm(dip, axis=1, keepdims=True)
+    d = eps * dip / norm
+    return np.vstack([xyz + d / 2, xyz - d / 2]), np.concatenate([norm[:, 0] / eps, -norm[:, 0] / eps])
+
+
+def pin_dipole_direct_is_charge_pair_limit(o):
+    """The direct sum over point dipoles equals that over the charge pairs
+    they are the limit of, to O(eps^2)."""
+    rng = np.random.default_rng(50)
+    tgt = rng.random((40, 3))
+    xd, dip = rng.random((30, 3)), rng.normal(size=(30, 3))
+    n_t = len(tgt)
+    pd, gd = o.direct_dipoles(np.vstack([tgt, xd]), np.zeros(n_t + 30), np.vstack([np.zeros((n_t, 3)), dip]),
+                              targets=np.arange(n_t))
+    errs = []
+    for eps in (1e-3, 1e-4):
+        xc, qc = _dipoles_as_charge_pairs(xd, dip, eps)
+        pc, gc = o.direct(np.vstack([tgt, xc]), np.concatenate([np.zeros(n_t), qc]), targets=np.arange(n_t))
+        errs.append((rel(pd, pc), rel(gd, gc)))
+    assert errs[1][0] < 1e-5 and errs[1][1] < 1e-5, errs
+    assert errs[1][0] < 0.02 * errs[0][0] and errs[1][1] < 0.02 * errs[0][1], errs  # second order
+
+
+def pin_dipole_p2m_is_charge_pair_limit(o):
+    """The multipole of point dipoles (a pure dipole moved by M2M) equals the
+    P2M of the charge pairs they are the limit of, to O(eps^2), and its
+    expansion reproduces the direct dipole field far away, better with p."""
+    rng = np.random.default_rng(51)
+    z = np.array([0.5, 0.5, 0.5])
+    xd, dip = 0.5 + 0.3 * (rng.random((12, 3)) - 0.5), rng.normal(size=(12, 3))
+    for p in (1, 4, 7):
+        M = o.p2m_dipole(p, z, xd, dip)
+        errs = []
+        for eps in (1e-2, 1e-3):
+            xc, qc = _dipoles_as_charge_pairs(xd, dip, eps)
+            errs.append(rel(M, o.p2m(p, z, xc, qc)))
+        # second order in eps (exact at p = 1: a charge pair has no rank-1 error)
+        assert errs[1] < 1e-5 and (errs[0] < 1e-10 or errs[1] < 0.05 * errs[0]), (p, errs)
+    tgt = np.array([[3.2, -1.7, 2.9], [-2.5, 3.1, 0.4]])
+    pd, gd = o.direct_dipoles(np.vstack([tgt, xd]), np.zeros(14), np.vstack([np.zeros((2, 3)), dip]),
+                              targets=np.arange(2))
+    prev = None
+    for p in (2, 4, 6, 8):
+        M = o.p2m_dipole(p, z, xd, dip)
+        got = []
+        for t in tgt:
+            L = o.m2l(p, t - z, M)
+            f, g = o.l2p(p, np.zeros(3), L)
+            got.append((f, g))
+        e = rel([f for f, _ in got], pd) + rel([g for _, g in got], gd)
+        assert prev is None or e < prev, (p, e, prev)
+        prev = e
+    assert prev < 1e-6
+
+
+def pin_dipole_fmm_vs_direct_decay(o):
+    """The uniform FMM with charges and point dipoles against the direct sum:
+    the errors fall with p."""
+    rng = np.random.default_rng(52)
+    xyz = rng.random((400, 3))
+    q, dip = rng.uniform(-1, 1, 400), 0.01 * rng.normal(size=(400, 3))
+    pd, gd = o.direct_dipoles(xyz, q, dip)
+    errs = []
+    for p in (2, 4, 6, 8):
+        pf, gf = o.fmm_uniform_dipoles(xyz, q, dip, p, 3)
+        errs.append((rel(pf, pd), rel(gf, gd)))
+    for a, b in zip(errs, errs[1:]):
+        assert b[0] < a[0] and b[1] < a[1], errs
+    assert errs[-1][1] < 1e-3, errs
+    # dipoles matter: without them the result is far off
+    pc, gc = o.fmm_uniform(xyz, q, 8, 3)
+    assert rel(gc, gd) > 100 * errs[-1][1]
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -71,6 +71,15 @@ MUTANTS = [
     ("order_table_ignored", "order = order_r2[dx * dx + dy * dy + dz * dz];", "order = p;", None),
     ("order_table_wrong_offset", "order = order_r2[dx * dx + dy * dy + dz * dz];",
      "order = order_r2[dx * dx + dy * dy + dz * dz >= 9 ? 27 : 4];", None),
+    ("pair_orders_shifted", "if (vorder) order = vorder[voff[i] + k];",
+     "if (vorder) order = vorder[voff[i] + (k + 1) % T.V[i].n];", None),
+    ("dipole_p2m_sign", "Md[g_idx[1][0][0]] = -dip[3 * a + 0];", "Md[g_idx[1][0][0]] = dip[3 * a + 0];", None),
+    ("dipole_p2m_shift_reversed", "double d[3] = {xyz[3 * a] - z[0], xyz[3 * a + 1] - z[1], xyz[3 * a + 2] - z[2]};",
+     "double d[3] = {z[0] - xyz[3 * a], z[1] - xyz[3 * a + 1], z[2] - xyz[3 * a + 2]};", None),
+    ("dipole_field_gradient_term", "grad[0] += pa[0] * ir3 - 3.0 * pr * dx * ir5;",
+     "grad[0] += pa[0] * ir3 - pr * dx * ir5;", None),
+    ("dipole_near_field_dropped",
+     "if (T->dip) pair_kernel_dipole(&T->xyz[3 * b], &T->xyz[3 * a], &T->dip[3 * a], &f, g);", "(void)0;", None),
 ]
 
 
