@@ -190,6 +190,20 @@ ctfmm_status ctfmm_set_allocator(ctfmm_ctx* ctx, ctfmm_alloc_fn alloc, ctfmm_fre
 ctfmm_status ctfmm_evaluate(ctfmm_ctx* ctx, int64_t n, const double* xyz, const double* q,
                             double* phi, double* grad);
 
+/* ctfmm_evaluate with point dipoles beside the charges (uniform tree): the
+ * potential and gradient at every particle of the charges q_a and dipoles
+ * d_a of all the others,
+ *     Phi(x_b) = sum_{a != b} [ q_a / |r| + d_a . r / |r|^3 ],  r = x_b - x_a,
+ * a dipole being the limit of two opposite charges infinitely close
+ * (Appendix B.1).  P2M forms each dipole's multipole as a pure dipole at
+ * the particle moved to the cell centre by Eq. M2M; the near field adds the
+ * dipole pair terms.
+ *   dip  dev, n*3 doubles row-major (d_x, d_y, d_z per particle)
+ * Other arguments as ctfmm_evaluate.  Errors as ctfmm_evaluate, and
+ * EUNSUPPORTED (adaptive tree). */
+ctfmm_status ctfmm_evaluate_dipoles(ctfmm_ctx* ctx, int64_t n, const double* xyz, const double* q,
+                                    const double* dip, double* phi, double* grad);
+
 /* ctfmm_evaluate with FP32 inputs and outputs (same layouts, float
  * instead of double).  The inputs are widened to FP64 on the device, the
  * method runs as in ctfmm_evaluate (its M2L in the context's precision),

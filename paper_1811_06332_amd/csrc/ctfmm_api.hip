@@ -223,6 +223,9 @@ struct ctfmm_ctx {
     } pend;
     ctfmm_stats_t st{};
 
+    // point dipoles in sorted order (uniform tree, ctfmm_evaluate_dipoles)
+    double4* Pd = nullptr;
+    size_t Pd_cap = 0;
     // FP64 copies of the caller's arrays for the FP32 entry points: xyz, q, phi, grad
     double* io[4] = {};
     size_t io_cap[4] = {};
@@ -472,6 +475,8 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     }
     c->owned = rest;
     c->cap_n = -1;
+    c->Pd = nullptr;  // released above with the particle workspace
+    c->Pd_cap = 0;
     const int d = c->prm.depth;
     const int p = c->prm.order_p;
     const size_t nc = (size_t)(p + 1) * (p + 1);
@@ -1386,6 +1391,8 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
     if (s == CTFMM_OK) {
         c->err_flag = (int*)dev_alloc(c, sizeof(int));
         if (!c->err_flag) s = fail(c, CTFMM_ENOMEM, "allocation failed");
+        else if (hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream) != hipSuccess)
+            s = fail(c, CTFMM_EDEVICE, "clearing the error flag failed");
     }
     if (s == CTFMM_OK) s = build_operators(c);
     if (s == CTFMM_OK) {
@@ -1417,19 +1424,19 @@ ctfmm_status ctfmm_set_allocator(ctfmm_ctx* c, ctfmm_alloc_fn alloc, ctfmm_free_
     if (s != CTFMM_OK) return s;
     c->err_flag = (int*)dev_alloc(c, sizeof(int));
     if (!c->err_flag) return fail(c, CTFMM_ENOMEM, "allocation failed");
+    HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), c->stream));  // workspace is never assumed zero
     return build_operators(c);
 }
 
-ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const double* q, double* phi,
-                            double* grad) {
-    if (!c) return CTFMM_EINVAL;
-    c->err.clear();
-    if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "n out of range");
-    if (n == 0) return CTFMM_OK;
-    if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
-    if (c->prm.tree == CTFMM_TREE_ADAPTIVE) return evaluate_adaptive(c, (int)n, xyz, q, phi, grad);
+namespace {
+
+// The uniform-tree evaluation; dip (may be null): point dipoles [n][3]
+ctfmm_status evaluate_uniform(ctfmm_ctx* c, int64_t n, const double* xyz, const double* q, const double* dip,
+                              double* phi, double* grad) {
     ctfmm_status s = ensure_workspace(c, n);
     if (s != CTFMM_OK) return s;
+    if (dip && !grow(c, c->Pd, c->Pd_cap, (size_t)n, false)) return fail(c, CTFMM_ENOMEM, "workspace allocation failed");
+    const double4* Pd = dip ? c->Pd : nullptr;
     const int d = c->prm.depth;
     const int p = c->prm.order_p;
     const size_t nc = (size_t)(p + 1) * (p + 1);
@@ -1445,6 +1452,7 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
     HIPCHK(c, hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, tmpb, c->keys, c->keys_sorted, c->idx,
                                                  c->idx_sorted, ni, 0, d > 0 ? 3 * d : 1, st));
     launch_gather(st, ni, c->idx_sorted, xyz, q, c->P);
+    if (dip) launch_gather_dip(st, ni, c->idx_sorted, dip, c->Pd);
     launch_leaf_start(st, nleaves, c->keys_sorted, ni, c->start);
     HIPCHK(c, hipGetLastError());
     rec(c, 1);
@@ -1453,7 +1461,7 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
     auto Ll = [&](int l) { return c->L + c->lvl_off[l] * ldm; };
     int evi = 5;
     if (d >= 2) {
-        launch_p2m(st, p, box, c->start, c->P, c->T, Ml(d));
+        launch_p2m(st, p, box, c->start, c->P, c->T, Ml(d), Pd);
         rec(c, 2);
         for (int l = d; l >= 3; --l) launch_m2m(st, p, l - 1, Ml(l), Ml(l - 1), c->T);
         rec(c, 3);
@@ -1473,12 +1481,12 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
         }
         rec(c, 4);
         launch_l2p(st, p, ni, box, c->keys_sorted, c->P, Ll(d), c->F);
-        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, c->F, phi, grad);
+        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, c->F, phi, grad, Pd);
     } else {
         rec(c, 2);
         rec(c, 3);
         rec(c, 4);
-        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, nullptr, phi, grad);
+        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, nullptr, phi, grad, Pd);
     }
     HIPCHK(c, hipGetLastError());
     const int ev_end = NPHASE_EV - 1;
@@ -1506,6 +1514,30 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
         }
     }
     return CTFMM_OK;
+}
+
+}  // namespace
+
+ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const double* q, double* phi,
+                            double* grad) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "n out of range");
+    if (n == 0) return CTFMM_OK;
+    if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
+    if (c->prm.tree == CTFMM_TREE_ADAPTIVE) return evaluate_adaptive(c, (int)n, xyz, q, phi, grad);
+    return evaluate_uniform(c, n, xyz, q, nullptr, phi, grad);
+}
+
+ctfmm_status ctfmm_evaluate_dipoles(ctfmm_ctx* c, int64_t n, const double* xyz, const double* q, const double* dip,
+                                    double* phi, double* grad) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(c, CTFMM_EINVAL, "n out of range");
+    if (n == 0) return CTFMM_OK;
+    if (!xyz || !q || !dip) return fail(c, CTFMM_EINVAL, "null xyz, q or dip");
+    if (c->prm.tree != CTFMM_TREE_UNIFORM) return fail(c, CTFMM_EUNSUPPORTED, "point dipoles need the uniform tree");
+    return evaluate_uniform(c, n, xyz, q, dip, phi, grad);
 }
 
 ctfmm_status ctfmm_evaluate_batched(ctfmm_ctx* c, int32_t nsys, const int64_t* offsets, const int32_t* orders,

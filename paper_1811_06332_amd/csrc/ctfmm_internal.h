@@ -153,15 +153,20 @@ struct AdaptM2L {
 // to 64 particles at a time in LDS and lanes over f.  (2) The detracer:
 // M~_n = sum_f DET[n][f] S_f for the independent n (Eq. P2M with Eq.
 // Detracer).  Particles [b, e) of P; writes the ldm_of(P) entries of Mc.
-template <int PP>
+// DIP: the particles also carry point dipoles d_a (Pd, xyz), each a pure
+// dipole (rank-1 moment -d_a) moved from x_a to z by Eq. M2M (Appendix B.1):
+// S_f += -(1/h) sum_i d_{a,i} f_i u_a^(f - e_i).
+template <int PP, bool DIP = false>
 __device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b, int e,
-                                const double4* __restrict__ P, const DevTables& T, double* __restrict__ Mc) {
+                                const double4* __restrict__ P, const DevTables& T, double* __restrict__ Mc,
+                                const double4* __restrict__ Pd = nullptr) {
     const int lane = threadIdx.x;
     constexpr int nc = (PP + 1) * (PP + 1);
     constexpr int nf = (PP + 1) * (PP + 2) * (PP + 3) / 6;
     constexpr int ldm = ldm_of(PP);
     __shared__ double pw[64][3][PP + 1];
     __shared__ double qs[64];
+    __shared__ double ds[DIP ? 64 : 1][3];
     __shared__ double S[nf];
     constexpr int FPL = (nf + 63) / 64;  // full components per lane
     double acc[FPL];
@@ -189,12 +194,27 @@ __device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b
                 }
             }
             qs[lane] = pt.w;
+            if (DIP) {
+                const double4 d = Pd[s0 + lane];
+                ds[DIP ? lane : 0][0] = -d.x / h;
+                ds[DIP ? lane : 0][1] = -d.y / h;
+                ds[DIP ? lane : 0][2] = -d.z / h;
+            }
         }
         __syncthreads();
         for (int i = 0; i < cnt; ++i) {
             const double q = qs[i];
 #pragma unroll
-            for (int k = 0; k < FPL; ++k) acc[k] += q * pw[i][0][fa[k]] * pw[i][1][fb[k]] * pw[i][2][fc[k]];
+            for (int k = 0; k < FPL; ++k) {
+                const double X = pw[i][0][fa[k]], Y = pw[i][1][fb[k]], Z = pw[i][2][fc[k]];
+                acc[k] += q * X * Y * Z;
+                if (DIP) {
+                    const int j = DIP ? i : 0;
+                    acc[k] += ds[j][0] * fa[k] * pw[i][0][max(fa[k] - 1, 0)] * Y * Z +
+                              ds[j][1] * fb[k] * X * pw[i][1][max(fb[k] - 1, 0)] * Z +
+                              ds[j][2] * fc[k] * X * Y * pw[i][2][max(fc[k] - 1, 0)];
+                }
+            }
         }
         __syncthreads();
     }
@@ -218,8 +238,12 @@ __device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b
 // ---- launchers (ctfmm_kernels.hip); every one enqueues on `s` ----
 void launch_keys(hipStream_t s, int n, const double* xyz, Box box, uint32_t* keys, int32_t* idx, int* err);
 void launch_gather(hipStream_t s, int n, const int32_t* idx, const double* xyz, const double* q, double4* P);
+// point dipoles in sorted order (x, y, z, 0)
+void launch_gather_dip(hipStream_t s, int n, const int32_t* idx, const double* dip, double4* Pd);
 void launch_leaf_start(hipStream_t s, int nleaves, const uint32_t* keys, int n, int32_t* start);
-void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M);
+// Pd (may be null): point dipoles in sorted order
+void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M,
+                const double4* Pd = nullptr);
 void launch_m2m(hipStream_t s, int p, int parent_level, const double* Mchild, double* Mparent, const DevTables& T);
 void launch_offset_dtensors(hipStream_t s, int p, double* Dv);
 void launch_build_k(hipStream_t s, int p, const double* Dv, const DevTables& T, double* Kt);
@@ -227,7 +251,7 @@ void launch_l2l(hipStream_t s, int p, int parent_level, const double* Lparent, d
 void launch_l2p(hipStream_t s, int p, int n, Box box, const uint32_t* keys, const double4* P, const double* L,
                 double4* F);
 void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32_t* start, const double4* P,
-                const int32_t* idx, const double4* F, double* phi, double* grad);
+                const int32_t* idx, const double4* F, double* phi, double* grad, const double4* Pd = nullptr);
 // M2L operand precision (ctfmm_precision values)
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 size_t m2l_packed_bytes(int p, int prec);

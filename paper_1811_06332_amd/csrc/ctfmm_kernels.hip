@@ -65,6 +65,19 @@ void launch_gather(hipStream_t s, int n, const int32_t* idx, const double* xyz, 
     hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, n, idx, xyz, q, P);
 }
 
+__global__ void k_gather_dip(int n, const int32_t* __restrict__ idx, const double* __restrict__ dip,
+                             double4* __restrict__ Pd) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const size_t i = (size_t)idx[s];
+    Pd[s] = make_double4(dip[3 * i], dip[3 * i + 1], dip[3 * i + 2], 0.0);
+}
+
+void launch_gather_dip(hipStream_t s, int n, const int32_t* idx, const double* dip, double4* Pd) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_dip, dim3(cdiv(n, 256)), dim3(256), 0, s, n, idx, dip, Pd);
+}
+
 // start[c] = first sorted position whose key is >= c (c = 0..nleaves)
 __global__ void k_leaf_start(int nleaves, const uint32_t* __restrict__ keys, int n, int32_t* __restrict__ start) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,21 +97,29 @@ void launch_leaf_start(hipStream_t s, int nleaves, const uint32_t* keys, int n, 
 // ------------------------------------------------------------------ P2M
 
 // One wavefront per leaf (the P2M of p2m_cell, ctfmm_internal.h).
-template <int PP>
+template <int PP, bool DIP>
 __global__ __launch_bounds__(64) void k_p2m(Box box, const int32_t* __restrict__ start,
-                                            const double4* __restrict__ P, DevTables T, double* __restrict__ M) {
+                                            const double4* __restrict__ P, DevTables T, double* __restrict__ M,
+                                            const double4* __restrict__ Pd) {
     const uint32_t c = blockIdx.x;
     const double h = box.side / (double)(1 << box.depth);
     const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
     const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
     const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
-    p2m_cell<PP>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP));
+    p2m_cell<PP, DIP>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP), Pd);
 }
 
-void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M) {
+void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M,
+                const double4* Pd) {
     const long long nleaves = 1ll << (3 * box.depth);
     switch (p) {
-#define CASE(PP) case PP: hipLaunchKernelGGL(k_p2m<PP>, dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, T, M); break;
+#define CASE(PP)                                                                                                   \
+    case PP:                                                                                                       \
+        if (Pd)                                                                                                    \
+            hipLaunchKernelGGL((k_p2m<PP, true>), dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, T, M, Pd);  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_p2m<PP, false>), dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, T, M, Pd); \
+        break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;
@@ -299,13 +320,32 @@ __global__ __launch_bounds__(256) void k_l2p(int n, Box box, const uint32_t* __r
     F[s] = make_double4(f / h, gx * ih2, gy * ih2, gz * ih2);
 }
 
+// One point dipole d at x_s on the target x: potential d.r/|r|^3, r = x - x_s,
+// and its gradient d/|r|^3 - 3 (d.r) r/|r|^5 (the limit of two opposite
+// charges, Appendix B.1); nothing for coincident points.
+__device__ inline void pair_add_dip(double x, double y, double z, const double4 src, const double4 d, double& f,
+                                    double& gx, double& gy, double& gz) {
+    const double dx = x - src.x, dy = y - src.y, dz = z - src.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) return;
+    const double ir = 1.0 / sqrt(r2);
+    const double ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+    const double pr = d.x * dx + d.y * dy + d.z * dz;
+    f += pr * ir3;
+    gx += d.x * ir3 - 3.0 * pr * dx * ir5;
+    gy += d.y * ir3 - 3.0 * pr * dy * ir5;
+    gz += d.z * ir3 - 3.0 * pr * dz * ir5;
+}
+
 // P2P: one thread per (sorted) target; sources are the particles of the 27
-// adjacent-or-equal leaves, self excluded (Appendix C near field).  Adds the
-// far field F[s] if given and writes the outputs in input order.
+// adjacent-or-equal leaves, self excluded (Appendix C near field), with their
+// point dipoles Pd if given.  Adds the far field F[s] if given and writes the
+// outputs in input order.
 __global__ __launch_bounds__(256) void k_p2p(int n, Box box, const uint32_t* __restrict__ keys,
                                              const int32_t* __restrict__ start, const double4* __restrict__ Pt,
                                              const int32_t* __restrict__ idx, const double4* __restrict__ F,
-                                             double* __restrict__ phi, double* __restrict__ grad) {
+                                             double* __restrict__ phi, double* __restrict__ grad,
+                                             const double4* __restrict__ Pd) {
     const long long s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int n1 = 1 << box.depth;
@@ -330,7 +370,9 @@ __global__ __launch_bounds__(256) void k_p2p(int n, Box box, const uint32_t* __r
                 const int sb = start[cn], se = start[cn + 1];
                 for (int s2 = sb; s2 < se; ++s2) {
                     if (s2 == s) continue;
-                    pair_add(pt.x, pt.y, pt.z, Pt[s2], f, gx, gy, gz);
+                    const double4 src = Pt[s2];
+                    pair_add(pt.x, pt.y, pt.z, src, f, gx, gy, gz);
+                    if (Pd) pair_add_dip(pt.x, pt.y, pt.z, src, Pd[s2], f, gx, gy, gz);
                 }
             }
         }
@@ -357,9 +399,9 @@ void launch_l2p(hipStream_t s, int p, int n, Box box, const uint32_t* keys, cons
 }
 
 void launch_p2p(hipStream_t s, int n, Box box, const uint32_t* keys, const int32_t* start, const double4* P,
-                const int32_t* idx, const double4* F, double* phi, double* grad) {
+                const int32_t* idx, const double4* F, double* phi, double* grad, const double4* Pd) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_p2p, dim3(cdiv(n, 256)), dim3(256), 0, s, n, box, keys, start, P, idx, F, phi, grad);
+    hipLaunchKernelGGL(k_p2p, dim3(cdiv(n, 256)), dim3(256), 0, s, n, box, keys, start, P, idx, F, phi, grad, Pd);
 }
 
 // ------------------------------------------------------------------ debug copy-out

@@ -22,7 +22,8 @@ CTFMM_DEPTH_MAX = 9
 CTFMM_ADAPTIVE_LEVEL_MAX = 21
 
 EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_allocator",
-            "ctfmm_evaluate", "ctfmm_evaluate_f32", "ctfmm_evaluate_batched", "ctfmm_evaluate_batched_f32",
+            "ctfmm_evaluate", "ctfmm_evaluate_dipoles", "ctfmm_evaluate_f32", "ctfmm_evaluate_batched",
+            "ctfmm_evaluate_batched_f32",
             "ctfmm_copy_expansions", "ctfmm_copy_tree", "ctfmm_tree_stats", "ctfmm_set_m2l_tile",
             "ctfmm_get_m2l_tile", "ctfmm_set_order_table", "ctfmm_set_order_hash", "ctfmm_set_order_model",
             "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_backward_noalloc", "ctfmm_mlp_train",
@@ -82,6 +83,7 @@ def load():
         L.ctfmm_set_allocator.argtypes = [vp, vp, vp, vp]
         L.ctfmm_evaluate.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ctfmm_evaluate_f32.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.ctfmm_evaluate_dipoles.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ctfmm_evaluate_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.ctfmm_evaluate_batched_f32.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.ctfmm_copy_expansions.argtypes = [vp, i32, i32, vp, C.c_size_t]
@@ -160,6 +162,15 @@ def ctfmm_evaluate(ctx, xyz, q, phi=None, grad=None):
     n = int(q.shape[0])
     _io_check(n, "torch.float64", xyz, q, phi, grad)
     _check(load().ctfmm_evaluate(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), _ptr(phi), _ptr(grad)), C.c_void_p(ctx))
+
+
+def ctfmm_evaluate_dipoles(ctx, xyz, q, dip, phi=None, grad=None):
+    """As ctfmm_evaluate with point dipoles dip: cuda float64 [n,3]."""
+    n = int(q.shape[0])
+    _io_check(n, "torch.float64", xyz, q, phi, grad)
+    _io_check(n, "torch.float64", dip, None, None, None)
+    _check(load().ctfmm_evaluate_dipoles(C.c_void_p(ctx), n, _ptr(xyz), _ptr(q), _ptr(dip), _ptr(phi), _ptr(grad)),
+           C.c_void_p(ctx))
 
 
 def ctfmm_evaluate_f32(ctx, xyz, q, phi=None, grad=None):
@@ -450,6 +461,18 @@ class FMM:
         if grad is None:
             grad = torch.empty((n, 3), dtype=torch.float64, device=q.device)
         ctfmm_evaluate(self.ctx, xyz, q, phi, grad)
+        if sync:
+            ctfmm_sync(self.ctx)
+        return phi, grad
+
+    def evaluate_dipoles(self, xyz, q, dip, phi=None, grad=None, sync=False):
+        import torch
+        n = int(q.shape[0])
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float64, device=q.device)
+        if grad is None:
+            grad = torch.empty((n, 3), dtype=torch.float64, device=q.device)
+        ctfmm_evaluate_dipoles(self.ctx, xyz, q, dip, phi, grad)
         if sync:
             ctfmm_sync(self.ctx)
         return phi, grad
