@@ -76,6 +76,12 @@ def _lib():
         L.oracle_fmm_adaptive_pair_orders.argtypes = [i64, _dp, _dp, i32, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
                                                       C.c_void_p, C.c_void_p, i32, C.c_void_p]
         L.oracle_fmm_adaptive_pair_orders.restype = i32
+        L.oracle_fmm_dual.argtypes = [i64, _dp, _dp, i32, i32, d, i32, _dp, d, i64, C.c_void_p, _dp, _dp,
+                                      C.c_void_p, C.c_void_p, i32]
+        L.oracle_fmm_dual.restype = i32
+        L.oracle_dual_pairs.argtypes = [i64, _dp, _dp, i32, d, i32, _dp, d, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]
+        L.oracle_dual_pairs.restype = i32
         L.oracle_adaptive_tree.argtypes = [i64, _dp, i32, _dp, d, C.c_void_p] + [C.c_void_p] * 15
         L.oracle_adaptive_tree.restype = i32
         _lib_handle = L
@@ -315,6 +321,61 @@ def fmm_adaptive(xyz, q, p, leaf_max, lo=None, side=0.0, targets=None, nthreads=
     info = {k: int(v) for k, v in zip(names, st[:7])}
     info["root_lo"] = root[:3].copy(); info["root_side"] = float(root[3])
     return phi, grad, info
+
+
+DUAL_CENTRES = {"geometric": 0, "mass": 1, "ap": 2}
+
+
+def fmm_dual(xyz, q, p, leaf_max, theta, centre="geometric", lo=None, side=0.0, targets=None, nthreads=0,
+             stats=False):
+    """The FMM driven by the dual-tree traversal with the theta MAC (see
+    oracle_fmm_dual); centre "geometric", "mass" or "ap" (centre of mass,
+    dipole dropped, gradient only: phi comes back as None)."""
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
+    n = xyz.shape[0]
+    if targets is None:
+        nt, tp, keep = n, None, None
+    else:
+        keep = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt, tp = keep.size, keep.ctypes.data
+    phi = np.zeros(nt); grad = np.zeros(3 * nt)
+    st = np.zeros(8, dtype=np.int64); root = np.zeros(4)
+    lo_arr = _vec(lo if lo is not None else (0.0, 0.0, 0.0), 3)
+    rc = _lib().oracle_fmm_dual(n, np.ascontiguousarray(xyz.ravel()), q, p, leaf_max, float(theta),
+                                DUAL_CENTRES[centre], lo_arr, float(side) if lo is not None else 0.0,
+                                nt, tp, phi, grad, st.ctypes.data, root.ctypes.data, nthreads)
+    del keep
+    if rc != 0:
+        raise RuntimeError(f"oracle_fmm_dual failed with code {rc}")
+    grad = grad.reshape(-1, 3)
+    if centre == "ap":
+        phi = None
+    if not stats:
+        return phi, grad
+    info = dict(zip(["nodes", "leaves", "max_level", "m2l_pairs", "direct_pairs"], (int(v) for v in st[:5])))
+    return phi, grad, info
+
+
+def dual_pairs(xyz, q, leaf_max, theta, centre="geometric", lo=None, side=0.0):
+    """The traversal's integer result (see oracle_dual_pairs): dict with
+    m2l (k, 2) accepted pairs in traversal order, p2p (k, 2) ordered direct
+    pairs, zr (nodes, 4) centres and radii; node numbers as adaptive_tree."""
+    xyz = _vec(xyz).reshape(-1, 3); q = _vec(q, xyz.shape[0])
+    n = xyz.shape[0]
+    lo_arr = _vec(lo if lo is not None else (0.0, 0.0, 0.0), 3)
+    sd = float(side) if lo is not None else 0.0
+    args = (n, np.ascontiguousarray(xyz.ravel()), q, leaf_max, float(theta), DUAL_CENTRES[centre], lo_arr, sd)
+    sizes = np.zeros(3, dtype=np.int64)
+    rc = _lib().oracle_dual_pairs(*args, sizes.ctypes.data, None, None, None)
+    if rc != 0:
+        raise RuntimeError(f"oracle_dual_pairs failed with code {rc}")
+    m2l = np.zeros((int(sizes[1]), 2), dtype=np.int32)
+    p2p = np.zeros((int(sizes[2]), 2), dtype=np.int32)
+    zr = np.zeros((int(sizes[0]), 4))
+    rc = _lib().oracle_dual_pairs(*args, sizes.ctypes.data, m2l.ctypes.data, p2p.ctypes.data, zr.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_dual_pairs failed with code {rc}")
+    return {"m2l": m2l, "p2p": p2p, "zr": zr}
 
 
 def adaptive_tree(xyz, leaf_max, lo=None, side=0.0):

@@ -1324,3 +1324,279 @@ static int fmm_adaptive_impl(int64_t n, const double *xyz, const double *q, int 
     oa_free(&T);
     return 0;
 }
+
+/* ================================================= dual-tree traversal (θ-MAC) */
+/*
+ * The FMM driver of Appendix C on the adaptive octree (geometric splits at
+ * the cell centre, leaves of at most leaf_max particles):
+ *   - expansion centre of every node: its geometric centre (centre = 0), or
+ *     the charge-weighted mean of its particles (centre = 1, and the AP
+ *     variant, centre = 2), the geometric centre where the node's total
+ *     charge is not positive; enclosing radius r = the largest distance
+ *     from the centre to a particle of the node;
+ *   - P2M at the leaves, M2M to the parents (Eq. P2M, Eq. M2M);
+ *   - dual-tree traversal from (root, root): a pair of distinct nodes
+ *     (A, B) is accepted when theta |z_B - z_A| > r_A + r_B (the MAC, read
+ *     with scalar radii) and then translated both ways by M2L (Eq. M2L);
+ *     otherwise the larger node -- by enclosing radius, the first of the
+ *     pair on a tie, and never a leaf -- is opened and each of its children
+ *     is paired with the other node; two leaves that fail the MAC are
+ *     summed directly both ways.  A node paired with itself is replaced by
+ *     the pairs of its children (each child with itself, and each two
+ *     children once, in octant order); a leaf with itself is summed
+ *     directly;
+ *   - L2L from every node to its children (Eq. L2L), L2P at the leaves
+ *     (Eq. L2P), plus the direct part.
+ * The AP variant (centre = 2) drops the rank-1 multipole (the dipole, which
+ * vanishes about the centre of mass) from every M2L and gives the gradient
+ * only (phi is not written and may be NULL); it needs positive charges.
+ * theta = 0 accepts no pair: the result is the direct sum.
+ */
+typedef struct {
+    oatree *T;
+    double theta;
+    double (*zr)[4];   /* centre and radius per node */
+    ivec m2l;          /* accepted pairs (a, b), a != b, in traversal order */
+    ivec *p2p;         /* per leaf: its direct partners (both ways, itself included) */
+    int64_t n_p2p;     /* unordered direct pairs, self pairs included */
+} oadual;
+
+static void dual_pair(oadual *D, int a, int b)
+{
+    oatree *T = D->T;
+    const oanode *A = &T->nd[a], *B = &T->nd[b];
+    if (a == b) {
+        if (A->leaf) {
+            ivec_push(&D->p2p[a], a);
+            D->n_p2p++;
+            return;
+        }
+        for (int i = 0; i < 8; ++i) {
+            int ci = A->child[i];
+            if (ci < 0) continue;
+            for (int j = i; j < 8; ++j) {
+                int cj = A->child[j];
+                if (cj >= 0) dual_pair(D, ci, cj);
+            }
+        }
+        return;
+    }
+    double dx = D->zr[b][0] - D->zr[a][0], dy = D->zr[b][1] - D->zr[a][1], dz = D->zr[b][2] - D->zr[a][2];
+    double dist = sqrt(dx * dx + dy * dy + dz * dz);
+    if (D->theta * dist > D->zr[a][3] + D->zr[b][3]) {
+        ivec_push(&D->m2l, a);
+        ivec_push(&D->m2l, b);
+        return;
+    }
+    if (A->leaf && B->leaf) {
+        ivec_push(&D->p2p[a], b);
+        ivec_push(&D->p2p[b], a);
+        D->n_p2p++;
+        return;
+    }
+    int open_a = !A->leaf && (B->leaf || D->zr[a][3] >= D->zr[b][3]);
+    const oanode *O = open_a ? A : B;
+    for (int i = 0; i < 8; ++i) {
+        int c = O->child[i];
+        if (c < 0) continue;
+        if (open_a) dual_pair(D, c, b);
+        else dual_pair(D, a, c);
+    }
+}
+
+/* centres and radii (see above), then the traversal */
+static int dual_setup(oadual *D, oatree *T, const double *xyz, const double *q, double theta, int centre)
+{
+    memset(D, 0, sizeof(*D));
+    D->T = T;
+    D->theta = theta;
+    D->zr = (double (*)[4])calloc((size_t)T->nn, sizeof(double[4]));
+    D->p2p = (ivec *)calloc((size_t)T->nn, sizeof(ivec));
+    if (!D->zr || !D->p2p) return -2;
+    for (int i = 0; i < T->nn; ++i) {
+        const oanode *x = &T->nd[i];
+        double z[3];
+        oa_center(T, x, z);
+        if (centre != 0) {
+            double w = 0.0, s[3] = {0.0, 0.0, 0.0};
+            for (int64_t k = x->b; k < x->e; ++k) {
+                int64_t a = T->order[k];
+                w += q[a];
+                for (int d = 0; d < 3; ++d) s[d] += q[a] * xyz[3 * a + d];
+            }
+            if (w > 0.0)
+                for (int d = 0; d < 3; ++d) z[d] = s[d] / w;
+        }
+        double r = 0.0;
+        for (int64_t k = x->b; k < x->e; ++k) {
+            int64_t a = T->order[k];
+            double dx = xyz[3 * a] - z[0], dy = xyz[3 * a + 1] - z[1], dz = xyz[3 * a + 2] - z[2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d > r) r = d;
+        }
+        D->zr[i][0] = z[0]; D->zr[i][1] = z[1]; D->zr[i][2] = z[2]; D->zr[i][3] = r;
+    }
+    dual_pair(D, 0, 0);
+    return 0;
+}
+
+static void dual_free(oadual *D)
+{
+    if (D->p2p)
+        for (int i = 0; i < D->T->nn; ++i) free(D->p2p[i].v);
+    free(D->p2p);
+    free(D->m2l.v);
+    free(D->zr);
+}
+
+static int dual_check(int64_t n, int leaf_max, double theta, int centre, const double *q)
+{
+    if (n < 1 || leaf_max < 1 || !(theta >= 0.0) || centre < 0 || centre > 2) return -1;
+    if (centre == 2)
+        for (int64_t a = 0; a < n; ++a)
+            if (!(q[a] > 0.0)) return -1;
+    return 0;
+}
+
+int oracle_fmm_dual(int64_t n, const double *xyz, const double *q, int p, int leaf_max, double theta, int centre,
+                    const double lo_in[3], double side_in, int64_t nt, const int64_t *tgt, double *phi, double *grad,
+                    int64_t *stats, double *root_out, int nthreads)
+{
+    init_tables();
+    if (p < 0 || p > OR_PMAX || dual_check(n, leaf_max, theta, centre, q) != 0) return -1;
+    if (centre != 2 && !phi) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    oatree T;
+    if (oa_make_tree(&T, n, xyz, q, p, leaf_max, lo_in, side_in) != 0) { oa_free(&T); return -2; }
+    if (root_out) { root_out[0] = T.lo[0]; root_out[1] = T.lo[1]; root_out[2] = T.lo[2]; root_out[3] = T.side; }
+    int nn = T.nn, nf = T.nf;
+    oadual D;
+    T.M = (double **)calloc((size_t)nn, sizeof(double *));
+    T.L = (double **)calloc((size_t)nn, sizeof(double *));
+    if (!T.M || !T.L || dual_setup(&D, &T, xyz, q, theta, centre) != 0) { dual_free(&D); oa_free(&T); return -2; }
+    for (int i = 0; i < nn; ++i) {
+        T.M[i] = (double *)calloc((size_t)nf, sizeof(double));
+        T.L[i] = (double *)calloc((size_t)nf, sizeof(double));
+    }
+    /* upward: P2M at the leaves, M2M from the deepest level up */
+    for (int i = 0; i < nn; ++i) {
+        if (!T.nd[i].leaf) continue;
+        int64_t cnt = T.nd[i].e - T.nd[i].b;
+        double *px = (double *)malloc((size_t)cnt * 3 * sizeof(double));
+        double *pq = (double *)malloc((size_t)cnt * sizeof(double));
+        for (int64_t s2 = T.nd[i].b; s2 < T.nd[i].e; ++s2) {
+            int64_t a = T.order[s2];
+            for (int d = 0; d < 3; ++d) px[3 * (s2 - T.nd[i].b) + d] = xyz[3 * a + d];
+            pq[s2 - T.nd[i].b] = q[a];
+        }
+        oracle_p2m(p, D.zr[i], cnt, px, pq, T.M[i]);
+        free(px);
+        free(pq);
+    }
+    for (int l = T.maxlev; l >= 1; --l)
+        for (int i = 0; i < nn; ++i) {
+            if (T.nd[i].level != l - 1 || T.nd[i].leaf) continue;
+            for (int o = 0; o < 8; ++o) {
+                int c = T.nd[i].child[o];
+                if (c < 0) continue;
+                double dd[3] = {D.zr[c][0] - D.zr[i][0], D.zr[c][1] - D.zr[i][1], D.zr[c][2] - D.zr[i][2]};
+                oracle_m2m(p, dd, T.M[c], T.M[i]);
+            }
+        }
+    /* AP: the dipole about the centre of mass is dropped */
+    if (centre == 2 && p >= 1)
+        for (int i = 0; i < nn; ++i) {
+            T.M[i][g_idx[1][0][0]] = 0.0;
+            T.M[i][g_idx[0][1][0]] = 0.0;
+            T.M[i][g_idx[0][0][1]] = 0.0;
+        }
+    /* the accepted pairs, both ways */
+    for (int k = 0; k < D.m2l.n; k += 2) {
+        int a = D.m2l.v[k], b = D.m2l.v[k + 1];
+        double r[3] = {D.zr[b][0] - D.zr[a][0], D.zr[b][1] - D.zr[a][1], D.zr[b][2] - D.zr[a][2]};
+        double rm[3] = {-r[0], -r[1], -r[2]};
+        oracle_m2l(p, r, T.M[a], T.L[b]);   /* A -> B */
+        oracle_m2l(p, rm, T.M[b], T.L[a]);  /* B -> A */
+    }
+    /* downward: L2L from the root down */
+    for (int l = 1; l <= T.maxlev; ++l)
+        for (int i = 0; i < nn; ++i) {
+            if (T.nd[i].level != l) continue;
+            int par = T.nd[i].parent;
+            double dd[3] = {D.zr[i][0] - D.zr[par][0], D.zr[i][1] - D.zr[par][1], D.zr[i][2] - D.zr[par][2]};
+            oracle_l2l(p, dd, T.L[par], T.L[i]);
+        }
+    /* evaluation: L2P at the particle's leaf + the direct partners */
+    int64_t cnt = tgt ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t b = tgt ? tgt[t] : t;
+        int B = (int)T.leaf_of[b];
+        const double *xb = &xyz[3 * b];
+        double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+        double rb[3] = {xb[0] - D.zr[B][0], xb[1] - D.zr[B][1], xb[2] - D.zr[B][2]};
+        oracle_l2p(p, rb, T.L[B], &f, g);
+        for (int k = 0; k < D.p2p[B].n; ++k) {
+            int C = D.p2p[B].v[k];
+            for (int64_t s2 = T.nd[C].b; s2 < T.nd[C].e; ++s2) {
+                int64_t a = T.order[s2];
+                if (a == b) continue;
+                pair_kernel(xb, &xyz[3 * a], q[a], &f, g);
+            }
+        }
+        if (phi) phi[t] = centre == 2 ? 0.0 : f;
+        grad[3 * t + 0] = g[0];
+        grad[3 * t + 1] = g[1];
+        grad[3 * t + 2] = g[2];
+    }
+    if (stats) {
+        int64_t st[8] = {T.nn, 0, T.maxlev, D.m2l.n / 2, D.n_p2p, 0, 0, 0};
+        for (int i = 0; i < T.nn; ++i) st[1] += T.nd[i].leaf;
+        memcpy(stats, st, sizeof(st));
+    }
+    dual_free(&D);
+    oa_free(&T);
+    return 0;
+}
+
+/*
+ * The integer result of the traversal, in the node order of
+ * oracle_adaptive_tree: sizes = {nodes, accepted pairs, ordered direct leaf
+ * pairs}; m2l[2k], m2l[2k+1] = the k-th accepted pair (a, b) in traversal
+ * order; p2p = ordered direct pairs (leaf, partner), leaves in node order and
+ * partners in traversal order (itself included); zr = centre and radius per
+ * node.  Outputs may be NULL (sizes only); m2l and p2p must hold the sizes.
+ */
+int oracle_dual_pairs(int64_t n, const double *xyz, const double *q, int leaf_max, double theta, int centre,
+                      const double lo_in[3], double side_in, int64_t *sizes, int32_t *m2l, int32_t *p2p, double *zr)
+{
+    init_tables();
+    if (!sizes || dual_check(n, leaf_max, theta, centre, q) != 0) return -1;
+    oatree T;
+    if (oa_make_tree(&T, n, xyz, q, 0, leaf_max, lo_in, side_in) != 0) { oa_free(&T); return -2; }
+    oadual D;
+    if (dual_setup(&D, &T, xyz, q, theta, centre) != 0) { dual_free(&D); oa_free(&T); return -2; }
+    int64_t np = 0;
+    for (int i = 0; i < T.nn; ++i) np += D.p2p[i].n;
+    sizes[0] = T.nn;
+    sizes[1] = D.m2l.n / 2;
+    sizes[2] = np;
+    if (m2l) memcpy(m2l, D.m2l.v, (size_t)D.m2l.n * sizeof(int32_t));
+    if (p2p) {
+        int64_t k = 0;
+        for (int i = 0; i < T.nn; ++i)
+            for (int j = 0; j < D.p2p[i].n; ++j) {
+                p2p[2 * k] = i;
+                p2p[2 * k + 1] = D.p2p[i].v[j];
+                ++k;
+            }
+    }
+    if (zr) memcpy(zr, D.zr, (size_t)T.nn * sizeof(double[4]));
+    dual_free(&D);
+    oa_free(&T);
+    return 0;
+}

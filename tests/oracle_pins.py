@@ -744,4 +744,150 @@ def pin_dipole_fmm_vs_direct_decay(o):
     assert rel(gc, gd) > 100 * errs[-1][1]
 
 
+# ------------------------------------------------------------ dual-tree traversal with the theta MAC
+
+def _dual_case(seed, n=600):
+    """a Plummer sphere (leaves at several levels)"""
+    from paper_1811_06332_amd.workloads import plummer
+    xyz, q = plummer(n, seed)
+    return xyz, q
+
+
+def pin_dual_theta0_is_direct(o):
+    """theta = 0 accepts no pair: every centre mode gives the direct sum."""
+    xyz, q = _dual_case(60, 500)
+    pd, gd = o.direct(xyz, q)
+    for centre in ("geometric", "mass", "ap"):
+        pf, gf, info = o.fmm_dual(xyz, q, 6, 8, 0.0, centre, stats=True)
+        assert info["m2l_pairs"] == 0
+        assert rel(gf, gd) < 1e-13, centre
+        if centre != "ap":
+            assert rel(pf, pd) < 1e-13, centre
+
+
+def pin_dual_vs_direct_decay(o):
+    """The error against the direct sum falls with p at fixed theta and with
+    theta at fixed p, in every centre mode."""
+    xyz, q = _dual_case(61, 1500)
+    pd, gd = o.direct(xyz, q)
+    for centre in ("geometric", "mass", "ap"):
+        errs = []
+        for p in (2, 4, 6, 8):
+            pf, gf = o.fmm_dual(xyz, q, p, 12, 0.5, centre)
+            errs.append(rel(gf, gd) + (rel(pf, pd) if pf is not None else 0.0))
+        assert all(b < 0.5 * a for a, b in zip(errs, errs[1:])), (centre, errs)
+        assert errs[-1] < 3e-4, (centre, errs)
+        et = [rel(o.fmm_dual(xyz, q, 4, 12, th, centre)[1], gd) for th in (0.3, 0.5, 0.7)]
+        assert et[0] < et[1] < et[2], (centre, et)
+
+
+def pin_dual_momentum_conserved(o):
+    """Mutual interactions: the total force sum_b q_b grad phi_b vanishes to
+    rounding (Newton's third law), while a single one-way translation would
+    leave an error of the size of the truncation error."""
+    xyz, q = _dual_case(62, 1200)
+    pd, gd = o.direct(xyz, q)
+    for centre in ("geometric", "mass", "ap"):
+        for p in (2, 5):
+            _, gf = o.fmm_dual(xyz, q, p, 10, 0.7, centre)
+            f = q[:, None] * gf
+            assert np.abs(f.sum(0)).max() < 1e-13 * np.abs(f).sum(), (centre, p)
+            assert rel(gf, gd) > 1e-6  # the expansions are really used
+
+
+def _dual_by_definition(o, xyz, q, theta, centre, t):
+    """Centres, radii and the dual-tree traversal written out here from the
+    definitions (numpy centres, recursion in Python) on the exported tree."""
+    nn = len(t["level"])
+    lo, side = o.auto_root(xyz)
+    lo = np.asarray(lo, dtype=np.float64)
+    zr = np.zeros((nn, 4))
+    child = [[] for _ in range(nn)]
+    for i in range(nn):
+        par = int(t["parent"][i])
+        if par >= 0:
+            child[par].append(i)
+    for i in range(nn):
+        idx = t["order"][t["pb"][i]:t["pe"][i]]
+        l, ix, iy, iz = _decode_key(int(t["level"][i]), int(t["key"][i]))
+        h = side / 2.0 ** l
+        z = lo + (np.array([ix, iy, iz]) + 0.5) * h
+        if centre != "geometric" and q[idx].sum() > 0:
+            z = (q[idx, None] * xyz[idx]).sum(0) / q[idx].sum()
+        zr[i, :3] = z
+        zr[i, 3] = np.sqrt(((xyz[idx] - z) ** 2).sum(1)).max()
+    key = {i: _decode_key(int(t["level"][i]), int(t["key"][i])) for i in range(nn)}
+    for i in range(nn):  # children in octant order
+        child[i].sort(key=lambda c: (key[c][1] & 1) | ((key[c][2] & 1) << 1) | ((key[c][3] & 1) << 2))
+    leaf = t["leaf"].astype(bool)
+    m2l, p2p = [], {i: [] for i in range(nn)}
+
+    def walk(a, b):
+        if a == b:
+            if leaf[a]:
+                p2p[a].append(a)
+                return
+            for x, ca in enumerate(child[a]):
+                for cb in child[a][x:]:
+                    walk(ca, cb)
+            return
+        d = np.sqrt(((zr[b, :3] - zr[a, :3]) ** 2).sum())
+        if theta * d > zr[a, 3] + zr[b, 3]:
+            m2l.append((a, b))
+            return
+        if leaf[a] and leaf[b]:
+            p2p[a].append(b)
+            p2p[b].append(a)
+            return
+        if not leaf[a] and (leaf[b] or zr[a, 3] >= zr[b, 3]):
+            for c in child[a]:
+                walk(c, b)
+        else:
+            for c in child[b]:
+                walk(a, c)
+
+    walk(0, 0)
+    return zr, m2l, p2p
+
+
+def pin_dual_traversal_by_definition(o):
+    """The oracle's centres, radii, accepted pairs and direct pairs equal the
+    ones worked out here from the definitions (same order), every accepted
+    pair passes the MAC and every direct pair fails it, and together they
+    cover every ordered particle pair exactly once."""
+    for seed, n, leaf_max, theta in ((63, 400, 6, 0.5), (64, 300, 4, 0.8)):
+        xyz, q = _dual_case(seed, n)
+        for centre in ("geometric", "mass", "ap"):
+            t = o.adaptive_tree(xyz, leaf_max)
+            got = o.dual_pairs(xyz, q, leaf_max, theta, centre)
+            zr, m2l, p2p = _dual_by_definition(o, xyz, q, theta, centre, t)
+            assert np.allclose(got["zr"], zr, rtol=1e-14, atol=1e-14), centre
+            assert [tuple(r) for r in got["m2l"].tolist()] == m2l, centre
+            ref = [(i, c) for i in range(len(zr)) for c in p2p[i]]
+            assert [tuple(r) for r in got["p2p"].tolist()] == ref, centre
+            cover = np.zeros((n, n), dtype=np.int32)
+            parts = [t["order"][t["pb"][i]:t["pe"][i]] for i in range(len(zr))]
+            for a, b in m2l:
+                cover[np.ix_(parts[b], parts[a])] += 1
+                cover[np.ix_(parts[a], parts[b])] += 1
+            for b, c in ref:
+                cover[np.ix_(parts[b], parts[c])] += 1
+            assert np.all(cover == 1), centre
+            assert len(m2l) > 50, centre
+
+
+def pin_dual_ap_is_centre_of_mass_ft(o):
+    """About the centre of mass the dipole of positive charges vanishes, so
+    the AP variant (dipole dropped, gradient only) gives the gradient of the
+    fully traceless expansion about the same centres to rounding."""
+    xyz, q = _dual_case(65, 1000)
+    z = (q[:, None] * xyz).sum(0) / q.sum()
+    M = o.p2m(4, z, xyz, q)
+    assert np.abs(M[1:4]).max() < 1e-14 * np.abs(M).max()
+    for p in (1, 3, 6):
+        _, gm = o.fmm_dual(xyz, q, p, 8, 0.6, "mass")
+        _, ga = o.fmm_dual(xyz, q, p, 8, 0.6, "ap")
+        assert rel(ga, gm) < 1e-12, p
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -80,6 +80,24 @@ MUTANTS = [
      "grad[0] += pa[0] * ir3 - pr * dx * ir5;", None),
     ("dipole_near_field_dropped",
      "if (T->dip) pair_kernel_dipole(&T->xyz[3 * b], &T->xyz[3 * a], &T->dip[3 * a], &f, g);", "(void)0;", None),
+    ("dual_mac_reversed", "if (D->theta * dist > D->zr[a][3] + D->zr[b][3]) {",
+     "if (D->theta * dist < D->zr[a][3] + D->zr[b][3]) {", None),
+    ("dual_one_way_m2l", "oracle_m2l(p, rm, T.M[b], T.L[a]);  /* B -> A */", "(void)rm;", None),
+    ("dual_open_smaller", "(B->leaf || D->zr[a][3] >= D->zr[b][3])", "(B->leaf || D->zr[a][3] <= D->zr[b][3])",
+     None),
+    ("dual_children_not_self_paired", "for (int j = i; j < 8; ++j) {\n                int cj = A->child[j];",
+     "for (int j = i + 1; j < 8; ++j) {\n                int cj = A->child[j];", None),
+    ("dual_unweighted_centre", "for (int d = 0; d < 3; ++d) s[d] += q[a] * xyz[3 * a + d];",
+     "for (int d = 0; d < 3; ++d) s[d] += q[a] * q[a] * xyz[3 * a + d];", None),
+    ("dual_radius_last_particle", "double d = sqrt(dx * dx + dy * dy + dz * dz);\n            if (d > r) r = d;",
+     "double d = sqrt(dx * dx + dy * dy + dz * dz);\n            r = d;", None),
+    ("dual_ap_drops_monopole", "T.M[i][g_idx[1][0][0]] = 0.0;", "T.M[i][g_idx[0][0][0]] = 0.0;", None),
+    ("dual_m2m_offset_reversed",
+     "double dd[3] = {D.zr[c][0] - D.zr[i][0], D.zr[c][1] - D.zr[i][1], D.zr[c][2] - D.zr[i][2]};",
+     "double dd[3] = {D.zr[i][0] - D.zr[c][0], D.zr[i][1] - D.zr[c][1], D.zr[i][2] - D.zr[c][2]};", None),
+    ("dual_l2l_offset_reversed",
+     "double dd[3] = {D.zr[i][0] - D.zr[par][0], D.zr[i][1] - D.zr[par][1], D.zr[i][2] - D.zr[par][2]};",
+     "double dd[3] = {D.zr[par][0] - D.zr[i][0], D.zr[par][1] - D.zr[i][1], D.zr[par][2] - D.zr[i][2]};", None),
 ]
 
 
