@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define CTFMM_ABI_VERSION 3
+#define CTFMM_ABI_VERSION 4
 /* largest expansion order compiled in */
 #define CTFMM_P_MAX 10
 /* deepest uniform octree (2^(3*depth) leaves) */
@@ -60,7 +60,7 @@ typedef enum ctfmm_status {
 
 typedef enum ctfmm_tree {
     CTFMM_TREE_UNIFORM = 0,  /* uniform octree of the given depth over a cube */
-    CTFMM_TREE_ADAPTIVE = 1  /* a node holding more than leaf_max particles is split
+    CTFMM_TREE_ADAPTIVE = 1, /* a node holding more than leaf_max particles is split
                                 into its non-empty octants, down to level
                                 CTFMM_ADAPTIVE_LEVEL_MAX (Appendix C: geometric
                                 splits at the cell centre).  Interactions follow
@@ -72,6 +72,17 @@ typedef enum ctfmm_tree {
                                 the leaf's particles; X (the converse of W) by
                                 forming the local expansion directly from the
                                 coarse leaf's particles. */
+    CTFMM_TREE_DUAL = 2      /* the same octree (leaf_max, root cube), driven by
+                                the dual-tree traversal of Appendix C: node pairs
+                                that satisfy the multipole acceptance criterion
+                                theta |z_B - z_A| > r_A + r_B (z the expansion
+                                centres, r the enclosing radii) interact by M2L
+                                in both directions (Newton's third law holds to
+                                rounding); otherwise the node of larger radius is
+                                opened; leaf pairs that fail it are summed
+                                directly.  theta and the centres are set with
+                                ctfmm_set_mac (default 0.5, geometric centres).
+                                FP64 only; no batches, no dipoles. */
 } ctfmm_tree;
 
 /* Arithmetic of the M2L translation.  Everything else (P2M, M2M, L2L, L2P,
@@ -269,7 +280,8 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* ctx, ctfmm_tree_stats_t* out);
  *                  list of node i in L_list[L_off[i] .. L_off[i+1])
  *   v_pairs[v_len][2] (target, source) of every M2L pair
  * Synchronises the stream.  Errors: EINVAL (null io, no adaptive evaluate
- * yet), EUNSUPPORTED (uniform tree), ENOMEM, EDEVICE. */
+ * yet), EUNSUPPORTED (uniform tree), ENOMEM, EDEVICE.  The dual tree has no
+ * U/V/W/X lists (their lengths are 0). */
 typedef struct ctfmm_tree_copy_t {
     int64_t nodes, particles, u_len, v_len, w_len, x_len;
     uint64_t* key;
@@ -310,6 +322,42 @@ ctfmm_status ctfmm_get_m2l_tile(ctfmm_ctx* ctx, int32_t p, int32_t* targets);
  * must lie in 0..p.  NULL restores the fixed order.  Errors: EINVAL,
  * EUNSUPPORTED (uniform tree). */
 ctfmm_status ctfmm_set_order_table(ctfmm_ctx* ctx, const int32_t* order_r2);
+
+/* ---- dual-tree traversal (tree CTFMM_TREE_DUAL, Appendix C) ---- */
+
+typedef enum ctfmm_centre {
+    CTFMM_CENTRE_GEOMETRIC = 0,  /* expansions about each cube's centre */
+    CTFMM_CENTRE_MASS = 1,       /* about the charge-weighted mean of the node's
+                                    particles (the cube's centre where the node's
+                                    total charge is not positive) */
+    CTFMM_CENTRE_AP = 2          /* the AP variant (Sec. 4): about the centre of
+                                    mass, the dipole (which vanishes there) left
+                                    out of every M2L, the gradient only; every
+                                    charge must be positive (else ctfmm_evaluate
+                                    returns EINVAL) and phi must be NULL */
+} ctfmm_centre;
+
+/* The acceptance parameter theta (0 <= theta <= 1; 0 accepts no pair, which
+ * is the direct sum) and the expansion centres (ctfmm_centre) of the
+ * dual-tree traversal.  The enclosing radius of a node is the largest
+ * distance from its centre to one of its particles.  Errors: EINVAL (theta
+ * outside [0, 1], unknown centre), EUNSUPPORTED (other trees). */
+ctfmm_status ctfmm_set_mac(ctfmm_ctx* ctx, double theta, int32_t centre);
+
+/* The traversal's result of the last evaluation (host buffers, each may be
+ * NULL; sizes are always written): zr [nodes][4] = centre and enclosing
+ * radius per node (node numbers as ctfmm_copy_tree), m2l [m2l][2] the
+ * directed M2L entries (target, source) in ascending order, p2p [p2p][2] the
+ * ordered direct leaf pairs (leaf, partner; a leaf with itself once) in
+ * ascending order.  Synchronises the stream.  Errors: EINVAL (null io, no
+ * evaluation yet), EUNSUPPORTED (other trees), EDEVICE. */
+typedef struct ctfmm_dual_copy_t {
+    int64_t nodes, m2l, p2p;
+    double* zr;
+    int32_t* m2l_pairs;
+    int32_t* p2p_pairs;
+} ctfmm_dual_copy_t;
+ctfmm_status ctfmm_copy_dual(ctfmm_ctx* ctx, ctfmm_dual_copy_t* io);
 
 /* Orders from a reproducible map of (source cell, distance class), to check
  * the per-pair-order machinery (the per-tile maximum, the operators of

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 GEN_DIR = os.path.join(CSRC, "generated")
 LIB = os.path.join(PKG, "libctfmm.so")
 
-SOURCES = ["ctfmm_api.hip", "ctfmm_kernels.hip", "ctfmm_adaptive.hip", "ctfmm_mlp.hip"]
+SOURCES = ["ctfmm_api.hip", "ctfmm_kernels.hip", "ctfmm_adaptive.hip", "ctfmm_mlp.hip", "ctfmm_dual.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -128,6 +128,17 @@ struct Forest {
     bool up_early = false;       // P2M and M2M already launched by the tree build
     double* part = nullptr;      // [nchunk][nn][ldm] partial local expansions
     size_t part_cap = 0;
+    // dual-tree traversal: centres and radii, round counters, frontiers, the
+    // M2L and direct-pair keys (unsorted, sorted), their CSR forms
+    double4* zr = nullptr;
+    int* dcnt = nullptr;
+    int2* front[2] = {};
+    uint64_t *mk = nullptr, *mks = nullptr, *pk = nullptr, *pks = nullptr;
+    int32_t *moff = nullptr, *msrc = nullptr, *poff = nullptr, *psrc = nullptr;
+    size_t zr_cap = 0, dcnt_cap = 0, front_cap[2] = {}, mk_cap = 0, mks_cap = 0, pk_cap = 0, pks_cap = 0;
+    size_t moff_cap = 0, msrc_cap = 0, poff_cap = 0, psrc_cap = 0;
+    size_t cap_f = 0, cap_m = 0, cap_p = 0;  // entries the traversal may write
+    int n_m2l = 0, n_p2p = 0, dual_sh = 0;
 };
 
 struct ctfmm_ctx {
@@ -190,6 +201,9 @@ struct ctfmm_ctx {
     int order_mode = 0;
     unsigned long long order_seed = 0;
     int order_pmin = 0;
+    // dual-tree traversal: acceptance parameter and expansion centres
+    double theta = 0.5;
+    int centre = CTFMM_CENTRE_GEOMETRIC;
     int32_t* order_tab = nullptr;  // device [28]
     float* model = nullptr;        // device [MLP_NPARAM + 24]: parameters, input mean, input std
     float order_thr = 0.f;         // log10(target error) - margin
@@ -360,6 +374,16 @@ ctfmm_status upload_tables(ctfmm_ctx* c) {
     const size_t o_ds = put(blob, GEN_DET_START, sizeof(GEN_DET_START) / sizeof(GEN_DET_START[0]));
     const size_t o_df = put(blob, GEN_DET_FULL, sizeof(GEN_DET_FULL) / sizeof(GEN_DET_FULL[0]));
     const size_t o_dc = put(blob, GEN_DET_COEF, sizeof(GEN_DET_COEF) / sizeof(GEN_DET_COEF[0]));
+#define NEL(a) (sizeof(a) / sizeof((a)[0]))
+    const size_t o_mgs = put(blob, GEN_M2MG_START, NEL(GEN_M2MG_START));
+    const size_t o_mgj = put(blob, GEN_M2MG_J, NEL(GEN_M2MG_J));
+    const size_t o_mgm = put(blob, GEN_M2MG_MONO, NEL(GEN_M2MG_MONO));
+    const size_t o_mgc = put(blob, GEN_M2MG_COEF, NEL(GEN_M2MG_COEF));
+    const size_t o_lgs = put(blob, GEN_L2LG_START, NEL(GEN_L2LG_START));
+    const size_t o_lgj = put(blob, GEN_L2LG_J, NEL(GEN_L2LG_J));
+    const size_t o_lgm = put(blob, GEN_L2LG_MONO, NEL(GEN_L2LG_MONO));
+    const size_t o_lgc = put(blob, GEN_L2LG_COEF, NEL(GEN_L2LG_COEF));
+#undef NEL
     void* d = dev_alloc(c, blob.size());
     if (!d) return fail(c, CTFMM_ENOMEM, "table allocation failed");
     HIPCHK(c, hipMemcpyAsync(d, blob.data(), blob.size(), hipMemcpyHostToDevice, c->stream));
@@ -384,6 +408,14 @@ ctfmm_status upload_tables(ctfmm_ctx* c) {
     c->T.det_start = (const int16_t*)(b + o_ds);
     c->T.det_full = (const int16_t*)(b + o_df);
     c->T.det_coef = (const double*)(b + o_dc);
+    c->T.m2mg_start = (const int32_t*)(b + o_mgs);
+    c->T.m2mg_j = (const uint8_t*)(b + o_mgj);
+    c->T.m2mg_mono = (const int16_t*)(b + o_mgm);
+    c->T.m2mg_coef = (const double*)(b + o_mgc);
+    c->T.l2lg_start = (const int32_t*)(b + o_lgs);
+    c->T.l2lg_j = (const uint8_t*)(b + o_lgj);
+    c->T.l2lg_mono = (const int16_t*)(b + o_lgm);
+    c->T.l2lg_coef = (const double*)(b + o_lgc);
     return CTFMM_OK;
 }
 
@@ -848,7 +880,7 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
 // the stream once per tree level and a few times more (sizes decide the next
 // launches).  f.p, f.nsys, f.goff_h and f.gbase_h are set by the caller.
 ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const double* q, bool explicit_box,
-                          bool early_up = false) {
+                          bool early_up = false, bool tree_only = false) {
     hipStream_t st = c->stream;
     const int n = f.n;
     const size_t nn_ = (size_t)std::max(n, 1);
@@ -973,6 +1005,7 @@ tree_again:
         if (!x) HIPCHK(c, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
     for (auto& e : c->side_ev)
         if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (tree_only) return CTFMM_OK;
     // P2M and M2M need only the nodes: with early_up they start here on a side
     // stream, beside the list and M2L-table construction, and the numeric
     // pass joins them
@@ -1331,6 +1364,155 @@ ctfmm_status evaluate_adaptive(ctfmm_ctx* c, int n, const double* xyz, const dou
     return CTFMM_OK;
 }
 
+// ------------------------------------------------------------------ dual-tree evaluation
+
+// The traversal in rounds (ctfmm_dual.hip).  Each round opens one node of a
+// pair (both halves of a self pair), so the level sum of a pair grows by at
+// least one per round and no pair is left after round 2 maxlev + 1.  The
+// host reads the round counts once: entries past a buffer's capacity were
+// counted but not written, and the traversal then runs again with larger
+// buffers (they are kept for the next evaluation).  Then both entry lists
+// are sorted and put in CSR form by target (leaf).
+ctfmm_status dual_traverse(ctfmm_ctx* c, Forest& f, int maxlev) {
+    hipStream_t st = c->stream;
+    const int nn = f.nn;
+    const int nr = 2 * maxlev + 2;
+    int sh = 1;
+    while ((1ll << sh) < (long long)nn) ++sh;
+    f.dual_sh = sh;
+    ACHK(grow(c, f.dcnt, f.dcnt_cap, (size_t)nr + 3, false));
+    if (f.cap_f == 0) {
+        f.cap_f = std::max<size_t>(4096, 16 * (size_t)nn);
+        f.cap_m = std::max<size_t>(4096, 128 * (size_t)nn);
+        f.cap_p = std::max<size_t>(4096, 32 * (size_t)nn);
+    }
+    int* pw = pinned_words(c);
+    if (!pw) return fail(c, CTFMM_ENOMEM, "pinned host allocation failed");
+    const int nw = nr + 4;
+    for (int attempt = 0;; ++attempt) {
+        ACHK(grow(c, f.front[0], f.front_cap[0], f.cap_f, false));
+        ACHK(grow(c, f.front[1], f.front_cap[1], f.cap_f, false));
+        ACHK(grow(c, f.mk, f.mk_cap, f.cap_m, false));
+        ACHK(grow(c, f.pk, f.pk_cap, f.cap_p, false));
+        launch_dual_init(st, nr, f.dcnt, f.front[0]);
+        for (int r = 0; r < nr; ++r)
+            launch_dual_round(st, r, nr, f.front[r & 1], f.front[(r + 1) & 1], (int)f.cap_f, f.mk, (int)f.cap_m, f.pk,
+                              (int)f.cap_p, sh, f.dcnt, f.tr, f.zr, c->theta);
+        HIPCHK(c, hipGetLastError());
+        arm_words(pw, nw);
+        HIPCHK(c, hipMemcpyAsync(pw, f.dcnt, (size_t)(nr + 3) * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(pw + nr + 3, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        SCHK(wait_words(c, pw, nw));
+        const int err = pw[nr + 3];
+        if (err) {
+            HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), st));
+            return fail(c, CTFMM_EINVAL, (err & 1) ? "non-finite particle coordinate"
+                                                   : "the AP variant needs positive charges");
+        }
+        size_t maxf = 0;
+        for (int r = 1; r <= nr; ++r) maxf = std::max<size_t>(maxf, (size_t)pw[r]);
+        const size_t nm = (size_t)pw[nr + 1], np = (size_t)pw[nr + 2];
+        if (maxf <= f.cap_f && nm <= f.cap_m && np <= f.cap_p) {
+            if (pw[nr] != 0) return fail(c, CTFMM_EDEVICE, "dual-tree traversal did not finish");
+            f.n_m2l = (int)nm;
+            f.n_p2p = (int)np;
+            break;
+        }
+        if (attempt >= 16 || nm > (size_t)INT_MAX / 2 || np > (size_t)INT_MAX / 2 || maxf > (size_t)INT_MAX / 2)
+            return fail(c, CTFMM_ENOMEM, "dual-tree traversal lists too long");
+        f.cap_f = std::max(2 * f.cap_f, maxf + maxf / 4);
+        f.cap_m = std::max(f.cap_m, nm + nm / 4 + 64);
+        f.cap_p = std::max(f.cap_p, np + np / 4 + 64);
+    }
+    ACHK(grow(c, f.mks, f.mks_cap, std::max<size_t>(f.n_m2l, 1), false));
+    ACHK(grow(c, f.pks, f.pks_cap, std::max<size_t>(f.n_p2p, 1), false));
+    ACHK(grow(c, f.msrc, f.msrc_cap, std::max<size_t>(f.n_m2l, 1), false));
+    ACHK(grow(c, f.psrc, f.psrc_cap, std::max<size_t>(f.n_p2p, 1), false));
+    const int nm = f.n_m2l, np = f.n_p2p;
+    if (nm > 0)
+        SCHK(cub_run(c, [&](void* t, size_t& b) {
+            return hipcub::DeviceRadixSort::SortKeys(t, b, f.mk, f.mks, nm, 0, 2 * sh, st);
+        }));
+    SCHK(cub_run(c, [&](void* t, size_t& b) {
+        return hipcub::DeviceRadixSort::SortKeys(t, b, f.pk, f.pks, np, 0, 2 * sh, st);
+    }));
+    launch_dual_csr(st, nn, f.mks, f.dcnt + nr + 1, (int)f.cap_m, sh, f.moff, f.msrc);
+    launch_dual_csr(st, nn, f.pks, f.dcnt + nr + 2, (int)f.cap_p, sh, f.poff, f.psrc);
+    HIPCHK(c, hipGetLastError());
+    return CTFMM_OK;
+}
+
+// events: 0 start, 1 tree and centres, 2 traversal and lists, 3 upward pass
+// joined, 4 M2L, 5 L2L, last: L2P and the near field joined
+void add_dual_times(ctfmm_ctx* c) {
+    const int e = NPHASE_EV - 1;
+    c->st.ms_total += elapsed(c, 0, e);
+    c->st.ms_tree += elapsed(c, 0, 2);
+    c->st.ms_m2l += elapsed(c, 3, 4);
+    c->st.ms_l2l += elapsed(c, 4, 5);
+    c->st.ms_near += elapsed(c, 5, e);
+}
+
+ctfmm_status evaluate_dual(ctfmm_ctx* c, int n, const double* xyz, const double* q, double* phi, double* grad) {
+    if (c->forests.empty()) c->forests.resize(1);
+    Forest& f = c->forests[0];
+    c->nforests = 1;
+    f.p = c->prm.order_p;
+    f.nsys = 1;
+    f.n = n;
+    f.goff_h = {0, n};
+    f.gbase_h = {0};
+    const bool ap = c->centre == CTFMM_CENTRE_AP;
+    hipStream_t st = c->stream;
+    rec(c, 0);
+    HIPCHK(c, hipMemsetAsync(c->err_flag, 0, sizeof(int), st));
+    SCHK(build_forest(c, f, xyz, q, c->prm.root_side > 0.0, false, true));
+    const int nn = f.nn, p = f.p, maxlev = (int)f.lev_first.size() - 1;
+    const size_t ldm = (size_t)ldm_of(p);
+    ACHK(grow(c, f.zr, f.zr_cap, (size_t)nn, false));
+    ACHK(grow(c, f.aM, f.aM_cap, (size_t)nn * ldm, false));
+    ACHK(grow(c, f.aL, f.aL_cap, (size_t)nn * ldm, false));
+    ACHK(grow(c, f.moff, f.moff_cap, (size_t)nn + 1, false));
+    ACHK(grow(c, f.poff, f.poff_cap, (size_t)nn + 1, false));
+    launch_dual_centres(st, nn, f.tr, f.boxes, f.a_P, c->centre, f.zr, c->err_flag);
+    rec(c, 1);
+    // the upward pass needs the centres only: it runs on a side stream beside
+    // the traversal
+    HIPCHK(c, hipEventRecord(c->side_ev[0], st));
+    HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[0], 0));
+    launch_dual_p2m(c->side[1], p, nn, f.tr, f.zr, f.a_P, c->T, f.aM);
+    for (int l = maxlev - 1; l >= 0; --l)
+        launch_dual_m2m(c->side[1], p, f.lev_first[l], f.lev_count[l], f.tr, f.zr, c->T, f.aM);
+    HIPCHK(c, hipEventRecord(c->side_ev[1], c->side[1]));
+    SCHK(dual_traverse(c, f, maxlev));
+    rec(c, 2);
+    // the near field beside the expansions
+    HIPCHK(c, hipEventRecord(c->side_ev[2], st));
+    HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[2], 0));
+    launch_p2p_near(c->side[0], n, nn, f.tr, f.a_P, f.poff, f.psrc, f.a_Fn);
+    HIPCHK(c, hipEventRecord(c->side_ev[3], c->side[0]));
+    HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[1], 0));
+    rec(c, 3);
+    launch_dual_m2l(st, p, ap, nn, f.tr, f.zr, f.moff, f.msrc, f.aM, f.aL);
+    rec(c, 4);
+    for (int l = 1; l <= maxlev; ++l) launch_dual_l2l(st, p, f.lev_first[l], f.lev_count[l], f.tr, f.zr, c->T, f.aL);
+    rec(c, 5);
+    HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[3], 0));
+    launch_dual_l2p(st, p, ap, n, f.tr, f.leaf_of, f.zr, f.a_P, f.aL, f.a_Fn, f.a_idxs, phi, grad);
+    HIPCHK(c, hipGetLastError());
+    rec(c, NPHASE_EV - 1);
+    c->have_result = true;
+    c->st.evaluations += 1;
+    c->st.m2l_launches += 1;
+    c->st.m2l_pairs += f.n_m2l;
+    c->st.p2p_leaf_pairs += f.n_p2p;
+    if (c->timing) {
+        HIPCHK(c, hipEventSynchronize(c->ev[NPHASE_EV - 1]));
+        add_dual_times(c);
+    }
+    return CTFMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1357,7 +1539,7 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
         return CTFMM_EINVAL;
     }
     *out = nullptr;
-    if (prm->tree != CTFMM_TREE_UNIFORM && prm->tree != CTFMM_TREE_ADAPTIVE) {
+    if (prm->tree != CTFMM_TREE_UNIFORM && prm->tree != CTFMM_TREE_ADAPTIVE && prm->tree != CTFMM_TREE_DUAL) {
         g_create_err = "unknown tree type";
         return CTFMM_EUNSUPPORTED;
     }
@@ -1365,7 +1547,7 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
         g_create_err = "expansion order above the compiled maximum (10)";
         return CTFMM_EUNSUPPORTED;
     }
-    const bool adaptive = prm->tree == CTFMM_TREE_ADAPTIVE;
+    const bool adaptive = prm->tree != CTFMM_TREE_UNIFORM;  // the adaptive octree (lists or dual traversal)
     const bool box_ok = std::isfinite(prm->root_side) && std::isfinite(prm->root_lo[0]) &&
                         std::isfinite(prm->root_lo[1]) && std::isfinite(prm->root_lo[2]) &&
                         (adaptive || prm->root_side > 0.0);
@@ -1378,6 +1560,10 @@ ctfmm_status ctfmm_create(const ctfmm_params* prm, void* hip_stream, ctfmm_ctx**
     if (prm->precision != CTFMM_PREC_FP64 && prm->precision != CTFMM_PREC_FP32 &&
         prm->precision != CTFMM_PREC_BF16X3) {
         g_create_err = "unknown precision mode";
+        return CTFMM_EUNSUPPORTED;
+    }
+    if (prm->tree == CTFMM_TREE_DUAL && prm->precision != CTFMM_PREC_FP64) {
+        g_create_err = "the dual-tree traversal is FP64 only";
         return CTFMM_EUNSUPPORTED;
     }
     ctfmm_ctx* c = new (std::nothrow) ctfmm_ctx();
@@ -1526,6 +1712,11 @@ ctfmm_status ctfmm_evaluate(ctfmm_ctx* c, int64_t n, const double* xyz, const do
     if (n == 0) return CTFMM_OK;
     if (!xyz || !q) return fail(c, CTFMM_EINVAL, "null xyz or q");
     if (c->prm.tree == CTFMM_TREE_ADAPTIVE) return evaluate_adaptive(c, (int)n, xyz, q, phi, grad);
+    if (c->prm.tree == CTFMM_TREE_DUAL) {
+        if (c->centre == CTFMM_CENTRE_AP && phi)
+            return fail(c, CTFMM_EINVAL, "the AP variant gives the gradient only (phi must be NULL)");
+        return evaluate_dual(c, (int)n, xyz, q, phi, grad);
+    }
     return evaluate_uniform(c, n, xyz, q, nullptr, phi, grad);
 }
 
@@ -1747,8 +1938,9 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
         for (int32_t v : info) out->leaves += (v >> 8) & 1;
         out->nodes += f.nn;
         out->max_level = std::max<int64_t>(out->max_level, (int64_t)f.lev_first.size() - 1);
-        out->v_pairs += f.v_pairs;
-        out->u_pairs += f.tot_u;
+        const bool dual = c->prm.tree == CTFMM_TREE_DUAL;
+        out->v_pairs += dual ? f.n_m2l : f.v_pairs;
+        out->u_pairs += dual ? f.n_p2p : f.tot_u;
         out->w_pairs += f.tot_w;
         out->x_pairs += f.tot_x;
     }
@@ -1763,10 +1955,11 @@ ctfmm_status ctfmm_tree_stats(ctfmm_ctx* c, ctfmm_tree_stats_t* out) {
 
 ctfmm_status ctfmm_copy_tree(ctfmm_ctx* c, ctfmm_tree_copy_t* io) {
     if (!c || !io) return CTFMM_EINVAL;
-    if (c->prm.tree != CTFMM_TREE_ADAPTIVE) return fail(c, CTFMM_EUNSUPPORTED, "tree copies need the adaptive tree");
+    if (c->prm.tree == CTFMM_TREE_UNIFORM) return fail(c, CTFMM_EUNSUPPORTED, "tree copies need the adaptive tree");
     if (!c->have_result || c->nforests < 1) return fail(c, CTFMM_EINVAL, "no evaluate yet");
     Forest& f = c->forests[0];
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    const bool lists = c->prm.tree == CTFMM_TREE_ADAPTIVE;
     const size_t nn = (size_t)f.nn, n1 = nn + 1, nt = f.tiles_host.size(), tt = (size_t)f.tt;
     std::vector<int32_t> tgt, src;
     if (nt > 0 && io->v_pairs) {
@@ -1791,12 +1984,17 @@ ctfmm_status ctfmm_copy_tree(ctfmm_ctx* c, ctfmm_tree_copy_t* io) {
     SCHK(get(io->pb, f.tr.pb, nn * 4));
     SCHK(get(io->pe, f.tr.pe, nn * 4));
     SCHK(get(io->perm, f.a_idxs, (size_t)f.n * 4));
-    SCHK(get(io->u_off, f.loff, n1 * 4));
-    SCHK(get(io->w_off, f.loff + n1, n1 * 4));
-    SCHK(get(io->x_off, f.loff + 2 * n1, n1 * 4));
-    SCHK(get(io->u_list, f.ulist, (size_t)f.tot_u * 4));
-    SCHK(get(io->w_list, f.wlist, (size_t)f.tot_w * 4));
-    SCHK(get(io->x_list, f.xlist, (size_t)f.tot_x * 4));
+    if (lists) {
+        SCHK(get(io->u_off, f.loff, n1 * 4));
+        SCHK(get(io->w_off, f.loff + n1, n1 * 4));
+        SCHK(get(io->x_off, f.loff + 2 * n1, n1 * 4));
+        SCHK(get(io->u_list, f.ulist, (size_t)f.tot_u * 4));
+        SCHK(get(io->w_list, f.wlist, (size_t)f.tot_w * 4));
+        SCHK(get(io->x_list, f.xlist, (size_t)f.tot_x * 4));
+    } else {
+        for (int32_t* o : {io->u_off, io->w_off, io->x_off})
+            if (o) std::memset(o, 0, n1 * 4);
+    }
     if (io->level || io->leaf) {
         std::vector<int32_t> info(nn);
         SCHK(get(info.data(), f.tr.info, nn * 4));
@@ -1851,6 +2049,43 @@ ctfmm_status ctfmm_set_order_hash(ctfmm_ctx* c, uint64_t seed, int32_t pmin) {
     c->order_seed = seed;
     c->order_pmin = pmin;
     c->order_mode = 3;
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_set_mac(ctfmm_ctx* c, double theta, int32_t centre) {
+    if (!c) return CTFMM_EINVAL;
+    c->err.clear();
+    if (c->prm.tree != CTFMM_TREE_DUAL) return fail(c, CTFMM_EUNSUPPORTED, "the MAC belongs to the dual tree");
+    if (!(theta >= 0.0 && theta <= 1.0)) return fail(c, CTFMM_EINVAL, "theta outside [0, 1]");
+    if (centre < CTFMM_CENTRE_GEOMETRIC || centre > CTFMM_CENTRE_AP) return fail(c, CTFMM_EINVAL, "unknown centre");
+    c->theta = theta;
+    c->centre = centre;
+    return CTFMM_OK;
+}
+
+ctfmm_status ctfmm_copy_dual(ctfmm_ctx* c, ctfmm_dual_copy_t* io) {
+    if (!c || !io) return CTFMM_EINVAL;
+    c->err.clear();
+    if (c->prm.tree != CTFMM_TREE_DUAL) return fail(c, CTFMM_EUNSUPPORTED, "traversal copies need the dual tree");
+    if (!c->have_result || c->nforests < 1) return fail(c, CTFMM_EINVAL, "no evaluate yet");
+    Forest& f = c->forests[0];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    io->nodes = f.nn;
+    io->m2l = f.n_m2l;
+    io->p2p = f.n_p2p;
+    if (io->zr) HIPCHK(c, hipMemcpy(io->zr, f.zr, (size_t)f.nn * sizeof(double4), hipMemcpyDeviceToHost));
+    const uint64_t mask = (1ull << f.dual_sh) - 1;
+    for (int w = 0; w < 2; ++w) {
+        int32_t* out = w == 0 ? io->m2l_pairs : io->p2p_pairs;
+        const size_t cnt = w == 0 ? (size_t)f.n_m2l : (size_t)f.n_p2p;
+        if (!out || cnt == 0) continue;
+        std::vector<uint64_t> k(cnt);
+        HIPCHK(c, hipMemcpy(k.data(), w == 0 ? f.mks : f.pks, cnt * 8, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < cnt; ++i) {
+            out[2 * i] = (int32_t)(k[i] >> f.dual_sh);
+            out[2 * i + 1] = (int32_t)(k[i] & mask);
+        }
+    }
     return CTFMM_OK;
 }
 
@@ -2060,7 +2295,8 @@ ctfmm_status ctfmm_sync(ctfmm_ctx* c) {
         HIPCHK(c, hipMemcpy(&h, c->err_flag, sizeof(int), hipMemcpyDeviceToHost));
         if (h) {
             HIPCHK(c, hipMemset(c->err_flag, 0, sizeof(int)));
-            return fail(c, CTFMM_EINVAL, "non-finite particle coordinate");
+            return fail(c, CTFMM_EINVAL, (h & 1) ? "non-finite particle coordinate"
+                                                 : "the AP variant needs positive charges");
         }
     }
     return CTFMM_OK;

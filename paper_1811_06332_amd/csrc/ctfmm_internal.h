@@ -32,6 +32,15 @@ struct DevTables {
     const int16_t* det_start;  // [NIND+1] detracer rows: independent n <- full f
     const int16_t* det_full;
     const double* det_coef;
+    // M2M and L2L for any shift: terms (j, monomial slot, coefficient) per output n
+    const int32_t* m2mg_start;  // [NIND+1]
+    const uint8_t* m2mg_j;
+    const int16_t* m2mg_mono;
+    const double* m2mg_coef;
+    const int32_t* l2lg_start;  // [NIND+1]
+    const uint8_t* l2lg_j;
+    const int16_t* l2lg_mono;
+    const double* l2lg_coef;
 };
 
 // row stride of the expansion buffers: (p+1)^2 rounded up to a multiple of 4
@@ -328,6 +337,29 @@ void launch_p2p_near(hipStream_t s, int n, int nn, const ATree& t, const double4
 void launch_wlist_adaptive(hipStream_t s, int p, int nn, const ABox* boxes, const ATree& t, const double4* P,
                            const double* Cm, const int32_t* woff, const int32_t* wlist, double4* F);
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
+
+// ---- dual-tree traversal (ctfmm_dual.hip) ----
+// centres and enclosing radii per node (mode: ctfmm_centre); err bit 2 = a
+// non-positive charge in the AP variant
+void launch_dual_centres(hipStream_t s, int nn, const ATree& t, const ABox* boxes, const double4* P, int mode,
+                         double4* zr, int* err);
+void launch_dual_p2m(hipStream_t s, int p, int nn, const ATree& t, const double4* zr, const double4* P,
+                     const DevTables& T, double* M);
+void launch_dual_m2m(hipStream_t s, int p, int first, int count, const ATree& t, const double4* zr,
+                     const DevTables& T, double* M);
+void launch_dual_l2l(hipStream_t s, int p, int first, int count, const ATree& t, const double4* zr,
+                     const DevTables& T, double* L);
+// cnt: [nr + 1] frontier sizes, then the M2L and direct-pair entry counts
+void launch_dual_init(hipStream_t s, int nr, int* cnt, int2* front);
+void launch_dual_round(hipStream_t s, int r, int nr, const int2* fin, int2* fout, int cap_f, uint64_t* mk, int cap_m,
+                       uint64_t* pk, int cap_p, int sh, int* cnt, const ATree& t, const double4* zr, double theta);
+void launch_dual_csr(hipStream_t s, int nn, const uint64_t* keys, const int* nkeys, int cap, int sh, int32_t* off,
+                     int32_t* src);
+void launch_dual_m2l(hipStream_t s, int p, bool ap, int nn, const ATree& t, const double4* zr, const int32_t* off,
+                     const int32_t* src, const double* M, double* L);
+void launch_dual_l2p(hipStream_t s, int p, bool ap, int n, const ATree& t, const int32_t* leaf_of, const double4* zr,
+                     const double4* P, const double* L, const double4* Fn, const int32_t* idx, double* phi,
+                     double* grad);
 
 // ---- expansion orders per pair (ctfmm_adaptive.hip, ctfmm_mlp.hip) ----
 // order of every (tile, offset): the largest its pairs ask for (-1 = no pair),

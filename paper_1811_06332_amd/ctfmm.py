@@ -14,8 +14,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libctfmm.so")
 
 CTFMM_OK, CTFMM_EINVAL, CTFMM_ENOMEM, CTFMM_EDEVICE, CTFMM_EUNSUPPORTED = 0, 1, 2, 3, 4
-CTFMM_TREE_UNIFORM, CTFMM_TREE_ADAPTIVE = 0, 1
-TREES = {"uniform": CTFMM_TREE_UNIFORM, "adaptive": CTFMM_TREE_ADAPTIVE}
+CTFMM_TREE_UNIFORM, CTFMM_TREE_ADAPTIVE, CTFMM_TREE_DUAL = 0, 1, 2
+TREES = {"uniform": CTFMM_TREE_UNIFORM, "adaptive": CTFMM_TREE_ADAPTIVE, "dual": CTFMM_TREE_DUAL}
+CENTRES = {"geometric": 0, "mass": 1, "ap": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 CTFMM_P_MAX = 10
 CTFMM_DEPTH_MAX = 9
@@ -26,6 +27,7 @@ EXPORTED = ["ctfmm_version", "ctfmm_default_params", "ctfmm_create", "ctfmm_set_
             "ctfmm_evaluate_batched_f32",
             "ctfmm_copy_expansions", "ctfmm_copy_tree", "ctfmm_tree_stats", "ctfmm_set_m2l_tile",
             "ctfmm_get_m2l_tile", "ctfmm_set_order_table", "ctfmm_set_order_hash", "ctfmm_set_order_model",
+            "ctfmm_set_mac", "ctfmm_copy_dual",
             "ctfmm_mlp_forward", "ctfmm_mlp_backward", "ctfmm_mlp_backward_noalloc", "ctfmm_mlp_train",
             "ctfmm_mlp_labels", "ctfmm_mlp_samples", "ctfmm_set_timing", "ctfmm_stats", "ctfmm_reset_stats",
             "ctfmm_sync", "ctfmm_last_error", "ctfmm_destroy"]
@@ -58,6 +60,11 @@ class ctfmm_tree_copy_t(C.Structure):
                 ("leaf", C.c_void_p), ("parent", C.c_void_p), ("pb", C.c_void_p), ("pe", C.c_void_p),
                 ("perm", C.c_void_p), ("u_off", C.c_void_p), ("u_list", C.c_void_p), ("w_off", C.c_void_p),
                 ("w_list", C.c_void_p), ("x_off", C.c_void_p), ("x_list", C.c_void_p), ("v_pairs", C.c_void_p)]
+
+
+class ctfmm_dual_copy_t(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("m2l", C.c_int64), ("p2p", C.c_int64), ("zr", C.c_void_p),
+                ("m2l_pairs", C.c_void_p), ("p2p_pairs", C.c_void_p)]
 
 
 class ctfmm_tree_stats_t(C.Structure):
@@ -93,6 +100,8 @@ def load():
         L.ctfmm_set_order_table.argtypes = [vp, vp]
         L.ctfmm_set_order_hash.argtypes = [vp, C.c_uint64, i32]
         L.ctfmm_set_order_model.argtypes = [vp, vp, vp, C.c_double, C.c_double]
+        L.ctfmm_set_mac.argtypes = [vp, C.c_double, i32]
+        L.ctfmm_copy_dual.argtypes = [vp, C.POINTER(ctfmm_dual_copy_t)]
         L.ctfmm_mlp_forward.argtypes = [vp, i64, vp, vp, i32, vp]
         L.ctfmm_mlp_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.ctfmm_mlp_backward_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp]
@@ -330,6 +339,26 @@ def ctfmm_set_order_hash(ctx, seed: int, pmin: int) -> None:
     _check(load().ctfmm_set_order_hash(C.c_void_p(ctx), int(seed), int(pmin)), C.c_void_p(ctx))
 
 
+def ctfmm_set_mac(ctx, theta: float, centre: int) -> None:
+    _check(load().ctfmm_set_mac(C.c_void_p(ctx), float(theta), int(centre)), C.c_void_p(ctx))
+
+
+def ctfmm_copy_dual(ctx) -> dict:
+    """The dual-tree traversal of the last evaluate as numpy arrays: zr
+    (nodes, 4), m2l (entries, 2) = (target, source), p2p (entries, 2) =
+    (leaf, partner), both sorted."""
+    import numpy as np
+    io = ctfmm_dual_copy_t()
+    _check(load().ctfmm_copy_dual(C.c_void_p(ctx), C.byref(io)), C.c_void_p(ctx))
+    out = {"zr": np.zeros((int(io.nodes), 4)), "m2l": np.zeros((max(int(io.m2l), 1), 2), np.int32),
+           "p2p": np.zeros((max(int(io.p2p), 1), 2), np.int32)}
+    io.zr, io.m2l_pairs, io.p2p_pairs = out["zr"].ctypes.data, out["m2l"].ctypes.data, out["p2p"].ctypes.data
+    _check(load().ctfmm_copy_dual(C.c_void_p(ctx), C.byref(io)), C.c_void_p(ctx))
+    out["m2l"] = out["m2l"][: int(io.m2l)]
+    out["p2p"] = out["p2p"][: int(io.p2p)]
+    return out
+
+
 def ctfmm_set_order_model(ctx, params, norm, target_rel_err: float, margin: float) -> None:
     import numpy as np
     if params is None:
@@ -429,11 +458,14 @@ class FMM:
 
     tree="uniform": octree of the given depth over the cube (root_lo, root_side).
     tree="adaptive": leaves of at most leaf_max particles; depth is ignored and
-    root_side=None (or <= 0) selects the automatic root cube."""
+    root_side=None (or <= 0) selects the automatic root cube.
+    tree="dual": the same octree driven by the dual-tree traversal with the
+    acceptance parameter theta and the expansion centres ("geometric",
+    "mass" or "ap"; the AP variant gives the gradient only)."""
 
     def __init__(self, p: int, depth: int = 0, precision: str = "fp64", root_lo=(0.0, 0.0, 0.0),
                  root_side: float | None = 1.0, stream: int | None = None, tree: str = "uniform",
-                 leaf_max: int = 64, torch_alloc: bool = True):
+                 leaf_max: int = 64, torch_alloc: bool = True, theta: float = 0.5, centre: str = "geometric"):
         prm = ctfmm_default_params()
         prm.order_p, prm.depth, prm.precision = p, depth, PRECISIONS[precision]
         prm.tree, prm.leaf_max = TREES[tree], leaf_max
@@ -446,6 +478,16 @@ class FMM:
         if torch_alloc:
             self._alloc = torch_allocator()
             ctfmm_set_allocator(self.ctx, *self._alloc)
+        self.centre = centre
+        if tree == "dual":
+            ctfmm_set_mac(self.ctx, theta, CENTRES[centre])
+
+    def set_mac(self, theta: float, centre: str = "geometric") -> None:
+        ctfmm_set_mac(self.ctx, theta, CENTRES[centre])
+        self.centre = centre
+
+    def dual_copy(self) -> dict:
+        return ctfmm_copy_dual(self.ctx)
 
     def tree_stats(self) -> dict:
         return ctfmm_tree_stats(self.ctx)
@@ -454,9 +496,10 @@ class FMM:
         return ctfmm_copy_tree(self.ctx)
 
     def evaluate(self, xyz, q, phi=None, grad=None, sync=False):
+        """phi and grad (allocated if None); the AP variant returns phi None"""
         import torch
         n = int(q.shape[0])
-        if phi is None:
+        if phi is None and not (self.tree == "dual" and self.centre == "ap"):
             phi = torch.empty(n, dtype=torch.float64, device=q.device)
         if grad is None:
             grad = torch.empty((n, 3), dtype=torch.float64, device=q.device)

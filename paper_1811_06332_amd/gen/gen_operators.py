@@ -207,6 +207,82 @@ def m2l_contraction():
     return out
 
 
+def m2m_generic():
+    """Per independent n: [(j, e, coef)] with, for any shift,
+        parent M~_n += sum coef * (d/h_P)^e * rho^|j| * child M~_j,
+    d = z_child - z_parent, rho = h_child / h_parent, e a full multi-index
+    of rank |n| - |j|.  Same derivation as m2m_matrix with the octant shift
+    sigma/4 and the scale 1/2 left symbolic (Eq. M2M, M2M part 2)."""
+    out = []
+    for ni, n in enumerate(IND):
+        acc = {}
+        for f, w in DET[ni].items():
+            nn = FULL[f]
+            for k1 in range(nn[0] + 1):
+                for k2 in range(nn[1] + 1):
+                    for k3 in range(nn[2] + 1):
+                        k = (k1, k2, k3)
+                        e = (nn[0] - k1, nn[1] - k2, nn[2] - k3)
+                        coef = Fraction(comb(nn[0], k1) * comb(nn[1], k2) * comb(nn[2], k3) * (-1) ** rank(e))
+                        for j, ej in expand(k).items():
+                            key = (j, FULL_POS[e])
+                            acc[key] = acc.get(key, 0) + w * coef * ej
+        out.append(sorted((j, e, v) for (j, e), v in acc.items() if v != 0))
+    return out
+
+
+def l2l_generic():
+    """Per independent n: [(j, k, coef)] with, for any shift,
+        child L~_n += rho^(|n|+1) sum coef * (d/h_P)^k * parent L~_j,
+    d = z_child - z_parent, rho = h_child / h_parent, k a full multi-index
+    of rank |j| - |n|: coef = expand(n + k)[j] / k!  (Eq. L2L)."""
+    out = []
+    for n in IND:
+        N = rank(n)
+        acc = {}
+        for K in range(PMAX - N + 1):
+            for k1 in range(K + 1):
+                for k2 in range(K - k1 + 1):
+                    k = (k1, k2, K - k1 - k2)
+                    for j, e in expand((n[0] + k[0], n[1] + k[1], n[2] + k[2])).items():
+                        key = (j, FULL_POS[k])
+                        acc[key] = acc.get(key, 0) + Fraction(e, mfact(k))
+        out.append(sorted((j, k, v) for (j, k), v in acc.items() if v != 0))
+    return out
+
+
+def m2l_pair_code(p, c):
+    """Straight-line M2L for one pair at order p (Eq. M2L with the contraction
+    c of m2l_contraction), for the outputs of ranks R0..R1 (template
+    parameters): L[n - R0^2] += sum_j (sum_i c[n,j,i] D[i]) * Ms[j] * rp[|j|].
+    Sources are taken rank by rank (j outer), so each multipole component is
+    read once; with AP the rank-1 sources (the dipole) are left out."""
+    out = []
+    nterms = 0
+    for ji, jm in enumerate(IND):
+        J = rank(jm)
+        if J > p:
+            break
+        body = []
+        for ni, n in enumerate(IND):
+            R = rank(n)
+            if R + J > p:
+                break
+            terms = c.get((ni, ji), {})
+            if not terms:
+                continue
+            expr = " + ".join(f"({float(v)!r}) * D[{i}]" for i, v in sorted(terms.items()))
+            body.append(f"  if constexpr (R0 <= {R} && {R} <= R1) L[{ni} - R0 * R0] += ({expr}) * m;")
+            nterms += len(terms)
+        if not body:
+            continue
+        guard = f"R0 <= {p - J}" + (" && !AP" if J == 1 else "")
+        out.append(f"if constexpr ({guard}) {{ const double m = Ms[{ji}] * rp[{J}];")
+        out.extend(body)
+        out.append("}")
+    return out, nterms
+
+
 DET = None
 
 
@@ -451,6 +527,20 @@ def emit(outdir):
     w(f"static const short GEN_DET_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
     w(f"static const short GEN_DET_FULL[{len(fs)}] = {{" + ",".join(map(str, fs)) + "};")
     w(f"static const double GEN_DET_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
+    # generic M2M / L2L: per output n, terms (j, monomial slot, coefficient)
+    for name, fn, doc in (("M2MG", m2m_generic, "parent M~_n += sum_t COEF[t] * (d/h_P)^FULL[MONO[t]] * rho^|J[t]| * child M~_J[t]"),
+                          ("L2LG", l2l_generic, "child L~_n += rho^(|n|+1) * sum_t COEF[t] * (d/h_P)^FULL[MONO[t]] * parent L~_J[t]")):
+        rows = fn()
+        starts, js, ms, cs = [0], [], [], []
+        for r in rows:
+            for (j, e, v) in r:
+                js.append(j); ms.append(e); cs.append(_hexf(v))
+            starts.append(len(js))
+        w(f"// {doc}; terms of output n in [START[n], START[n+1]), d = z_child - z_parent, rho = h_child / h_parent")
+        w(f"static const int GEN_{name}_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
+        w(f"static const unsigned char GEN_{name}_J[{len(js)}] = {{" + ",".join(map(str, js)) + "};")
+        w(f"static const short GEN_{name}_MONO[{len(ms)}] = {{" + ",".join(map(str, ms)) + "};")
+        w(f"static const double GEN_{name}_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
     # inverse factorials of full components (L2P)
     w("// 1/n! for full slots (L2P weights)")
     w("static const double GEN_INV_MFACT[GEN_NFULL] = {" + ",".join(_hexf(Fraction(1, mfact(m))) for m in FULL) + "};")
@@ -489,6 +579,20 @@ def emit(outdir):
     for p in range(PMAX + 1):
         w(f"template <> __device__ inline void gen_l2p<{p}>(double x, double y, double z, const double* L, double& f, "
           f"double& gx, double& gy, double& gz) {{ gen_l2p_p{p}(x, y, z, L, f, gx, gy, gz); }}")
+    for p in range(PMAX + 1):
+        lines, nt = m2l_pair_code(p, c)
+        w(f"// M2L of one pair at order {p} for the outputs of ranks R0..R1: {nt} contraction terms in all")
+        w(f"template <int R0, int R1, bool AP> __device__ __forceinline__ void gen_m2l_pair_p{p}(")
+        w("    const double* __restrict__ D, const double* __restrict__ Ms, const double* rp, double* L) {")
+        for ln in lines:
+            w("  " + ln)
+        w("}")
+    w("template <int P, int R0, int R1, bool AP> __device__ __forceinline__ void gen_m2l_pair(const double* D, const double* Ms,")
+    w("                                                                                   const double* rp, double* L) {")
+    for p in range(PMAX + 1):
+        kw = "if" if p == 0 else "else if"
+        w(f"  {kw} constexpr (P == {p}) gen_m2l_pair_p{p}<R0, R1, AP>(D, Ms, rp, L);")
+    w("}")
     w("template <int P> __host__ __device__ inline void gen_dtensor(double x, double y, double z, double* D);")
     for p in range(PMAX + 1):
         w(f"template <> __host__ __device__ inline void gen_dtensor<{p}>(double x, double y, double z, double* D) {{ gen_dtensor_p{p}(x, y, z, D); }}")

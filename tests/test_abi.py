@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert F.ctfmm_version() == 3
+    assert F.ctfmm_version() == 4
     prm = F.ctfmm_default_params()
     assert (prm.order_p, prm.depth, prm.ws, prm.precision, prm.root_side) == (4, 3, 1, 0, 1.0)
     assert (prm.tree, prm.leaf_max) == (F.CTFMM_TREE_UNIFORM, 64)
@@ -40,12 +40,15 @@ def test_version_and_defaults():
     # adaptive tree: leaf_max >= 1; root_side <= 0 is the automatic cube but must be finite
     ("adaptive:leaf_max", 0, F.CTFMM_EINVAL), ("adaptive:root_side", float("inf"), F.CTFMM_EINVAL),
     ("adaptive:order_p", 11, F.CTFMM_EUNSUPPORTED),
+    # dual tree: FP64 only, adaptive-tree parameter rules
+    ("dual:precision", 1, F.CTFMM_EUNSUPPORTED), ("dual:precision", 2, F.CTFMM_EUNSUPPORTED),
+    ("dual:leaf_max", 0, F.CTFMM_EINVAL), ("dual:order_p", 11, F.CTFMM_EUNSUPPORTED),
 ])
 def test_create_rejects_bad_params(field, value, status):
     lib = F.load()
     prm = F.ctfmm_default_params()
-    if field.startswith("adaptive:"):
-        prm.tree = F.CTFMM_TREE_ADAPTIVE
+    if field.startswith("adaptive:") or field.startswith("dual:"):
+        prm.tree = F.CTFMM_TREE_ADAPTIVE if field.startswith("adaptive:") else F.CTFMM_TREE_DUAL
         field = field.split(":", 1)[1]
     setattr(prm, field, value)
     h = C.c_void_p()
@@ -64,6 +67,8 @@ def test_null_arguments():
     assert lib.ctfmm_set_allocator(None, None, None, None) == F.CTFMM_EINVAL
     assert lib.ctfmm_sync(None) == F.CTFMM_EINVAL
     assert lib.ctfmm_default_params(None) == F.CTFMM_EINVAL
+    assert lib.ctfmm_set_mac(None, 0.5, 0) == F.CTFMM_EINVAL
+    assert lib.ctfmm_copy_dual(None, None) == F.CTFMM_EINVAL
     lib.ctfmm_destroy(None)
 
 
