@@ -20,6 +20,9 @@ Further workloads, reported in "extras" of the same JSON line:
               M2L orders chosen by the network (trained here on pairs of
               another cluster, decision margin tuned on a third) against the
               fixed order 10 (FP64 M2L both)
+  dual1M      the headline workload through the dual-tree traversal with
+              the theta MAC (theta 0.5, mutual M2L, FP64): geometric centres
+              and the AP variant (centre of mass, gradient only)
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3]
                     [--no-extras] [--no-cpu-baseline]
@@ -56,12 +59,13 @@ def log(msg):
 
 
 def run_leg(F, torch, X, Q, p, precision, steps, warmup, tree="adaptive", depth=0, leaf_max=64, root_side=None,
-            setup=None):
-    f = F.FMM(p, depth, precision, root_side=root_side, tree=tree, leaf_max=leaf_max)
+            setup=None, theta=0.5, centre="geometric"):
+    f = F.FMM(p, depth, precision, root_side=root_side, tree=tree, leaf_max=leaf_max, theta=theta, centre=centre)
     if setup is not None:
         setup(f)
     n = int(Q.shape[0])
-    phi = torch.empty(n, dtype=torch.float64, device=Q.device)
+    # the AP variant of the dual tree gives the gradient only
+    phi = None if (tree == "dual" and centre == "ap") else torch.empty(n, dtype=torch.float64, device=Q.device)
     grad = torch.empty((n, 3), dtype=torch.float64, device=Q.device)
     for _ in range(warmup):
         f.evaluate(X, Q, phi, grad)
@@ -282,6 +286,41 @@ def extra_bf16x3(F, torch, W, args, dev):
     return out
 
 
+def extra_dual(F, torch, W, args, dev):
+    """The headline workload through the dual-tree traversal (theta MAC,
+    mutual M2L) in FP64: geometric centres and the AP variant."""
+    cfg = W.CONFIGS[1]
+    xyz, q = W.make(cfg)
+    X = torch.from_numpy(xyz).to(dev)
+    Q = torch.from_numpy(q).to(dev)
+    del xyz, q
+    out = {"workload": cfg["name"], "n": cfg["n"], "p": cfg["p"], "leaf_max": cfg["leaf_max"], "theta": 0.5,
+           "precision": "fp64"}
+    ref, phi_r, grad_r = run_leg(F, torch, X, Q, cfg["p"], "fp64", 1, 1, tree="adaptive", leaf_max=cfg["leaf_max"])
+    for centre in ("geometric", "ap"):
+        log(f"dual1M {centre}")
+        leg, phi_d, grad_d = run_leg(F, torch, X, Q, cfg["p"], "fp64", args.steps, args.warmup, tree="dual",
+                                     leaf_max=cfg["leaf_max"], theta=0.5, centre=centre)
+        flops = leg["m2l_alg_flops_per_step"]
+        m2l_ms = leg["phase_ms_per_step"]["m2l"]
+        ach = flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else None
+        out[centre] = {
+            "particles_per_s": leg["particles_per_s"], "ms_per_step": leg["ms_per_step"],
+            "phase_ms_per_step": leg["phase_ms_per_step"], "m2l_directed_pairs_per_step": leg["m2l_pairs_per_step"],
+            "direct_leaf_pairs": leg["tree"]["u_pairs"], "nodes": leg["tree"]["nodes"],
+            "rel_force_diff_vs_adaptive_fp64": rel_err(torch, grad_d, grad_r),
+            "m2l_roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                             "frac": ach / PEAK_TFLOPS["fp64"] if ach else None,
+                             "note": "algorithmic 2*S(p) flops per directed pair over the M2L phase (its passes, "
+                                     "with the near field running beside it); the derivative tensors are not "
+                                     "counted"},
+        }
+        del phi_d, grad_d
+    del X, Q, phi_r, grad_r
+    torch.cuda.empty_cache()
+    return out
+
+
 def extra_learned(F, torch, W, args, dev):
     import numpy as np
     log("learned4M: training pairs")
@@ -363,7 +402,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="uniform16M,batched256,learned4M,bf16x3")
+    ap.add_argument("--extras", default="uniform16M,batched256,learned4M,bf16x3,dual1M")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -430,7 +469,7 @@ def main():
     if not args.no_extras:
         for name in [e for e in args.extras.split(",") if e]:
             fn = {"uniform16M": extra_uniform16m, "batched256": extra_batched, "learned4M": extra_learned,
-                  "bf16x3": extra_bf16x3}[name]
+                  "bf16x3": extra_bf16x3, "dual1M": extra_dual}[name]
             extras[name] = fn(F, torch, W, args, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg["p"], cfg["leaf_max"], cfg["n"])
     out = {

@@ -131,6 +131,8 @@ struct Forest {
     // dual-tree traversal: centres and radii, round counters, frontiers, the
     // M2L and direct-pair keys (unsorted, sorted), their CSR forms
     double4* zr = nullptr;
+    double4* zsum = nullptr;  // charge sums per node (charge-weighted centres)
+    size_t zsum_cap = 0;
     int* dcnt = nullptr;
     int2* front[2] = {};
     uint64_t *mk = nullptr, *mks = nullptr, *pk = nullptr, *pks = nullptr;
@@ -374,16 +376,6 @@ ctfmm_status upload_tables(ctfmm_ctx* c) {
     const size_t o_ds = put(blob, GEN_DET_START, sizeof(GEN_DET_START) / sizeof(GEN_DET_START[0]));
     const size_t o_df = put(blob, GEN_DET_FULL, sizeof(GEN_DET_FULL) / sizeof(GEN_DET_FULL[0]));
     const size_t o_dc = put(blob, GEN_DET_COEF, sizeof(GEN_DET_COEF) / sizeof(GEN_DET_COEF[0]));
-#define NEL(a) (sizeof(a) / sizeof((a)[0]))
-    const size_t o_mgs = put(blob, GEN_M2MG_START, NEL(GEN_M2MG_START));
-    const size_t o_mgj = put(blob, GEN_M2MG_J, NEL(GEN_M2MG_J));
-    const size_t o_mgm = put(blob, GEN_M2MG_MONO, NEL(GEN_M2MG_MONO));
-    const size_t o_mgc = put(blob, GEN_M2MG_COEF, NEL(GEN_M2MG_COEF));
-    const size_t o_lgs = put(blob, GEN_L2LG_START, NEL(GEN_L2LG_START));
-    const size_t o_lgj = put(blob, GEN_L2LG_J, NEL(GEN_L2LG_J));
-    const size_t o_lgm = put(blob, GEN_L2LG_MONO, NEL(GEN_L2LG_MONO));
-    const size_t o_lgc = put(blob, GEN_L2LG_COEF, NEL(GEN_L2LG_COEF));
-#undef NEL
     void* d = dev_alloc(c, blob.size());
     if (!d) return fail(c, CTFMM_ENOMEM, "table allocation failed");
     HIPCHK(c, hipMemcpyAsync(d, blob.data(), blob.size(), hipMemcpyHostToDevice, c->stream));
@@ -408,14 +400,6 @@ ctfmm_status upload_tables(ctfmm_ctx* c) {
     c->T.det_start = (const int16_t*)(b + o_ds);
     c->T.det_full = (const int16_t*)(b + o_df);
     c->T.det_coef = (const double*)(b + o_dc);
-    c->T.m2mg_start = (const int32_t*)(b + o_mgs);
-    c->T.m2mg_j = (const uint8_t*)(b + o_mgj);
-    c->T.m2mg_mono = (const int16_t*)(b + o_mgm);
-    c->T.m2mg_coef = (const double*)(b + o_mgc);
-    c->T.l2lg_start = (const int32_t*)(b + o_lgs);
-    c->T.l2lg_j = (const uint8_t*)(b + o_lgj);
-    c->T.l2lg_mono = (const int16_t*)(b + o_lgm);
-    c->T.l2lg_coef = (const double*)(b + o_lgc);
     return CTFMM_OK;
 }
 
@@ -1474,7 +1458,9 @@ ctfmm_status evaluate_dual(ctfmm_ctx* c, int n, const double* xyz, const double*
     ACHK(grow(c, f.aL, f.aL_cap, (size_t)nn * ldm, false));
     ACHK(grow(c, f.moff, f.moff_cap, (size_t)nn + 1, false));
     ACHK(grow(c, f.poff, f.poff_cap, (size_t)nn + 1, false));
-    launch_dual_centres(st, nn, f.tr, f.boxes, f.a_P, c->centre, f.zr, c->err_flag);
+    ACHK(grow(c, f.zsum, f.zsum_cap, (size_t)nn, false));
+    launch_dual_centres(st, n, nn, f.lev_first, f.lev_count, f.tr, f.boxes, f.leaf_of, f.a_P, c->centre, f.zsum, f.zr,
+                        c->err_flag);
     rec(c, 1);
     // the upward pass needs the centres only: it runs on a side stream beside
     // the traversal

@@ -5,7 +5,9 @@
 //             charge-weighted mean of its particles) and enclosing radius r
 //             (the largest distance from z to one of its particles);
 //   upward    P2M at the leaves about z (Eq. P2M), then M2M to the parents
-//             with the shift z_child - z_parent (Eq. M2M) level by level;
+//             with the shift z_child - z_parent (Eq. M2M) level by level,
+//             as three one-axis binomial shifts of the full components and
+//             the detracer;
 //   traversal from the pair (root, root), in rounds: a round takes every
 //             pair of its frontier and either accepts it (theta |z_B - z_A|
 //             > r_A + r_B: two directed M2L entries), sums it directly (two
@@ -13,14 +15,16 @@
 //             puts its children's pairs into the next frontier; a node paired
 //             with itself gives its children's self pairs and each two
 //             children once.  The entries are appended with one atomic per
-//             wavefront and sorted afterwards, so the lists (and every sum
-//             over them) do not depend on the order of the appends;
+//             workgroup and chunk of pairs and sorted afterwards, so the
+//             lists (and every sum over them) do not depend on the order of
+//             the appends;
 //   M2L       per target node, its sources in ascending order, one lane per
 //             source: the traceless gradient of 1/r at the pair's offset and
 //             the contraction of Eq. M2L, both straight-line generated code;
 //             the lanes' sums are added by a butterfly (the same total on
 //             every lane);
-//   downward  L2L from each parent to its children (Eq. L2L), L2P at the
+//   downward  L2L from each parent to its children (Eq. L2L, three one-axis
+//             Taylor shifts of the full components), L2P at the
 //             leaves (Eq. L2P); the direct part by the leaf-pair kernel of
 //             the adaptive tree.
 // Scaled expansions per node: M~_n = M_n / h^|n| and L~_n = L_n h^(|n|+1)
@@ -28,6 +32,8 @@
 // positive charges) leaves the dipole out of every M2L and computes the
 // gradient only.
 #include <math.h>
+
+#include <vector>
 
 #include "ctfmm_internal.h"
 
@@ -62,90 +68,127 @@ __device__ inline void cube_centre(const ABox& box, uint64_t key, int level, dou
     for (int d = 0; d < 3; ++d) z[d] = box.lo[d] + ((double)compact21(key >> d) + 0.5) * h;
 }
 
-// wavefront-wide exclusive position of this lane's cnt entries in a buffer
-// whose fill counter is *ctr (one atomic per wavefront); every lane calls it
-__device__ inline int wave_append(int* ctr, int cnt) {
-    const int lane = threadIdx.x & 63;
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int o = __shfl_up(incl, d);
-        if (lane >= d) incl += o;
-    }
-    const int tot = __shfl(incl, 63);
-    int base = 0;
-    if (lane == 63 && tot > 0) base = atomicAdd(ctr, tot);
-    base = __shfl(base, 63);
-    return base + incl - cnt;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ centres and radii
 
-// One workgroup per node.  mode 0: geometric centre; 1 and 2: the
-// charge-weighted mean where the node's total charge is positive (else the
-// geometric centre); 2 (AP) also flags a non-positive charge (bit 2 of err).
-constexpr int DC_B = 256;
-__global__ __launch_bounds__(DC_B) void k_dual_centres(ATree t, const ABox* __restrict__ boxes,
-                                                       const double4* __restrict__ P, int mode,
-                                                       double4* __restrict__ zr, int* __restrict__ err) {
+// charge and charge moment (q, q x, q y, q z) of every leaf, one wavefront
+// per leaf; AP (mode 2) flags a non-positive charge (bit 2 of err)
+__global__ __launch_bounds__(64) void k_dual_leafsum(ATree t, const double4* __restrict__ P, int mode,
+                                                     double4* __restrict__ sum, int* __restrict__ err) {
     const int g = blockIdx.x;
+    if (!leaf_d(t.info[g])) return;
     const int b = t.pb[g], e = t.pe[g];
-    __shared__ double red[4][DC_B];
-    __shared__ double zc[3];
-    const int tid = threadIdx.x;
-    if (tid == 0) cube_centre(boxes[t.sys[g]], t.key[g], t.info[g] & 0xff, zc);
-    if (mode != 0) {
-        double w = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        bool bad = false;
-        for (int s = b + tid; s < e; s += DC_B) {
-            const double4 pt = P[s];
-            w += pt.w;
-            sx += pt.w * pt.x;
-            sy += pt.w * pt.y;
-            sz += pt.w * pt.z;
-            bad |= !(pt.w > 0.0);
-        }
-        if (mode == 2 && bad) atomicOr(err, 2);
-        red[0][tid] = w;
-        red[1][tid] = sx;
-        red[2][tid] = sy;
-        red[3][tid] = sz;
-        __syncthreads();
-        for (int h = DC_B / 2; h > 0; h >>= 1) {
-            if (tid < h)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + h];
-            __syncthreads();
-        }
-        if (tid == 0 && red[0][0] > 0.0) {
-            zc[0] = red[1][0] / red[0][0];
-            zc[1] = red[2][0] / red[0][0];
-            zc[2] = red[3][0] / red[0][0];
-        }
-    }
-    __syncthreads();
-    const double zx = zc[0], zy = zc[1], zz = zc[2];
-    double r = 0.0;
-    for (int s = b + tid; s < e; s += DC_B) {
+    double w = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    bool bad = false;
+    for (int s = b + (int)threadIdx.x; s < e; s += 64) {
         const double4 pt = P[s];
-        r = fmax(r, norm_plain(pt.x - zx, pt.y - zy, pt.z - zz));
+        w += pt.w;
+        sx += pt.w * pt.x;
+        sy += pt.w * pt.y;
+        sz += pt.w * pt.z;
+        bad |= !(pt.w > 0.0);
     }
-    __syncthreads();  // red is reused
-    red[0][tid] = r;
-    __syncthreads();
-    for (int h = DC_B / 2; h > 0; h >>= 1) {
-        if (tid < h) red[0][tid] = fmax(red[0][tid], red[0][tid + h]);
-        __syncthreads();
+    if (mode == 2 && bad) atomicOr(err, 2);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        w += __shfl_xor(w, m);
+        sx += __shfl_xor(sx, m);
+        sy += __shfl_xor(sy, m);
+        sz += __shfl_xor(sz, m);
     }
-    if (tid == 0) zr[g] = make_double4(zx, zy, zz, red[0][0]);
+    if (threadIdx.x == 0) sum[g] = make_double4(sx, sy, sz, w);
 }
 
-void launch_dual_centres(hipStream_t s, int nn, const ATree& t, const ABox* boxes, const double4* P, int mode,
-                         double4* zr, int* err) {
+// the non-leaf nodes of [first, first+count): the sums of their children
+// in octant order
+__global__ void k_dual_upsum(int first, int count, ATree t, double4* __restrict__ sum) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int g = first + i;
+    if (leaf_d(t.info[g])) return;
+    double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int o = 0; o < 8; ++o) {
+        const int c = t.child[8 * g + o];
+        if (c < 0) continue;
+        const double4 v = sum[c];
+        a.x += v.x;
+        a.y += v.y;
+        a.z += v.z;
+        a.w += v.w;
+    }
+    sum[g] = a;
+}
+
+// centre of every node (mode 0: the cube centre; else the charge-weighted
+// mean where the total charge is positive, else the cube centre); radius 0
+__global__ void k_dual_zr(int nn, ATree t, const ABox* __restrict__ boxes, int mode, const double4* __restrict__ sum,
+                          double4* __restrict__ zr) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nn) return;
+    double z[3];
+    cube_centre(boxes[t.sys[g]], t.key[g], t.info[g] & 0xff, z);
+    if (mode != 0) {
+        const double4 v = sum[g];
+        if (v.w > 0.0) {
+            z[0] = v.x / v.w;
+            z[1] = v.y / v.w;
+            z[2] = v.z / v.w;
+        }
+    }
+    zr[g] = make_double4(z[0], z[1], z[2], 0.0);
+}
+
+// enclosing radii: every particle takes its distance to the centre of each
+// node that holds it (level by level from its leaf up); the lanes of a
+// wavefront that share a node take the largest of theirs and one of them
+// raises the node's radius by an atomic maximum on the bit pattern (radii
+// are non-negative, so the bit patterns order like the values)
+__global__ __launch_bounds__(256) void k_dual_radius(int n, int maxlev, ATree t, const int32_t* __restrict__ leaf_of,
+                                                     const double4* __restrict__ P, double4* __restrict__ zr) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = s < n;
+    int cur = live ? leaf_of[s] : -1;
+    const double4 pt = live ? P[s] : make_double4(0.0, 0.0, 0.0, 0.0);
+    int lev = cur >= 0 ? (t.info[cur] & 0xff) : -1;
+    for (int l = maxlev; l >= 0; --l) {
+        const int node = lev == l ? cur : -1;
+        double d = 0.0;
+        if (node >= 0) {
+            const double4 z = zr[node];
+            d = norm_plain(pt.x - z.x, pt.y - z.y, pt.z - z.z);
+            cur = t.par[node];
+            lev = cur >= 0 ? l - 1 : -1;
+        }
+        // one atomic per distinct node among the wavefront's lanes
+        uint64_t todo = __ballot(node >= 0);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int ln = __shfl(node, leader);
+            const bool mine = node == ln && node >= 0;
+            double v = mine ? d : 0.0;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+            if ((int)(threadIdx.x & 63) == leader)
+                atomicMax((unsigned long long*)&zr[ln].w, (unsigned long long)__double_as_longlong(v));
+            todo &= ~__ballot(mine);
+        }
+    }
+}
+
+void launch_dual_centres(hipStream_t s, int n, int nn, const std::vector<int>& lev_first,
+                         const std::vector<int>& lev_count, const ATree& t, const ABox* boxes,
+                         const int32_t* leaf_of, const double4* P, int mode, double4* sum, double4* zr, int* err) {
     if (nn <= 0) return;
-    hipLaunchKernelGGL(k_dual_centres, dim3(nn), dim3(DC_B), 0, s, t, boxes, P, mode, zr, err);
+    const int maxlev = (int)lev_first.size() - 1;
+    if (mode != 0) {
+        hipLaunchKernelGGL(k_dual_leafsum, dim3(nn), dim3(64), 0, s, t, P, mode, sum, err);
+        for (int l = maxlev - 1; l >= 0; --l)
+            hipLaunchKernelGGL(k_dual_upsum, dim3(cdiv(lev_count[l], 256)), dim3(256), 0, s, lev_first[l],
+                               lev_count[l], t, sum);
+    }
+    hipLaunchKernelGGL(k_dual_zr, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, t, boxes, mode, sum, zr);
+    hipLaunchKernelGGL(k_dual_radius, dim3(cdiv(n, 256)), dim3(256), 0, s, n, maxlev, t, leaf_of, P, zr);
 }
 
 // ------------------------------------------------------------------ P2M, M2M, L2L about arbitrary centres
@@ -160,65 +203,140 @@ __global__ __launch_bounds__(64) void k_dual_p2m(ATree t, const double4* __restr
     p2m_cell<PP>(z.x, z.y, z.z, t.geo[g].w, t.pb[g], t.pe[g], P, T, M + (size_t)g * ldm_of(PP));
 }
 
-// the monomials (d/h)^f of the full components f, |f| <= P, into mono
+// position of the full component (a, b, c) (rank-major, a then b descending)
+__device__ inline int fidx(int a, int b, int c) {
+    const int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
+}
+
+// full traceless components X[f], |f| <= P, of the independent ones x
+// (scaled by 2^-|f| if halve), one wavefront
 template <int P>
-__device__ inline void monomials(double dx, double dy, double dz, const DevTables& T, double* mono) {
+__device__ inline void expand_full(const double* __restrict__ x, bool halve, const DevTables& T, double* X) {
     constexpr int nf = (P + 1) * (P + 2) * (P + 3) / 6;
     for (int f = threadIdx.x; f < nf; f += 64) {
-        const int a = T.full[3 * f], b = T.full[3 * f + 1], c = T.full[3 * f + 2];
-        double v = 1.0;
-        for (int k = 0; k < a; ++k) v *= dx;
-        for (int k = 0; k < b; ++k) v *= dy;
-        for (int k = 0; k < c; ++k) v *= dz;
-        mono[f] = v;
+        double v = 0.0;
+        const int t1 = T.exp_start[f + 1];
+        for (int t = T.exp_start[f]; t < t1; ++t) v += (double)T.exp_coef[t] * x[T.exp_slot[t]];
+        X[f] = halve ? ldexp(v, -(T.full[3 * f] + T.full[3 * f + 1] + T.full[3 * f + 2])) : v;
     }
 }
 
-// M~(parent) = sum over its children, in octant order, of the shift of
-// Eq. M2M with d = z_child - z_parent and rho = 1/2:
-//   M~_n += sum_t COEF[t] (d/h_P)^MONO[t] rho^|J[t]| M~child_J[t]
-// One wavefront per non-leaf node of [first, first+count); lanes over n.
+// Y[n] = sum_t w(n_d, t) X[n with n_d replaced] along axis d, for every
+// full n with |n| <= P.  M2M (shift of the moments, Eq. M2M): the binomial
+// sum over t <= n_d of C(n_d, t) s^(n_d - t) X[.., t, ..]; L2L (Taylor
+// shift, Eq. L2L): the sum over t <= P - |n| of s^t / t! X[.., n_d + t, ..].
+template <int P, bool TAYLOR>
+__device__ inline void shift_axis(int d, double s, const double* X, double* Y, bool add, const DevTables& T) {
+    constexpr int nf = (P + 1) * (P + 2) * (P + 3) / 6;
+    for (int f = threadIdx.x; f < nf; f += 64) {
+        int e[3] = {T.full[3 * f], T.full[3 * f + 1], T.full[3 * f + 2]};
+        const int nd = e[d], rank = e[0] + e[1] + e[2];
+        double v = 0.0;
+        if (TAYLOR) {
+            double w = 1.0;
+            for (int t = 0; t <= P - rank; ++t) {
+                e[d] = nd + t;
+                v += w * X[fidx(e[0], e[1], e[2])];
+                w *= s / (double)(t + 1);
+            }
+        } else {
+            double w = 1.0;  // C(nd, t) s^(nd - t), from t = nd down
+            for (int t = nd; t >= 0; --t) {
+                e[d] = t;
+                v += w * X[fidx(e[0], e[1], e[2])];
+                w *= s * (double)t / (double)(nd - t + 1);
+            }
+        }
+        Y[f] = add ? Y[f] + v : v;
+    }
+}
+
+// M~(parent) = the detracer of the sum over its children, in octant order,
+// of the child's multipole (full components, rho = 1/2 applied) moved by
+// d = z_child - z_parent (Eq. M2M): three one-axis binomial shifts with
+// s = -d/h_P, then M~_n = sum DET[n][f] S_f (Eq. Detracer, as in P2M).
+// One workgroup per non-leaf node of [first, first+count); the eight
+// children are shifted side by side (a missing child contributes zeros).
+constexpr int M2M_B = 256;
 template <int P>
-__global__ __launch_bounds__(64) void k_dual_m2m(int first, ATree t, const double4* __restrict__ zr, DevTables T,
-                                                 double* __restrict__ M) {
+__global__ __launch_bounds__(M2M_B) void k_dual_m2m(int first, ATree t, const double4* __restrict__ zr, DevTables T,
+                                                    double* __restrict__ M) {
     constexpr int nc = (P + 1) * (P + 1);
     constexpr int nf = (P + 1) * (P + 2) * (P + 3) / 6;
     constexpr int ldm = ldm_of(P);
     const int g = first + blockIdx.x;
     if (leaf_d(t.info[g])) return;
-    __shared__ double mono[nf];
-    __shared__ double mc[nc];
-    const int lane = threadIdx.x;
-    const double4 zp = zr[g];
-    const double ih = 1.0 / t.geo[g].w;
-    double acc[2] = {0.0, 0.0};
-    for (int o = 0; o < 8; ++o) {
-        const int c = t.child[8 * g + o];
-        if (c < 0) continue;
-        __syncthreads();  // the previous child's tables are read
-        const double4 zc = zr[c];
-        monomials<P>((zc.x - zp.x) * ih, (zc.y - zp.y) * ih, (zc.z - zp.z) * ih, T, mono);
-        for (int j = lane; j < nc; j += 64) mc[j] = ldexp(M[(size_t)c * ldm + j], -rank_d(j));
+    __shared__ double X[8][nf], Y[8][nf];
+    __shared__ int8_t E[nf][3];
+    __shared__ double sd[8][3];
+    __shared__ int cid[8];
+    const int tid = threadIdx.x;
+    for (int f = tid; f < nf; f += M2M_B)
+        for (int d = 0; d < 3; ++d) E[f][d] = T.full[3 * f + d];
+    if (tid < 8) {
+        const int c = t.child[8 * g + tid];
+        cid[tid] = c;
+        const double4 zp = zr[g];
+        const double ih = 1.0 / t.geo[g].w;
+        const double4 zc = c >= 0 ? zr[c] : zp;
+        sd[tid][0] = -(zc.x - zp.x) * ih;
+        sd[tid][1] = -(zc.y - zp.y) * ih;
+        sd[tid][2] = -(zc.z - zp.z) * ih;
+    }
+    __syncthreads();
+    for (int it = tid; it < 8 * nf; it += M2M_B) {
+        const int ch = it / nf, f = it % nf;
+        const int c = cid[ch];
+        double v = 0.0;
+        if (c >= 0) {
+            const double* x = M + (size_t)c * ldm;
+            const int t1 = T.exp_start[f + 1];
+            for (int q = T.exp_start[f]; q < t1; ++q) v += (double)T.exp_coef[q] * x[T.exp_slot[q]];
+            v = ldexp(v, -(E[f][0] + E[f][1] + E[f][2]));
+        }
+        X[ch][f] = v;
+    }
+    // three one-axis shifts: X -> Y (x), Y -> X (y), X -> Y (z)
+    for (int d = 0; d < 3; ++d) {
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int n = lane + 64 * k;
-            if (n >= nc) break;
-            double v = 0.0;
-            const int t1 = T.m2mg_start[n + 1];
-            for (int q = T.m2mg_start[n]; q < t1; ++q) v += T.m2mg_coef[q] * mono[T.m2mg_mono[q]] * mc[T.m2mg_j[q]];
-            acc[k] += v;
+        double(*src)[nf] = (d == 1) ? Y : X;
+        double(*dst)[nf] = (d == 1) ? X : Y;
+        for (int it = tid; it < 8 * nf; it += M2M_B) {
+            const int ch = it / nf, f = it % nf;
+            int e[3] = {E[f][0], E[f][1], E[f][2]};
+            const int nd = e[d];
+            const double sv = sd[ch][d];
+            double v = 0.0, w = 1.0;  // C(nd, t) s^(nd - t), from t = nd down
+            for (int tt = nd; tt >= 0; --tt) {
+                e[d] = tt;
+                v += w * src[ch][fidx(e[0], e[1], e[2])];
+                w *= sv * (double)tt / (double)(nd - tt + 1);
+            }
+            dst[ch][f] = v;
         }
     }
-    for (int k = 0; k < 2; ++k) {
-        const int n = lane + 64 * k;
-        if (n < ldm) M[(size_t)g * ldm + n] = n < nc ? acc[k] : 0.0;
+    __syncthreads();
+    for (int n = tid; n < ldm; n += M2M_B) {
+        double v = 0.0;
+        if (n < nc) {
+            const int t1 = T.det_start[n + 1];
+            for (int q = T.det_start[n]; q < t1; ++q) {
+                const int f = T.det_full[q];
+                double sf = 0.0;
+#pragma unroll
+                for (int ch = 0; ch < 8; ++ch) sf += Y[ch][f];
+                v += T.det_coef[q] * sf;
+            }
+        }
+        M[(size_t)g * ldm + n] = v;  // padding stays zero
     }
 }
 
-// L~(child) += rho^(|n|+1) sum_t COEF[t] (d/h_P)^MONO[t] L~parent_J[t]
-// (Eq. L2L), d = z_child - z_parent, rho = 1/2, terms with rank(J) > P left
-// out.  One wavefront per node of [first, first+count) (level >= 1).
+// L~(child) += rho^(|n|+1) [Taylor shift of the parent's expansion by
+// d = z_child - z_parent (Eq. L2L)]_n, rho = 1/2: the parent's full
+// components, three one-axis Taylor shifts with s = d/h_P, truncated at
+// rank P.  One wavefront per node of [first, first+count) (level >= 1).
 template <int P>
 __global__ __launch_bounds__(64) void k_dual_l2l(int first, ATree t, const double4* __restrict__ zr, DevTables T,
                                                  double* __restrict__ L) {
@@ -227,26 +345,21 @@ __global__ __launch_bounds__(64) void k_dual_l2l(int first, ATree t, const doubl
     constexpr int ldm = ldm_of(P);
     const int g = first + blockIdx.x;
     const int par = t.par[g];
-    __shared__ double mono[nf];
-    __shared__ double lp[nc];
+    __shared__ double X[nf], Y[nf];
     const int lane = threadIdx.x;
     const double4 zp = zr[par], zc = zr[g];
     const double ih = 1.0 / t.geo[par].w;
-    monomials<P>((zc.x - zp.x) * ih, (zc.y - zp.y) * ih, (zc.z - zp.z) * ih, T, mono);
-    for (int j = lane; j < nc; j += 64) lp[j] = L[(size_t)par * ldm + j];
+    expand_full<P>(L + (size_t)par * ldm, false, T, X);
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int n = lane + 64 * k;
-        if (n >= nc) break;
-        double v = 0.0;
-        const int t1 = T.l2lg_start[n + 1];
-        for (int q = T.l2lg_start[n]; q < t1; ++q) {
-            const int j = T.l2lg_j[q];
-            if (j >= nc) break;  // terms are ordered by J
-            v += T.l2lg_coef[q] * mono[T.l2lg_mono[q]] * lp[j];
-        }
-        L[(size_t)g * ldm + n] += ldexp(v, -(rank_d(n) + 1));
+    shift_axis<P, true>(0, (zc.x - zp.x) * ih, X, Y, false, T);
+    __syncthreads();
+    shift_axis<P, true>(1, (zc.y - zp.y) * ih, Y, X, false, T);
+    __syncthreads();
+    shift_axis<P, true>(2, (zc.z - zp.z) * ih, X, Y, false, T);
+    __syncthreads();
+    for (int n = lane; n < nc; n += 64) {
+        const int a = T.ind[3 * n], b = T.ind[3 * n + 1], c = T.ind[3 * n + 2];
+        L[(size_t)g * ldm + n] += ldexp(Y[fidx(a, b, c)], -(a + b + c + 1));
     }
 }
 
@@ -265,7 +378,7 @@ void launch_dual_m2m(hipStream_t s, int p, int first, int count, const ATree& t,
                      const DevTables& T, double* M) {
     if (count <= 0) return;
     switch (p) {
-#define CASE(PP) case PP: hipLaunchKernelGGL(k_dual_m2m<PP>, dim3(count), dim3(64), 0, s, first, t, zr, T, M); break;
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_dual_m2m<PP>, dim3(count), dim3(M2M_B), 0, s, first, t, zr, T, M); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;
@@ -295,74 +408,124 @@ __global__ void k_dual_init(int nr, int* __restrict__ cnt, int2* __restrict__ fr
 // One round.  Entries past a buffer's capacity are counted but not written
 // (the host then grows the buffers and runs the traversal again).  M2L
 // entries are keys (target << sh) | source, direct pairs (leaf << sh) |
-// partner.
-constexpr int DW_B = 256;
+// partner.  A workgroup takes DW_B * DW_I pairs at a time, DW_I consecutive
+// ones per thread, and reserves its room in each output with one atomic.
+constexpr int DW_B = 256, DW_I = 16;
+
+struct PairStep {
+    int kind;   // 0 none, 1 M2L, 2 direct, 3 open node o against other, 4 split a self pair
+    int a, b, o, other, nch;
+};
+
+__device__ inline PairStep pair_step(int i, int nin, const int2* __restrict__ fin, const ATree& t,
+                                     const double4* __restrict__ zr, double theta) {
+    PairStep q{0, 0, 0, 0, 0, 0};
+    if (i >= nin) return q;
+    const int2 pr = fin[i];
+    q.a = pr.x;
+    q.b = pr.y;
+    const bool la = leaf_d(t.info[q.a]), lb = leaf_d(t.info[q.b]);
+    if (q.a == q.b) {
+        q.kind = la ? 2 : 4;
+        q.o = q.a;
+    } else {
+        const double4 A = zr[q.a], B = zr[q.b];
+        const double dist = norm_plain(B.x - A.x, B.y - A.y, B.z - A.z);
+        if (theta * dist > A.w + B.w) {
+            q.kind = 1;
+        } else if (la && lb) {
+            q.kind = 2;
+        } else {
+            const bool open_a = !la && (lb || A.w >= B.w);
+            q.kind = 3;
+            q.o = open_a ? q.a : q.b;
+            q.other = open_a ? q.b : q.a;
+        }
+    }
+    if (q.kind >= 3)
+        for (int k = 0; k < 8; ++k) q.nch += t.child[8 * q.o + k] >= 0;
+    return q;
+}
+
 __global__ __launch_bounds__(DW_B) void k_dual_round(int r, int nr, const int2* __restrict__ fin,
                                                      int2* __restrict__ fout, int cap_f, uint64_t* __restrict__ mk,
                                                      int cap_m, uint64_t* __restrict__ pk, int cap_p, int sh,
                                                      int* __restrict__ cnt, ATree t, const double4* __restrict__ zr,
                                                      double theta) {
     const int nin = min(cnt[r], cap_f);
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * DW_B + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * DW_B) >> 6;
-    for (int i0 = wave * 64; i0 < nin; i0 += nwaves * 64) {
-        const int i = i0 + lane;
-        int kind = 0;  // 0 none, 1 M2L, 2 direct, 3 open node o against other
-        int a = 0, b = 0, o = 0, other = 0, nch = 0;
-        int ch[8];
-        if (i < nin) {
-            const int2 pr = fin[i];
-            a = pr.x;
-            b = pr.y;
-            const bool la = leaf_d(t.info[a]), lb = leaf_d(t.info[b]);
-            if (a == b) {
-                kind = la ? 2 : 4;
-                o = a;
-            } else {
-                const double4 A = zr[a], B = zr[b];
-                const double dist = norm_plain(B.x - A.x, B.y - A.y, B.z - A.z);
-                if (theta * dist > A.w + B.w) {
-                    kind = 1;
-                } else if (la && lb) {
-                    kind = 2;
-                } else {
-                    const bool open_a = !la && (lb || A.w >= B.w);
-                    kind = 3;
-                    o = open_a ? a : b;
-                    other = open_a ? b : a;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ int wtot[3][DW_B / 64];
+    __shared__ int bbase[3];
+    for (long long c0 = (long long)blockIdx.x * DW_B * DW_I; c0 < nin; c0 += (long long)gridDim.x * DW_B * DW_I) {
+        const int i0 = (int)c0 + tid * DW_I;
+        int tf = 0, tm = 0, tp = 0;
+#pragma unroll 4
+        for (int k = 0; k < DW_I; ++k) {
+            const PairStep q = pair_step(i0 + k, nin, fin, t, zr, theta);
+            tf += q.kind == 3 ? q.nch : (q.kind == 4 ? q.nch * (q.nch + 1) / 2 : 0);
+            tm += q.kind == 1 ? 2 : 0;
+            tp += q.kind == 2 ? (q.a == q.b ? 1 : 2) : 0;
+        }
+        // exclusive positions of this thread's entries within the workgroup
+        int v[3] = {tf, tm, tp};
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            int incl = v[x];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int o = __shfl_up(incl, d);
+                if (lane >= d) incl += o;
+            }
+            if (lane == 63) wtot[x][wv] = incl;
+            v[x] = incl - v[x];
+        }
+        __syncthreads();
+        if (tid < 3) {
+            int tot = 0;
+            for (int w = 0; w < DW_B / 64; ++w) tot += wtot[tid][w];
+            const int ctr = tid == 0 ? r + 1 : nr + tid;
+            bbase[tid] = tot > 0 ? atomicAdd(&cnt[ctr], tot) : 0;
+        }
+        __syncthreads();
+        int pf = bbase[0] + v[0], pm = bbase[1] + v[1], pp = bbase[2] + v[2];
+        for (int w = 0; w < wv; ++w) {
+            pf += wtot[0][w];
+            pm += wtot[1][w];
+            pp += wtot[2][w];
+        }
+        for (int k = 0; k < DW_I; ++k) {
+            const PairStep q = pair_step(i0 + k, nin, fin, t, zr, theta);
+            if (q.kind == 1) {
+                if (pm + 1 < cap_m) {
+                    mk[pm] = ((uint64_t)q.b << sh) | (uint64_t)q.a;      // A -> B
+                    mk[pm + 1] = ((uint64_t)q.a << sh) | (uint64_t)q.b;  // B -> A
+                }
+                pm += 2;
+            } else if (q.kind == 2) {
+                if (pp < cap_p) pk[pp] = ((uint64_t)q.a << sh) | (uint64_t)q.b;
+                if (q.a != q.b && pp + 1 < cap_p) pk[pp + 1] = ((uint64_t)q.b << sh) | (uint64_t)q.a;
+                pp += q.a == q.b ? 1 : 2;
+            } else if (q.kind == 3) {
+                for (int k2 = 0; k2 < 8; ++k2) {
+                    const int c = t.child[8 * q.o + k2];
+                    if (c < 0) continue;
+                    if (pf < cap_f) fout[pf] = q.o == q.a ? make_int2(c, q.other) : make_int2(q.other, c);
+                    ++pf;
+                }
+            } else if (q.kind == 4) {
+                for (int x = 0; x < 8; ++x) {
+                    const int cx = t.child[8 * q.o + x];
+                    if (cx < 0) continue;
+                    for (int y = x; y < 8; ++y) {
+                        const int cy = t.child[8 * q.o + y];
+                        if (cy < 0) continue;
+                        if (pf < cap_f) fout[pf] = make_int2(cx, cy);
+                        ++pf;
+                    }
                 }
             }
-            if (kind >= 3)
-                for (int k = 0; k < 8; ++k) {
-                    const int c = t.child[8 * o + k];
-                    if (c >= 0) ch[nch++] = c;
-                }
         }
-        const int nf = kind == 3 ? nch : (kind == 4 ? nch * (nch + 1) / 2 : 0);
-        const int nm = kind == 1 ? 2 : 0;
-        const int np = kind == 2 ? (a == b ? 1 : 2) : 0;
-        const int bf = wave_append(&cnt[r + 1], nf);
-        const int bm = wave_append(&cnt[nr + 1], nm);
-        const int bp = wave_append(&cnt[nr + 2], np);
-        if (kind == 1 && bm + 1 < cap_m) {
-            mk[bm] = ((uint64_t)b << sh) | (uint64_t)a;  // A -> B
-            mk[bm + 1] = ((uint64_t)a << sh) | (uint64_t)b;  // B -> A
-        }
-        if (kind == 2) {
-            if (bp < cap_p) pk[bp] = ((uint64_t)a << sh) | (uint64_t)b;
-            if (np == 2 && bp + 1 < cap_p) pk[bp + 1] = ((uint64_t)b << sh) | (uint64_t)a;
-        }
-        if (kind == 3) {
-            for (int k = 0; k < nch; ++k)
-                if (bf + k < cap_f) fout[bf + k] = o == a ? make_int2(ch[k], other) : make_int2(other, ch[k]);
-        }
-        if (kind == 4) {
-            int w = bf;
-            for (int x = 0; x < nch; ++x)
-                for (int y = x; y < nch; ++y, ++w)
-                    if (w < cap_f) fout[w] = make_int2(ch[x], ch[y]);
-        }
+        __syncthreads();  // wtot and bbase are rewritten by the next chunk
     }
 }
 
@@ -372,8 +535,8 @@ void launch_dual_init(hipStream_t s, int nr, int* cnt, int2* front) {
 
 void launch_dual_round(hipStream_t s, int r, int nr, const int2* fin, int2* fout, int cap_f, uint64_t* mk, int cap_m,
                        uint64_t* pk, int cap_p, int sh, int* cnt, const ATree& t, const double4* zr, double theta) {
-    // enough wavefronts for the largest frontiers; smaller rounds exit early
-    hipLaunchKernelGGL(k_dual_round, dim3(2048), dim3(DW_B), 0, s, r, nr, fin, fout, cap_f, mk, cap_m, pk, cap_p, sh,
+    // enough workgroups for the largest frontiers; smaller rounds exit early
+    hipLaunchKernelGGL(k_dual_round, dim3(1024), dim3(DW_B), 0, s, r, nr, fin, fout, cap_f, mk, cap_m, pk, cap_p, sh,
                        cnt, t, zr, theta);
 }
 
@@ -450,6 +613,8 @@ template <int P, bool AP>
 void dual_m2l_passes(hipStream_t s, int nn, const ATree& t, const double4* zr, const int32_t* off, const int32_t* src,
                      const double* M, double* L) {
     // output ranks per pass, so that D and the pass's sums stay in registers
+    // (narrower passes lower the register count but recompute D more often,
+    // which measured slower)
 #define PASS(A, B) hipLaunchKernelGGL((k_dual_m2l<P, A, B, AP>), dim3(nn), dim3(64), 0, s, t, zr, off, src, M, L)
     if constexpr (P <= 6) {
         PASS(0, P);
@@ -499,7 +664,11 @@ __global__ __launch_bounds__(256) void k_dual_l2p(int n, ATree t, const int32_t*
     const double h = t.geo[B].w;
     const double ih = 1.0 / h;
     double lf = 0.0, lx = 0.0, ly = 0.0, lz = 0.0;
-    gen_l2p<P>((pt.x - z.x) * ih, (pt.y - z.y) * ih, (pt.z - z.z) * ih, L + (size_t)B * ldm_of(P), lf, lx, ly, lz);
+    // (always taken: without the branch the compiler schedules the
+    // polynomial's coefficient loads ahead and the kernel spills)
+    if (h > 0.0)
+        gen_l2p<P>((pt.x - z.x) * ih, (pt.y - z.y) * ih, (pt.z - z.z) * ih, L + (size_t)B * ldm_of(P), lf, lx, ly,
+                   lz);
     const double ih2 = ih * ih;
     const double4 nf = Fn[s];
     const size_t o = (size_t)idx[s];

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "generated/ctfmm_gen.h"
 
 namespace ctfmm {
@@ -32,15 +34,6 @@ struct DevTables {
     const int16_t* det_start;  // [NIND+1] detracer rows: independent n <- full f
     const int16_t* det_full;
     const double* det_coef;
-    // M2M and L2L for any shift: terms (j, monomial slot, coefficient) per output n
-    const int32_t* m2mg_start;  // [NIND+1]
-    const uint8_t* m2mg_j;
-    const int16_t* m2mg_mono;
-    const double* m2mg_coef;
-    const int32_t* l2lg_start;  // [NIND+1]
-    const uint8_t* l2lg_j;
-    const int16_t* l2lg_mono;
-    const double* l2lg_coef;
 };
 
 // row stride of the expansion buffers: (p+1)^2 rounded up to a multiple of 4
@@ -339,10 +332,12 @@ void launch_wlist_adaptive(hipStream_t s, int p, int nn, const ABox* boxes, cons
 void launch_scatter_out(hipStream_t s, int n, const int32_t* idx, const double4* F, double* phi, double* grad);
 
 // ---- dual-tree traversal (ctfmm_dual.hip) ----
-// centres and enclosing radii per node (mode: ctfmm_centre); err bit 2 = a
-// non-positive charge in the AP variant
-void launch_dual_centres(hipStream_t s, int nn, const ATree& t, const ABox* boxes, const double4* P, int mode,
-                         double4* zr, int* err);
+// centres and enclosing radii per node (mode: ctfmm_centre; sum: [nn]
+// charge sums, used for modes 1 and 2); err bit 2 = a non-positive charge in
+// the AP variant
+void launch_dual_centres(hipStream_t s, int n, int nn, const std::vector<int>& lev_first,
+                         const std::vector<int>& lev_count, const ATree& t, const ABox* boxes,
+                         const int32_t* leaf_of, const double4* P, int mode, double4* sum, double4* zr, int* err);
 void launch_dual_p2m(hipStream_t s, int p, int nn, const ATree& t, const double4* zr, const double4* P,
                      const DevTables& T, double* M);
 void launch_dual_m2m(hipStream_t s, int p, int first, int count, const ATree& t, const double4* zr,

@@ -207,50 +207,6 @@ def m2l_contraction():
     return out
 
 
-def m2m_generic():
-    """Per independent n: [(j, e, coef)] with, for any shift,
-        parent M~_n += sum coef * (d/h_P)^e * rho^|j| * child M~_j,
-    d = z_child - z_parent, rho = h_child / h_parent, e a full multi-index
-    of rank |n| - |j|.  Same derivation as m2m_matrix with the octant shift
-    sigma/4 and the scale 1/2 left symbolic (Eq. M2M, M2M part 2)."""
-    out = []
-    for ni, n in enumerate(IND):
-        acc = {}
-        for f, w in DET[ni].items():
-            nn = FULL[f]
-            for k1 in range(nn[0] + 1):
-                for k2 in range(nn[1] + 1):
-                    for k3 in range(nn[2] + 1):
-                        k = (k1, k2, k3)
-                        e = (nn[0] - k1, nn[1] - k2, nn[2] - k3)
-                        coef = Fraction(comb(nn[0], k1) * comb(nn[1], k2) * comb(nn[2], k3) * (-1) ** rank(e))
-                        for j, ej in expand(k).items():
-                            key = (j, FULL_POS[e])
-                            acc[key] = acc.get(key, 0) + w * coef * ej
-        out.append(sorted((j, e, v) for (j, e), v in acc.items() if v != 0))
-    return out
-
-
-def l2l_generic():
-    """Per independent n: [(j, k, coef)] with, for any shift,
-        child L~_n += rho^(|n|+1) sum coef * (d/h_P)^k * parent L~_j,
-    d = z_child - z_parent, rho = h_child / h_parent, k a full multi-index
-    of rank |j| - |n|: coef = expand(n + k)[j] / k!  (Eq. L2L)."""
-    out = []
-    for n in IND:
-        N = rank(n)
-        acc = {}
-        for K in range(PMAX - N + 1):
-            for k1 in range(K + 1):
-                for k2 in range(K - k1 + 1):
-                    k = (k1, k2, K - k1 - k2)
-                    for j, e in expand((n[0] + k[0], n[1] + k[1], n[2] + k[2])).items():
-                        key = (j, FULL_POS[k])
-                        acc[key] = acc.get(key, 0) + Fraction(e, mfact(k))
-        out.append(sorted((j, k, v) for (j, k), v in acc.items() if v != 0))
-    return out
-
-
 def m2l_pair_code(p, c):
     """Straight-line M2L for one pair at order p (Eq. M2L with the contraction
     c of m2l_contraction), for the outputs of ranks R0..R1 (template
@@ -527,20 +483,6 @@ def emit(outdir):
     w(f"static const short GEN_DET_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
     w(f"static const short GEN_DET_FULL[{len(fs)}] = {{" + ",".join(map(str, fs)) + "};")
     w(f"static const double GEN_DET_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
-    # generic M2M / L2L: per output n, terms (j, monomial slot, coefficient)
-    for name, fn, doc in (("M2MG", m2m_generic, "parent M~_n += sum_t COEF[t] * (d/h_P)^FULL[MONO[t]] * rho^|J[t]| * child M~_J[t]"),
-                          ("L2LG", l2l_generic, "child L~_n += rho^(|n|+1) * sum_t COEF[t] * (d/h_P)^FULL[MONO[t]] * parent L~_J[t]")):
-        rows = fn()
-        starts, js, ms, cs = [0], [], [], []
-        for r in rows:
-            for (j, e, v) in r:
-                js.append(j); ms.append(e); cs.append(_hexf(v))
-            starts.append(len(js))
-        w(f"// {doc}; terms of output n in [START[n], START[n+1]), d = z_child - z_parent, rho = h_child / h_parent")
-        w(f"static const int GEN_{name}_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
-        w(f"static const unsigned char GEN_{name}_J[{len(js)}] = {{" + ",".join(map(str, js)) + "};")
-        w(f"static const short GEN_{name}_MONO[{len(ms)}] = {{" + ",".join(map(str, ms)) + "};")
-        w(f"static const double GEN_{name}_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
     # inverse factorials of full components (L2P)
     w("// 1/n! for full slots (L2P weights)")
     w("static const double GEN_INV_MFACT[GEN_NFULL] = {" + ",".join(_hexf(Fraction(1, mfact(m))) for m in FULL) + "};")
