@@ -734,7 +734,8 @@ AdaptM2L m2l_args(ctfmm_ctx* c, const Forest& f, bool orders) {
 hipError_t m2l_adaptive(ctfmm_ctx* c, const Forest& f, hipStream_t st, const AdaptM2L& ad, const void* msrc,
                         double* out) {
     const int nt = (int)f.tiles_host.size();
-    const unsigned char* K = ad.ivord ? f.Kmix : f.Kpk;
+    // the FP32 kernel truncates the order-p operators per offset itself
+    const unsigned char* K = (ad.ivord && !rb_m2l(c)) ? f.Kmix : f.Kpk;
     if (rb_m2l(c)) return launch_m2l_rb(st, f.p, f.tt, nt, ad, static_cast<const float*>(msrc), out, K, c->zero_row);
     return launch_m2l_tables(st, f.p, c->prm.precision, f.tt, nt, ad, msrc, out, K, c->zero_row);
 }
@@ -1083,7 +1084,7 @@ tree_again:
     SCHK(make_tiles(c, f, tt ? tt : 64));
     if (order_mode_of(c, f) != 0 && !f.tiles_host.empty()) {
         const size_t nt = f.tiles_host.size();
-        SCHK(get_mixed_ops(c, f.p, &f.Kmix));
+        if (!rb_m2l(c)) SCHK(get_mixed_ops(c, f.p, &f.Kmix));  // FP32 truncates the order-p set itself
         ACHK(grow(c, f.ordn, f.ordn_cap, (size_t)nn * NCLASS, false));
         ACHK(grow(c, f.tq, f.tq_cap, 189 * nt, false));
         ACHK(grow(c, f.ocnt, f.ocnt_cap, (size_t)11 * 189 * nt, false));

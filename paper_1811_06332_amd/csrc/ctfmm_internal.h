@@ -131,7 +131,9 @@ struct ASys {
 // ivord[189 t + j] (<= the kernel order P), using the operators of that
 // order at Kpk + order * kord_stride (each order's set in the order-P chunk
 // layout, of which the first nup[order] chunks are non-zero; the launcher
-// fills nup).  acc adds to L instead of writing it.
+// fills nup); the FP32 kernel (launch_m2l_rb) instead takes the order-P set
+// and truncates it per offset in registers.  acc adds to L instead of
+// writing it.
 struct AdaptM2L {
     const int4* tiles;
     const int32_t* tgt;

@@ -493,6 +493,10 @@ struct Tile {
     // the order-q operator are then a prefix, nup(q) long, of every offset's
     // fragments, whatever q <= P.
     static constexpr int minord(int r, int c) { return rank_ce(16 * r) + rank_ce(KW * c); }
+    // largest total rank of the chunk's entries (its padding is zero anyway)
+    static constexpr int maxord(int r, int c) {
+        return rank_ce(16 * r + 15 < NC ? 16 * r + 15 : NC - 1) + rank_ce(KW * c + KW - 1 < NC ? KW * c + KW - 1 : NC - 1);
+    }
     struct PosTab {
         int v[R][NB > 0 ? NB : 1];
         int nup[P + 1];
@@ -950,7 +954,11 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
 // the waves).  Per offset, a wave first reads its A fragments from LDS, then
 // issues the copies of the next K_v, the loads of the next B fragments and
 // the row-table loads of the offset after, then the MFMAs; every load of the
-// iteration is waited for at its end.
+// iteration is waited for at its end.  With an order q per offset (ORD), the
+// order-P operators are used: only the chunks of the order-q prefix are
+// copied, and in the chunks that straddle the truncation each lane zeroes its
+// entries of rank(n) + rank(j) > q in registers (one operator set for every
+// order keeps the operators' cache footprint that of the fixed order).
 template <int P, int NW, bool ORD = false>
 __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M32k, double* __restrict__ L,
                                                     const unsigned char* __restrict__ Kpk,
@@ -986,7 +994,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     // K_v of operator slot ks at order q: every chunk (fixed order) or the
     // first nup[q] (the others are zero)
     auto stage_k = [&](int q, int ks, int buf) {
-        const unsigned char* src = Kpk + (ORD ? (size_t)q * ad.kord_stride : 0) + (size_t)ks * S::KBYTES;
+        const unsigned char* src = Kpk + (size_t)ks * S::KBYTES;
         const int ku = ORD ? ad.nup[q] * CU : KU;
         for (int i = w; i * 64 < ku; i += NW) {
             const int u = i * 64 + lane;
@@ -994,6 +1002,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
         }
     };
     const int kq = lane >> 4;
+    // ranks of this lane's operator rows (16 r + lane % 16) for the truncation
+    int rrow[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rrow[r] = (int)sqrtf((float)(16 * r + (lane & 15)));
     // table entry of (offset 0, this lane's target slot 16 w + n)
     const size_t tab0 = 189 * (size_t)work * TT + 16 * w + (lane & 15);
     auto row_of = [&](int iv) { return ad.src[tab0 + (size_t)iv * TT]; };
@@ -1020,14 +1032,13 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     __syncthreads();
     for (int j = 0; j < nv; ++j) {
         const float* Kf = reinterpret_cast<const float*>(Kb[j & 1]);
-        // this offset's order (wave-uniform) and the chunks it needs
+        // this offset's order (wave-uniform).  Every chunk is read (an early
+        // exit here would put apre in scratch memory); those past the order's
+        // prefix hold stale data that no MFMA below uses (a chunk's position
+        // is below nup[q] exactly when minord <= q)
         const int qj = ORD ? __builtin_amdgcn_readfirstlane((int)s_q[ORD ? j : 0]) : P;
-        const int nupj = ORD ? ad.nup[qj] : NCH;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            if (ORD && ch >= nupj) break;
-            apre[ch] = Kf[ch * 64 + lane];
-        }
+        for (int ch = 0; ch < NCH; ++ch) apre[ch] = Kf[ch * 64 + lane];
         // table entries of the next offsets, read before any copy is issued
         const int j1 = j + 1 < nv ? j + 1 : 0;
         const int ks1 = s_ks[j1];
@@ -1043,11 +1054,15 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
             if (ORD && S::minord(0, c) > qj) break;
+            // rank of this lane's source component 4 c + kq
+            const int rcol = ORD ? (int)sqrtf((float)(4 * c + kq)) : 0;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (c < S::nch(r) && (!ORD || S::minord(r, c) <= qj))
-                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(apre[S::pos(r, c)], bcur[c], acc[r][c & 1],
-                                                                         0, 0, 0);
+                if (c < S::nch(r) && (!ORD || S::minord(r, c) <= qj)) {
+                    float a = apre[S::pos(r, c)];
+                    if (ORD && S::maxord(r, c) > qj && rrow[r] + rcol > qj) a = 0.f;
+                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bcur[c], acc[r][c & 1], 0, 0, 0);
+                }
         }
         // every load of the iteration is waited for here (on every path); the
         // scheduling barrier keeps the MFMAs above the wait
