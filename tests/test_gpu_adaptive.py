@@ -192,14 +192,18 @@ def test_adaptive_mixed_precision_force_error(precision, p):
 
 def test_config1_fullsize_sampled():
     """Plummer N = 2^20, p = 8, leaf <= 64, in the launch configuration the
-    benchmark times: FP64 against the oracle on sampled particles (the oracle's
-    upward pass is complete; its downward pass covers the sampled leaves'
-    paths), and the lists' sizes against the oracle's exactly."""
+    benchmark times, in FP64, FP32 (the headline mode) and BF16x3, against the
+    oracle on sampled particles (the oracle's upward pass is complete; its
+    downward pass covers the sampled leaves' paths): FP64 within 1e-12
+    normwise and 1e-10 per particle, the mixed modes within a relative force
+    error of 1e-6; and the lists' sizes against the oracle's exactly."""
     cfg = W.CONFIGS[1]
     xyz, q = W.make(cfg)
     n = len(q)
     print(f"[case] config1 fullsize n={n}", flush=True)
-    pg, gg, st = gpu_adaptive(xyz, q, cfg["p"], cfg["leaf_max"])
+    res = {prec: gpu_adaptive(xyz, q, cfg["p"], cfg["leaf_max"], precision=prec)
+           for prec in ("fp64", "fp32", "bf16x3")}
+    pg, gg, st = res["fp64"]
     rng = np.random.default_rng(78)
     idx = np.unique(np.concatenate([rng.choice(n, 46, replace=False), [0, n - 1]]))
     print(f"[case] oracle on {len(idx)} sampled particles", flush=True)
@@ -210,8 +214,15 @@ def test_config1_fullsize_sampled():
     print(f"[case] gpu lists {got}", flush=True)
     assert got == {k: info[k] for k in got}
     eP, eF = rel(pg[idx], po), rel(gg[idx], go)
-    print(f"[case] e_phi={eP:.3e} e_grad={eF:.3e}", flush=True)
+    print(f"[case] fp64 e_phi={eP:.3e} e_grad={eF:.3e} max {maxrel(gg[idx], go):.3e}", flush=True)
     assert eP <= TOL and eF <= TOL
+    assert maxrel(pg[idx], po) <= MAXREL_FP64 and maxrel(gg[idx], go) <= MAXREL_FP64
+    for prec in ("fp32", "bf16x3"):
+        pm, gm, _ = res[prec]
+        eP, eF = rel(pm[idx], po), rel(gm[idx], go)
+        print(f"[case] {prec} e_phi={eP:.3e} e_grad={eF:.3e} max {maxrel(gm[idx], go):.3e}", flush=True)
+        assert eP <= 1e-6 and eF <= 1e-6
+        assert maxrel(gm[idx], go) <= MAXREL_MIXED
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

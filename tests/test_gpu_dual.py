@@ -199,3 +199,43 @@ def test_dual_f32_entry_point():
     x32, q32 = xyz.astype(np.float32).astype(np.float64), q.astype(np.float32).astype(np.float64)
     po, go = oracle.fmm_dual(x32, q32, 5, 16, 0.5, "mass")
     assert rel(g["grad"], go) < 1e-6 and rel(g["phi"], po) < 1e-6
+
+
+def test_dual_fullsize_properties():
+    """The headline workload (Plummer N = 2^20, p = 8, leaves <= 64) through
+    the dual tree at theta 0.5, as bench.py times it, checked by properties
+    that hold at any size: every directed M2L entry has its reverse; on the
+    exported centres and radii every accepted pair passes the criterion and
+    every direct pair of distinct leaves fails it, and no pair is both; the
+    total force vanishes to rounding; and on sampled particles the error
+    against the direct sum stays at the truncation level."""
+    cfg = W.CONFIGS[1]
+    xyz, q = W.make(cfg)
+    n = len(q)
+    print(f"[case] dual fullsize n={n}", flush=True)
+    g = gpu_dual(xyz, q, cfg["p"], cfg["leaf_max"], 0.5, "geometric", copy=True)
+    d, t = g["dual"], g["tree"]
+    zr, m, pp = d["zr"], d["m2l"].astype(np.int64), d["p2p"].astype(np.int64)
+    nn = len(zr)
+    key, rkey = m[:, 0] * nn + m[:, 1], m[:, 1] * nn + m[:, 0]
+    assert np.array_equal(np.sort(key), np.sort(rkey))
+
+    def mac(a, b):
+        dx, dy, dz = (zr[b, k] - zr[a, k] for k in range(3))
+        return 0.5 * np.sqrt((dx * dx + dy * dy) + dz * dz) > zr[a, 3] + zr[b, 3]
+
+    assert np.all(mac(m[:, 0], m[:, 1]))
+    other = pp[pp[:, 0] != pp[:, 1]]
+    assert not np.any(mac(other[:, 0], other[:, 1]))
+    assert np.all(t["leaf"][pp[:, 0]] == 1) and np.all(t["leaf"][pp[:, 1]] == 1)
+    assert len(np.intersect1d(key, other[:, 0] * nn + other[:, 1])) == 0
+    f = q[:, None] * g["grad"]
+    mom = np.abs(f.sum(0)).max() / np.abs(f).sum()
+    rng = np.random.default_rng(79)
+    idx = np.unique(np.concatenate([rng.choice(n, 62, replace=False), [0, n - 1]]))
+    pd, gd = oracle.direct(xyz, q, targets=idx, nthreads=len(os.sched_getaffinity(0)))
+    eP, eF = rel(g["phi"][idx], pd), rel(g["grad"][idx], gd)
+    print(f"[case] entries {len(m)} direct {len(pp)} momentum {mom:.2e} vs direct: e_phi={eP:.2e} "
+          f"e_grad={eF:.2e}", flush=True)
+    assert mom < 1e-12
+    assert eP < 1e-4 and eF < 1e-3
