@@ -1116,34 +1116,6 @@ void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M
 
 size_t m2p_coef_ld(int p) { return (size_t)ldc_of(p); }
 
-// one source: phi += q/r, grad -= q (x_b - x_a)/r^3; a pair at distance 0
-// (the particle itself, or a coincident one) contributes nothing (no branch:
-// the reciprocal distance is selected to 0)
-// 1/sqrt(x) for x > 0: the hardware estimate y0, refined by the second-order
-// expansion of (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ... with e = 1 - x y0^2.
-// Measured over 2^22 values spread across 2^+-40: the estimate is within
-// 2^-24.2 relative, so the neglected e^3 term is far below double rounding,
-// and the result within 1.25 ulp.  x = 0 gives a NaN, selected away by the caller.
-__device__ inline double rsqrt_pos(double x) {
-    const double y0 = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y0, y0, 1.0);
-    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
-}
-
-// Eq. PhiAB for one pair: potential and gradient at (xb, yb, zb) of the
-// charge src.w at src.xyz; coincident points (the particle itself) add nothing.
-__device__ inline void pair_add_a(double xb, double yb, double zb, double4 src, double& f, double& gx, double& gy,
-                                  double& gz) {
-    const double dx = xb - src.x, dy = yb - src.y, dz = zb - src.z;
-    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const double y = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;  // a select: both sides are computed
-    const double qy = src.w * y;
-    f += qy;
-    const double ir3 = qy * y * y;
-    gx = fma(-ir3, dx, gx);
-    gy = fma(-ir3, dy, gy);
-    gz = fma(-ir3, dz, gz);
-}
 
 
 // Far field of one sorted particle s (one thread each) from the local

@@ -1653,13 +1653,15 @@ ctfmm_status evaluate_uniform(ctfmm_ctx* c, int64_t n, const double* xyz, const 
             evi += 4;
         }
         rec(c, 4);
-        launch_l2p(st, p, ni, box, c->keys_sorted, c->P, Ll(d), c->F);
-        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, c->F, phi, grad, Pd);
+        launch_l2p(st, p, ni, box, c->start, c->keys_sorted, c->P, Ll(d), c->F);
+        if (Pd) launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, c->F, phi, grad, Pd);
+        else launch_p2p_leaves(st, box, c->start, c->P, c->idx_sorted, c->F, phi, grad);
     } else {
         rec(c, 2);
         rec(c, 3);
         rec(c, 4);
-        launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, nullptr, phi, grad, Pd);
+        if (Pd) launch_p2p(st, ni, box, c->keys_sorted, c->start, c->P, c->idx_sorted, nullptr, phi, grad, Pd);
+        else launch_p2p_leaves(st, box, c->start, c->P, c->idx_sorted, nullptr, phi, grad);
     }
     HIPCHK(c, hipGetLastError());
     const int ev_end = NPHASE_EV - 1;

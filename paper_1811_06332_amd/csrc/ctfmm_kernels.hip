@@ -298,26 +298,37 @@ __device__ inline long long xcd_remap(long long b, long long nb) {
     return x * per + (x < rem ? x : rem) + b / 8;
 }
 
-// L2P: one thread per (sorted) particle; the generated straight-line L2P
-// (Eq. L2P: potential and gradient of the degree-p local polynomial at
-// r = (x - z)/h) from its leaf's independent coefficients.  F[s] = far field.
+// L2P of the uniform tree, one workgroup per L2P_LB consecutive leaves: their
+// independent coefficient rows are staged in LDS once, and every particle of
+// those leaves (one thread each, sorted order) evaluates the generated
+// straight-line L2P (Eq. L2P: potential and gradient of the degree-p local
+// polynomial at r = (x - z)/h) reading them there.  F[s] = far field.
+constexpr int L2P_LB = 32;
 template <int P>
-__global__ __launch_bounds__(256) void k_l2p(int n, Box box, const uint32_t* __restrict__ keys,
-                                             const double4* __restrict__ Pt, const double* __restrict__ L,
-                                             double4* __restrict__ F) {
-    const long long s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int n1 = 1 << box.depth;
-    const double h = box.side / (double)n1;
-    const uint32_t key = keys[s];
-    const double4 pt = Pt[s];
-    const double zx = box.lo[0] + ((double)compact3(key) + 0.5) * h;
-    const double zy = box.lo[1] + ((double)compact3(key >> 1) + 0.5) * h;
-    const double zz = box.lo[2] + ((double)compact3(key >> 2) + 0.5) * h;
-    double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    gen_l2p<P>((pt.x - zx) / h, (pt.y - zy) / h, (pt.z - zz) / h, L + (size_t)key * ldm_of(P), f, gx, gy, gz);
+__global__ __launch_bounds__(256) void k_l2p(long long nleaves, Box box, const int32_t* __restrict__ start,
+                                             const uint32_t* __restrict__ keys, const double4* __restrict__ Pt,
+                                             const double* __restrict__ L, double4* __restrict__ F) {
+    constexpr int ldm = ldm_of(P);
+    __shared__ __attribute__((aligned(16))) double Ls[L2P_LB * ldm];
+    const long long c0 = xcd_remap(blockIdx.x, gridDim.x) * L2P_LB;
+    const int nl = (int)min((long long)L2P_LB, nleaves - c0);
+    const int s0 = start[c0], s1 = start[c0 + nl];
+    if (s0 == s1) return;
+    for (int i = threadIdx.x; i < nl * ldm; i += blockDim.x) Ls[i] = L[(size_t)c0 * ldm + i];
+    __syncthreads();
+    const double h = box.side / (double)(1 << box.depth);
     const double ih2 = 1.0 / (h * h);
-    F[s] = make_double4(f / h, gx * ih2, gy * ih2, gz * ih2);
+    for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+        const uint32_t key = keys[s];
+        const double4 pt = Pt[s];
+        const double zx = box.lo[0] + ((double)compact3(key) + 0.5) * h;
+        const double zy = box.lo[1] + ((double)compact3(key >> 1) + 0.5) * h;
+        const double zz = box.lo[2] + ((double)compact3(key >> 2) + 0.5) * h;
+        lds_cdouble* Lp = (lds_cdouble*)(Ls + (size_t)(key - (uint32_t)c0) * ldm);
+        double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        gen_l2p_lds<P>((pt.x - zx) / h, (pt.y - zy) / h, (pt.z - zz) / h, Lp, f, gx, gy, gz);
+        F[s] = make_double4(f / h, gx * ih2, gy * ih2, gz * ih2);
+    }
 }
 
 // One point dipole d at x_s on the target x: potential d.r/|r|^3, r = x - x_s,
@@ -386,12 +397,128 @@ __global__ __launch_bounds__(256) void k_p2p(int n, Box box, const uint32_t* __r
     }
 }
 
-void launch_l2p(hipStream_t s, int p, int n, Box box, const uint32_t* keys, const double4* P, const double* L,
-                double4* F) {
+// P2P of the uniform tree, one wavefront per leaf, after the adaptive tree's
+// k_p2p_leaf: the sources of the 27 adjacent-or-equal leaves (Appendix C near
+// field) are staged in LDS, 64 KS at a time; the leaf's targets go to the
+// lanes in chunks of ntc, the sources of each stage to G = 64/ntc groups
+// (source j to group j mod G), whose sums are added in group order.  The far
+// field F (if given) is added and the outputs written in input order.
+constexpr int UP_KS = 3;
+__global__ __launch_bounds__(64) void k_p2p_uleaf(Box box, const int32_t* __restrict__ start,
+                                                  const double4* __restrict__ Pt, const int32_t* __restrict__ idx,
+                                                  const double4* __restrict__ F, double* __restrict__ phi,
+                                                  double* __restrict__ grad) {
+    constexpr int KS = UP_KS;
+    __shared__ double4 S[64 * KS];
+    double4* red = S;  // the group sums, once the sources are no longer read
+    __shared__ int epb[27], epre[28];
+    const uint32_t c = (uint32_t)xcd_remap(blockIdx.x, gridDim.x);
+    const int b = start[c], e = start[c + 1];
+    if (b == e) return;
+    const int lane = threadIdx.x;
+    const int n1 = 1 << box.depth;
+    const int ix = compact3(c), iy = compact3(c >> 1), iz = compact3(c >> 2);
+    // lane k < 27: the neighbour at offset (k mod 3, k/3 mod 3, k/9) - 1
+    int sz = 0;
+    if (lane < 27) {
+        const int cx = ix + lane % 3 - 1, cy = iy + (lane / 3) % 3 - 1, cz = iz + lane / 9 - 1;
+        int pb = 0;
+        if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) {
+            const uint32_t cn = morton3(cx, cy, cz);
+            pb = start[cn];
+            sz = start[cn + 1] - pb;
+        }
+        epb[lane] = pb;
+    }
+    int incl = sz;  // inclusive scan over the lanes
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    if (lane < 27) epre[lane + 1] = incl;
+    if (lane == 0) epre[0] = 0;
+    __syncthreads();
+    const int tot = epre[27];
+    for (int t0 = b; t0 < e;) {
+        int ntc = min(64, e - t0);
+        if ((64 / ntc) * ntc * 8 < 64 * 7) ntc = 1 << (31 - __builtin_clz(ntc));
+        const int G = 64 / ntc;
+        const int g = lane / ntc, tl = lane % ntc;
+        const bool active = g < G;
+        const int s = t0 + tl;
+        const double4 pt = Pt[s];
+        double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, f2 = 0.0, gx2 = 0.0, gy2 = 0.0, gz2 = 0.0;
+        for (int base = 0; base < tot; base += 64 * KS) {
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                const int j = base + lane + 64 * k;
+                if (j < tot) {
+                    int lo = 0, hi = 27;  // entry with epre[lo] <= j < epre[lo + 1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (epre[mid] <= j) lo = mid; else hi = mid;
+                    }
+                    S[lane + 64 * k] = Pt[epb[lo] + j - epre[lo]];
+                }
+            }
+            __syncthreads();
+            const int cnt = min(64 * KS, tot - base);
+            if (active) {
+                // two independent accumulator chains; the next two sources
+                // are read ahead (indices clamped into the array, values past
+                // cnt unused)
+                constexpr int LIM = 64 * KS - 1;
+                int jj = g;
+                double4 a0 = S[min(jj, LIM)], a1 = S[min(jj + G, LIM)];
+                for (; jj + G < cnt; jj += 2 * G) {
+                    const double4 c0 = a0, c1 = a1;
+                    a0 = S[min(jj + 2 * G, LIM)];
+                    a1 = S[min(jj + 3 * G, LIM)];
+                    pair_add_a(pt.x, pt.y, pt.z, c0, f, gx, gy, gz);
+                    pair_add_a(pt.x, pt.y, pt.z, c1, f2, gx2, gy2, gz2);
+                }
+                if (jj < cnt) pair_add_a(pt.x, pt.y, pt.z, a0, f, gx, gy, gz);
+            }
+            __syncthreads();
+        }
+        red[lane] = make_double4(f + f2, gx + gx2, gy + gy2, gz + gz2);
+        __syncthreads();
+        if (g == 0) {
+            double4 r = F ? F[s] : make_double4(0.0, 0.0, 0.0, 0.0);
+            for (int gg = 0; gg < G; ++gg) {
+                const double4 v = red[tl + ntc * gg];
+                r.x += v.x;
+                r.y += v.y;
+                r.z += v.z;
+                r.w += v.w;
+            }
+            const size_t o = (size_t)idx[s];
+            if (phi) phi[o] = r.x;
+            if (grad) {
+                grad[3 * o] = r.y;
+                grad[3 * o + 1] = r.z;
+                grad[3 * o + 2] = r.w;
+            }
+        }
+        __syncthreads();
+        t0 += ntc;
+    }
+}
+
+void launch_p2p_leaves(hipStream_t s, Box box, const int32_t* start, const double4* P, const int32_t* idx,
+                       const double4* F, double* phi, double* grad) {
+    const long long nleaves = 1ll << (3 * box.depth);
+    hipLaunchKernelGGL(k_p2p_uleaf, dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, idx, F, phi, grad);
+}
+
+void launch_l2p(hipStream_t s, int p, int n, Box box, const int32_t* start, const uint32_t* keys, const double4* P,
+                const double* L, double4* F) {
     if (n <= 0) return;
-    const dim3 grid(cdiv(n, 256)), blk(256);
+    const long long nleaves = 1ll << (3 * box.depth);
+    const dim3 grid((unsigned)((nleaves + L2P_LB - 1) / L2P_LB)), blk(256);
     switch (p) {
-#define CASE(PP) case PP: hipLaunchKernelGGL(k_l2p<PP>, grid, blk, 0, s, n, box, keys, P, L, F); break;
+#define CASE(PP) case PP: hipLaunchKernelGGL(k_l2p<PP>, grid, blk, 0, s, nleaves, box, start, keys, P, L, F); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;

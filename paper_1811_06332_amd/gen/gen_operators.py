@@ -516,6 +516,29 @@ def emit(outdir):
             w("  " + ln)
         w("}")
     w("#undef LD")
+    # the same L2P reading the coefficients from LDS
+    w("typedef __attribute__((address_space(3))) const double lds_cdouble;")
+    w("__device__ __forceinline__ lds_cdouble* gen_launder_lds(lds_cdouble* p) {")
+    w("  unsigned a = (unsigned)(unsigned long long)p;")
+    w('  __asm__ volatile("" : "+v"(a));')
+    w("  return (lds_cdouble*)(unsigned long long)a;")
+    w("}")
+    w("#define LD(j) (Lg[(j)])")
+    for p in range(PMAX + 1):
+        lines, nt = l2p_code(p)
+        lines = [ln.replace("const double* Lg = gen_launder(L);", "lds_cdouble* Lg = gen_launder_lds(L);") for ln in lines]
+        w(f"// L2P at order {p} with the coefficients in LDS")
+        w(f"__device__ static inline void gen_l2p_lds_p{p}(double x, double y, double z, lds_cdouble* __restrict__ L,")
+        w("                                              double& f, double& gx, double& gy, double& gz) {")
+        for ln in lines:
+            w("  " + ln)
+        w("}")
+    w("#undef LD")
+    w("template <int P> __device__ inline void gen_l2p_lds(double x, double y, double z, lds_cdouble* L, double& f,")
+    w("                                                double& gx, double& gy, double& gz);")
+    for p in range(PMAX + 1):
+        w(f"template <> __device__ inline void gen_l2p_lds<{p}>(double x, double y, double z, lds_cdouble* L, double& f, "
+          f"double& gx, double& gy, double& gz) {{ gen_l2p_lds_p{p}(x, y, z, L, f, gx, gy, gz); }}")
     w("template <int P> __device__ inline void gen_l2p(double x, double y, double z, const double* L, double& f,")
     w("                                            double& gx, double& gy, double& gz);")
     for p in range(PMAX + 1):
