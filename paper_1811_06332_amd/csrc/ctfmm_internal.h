@@ -160,17 +160,20 @@ struct AdaptM2L {
 // DIP: the particles also carry point dipoles d_a (Pd, xyz), each a pure
 // dipole (rank-1 moment -d_a) moved from x_a to z by Eq. M2M (Appendix B.1):
 // S_f += -(1/h) sum_i d_{a,i} f_i u_a^(f - e_i).
-template <int PP, bool DIP = false>
+// CH: particles whose power tables are staged at a time (the LDS held per
+// wavefront; small for trees with few particles per leaf).
+template <int PP, bool DIP = false, int CH = 64>
 __device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b, int e,
                                 const double4* __restrict__ P, const DevTables& T, double* __restrict__ Mc,
                                 const double4* __restrict__ Pd = nullptr) {
+    static_assert(CH >= 1 && CH <= 64, "one wavefront stages at most 64 particles");
     const int lane = threadIdx.x;
     constexpr int nc = (PP + 1) * (PP + 1);
     constexpr int nf = (PP + 1) * (PP + 2) * (PP + 3) / 6;
     constexpr int ldm = ldm_of(PP);
-    __shared__ double pw[64][3][PP + 1];
-    __shared__ double qs[64];
-    __shared__ double ds[DIP ? 64 : 1][3];
+    __shared__ double pw[CH][3][PP + 1];
+    __shared__ double qs[CH];
+    __shared__ double ds[DIP ? CH : 1][3];
     __shared__ double S[nf];
     constexpr int FPL = (nf + 63) / 64;  // full components per lane
     double acc[FPL];
@@ -183,8 +186,8 @@ __device__ inline void p2m_cell(double zx, double zy, double zz, double h, int b
         fb[k] = f < nf ? T.full[3 * f + 1] : 0;
         fc[k] = f < nf ? T.full[3 * f + 2] : 0;
     }
-    for (int s0 = b; s0 < e; s0 += 64) {
-        const int cnt = min(64, e - s0);
+    for (int s0 = b; s0 < e; s0 += CH) {
+        const int cnt = min(CH, e - s0);
         if (lane < cnt) {
             const double4 pt = P[s0 + lane];
             const double u[3] = {(zx - pt.x) / h, (zy - pt.y) / h, (zz - pt.z) / h};

@@ -106,7 +106,8 @@ __global__ __launch_bounds__(64) void k_p2m(Box box, const int32_t* __restrict__
     const double zx = box.lo[0] + ((double)compact3(c) + 0.5) * h;
     const double zy = box.lo[1] + ((double)compact3(c >> 1) + 0.5) * h;
     const double zz = box.lo[2] + ((double)compact3(c >> 2) + 0.5) * h;
-    p2m_cell<PP, DIP>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP), Pd);
+    // uniform leaves hold few particles: 16 are staged at a time
+    p2m_cell<PP, DIP, 16>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP), Pd);
 }
 
 void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M,
