@@ -1140,6 +1140,18 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     HIPCHK(c, hipEventRecord(c->side_ev[0], st));
     HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[0], 0));
     launch_p2p_near(c->side[0], f.n, nn, f.tr, f.a_P, f.loff, f.ulist, f.a_Fn);
+    // the X lists need only the particles too: they start on a second side
+    // stream into the last partial-sum slot of M2L (all slots cleared first)
+    const size_t lsz = (size_t)nn * ldm_of(p);
+    const bool x_early = !f.tiles_host.empty() && f.tot_x > 0;
+    if (x_early) {
+        launch_fill0(st, (long long)((f.nchunk + 1) * lsz), f.part);
+        HIPCHK(c, hipEventRecord(c->side_ev[2], st));
+        HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[2], 0));
+        launch_p2l(c->side[1], p, nn, f.boxes, f.tr, f.loff + 2 * n1, f.xlist, f.a_P, c->T,
+                   f.part + (size_t)f.nchunk * lsz);
+        HIPCHK(c, hipEventRecord(c->side_ev[3], c->side[1]));
+    }
     if (f.up_early) {
         HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[6], 0));
         mark(1);
@@ -1172,7 +1184,6 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     // every level at once (it reads only M), the X lists beside it, then L2L
     // top-down.
     const int omode = order_mode_of(c, f);
-    const size_t lsz = (size_t)nn * ldm_of(p);
     bool x_done = false;
     if (!f.tiles_host.empty()) {
         const int nt = (int)f.tiles_host.size();
@@ -1204,8 +1215,8 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             HIPCHK(c, m2l_adaptive(c, f, st, ad, msrc, f.aL));
             mark(9);
         } else {
-            launch_fill0(st, (long long)(slots * lsz), f.part);
-            if (xs) {
+            if (!x_early) launch_fill0(st, (long long)(slots * lsz), f.part);
+            if (xs && !x_early) {
                 HIPCHK(c, hipEventRecord(c->side_ev[2], st));
                 HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[2], 0));
                 launch_p2l(c->side[1], p, nn, f.boxes, f.tr, f.loff + 2 * n1, f.xlist, f.a_P, c->T,

@@ -132,8 +132,7 @@ struct ASys {
 // order at Kpk + order * kord_stride (each order's set in the order-P chunk
 // layout, of which the first nup[order] chunks are non-zero; the launcher
 // fills nup); the FP32 kernel (launch_m2l_rb) instead takes the order-P set
-// and truncates it per offset in registers.  acc adds to L instead of
-// writing it.
+// and truncates it per offset in registers.
 struct AdaptM2L {
     const int4* tiles;
     const int32_t* tgt;
@@ -147,7 +146,9 @@ struct AdaptM2L {
     int nup[11] = {};
     bool acc = false;
     // the offsets of a tile split over nchunk workgroups (balanced, in list
-    // order); chunk c adds into L + c * chunk_stride (nchunk > 1 needs acc)
+    // order); chunk c writes its sums into L + c * chunk_stride.  acc: the
+    // caller has cleared those slots (needed for nchunk > 1; a chunk without
+    // offsets then writes nothing, else it writes zeros)
     int nchunk = 1;
     size_t chunk_stride = 0;
 };

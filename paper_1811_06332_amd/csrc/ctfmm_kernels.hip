@@ -734,6 +734,17 @@ __device__ inline void lds_copy16(const void* g, void* lds) {
     __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
+// Targets of a tile whose chunk has no offsets: with a direct output (no
+// cleared partial-sum slots) their local expansions are written as zeros.
+__device__ inline void m2l_zero_tile(double* __restrict__ L, const AdaptM2L& ad, long long work, int tt, int ldm) {
+    if (ad.acc) return;  // the caller cleared the slot
+    for (int x = threadIdx.x; x < tt; x += blockDim.x) {
+        const long long t = ad.tgt[(size_t)tt * work + x];
+        if (t < 0) continue;
+        for (int k = 0; k < ldm; ++k) L[(size_t)t * ldm + k] = 0.0;
+    }
+}
+
 // ADAPT = true: the work unit is a tile of the adaptive tree (AdaptM2L):
 // targets, sources and the octant come from the tables instead of the
 // uniform grid, and rows are node indices; the tile's offsets are all 189 or
@@ -771,7 +782,10 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     const int nv_all = (ADAPT && ad.ivcnt) ? ad.ivcnt[work] : 189;
     const int j0 = ADAPT ? (int)((long long)nv_all * chunk / ad.nchunk) : 0;
     const int nv = ADAPT ? (int)((long long)nv_all * (chunk + 1) / ad.nchunk) - j0 : 189;
-    if (nv == 0) return;  // nothing to add (only with ad.acc)
+    if (nv == 0) {
+        if (ADAPT) m2l_zero_tile(L, ad, work, TT, LDM);
+        return;
+    }
     auto ivof = [&](int j) -> int {
         return (ADAPT && ad.ivlist) ? (int)ad.ivlist[189 * work + j0 + j] : j0 + j;
     };
@@ -1035,7 +1049,6 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
         if (par >= nparents) return;
         trow_out = par * 8 + o;
     }
-    const bool acc_out = ADAPT && ad.acc;
     double* Lt = L + (ADAPT ? (size_t)chunk * ad.chunk_stride : 0) + (size_t)trow_out * LDM;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1045,10 +1058,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
             const int row0 = 16 * r + (lane >> 4);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (row0 + 4 * j < NC) {
-                    if (acc_out) Lt[row0 + 4 * j] += sacc[j];
-                    else Lt[row0 + 4 * j] = sacc[j];
-                }
+                if (row0 + 4 * j < NC) Lt[row0 + 4 * j] = sacc[j];
         } else {
             // FP32 16x16 accumulator: element j holds row 16r + 4*(lane/16) + j
             const int row0 = 16 * r + 4 * (lane >> 4);
@@ -1062,10 +1072,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
 #pragma unroll
                     for (int k = 0; k < 6; ++k) v += (double)accb[r][k][j];
                 }
-                if (row0 + j < NC) {
-                    if (acc_out) Lt[row0 + j] += v;
-                    else Lt[row0 + j] = v;
-                }
+                if (row0 + j < NC) Lt[row0 + j] = v;
             }
         }
     }
@@ -1110,7 +1117,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     const int nv_all = ad.ivcnt ? ad.ivcnt[work] : 189;
     const int j0 = (int)((long long)nv_all * chunk / ad.nchunk);
     const int nv = (int)((long long)nv_all * (chunk + 1) / ad.nchunk) - j0;
-    if (nv == 0) return;
+    // a chunk without offsets writes zeros (nothing with cleared slots)
+    if (nv == 0 && ad.acc) return;
     const int o = ad.tiles[work].x;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int x = tid; x < nv; x += 64 * NW) {
@@ -1153,8 +1161,9 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
     float bcur[4 * NBL], bnxt[4 * NBL], apre[NCH];
     __syncthreads();  // the tables
-    stage_k(ORD ? (int)s_q[0] : P, s_ks[0], 0);
-    load_b(row_of(s_iv[0]), bcur);
+    // (without offsets: operator slot 0 and the zero row, unused)
+    stage_k(ORD && nv ? (int)s_q[0] : P, nv ? (int)s_ks[0] : 0, 0);
+    load_b(nv ? row_of(s_iv[0]) : -1, bcur);
     int rnxt = nv > 1 ? row_of(s_iv[1]) : -1;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -1211,10 +1220,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const double v = (double)acc[r][0][i] + (double)acc[r][1][i];
-            if (row0 + i < NC) {
-                if (ad.acc) Lt[row0 + i] += v;
-                else Lt[row0 + i] = v;
-            }
+            if (row0 + i < NC) Lt[row0 + i] = v;
         }
     }
 }
