@@ -158,6 +158,7 @@ struct ctfmm_ctx {
     double* Dv = nullptr;  // [NOFF][NIND] derivative tensors of the offsets
     double* Kt = nullptr;  // [NOFF][nc][nc] K_v transposed
     unsigned char* Kpk = nullptr;  // K_v as MFMA A-fragments of the M2L precision
+    float* Kq = nullptr;           // FP32: the same, four chunks of a lane side by side
     unsigned char* Kmix = nullptr; // the operators of every order <= p (per-pair orders)
     int16_t* offlist = nullptr;    // [8][189] offset slots of each target octant
     unsigned char* zero_row = nullptr;  // a zero source row (out-of-domain sources)
@@ -425,6 +426,11 @@ ctfmm_status build_operators(ctfmm_ctx* c) {
     if (!c->Kpk || !c->zero_row) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
     HIPCHK(c, hipMemsetAsync(c->zero_row, 0, zbytes, c->stream));
     launch_pack_k(c->stream, p, prec, c->Kt, c->Kpk, p);
+    if (prec == CTFMM_PREC_FP32) {
+        c->Kq = (float*)dev_alloc(c, m2l_quad_bytes(p));
+        if (!c->Kq) return fail(c, CTFMM_ENOMEM, "operator allocation failed");
+        launch_quad_k(c->stream, p, c->Kpk, c->Kq);
+    }
     HIPCHK(c, hipGetLastError());
     // offsets v of the ws=1 list for a target in octant o: v_d in [-2-o_d, 3-o_d], max|v_d| >= 2
     std::vector<int16_t> off(8 * 189);
@@ -477,7 +483,8 @@ ctfmm_status ensure_workspace(ctfmm_ctx* c, int64_t n) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<void*> keep = {c->tab_blob,      (void*)c->Dv,       (void*)c->Kt,       (void*)c->Kpk,
                                (void*)c->offlist, (void*)c->alist,    (void*)c->zero_row, (void*)c->err_flag,
-                               (void*)c->io[0],   (void*)c->io[1],    (void*)c->io[2],    (void*)c->io[3]};
+                               (void*)c->io[0],   (void*)c->io[1],    (void*)c->io[2],    (void*)c->io[3],
+                               (void*)c->Kq};
     std::vector<void*> rest;
     for (void* p : c->owned) {
         bool k = false;
@@ -1657,7 +1664,7 @@ ctfmm_status evaluate_uniform(ctfmm_ctx* c, int64_t n, const double* xyz, const 
                 msrc = c->M32;
             }
             rec(c, evi + 1);
-            HIPCHK(c, launch_m2l(st, p, c->prm.precision, l, msrc, Ll(l), c->Kpk, c->offlist, c->zero_row));
+            HIPCHK(c, launch_m2l(st, p, c->prm.precision, l, msrc, Ll(l), c->Kpk, c->offlist, c->zero_row, c->Kq));
             rec(c, evi + 2);
             if (l >= 3) launch_l2l(st, p, l - 1, Ll(l - 1), Ll(l), c->T);
             rec(c, evi + 3);

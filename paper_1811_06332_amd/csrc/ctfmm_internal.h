@@ -303,7 +303,12 @@ void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float
 // the k-quad-major FP32 rows read by launch_m2l_rb
 void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, float* M32);
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L,
-                      const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row);
+                      const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row,
+                      const float* Kq = nullptr);
+// FP32 operators with the chunks of a lane four at a time side by side:
+// Kq[slot][chunk / 4][lane][chunk % 4] (chunks past the last are zero)
+size_t m2l_quad_bytes(int p);
+void launch_quad_k(hipStream_t s, int p, const unsigned char* Kpk, float* Kq);
 // M2L of ntiles tiles of tt targets (32, 64 or 128) of the adaptive tree (any
 // precision; rows are node indices)
 hipError_t launch_m2l_tables(hipStream_t s, int p, int prec, int tt, int ntiles, const AdaptM2L& ad, const void* Msrc,

@@ -1243,8 +1243,12 @@ __global__ void k_to_f32_kq(long long ncell, int nc, int ldm, int s32, const dou
 // the sources: for each source octant q the 6x6x6 halo of octant-q cells
 // around the block (parents base-1 .. base+4) is staged in LDS once, and the
 // 27 parent offsets u (v = 2u + q - o, the adjacent ones skipped) are all
-// served from it; only K_v streams per offset, double-buffered in LDS.  189
-// offsets cost 8 halo stagings instead of 189 source stagings.
+// served from it: 189 offsets cost 8 halo stagings instead of 189 source
+// stagings.  K_v does not go through LDS: every wave loads its A fragments
+// straight into registers from the four-chunk layout (16-byte loads), one
+// offset ahead in a second register set, so the offsets need no barrier,
+// only the 8 stagings do; the waves of a workgroup read the same K_v, which
+// the vector L1 cache serves.
 template <int P>
 struct Halo32 {
     using T = Tile<P, PREC_F32>;
@@ -1254,52 +1258,38 @@ struct Halo32 {
     // its per-read address arithmetic costs more than the 2-way conflicts)
     static constexpr int HROWB = T::S32 * 4 + 16;
     static constexpr int HBYTES = 216 * HROWB;
-    static constexpr int NKB = 2;  // a third buffer (prefetch distance 2) measured slower
-    static constexpr int LDS = HBYTES + NKB * T::KBYTES;
 };
 
 template <int P>
 __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __restrict__ M32, double* __restrict__ L,
-                                                    const unsigned char* __restrict__ Kpk,
-                                                    const int16_t* __restrict__ hlist,
-                                                    const unsigned char* __restrict__ zero_row) {
+                                                     const float* __restrict__ Kf, const int16_t* __restrict__ hlist,
+                                                     const unsigned char* __restrict__ zero_row) {
     using S = Tile<P, PREC_F32>;
     using H = Halo32<P>;
-    constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB, U = H::U, NKB = H::NKB, KD = NKB - 1;
-    constexpr int KU = S::KBYTES / 16;
-    constexpr int KI = (KU + 63) / 64;             // copy instructions per K_v (over the 4 waves)
+    constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB, NCH = S::NCH, U = H::U;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    unsigned char* Hb = lds;                       // [216][S32] floats, units rotated
-    unsigned char* Kb = lds + H::HBYTES;           // [NKB][KBYTES]
-
+    unsigned char* Hb = lds;  // [216][S32] floats, rows padded
     const long long work = xcd_remap(blockIdx.x, gridDim.x);
     const int o = (int)(work & 7);
     const long long pb = work >> 3;
-    // 4 waves: wave w owns target tile w and every row tile
     constexpr int NW = 4;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int tt = w;
-    const int np1 = 1 << (level - 1);              // parents per dimension
+    const int np1 = 1 << (level - 1);
     const long long nparents = (long long)np1 * np1 * np1;
     const uint32_t base_m = (uint32_t)(pb * 64);
     const int bx = (int)compact3(base_m), by = (int)compact3(base_m >> 1), bz = (int)compact3(base_m >> 2);
-    const int tloc = tt * 16 + (lane & 15);        // this lane's target slot in the block
+    const int tloc = w * 16 + (lane & 15);
     const int tx = (int)compact3((uint32_t)tloc), ty = (int)compact3((uint32_t)tloc >> 1),
               tz = (int)compact3((uint32_t)tloc >> 2);
     const int kq = lane >> 4;
-    // hlist[o][i] = (q << 5 | u) of the i-th offset, hlist[8*189 + o*189 + i] = K slot of r = -v
-    const int16_t* qu_list = hlist + o * 189;
-    const int16_t* ks_list = hlist + 8 * 189 + o * 189;
-
-    auto stage_k = [&](int vslot, int buf) {
-        const unsigned char* src = Kpk + (size_t)vslot * S::KBYTES;
-        unsigned char* dst = Kb + buf * S::KBYTES;
-        for (int i = w; i < KI; i += NW) {
-            const int u = i * 64 + lane;
-            if (u < KU) lds_copy16(src + (size_t)u * 16, dst + i * 1024);
-        }
-    };
+    // the octant's offset list in LDS (read per offset without a memory wait)
+    __shared__ int16_t qu_list[189], ks_list[189];
+    for (int x = tid; x < 189; x += 64 * NW) {
+        qu_list[x] = hlist[o * 189 + x];
+        ks_list[x] = hlist[8 * 189 + o * 189 + x];
+    }
+    __syncthreads();
     auto stage_halo = [&](int q) {
         int myrow[4];
 #pragma unroll
@@ -1327,19 +1317,28 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
             }
         }
     };
-
+    constexpr int NQ = (NCH + 3) / 4;  // 16-byte loads per lane and offset
+    auto load_a = [&](int iv, float (&a)[4 * NQ]) {
+        const int ks = __builtin_amdgcn_readfirstlane((int)ks_list[iv]);
+        const float4* ka = reinterpret_cast<const float4*>(Kf) + (size_t)ks * (NQ * 64) + lane;
+#pragma unroll
+        for (int g = 0; g < NQ; ++g) {
+            const float4 v = ka[g * 64];
+            a[4 * g] = v.x;
+            a[4 * g + 1] = v.y;
+            a[4 * g + 2] = v.z;
+            a[4 * g + 3] = v.w;
+        }
+    };
     v4f acc[R][2];
     v4f acc0[4];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc0[k] = v4f{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-    for (int j = 0; j < KD; ++j) stage_k(ks_list[j], j);
     int qcur = -1;
-    for (int iv = 0; iv < 189; ++iv) {
-        const int qu = qu_list[iv];
+    auto step = [&](int iv, const float (&a)[4 * NQ], float (&an)[4 * NQ]) {
+        const int qu = __builtin_amdgcn_readfirstlane((int)qu_list[iv]);
         const int q = qu >> 5, u = qu & 31;
         if (q != qcur) {
             __syncthreads();  // every wave is done with the previous halo
@@ -1348,34 +1347,42 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
             __syncthreads();
             qcur = q;
         }
-        // buffer (iv+KD) % NKB was last read at offset iv-1 (followed by a barrier)
-        if (iv + KD < 189) stage_k(ks_list[iv + KD], (iv + KD) % NKB);
-        const float* Kf = reinterpret_cast<const float*>(Kb + (iv % NKB) * S::KBYTES);
+        load_a(iv + 1 < 189 ? iv + 1 : iv, an);  // the next offset's fragments
+        // keep those loads here: otherwise they are sunk to their first use
+        // in the next step, which then waits for them
+        __asm__ volatile("" ::: "memory");
         const int ux = u % 3 - 1, uy = (u / 3) % 3 - 1, uz = u / 9 - 1;
         const int h = (tx + 1 + ux) + 6 * (ty + 1 + uy) + 36 * (tz + 1 + uz);
         const float* Bf = reinterpret_cast<const float*>(Hb + (size_t)h * H::HROWB);
-        // row tile 0 (the longest: all columns) runs on four accumulator chains
+        // all B values of the offset first (one wait, not one per column)
+        float b[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) b[c] = Bf[4 * c + kq];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
-            const float b = Bf[4 * c + kq];
-            acc0[c & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kf[S::pos(0, c) * 64 + lane], b, acc0[c & 3], 0, 0, 0);
+            acc0[c & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[S::pos(0, c)], b[c], acc0[c & 3], 0, 0, 0);
 #pragma unroll
             for (int r = 1; r < R; ++r)
-                if (c < S::nch(r)) {
-                    const float a = Kf[S::pos(r, c) * 64 + lane];
-                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r][c & 1], 0, 0, 0);
-                }
+                if (c < S::nch(r))
+                    acc[r][c & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[S::pos(r, c)], b[c], acc[r][c & 1], 0, 0, 0);
         }
-        // K of offset iv+1 must have landed; K of iv+KD (just issued) may stay in flight
-        __builtin_amdgcn_s_waitcnt(0);  // K of offset iv+1 has landed
-        __syncthreads();
+        // the B reads as one group ahead of the MFMAs (the compiler would
+        // move each read down to its first use and wait for it there)
+        __builtin_amdgcn_sched_group_barrier(0x100, NB, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NCH, 0);
+    };
+    float a0[4 * NQ], a1[4 * NQ];
+    load_a(0, a0);
+    for (int iv = 0; iv < 189; iv += 2) {
+        step(iv, a0, a1);
+        if (iv + 1 >= 189) break;
+        step(iv + 1, a1, a0);
     }
     const long long par = pb * 64 + tloc;
     if (par >= nparents) return;
     double* Lt = L + (size_t)(par * 8 + o) * LDM;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        // FP32 16x16 accumulator: element j holds row 16r + 4*(lane/16) + j
         const int row0 = 16 * r + 4 * (lane >> 4);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1387,19 +1394,20 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
 }
 
 template <int P>
-hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L, const unsigned char* Kpk,
-                           const int16_t* hlist, const unsigned char* zero_row) {
+hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L, const int16_t* hlist,
+                           const unsigned char* zero_row, const float* Kq) {
+    if (!Kq) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_m2l_halo32<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           Halo32<P>::LDS);
+                                           Halo32<P>::HBYTES);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const long long nparents = 1ll << (3 * (level - 1));
     const long long nblk = (nparents + 63) / 64;
-    hipLaunchKernelGGL(k_m2l_halo32<P>, dim3((unsigned)(8 * nblk)), dim3(256), Halo32<P>::LDS, s, level, M32, L, Kpk,
-                       hlist, zero_row);
+    hipLaunchKernelGGL(k_m2l_halo32<P>, dim3((unsigned)(8 * nblk)), dim3(256), Halo32<P>::HBYTES, s, level, M32, L,
+                       Kq, hlist, zero_row);
     return hipGetLastError();
 }
 
@@ -1479,7 +1487,7 @@ size_t m2l_tile_lds_bytes(int p, int prec, int tt) {
 size_t m2l_lds_bytes(int p, int prec) {
     if (prec == PREC_F32) {
         switch (p) {
-#define CASE(PP) case PP: return (size_t)Halo32<PP>::LDS;
+#define CASE(PP) case PP: return (size_t)Halo32<PP>::HBYTES + 1024;
             CTFMM_P_CASES(CASE)
 #undef CASE
             default: return 0;
@@ -1508,13 +1516,49 @@ void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float
     hipLaunchKernelGGL(k_to_f32, dim3(cdiv(ncell * s32, 256)), dim3(256), 0, s, ncell, nc, ldm_of(p), s32, M, M32);
 }
 
+__global__ void k_quad_k(long long total, int nch, int nq, const float* __restrict__ Kf, float* __restrict__ Kq) {
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= total) return;
+    const int j = (int)(gid % 4), lane = (int)((gid / 4) % 64);
+    const long long gq = gid / 256;
+    const int g = (int)(gq % nq);
+    const long long slot = gq / nq;
+    const int ch = 4 * g + j;
+    Kq[gid] = ch < nch ? Kf[(slot * nch + ch) * 64 + lane] : 0.0f;
+}
+
+size_t m2l_quad_bytes(int p) {
+    size_t nch = 0;
+    switch (p) {
+#define CASE(PP) case PP: nch = Tile<PP, PREC_F32>::NCH; break;
+        CTFMM_P_CASES(CASE)
+#undef CASE
+        default: break;
+    }
+    return (size_t)NOFF * ((nch + 3) / 4) * 256 * sizeof(float);
+}
+
+void launch_quad_k(hipStream_t s, int p, const unsigned char* Kpk, float* Kq) {
+    int nch = 0;
+    switch (p) {
+#define CASE(PP) case PP: nch = Tile<PP, PREC_F32>::NCH; break;
+        CTFMM_P_CASES(CASE)
+#undef CASE
+        default: return;
+    }
+    const int nq = (nch + 3) / 4;
+    const long long total = (long long)NOFF * nq * 256;
+    hipLaunchKernelGGL(k_quad_k, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, total, nch, nq,
+                       reinterpret_cast<const float*>(Kpk), Kq);
+}
+
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L, const unsigned char* Kpk,
-                      const int16_t* offlist, const unsigned char* zero_row) {
+                      const int16_t* offlist, const unsigned char* zero_row, const float* Kq) {
     switch (p) {
 #define CASE(PP)                                                                                           \
     case PP:                                                                                               \
         if (prec == PREC_F64) return m2l_tile_impl<PP, PREC_F64>(s, level, Msrc, L, Kpk, offlist, zero_row); \
-        if (prec == PREC_F32) return m2l_halo32_impl<PP>(s, level, (const float*)Msrc, L, Kpk, offlist, zero_row); \
+        if (prec == PREC_F32) return m2l_halo32_impl<PP>(s, level, (const float*)Msrc, L, offlist, zero_row, Kq); \
         return m2l_tile_impl<PP, PREC_BF16X3>(s, level, Msrc, L, Kpk, offlist, zero_row);
         CTFMM_P_CASES(CASE)
 #undef CASE
