@@ -1290,30 +1290,45 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
         ks_list[x] = hlist[8 * 189 + o * 189 + x];
     }
     __syncthreads();
-    auto stage_halo = [&](int q) {
-        int myrow[4];
+    // The halo of octant q is loaded into registers (NHU 16-byte units per
+    // thread) while the previous octant's offsets run, and written to LDS at
+    // the switch.  Cell h of the halo is the octant-q child of parent
+    // (bx-1 + h%6, by-1 + h/6%6, bz-1 + h/36): row 8 morton(parent) + q, or
+    // none outside the grid (hrow = -1).
+    __shared__ int hrow[216];
+    for (int h = tid; h < 216; h += 64 * NW) {
+        const int px = bx - 1 + h % 6, py = by - 1 + (h / 6) % 6, pz = bz - 1 + h / 36;
+        hrow[h] = (px >= 0 && py >= 0 && pz >= 0 && px < np1 && py < np1 && pz < np1) ? (int)(8 * morton3(px, py, pz))
+                                                                                     : -1;
+    }
+    __syncthreads();
+    constexpr int NHU = (216 * U + 64 * NW - 1) / (64 * NW);
+    float hv[4 * NHU];
+    auto load_halo = [&](int q) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r = lane + 64 * k;
-            int row = -1;
-            if (r < 216) {
-                const int px = bx - 1 + r % 6, py = by - 1 + (r / 6) % 6, pz = bz - 1 + r / 36;
-                if (px >= 0 && py >= 0 && pz >= 0 && px < np1 && py < np1 && pz < np1)
-                    row = (int)morton3(2 * px + (q & 1), 2 * py + ((q >> 1) & 1), 2 * pz + ((q >> 2) & 1));
+        for (int k = 0; k < NHU; ++k) {
+            const int unit = k * 64 * NW + tid;
+            if (unit < 216 * U) {
+                const int h = unit / U, uu = unit - h * U;
+                const int row = hrow[h];
+                const float4* g = row >= 0 ? reinterpret_cast<const float4*>(M32 + (size_t)(row + q) * S::S32) + uu
+                                           : reinterpret_cast<const float4*>(zero_row) + uu;
+                const float4 v = *g;
+                hv[4 * k] = v.x;
+                hv[4 * k + 1] = v.y;
+                hv[4 * k + 2] = v.z;
+                hv[4 * k + 3] = v.w;
             }
-            myrow[k] = row;
         }
+    };
+    auto store_halo = [&]() {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            for (int i = w; i < 64 && 64 * k + i < 216; i += NW) {
-                const int h = 64 * k + i;
-                const int row = __builtin_amdgcn_readlane(myrow[k], i);
-                if (lane < U) {
-                    const unsigned char* g = row >= 0 ? reinterpret_cast<const unsigned char*>(M32) +
-                                                            (size_t)row * S::S32 * 4 + lane * 16
-                                                      : zero_row + lane * 16;
-                    lds_copy16(g, Hb + (size_t)h * H::HROWB);
-                }
+        for (int k = 0; k < NHU; ++k) {
+            const int unit = k * 64 * NW + tid;
+            if (unit < 216 * U) {
+                const int h = unit / U, uu = unit - h * U;
+                *reinterpret_cast<float4*>(Hb + (size_t)h * H::HROWB + uu * 16) =
+                    make_float4(hv[4 * k], hv[4 * k + 1], hv[4 * k + 2], hv[4 * k + 3]);
             }
         }
     };
@@ -1342,10 +1357,15 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
         const int q = qu >> 5, u = qu & 31;
         if (q != qcur) {
             __syncthreads();  // every wave is done with the previous halo
-            stage_halo(q);
-            __builtin_amdgcn_s_waitcnt(0);
+            store_halo();
             __syncthreads();
             qcur = q;
+            // the next octant's halo (offsets are grouped by octant) arrives
+            // while this one's offsets run
+            int qn = -1;
+            for (int j = iv + 1; j < 189 && qn < 0; ++j)
+                if ((qu_list[j] >> 5) != q) qn = qu_list[j] >> 5;
+            if (qn >= 0) load_halo(__builtin_amdgcn_readfirstlane(qn));
         }
         load_a(iv + 1 < 189 ? iv + 1 : iv, an);  // the next offset's fragments
         // keep those loads here: otherwise they are sunk to their first use
@@ -1372,6 +1392,7 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
         __builtin_amdgcn_sched_group_barrier(0x008, NCH, 0);
     };
     float a0[4 * NQ], a1[4 * NQ];
+    load_halo(__builtin_amdgcn_readfirstlane((int)qu_list[0] >> 5));
     load_a(0, a0);
     for (int iv = 0; iv < 189; iv += 2) {
         step(iv, a0, a1);
