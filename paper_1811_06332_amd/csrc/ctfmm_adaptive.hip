@@ -226,9 +226,12 @@ __device__ inline uint64_t morton63(double x, double y, double z, const ABox& bo
 
 // keys[i]: the 63-bit Morton key of particle i of its system; k32[i] its top
 // 32 bits (levels 1..10 and two bits of level 11)
+// keys[i] = the 63-bit key, or with composite (several systems) the system
+// index above the top 32 key bits, so that one radix sort orders the
+// particles by system and then by cell down to level 10.
 __global__ void k_keys64(int n, ASys sy, const double* __restrict__ xyz, const ABox* __restrict__ boxes,
                          uint64_t* __restrict__ keys, uint32_t* __restrict__ k32, int32_t* __restrict__ idx,
-                         int* __restrict__ err) {
+                         int* __restrict__ err, int composite) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int sidx = sy.nsys == 1 ? 0 : seg_of(sy.goff, sy.nsys, i);
@@ -237,15 +240,17 @@ __global__ void k_keys64(int n, ASys sy, const double* __restrict__ xyz, const A
     const double x = xyz[3 * gi], y = xyz[3 * gi + 1], z = xyz[3 * gi + 2];
     if (!isfinite(x) || !isfinite(y) || !isfinite(z)) atomicOr(err, 1);
     const uint64_t k = morton63(x, y, z, box);
-    keys[i] = k;
-    k32[i] = (uint32_t)(k >> (3 * AMAX - 32));
+    const uint32_t top = (uint32_t)(k >> (3 * AMAX - 32));
+    keys[i] = composite ? ((uint64_t)sidx << 32) | top : k;
+    k32[i] = top;
     idx[i] = (int32_t)gi;
 }
 
 void launch_keys64(hipStream_t s, int n, const ASys& sy, const double* xyz, const ABox* boxes, uint64_t* keys,
-                   uint32_t* k32, int32_t* idx, int* err) {
+                   uint32_t* k32, int32_t* idx, int* err, bool composite) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_keys64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, xyz, boxes, keys, k32, idx, err);
+    hipLaunchKernelGGL(k_keys64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sy, xyz, boxes, keys, k32, idx, err,
+                       composite ? 1 : 0);
 }
 
 // P and the full key of every sorted position j (the particle idx[j] of its system)
@@ -270,6 +275,17 @@ void launch_gather_keyed(hipStream_t s, int n, const ASys& sy, const int32_t* id
 // *flag |= 1 when some cell of level 10 holds more than leaf_max particles of
 // one system (positions j and j + leaf_max share the 30-bit prefix), i.e. when
 // the tree goes deeper than the 32-bit sort orders
+// the top 32 key bits of the sorted composite keys (system << 32 | bits)
+__global__ void k_low32(int n, const uint64_t* __restrict__ kc, uint32_t* __restrict__ k32s) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) k32s[j] = (uint32_t)kc[j];
+}
+
+void launch_low32(hipStream_t s, int n, const uint64_t* kc, uint32_t* k32s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_low32, dim3(cdiv(n, 256)), dim3(256), 0, s, n, kc, k32s);
+}
+
 __global__ void k_deep_check(int n, ASys sy, const uint32_t* __restrict__ k32s, int leaf_max, int* __restrict__ flag) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j + leaf_max >= n) return;

@@ -909,22 +909,26 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
     } else {
         launch_bbox_systems(st, sy, xyz, f.boxes);
     }
-    launch_keys64(st, n, sy, xyz, f.boxes, f.k64, f.k32, f.a_idx, c->err_flag);
+    launch_keys64(st, n, sy, xyz, f.boxes, f.k64, f.k32, f.a_idx, c->err_flag, f.nsys > 1);
     // The particles are sorted by the top 32 key bits (4 radix passes instead
     // of 8), which orders every cell down to level 10, and the full keys are
-    // recomputed in sorted order.  A tree that goes deeper (some level-10 cell
-    // holds more than leaf_max particles) is detected with the first level's
-    // count; the particles are then sorted on all 63 bits and the tree built
-    // again.
+    // recomputed in sorted order.  Several systems are sorted at once on the
+    // system index above those bits (one radix sort over all particles: a
+    // segmented sort gives each system, up to 500 k particles, to one
+    // workgroup).  A tree that goes deeper (some level-10 cell holds more
+    // than leaf_max particles) is detected with the first level's count; the
+    // particles are then sorted on all 63 bits and the tree built again.
     if (f.nsys == 1) {
         SCHK(cub_run(c, [&](void* t, size_t& b) {
             return hipcub::DeviceRadixSort::SortPairs(t, b, f.k32, f.k32s, f.a_idx, f.a_idxs, n, 0, 32, st);
         }));
     } else {
+        int sbits = 1;
+        while ((1 << sbits) < f.nsys) ++sbits;
         SCHK(cub_run(c, [&](void* t, size_t& b) {
-            return hipcub::DeviceSegmentedRadixSort::SortPairs(t, b, f.k32, f.k32s, f.a_idx, f.a_idxs, n, f.nsys,
-                                                                f.goff, f.goff + 1, 0, 32, st);
+            return hipcub::DeviceRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, 0, 32 + sbits, st);
         }));
+        launch_low32(st, n, f.k64s, f.k32s);
     }
     launch_gather_keyed(st, n, sy, f.a_idxs, xyz, q, f.boxes, f.a_P, f.k64s);
     launch_deep_check(st, n, sy, f.k32s, c->prm.leaf_max, f.deep);
@@ -935,6 +939,8 @@ ctfmm_status build_forest(ctfmm_ctx* c, Forest& f, const double* xyz, const doub
                 return hipcub::DeviceRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n, 0, 3 * AMAX, st);
             }));
         } else {
+            // the full keys again (the first sort's keys held the system index)
+            launch_keys64(st, n, sy, xyz, f.boxes, f.k64, f.k32, f.a_idx, c->err_flag, false);
             SCHK(cub_run(c, [&](void* t, size_t& b) {
                 return hipcub::DeviceSegmentedRadixSort::SortPairs(t, b, f.k64, f.k64s, f.a_idx, f.a_idxs, n,
                                                                     f.nsys, f.goff, f.goff + 1, 0, 3 * AMAX, st);

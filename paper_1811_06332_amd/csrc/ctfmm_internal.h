@@ -324,8 +324,10 @@ void launch_unscale_copy(hipStream_t s, int p, int level, int which, double side
 // ---- adaptive tree launchers (ctfmm_adaptive.hip) ----
 void launch_bbox(hipStream_t s, int n, const double* xyz, double* part, int nparts, double* out);
 void launch_bbox_systems(hipStream_t s, const ASys& sy, const double* xyz, ABox* boxes);
+void launch_low32(hipStream_t s, int n, const uint64_t* kc, uint32_t* k32s);
+// composite: keys = system index << 32 | top 32 key bits (else the 63-bit keys)
 void launch_keys64(hipStream_t s, int n, const ASys& sy, const double* xyz, const ABox* boxes, uint64_t* keys,
-                   uint32_t* k32, int32_t* idx, int* err);
+                   uint32_t* k32, int32_t* idx, int* err, bool composite = false);
 void launch_gather_keyed(hipStream_t s, int n, const ASys& sy, const int32_t* idx, const double* xyz, const double* q,
                          const ABox* boxes, double4* P, uint64_t* keys);
 void launch_deep_check(hipStream_t s, int n, const ASys& sy, const uint32_t* k32s, int leaf_max, int* flag);
