@@ -841,9 +841,12 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
                 out = f.part;
             }
             auto run = [&]() -> ctfmm_status {
-                if (slots > 1) launch_fill0(c->stream, (long long)(slots * lsz), f.part);
+                // only the X-list slot is added into; the M2L chunks write theirs
+                if (slots > nchunk) launch_fill0(c->stream, (long long)lsz, f.part + (size_t)nchunk * lsz);
                 HIPCHK(c, m2l_adaptive(c, f, c->stream, ad, msrc, out));
-                if (slots > 1) launch_sum_chunks(c->stream, slots, lsz, f.part, f.aL);
+                if (slots > 1)
+                    launch_sum_chunks(c->stream, slots, lsz, f.part, f.aL, (f.p + 1) * (f.p + 1), ldm_of(f.p),
+                                      f.lev_first.size() > 2 ? f.lev_first[2] : 0);
                 return CTFMM_OK;
             };
             SCHK(run());
@@ -1158,7 +1161,7 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     const size_t lsz = (size_t)nn * ldm_of(p);
     const bool x_early = !f.tiles_host.empty() && f.tot_x > 0;
     if (x_early) {
-        launch_fill0(st, (long long)((f.nchunk + 1) * lsz), f.part);
+        launch_fill0(st, (long long)lsz, f.part + (size_t)f.nchunk * lsz);
         HIPCHK(c, hipEventRecord(c->side_ev[2], st));
         HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[2], 0));
         launch_p2l(c->side[1], p, nn, f.boxes, f.tr, f.loff + 2 * n1, f.xlist, f.a_P, c->T,
@@ -1228,7 +1231,7 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             HIPCHK(c, m2l_adaptive(c, f, st, ad, msrc, f.aL));
             mark(9);
         } else {
-            if (!x_early) launch_fill0(st, (long long)(slots * lsz), f.part);
+            if (xs && !x_early) launch_fill0(st, (long long)lsz, f.part + (size_t)f.nchunk * lsz);
             if (xs && !x_early) {
                 HIPCHK(c, hipEventRecord(c->side_ev[2], st));
                 HIPCHK(c, hipStreamWaitEvent(c->side[1], c->side_ev[2], 0));
@@ -1243,7 +1246,7 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
             HIPCHK(c, m2l_adaptive(c, f, st, ad, msrc, f.part));
             mark(9);
             if (xs) HIPCHK(c, hipStreamWaitEvent(st, c->side_ev[3], 0));
-            launch_sum_chunks(st, slots, lsz, f.part, f.aL);
+            launch_sum_chunks(st, slots, lsz, f.part, f.aL, (p + 1) * (p + 1), ldm_of(p), f.lev_first[2]);
         }
         x_done = true;
     } else {

@@ -146,9 +146,10 @@ struct AdaptM2L {
     int nup[11] = {};
     bool acc = false;
     // the offsets of a tile split over nchunk workgroups (balanced, in list
-    // order); chunk c writes its sums into L + c * chunk_stride.  acc: the
-    // caller has cleared those slots (needed for nchunk > 1; a chunk without
-    // offsets then writes nothing, else it writes zeros)
+    // order); chunk c writes the first (p+1)^2 entries of its targets' rows
+    // into L + c * chunk_stride (zeros if it has no offsets); other entries
+    // of a slot are left as they were.  acc: the output is partial-sum slots
+    // (needed for nchunk > 1)
     int nchunk = 1;
     size_t chunk_stride = 0;
 };
@@ -436,6 +437,7 @@ void launch_order_table(hipStream_t s, int count, const int32_t* tab, int8_t* or
 void launch_order_hash(hipStream_t s, int count, const ATree& t, unsigned long long seed, int pmin, int p,
                        int8_t* ord);
 
-void launch_sum_chunks(hipStream_t s, int nchunk, size_t stride, const double* part, double* L);
+void launch_sum_chunks(hipStream_t s, int nslots, size_t stride, const double* part, double* L, int nc, int ldm,
+                       long long row0);
 
 }  // namespace ctfmm

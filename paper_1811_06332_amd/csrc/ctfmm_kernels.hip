@@ -734,10 +734,11 @@ __device__ inline void lds_copy16(const void* g, void* lds) {
     __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-// Targets of a tile whose chunk has no offsets: with a direct output (no
-// cleared partial-sum slots) their local expansions are written as zeros.
-__device__ inline void m2l_zero_tile(double* __restrict__ L, const AdaptM2L& ad, long long work, int tt, int ldm) {
-    if (ad.acc) return;  // the caller cleared the slot
+// Targets of a tile whose chunk has no offsets: their local expansions (in
+// the chunk's slot) are written as zeros.
+__device__ inline void m2l_zero_tile(double* __restrict__ L, const AdaptM2L& ad, long long work, int chunk, int tt,
+                                     int ldm) {
+    L += (size_t)chunk * ad.chunk_stride;
     for (int x = threadIdx.x; x < tt; x += blockDim.x) {
         const long long t = ad.tgt[(size_t)tt * work + x];
         if (t < 0) continue;
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_tile(int level, const void* __r
     const int j0 = ADAPT ? (int)((long long)nv_all * chunk / ad.nchunk) : 0;
     const int nv = ADAPT ? (int)((long long)nv_all * (chunk + 1) / ad.nchunk) - j0 : 189;
     if (nv == 0) {
-        if (ADAPT) m2l_zero_tile(L, ad, work, TT, LDM);
+        if (ADAPT) m2l_zero_tile(L, ad, work, chunk, TT, LDM);
         return;
     }
     auto ivof = [&](int j) -> int {
@@ -1117,8 +1118,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_rb(const float* __restrict__ M3
     const int nv_all = ad.ivcnt ? ad.ivcnt[work] : 189;
     const int j0 = (int)((long long)nv_all * chunk / ad.nchunk);
     const int nv = (int)((long long)nv_all * (chunk + 1) / ad.nchunk) - j0;
-    // a chunk without offsets writes zeros (nothing with cleared slots)
-    if (nv == 0 && ad.acc) return;
+    // (a chunk without offsets runs no offset and writes zeros)
     const int o = ad.tiles[work].x;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int x = tid; x < nv; x += 64 * NW) {
@@ -1597,17 +1597,24 @@ hipError_t m2l_tables_prec(hipStream_t s, int prec, int ntiles, const AdaptM2L& 
     return m2l_tile_impl<P, PREC_BF16X3, true, NW, ORD>(s, 0, ntiles, Msrc, L, Kpk, nullptr, zero_row, ad);
 }
 
-__global__ void k_sum_chunks(int nchunk, size_t stride, const double* __restrict__ part, double* __restrict__ L) {
+// L = the sum of the nslots partial slots, in slot order, over the M2L
+// targets (rows from row0, the first nc of ldm columns); zero elsewhere
+// (the slots hold nothing defined there)
+__global__ void k_sum_chunks(int nslots, size_t stride, const double* __restrict__ part, double* __restrict__ L, int nc,
+                             int ldm, long long row0) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= stride) return;
     double v = 0.0;
-    for (int c = 0; c < nchunk; ++c) v += part[c * stride + i];
+    if ((int)(i % ldm) < nc && (long long)(i / ldm) >= row0)
+        for (int c = 0; c < nslots; ++c) v += part[c * stride + i];
     L[i] = v;
 }
 
-void launch_sum_chunks(hipStream_t s, int nchunk, size_t stride, const double* part, double* L) {
+void launch_sum_chunks(hipStream_t s, int nslots, size_t stride, const double* part, double* L, int nc, int ldm,
+                       long long row0) {
     if (stride == 0) return;
-    hipLaunchKernelGGL(k_sum_chunks, dim3(cdiv((long long)stride, 256)), dim3(256), 0, s, nchunk, stride, part, L);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(cdiv((long long)stride, 256)), dim3(256), 0, s, nslots, stride, part, L, nc,
+                       ldm, row0);
 }
 
 void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, float* M32) {
