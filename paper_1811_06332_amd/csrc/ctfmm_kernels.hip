@@ -110,16 +110,76 @@ __global__ __launch_bounds__(64) void k_p2m(Box box, const int32_t* __restrict__
     p2m_cell<PP, DIP, 16>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP), Pd);
 }
 
+// P2M of the uniform tree without dipoles, one thread per leaf (leaves hold
+// few particles): rank by rank, the full monomial moments S_f = sum_a q_a
+// u_a^f, u = (z - x)/h, |f| = N, are summed in registers and mapped to the
+// rank's independent components by the generated detracer rows (Eq. P2M
+// with Eq. Detracer).  The padding of each row is written as zero.
+template <int P, int N>
+__device__ __forceinline__ void p2m_lane_rank(double zx, double zy, double zz, double h, int b, int e,
+                                              const double4* __restrict__ Pt, double* __restrict__ Mc) {
+    if constexpr (N <= P) {
+        constexpr int NF = (N + 1) * (N + 2) / 2;
+        double S[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) S[k] = 0.0;
+        for (int i = b; i < e; ++i) {
+            const double4 pt = Pt[i];
+            const double ux = (zx - pt.x) / h, uy = (zy - pt.y) / h, uz = (zz - pt.z) / h;
+            double px[N + 1], py[N + 1], pz[N + 1];
+            px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+            for (int k = 1; k <= N; ++k) {
+                px[k] = px[k - 1] * ux;
+                py[k] = py[k - 1] * uy;
+                pz[k] = pz[k - 1] * uz;
+            }
+            int f = 0;  // full-slot order within the rank: x exponent, then y exponent, descending
+#pragma unroll
+            for (int a = N; a >= 0; --a) {
+                const double t = pt.w * px[a];
+#pragma unroll
+                for (int c = N - a; c >= 0; --c) {
+                    S[f] = fma(t * py[c], pz[N - a - c], S[f]);
+                    ++f;
+                }
+            }
+        }
+        double out[2 * N + 1];
+        gen_det_rank<N>(S, out);
+#pragma unroll
+        for (int k = 0; k < 2 * N + 1; ++k) Mc[N * N + k] = out[k];
+        p2m_lane_rank<P, N + 1>(zx, zy, zz, h, b, e, Pt, Mc);
+    }
+}
+
+template <int PP>
+__global__ __launch_bounds__(256) void k_p2m_lane(Box box, const int32_t* __restrict__ start,
+                                                  const double4* __restrict__ P, double* __restrict__ M) {
+    const long long nleaves = 1ll << (3 * box.depth);
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nleaves) return;
+    const double h = box.side / (double)(1 << box.depth);
+    const double zx = box.lo[0] + ((double)compact3((uint32_t)c) + 0.5) * h;
+    const double zy = box.lo[1] + ((double)compact3((uint32_t)c >> 1) + 0.5) * h;
+    const double zz = box.lo[2] + ((double)compact3((uint32_t)c >> 2) + 0.5) * h;
+    double* Mc = M + (size_t)c * ldm_of(PP);
+    p2m_lane_rank<PP, 0>(zx, zy, zz, h, start[c], start[c + 1], P, Mc);
+#pragma unroll
+    for (int k = (PP + 1) * (PP + 1); k < ldm_of(PP); ++k) Mc[k] = 0.0;
+}
+
 void launch_p2m(hipStream_t s, int p, Box box, const int32_t* start, const double4* P, const DevTables& T, double* M,
                 const double4* Pd) {
     const long long nleaves = 1ll << (3 * box.depth);
+    const unsigned nb = (unsigned)cdiv(nleaves, 256);
     switch (p) {
 #define CASE(PP)                                                                                                   \
     case PP:                                                                                                       \
         if (Pd)                                                                                                    \
             hipLaunchKernelGGL((k_p2m<PP, true>), dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, T, M, Pd);  \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_p2m<PP, false>), dim3((unsigned)nleaves), dim3(64), 0, s, box, start, P, T, M, Pd); \
+            hipLaunchKernelGGL((k_p2m_lane<PP>), dim3(nb), dim3(256), 0, s, box, start, P, M);                      \
         break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE

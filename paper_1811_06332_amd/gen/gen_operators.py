@@ -483,6 +483,20 @@ def emit(outdir):
     w(f"static const short GEN_DET_START[{len(starts)}] = {{" + ",".join(map(str, starts)) + "};")
     w(f"static const short GEN_DET_FULL[{len(fs)}] = {{" + ",".join(map(str, fs)) + "};")
     w(f"static const double GEN_DET_COEF[{len(cs)}] = {{" + ",".join(cs) + "};")
+    # the same rows as straight-line code per rank (a thread per cell)
+    w("// P2M detracer rows of one rank N: out[i] = M~ of the i-th independent component of")
+    w("// rank N from S[k], the full monomial moments of rank N in full-slot order")
+    w("template <int N> __device__ __forceinline__ void gen_det_rank(const double* __restrict__ S, double* __restrict__ out);")
+    for N in range(PMAX + 1):
+        f0 = N * (N + 1) * (N + 2) // 6
+        w(f"template <> __device__ __forceinline__ void gen_det_rank<{N}>(const double* __restrict__ S, "
+          f"double* __restrict__ out) {{")
+        for i in range(2 * N + 1):
+            row = DET[N * N + i]
+            assert all(f0 <= f < f0 + (N + 1) * (N + 2) // 2 for f in row)
+            terms = " + ".join(f"{_hexf(row[f])} * S[{f - f0}]" for f in sorted(row))
+            w(f"  out[{i}] = {terms if terms else '0.0'};")
+        w("}")
     # inverse factorials of full components (L2P)
     w("// 1/n! for full slots (L2P weights)")
     w("static const double GEN_INV_MFACT[GEN_NFULL] = {" + ",".join(_hexf(Fraction(1, mfact(m))) for m in FULL) + "};")
