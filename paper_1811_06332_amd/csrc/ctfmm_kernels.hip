@@ -1380,6 +1380,10 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
                 hv[4 * k + 3] = v.w;
             }
         }
+        // the row-table reads first, then the loads (else each load waits
+        // for its own table read)
+        __builtin_amdgcn_sched_group_barrier(0x100, NHU, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, NHU, 0);
     };
     auto store_halo = [&]() {
 #pragma unroll
@@ -1393,8 +1397,7 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
         }
     };
     constexpr int NQ = (NCH + 3) / 4;  // 16-byte loads per lane and offset
-    auto load_a = [&](int iv, float (&a)[4 * NQ]) {
-        const int ks = __builtin_amdgcn_readfirstlane((int)ks_list[iv]);
+    auto load_a = [&](int ks, float (&a)[4 * NQ]) {
         const float4* ka = reinterpret_cast<const float4*>(Kf) + (size_t)ks * (NQ * 64) + lane;
 #pragma unroll
         for (int g = 0; g < NQ; ++g) {
@@ -1412,8 +1415,15 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc0[k] = v4f{0.f, 0.f, 0.f, 0.f};
     int qcur = -1;
+    // list entries read a step ahead (their LDS reads then never wait): the
+    // octant and parent offset of this step's offset, the operator slot of
+    // the next one
+    int qu_c = qu_list[0], ks_n = ks_list[1];
     auto step = [&](int iv, const float (&a)[4 * NQ], float (&an)[4 * NQ]) {
-        const int qu = __builtin_amdgcn_readfirstlane((int)qu_list[iv]);
+        const int qu = __builtin_amdgcn_readfirstlane(qu_c);
+        const int ks1 = __builtin_amdgcn_readfirstlane(ks_n);
+        qu_c = qu_list[iv + 1 < 189 ? iv + 1 : iv];
+        ks_n = ks_list[iv + 2 < 189 ? iv + 2 : 188];
         const int q = qu >> 5, u = qu & 31;
         if (q != qcur) {
             __syncthreads();  // every wave is done with the previous halo
@@ -1427,7 +1437,7 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
                 if ((qu_list[j] >> 5) != q) qn = qu_list[j] >> 5;
             if (qn >= 0) load_halo(__builtin_amdgcn_readfirstlane(qn));
         }
-        load_a(iv + 1 < 189 ? iv + 1 : iv, an);  // the next offset's fragments
+        load_a(ks1, an);  // the next offset's fragments (the last offset's again past the end)
         // keep those loads here: otherwise they are sunk to their first use
         // in the next step, which then waits for them
         __asm__ volatile("" ::: "memory");
@@ -1453,7 +1463,7 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
     };
     float a0[4 * NQ], a1[4 * NQ];
     load_halo(__builtin_amdgcn_readfirstlane((int)qu_list[0] >> 5));
-    load_a(0, a0);
+    load_a(__builtin_amdgcn_readfirstlane((int)ks_list[0]), a0);
     for (int iv = 0; iv < 189; iv += 2) {
         step(iv, a0, a1);
         if (iv + 1 >= 189) break;
