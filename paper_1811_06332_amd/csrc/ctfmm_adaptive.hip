@@ -1088,46 +1088,92 @@ __host__ __device__ constexpr int hpos(int p, int a, int b, int c) {
                          : nfull_of(p - 1) + (p - a) * (p - a + 1) / 2 + (p - a - b);
 }
 
-__global__ void k_m2p_coef(int p, int first, int count, const double* __restrict__ M, DevTables T,
-                           double* __restrict__ Cm) {
-    const int ldc = ldc_of(p);
+// The terms of every coefficient of order P, in row order k: c_k = sum_t
+// coef[t] * M~[slot[t]] over t in [start[k], start[k+1]), with the factor
+// (-1)^n (2n-1)!! / m! folded into coef and the dependent components of M~
+// expanded into independent ones by the trace relation
+// (A_{a,b,2s+t} = (-1)^s sum_i C(s,i) A_{a+2i, b+2(s-i), t}).
+template <int P>
+struct M2PCoefRows {
+    static constexpr int NF = nfull_of(P), NT = NF * (P / 2 + 1);
+    int start[NF + 1];
+    int slot[NT];
+    double coef[NT];
+    static constexpr int ind_slot(int a, int b, int t) {
+        const int n = a + b + t;
+        return t == 0 ? n * n + (n - a) : n * n + (n + 1) + (n - 1 - a);
+    }
+    static constexpr double binom(int n, int k) {
+        double r = 1.0;
+        for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+        return r;
+    }
+    static constexpr M2PCoefRows make() {
+        M2PCoefRows tb{};
+        int at[NF] = {}, bt[NF] = {}, ct[NF] = {};
+        for (int n = 0; n <= P; ++n)
+            for (int a = 0; a <= n; ++a)
+                for (int b = 0; b <= n - a; ++b) {
+                    const int k = hpos(P, a, b, n - a - b);
+                    at[k] = a;
+                    bt[k] = b;
+                    ct[k] = n - a - b;
+                }
+        int t = 0;
+        for (int k = 0; k < NF; ++k) {
+            tb.start[k] = t;
+            const int a = at[k], b = bt[k], c = ct[k], n = a + b + c;
+            double w = 1.0;  // (-1)^n (2n-1)!! / (a! b! c!)
+            for (int i = 1; i <= n; ++i) w *= -(double)(2 * i - 1);
+            for (int i = 2; i <= a; ++i) w /= i;
+            for (int i = 2; i <= b; ++i) w /= i;
+            for (int i = 2; i <= c; ++i) w /= i;
+            const int sh = c / 2, tz = c % 2;
+            for (int i = 0; i <= sh; ++i) {
+                tb.slot[t] = ind_slot(a + 2 * i, b + 2 * (sh - i), tz);
+                tb.coef[t] = w * (sh % 2 ? -1.0 : 1.0) * binom(sh, i);
+                ++t;
+            }
+        }
+        tb.start[NF] = t;
+        return tb;
+    }
+};
+template <int P>
+struct M2PCoefTab {
+    static constexpr int NF = M2PCoefRows<P>::NF;
+    static constexpr M2PCoefRows<P> tab = M2PCoefRows<P>::make();
+};
+
+template <int P>
+__global__ void k_m2p_coef(int first, int count, const double* __restrict__ M, double* __restrict__ Cm) {
+    using TB = M2PCoefTab<P>;
+    constexpr int ldc = ldc_of(P);
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (long long)count * ldc) return;
     const int k = (int)(gid % ldc);
     const size_t row = (size_t)first + gid / ldc;
     double v = 0.0;
-    if (k < nfull_of(p)) {
-        int a = 0, b = 0, c = 0;  // invert hpos
-        const int n1 = nfull_of(p - 1);
-        if (k < n1) {
-            const int d = p - 1;
-            int r = n1 - 1 - k;
-            while (r >= (d - a + 1) * (d - a + 2) / 2) r -= (d - a + 1) * (d - a + 2) / 2, ++a;
-            while (r >= d - a - b + 1) r -= d - a - b + 1, ++b;
-            c = r;
-        } else {
-            const int t = k - n1;
-            int j = 0;
-            while ((j + 1) * (j + 2) / 2 <= t) ++j;
-            a = p - j;
-            b = p - a - (t - j * (j + 1) / 2);
-            c = p - a - b;
-        }
-        const int n = a + b + c;
-        const int f = n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);  // full slot
-        const double* Mr = M + row * ldm_of(p);
-        for (int t = T.exp_start[f]; t < T.exp_start[f + 1]; ++t) v += (double)T.exp_coef[t] * Mr[T.exp_slot[t]];
-        double w = T.inv_mfact[f];
-        for (int i = 1; i <= n; ++i) w *= -(double)(2 * i - 1);
-        v *= w;
+    if (k < TB::NF) {
+        const double* Mr = M + row * ldm_of(P);
+        for (int t = TB::tab.start[k]; t < TB::tab.start[k + 1]; ++t) v += TB::tab.coef[t] * Mr[TB::tab.slot[t]];
     }
     Cm[row * ldc + k] = v;
 }
 
 void launch_m2p_coef(hipStream_t s, int p, int first, int count, const double* M, const DevTables& T, double* Cm) {
+    (void)T;
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_m2p_coef, dim3(cdiv((long long)count * ldc_of(p), 256)), dim3(256), 0, s, p, first, count, M,
-                       T, Cm);
+    switch (p) {
+#define CASE(PP)                                                                                                  \
+    case PP:                                                                                                      \
+        hipLaunchKernelGGL(k_m2p_coef<PP>, dim3(cdiv((long long)count * ldc_of(PP), 256)), dim3(256), 0, s, first, \
+                           count, M, Cm);                                                                         \
+        break;
+        CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+#undef CASE
+        default: break;
+    }
 }
 
 size_t m2p_coef_ld(int p) { return (size_t)ldc_of(p); }
