@@ -1673,9 +1673,12 @@ ctfmm_status evaluate_uniform(ctfmm_ctx* c, int64_t n, const double* xyz, const 
                 msrc = c->M32;
             }
             rec(c, evi + 1);
-            HIPCHK(c, launch_m2l(st, p, c->prm.precision, l, msrc, Ll(l), c->Kpk, c->offlist, c->zero_row, c->Kq));
+            // FP32: the M2L kernel adds the L2L from the parents itself
+            const bool fused = c->prm.precision == CTFMM_PREC_FP32 && l >= 3;
+            HIPCHK(c, launch_m2l(st, p, c->prm.precision, l, msrc, Ll(l), c->Kpk, c->offlist, c->zero_row, c->Kq,
+                                 fused ? Ll(l - 1) : nullptr, c->T.l2l_t));
             rec(c, evi + 2);
-            if (l >= 3) launch_l2l(st, p, l - 1, Ll(l - 1), Ll(l), c->T);
+            if (l >= 3 && !fused) launch_l2l(st, p, l - 1, Ll(l - 1), Ll(l), c->T);
             rec(c, evi + 3);
             evi += 4;
         }

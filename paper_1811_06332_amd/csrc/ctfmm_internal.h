@@ -303,9 +303,11 @@ void launch_pack_k(hipStream_t s, int p, int prec, const double* Kt, unsigned ch
 void launch_to_f32(hipStream_t s, int p, long long ncell, const double* M, float* M32);
 // the k-quad-major FP32 rows read by launch_m2l_rb
 void launch_to_f32_kq(hipStream_t s, int p, long long ncell, const double* M, float* M32);
+// FP32 (Kq given): with Lpar (the parent level's local expansions) the
+// kernel also adds the L2L from the parents and writes L once
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L,
                       const unsigned char* Kpk, const int16_t* offlist, const unsigned char* zero_row,
-                      const float* Kq = nullptr);
+                      const float* Kq = nullptr, const double* Lpar = nullptr, const double* l2l_t = nullptr);
 // FP32 operators with the chunks of a lane four at a time side by side:
 // Kq[slot][chunk / 4][lane][chunk % 4] (chunks past the last are zero)
 size_t m2l_quad_bytes(int p);

@@ -1323,7 +1323,8 @@ struct Halo32 {
 template <int P>
 __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __restrict__ M32, double* __restrict__ L,
                                                      const float* __restrict__ Kf, const int16_t* __restrict__ hlist,
-                                                     const unsigned char* __restrict__ zero_row) {
+                                                     const unsigned char* __restrict__ zero_row,
+                                                     const double* __restrict__ Lpar, const double* __restrict__ l2l_t) {
     using S = Tile<P, PREC_F32>;
     using H = Halo32<P>;
     constexpr int NC = S::NC, LDM = S::LDM, R = S::R, NB = S::NB, NCH = S::NCH, U = H::U;
@@ -1470,23 +1471,70 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
         step(iv + 1, a1, a0);
     }
     const long long par = pb * 64 + tloc;
-    if (par >= nparents) return;
-    double* Lt = L + (size_t)(par * 8 + o) * LDM;
+    auto m2l_sum = [&](int r, int j) {
+        return r == 0 ? ((double)acc0[0][j] + (double)acc0[1][j]) + ((double)acc0[2][j] + (double)acc0[3][j])
+                      : (double)acc[r][0][j] + (double)acc[r][1][j];
+    };
+    if (!Lpar) {
+        if (par >= nparents) return;
+        double* Lt = L + (size_t)(par * 8 + o) * LDM;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row0 = 16 * r + 4 * kq;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (row0 + j < NC) Lt[row0 + j] = m2l_sum(r, j);
+        }
+        return;
+    }
+    // With the parents' local expansions (levels below the first): L2L from
+    // the parent, child L~ += B_o L~_parent (Eq. L2L in scaled form), added
+    // here in FP64 on the matrix cores, so that L is written once.  The
+    // 16x16 FP64 accumulators hold rows 16r + lane/16 + 4j, the FP32 ones
+    // rows 16r + 4 lane/16 + j: the M2L sums go through LDS (the halo's
+    // space, 128 rows per target) into the FP64 layout.  B_o[n][j] vanishes
+    // for rank(j) < rank(n), so row tile r starts at column rank(16 r)^2.
+    static_assert(64 * 16 * R * 8 <= H::HBYTES, "the M2L sums fit the halo's LDS");
+    __syncthreads();  // every wave is done with the halo
+    double* Ls = reinterpret_cast<double*>(Hb) + (size_t)tloc * 16 * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Ls[16 * r + 4 * kq + j] = m2l_sum(r, j);
+    constexpr int NKC = (NC + 3) / 4;
+    const bool valid = par < nparents;
+    const double* lp = Lpar + (size_t)(valid ? par : 0) * LDM;
+    double bp[NKC];
+#pragma unroll
+    for (int c = 0; c < NKC; ++c) bp[c] = (valid && 4 * c + kq < NC) ? lp[4 * c + kq] : 0.0;
+    const double* Bo = l2l_t + (size_t)o * NIND * NIND;
+    double* Lt = L + (size_t)(valid ? par * 8 + o : 0) * LDM;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int row0 = 16 * r + 4 * (lane >> 4);
+        const int n = 16 * r + (lane & 15);
+        v4d a64;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a64[j] = Ls[16 * r + kq + 4 * j];
+        constexpr int C0 = 0;
+        const int c0 = __builtin_amdgcn_readfirstlane(rank_ce(16 * r) * rank_ce(16 * r) / 4);
+#pragma unroll
+        for (int c = C0; c < NKC; ++c) {
+            if (c < c0) continue;
+            const int jj = 4 * c + kq;
+            const double b_ = (n < NC && jj < NC) ? Bo[(size_t)jj * NIND + n] : 0.0;
+            a64 = __builtin_amdgcn_mfma_f64_16x16x4f64(b_, bp[c], a64, 0, 0, 0);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const double v = r == 0 ? ((double)acc0[0][j] + (double)acc0[1][j]) + ((double)acc0[2][j] + (double)acc0[3][j])
-                                    : (double)acc[r][0][j] + (double)acc[r][1][j];
-            if (row0 + j < NC) Lt[row0 + j] = v;
+            const int row = 16 * r + kq + 4 * j;
+            if (valid && row < NC) Lt[row] = a64[j];
         }
     }
 }
 
 template <int P>
 hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L, const int16_t* hlist,
-                           const unsigned char* zero_row, const float* Kq) {
+                           const unsigned char* zero_row, const float* Kq, const double* Lpar, const double* l2l_t) {
     if (!Kq) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
@@ -1498,7 +1546,7 @@ hipError_t m2l_halo32_impl(hipStream_t s, int level, const float* M32, double* L
     const long long nparents = 1ll << (3 * (level - 1));
     const long long nblk = (nparents + 63) / 64;
     hipLaunchKernelGGL(k_m2l_halo32<P>, dim3((unsigned)(8 * nblk)), dim3(256), Halo32<P>::HBYTES, s, level, M32, L,
-                       Kq, hlist, zero_row);
+                       Kq, hlist, zero_row, Lpar, l2l_t);
     return hipGetLastError();
 }
 
@@ -1644,12 +1692,13 @@ void launch_quad_k(hipStream_t s, int p, const unsigned char* Kpk, float* Kq) {
 }
 
 hipError_t launch_m2l(hipStream_t s, int p, int prec, int level, const void* Msrc, double* L, const unsigned char* Kpk,
-                      const int16_t* offlist, const unsigned char* zero_row, const float* Kq) {
+                      const int16_t* offlist, const unsigned char* zero_row, const float* Kq, const double* Lpar,
+                      const double* l2l_t) {
     switch (p) {
 #define CASE(PP)                                                                                           \
     case PP:                                                                                               \
         if (prec == PREC_F64) return m2l_tile_impl<PP, PREC_F64>(s, level, Msrc, L, Kpk, offlist, zero_row); \
-        if (prec == PREC_F32) return m2l_halo32_impl<PP>(s, level, (const float*)Msrc, L, offlist, zero_row, Kq); \
+        if (prec == PREC_F32) return m2l_halo32_impl<PP>(s, level, (const float*)Msrc, L, offlist, zero_row, Kq, Lpar, l2l_t); \
         return m2l_tile_impl<PP, PREC_BF16X3>(s, level, Msrc, L, Kpk, offlist, zero_row);
         CTFMM_P_CASES(CASE)
 #undef CASE
