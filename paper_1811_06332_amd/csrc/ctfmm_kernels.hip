@@ -1509,26 +1509,40 @@ __global__ __launch_bounds__(256) void k_m2l_halo32(int level, const float* __re
     for (int c = 0; c < NKC; ++c) bp[c] = (valid && 4 * c + kq < NC) ? lp[4 * c + kq] : 0.0;
     const double* Bo = l2l_t + (size_t)o * NIND * NIND;
     double* Lt = L + (size_t)(valid ? par * 8 + o : 0) * LDM;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
+    // the operator fragments of row tile r + 1 are loaded while r runs
+    double af0[NKC], af1[NKC];
+    auto load_af = [&](int r, double (&af)[NKC]) {
         const int n = 16 * r + (lane & 15);
+#pragma unroll
+        for (int c = 0; c < NKC; ++c) {
+            const int jj = 4 * c + kq;
+            af[c] = (c >= rank_ce(16 * r) * rank_ce(16 * r) / 4 && n < NC && jj < NC) ? Bo[(size_t)jj * NIND + n] : 0.0;
+        }
+    };
+    auto tile = [&](int r, const double (&af)[NKC]) {
         v4d a64;
 #pragma unroll
         for (int j = 0; j < 4; ++j) a64[j] = Ls[16 * r + kq + 4 * j];
-        constexpr int C0 = 0;
-        const int c0 = __builtin_amdgcn_readfirstlane(rank_ce(16 * r) * rank_ce(16 * r) / 4);
 #pragma unroll
-        for (int c = C0; c < NKC; ++c) {
-            if (c < c0) continue;
-            const int jj = 4 * c + kq;
-            const double b_ = (n < NC && jj < NC) ? Bo[(size_t)jj * NIND + n] : 0.0;
-            a64 = __builtin_amdgcn_mfma_f64_16x16x4f64(b_, bp[c], a64, 0, 0, 0);
-        }
+        for (int c = 0; c < NKC; ++c)
+            if (c >= rank_ce(16 * r) * rank_ce(16 * r) / 4)
+                a64 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c], bp[c], a64, 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int row = 16 * r + kq + 4 * j;
             if (valid && row < NC) Lt[row] = a64[j];
         }
+    };
+    load_af(0, af0);
+#pragma unroll
+    for (int r = 0; r < R; r += 2) {
+        if (r + 1 < R) load_af(r + 1, af1);
+        __asm__ volatile("" ::: "memory");  // (keeps the loads ahead of the MFMAs)
+        tile(r, af0);
+        if (r + 1 >= R) break;
+        if (r + 2 < R) load_af(r + 2, af0);
+        __asm__ volatile("" ::: "memory");
+        tile(r + 1, af1);
     }
 }
 
