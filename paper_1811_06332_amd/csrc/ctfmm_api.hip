@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "ctfmm.h"
@@ -812,9 +813,14 @@ ctfmm_status make_tiles(ctfmm_ctx* c, Forest& f, int tt) {
 // The tile-shape tuner: for every tile size the device's LDS admits (on this
 // forest's own tables) and every split of a tile's offsets over 1 to 4
 // workgroups, times three runs (after a warm-up run) of the M2L launch (at
-// the forest's order) with the clear and the sum of its partial-sum slots,
-// and returns the fastest.  The multipole buffer's contents do not matter
-// for the timing; what it writes is overwritten by the real pass.
+// the forest's order) with the clear and the sum of its partial-sum slots.
+// It returns the smallest tile within 5% of the fastest time (the fastest
+// split for it): the trial launches run alone, while in an evaluation M2L
+// shares the GPU with the near field and the X and W lists, where smaller
+// workgroups fit beside them (Plummer 2^20, p=8: 32 targets 3.66-3.69 ms
+// per step, 64 targets 3.82, with the same time alone).  The multipole
+// buffer's contents do not matter for the timing; what it writes is
+// overwritten by the real pass.
 ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
     const int prec = c->prm.precision;
     int max_lds = 0;
@@ -823,7 +829,7 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
         if (!e) HIPCHK(c, hipEventCreate(&e));
     const void* msrc = prec == CTFMM_PREC_FP64 ? (const void*)f.aM : (const void*)f.aM32;
     const size_t lsz = (size_t)f.nn * ldm_of(f.p);
-    float tbest = 0.f;
+    std::vector<std::array<float, 3>> trials;  // (tile, chunks, ms)
     *best = 32;  // fits wherever the context could be created
     *best_chunks = 0;
     for (int tt : {32, 64, 128}) {
@@ -860,11 +866,20 @@ ctfmm_status tune_tile(ctfmm_ctx* c, Forest& f, int* best, int* best_chunks) {
                 HIPCHK(c, hipEventElapsedTime(&t, c->tev[0], c->tev[1]));
                 ms = rep == 0 ? t : std::min(ms, t);
             }
-            if (tbest == 0.f || ms < tbest) {
-                tbest = ms;
-                *best = tt;
-                *best_chunks = nchunk;
-            }
+            trials.push_back({(float)tt, (float)nchunk, ms});
+        }
+    }
+    float tmin = 0.f;
+    for (const auto& t : trials)
+        if (tmin == 0.f || t[2] < tmin) tmin = t[2];
+    float tsel = 0.f;
+    for (const auto& t : trials) {
+        if (t[2] > 1.05f * tmin) continue;
+        const int tt = (int)t[0];
+        if (*best_chunks == 0 || tt < *best || (tt == *best && t[2] < tsel)) {
+            *best = tt;
+            *best_chunks = (int)t[1];
+            tsel = t[2];
         }
     }
     return CTFMM_OK;
