@@ -9,6 +9,7 @@
 // same at every level (grad^n r^-1 is homogeneous of degree -n-1) and the
 // M2M/L2L shifts are constant per octant.
 #include <math.h>
+#include <algorithm>
 
 #include "ctfmm_internal.h"
 
@@ -359,37 +360,133 @@ __device__ inline long long xcd_remap(long long b, long long nb) {
     return x * per + (x < rem ? x : rem) + b / 8;
 }
 
-// L2P of the uniform tree, one workgroup per L2P_LB consecutive leaves: their
-// independent coefficient rows are staged in LDS once, and every particle of
-// those leaves (one thread each, sorted order) evaluates the generated
-// straight-line L2P (Eq. L2P: potential and gradient of the degree-p local
-// polynomial at r = (x - z)/h) reading them there.  F[s] = far field.
-constexpr int L2P_LB = 32;
+// Workgroup barrier that orders LDS only: global loads in flight stay in
+// flight across it (a full barrier also waits for them).
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// L2P of the uniform tree (Eq. L2P).  A persistent workgroup of L2P_THR
+// threads takes groups of L2P_LB consecutive leaves (g, g + gridDim.x, ...).
+// Per group it writes each leaf's local expansion as the NF coefficients
+// C_n = L_n / n! of a plain polynomial in r = (x - z)/h, in LDS: the
+// independent components scaled into their slots, then the others by the
+// trace condition, pass by pass over n_z (each pass reads slots of the passes
+// before it); then every particle of the group (one thread each, sorted
+// order) evaluates the polynomial and its gradient by nested Horner, one FMA
+// per coefficient and level.  The next group's coefficient rows, leaf range
+// and first particle per thread are loaded while the current one is worked
+// on; the construction tables sit in LDS for the whole launch.  F[s] = far
+// field.
+constexpr int L2P_LB = 32, L2P_THR = 256;
 template <int P>
-__global__ __launch_bounds__(256) void k_l2p(long long nleaves, Box box, const int32_t* __restrict__ start,
-                                             const uint32_t* __restrict__ keys, const double4* __restrict__ Pt,
-                                             const double* __restrict__ L, double4* __restrict__ F) {
-    constexpr int ldm = ldm_of(P);
-    __shared__ __attribute__((aligned(16))) double Ls[L2P_LB * ldm];
-    const long long c0 = xcd_remap(blockIdx.x, gridDim.x) * L2P_LB;
-    const int nl = (int)min((long long)L2P_LB, nleaves - c0);
-    const int s0 = start[c0], s1 = start[c0 + nl];
-    if (s0 == s1) return;
-    for (int i = threadIdx.x; i < nl * ldm; i += blockDim.x) Ls[i] = L[(size_t)c0 * ldm + i];
-    __syncthreads();
-    const double h = box.side / (double)(1 << box.depth);
-    const double ih2 = 1.0 / (h * h);
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
-        const uint32_t key = keys[s];
-        const double4 pt = Pt[s];
-        const double zx = box.lo[0] + ((double)compact3(key) + 0.5) * h;
-        const double zy = box.lo[1] + ((double)compact3(key >> 1) + 0.5) * h;
-        const double zz = box.lo[2] + ((double)compact3(key >> 2) + 0.5) * h;
-        lds_cdouble* Lp = (lds_cdouble*)(Ls + (size_t)(key - (uint32_t)c0) * ldm);
-        double f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-        gen_l2p_lds<P>((pt.x - zx) / h, (pt.y - zy) / h, (pt.z - zz) / h, Lp, f, gx, gy, gz);
-        F[s] = make_double4(f / h, gx * ih2, gy * ih2, gz * ih2);
+__global__ __launch_bounds__(L2P_THR) __attribute__((amdgpu_waves_per_eu(2))) void k_l2p(
+    long long nleaves, Box box, const int32_t* __restrict__ start, const uint32_t* __restrict__ keys,
+    const double4* __restrict__ Pt, const double* __restrict__ L, double4* __restrict__ F) {
+    using T = GenL2PFull<P>;
+    constexpr int ldm = ldm_of(P), NF = T::NF, NI = T::NI, NU = (L2P_LB * NI + L2P_THR - 1) / L2P_THR;
+    constexpr int ND = T::dep_off(T::NPASS) > 0 ? T::dep_off(T::NPASS) : 1;
+    __shared__ __attribute__((aligned(16))) double Cs[L2P_LB * NF];
+    __shared__ double tIW[NI], tDA[ND], tDB[ND];
+    __shared__ unsigned tDD[ND];
+    __shared__ unsigned short tIS[NI];
+    const long long ngroups = (nleaves + L2P_LB - 1) / L2P_LB;
+    long long g = blockIdx.x;
+    if (g >= ngroups) return;
+    for (int i = threadIdx.x; i < NI; i += L2P_THR) {
+        tIS[i] = T::is()[i];
+        tIW[i] = T::iw()[i];
     }
+    for (int i = threadIdx.x; i < T::dep_off(T::NPASS); i += L2P_THR) {
+        tDD[i] = T::dd()[i];
+        tDA[i] = T::da()[i];
+        tDB[i] = T::db()[i];
+    }
+    const int tid0 = (int)threadIdx.x;
+    const double h = box.side / (double)(1 << box.depth);
+    const double ih = 1.0 / h;
+    double lr[NU];
+    int st0, st1;
+    // coefficient rows (NI per leaf, row stride ldm) and leaf range of group gg
+#define L2P_LOAD_GROUP(gg)                                                          \
+    {                                                                               \
+        const long long cc = (gg) * L2P_LB;                                         \
+        const int nn = (int)min((long long)L2P_LB, nleaves - cc);                   \
+        const double* Lg = L + (size_t)cc * ldm;                                    \
+        _Pragma("unroll") for (int u = 0; u < NU; ++u) {                            \
+            const int i = tid + u * L2P_THR;                                        \
+            const int lf = i / NI, j = i - lf * NI;                                 \
+            lr[u] = i < nn * NI ? Lg[(size_t)lf * ldm + j] : 0.0;                   \
+        }                                                                           \
+        st0 = start[cc];                                                            \
+        st1 = start[cc + nn];                                                       \
+    }
+    {
+        const int tid = tid0;
+        L2P_LOAD_GROUP(g);
+    }
+    __syncthreads();
+    uint32_t pkey = 0;
+    double4 ppt = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (st0 + tid0 < st1) {
+        pkey = keys[st0 + tid0];
+        ppt = Pt[st0 + tid0];
+    }
+    for (; g < ngroups; g += gridDim.x) {
+        const long long c0 = g * L2P_LB;
+        const int nl = (int)min((long long)L2P_LB, nleaves - c0);
+        const int s0 = st0, s1 = st1;
+        // recomputed per group: values derived from the thread index alone are
+        // not kept live across the loop (they would not fit in registers)
+        int tid = tid0;
+        __asm__ volatile("" : "+v"(tid));
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int i = tid + u * L2P_THR;
+            if (i < nl * NI) {
+                const int lf = i / NI, j = i - lf * NI;
+                Cs[lf * NF + tIS[j]] = tIW[j] * lr[u];
+            }
+        }
+        const bool more = g + gridDim.x < ngroups;
+        if (more) L2P_LOAD_GROUP(g + gridDim.x);
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < T::NPASS; ++k) {
+            const int e0 = T::dep_off(k), cnt = T::dep_off(k + 1) - e0;
+#pragma unroll
+            for (int u = 0; u < (L2P_LB * cnt + L2P_THR - 1) / L2P_THR; ++u) {
+                const int i = tid + u * L2P_THR;
+                if (i < nl * cnt) {
+                    const int lf = i / cnt, e = e0 + i - lf * cnt;
+                    const unsigned d = tDD[e];
+                    double* C = Cs + lf * NF;
+                    C[d & 1023u] = fma(tDA[e], C[(d >> 10) & 1023u], tDB[e] * C[d >> 20]);
+                }
+            }
+            lds_barrier();
+        }
+        for (int s = s0 + tid; s < s1; s += L2P_THR) {
+            const bool first = s == s0 + tid;
+            const uint32_t key = first ? pkey : keys[s];
+            const double4 pt = first ? ppt : Pt[s];
+            const double zx = box.lo[0] + ((double)compact3(key) + 0.5) * h;
+            const double zy = box.lo[1] + ((double)compact3(key >> 1) + 0.5) * h;
+            const double zz = box.lo[2] + ((double)compact3(key >> 2) + 0.5) * h;
+            lds_cdouble* Cp = (lds_cdouble*)(Cs + (size_t)(key - (uint32_t)c0) * NF);
+            double f, gx, gy, gz;
+            T::eval((pt.x - zx) * ih, (pt.y - zy) * ih, (pt.z - zz) * ih, Cp, f, gx, gy, gz);
+            F[s] = make_double4(f * ih, gx * ih * ih, gy * ih * ih, gz * ih * ih);
+        }
+        if (more && st0 + tid < st1) {
+            pkey = keys[st0 + tid];
+            ppt = Pt[st0 + tid];
+        }
+        lds_barrier();
+    }
+#undef L2P_LOAD_GROUP
 }
 
 // One point dipole d at x_s on the target x: potential d.r/|r|^3, r = x - x_s,
@@ -577,9 +674,22 @@ void launch_l2p(hipStream_t s, int p, int n, Box box, const int32_t* start, cons
                 const double* L, double4* F) {
     if (n <= 0) return;
     const long long nleaves = 1ll << (3 * box.depth);
-    const dim3 grid((unsigned)((nleaves + L2P_LB - 1) / L2P_LB)), blk(256);
+    const long long ngroups = (nleaves + L2P_LB - 1) / L2P_LB;
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    // persistent: as many workgroups as fit on the device at once
+    auto grid_of = [&](const void* k) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, L2P_THR, 0) != hipSuccess || per < 1) per = 1;
+        return dim3((unsigned)std::min<long long>(ngroups, (long long)std::max(ncu, 1) * per));
+    };
+    const dim3 blk(L2P_THR);
     switch (p) {
-#define CASE(PP) case PP: hipLaunchKernelGGL(k_l2p<PP>, grid, blk, 0, s, nleaves, box, start, keys, P, L, F); break;
+#define CASE(PP)                                                                                         \
+    case PP:                                                                                             \
+        hipLaunchKernelGGL(k_l2p<PP>, grid_of((const void*)k_l2p<PP>), blk, 0, s, nleaves, box, start, keys, P, L, F); \
+        break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
 #undef CASE
         default: break;

@@ -400,6 +400,131 @@ def l2p_code(p):
     return lines + out, nterms
 
 
+# ------------------------------------------------------ nested-Horner L2P
+
+def l2p_horner_layout(p):
+    """The full components (a, b, c), |n| <= p, in the order the nested Horner
+    scheme reads them: a descending, then b descending, then c descending."""
+    return [(a, b, c) for a in range(p, -1, -1) for b in range(p - a, -1, -1) for c in range(p - a - b, -1, -1)]
+
+
+def l2p_full_table(p):
+    """For each slot of l2p_horner_layout(p): the polynomial coefficient
+    L_n / n! of the local expansion (Eq. L2P) as {independent slot: weight},
+    the full component L_n written through the independent ones (expand)."""
+    rows = []
+    for m in l2p_horner_layout(p):
+        inv = Fraction(1, mfact(m))
+        rows.append({j: inv * cj for j, cj in sorted(expand(m).items())})
+    return rows
+
+
+def l2p_build_tables(p):
+    """How the kernels build the full coefficients C_n = L_n / n! in Horner
+    order: the independent components (c <= 1) are scaled into their slots,
+    (slot, 1/n!) per independent index; every other component follows from the
+    trace condition L_{a,b,c} = -(L_{a+2,b,c-2} + L_{a,b+2,c-2}), i.e.
+        C_{a,b,c} = alpha C_{a+2,b,c-2} + beta C_{a,b+2,c-2},
+        alpha = -(a+1)(a+2) / (c(c-1)),  beta = -(b+1)(b+2) / (c(c-1)),
+    in passes over c = (2,3), (4,5), ...: each pass reads only slots written
+    before it.  Returns (ind, passes), ind[j] = (slot, weight) and passes a list
+    of [(dst, src1, src2, alpha, beta)]."""
+    lay = l2p_horner_layout(p)
+    pos = {m: i for i, m in enumerate(lay)}
+    ind = [(pos[m], Fraction(1, mfact(m))) for m in IND if rank(m) <= p]
+    passes = []
+    for c0 in range(2, p + 1, 2):
+        ent = []
+        for c in (c0, c0 + 1):
+            for m in lay:
+                if m[2] == c:
+                    a, b, _ = m
+                    ent.append((pos[m], pos[(a + 2, b, c - 2)], pos[(a, b + 2, c - 2)],
+                                Fraction(-(a + 1) * (a + 2), c * (c - 1)), Fraction(-(b + 1) * (b + 2), c * (c - 1))))
+        passes.append(ent)
+    return ind, passes
+
+
+def l2p_horner_ops(p):
+    """Potential and gradient of the degree-p polynomial f(r) = sum_n C_n r^n
+    (C in l2p_horner_layout order) by nested Horner with derivatives:
+        f = sum_a x^a Q_a(y, z),  Q_a = sum_b y^b S_ab(z),  S_ab = sum_c z^c C_abc,
+    each level carrying its value and the derivatives it needs (Horner's rule
+    for a polynomial and its derivative).  Returned as straight-line
+    operations (dst, acc, var, add): dst = acc * var + add, where acc or add
+    None means zero and add may be ("C", k), the k-th coefficient; the
+    results are the names in the final ("out", ...) entry."""
+    ops = []
+    cnt = [0]
+
+    def fma(acc, var, add):
+        if acc is None and add is None:
+            return None
+        if acc is None and isinstance(add, str):
+            return add
+        dst = f"t{cnt[0]}"
+        cnt[0] += 1
+        ops.append((dst, acc, var, add))
+        return dst
+
+    k = 0
+    f = gx = gy = gz = None
+    for a in range(p, -1, -1):
+        q = qy = qz = None
+        for b in range(p - a, -1, -1):
+            s = sz = None
+            for c in range(p - a - b, -1, -1):
+                sz = fma(sz, "z", s)
+                s = fma(s, "z", ("C", k))
+                k += 1
+            qy = fma(qy, "y", q)
+            q = fma(q, "y", s)
+            qz = fma(qz, "y", sz)
+        gx = fma(gx, "x", f)
+        f = fma(f, "x", q)
+        gy = fma(gy, "x", qy)
+        gz = fma(gz, "x", qz)
+    ops.append(("out", f, gx, gy, gz))
+    return ops
+
+
+def l2p_horner_code(p, chunk=32):
+    """C text of l2p_horner_ops(p), the coefficient slot k read as C[k].  The
+    reads are software-pipelined in chunks of `chunk` slots: the reads of chunk
+    i + 1 are issued before the operations that use chunk i, with a scheduling
+    barrier between chunks, so at most two chunks of coefficients are live."""
+    ops = l2p_horner_ops(p)
+    nf = len(l2p_horner_layout(p))
+    chunks = [list(range(k, min(nf, k + chunk))) for k in range(0, nf, chunk)]
+    lines = []
+
+    def loads(i):
+        if i < len(chunks):
+            lines.extend(f"const double c{k} = C[{k}];" for k in chunks[i])
+
+    loads(0)
+    ci = 0
+    lines.append("__builtin_amdgcn_sched_barrier(0);")
+    loads(1)
+    for op in ops[:-1]:
+        dst, acc, var, add = op
+        if isinstance(add, tuple) and add[1] // chunk > ci:
+            ci = add[1] // chunk
+            lines.append("__builtin_amdgcn_sched_barrier(0);")
+            loads(ci + 1)
+        addt = f"c{add[1]}" if isinstance(add, tuple) else add
+        if acc is None:
+            lines.append(f"const double {dst} = {addt};")
+        elif add is None:
+            lines.append(f"const double {dst} = {acc} * {var};")
+        else:
+            lines.append(f"const double {dst} = __builtin_fma({acc}, {var}, {addt});")
+    _, f, gx, gy, gz = ops[-1]
+    for nm, v in (("f", f), ("gx", gx), ("gy", gy), ("gz", gz)):
+        lines.append(f"{nm} = {v if v is not None else '0.0'};")
+    return lines, sum(1 for op in ops[:-1] if op[1] is not None)
+
+
 # ------------------------------------------------------------------ emit
 
 def _hexf(v):
@@ -553,6 +678,45 @@ def emit(outdir):
     for p in range(PMAX + 1):
         w(f"template <> __device__ inline void gen_l2p_lds<{p}>(double x, double y, double z, lds_cdouble* L, double& f, "
           f"double& gx, double& gy, double& gz) {{ gen_l2p_lds_p{p}(x, y, z, L, f, gx, gy, gz); }}")
+    # nested-Horner L2P: the tables that build the full coefficients, and the evaluation
+    w("template <int P> struct GenL2PFull;")
+    w("// Nested-Horner L2P.  The full coefficient array C (Horner order: a, b, c")
+    w("// descending) holds C_n = L_n / n!: independent index j goes to slot IS[j]")
+    w("// times IW[j]; the other slots follow from the trace condition in passes,")
+    w("// entry e: C[dst] = DA[e] C[src1] + DB[e] C[src2], DD[e] = dst | src1 << 10 |")
+    w("// src2 << 20, pass k holding the entries dep_off(k) .. dep_off(k + 1) - 1.")
+    for p in range(PMAX + 1):
+        ind, passes = l2p_build_tables(p)
+        ent = [e for ps in passes for e in ps]
+        offs = [0]
+        for ps in passes:
+            offs.append(offs[-1] + len(ps))
+        w(f"static __device__ const unsigned short gen_l2p_is_p{p}[{len(ind)}] = {{{', '.join(str(s) for s, _ in ind)}}};")
+        w(f"static __device__ const double gen_l2p_iw_p{p}[{len(ind)}] = {{{', '.join(repr(float(v)) for _, v in ind)}}};")
+        nd = max(1, len(ent))
+        dd = [str(d | (s1 << 10) | (s2 << 20)) for d, s1, s2, _, _ in ent] or ["0"]
+        da = [repr(float(a)) for _, _, _, a, _ in ent] or ["0.0"]
+        db = [repr(float(b)) for _, _, _, _, b in ent] or ["0.0"]
+        w(f"static __device__ const unsigned int gen_l2p_dd_p{p}[{nd}] = {{{', '.join(dd)}}};")
+        w(f"static __device__ const double gen_l2p_da_p{p}[{nd}] = {{{', '.join(da)}}};")
+        w(f"static __device__ const double gen_l2p_db_p{p}[{nd}] = {{{', '.join(db)}}};")
+        lines, nf = l2p_horner_code(p)
+        w(f"// L2P at order {p} by nested Horner over the {len(l2p_horner_layout(p))} full coefficients in LDS: {nf} FMAs")
+        w(f"__device__ static inline void gen_l2p_horner_p{p}(double x, double y, double z, lds_cdouble* __restrict__ C,")
+        w("                                                 double& f, double& gx, double& gy, double& gz) {")
+        for ln in lines:
+            w("  " + ln)
+        w("}")
+        w(f"template <> struct GenL2PFull<{p}> {{")
+        w(f"  static constexpr int NF = {len(l2p_horner_layout(p))}, NI = {len(ind)}, NPASS = {len(passes)};")
+        chain = " : ".join(f"k == {k} ? {o}" for k, o in enumerate(offs)) + " : 0"
+        w(f"  __host__ __device__ static constexpr int dep_off(int k) {{ return {chain}; }}")
+        for nm, arr in (("is", "is"), ("iw", "iw"), ("dd", "dd"), ("da", "da"), ("db", "db")):
+            ty = {"is": "unsigned short", "iw": "double", "dd": "unsigned int", "da": "double", "db": "double"}[nm]
+            w(f"  __device__ static const {ty}* {nm}() {{ return gen_l2p_{arr}_p{p}; }}")
+        w(f"  __device__ static void eval(double x, double y, double z, lds_cdouble* C, double& f, double& gx, double& gy,")
+        w(f"                              double& gz) {{ gen_l2p_horner_p{p}(x, y, z, C, f, gx, gy, gz); }}")
+        w("};")
     w("template <int P> __device__ inline void gen_l2p(double x, double y, double z, const double* L, double& f,")
     w("                                            double& gx, double& gy, double& gz);")
     for p in range(PMAX + 1):

@@ -150,12 +150,80 @@ def test_expansion_of_dependent_components_matches_the_trace():
     _close(full, ref)
 
 
+def _build_full(p, Lind):
+    """The full coefficients as the kernels build them (the generated slot
+    table, then the trace-condition passes), in FP64."""
+    ind, passes = G.l2p_build_tables(p)
+    C = [None] * len(G.l2p_horner_layout(p))
+    for j, (slot, w) in enumerate(ind):
+        C[slot] = float(w) * Lind[j]
+    for ps in passes:
+        for d, s1, s2, a, b in ps:
+            assert C[s1] is not None and C[s2] is not None and C[d] is None
+        for d, s1, s2, a, b in ps:
+            C[d] = float(a) * C[s1] + float(b) * C[s2]
+    assert all(c is not None for c in C)
+    return C
+
+
+def _horner_eval(p, Lind, r):
+    """Run the generated nested-Horner L2P (its straight-line operations) on the
+    full coefficients built as the kernels build them."""
+    ops = G.l2p_horner_ops(p)
+    C = _build_full(p, Lind)
+    env = {"x": r[0], "y": r[1], "z": r[2]}
+    val = lambda v: 0.0 if v is None else (C[v[1]] if isinstance(v, tuple) else env[v])
+    for op in ops[:-1]:
+        dst, acc, var, add = op
+        env[dst] = (0.0 if acc is None else env[acc] * env[var]) + val(add)
+    return [val(v) for v in ops[-1][1:]]
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 5, 8, P])
+def test_horner_l2p_matches_oracle_l2p(p):
+    """The nested-Horner L2P (the full coefficients L_n / n! from the generated
+    weights, then the generated Horner operations) gives the oracle's L2P
+    potential and gradient (Eq. L2P) at points of the leaf, h = 1."""
+    rng = np.random.default_rng(500 + p)
+    xyz, q = _cluster(rng, (5.0, -4.0, 3.0), 0.5, 7)
+    M = oracle.p2m(p, (5.0, -4.0, 3.0), xyz, q)
+    Lfull = oracle.m2l(p, (-5.0, 4.0, -3.0), M)
+    Lind = _oracle_ind(Lfull, p)
+    for _ in range(4):
+        r = rng.uniform(-0.5, 0.5, 3)
+        phi, grad = oracle.l2p(p, r, Lfull)
+        got = _horner_eval(p, Lind, r)
+        _close(np.array(got), np.array([phi, *grad]), 1e-12)
+
+
+def test_horner_layout_covers_each_full_component_once():
+    """The Horner order visits every full component of rank <= p exactly once."""
+    for p in range(P + 1):
+        lay = G.l2p_horner_layout(p)
+        assert len(lay) == len(set(lay)) == (p + 1) * (p + 2) * (p + 3) // 6
+        assert all(G.rank(m) <= p for m in lay)
+
+
+@pytest.mark.parametrize("p", [2, 7, P])
+def test_trace_recursion_build_matches_the_direct_expansion(p):
+    """The pass-by-pass build of the full coefficients (slot table plus trace
+    condition) equals L_n / n! with L_n written directly through the
+    independent components (expand), at every slot; each pass reads only slots
+    written before it (checked inside the build)."""
+    rng = np.random.default_rng(600 + p)
+    Lind = rng.normal(size=(p + 1) ** 2)
+    direct = np.array([sum(float(w) * Lind[j] for j, w in row.items()) for row in G.l2p_full_table(p)])
+    _close(np.array(_build_full(p, Lind)), direct, 1e-13)
+
+
 def test_planted_table_mistakes_are_caught(monkeypatch):
     """Each comparison above rejects a small mistake planted in the table it
     checks: one detracer coefficient off by 1e-6, the M2M matrix of the
     opposite octant, the L2L row of one component without its top-rank terms,
-    one M2L contraction term dropped, and a sign flipped in the expansion of a
-    dependent component."""
+    one M2L contraction term dropped, a sign flipped in the expansion of a
+    dependent component, one term dropped from a full coefficient of the
+    Horner L2P, a sign flipped in its trace-condition build, and a y step of
+    its Horner scheme taken in z."""
     from fractions import Fraction
 
     def rejects(fn, *args):
@@ -197,3 +265,37 @@ def test_planted_table_mistakes_are_caught(monkeypatch):
     expand = G.expand
     monkeypatch.setattr(G, "expand", lambda m: {j: -v for j, v in expand(m).items()} if m == (1, 1, 2) else expand(m))
     rejects(test_expansion_of_dependent_components_matches_the_trace)
+    monkeypatch.setattr(G, "expand", expand)
+    table = G.l2p_full_table
+
+    def table_short(p):
+        t = table(p)
+        k = G.l2p_horner_layout(p).index((0, 1, 4))
+        t[k] = dict(list(t[k].items())[:-1])
+        return t
+
+    monkeypatch.setattr(G, "l2p_full_table", table_short)
+    rejects(test_trace_recursion_build_matches_the_direct_expansion, 7)
+    monkeypatch.setattr(G, "l2p_full_table", table)
+    build = G.l2p_build_tables
+
+    def build_wrong_beta(p):
+        ind, passes = build(p)
+        d, s1, s2, a, b = passes[1][3]
+        passes[1][3] = (d, s1, s2, a, -b)
+        return ind, passes
+
+    monkeypatch.setattr(G, "l2p_build_tables", build_wrong_beta)
+    rejects(test_horner_l2p_matches_oracle_l2p, 8)
+    monkeypatch.setattr(G, "l2p_build_tables", build)
+    ops = G.l2p_horner_ops
+
+    def ops_swapped(p):
+        o = ops(p)
+        i = next(i for i, op in enumerate(o) if op[2] == "y" and op[1] is not None)
+        dst, acc, var, add = o[i]
+        o[i] = (dst, acc, "z", add)
+        return o
+
+    monkeypatch.setattr(G, "l2p_horner_ops", ops_swapped)
+    rejects(test_horner_l2p_matches_oracle_l2p, 5)
