@@ -1181,7 +1181,9 @@ size_t m2p_coef_ld(int p) { return (size_t)ldc_of(p); }
 
 
 // Far field of one sorted particle s (one thread each) from the local
-// expansion of its leaf B (Eq. L2P; zero for leaves above level 2), plus its
+// expansion of its leaf B (Eq. L2P, nested Horner over the full polynomial
+// coefficients, each formed from the leaf's independent ones as it is
+// needed; zero for leaves above level 2), plus its
 // near field Fn[s]: the total goes to phi and grad in input order, or with
 // to_F back into F[s].
 template <int P>
@@ -1199,8 +1201,8 @@ __global__ __launch_bounds__(256) void k_l2p_adaptive(int n, const ABox* __restr
         const double4 pt = Pt[s];
         const NodeGeom G = node_geom(boxes, t, B);
         double lf = 0.0, lx = 0.0, ly = 0.0, lz = 0.0;
-        gen_l2p<P>((pt.x - G.zx) / G.h, (pt.y - G.zy) / G.h, (pt.z - G.zz) / G.h, L + (size_t)B * ldm_of(P), lf, lx,
-                   ly, lz);
+        gen_l2p_hg<P>((pt.x - G.zx) / G.h, (pt.y - G.zy) / G.h, (pt.z - G.zz) / G.h, L + (size_t)B * ldm_of(P), lf,
+                      lx, ly, lz);
         const double ih2 = 1.0 / (G.h * G.h);
         out = make_double4(lf / G.h, lx * ih2, ly * ih2, lz * ih2);
     }

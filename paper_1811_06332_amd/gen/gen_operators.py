@@ -525,6 +525,51 @@ def l2p_horner_code(p, chunk=32):
     return lines, sum(1 for op in ops[:-1] if op[1] is not None)
 
 
+def l2p_horner_global_code(p, chunk=24):
+    """Nested-Horner L2P reading the independent coefficients Lt[j] directly
+    (one thread per particle, no staging): each full coefficient of chunk i is
+    formed from its independent components (l2p_full_table) just before the
+    Horner operations that use chunk i - 1 run, through a laundered copy of the
+    pointer per chunk (the reads of one chunk are shared, the chunks' are
+    not kept live)."""
+    ops = l2p_horner_ops(p)
+    table = l2p_full_table(p)
+    nf = len(table)
+    chunks = [list(range(k, min(nf, k + chunk))) for k in range(0, nf, chunk)]
+    lines = []
+
+    def coefs(i):
+        if i < len(chunks):
+            lines.append(f"{{ const double* Lg = gen_launder(L);")
+            for k in chunks[i]:
+                terms = " + ".join(f"({float(w)!r}) * Lg[{j}]" for j, w in sorted(table[k].items()))
+                lines.append(f"  c{k} = {terms};")
+            lines.append("}")
+
+    lines.append("double " + ", ".join(f"c{k}" for k in range(nf)) + ";")
+    coefs(0)
+    ci = 0
+    lines.append("__builtin_amdgcn_sched_barrier(0);")
+    coefs(1)
+    for op in ops[:-1]:
+        dst, acc, var, add = op
+        if isinstance(add, tuple) and add[1] // chunk > ci:
+            ci = add[1] // chunk
+            lines.append("__builtin_amdgcn_sched_barrier(0);")
+            coefs(ci + 1)
+        addt = f"c{add[1]}" if isinstance(add, tuple) else add
+        if acc is None:
+            lines.append(f"const double {dst} = {addt};")
+        elif add is None:
+            lines.append(f"const double {dst} = {acc} * {var};")
+        else:
+            lines.append(f"const double {dst} = __builtin_fma({acc}, {var}, {addt});")
+    _, f, gx, gy, gz = ops[-1]
+    for nm, v in (("f", f), ("gx", gx), ("gy", gy), ("gz", gz)):
+        lines.append(f"{nm} = {v if v is not None else '0.0'};")
+    return lines
+
+
 # ------------------------------------------------------------------ emit
 
 def _hexf(v):
@@ -717,6 +762,18 @@ def emit(outdir):
         w(f"  __device__ static void eval(double x, double y, double z, lds_cdouble* C, double& f, double& gx, double& gy,")
         w(f"                              double& gz) {{ gen_l2p_horner_p{p}(x, y, z, C, f, gx, gy, gz); }}")
         w("};")
+    for p in range(PMAX + 1):
+        w(f"// L2P at order {p} by nested Horner, the full coefficients formed from Lt in global memory")
+        w(f"__device__ static inline void gen_l2p_hg_p{p}(double x, double y, double z, const double* __restrict__ L,")
+        w("                                             double& f, double& gx, double& gy, double& gz) {")
+        for ln in l2p_horner_global_code(p):
+            w("  " + ln)
+        w("}")
+    w("template <int P> __device__ inline void gen_l2p_hg(double x, double y, double z, const double* L, double& f,")
+    w("                                               double& gx, double& gy, double& gz);")
+    for p in range(PMAX + 1):
+        w(f"template <> __device__ inline void gen_l2p_hg<{p}>(double x, double y, double z, const double* L, double& f, "
+          f"double& gx, double& gy, double& gz) {{ gen_l2p_hg_p{p}(x, y, z, L, f, gx, gy, gz); }}")
     w("template <int P> __device__ inline void gen_l2p(double x, double y, double z, const double* L, double& f,")
     w("                                            double& gx, double& gy, double& gz);")
     for p in range(PMAX + 1):
