@@ -648,8 +648,10 @@ void launch_dual_m2l(hipStream_t s, int p, bool ap, int nn, const ATree& t, cons
 // ------------------------------------------------------------------ L2P
 
 // the far field of sorted particle s from its leaf's local expansion (Eq.
-// L2P) plus its near field Fn[s], written in input order; AP: the gradient
-// only (the potential's terms are dead code and phi is not written)
+// L2P, nested Horner over the full polynomial coefficients) plus its near
+// field Fn[s], written in input order; AP: the gradient only (phi is not
+// written; the Horner scheme still carries the potential, which the
+// gradient's recurrences use)
 template <int P, bool AP>
 __global__ __launch_bounds__(256) void k_dual_l2p(int n, ATree t, const int32_t* __restrict__ leaf_of,
                                                   const double4* __restrict__ zr, const double4* __restrict__ Pt,
@@ -667,8 +669,8 @@ __global__ __launch_bounds__(256) void k_dual_l2p(int n, ATree t, const int32_t*
     // (always taken: without the branch the compiler schedules the
     // polynomial's coefficient loads ahead and the kernel spills)
     if (h > 0.0)
-        gen_l2p<P>((pt.x - z.x) * ih, (pt.y - z.y) * ih, (pt.z - z.z) * ih, L + (size_t)B * ldm_of(P), lf, lx, ly,
-                   lz);
+        gen_l2p_hg<P>((pt.x - z.x) * ih, (pt.y - z.y) * ih, (pt.z - z.z) * ih, L + (size_t)B * ldm_of(P), lf, lx,
+                      ly, lz);
     const double ih2 = ih * ih;
     const double4 nf = Fn[s];
     const size_t o = (size_t)idx[s];
