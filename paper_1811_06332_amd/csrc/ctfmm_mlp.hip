@@ -254,88 +254,108 @@ void launch_adam(hipStream_t s, int step, float lr, float* prm, const float* g, 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-// One wavefront per 16 samples.  Every layer is computed transposed,
-// out^T = W in^T, with the 16x16x16 FP16 MFMA (FP32 accumulation): the
-// A operand is a 16x16 block of W (row = output unit, k = input unit), the
-// B operand a 16x16 block of in^T (k = input unit, column = sample).  The
-// accumulator of output block jb holds out^T[16 jb + 4 (lane/16) + e][lane%16],
-// which is exactly the B operand layout of input block jb of the next layer,
-// so the activations never leave registers.  Inputs are standardised
-// ((x - mean) / std) on load when norm is given.
+// Each wavefront takes blocks of 16 samples (block w, w + nwaves, ...).  Every
+// layer is computed transposed, out^T = W in^T, with the 16x16x16 FP16 MFMA
+// (FP32 accumulation): the A operand is a 16x16 block of W (row = output
+// unit, k = input unit), the B operand a 16x16 block of in^T (k = input
+// unit, column = sample).  The accumulator of output block jb holds
+// out^T[16 jb + 4 (lane/16) + e][lane%16], which is exactly the B operand
+// layout of input block jb of the next layer, so the activations never leave
+// registers.  The weights' A blocks, the biases and the standardisation
+// constants are loaded once per wavefront and kept in registers for all its
+// blocks.  Inputs are standardised ((x - mean) / std) on load when norm is
+// given.
 __global__ __launch_bounds__(256) void k_mlp_forward16(long long n, const float* __restrict__ x,
                                                        const float* __restrict__ prm,
                                                        const float* __restrict__ norm, float* __restrict__ y) {
     const int lane = threadIdx.x & 63;
-    const long long base = ((long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * 16;
-    if (base >= n) return;
+    const long long wave = (long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const long long nwaves = (long long)gridDim.x * (blockDim.x / 64);
+    if (wave * 16 >= n) return;
     const int col = lane & 15, kq = lane >> 4;
-    const long long smp = base + col;
-    const bool valid = smp < n;
-    // layer 1: in^T block (k = 4 kq + e, inputs padded from 12 to 16)
-    half4_t bx;
+    half4_t w1[4], w2[4][4], w3[4];
+    float b1[4][4], b2[4][4], b3[4], mu[4], sd[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int k = 4 * kq + e;
-        float v = 0.f;
-        if (valid && k < MLP_NIN) {
-            v = x[smp * MLP_NIN + k];
-            if (norm) v = (v - norm[k]) / norm[MLP_NIN + k];
-        }
-        bx[e] = (_Float16)v;
-    }
-    half4_t h1[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-        half4_t a;
+    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int k = 4 * kq + e;
-            a[e] = (_Float16)(k < MLP_NIN ? prm[OW1 + (16 * jb + col) * MLP_NIN + k] : 0.f);
-        }
-        f4_t acc = {0.f, 0.f, 0.f, 0.f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bx, acc, 0, 0, 0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float z = acc[e] + prm[OB1 + 16 * jb + 4 * kq + e];
-            h1[jb][e] = (_Float16)(z > 0.f ? z : 0.f);
-        }
-    }
-    half4_t h2[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-        f4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            half4_t a;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[e] = (_Float16)prm[OW2 + (16 * jb + col) * MLP_NH + 16 * kb + 4 * kq + e];
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, h1[kb], acc, 0, 0, 0);
+            w1[jb][e] = (_Float16)(k < MLP_NIN ? prm[OW1 + (16 * jb + col) * MLP_NIN + k] : 0.f);
+            b1[jb][e] = prm[OB1 + 16 * jb + 4 * kq + e];
+            b2[jb][e] = prm[OB2 + 16 * jb + 4 * kq + e];
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float z = acc[e] + prm[OB2 + 16 * jb + 4 * kq + e];
-            h2[jb][e] = (_Float16)(z > 0.f ? z : 0.f);
-        }
-    }
-    f4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-        half4_t a;
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w2[jb][kb][e] = (_Float16)prm[OW2 + (16 * jb + col) * MLP_NH + 16 * kb + 4 * kq + e];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            a[e] = (_Float16)(col < MLP_NOUT ? prm[OW3 + col * MLP_NH + 16 * kb + 4 * kq + e] : 0.f);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, h2[kb], acc, 0, 0, 0);
-    }
+            w3[kb][e] = (_Float16)(col < MLP_NOUT ? prm[OW3 + col * MLP_NH + 16 * kb + 4 * kq + e] : 0.f);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int j = 4 * kq + e;
-        if (valid && j < MLP_NOUT) y[smp * MLP_NOUT + j] = acc[e] + prm[OB3 + j];
+        const int j = 4 * kq + e, k = 4 * kq + e;
+        b3[e] = j < MLP_NOUT ? prm[OB3 + j] : 0.f;
+        mu[e] = (norm && k < MLP_NIN) ? norm[k] : 0.f;
+        sd[e] = (norm && k < MLP_NIN) ? norm[MLP_NIN + k] : 1.f;
+    }
+    for (long long base = wave * 16; base < n; base += nwaves * 16) {
+        const long long smp = base + col;
+        const bool valid = smp < n;
+        // layer 1: in^T block (k = 4 kq + e, inputs padded from 12 to 16)
+        half4_t bx;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * kq + e;
+            float v = 0.f;
+            if (valid && k < MLP_NIN) {
+                v = x[smp * MLP_NIN + k];
+                if (norm) v = (v - mu[e]) / sd[e];
+            }
+            bx[e] = (_Float16)v;
+        }
+        half4_t h1[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            f4_t acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[jb], bx, acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float z = acc[e] + b1[jb][e];
+                h1[jb][e] = (_Float16)(z > 0.f ? z : 0.f);
+            }
+        }
+        half4_t h2[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16f16(w2[jb][kb], h1[kb], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float z = acc[e] + b2[jb][e];
+                h2[jb][e] = (_Float16)(z > 0.f ? z : 0.f);
+            }
+        }
+        f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16f16(w3[kb], h2[kb], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * kq + e;
+            if (valid && j < MLP_NOUT) y[smp * MLP_NOUT + j] = acc[e] + b3[e];
+        }
     }
 }
 
 void launch_mlp_forward16(hipStream_t s, long long n, const float* x, const float* prm, const float* norm, float* y) {
     if (n <= 0) return;
-    const long long waves = (n + 15) / 16;
+    // at most 4096 wavefronts (16 per CU), each looping over its blocks
+    const long long blocks = (n + 15) / 16;
+    const long long waves = blocks < 4096 ? blocks : 4096;
     hipLaunchKernelGGL(k_mlp_forward16, dim3(cdiv(waves, 4)), dim3(256), 0, s, n, x, prm, norm, y);
 }
 
