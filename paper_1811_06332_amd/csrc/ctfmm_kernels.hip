@@ -111,49 +111,71 @@ __global__ __launch_bounds__(64) void k_p2m(Box box, const int32_t* __restrict__
     p2m_cell<PP, DIP, 16>(zx, zy, zz, h, start[c], start[c + 1], P, T, M + (size_t)c * ldm_of(PP), Pd);
 }
 
-// P2M of the uniform tree without dipoles, one thread per leaf (leaves hold
-// few particles): rank by rank, the full monomial moments S_f = sum_a q_a
-// u_a^f, u = (z - x)/h, |f| = N, are summed in registers and mapped to the
-// rank's independent components by the generated detracer rows (Eq. P2M
-// with Eq. Detracer).  The padding of each row is written as zero.
-template <int P, int N>
-__device__ __forceinline__ void p2m_lane_rank(double zx, double zy, double zz, double h, int b, int e,
-                                              const double4* __restrict__ Pt, double* __restrict__ Mc) {
-    if constexpr (N <= P) {
-        constexpr int NF = (N + 1) * (N + 2) / 2;
-        double S[NF];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) S[k] = 0.0;
-        for (int i = b; i < e; ++i) {
-            const double4 pt = Pt[i];
-            const double ux = (zx - pt.x) / h, uy = (zy - pt.y) / h, uz = (zz - pt.z) / h;
-            double px[N + 1], py[N + 1], pz[N + 1];
-            px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-            for (int k = 1; k <= N; ++k) {
-                px[k] = px[k - 1] * ux;
-                py[k] = py[k - 1] * uy;
-                pz[k] = pz[k - 1] * uz;
-            }
-            int f = 0;  // full-slot order within the rank: x exponent, then y exponent, descending
-#pragma unroll
-            for (int a = N; a >= 0; --a) {
-                const double t = pt.w * px[a];
-#pragma unroll
-                for (int c = N - a; c >= 0; --c) {
-                    S[f] = fma(t * py[c], pz[N - a - c], S[f]);
-                    ++f;
-                }
-            }
-        }
+// the independent components of ranks N .. N1 from their moments S (rank by
+// rank, each rank's (N+1)(N+2)/2 sums in turn)
+template <int N, int N1>
+__device__ __forceinline__ void p2m_lane_store(const double* S, double* __restrict__ Mc) {
+    if constexpr (N <= N1) {
         double out[2 * N + 1];
         gen_det_rank<N>(S, out);
 #pragma unroll
         for (int k = 0; k < 2 * N + 1; ++k) Mc[N * N + k] = out[k];
-        p2m_lane_rank<P, N + 1>(zx, zy, zz, h, b, e, Pt, Mc);
+        p2m_lane_store<N + 1, N1>(S + (N + 1) * (N + 2) / 2, Mc);
     }
 }
 
+// P2M of the uniform tree without dipoles, one thread per leaf (leaves hold
+// few particles): for a group of ranks N0..N1 at a time, the full monomial
+// moments S_f = sum_a q_a u_a^f, u = (z - x)/h, |f| = N, are summed in
+// registers over one pass through the leaf's particles, and each rank's are
+// mapped to its independent components by the generated detracer rows
+// (Eq. P2M with Eq. Detracer).  A group holds at most 66 sums (rank 10 alone),
+// so p = 10 takes five passes over the particles instead of eleven.  The
+// padding of each row is written as zero.
+__host__ __device__ constexpr int p2m_nf(int n) { return (n + 1) * (n + 2) / 2; }
+__host__ __device__ constexpr int p2m_group_end(int n0, int p) {
+    int n1 = n0, tot = p2m_nf(n0);
+    while (n1 < p && tot + p2m_nf(n1 + 1) <= 66) tot += p2m_nf(++n1);
+    return n1;
+}
+template <int P, int N0>
+__device__ __forceinline__ void p2m_lane_rank(double zx, double zy, double zz, double h, int b, int e,
+                                              const double4* __restrict__ Pt, double* __restrict__ Mc) {
+    if constexpr (N0 <= P) {
+        constexpr int N1 = p2m_group_end(N0, P);
+        constexpr int NS = (N1 + 1) * (N1 + 2) * (N1 + 3) / 6 - N0 * (N0 + 1) * (N0 + 2) / 6;
+        double S[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) S[k] = 0.0;
+        for (int i = b; i < e; ++i) {
+            const double4 pt = Pt[i];
+            const double ux = (zx - pt.x) / h, uy = (zy - pt.y) / h, uz = (zz - pt.z) / h;
+            double px[N1 + 1], py[N1 + 1], pz[N1 + 1];
+            px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+            for (int k = 1; k <= N1; ++k) {
+                px[k] = px[k - 1] * ux;
+                py[k] = py[k - 1] * uy;
+                pz[k] = pz[k - 1] * uz;
+            }
+            // per rank, full-slot order: x exponent, then y exponent, descending
+            int f = 0;
+#pragma unroll
+            for (int N = N0; N <= N1; ++N)
+#pragma unroll
+                for (int a = N; a >= 0; --a) {
+                    const double t = pt.w * px[a];
+#pragma unroll
+                    for (int c = N - a; c >= 0; --c) {
+                        S[f] = fma(t * py[c], pz[N - a - c], S[f]);
+                        ++f;
+                    }
+                }
+        }
+        p2m_lane_store<N0, N1>(S, Mc);
+        p2m_lane_rank<P, N1 + 1>(zx, zy, zz, h, b, e, Pt, Mc);
+    }
+}
 template <int PP>
 __global__ __launch_bounds__(256) void k_p2m_lane(Box box, const int32_t* __restrict__ start,
                                                   const double4* __restrict__ P, double* __restrict__ M) {
