@@ -1197,13 +1197,11 @@ ctfmm_status numeric_forest(ctfmm_ctx* c, Forest& f, double* phi, double* grad, 
     if (maxlev >= 2) {
         const int f2 = f.lev_first[2];
         if (f.tot_w > 0) {
-            // the W lists need only the multipoles: their coefficients and the
-            // lists follow P2P on its side stream, adding into the near field
-            // (on the main stream the coefficients would wait for CUs behind
-            // P2P and the X lists and hold back M2L)
+            // the W lists need only the multipoles: they follow P2P on its side
+            // stream, adding into the near field
+            launch_m2p_coef(st, p, f2, nn - f2, f.aM, c->T, f.aWc);
             HIPCHK(c, hipEventRecord(c->side_ev[4], st));
             HIPCHK(c, hipStreamWaitEvent(c->side[0], c->side_ev[4], 0));
-            launch_m2p_coef(c->side[0], p, f2, nn - f2, f.aM, c->T, f.aWc);
             launch_wlist_adaptive(c->side[0], p, nn, f.boxes, f.tr, f.a_P, f.aWc, f.loff + n1, f.wlist, f.a_Fn);
         }
         if (prec != CTFMM_PREC_FP64) {
